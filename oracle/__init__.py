@@ -1,0 +1,22 @@
+"""Plain, slow CPU FP64 oracle for the QUEEN residual-fitting hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import anything from here.  The product path (``paper_2412_04469_amd``) never imports
+this package and this package never imports the product path; the two share no code.  The only
+common source is ``paper_2412_04469_amd.synth``, the seeded input generator, which holds none of the
+method's arithmetic (and which this package does not import either: the callers pass inputs in).
+
+Modules
+    sh        real SH basis from its definition (Sec. 3.1 view-dependent colour)
+    project   quaternion/scale covariance and EWA projection (Eq. 1), SH colour, support rectangle
+    composite per-pixel depth-ordered alpha compositing (Eq. 2) and its adjoint (C, FP64)
+    binning   (tile, depth) keys, stable sort and tile ranges (plain definition)
+    decode    latent rounding with STE and the residual decoder (Eq. 4-5), position gate (Eq. 6-8)
+    gate      viewspace-gradient difference (Eq. 9) and gate initialisation (Eq. 10)
+    loss      L1 loss (Eq. 3 without D-SSIM) and PSNR
+    adam      Adam update
+    brute     an independent NumPy compositor for tiny scenes (pins ``composite``)
+    render    the whole forward/backward chain glued together
+
+Parity status of each function is stated in its module docstring.
+"""

@@ -1,0 +1,183 @@
+"""Pins of the oracle compositor (Eq. 2): closed forms, invariants, brute force, finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import composite as C
+from paper_2412_04469_amd import synth
+
+
+def _splats(xy, conic, op, rgb, depth):
+    return {"xy": np.atleast_2d(xy).astype(float), "conic": np.atleast_2d(conic).astype(float),
+            "opacity": np.atleast_1d(op).astype(float), "rgb": np.atleast_2d(rgb).astype(float),
+            "depth": np.atleast_1d(depth).astype(float)}
+
+
+def test_single_splat_closed_form():
+    bg = (0.25, 0.5, 0.75)
+    sp = _splats([10.5, 7.5], [1 / 9, 0.0, 1 / 4], 0.6, [0.9, 0.1, 0.4], 2.0)
+    r = C.composite(sp, np.array([10.5, 12.5]), np.array([7.5, 8.5]), bg)
+    a0 = 0.6
+    a1 = 0.6 * math.exp(-0.5 * (4 / 9 + 1 / 4))
+    for p, a in enumerate([a0, a1]):
+        np.testing.assert_allclose(r["color"][p], a * np.array([0.9, 0.1, 0.4]) + (1 - a) * np.array(bg), atol=1e-15)
+        np.testing.assert_allclose(r["t_final"][p], 1 - a, atol=1e-15)
+        assert r["last_id"][p] == 0 and r["n_contrib"][p] == 1
+
+
+def test_alpha_clamp_099():
+    o = 1 / (1 + math.exp(-10.0))
+    sp = _splats([4.5, 4.5], [1.0, 0.0, 1.0], o, [1, 1, 1], 1.0)
+    r = C.composite(sp, np.array([4.5]), np.array([4.5]))
+    np.testing.assert_allclose(r["t_final"][0], 0.01, atol=1e-15)
+    np.testing.assert_allclose(r["color"][0], 0.99, atol=1e-15)
+
+
+def test_footprint_489_pixels():
+    """Isotropic sigma' = 4 px, o = 0.5, centred on a pixel centre: alpha >= 1/255 on the disc of
+    radius 4 sqrt(2 ln 127.5) = 12.4555 px, which holds 489 pixel centres."""
+    sp = _splats([32.5, 32.5], [1 / 16, 0.0, 1 / 16], 0.5, [1, 1, 1], 1.0)
+    r = C.composite_image(sp, 64, 64)
+    assert int((r["n_contrib"] > 0).sum()) == 489
+    rad = 4 * math.sqrt(2 * math.log(127.5))
+    assert abs(rad - 12.45551) < 1e-5
+
+
+@pytest.mark.parametrize("k", [14, 20])
+def test_termination_count(k):
+    """k >= 14 splats with alpha = 1/2 at the pixel: 13 contribute, T_final = 2^-13, I = (1 - 2^-13) c."""
+    sp = _splats(np.tile([3.5, 3.5], (k, 1)), np.tile([0.5, 0, 0.5], (k, 1)), np.full(k, 0.5),
+                 np.tile([0.2, 0.4, 0.8], (k, 1)), np.arange(k, 0, -1) * 0.5)
+    r = C.composite(sp, np.array([3.5]), np.array([3.5]))
+    assert r["n_contrib"][0] == 13
+    assert r["t_final"][0] == 2.0 ** -13
+    np.testing.assert_allclose(r["color"][0], (1 - 2.0 ** -13) * np.array([0.2, 0.4, 0.8]), rtol=1e-15)
+    # front-most (smallest depth) first: last contributor is the 13th nearest
+    assert r["last_id"][0] == k - 13
+
+
+def test_two_clamped_splats_fp64_boundary():
+    """(1-0.99)^2 in float64 is 1.0000000000000018e-4 >= 1e-4, so both splats contribute here; in float32 the
+    same product rounds below 1e-4.  The pixel's margin must flag it."""
+    o = 1 / (1 + math.exp(-10.0))
+    sp = _splats([[4.5, 4.5]] * 2, [[1, 0, 1]] * 2, [o, o], [[1, 1, 1]] * 2, [1.0, 2.0])
+    r = C.composite(sp, np.array([4.5]), np.array([4.5]))
+    assert (1 - 0.99) ** 2 >= 1e-4
+    assert np.float32(1 - np.float32(0.99)) ** 2 < np.float32(1e-4)
+    assert r["n_contrib"][0] == 2
+    assert r["margin"][0] < 1e-6
+
+
+def _random(n, w, h, seed):
+    rng = synth.rng_for(seed)
+    return synth.random_splats(rng, n, w, h)
+
+
+def test_weights_plus_tfinal_sum_to_one():
+    sp = _random(300, 40, 32, 11)
+    sp1 = dict(sp, rgb=np.ones((300, 3)))
+    r = C.composite_image(sp1, 40, 32)
+    np.testing.assert_allclose(r["image"][0] + r["t_final"], 1.0, atol=1e-12)
+
+
+def test_input_order_invariance():
+    sp = _random(300, 40, 32, 12)
+    r = C.composite_image(sp, 40, 32)
+    perm = np.random.default_rng(0).permutation(300)
+    sp2 = {k: np.asarray(v)[perm] for k, v in sp.items()}
+    r2 = C.composite_image(sp2, 40, 32)
+    assert np.array_equal(r["image"], r2["image"])
+    assert np.array_equal(r["t_final"], r2["t_final"])
+    assert np.array_equal(perm[r2["last_id"][r2["last_id"] >= 0]], r["last_id"][r["last_id"] >= 0])
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.25, 0.5, 0.75)])
+def test_matches_independent_brute_force(bg):
+    sp = _random(250, 36, 28, 13)
+    r = C.composite_image(sp, 36, 28, bg)
+    img, tf, last = brute.render(sp["xy"], sp["conic"], sp["opacity"], sp["rgb"], sp["depth"], 36, 28, bg)
+    np.testing.assert_allclose(r["image"], img, atol=1e-12)
+    np.testing.assert_allclose(r["t_final"], tf, atol=1e-12)
+    assert np.array_equal(r["last_id"], last)
+
+
+def _loss(sp, w, h, G, bg, **kw):
+    r = C.composite_image(sp, w, h, bg, **kw)
+    return float((r["image"] * G).sum())
+
+
+@pytest.mark.parametrize("reverse_t", [False, True])
+def test_adjoint_vs_central_fd_smooth(reverse_t):
+    """Smooth mode (no clamp/skip/termination): adjoint equals central differences to 1e-6 relative."""
+    w, h = 14, 12
+    sp = _random(12, w, h, 14)
+    sp["opacity"] = np.asarray(sp["opacity"], float) * 0.9
+    G = np.random.default_rng(1).normal(size=(3, h, w))
+    bg = (0.1, 0.2, 0.3)
+    kw = dict(alpha_min=0.0, alpha_max=np.inf, t_min=0.0)
+    r = C.composite_image(sp, w, h, bg, grad_image=G, reverse_t=reverse_t, **kw)
+    grads = {"xy": r["g_xy"], "conic": r["g_conic"], "opacity": r["g_opacity"], "rgb": r["g_rgb"]}
+    sp64 = {k: np.array(v, np.float64) for k, v in sp.items()}
+    for name, g in grads.items():
+        arr = sp64[name]
+        flat = arr.reshape(-1)
+        fd = np.zeros_like(flat)
+        for j in range(flat.size):
+            hh = 1e-6 * max(1.0, abs(flat[j]))
+            old = flat[j]
+            flat[j] = old + hh
+            lp = _loss(sp64, w, h, G, bg, **kw)
+            flat[j] = old - hh
+            lm = _loss(sp64, w, h, G, bg, **kw)
+            flat[j] = old
+            fd[j] = (lp - lm) / (2 * hh)
+        rel = np.linalg.norm(fd - g.reshape(-1)) / np.linalg.norm(fd)
+        assert rel < 1e-6, (name, rel)
+
+
+def test_adjoint_vs_central_fd_standard_mode():
+    """Standard mode: parameters whose perturbation changes a decision are excluded (FD at two step sizes
+    must agree); the rest match the adjoint."""
+    w, h = 16, 16
+    sp = _random(40, w, h, 15)
+    G = np.random.default_rng(2).normal(size=(3, h, w))
+    r = C.composite_image(sp, w, h, grad_image=G)
+    sp64 = {k: np.array(v, np.float64) for k, v in sp.items()}
+    checked = 0
+    for name, key in (("xy", "g_xy"), ("conic", "g_conic"), ("opacity", "g_opacity"), ("rgb", "g_rgb")):
+        flat = sp64[name].reshape(-1)
+        gad = r[key].reshape(-1)
+        for j in range(flat.size):
+            old = flat[j]
+            fds = []
+            for hh in (1e-6 * max(1, abs(old)), 2e-6 * max(1, abs(old))):
+                flat[j] = old + hh
+                lp = _loss(sp64, w, h, G, (0, 0, 0))
+                flat[j] = old - hh
+                lm = _loss(sp64, w, h, G, (0, 0, 0))
+                flat[j] = old
+                fds.append((lp - lm) / (2 * hh))
+            if abs(fds[0] - fds[1]) > 1e-6 * max(1.0, abs(fds[0])):
+                continue  # decision set changed inside the stencil
+            checked += 1
+            assert abs(fds[0] - gad[j]) <= 1e-6 * max(1.0, abs(gad[j])), (name, j, fds[0], gad[j])
+    assert checked > 300
+
+
+def test_reverse_t_equals_stored_t():
+    sp = _random(400, 48, 40, 16)
+    G = np.random.default_rng(3).normal(size=(3, 40, 48))
+    a = C.composite_image(sp, 48, 40, (0.2, 0.3, 0.4), grad_image=G, reverse_t=False)
+    b = C.composite_image(sp, 48, 40, (0.2, 0.3, 0.4), grad_image=G, reverse_t=True)
+    for k in ("g_xy", "g_conic", "g_opacity", "g_rgb"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-10, atol=1e-12)
+
+
+def test_empty_scene_is_background():
+    sp = _splats(np.zeros((0, 2)), np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros(0))
+    sp = {k: v.reshape((0,) + v.shape[1:]) for k, v in sp.items()}
+    r = C.composite_image(sp, 5, 4, (0.1, 0.2, 0.3), grad_image=np.ones((3, 4, 5)))
+    np.testing.assert_array_equal(r["image"][:, 0, 0], [0.1, 0.2, 0.3])
+    assert (r["t_final"] == 1).all() and (r["last_id"] == -1).all()
