@@ -1,0 +1,235 @@
+/*
+ * qg.h -- C ABI of the MI355X (gfx950) hot path of QUEEN's per-frame residual fitting
+ * (differentiable 3D Gaussian splatting with a quantised-latent residual decoder and gated
+ * position residuals).  Paper: QUEEN: QUantized Efficient ENcoding of Dynamic Gaussians for
+ * Streaming Free-viewpoint Videos (NeurIPS 2024, arXiv 2412.04469).
+ *
+ * General rules
+ *   - Pointers are DEVICE pointers unless marked [host].  Every call only enqueues work on
+ *     `stream` (a hipStream_t; NULL is the null stream): no host synchronisation, no device
+ *     allocation, no device free.  The caller owns every buffer; the library keeps no pointer
+ *     after a call returns.  Host arrays ([host]) are read during the call only.
+ *   - Validation happens before anything is enqueued.  On a bad argument the call returns
+ *     QG_ERR_ARG and enqueues nothing; a failed launch returns QG_ERR_HIP.  qg_last_error()
+ *     returns a thread-local message for the last non-OK status.  Nothing throws across the ABI.
+ *   - Gradient outputs are accumulated (+=): the caller zeroes them once per step.
+ *   - Float data are IEEE float32.  Results of the forward calls are bit-reproducible run to run;
+ *     backward calls accumulate with float32 atomics (run-to-run differences ~1e-6 relative).
+ *
+ * Attribute layout (the Gaussian attribute set A = {p, q, s, o, h} of Sec. 3.1): 59 float32
+ * planes of length n with plane stride ld >= n ("[59][ld]"):
+ *     0-2    mean x, y, z
+ *     3-6    quaternion w, x, y, z (stored unnormalised; normalised before use)
+ *     7-9    log-scale x, y, z (scale = exp)
+ *     10     opacity logit (opacity = sigmoid)
+ *     11+3k+ch  SH coefficient of real basis function k (0..15, l-major, m = -l..l, Condon-Shortley
+ *               phase), colour channel ch
+ */
+#ifndef QG_H_
+#define QG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qg_status;
+#define QG_OK 0
+#define QG_ERR_ARG (-1)
+#define QG_ERR_HIP (-2)
+#define QG_ERR_UNSUPPORTED (-3)
+
+#define QG_N_PLANES 59
+#define QG_MAX_VIEWS 16
+#define QG_SPLAT_STRIDE 12 /* floats per projected splat record */
+#define QG_GRAD2D_STRIDE 12 /* floats per 2D gradient record */
+
+typedef void* qg_stream; /* hipStream_t */
+
+/* Thread-local message describing the last non-OK status of this thread ("" if none). */
+const char* qg_last_error(void);
+/* ABI version (incremented on incompatible change). */
+int32_t qg_version(void);
+
+/*
+ * Pinhole camera (Sec. 3.1: intrinsics K and viewing transform W), OpenCV axes (x right, y down,
+ * z forward), world->camera u = R p + t with R row-major.  p' = (fx ux/uz + cx, fy uy/uz + cy);
+ * pixel (row i, column j) has its centre at (j + 0.5, i + 0.5).  Gaussians with uz <= z_near are culled.
+ */
+typedef struct {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    int32_t width, height;
+    float z_near;
+} qg_camera;
+
+/* Tile shape: one of 8x8, 16x16, 32x8 (tile_w x tile_h). */
+typedef struct {
+    int32_t tile_w, tile_h;
+} qg_tiling;
+
+/*
+ * Per-view output of qg_project / input of the later calls (all device, length n):
+ *   splat     [n][12] float: x, y, opacity, 0 | A, B, C, 0 | r, g, b, 0
+ *             where (x, y) = p' (Eq. 1), (A, B, C) = Sigma'^{-1} in q = A dx^2 + 2B dx dy + C dy^2,
+ *             opacity = sigmoid(logit), (r, g, b) = max(0, SH colour + 0.5).
+ *   depth     [n] float camera-space z (the order of Eq. 2's depth sort).
+ *   rect      [n][4] int32 half-open tile rectangle tx0, ty0, tx1, ty1 of the tiles that hold a
+ *             pixel centre with alpha >= 1/255 (axis-aligned bound of that ellipse, clipped to the
+ *             image); all zero if none.
+ *   ntiles    [n] int32 number of tiles in rect (0 for culled Gaussians).
+ *   flags     [n] uint8: bit ch (0..2) = colour channel ch clamped at 0; bit 7 = culled.
+ */
+typedef struct {
+    float* splat;
+    float* depth;
+    int32_t* rect;
+    int32_t* ntiles;
+    uint8_t* flags;
+} qg_projected;
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Decode and gate (Eq. 4-8).                                                                      */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * attrs_out = prev_attrs + [g * l_p ; W2 SiLU(W1 rint(latents))]          (Eq. 4, 5, Sec. 3.2.2)
+ *   latent rounding is round-half-to-even, used straight-through in the backward (Eq. 5);
+ *   the decoder is a shared bias-free MLP (L -> Hd -> M) with SiLU; M = 56 maps onto planes 3..58
+ *   (rotation 4, log-scale 3, opacity logit 1, SH 48).  Built shape: L = 8, Hd = 32, M = 56; other
+ *   shapes return QG_ERR_UNSUPPORTED.
+ *   g = min(1, max(0, sigmoid(a / tau) (gamma1 - gamma0) + gamma0))      (Eq. 6-7)
+ *   lreg_partial receives one float per 256-Gaussian block: the block's sum of
+ *   sigmoid(a - tau ln(-gamma0/gamma1)) (Eq. 8); the caller reduces (qg_decode_lreg_blocks()).
+ * Sizes: n >= 0, ld >= n; latents [L][ld]; W1 [Hd][L], W2 [M][Hd]; pos_pre (l_p) [3][ld]; gate_logit (a) [n];
+ *   attrs_out [59][ld] (may not alias prev_attrs); gate_out [n] (may be NULL); lreg_partial
+ *   [qg_decode_lreg_blocks(n)] (may be NULL).  gamma0 < 0 < 1 < gamma1, tau > 0.
+ */
+qg_status qg_decode_residuals(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L,
+                              const float* W1, const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
+                              const float* gate_logit, float gamma0, float gamma1, float tau, float* attrs_out,
+                              float* gate_out, float* lreg_partial, qg_stream stream);
+
+int64_t qg_decode_lreg_blocks(int64_t n);
+
+/*
+ * Backward of qg_decode_residuals for loss = f(attrs_out) + lambda_reg * mean_i sigmoid(a_i - tau ln(-g0/g1)):
+ *   grad_latents (+=) [L][ld]: straight-through: d/d latents = d/d rint(latents)
+ *   grad_W1 (+=) [Hd][L], grad_W2 (+=) [M][Hd]: summed over Gaussians (block partials in `ws`,
+ *     then a deterministic fixed-order sum)
+ *   grad_pos_pre (+=) [3][ld] = g * dL/d(mean residual)
+ *   grad_gate_logit (+=) [n] = (dL/d dp . l_p) (gamma1-gamma0) ghat (1-ghat)/tau [0 < g~ < 1]
+ *                              + lambda_reg sigmoid'(a - tau ln(-g0/g1)) / n
+ * grad_attrs [59][ld] is dL/d attrs_out.  ws must hold qg_decode_bwd_workspace_size(n, L, Hd, M) bytes.
+ */
+size_t qg_decode_bwd_workspace_size(int64_t n, int32_t L, int32_t Hd, int32_t M);
+qg_status qg_decode_residuals_bwd(int64_t n, int64_t ld, const float* latents, int32_t L, const float* W1,
+                                  const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
+                                  const float* gate_logit, float gamma0, float gamma1, float tau,
+                                  const float* grad_attrs, float lambda_reg, float* grad_latents, float* grad_W1,
+                                  float* grad_W2, float* grad_pos_pre, float* grad_gate_logit, void* ws,
+                                  size_t ws_bytes, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Projection (Eq. 1) with SH colour.                                                              */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * For every Gaussian and each of the V cameras (attributes read once for all views):
+ *   Sigma = R(q) diag(exp(2 s)) R(q)^T; u = R_v p + t_v; cull if uz <= z_near, non-finite input,
+ *   non-positive-definite Sigma' or opacity < 1/255;
+ *   Sigma' = J R_v Sigma R_v^T J^T + dilation I, J = [[fx/uz, 0, -fx ux/uz^2], [0, fy/uz, -fy uy/uz^2]];
+ *   conic = Sigma'^{-1}; opacity = sigmoid(logit); colour from degree-`sh_degree` SH at the direction
+ *   from the camera centre to the mean; tile rectangle from k^2 = 2 ln(255 opacity).
+ * 1 <= V <= QG_MAX_VIEWS; 0 <= sh_degree <= 3; dilation >= 0; cams [host] V; out [host] V.
+ */
+qg_status qg_project(int64_t n, int64_t ld, const float* attrs, int32_t sh_degree, const qg_camera* cams, int32_t V,
+                     qg_tiling tiling, float dilation, const qg_projected* out, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Tile binning: (tile, depth) keys and a device radix sort.                                       */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * Every (view, Gaussian) pair whose rectangle covers a tile yields one entry.  Entries are ordered by
+ * the 64-bit key (global tile id << 32) | float32 bits of depth, ties by Gaussian index -- the
+ * per-tile depth order of Eq. 2.  Global tile id of view v = sum of the earlier views' tile counts +
+ * ty * grid_w(v) + tx.  The sort is a stable LSD radix sort: the 32 depth bits are sorted once per
+ * (view, Gaussian) before pairs are emitted, then the tile bits over the pairs.
+ *   vals        [capacity] uint32 sorted Gaussian indices (within their view).
+ *   keys        [capacity] uint64 sorted keys (optional, NULL to skip).
+ *   tile_ranges [total_tiles][2] uint32 half-open spans into vals ([0,0) for an empty tile).
+ *   num_pairs   [1] int64: the pair count P.  If P > capacity nothing is emitted, tile_ranges are all
+ *               empty, and the caller must not render this step; re-run with capacity >= P.
+ *   ws          qg_bin_workspace_size(n, V, capacity, total_tiles) bytes.
+ * capacity <= 2^32 - 1.  total_tiles = sum over views of ceil(W/tile_w) * ceil(H/tile_h).
+ */
+size_t qg_bin_workspace_size(int64_t n, int32_t V, int64_t capacity, int64_t total_tiles);
+int64_t qg_total_tiles(const qg_camera* cams, int32_t V, qg_tiling tiling);
+qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                 int64_t capacity, uint32_t* vals, uint64_t* keys, uint32_t* tile_ranges, int64_t* num_pairs,
+                 void* ws, size_t ws_bytes, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Front-to-back alpha compositing (Eq. 2).                                                        */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * Per pixel centre x, over its tile's depth-ordered entries:
+ *   alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255; T' = T (1 - alpha); stop before an entry
+ *   with T' < 1e-4 (that entry is not added); C += c alpha T; T = T'.   Output C + T bg.
+ * image [V] -> [3][H][W] float (planar), T_final [V] -> [H][W] float, last [V] -> [H][W] uint32: the
+ * exclusive end position (in vals) of the pixel's contributors (= its tile start if none).
+ * bg [host] 3 floats.  image, T_final, last are [host] arrays of V device pointers.  If qg_bin reported
+ * num_pairs > capacity, every tile range is empty and the image is the background: do not use it.
+ */
+qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                        const uint32_t* vals, const uint32_t* tile_ranges, const float* bg, float* const* image,
+                        float* const* T_final, uint32_t* const* last, qg_stream stream);
+
+/*
+ * Adjoint of qg_render_fwd followed by the adjoint of qg_project (Eq. 1-2), for the loss gradient
+ * grad_image [V] -> [3][H][W].  The blend adjoint walks each pixel's entries in reverse from `last`,
+ * recomputing T_i = T_{i+1} / (1 - alpha_i) from T_final (no per-pixel lists are stored).
+ *   grad_attrs   (+=) [59][ld] gradient with respect to the attribute planes, summed over views.
+ *   grad_xy_abs  (+=) [n] sum over views of |dL/dp'| (optional, NULL to skip).
+ *   grad_xy      [host] V pointers (optional, NULL to skip; entries may be NULL) -> (+=) [2][n] dL/dp'
+ *                per view (the viewspace gradient of Eq. 9).
+ *   ws           qg_render_bwd_workspace_size(n, V) bytes (per-view 2D gradient records).
+ * The other arguments must be those of the qg_project / qg_bin / qg_render_fwd calls of this step.
+ */
+size_t qg_render_bwd_workspace_size(int64_t n, int32_t V);
+qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, int32_t sh_degree, const qg_camera* cams,
+                        int32_t V, qg_tiling tiling, float dilation, const qg_projected* proj, const uint32_t* vals,
+                        const uint32_t* tile_ranges, const float* bg, const float* const* T_final, const uint32_t* const* last, const float* const* grad_image,
+                        float* grad_attrs, float* grad_xy_abs, float* const* grad_xy, void* ws, size_t ws_bytes,
+                        qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Loss (L1 term of Eq. 3), PSNR, Adam.                                                            */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * L1 = mean |image - gt| over count values; grad_image = scale * sign(image - gt) / count (sign(0) = 0;
+ * written, not accumulated; may be NULL).  partials receives 2 doubles per block of
+ * qg_loss_block_elems() values: sum |d| and sum (clamp(image,0,1) - gt)^2; qg_loss_reduce sums
+ * them in a fixed order into out[0] = L1, out[1] = MSE of the clamped image (PSNR = -10 log10 MSE).
+ */
+int64_t qg_loss_blocks(int64_t count);
+qg_status qg_l1_loss(int64_t count, const float* image, const float* gt, float scale, float* grad_image,
+                     double* partials, qg_stream stream);
+qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_stream stream);
+
+/*
+ * One bias-corrected Adam step on `count` parameters (beta = (b1, b2), eps) at 1-based step `t`:
+ *   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ */
+qg_status qg_adam(int64_t count, float* param, const float* grad, float* m, float* v, float lr, float b1,
+                  float b2, float eps, int32_t t, qg_stream stream);
+
+/* dst[i] = 0 for i < count (a fill kernel, safe under stream capture). */
+qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QG_H_ */

@@ -1,0 +1,131 @@
+// Error state, argument tables and small utilities of libqg.
+#include <cmath>
+#include <cstring>
+
+#include "qg_internal.h"
+
+namespace qg {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+bool tiling_ok(qg_tiling t) {
+    return (t.tile_w == 8 && t.tile_h == 8) || (t.tile_w == 16 && t.tile_h == 16) ||
+           (t.tile_w == 32 && t.tile_h == 8);
+}
+
+bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V, qg_tiling tiling,
+                     bool need_proj, ViewTable* out) {
+    if (V < 1 || V > QG_MAX_VIEWS) {
+        set_error("V=%d outside [1, %d]", V, QG_MAX_VIEWS);
+        return false;
+    }
+    if (!cams) {
+        set_error("cams is NULL");
+        return false;
+    }
+    if (!tiling_ok(tiling)) {
+        set_error("unsupported tiling %dx%d (8x8, 16x16, 32x8)", tiling.tile_w, tiling.tile_h);
+        return false;
+    }
+    if (need_proj && !proj) {
+        set_error("proj is NULL");
+        return false;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->V = V;
+    uint64_t off = 0;
+    for (int v = 0; v < V; ++v) {
+        const qg_camera& c = cams[v];
+        if (c.width < 1 || c.width > 16384 || c.height < 1 || c.height > 16384) {
+            set_error("view %d: size %dx%d outside [1, 16384]", v, c.width, c.height);
+            return false;
+        }
+        if (!(c.z_near > 0.f) || !std::isfinite(c.fx) || !std::isfinite(c.fy)) {
+            set_error("view %d: z_near must be > 0 and focal lengths finite", v);
+            return false;
+        }
+        CamDev& d = out->cam[v];
+        d.fx = c.fx;
+        d.fy = c.fy;
+        d.cx = c.cx;
+        d.cy = c.cy;
+        for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+        for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+        for (int k = 0; k < 3; ++k)  // centre = -R^T t, in double then rounded
+            d.cpos[k] = (float)(-((double)c.R[0 + k] * c.t[0] + (double)c.R[3 + k] * c.t[1] +
+                                  (double)c.R[6 + k] * c.t[2]));
+        d.width = c.width;
+        d.height = c.height;
+        d.z_near = c.z_near;
+        d.grid_w = (c.width + tiling.tile_w - 1) / tiling.tile_w;
+        d.grid_h = (c.height + tiling.tile_h - 1) / tiling.tile_h;
+        d.tile_off = (uint32_t)off;
+        off += (uint64_t)d.grid_w * d.grid_h;
+        if (need_proj) {
+            const qg_projected& p = proj[v];
+            if (!p.splat || !p.depth || !p.rect || !p.ntiles || !p.flags) {
+                set_error("view %d: a projected buffer is NULL", v);
+                return false;
+            }
+            out->proj[v] = ProjDev{p.splat, p.depth, p.rect, p.ntiles, p.flags};
+        }
+    }
+    if (off >= (1ull << 31)) {
+        set_error("total tile count %llu too large", (unsigned long long)off);
+        return false;
+    }
+    out->total_tiles = (uint32_t)off;
+    return true;
+}
+
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t words) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride) p[i] = 0u;
+}
+
+__global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t bytes) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < bytes) p[i] = 0;
+}
+
+}  // namespace qg
+
+using namespace qg;
+
+extern "C" const char* qg_last_error(void) { return g_err; }
+
+extern "C" int32_t qg_version(void) { return 1; }
+
+extern "C" int64_t qg_total_tiles(const qg_camera* cams, int32_t V, qg_tiling tiling) {
+    ViewTable t;
+    if (!make_view_table(cams, nullptr, V, tiling, false, &t)) return -1;
+    return t.total_tiles;
+}
+
+extern "C" qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(bytes >= 0, "bytes < 0");
+    if (bytes == 0) return QG_OK;
+    QG_REQUIRE(dst != nullptr, "dst is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    uintptr_t a = (uintptr_t)dst;
+    if (a % 4 == 0 && bytes % 4 == 0) {
+        int64_t words = bytes / 4;
+        int64_t blocks = std::min<int64_t>(ceil_div(words, 256), 65536);
+        k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)dst, words);
+    } else {
+        k_zero_bytes<<<(unsigned)ceil_div(bytes, 256), 256, 0, s>>>((uint8_t*)dst, bytes);
+    }
+    QG_LAUNCH_CHECK("qg_zero");
+    return QG_OK;
+}

@@ -1,0 +1,117 @@
+// L1 loss with its image gradient and the clamped-image MSE used for PSNR; Adam.
+#include <cmath>
+
+#include "qg_internal.h"
+
+namespace qg {
+namespace {
+
+constexpr int kLBlock = 256;
+constexpr int kLIPT = 16;
+constexpr int64_t kLTile = (int64_t)kLBlock * kLIPT;
+
+__global__ __launch_bounds__(kLBlock) void k_l1(int64_t count, const float* __restrict__ img,
+                                                const float* __restrict__ gt, float gscale,
+                                                float* __restrict__ grad, double* __restrict__ part) {
+    __shared__ double s_a[kLBlock / kWave], s_b[kLBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kLTile;
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int r = 0; r < kLIPT; ++r) {
+        const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
+        if (i < count) {
+            const float x = img[i], y = gt[i];
+            const float d = x - y;
+            sa += fabsf(d);
+            const float c = fminf(1.f, fmaxf(0.f, x)) - y;
+            sb = __builtin_fmaf(c, c, sb);
+            if (grad) grad[i] = d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
+        }
+    }
+    double da = sa, db = sb;
+    for (int o = 32; o >= 1; o >>= 1) {
+        da += __shfl_xor(da, o);
+        db += __shfl_xor(db, o);
+    }
+    if (__lane_id() == 0) {
+        s_a[threadIdx.x / kWave] = da;
+        s_b[threadIdx.x / kWave] = db;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0, tb = 0;
+        for (int w = 0; w < kLBlock / kWave; ++w) {
+            ta += s_a[w];
+            tb += s_b[w];
+        }
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void k_loss_reduce(int64_t nb, int64_t count, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0, b = 0;
+    for (int64_t k = 0; k < nb; ++k) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    out[0] = count > 0 ? a / (double)count : 0.0;
+    out[1] = count > 0 ? b / (double)count : 0.0;
+}
+
+__global__ void k_adam(int64_t count, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+}  // namespace qg
+
+using namespace qg;
+
+extern "C" int64_t qg_loss_blocks(int64_t count) { return std::max<int64_t>(1, ceil_div(count, kLTile)); }
+
+extern "C" qg_status qg_l1_loss(int64_t count, const float* image, const float* gt, float scale, float* grad_image,
+                                double* partials, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(count >= 0, "count < 0");
+    QG_REQUIRE(partials, "partials is NULL");
+    QG_REQUIRE(count == 0 || (image && gt), "image/gt NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = qg_loss_blocks(count);
+    const float gs = count > 0 ? scale / (float)count : 0.f;
+    k_l1<<<(unsigned)nb, kLBlock, 0, s>>>(count, image, gt, gs, grad_image, partials);
+    QG_LAUNCH_CHECK("qg_l1_loss");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(count >= 0 && partials && out, "bad arguments");
+    k_loss_reduce<<<1, 64, 0, (hipStream_t)stream>>>(qg_loss_blocks(count), count, partials, out);
+    QG_LAUNCH_CHECK("qg_loss_reduce");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_adam(int64_t count, float* param, const float* grad, float* m, float* v, float lr, float b1,
+                             float b2, float eps, int32_t t, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(count >= 0 && t >= 1, "count >= 0 and t >= 1 required");
+    QG_REQUIRE(count == 0 || (param && grad && m && v), "a pointer is NULL");
+    QG_REQUIRE(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f, "bad Adam constants");
+    if (count == 0) return QG_OK;
+    const float c1 = (float)(1.0 - std::pow((double)b1, t));
+    const float c2 = (float)(1.0 - std::pow((double)b2, t));
+    k_adam<<<(unsigned)ceil_div(count, 256), 256, 0, (hipStream_t)stream>>>(count, param, grad, m, v, lr, b1, b2, eps,
+                                                                          c1, c2);
+    QG_LAUNCH_CHECK("qg_adam");
+    return QG_OK;
+}

@@ -1,0 +1,73 @@
+// Internal helpers shared by the HIP translation units of libqg (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "qg.h"
+
+namespace qg {
+
+// Thread-local error message behind qg_last_error().
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define QG_REQUIRE(cond, ...)              \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::qg::set_error(__VA_ARGS__);  \
+            return QG_ERR_ARG;             \
+        }                                  \
+    } while (0)
+
+#define QG_LAUNCH_CHECK(what)                                                              \
+    do {                                                                                   \
+        hipError_t e_ = hipGetLastError();                                                 \
+        if (e_ != hipSuccess) {                                                            \
+            ::qg::set_error("%s: launch failed: %s", what, hipGetErrorString(e_));         \
+            return QG_ERR_HIP;                                                             \
+        }                                                                                  \
+    } while (0)
+
+constexpr int kWave = 64;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Camera in the form the kernels use (float32, by value in kernel arguments).
+struct CamDev {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float cpos[3];  // camera centre -R^T t
+    int32_t width, height;
+    float z_near;
+    int32_t grid_w, grid_h;  // tiles
+    uint32_t tile_off;       // first global tile id of this view
+};
+
+// Projected per-view buffers in kernel-argument form.
+struct ProjDev {
+    float* splat;
+    float* depth;
+    int32_t* rect;
+    int32_t* ntiles;
+    uint8_t* flags;
+};
+
+struct ViewTable {
+    CamDev cam[QG_MAX_VIEWS];
+    ProjDev proj[QG_MAX_VIEWS];
+    int32_t V;
+    uint32_t total_tiles;
+};
+
+// Fill a view table from host arrays; returns false (with the error set) on a bad argument.
+bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V, qg_tiling tiling,
+                     bool need_proj, ViewTable* out);
+bool tiling_ok(qg_tiling t);
+
+}  // namespace qg

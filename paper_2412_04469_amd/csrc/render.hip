@@ -1,0 +1,402 @@
+// Front-to-back alpha compositing (Eq. 2) over tiles, and its reverse-order adjoint.
+//
+// Layout: one 64-lane wavefront per tile (one workgroup = one wave, so no cross-wave reduction is
+// ever needed).  A tile of TW x TH pixels gives each lane PPL = TW*TH/64 pixels that all lie in one
+// column: the lane's x offset (and every term of the conic form that only depends on dx) is shared
+// by its PPL pixels.  The tile's depth-ordered entries are staged 64 at a time in LDS (one record per
+// lane, gathered from the 48-byte splat records) and read back as wave-uniform broadcasts.  A ballot
+// over the pixels still running ends the loop early.
+//
+// The adjoint walks the entries backwards from each pixel's last contributor and recomputes the
+// transmittance in reverse, T_i = T_{i+1} / (1 - alpha_i), starting from the stored final T, so no
+// per-pixel lists are kept.  Per entry, each lane first sums its PPL pixels, then the wave sums its
+// 64 lanes with DPP row shifts/broadcasts, and 9 lanes issue one float atomic each into the
+// Gaussian's 2D gradient record.
+//
+// The blend alpha is evaluated by one inline function used by both kernels, with explicit fused
+// multiply-adds, so the forward's skip/clamp/termination decisions are reproduced exactly.
+#include "qg_internal.h"
+
+namespace qg {
+
+qg_status project_bwd_launch(int64_t n, int64_t ld, const float* attrs, int sh_degree, const ViewTable& vt,
+                             float dilation, const float* grad2d, int64_t g2d_view_stride, float* grad_attrs,
+                             float* grad_xy_abs, float* const* grad_xy, hipStream_t s);
+
+namespace {
+
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+// -0.5 * log2(e): exp(-q/2) = exp2(kFold * q)
+constexpr float kFold = -0.72134752044448170f;
+
+struct ViewPtrsF {
+    float* p[QG_MAX_VIEWS];
+};
+struct ViewPtrsCF {
+    const float* p[QG_MAX_VIEWS];
+};
+struct ViewPtrsU {
+    uint32_t* p[QG_MAX_VIEWS];
+};
+struct ViewPtrsCU {
+    const uint32_t* p[QG_MAX_VIEWS];
+};
+
+// Map workgroup -> tile so that each of the 8 XCDs (which take workgroups round-robin) gets a contiguous
+// run of tiles: neighbouring tiles share splats, so they should share an L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t per_xcd) { return (b % 8) * per_xcd + b / 8; }
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, uint32_t t) {
+    int v = 0;
+    for (int k = 1; k < vt.V; ++k)
+        if (t >= vt.cam[k].tile_off) v = k;
+    return v;
+}
+
+// Folded conic: q' = kFold * q = A' dx^2 + 2 B' dx dy + C' dy^2; returns exp(-q/2) = exp2(q').
+// The blend alpha is min(0.99, o * blend_e(...)).
+__device__ __forceinline__ float blend_e(float fa, float fb2, float fc, float dx, float dy) {
+    const float adx2 = (fa * dx) * dx;
+    const float bdx = fb2 * dx;
+    const float qf = __builtin_fmaf(__builtin_fmaf(fc, dy, bdx), dy, adx2);
+    return __builtin_amdgcn_exp2f(qf);
+}
+
+template <int TW, int TH>
+struct TileGeom {
+    static constexpr int PPL = TW * TH / 64;
+    static constexpr int ROWS_PER_K = 64 / TW;  // rows advanced per pixel slot
+};
+
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                                   float bg2, ViewPtrsF image, ViewPtrsF tfinal, ViewPtrsU lastp,
+                                                   int64_t per_xcd) {
+    constexpr int PPL = TileGeom<TW, TH>::PPL;
+    constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
+    __shared__ float4 s_a[64];  // x, y, o, A'
+    __shared__ float4 s_b[64];  // 2B', C', r, g
+    __shared__ float s_c[64];   // b
+    const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
+    if (tile >= vt.total_tiles) return;
+    const int v = view_of_tile(vt, (uint32_t)tile);
+    const CamDev& cam = vt.cam[v];
+    const int local = (int)(tile - cam.tile_off);
+    const int tx = local % cam.grid_w, ty = local / cam.grid_w;
+    const int lane = threadIdx.x;
+    const int px = tx * TW + (lane % TW);
+    const int py0 = ty * TH + lane / TW;
+    const float fx = (float)px + 0.5f;
+    float T[PPL], C0[PPL], C1[PPL], C2[PPL];
+    uint32_t last[PPL];
+    bool run[PPL];
+    const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        T[k] = 1.f;
+        C0[k] = C1[k] = C2[k] = 0.f;
+        last[k] = s;
+        run[k] = px < cam.width && (py0 + k * RPK) < cam.height;
+    }
+    const float* __restrict__ splat = vt.proj[v].splat;
+    for (uint32_t b = s; b < e; b += 64) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) any |= run[k];
+        if (__ballot(any) == 0) break;
+        const uint32_t j = b + lane;
+        if (j < e) {
+            const uint32_t gid = vals[j];
+            const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
+            const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+            s_a[lane] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+            s_b[lane] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
+            s_c[lane] = r2.z;
+        }
+        __syncthreads();
+        const int cnt = (int)min(64u, e - b);
+        for (int jj = 0; jj < cnt; ++jj) {
+            const float4 a = s_a[jj];
+            const float4 bb = s_b[jj];
+            const float cb = s_c[jj];
+            const float dx = fx - a.x;
+            bool any2 = false;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const float dy = (float)(py0 + k * RPK) + 0.5f - a.y;
+                const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
+                const float al = fminf(kAlphaMax, raw);
+                if (run[k] && al >= kAlphaMin) {
+                    const float tn = T[k] * (1.f - al);
+                    if (tn < kTMin) {
+                        run[k] = false;
+                    } else {
+                        const float w = al * T[k];
+                        C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
+                        C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
+                        C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                        T[k] = tn;
+                        last[k] = b + jj + 1;
+                    }
+                }
+                any2 |= run[k];
+            }
+            if (__ballot(any2) == 0) break;
+        }
+        __syncthreads();
+    }
+    const int W = cam.width, H = cam.height;
+    float* img = image.p[v];
+    float* tf = tfinal.p[v];
+    uint32_t* lp = lastp.p[v];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int py = py0 + k * RPK;
+        if (px < W && py < H) {
+            const size_t o = (size_t)py * W + px;
+            const size_t plane = (size_t)W * H;
+            img[o] = C0[k] + T[k] * bg0;
+            img[plane + o] = C1[k] + T[k] * bg1;
+            img[2 * plane + o] = C2[k] + T[k] * bg2;
+            tf[o] = T[k];
+            lp[o] = last[k];
+        }
+    }
+}
+
+// ---- wave64 sum with DPP: inclusive row scans (shr 1,2,4,8), then row_bcast15 / row_bcast31; the total
+// ends in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_term(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += dpp_term<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_term<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_term<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_term<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_term<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_term<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                                   float bg2, ViewPtrsCF tfinal, ViewPtrsCU lastp, ViewPtrsCF gimage,
+                                                   float* __restrict__ grad2d, int64_t g2d_view_stride,
+                                                   int64_t per_xcd) {
+    constexpr int PPL = TileGeom<TW, TH>::PPL;
+    constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
+    __shared__ float4 s_a[64];  // x, y, o, A'
+    __shared__ float4 s_b[64];  // 2B', C', r, g
+    __shared__ float4 s_c[64];  // b, A, B, C
+    __shared__ uint32_t s_gid[64];
+    const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
+    if (tile >= vt.total_tiles) return;
+    const int v = view_of_tile(vt, (uint32_t)tile);
+    const CamDev& cam = vt.cam[v];
+    const int local = (int)(tile - cam.tile_off);
+    const int tx = local % cam.grid_w, ty = local / cam.grid_w;
+    const int lane = threadIdx.x;
+    const int px = tx * TW + (lane % TW);
+    const int py0 = ty * TH + lane / TW;
+    const float fx = (float)px + 0.5f;
+    const uint32_t s = ranges[2 * tile];
+    const int W = cam.width, H = cam.height;
+    const size_t plane = (size_t)W * H;
+    float T[PPL], S0[PPL], S1[PPL], S2[PPL], G0[PPL], G1[PPL], G2[PPL];
+    uint32_t last[PPL];
+    uint32_t maxlast = s;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int py = py0 + k * RPK;
+        const bool in = px < W && py < H;
+        const size_t o = (size_t)(in ? py : 0) * W + (in ? px : 0);
+        T[k] = in ? tfinal.p[v][o] : 1.f;
+        last[k] = in ? lastp.p[v][o] : s;
+        G0[k] = in ? gimage.p[v][o] : 0.f;
+        G1[k] = in ? gimage.p[v][plane + o] : 0.f;
+        G2[k] = in ? gimage.p[v][2 * plane + o] : 0.f;
+        S0[k] = bg0;
+        S1[k] = bg1;
+        S2[k] = bg2;
+        maxlast = max(maxlast, last[k]);
+    }
+    // wave max of last
+    for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, o));
+    const float* __restrict__ splat = vt.proj[v].splat;
+    float* __restrict__ g2 = grad2d + (int64_t)v * g2d_view_stride;
+    for (uint32_t hi = maxlast; hi > s;) {
+        const uint32_t lo = hi - s > 64u ? hi - 64u : s;
+        const uint32_t j = lo + lane;
+        if (j < hi) {
+            const uint32_t gid = vals[j];
+            const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
+            const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+            s_a[lane] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+            s_b[lane] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
+            s_c[lane] = make_float4(r2.z, r1.x, r1.y, r1.z);
+            s_gid[lane] = gid;
+        }
+        __syncthreads();
+        for (int jj = (int)(hi - lo) - 1; jj >= 0; --jj) {
+            const uint32_t pos = lo + (uint32_t)jj;
+            const float4 a = s_a[jj];
+            const float4 bb = s_b[jj];
+            const float4 cc = s_c[jj];
+            const float dx = fx - a.x;
+            float gx = 0.f, gy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+            bool hit = false;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                if (pos < last[k]) {
+                    const float dy = (float)(py0 + k * RPK) + 0.5f - a.y;
+                    const float ek = blend_e(a.w, bb.x, bb.y, dx, dy);
+                    const float raw = a.z * ek;
+                    const float al = fminf(kAlphaMax, raw);
+                    if (al >= kAlphaMin) {
+                        hit = true;
+                        const float Ti = T[k] * __builtin_amdgcn_rcpf(1.f - al);
+                        const float w = al * Ti;
+                        gr = __builtin_fmaf(w, G0[k], gr);
+                        gg = __builtin_fmaf(w, G1[k], gg);
+                        gb = __builtin_fmaf(w, G2[k], gb);
+                        const float dLda = Ti * ((bb.z - S0[k]) * G0[k] + (bb.w - S1[k]) * G1[k] + (cc.x - S2[k]) * G2[k]);
+                        S0[k] = __builtin_fmaf(al, bb.z - S0[k], S0[k]);
+                        S1[k] = __builtin_fmaf(al, bb.w - S1[k], S1[k]);
+                        S2[k] = __builtin_fmaf(al, cc.x - S2[k], S2[k]);
+                        T[k] = Ti;
+                        if (raw <= kAlphaMax) {
+                            go = __builtin_fmaf(dLda, ek, go);
+                            const float dq = -0.5f * al * dLda;
+                            gx -= dq * 2.f * (cc.y * dx + cc.z * dy);
+                            gy -= dq * 2.f * (cc.z * dx + cc.w * dy);
+                            gA = __builtin_fmaf(dq, dx * dx, gA);
+                            gB = __builtin_fmaf(dq, 2.f * dx * dy, gB);
+                            gC = __builtin_fmaf(dq, dy * dy, gC);
+                        }
+                    }
+                }
+            }
+            if (__ballot(hit) == 0) continue;
+            gx = wave_sum_to_lane63(gx);
+            gy = wave_sum_to_lane63(gy);
+            gA = wave_sum_to_lane63(gA);
+            gB = wave_sum_to_lane63(gB);
+            gC = wave_sum_to_lane63(gC);
+            go = wave_sum_to_lane63(go);
+            gr = wave_sum_to_lane63(gr);
+            gg = wave_sum_to_lane63(gg);
+            gb = wave_sum_to_lane63(gb);
+            const float t0 = __shfl(gx, 63), t1 = __shfl(gy, 63), t2 = __shfl(gA, 63), t3 = __shfl(gB, 63),
+                        t4 = __shfl(gC, 63), t5 = __shfl(go, 63), t6 = __shfl(gr, 63), t7 = __shfl(gg, 63),
+                        t8 = __shfl(gb, 63);
+            if (lane < 9) {
+                const float val = lane == 0 ? t0 : lane == 1 ? t1 : lane == 2 ? t2 : lane == 3 ? t3 : lane == 4 ? t4
+                                : lane == 5 ? t5 : lane == 6 ? t6 : lane == 7 ? t7 : t8;
+                atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
+            }
+        }
+        __syncthreads();
+        hi = lo;
+    }
+}
+
+template <int TW, int TH>
+qg_status launch_fwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* ranges, const float* bg,
+                     const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp, hipStream_t s) {
+    const int64_t per = ceil_div(vt.total_tiles, 8);
+    k_render_fwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp, per);
+    QG_LAUNCH_CHECK("qg_render_fwd");
+    return QG_OK;
+}
+
+template <int TW, int TH>
+qg_status launch_bwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* ranges, const float* bg,
+                     const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi, float* grad2d,
+                     int64_t stride, hipStream_t s) {
+    const int64_t per = ceil_div(vt.total_tiles, 8);
+    k_render_bwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
+                                                             grad2d, stride, per);
+    QG_LAUNCH_CHECK("qg_render_bwd");
+    return QG_OK;
+}
+
+}  // namespace
+
+}  // namespace qg
+
+using namespace qg;
+
+extern "C" qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                                   const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
+                                   float* const* image, float* const* T_final, uint32_t* const* last,
+                                   qg_stream stream) {
+    clear_error();
+    ViewTable vt;
+    if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
+    QG_REQUIRE(tile_ranges && bg && image && T_final && last, "a required pointer is NULL");
+    ViewPtrsF img = {}, tf = {};
+    ViewPtrsU lp = {};
+    for (int v = 0; v < V; ++v) {
+        QG_REQUIRE(image[v] && T_final[v] && last[v], "view %d: an output pointer is NULL", v);
+        img.p[v] = image[v];
+        tf.p[v] = T_final[v];
+        lp.p[v] = last[v];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (tiling.tile_w == 16) return launch_fwd<16, 16>(vt, vals, tile_ranges, bg, img, tf, lp, s);
+    if (tiling.tile_w == 8) return launch_fwd<8, 8>(vt, vals, tile_ranges, bg, img, tf, lp, s);
+    return launch_fwd<32, 8>(vt, vals, tile_ranges, bg, img, tf, lp, s);
+}
+
+extern "C" size_t qg_render_bwd_workspace_size(int64_t n, int32_t V) {
+    if (n < 0 || V < 1) return 0;
+    return align_up((size_t)V * (size_t)(n > 0 ? n : 1) * QG_GRAD2D_STRIDE * sizeof(float));
+}
+
+extern "C" qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, int32_t sh_degree,
+                                   const qg_camera* cams, int32_t V, qg_tiling tiling, float dilation,
+                                   const qg_projected* proj, const uint32_t* vals, const uint32_t* tile_ranges,
+                                   const float* bg, const float* const* T_final, const uint32_t* const* last,
+                                   const float* const* grad_image, float* grad_attrs, float* grad_xy_abs,
+                                   float* const* grad_xy, void* ws, size_t ws_bytes, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0 && ld >= n && n < (1ll << 31), "n=%lld ld=%lld invalid", (long long)n, (long long)ld);
+    QG_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree=%d outside [0, 3]", sh_degree);
+    QG_REQUIRE(dilation >= 0.f, "dilation < 0");
+    ViewTable vt;
+    if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
+    QG_REQUIRE(tile_ranges && bg && T_final && last && grad_image, "a required pointer is NULL");
+    QG_REQUIRE(n == 0 || (attrs && grad_attrs), "attrs/grad_attrs NULL");
+    const size_t need = qg_render_bwd_workspace_size(n, V);
+    QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    ViewPtrsCF tf = {}, gi = {};
+    ViewPtrsCU lp = {};
+    for (int v = 0; v < V; ++v) {
+        QG_REQUIRE(T_final[v] && last[v] && grad_image[v], "view %d: an input pointer is NULL", v);
+        tf.p[v] = T_final[v];
+        lp.p[v] = last[v];
+        gi.p[v] = grad_image[v];
+    }
+    if (n == 0) return QG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    float* grad2d = (float*)ws;
+    const int64_t stride = n * QG_GRAD2D_STRIDE;
+    qg_status st = qg_zero(grad2d, (int64_t)V * stride * 4, stream);
+    if (st != QG_OK) return st;
+    if (tiling.tile_w == 16)
+        st = launch_bwd<16, 16>(vt, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
+    else if (tiling.tile_w == 8)
+        st = launch_bwd<8, 8>(vt, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
+    else
+        st = launch_bwd<32, 8>(vt, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
+    if (st != QG_OK) return st;
+    return project_bwd_launch(n, ld, attrs, sh_degree, vt, dilation, grad2d, stride, grad_attrs, grad_xy_abs,
+                              grad_xy, s);
+}

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of ``libqg.so`` (the C ABI in ``include/qg.h``), argument marshalling only.
+
+Every function has the name of its C entry point.  Device buffers are passed as torch tensors (or raw
+integer addresses); host structures (cameras, tiling, projected-buffer tables) are built here.  A
+non-OK status raises ``QGError`` with ``qg_last_error()``.  Loading fails loudly if the library has
+not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqg.so")
+
+QG_OK = 0
+QG_ERR_ARG = -1
+QG_ERR_HIP = -2
+QG_ERR_UNSUPPORTED = -3
+N_PLANES = 59
+MAX_VIEWS = 16
+SPLAT_STRIDE = 12
+
+
+class QGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qg status {status}: {msg}")
+        self.status = status
+
+
+class qg_camera(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("z_near", ctypes.c_float)]
+
+
+class qg_tiling(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+
+
+class qg_projected(ctypes.Structure):
+    _fields_ = [("splat", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("rect", ctypes.c_void_p),
+                ("ntiles", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_04469_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, f32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+        CAM = ctypes.POINTER(qg_camera)
+        PRJ = ctypes.POINTER(qg_projected)
+        sig = {
+            "qg_last_error": ([], ctypes.c_char_p),
+            "qg_version": ([], i32),
+            "qg_zero": ([P, i64, P], i32),
+            "qg_total_tiles": ([CAM, i32, qg_tiling], i64),
+            "qg_decode_residuals": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, P, P, P, P], i32),
+            "qg_decode_lreg_blocks": ([i64], i64),
+            "qg_decode_bwd_workspace_size": ([i64, i32, i32, i32], sz),
+            "qg_decode_residuals_bwd": ([i64, i64, P, i32, P, P, i32, i32, P, P, f32, f32, f32, P, f32, P, P, P, P, P,
+                                         P, sz, P], i32),
+            "qg_project": ([i64, i64, P, i32, CAM, i32, qg_tiling, f32, PRJ, P], i32),
+            "qg_bin_workspace_size": ([i64, i32, i64, i64], sz),
+            "qg_bin": ([i64, PRJ, CAM, i32, qg_tiling, i64, P, P, P, P, P, sz, P], i32),
+            "qg_render_fwd": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P, P, P], i32),
+            "qg_render_bwd_workspace_size": ([i64, i32], sz),
+            "qg_render_bwd": ([i64, i64, P, i32, CAM, i32, qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, sz, P],
+                              i32),
+            "qg_loss_blocks": ([i64], i64),
+            "qg_l1_loss": ([i64, P, P, f32, P, P, P], i32),
+            "qg_loss_reduce": ([i64, P, P, P], i32),
+            "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [n for n in dir(lib()) if n.startswith("qg_")]
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status):
+    if status != QG_OK:
+        raise QGError(status, lib().qg_last_error().decode())
+
+
+def make_camera(cam) -> qg_camera:
+    """qg_camera from an object with fx, fy, cx, cy, R [3,3], t [3], width, height, z_near."""
+    c = qg_camera()
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    t = np.asarray(cam.t, np.float32).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    c.width, c.height, c.z_near = int(cam.width), int(cam.height), float(cam.z_near)
+    return c
+
+
+def camera_array(cams):
+    arr = (qg_camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k] = c if isinstance(c, qg_camera) else make_camera(c)
+    return arr
+
+
+def tiling(tw=16, th=16) -> qg_tiling:
+    return qg_tiling(int(tw), int(th))
+
+
+def projected_array(bufs):
+    """bufs: list of dicts with splat, depth, rect, ntiles, flags tensors."""
+    arr = (qg_projected * len(bufs))()
+    for k, b in enumerate(bufs):
+        arr[k] = qg_projected(_ptr(b["splat"]), _ptr(b["depth"]), _ptr(b["rect"]), _ptr(b["ntiles"]), _ptr(b["flags"]))
+    return arr
+
+
+def _ptr_array(xs):
+    arr = (ctypes.c_void_p * len(xs))()
+    for k, x in enumerate(xs):
+        arr[k] = _ptr(x)
+    return arr
+
+
+# ---------------------------------------------------------------------------------------------- calls
+
+def qg_version():
+    return lib().qg_version()
+
+
+def qg_zero(dst, nbytes, stream=None):
+    _check(lib().qg_zero(_ptr(dst), int(nbytes), _stream(stream)))
+
+
+def qg_total_tiles(cams, tile):
+    ca = camera_array(cams)
+    return int(lib().qg_total_tiles(ca, len(cams), tile))
+
+
+def qg_decode_residuals(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
+                        attrs_out, gate_out=None, lreg_partial=None, stream=None):
+    _check(lib().qg_decode_residuals(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), int(L), _ptr(W1), _ptr(W2),
+                                     int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
+                                     float(tau), _ptr(attrs_out), _ptr(gate_out), _ptr(lreg_partial),
+                                     _stream(stream)))
+
+
+def qg_decode_lreg_blocks(n):
+    return int(lib().qg_decode_lreg_blocks(int(n)))
+
+
+def qg_decode_bwd_workspace_size(n, L, Hd, M):
+    return int(lib().qg_decode_bwd_workspace_size(int(n), int(L), int(Hd), int(M)))
+
+
+def qg_decode_residuals_bwd(n, ld, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau, grad_attrs,
+                            lambda_reg, grad_latents, grad_W1, grad_W2, grad_pos_pre, grad_gate_logit, ws, ws_bytes,
+                            stream=None):
+    _check(lib().qg_decode_residuals_bwd(int(n), int(ld), _ptr(latents), int(L), _ptr(W1), _ptr(W2), int(Hd), int(M),
+                                         _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1), float(tau),
+                                         _ptr(grad_attrs), float(lambda_reg), _ptr(grad_latents), _ptr(grad_W1),
+                                         _ptr(grad_W2), _ptr(grad_pos_pre), _ptr(grad_gate_logit), _ptr(ws),
+                                         int(ws_bytes), _stream(stream)))
+
+
+def qg_project(n, ld, attrs, sh_degree, cams, tile, dilation, out, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(out)
+    _check(lib().qg_project(int(n), int(ld), _ptr(attrs), int(sh_degree), ca, len(cams), tile, float(dilation), pa,
+                            _stream(stream)))
+
+
+def qg_bin_workspace_size(n, V, capacity, total_tiles):
+    return int(lib().qg_bin_workspace_size(int(n), int(V), int(capacity), int(total_tiles)))
+
+
+def qg_bin(n, proj, cams, tile, capacity, vals, keys, tile_ranges, num_pairs, ws, ws_bytes, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    _check(lib().qg_bin(int(n), pa, ca, len(cams), tile, int(capacity), _ptr(vals), _ptr(keys), _ptr(tile_ranges),
+                        _ptr(num_pairs), _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def qg_render_fwd(proj, cams, tile, vals, tile_ranges, bg, image, T_final, last, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    bga = (ctypes.c_float * 3)(*[float(b) for b in bg])
+    _check(lib().qg_render_fwd(pa, ca, len(cams), tile, _ptr(vals), _ptr(tile_ranges), bga, _ptr_array(image),
+                               _ptr_array(T_final), _ptr_array(last), _stream(stream)))
+
+
+def qg_render_bwd_workspace_size(n, V):
+    return int(lib().qg_render_bwd_workspace_size(int(n), int(V)))
+
+
+def qg_render_bwd(n, ld, attrs, sh_degree, cams, tile, dilation, proj, vals, tile_ranges, bg, T_final, last,
+                  grad_image, grad_attrs, grad_xy_abs, grad_xy, ws, ws_bytes, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    bga = (ctypes.c_float * 3)(*[float(b) for b in bg])
+    gxy = None if grad_xy is None else _ptr_array(grad_xy)
+    _check(lib().qg_render_bwd(int(n), int(ld), _ptr(attrs), int(sh_degree), ca, len(cams), tile, float(dilation), pa,
+                               _ptr(vals), _ptr(tile_ranges), bga, _ptr_array(T_final), _ptr_array(last),
+                               _ptr_array(grad_image), _ptr(grad_attrs), _ptr(grad_xy_abs), gxy, _ptr(ws),
+                               int(ws_bytes), _stream(stream)))
+
+
+def qg_loss_blocks(count):
+    return int(lib().qg_loss_blocks(int(count)))
+
+
+def qg_l1_loss(count, image, gt, scale, grad_image, partials, stream=None):
+    _check(lib().qg_l1_loss(int(count), _ptr(image), _ptr(gt), float(scale), _ptr(grad_image), _ptr(partials),
+                            _stream(stream)))
+
+
+def qg_loss_reduce(count, partials, out, stream=None):
+    _check(lib().qg_loss_reduce(int(count), _ptr(partials), _ptr(out), _stream(stream)))
+
+
+def qg_adam(count, param, grad, m, v, lr, b1, b2, eps, t, stream=None):
+    _check(lib().qg_adam(int(count), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr), float(b1), float(b2),
+                         float(eps), int(t), _stream(stream)))

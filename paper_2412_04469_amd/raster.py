@@ -1,0 +1,153 @@
+"""Device buffers and autograd glue around the C ABI (no arithmetic of the method happens here).
+
+``Rasterizer`` owns, for a fixed set of cameras and Gaussian count, every buffer that qg_project,
+qg_bin, qg_render_fwd and qg_render_bwd need, and enqueues the calls on the current stream.  The bin
+capacity grows on demand: after a step whose pair count exceeded the capacity, the step is re-binned.
+``RasterizeFn`` and ``DecodeFn`` wrap the hand-written adjoints as ``torch.autograd.Function``s.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import qg
+
+
+def _u32(shape, device):
+    return torch.empty(shape, dtype=torch.int32, device=device)
+
+
+class Rasterizer:
+    def __init__(self, n, cams, tile=(16, 16), sh_degree=3, dilation=0.3, bg=(0.0, 0.0, 0.0), device="cuda",
+                 capacity=None, want_keys=False):
+        self.n = int(n)
+        self.cams = list(cams)
+        self.V = len(self.cams)
+        self.tile = qg.tiling(*tile)
+        self.tile_wh = tuple(tile)
+        self.sh_degree = int(sh_degree)
+        self.dilation = float(dilation)
+        self.bg = tuple(float(b) for b in bg)
+        self.device = torch.device(device)
+        self.want_keys = want_keys
+        self.qcams = qg.camera_array(self.cams)
+        d = self.device
+        n1 = max(self.n, 1)
+        self.proj = [{"splat": torch.zeros(n1, qg.SPLAT_STRIDE, device=d),
+                      "depth": torch.zeros(n1, device=d),
+                      "rect": torch.zeros(n1, 4, dtype=torch.int32, device=d),
+                      "ntiles": torch.zeros(n1, dtype=torch.int32, device=d),
+                      "flags": torch.zeros(n1, dtype=torch.uint8, device=d)} for _ in range(self.V)]
+        self.images = [torch.zeros(3, c.height, c.width, device=d) for c in self.cams]
+        self.tfinal = [torch.zeros(c.height, c.width, device=d) for c in self.cams]
+        self.last = [_u32((c.height, c.width), d) for c in self.cams]
+        self.total_tiles = qg.qg_total_tiles(self.cams, self.tile)
+        self.ranges = _u32((self.total_tiles, 2), d)
+        self.num_pairs = torch.zeros(1, dtype=torch.int64, device=d)
+        if capacity is None:
+            capacity = max(1024, 16 * self.n * self.V)
+        self._alloc_capacity(int(capacity))
+        self.bwd_ws_bytes = qg.qg_render_bwd_workspace_size(self.n, self.V)
+        self.bwd_ws = torch.empty(self.bwd_ws_bytes, dtype=torch.uint8, device=d)
+
+    def _alloc_capacity(self, cap):
+        self.capacity = int(min(cap, 2 ** 32 - 1))
+        d = self.device
+        self.vals = _u32((max(self.capacity, 1),), d)
+        self.keys = torch.empty(max(self.capacity, 1), dtype=torch.int64, device=d) if self.want_keys else None
+        self.bin_ws_bytes = qg.qg_bin_workspace_size(self.n, self.V, self.capacity, self.total_tiles)
+        self.bin_ws = torch.empty(self.bin_ws_bytes, dtype=torch.uint8, device=d)
+
+    # -- individual ABI steps -----------------------------------------------------------------
+    def project(self, attrs, stream=None):
+        qg.qg_project(self.n, attrs.stride(0), attrs, self.sh_degree, self.qcams, self.tile, self.dilation, self.proj,
+                      stream)
+
+    def bin(self, stream=None):
+        qg.qg_bin(self.n, self.proj, self.qcams, self.tile, self.capacity, self.vals, self.keys, self.ranges,
+                  self.num_pairs, self.bin_ws, self.bin_ws_bytes, stream)
+
+    def render(self, stream=None):
+        qg.qg_render_fwd(self.proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.images, self.tfinal,
+                         self.last, stream)
+
+    def ensure_capacity(self, margin=1.25) -> bool:
+        """Host-synchronising check of the last bin; grows the buffers and returns True if it overflowed."""
+        p = int(self.num_pairs.item())
+        if p > self.capacity:
+            self._alloc_capacity(int(math.ceil(p * margin)))
+            return True
+        return False
+
+    def forward(self, attrs, stream=None, check=True):
+        """project -> bin -> render; returns the list of per-view images [3,H,W]."""
+        self.project(attrs, stream)
+        self.bin(stream)
+        if check and self.ensure_capacity():
+            self.bin(stream)
+        self.render(stream)
+        return self.images
+
+    def backward(self, attrs, grad_images, grad_attrs, grad_xy_abs=None, grad_xy=None, stream=None):
+        """Accumulate dL/dattrs (+=) for dL/dimages."""
+        qg.qg_render_bwd(self.n, attrs.stride(0), attrs, self.sh_degree, self.qcams, self.tile, self.dilation,
+                         self.proj, self.vals, self.ranges, self.bg, self.tfinal, self.last,
+                         [g.contiguous() for g in grad_images], grad_attrs, grad_xy_abs, grad_xy, self.bwd_ws,
+                         self.bwd_ws_bytes, stream)
+
+
+class RasterizeFn(torch.autograd.Function):
+    """images = R(attrs) for all cameras of ``rast`` (Eq. 1-2); backward by the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, attrs, rast: Rasterizer):
+        attrs = attrs.contiguous()
+        imgs = rast.forward(attrs)
+        ctx.rast = rast
+        ctx.save_for_backward(attrs)
+        return tuple(im.clone() for im in imgs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        (attrs,) = ctx.saved_tensors
+        rast = ctx.rast
+        g_attrs = torch.zeros_like(attrs)
+        gi = [g if g is not None else torch.zeros_like(im) for g, im in zip(grads, rast.images)]
+        rast.backward(attrs, gi, g_attrs)
+        return g_attrs, None
+
+
+class DecodeFn(torch.autograd.Function):
+    """(attrs, L_reg) = decode(prev, latents, W1, W2, l_p, a) (Eq. 4-8) with the straight-through estimator."""
+
+    @staticmethod
+    def forward(ctx, latents, W1, W2, l_p, a, prev, gamma0, gamma1, tau):
+        n = prev.shape[1]
+        out = torch.empty_like(prev)
+        gate = torch.empty(max(n, 1), device=prev.device)
+        nb = qg.qg_decode_lreg_blocks(n)
+        part = torch.empty(nb, device=prev.device)
+        qg.qg_decode_residuals(n, prev.stride(0), prev, latents, latents.shape[0], W1, W2, W1.shape[0], W2.shape[0],
+                               l_p, a, gamma0, gamma1, tau, out, gate, part)
+        lreg = part.sum() / max(n, 1)
+        ctx.save_for_backward(latents, W1, W2, l_p, a)
+        ctx.hp = (gamma0, gamma1, tau, n, prev.stride(0))
+        return out, lreg
+
+    @staticmethod
+    def backward(ctx, g_out, g_lreg):
+        latents, W1, W2, l_p, a = ctx.saved_tensors
+        gamma0, gamma1, tau, n, ld = ctx.hp
+        g_out = torch.zeros((59, ld), device=a.device) if g_out is None else g_out.contiguous()
+        lam = float(g_lreg) if g_lreg is not None else 0.0
+        gl = torch.zeros_like(latents)
+        gW1 = torch.zeros_like(W1)
+        gW2 = torch.zeros_like(W2)
+        glp = torch.zeros_like(l_p)
+        ga = torch.zeros_like(a)
+        wsb = qg.qg_decode_bwd_workspace_size(n, latents.shape[0], W1.shape[0], W2.shape[0])
+        ws = torch.empty(wsb, dtype=torch.uint8, device=a.device)
+        qg.qg_decode_residuals_bwd(n, ld, latents, latents.shape[0], W1, W2, W1.shape[0], W2.shape[0], l_p, a, gamma0,
+                                   gamma1, tau, g_out, lam, gl, gW1, gW2, glp, ga, ws, wsb)
+        return gl, gW1, gW2, glp, ga, None, None, None, None

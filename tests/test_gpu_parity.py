@@ -1,0 +1,341 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: images and T_final within 1e-4 absolute, gradients within 1e-3 relative L2 per attribute
+group, integer outputs (tile rectangles, sorted keys/values, ranges, pair counts, last contributor)
+bit-exact.  Pixels whose oracle decision margin (1/255 skip, 0.99 clamp, T < 1e-4 stop, order of two
+adjacent depths) is below MARGIN_FWD may decide differently in float32 and are excluded and counted.
+"""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import MARGIN_FWD, cams_small, rel_l2, small_scene, splat_fields, to_dev
+from oracle import binning as OB
+from oracle import composite as OC
+from oracle import decode as OD
+from oracle import loss as OL
+from oracle import project as OP
+from oracle import render as OR
+from paper_2412_04469_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qgm():
+    from paper_2412_04469_amd import qg, raster
+    qg.lib()
+    return qg, raster
+
+
+def _oracle_proj(scene, cam, deg=3, dil=0.3):
+    return OP.project(*OP.scene_tensors(scene), cam, deg, dil)
+
+
+@pytest.mark.parametrize("deg", [3, 1])
+def test_project_parity(qgm, deg):
+    qg, raster = qgm
+    sc = small_scene(seed=11, n=3000)
+    cams = cams_small()
+    rast = raster.Rasterizer(sc.n, cams, tile=(16, 16), sh_degree=deg)
+    attrs = to_dev(sc.planes())
+    rast.project(attrs)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        g = splat_fields(rast.proj[v])
+        o = _oracle_proj(sc, cam, deg)
+        valid = o["valid"].numpy()
+        gvalid = (g["flags"] & 0x80) == 0
+        assert np.array_equal(valid, gvalid)
+        assert valid.sum() > 1000
+        np.testing.assert_allclose(g["xy"][valid], o["xy"].detach().numpy()[valid], rtol=1e-5, atol=2e-4)
+        np.testing.assert_allclose(g["depth"][valid], o["depth"].detach().numpy()[valid], rtol=1e-6)
+        np.testing.assert_allclose(g["opacity"][valid], o["opacity"].detach().numpy()[valid], rtol=1e-6)
+        np.testing.assert_allclose(g["rgb"][valid], o["rgb"].detach().numpy()[valid], rtol=1e-5, atol=1e-5)
+        oc = o["conic"].detach().numpy()[valid]
+        scale = np.abs(oc).max(1, keepdims=True)
+        np.testing.assert_allclose(g["conic"][valid] / scale, oc / scale, atol=5e-5)
+        rect, nt, edges = OP.tile_rect(o["xy"].detach().numpy(), o["cov2d"].detach().numpy(),
+                                       o["opacity"].detach().numpy(), valid, cam.width, cam.height, 16, 16)
+        near = (np.abs(edges - np.round(edges)) < 1e-3).any(1) & valid
+        ok = ~near
+        assert np.array_equal(g["rect"][ok], rect[ok])
+        assert np.array_equal(g["ntiles"][ok], nt[ok])
+        assert near.sum() <= 0.01 * valid.sum()
+        # colour-clamp bits agree where the pre-clamp value is not at rounding distance of 0
+        pre = o["rgb_pre"].detach().numpy()
+        far = (np.abs(pre) > 1e-5).all(1) & valid
+        bits = np.stack([(g["flags"] >> c) & 1 for c in range(3)], 1).astype(bool)
+        assert np.array_equal(bits[far], (pre < 0)[far])
+
+
+def _fill_proj_for_bin(qg, bufs, rect, depth):
+    n = len(depth)
+    nt = (rect[:, 2] - rect[:, 0]) * (rect[:, 3] - rect[:, 1])
+    bufs["rect"].copy_(to_dev(rect, torch.int32))
+    bufs["ntiles"].copy_(to_dev(nt.astype(np.int32), torch.int32))
+    bufs["depth"].copy_(to_dev(depth))
+    bufs["flags"].zero_()
+    return nt
+
+
+def _random_rects(rng, n, gw, gh, empty_frac=0.2, max_w=6):
+    x0 = rng.integers(0, gw, n)
+    y0 = rng.integers(0, gh, n)
+    x1 = np.minimum(x0 + 1 + rng.integers(0, max_w, n), gw)
+    y1 = np.minimum(y0 + 1 + rng.integers(0, max_w, n), gh)
+    r = np.stack([x0, y0, x1, y1], 1).astype(np.int32)
+    r[rng.uniform(size=n) < empty_frac] = 0
+    return r
+
+
+@pytest.mark.parametrize("tile,sizes,n", [((16, 16), [(100, 70)], 5000),
+                                          ((8, 8), [(100, 70), (64, 64), (33, 17)], 3000),
+                                          ((32, 8), [(300, 200), (50, 40)], 20000),
+                                          ((16, 16), [(1352, 1014)], 70000)])
+def test_bin_bit_exact(qgm, tile, sizes, n):
+    qg, raster = qgm
+    rng = synth.rng_for(20 + n)
+    cams = [synth.make_camera((0, 0, -4), w, h) for (w, h) in sizes]
+    rast = raster.Rasterizer(n, cams, tile=tile, want_keys=True, capacity=64)
+    keys_all, vals_all = [], []
+    off = 0
+    for v, c in enumerate(cams):
+        gw, gh = -(-c.width // tile[0]), -(-c.height // tile[1])
+        rect = _random_rects(rng, n, gw, gh)
+        depth = rng.uniform(0.3, 30.0, n).astype(np.float32)
+        depth[rng.integers(0, n, n // 10)] = depth[0]  # equal depths: ties by index
+        _fill_proj_for_bin(qg, rast.proj[v], rect, depth)
+        k, vv = OB.make_pairs_fast(rect, depth, gw, off)
+        keys_all.append(k)
+        vals_all.append(vv)
+        off += gw * gh
+    keys = np.concatenate(keys_all)
+    vals = np.concatenate(vals_all)
+    ks, vs = OB.sort_pairs(keys, vals)
+    ranges = OB.tile_ranges(ks, off)
+    # first with a capacity that is too small: overflow reported, nothing emitted, ranges empty
+    rast.bin()
+    torch.cuda.synchronize()
+    assert int(rast.num_pairs.item()) == len(ks)
+    assert (rast.ranges.cpu().numpy() == 0).all()
+    assert rast.ensure_capacity()
+    rast.bin()
+    torch.cuda.synchronize()
+    P = int(rast.num_pairs.item())
+    assert P == len(ks)
+    assert np.array_equal(rast.vals[:P].cpu().numpy().astype(np.uint32), vs)
+    assert np.array_equal(rast.keys[:P].cpu().numpy().view(np.uint64), ks)
+    assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
+
+
+def test_bin_empty(qgm):
+    qg, raster = qgm
+    cams = [synth.make_camera((0, 0, -4), 64, 48)]
+    rast = raster.Rasterizer(0, cams, capacity=16)
+    rast.bin()
+    torch.cuda.synchronize()
+    assert int(rast.num_pairs.item()) == 0
+    assert (rast.ranges.cpu().numpy() == 0).all()
+
+
+def _blend_inputs(qg, rast, sp, cam_w, cam_h, tile):
+    """Write 2D splat records straight into the projected buffers, with rectangles covering the whole image."""
+    n = len(sp["opacity"])
+    rec = np.zeros((n, 12), np.float32)
+    rec[:, 0:2] = sp["xy"]
+    rec[:, 2] = sp["opacity"]
+    rec[:, 4:7] = sp["conic"]
+    rec[:, 8:11] = sp["rgb"]
+    gw, gh = -(-cam_w // tile[0]), -(-cam_h // tile[1])
+    rect = np.tile(np.array([0, 0, gw, gh], np.int32), (n, 1))
+    b = rast.proj[0]
+    b["splat"].copy_(to_dev(rec))
+    _fill_proj_for_bin(qg, b, rect, sp["depth"])
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.25, 0.5, 0.75)])
+def test_blend_fwd_parity_and_tiling_invariance(qgm, bg):
+    qg, raster = qgm
+    W, H, n = 100, 70, 600
+    sp = synth.random_splats(synth.rng_for(31), n, W, H, radius_px=(1.0, 10.0), opacity=(0.02, 0.99))
+    cam = synth.make_camera((0, 0, -4), W, H)
+    ref = OC.composite_image(sp, W, H, bg)
+    keep = ref["margin"] >= MARGIN_FWD
+    assert keep.mean() > 0.99
+    outs = []
+    for tile in [(16, 16), (8, 8), (32, 8)]:
+        rast = raster.Rasterizer(n, [cam], tile=tile, bg=bg)
+        _blend_inputs(qg, rast, sp, W, H, tile)
+        rast.bin()
+        assert not rast.ensure_capacity()
+        rast.render()
+        torch.cuda.synchronize()
+        img = rast.images[0].cpu().numpy()
+        tf = rast.tfinal[0].cpu().numpy()
+        last = rast.last[0].cpu().numpy().astype(np.int64)
+        vals = rast.vals.cpu().numpy().astype(np.int64)
+        gid = np.where(last > 0, vals[np.maximum(last - 1, 0)], -1)
+        # a pixel with no contributor has last == its tile start; map those to -1
+        starts = rast.ranges.cpu().numpy()[:, 0].astype(np.int64)
+        gw = -(-W // tile[0])
+        ti = (np.arange(H)[:, None] // tile[1]) * gw + (np.arange(W)[None, :] // tile[0])
+        gid = np.where(last == starts[ti], -1, gid)
+        assert np.abs(img - ref["image"])[:, keep].max() <= 1e-4
+        assert np.abs(tf - ref["t_final"])[keep].max() <= 1e-4
+        assert np.array_equal(gid[keep], ref["last_id"][keep])
+        outs.append((img, tf))
+    for img, tf in outs[1:]:
+        assert np.array_equal(img, outs[0][0]) and np.array_equal(tf, outs[0][1])
+
+
+def _gpu_chain(raster, sc, cams, tile=(16, 16), deg=3, bg=(0.0, 0.0, 0.0)):
+    rast = raster.Rasterizer(sc.n, cams, tile=tile, sh_degree=deg, bg=bg)
+    attrs = to_dev(sc.planes())
+    rast.forward(attrs)
+    torch.cuda.synchronize()
+    return rast, attrs
+
+
+def _gid_of_last(rast, v, tile):
+    cam = rast.cams[v]
+    W, H = cam.width, cam.height
+    last = rast.last[v].cpu().numpy().astype(np.int64)
+    vals = rast.vals.cpu().numpy().astype(np.int64)
+    starts = rast.ranges.cpu().numpy()[:, 0].astype(np.int64)
+    gw = -(-W // tile[0])
+    gh = -(-H // tile[1])
+    off = sum(-(-c.width // tile[0]) * -(-c.height // tile[1]) for c in rast.cams[:v])
+    ti = off + (np.arange(H)[:, None] // tile[1]) * gw + (np.arange(W)[None, :] // tile[0])
+    gid = np.where(last > 0, vals[np.maximum(last - 1, 0)], -1)
+    return np.where(last == starts[ti], -1, gid)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_chain_fwd_parity(qgm, tile):
+    qg, raster = qgm
+    sc = small_scene(seed=12, n=4000)
+    cams = cams_small(150, 110)
+    bg = (0.1, 0.2, 0.3)
+    rast, _ = _gpu_chain(raster, sc, cams, tile, bg=bg)
+    for v, cam in enumerate(cams):
+        ref = OR.render(sc.planes().astype(np.float64), cam, bg)
+        keep = ref["margin"] >= MARGIN_FWD
+        assert keep.mean() > 0.995, keep.mean()
+        img = rast.images[v].cpu().numpy()
+        assert np.abs(img - ref["image"])[:, keep].max() <= 1e-4
+        assert np.abs(rast.tfinal[v].cpu().numpy() - ref["t_final"])[keep].max() <= 1e-4
+        gid = _gid_of_last(rast, v, tile)
+        assert np.array_equal(gid[keep], ref["last_id"][keep])
+
+
+def _groups(g):
+    return {"mean": g[0:3], "quat": g[3:7], "log_scale": g[7:10], "logit": g[10:11], "sh_dc": g[11:14],
+            "sh_rest": g[14:59]}
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_chain_bwd_parity(qgm, tile):
+    qg, raster = qgm
+    sc = small_scene(seed=13, n=2500)
+    cams = cams_small(128, 96)
+    bg = (0.2, 0.1, 0.3)
+    rast, attrs = _gpu_chain(raster, sc, cams, tile, bg=bg)
+    rng = np.random.default_rng(5)
+    gis, refs = [], []
+    g_ref = np.zeros((59, sc.n))
+    gxy_ref = []
+    for v, cam in enumerate(cams):
+        ref0 = OR.render(sc.planes().astype(np.float64), cam, bg)
+        G = rng.normal(size=(3, cam.height, cam.width)) / (3 * cam.width * cam.height)
+        G[:, ref0["margin"] < MARGIN_FWD] = 0.0
+        G = G.astype(np.float32)
+        planes = torch.tensor(sc.planes().astype(np.float64), requires_grad=True)
+        ref = OR.render(planes, cam, bg, grad_image=G.astype(np.float64))
+        g_ref += planes.grad.numpy()
+        gxy_ref.append(ref["g_xy"])
+        gis.append(to_dev(G))
+    g_attrs = torch.zeros_like(attrs)
+    gabs = torch.zeros(sc.n, device="cuda")
+    gxy = [torch.zeros(2, sc.n, device="cuda") for _ in cams]
+    rast.backward(attrs, gis, g_attrs, gabs, gxy)
+    torch.cuda.synchronize()
+    g = g_attrs.cpu().numpy()
+    for name, gg in _groups(g).items():
+        assert rel_l2(gg, _groups(g_ref)[name]) <= 1e-3, (name, rel_l2(gg, _groups(g_ref)[name]))
+    for v in range(len(cams)):
+        assert rel_l2(gxy[v].cpu().numpy(), gxy_ref[v].T) <= 1e-3
+    np.testing.assert_allclose(gabs.cpu().numpy(),
+                               sum(np.linalg.norm(x, axis=1) for x in gxy_ref), rtol=1e-3, atol=1e-9)
+
+
+def test_decode_parity(qgm):
+    qg, raster = qgm
+    rng = synth.rng_for(40)
+    n = 5000
+    prev = rng.normal(size=(59, n)).astype(np.float32)
+    lat = rng.normal(0, 1.5, size=(8, n)).astype(np.float32)
+    W1 = (rng.normal(size=(32, 8)) * 0.3).astype(np.float32)
+    W2 = (rng.normal(size=(56, 32)) * 0.2).astype(np.float32)
+    lp = rng.normal(0, 0.1, size=(3, n)).astype(np.float32)
+    a = rng.normal(0, 1.0, size=n).astype(np.float32)
+    hp = (-0.5, 1.01, 0.3)
+    Gout = rng.normal(size=(59, n)).astype(np.float32)
+    lam = 0.01
+    # oracle (float64, autograd)
+    t = lambda x: torch.tensor(x.astype(np.float64), requires_grad=True)
+    tl, tW1, tW2, tlp, ta = t(lat), t(W1), t(W2), t(lp), t(a)
+    out, g, lreg = OD.decode(torch.tensor(prev.astype(np.float64)), tl, tW1, tW2, tlp, ta, *hp)
+    ((out * torch.tensor(Gout.astype(np.float64))).sum() + lam * lreg).backward()
+    # GPU
+    d = {k: to_dev(x) for k, x in dict(prev=prev, lat=lat, W1=W1, W2=W2, lp=lp, a=a, G=Gout).items()}
+    o_g = torch.empty_like(d["prev"])
+    gate = torch.empty(n, device="cuda")
+    part = torch.empty(qg.qg_decode_lreg_blocks(n), device="cuda")
+    qg.qg_decode_residuals(n, n, d["prev"], d["lat"], 8, d["W1"], d["W2"], 32, 56, d["lp"], d["a"], *hp, o_g, gate,
+                           part)
+    grads = [torch.zeros_like(d[k]) for k in ("lat", "W1", "W2", "lp", "a")]
+    wsb = qg.qg_decode_bwd_workspace_size(n, 8, 32, 56)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    qg.qg_decode_residuals_bwd(n, n, d["lat"], 8, d["W1"], d["W2"], 32, 56, d["lp"], d["a"], *hp, d["G"], lam,
+                               *grads, ws, wsb)
+    torch.cuda.synchronize()
+    on = out.detach().numpy()
+    scale = np.abs(on - prev) + np.abs(prev) + 1.0
+    assert (np.abs(o_g.cpu().numpy() - on) / scale).max() < 2e-6
+    np.testing.assert_allclose(gate.cpu().numpy(), g.detach().numpy(), rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(part.sum().item() / n, lreg.item(), rtol=1e-5)
+    for name, gg, ref in zip(("lat", "W1", "W2", "lp", "a"), grads, (tl, tW1, tW2, tlp, ta)):
+        assert rel_l2(gg.cpu().numpy(), ref.grad.numpy()) <= 1e-5, name
+
+
+def test_loss_and_adam_parity(qgm):
+    qg, raster = qgm
+    rng = synth.rng_for(41)
+    img = rng.uniform(-0.2, 1.2, size=(3, 67, 91)).astype(np.float32)
+    gt = rng.uniform(0, 1, size=(3, 67, 91)).astype(np.float32)
+    gt.ravel()[::97] = img.ravel()[::97]  # exact ties: sign(0) = 0
+    cnt = img.size
+    d_img, d_gt = to_dev(img), to_dev(gt)
+    grad = torch.empty_like(d_img)
+    part = torch.empty(2 * qg.qg_loss_blocks(cnt), dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    qg.qg_l1_loss(cnt, d_img, d_gt, 1.0, grad, part)
+    qg.qg_loss_reduce(cnt, part, out)
+    torch.cuda.synchronize()
+    l1, g = OL.l1(img, gt)
+    np.testing.assert_allclose(out[0].item(), l1, rtol=1e-6)
+    assert np.array_equal(grad.cpu().numpy(), g.astype(np.float32))
+    mse = ((np.clip(img.astype(np.float64), 0, 1) - gt) ** 2).mean()
+    np.testing.assert_allclose(out[1].item(), mse, rtol=1e-6)
+    np.testing.assert_allclose(-10 * np.log10(out[1].item()), OL.psnr(img, gt), rtol=1e-6)
+    from oracle import adam as OA
+    p = rng.normal(size=1000).astype(np.float32)
+    m = np.zeros(1000); v = np.zeros(1000); pp = p.astype(np.float64)
+    dp, dm, dv = to_dev(p), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    for step in range(1, 4):
+        gr = rng.normal(size=1000).astype(np.float32)
+        qg.qg_adam(1000, dp, to_dev(gr), dm, dv, 0.01, 0.9, 0.999, 1e-8, step)
+        pp, m, v = OA.adam_step(pp, gr.astype(np.float64), m, v, step, 0.01)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dp.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
