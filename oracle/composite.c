@@ -22,7 +22,9 @@
  * the 0.99 clamp is active) and q(d, conic).
  *
  * Decision margins: for each pixel the oracle reports the smallest relative distance of any
- * decision taken on its path to its threshold (skip, clamp, termination, order of adjacent depths).
+ * alpha/transmittance decision taken on its path to its threshold (1/255 skip, 0.99 clamp,
+ * termination) and, separately, the smallest relative gap between two adjacent depths on the path
+ * (an order decision, which can only differ when the two sides compute depths independently).
  * Pixels with a tiny margin may legitimately decide differently in float32 and are excluded from
  * parity comparisons by the tests.
  */
@@ -63,7 +65,7 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
                      double alpha_min, double alpha_max, double t_min, int reverse_t,
                      const double* grad_color,
                      double* color, double* t_final, int64_t* last_id, int32_t* n_contrib,
-                     double* margin,
+                     double* margin, double* order_margin,
                      double* g_xy, double* g_conic, double* g_opacity, double* g_rgb,
                      int nthreads) {
     if (n < 0 || m < 0) return -1;
@@ -98,7 +100,7 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
         for (int64_t p = 0; p < m; ++p) {
             if (!cand || !Tk) continue;
             const double x = px[p], y = py[p];
-            double mg = INFINITY;
+            double mg = INFINITY, og = INFINITY;
             int64_t nc = 0;
             /* 1. all splats with alpha close to or above alpha_min */
             for (int64_t i = 0; i < n; ++i) {
@@ -128,7 +130,7 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
             for (k = 0; k < nc; ++k) {
                 const cand_t* c = &cand[k];
                 if (!isnan(prev_depth) && c->depth != 0.0)
-                    mg = fmin(mg, fabs(c->depth - prev_depth) / fabs(c->depth));
+                    og = fmin(og, fabs(c->depth - prev_depth) / fabs(c->depth));
                 prev_depth = c->depth;
                 if (alpha_min > 0.0) mg = fmin(mg, rel(c->raw, alpha_min));
                 if (isfinite(alpha_max)) mg = fmin(mg, rel(c->raw, alpha_max));
@@ -149,6 +151,7 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
             last_id[p] = last;
             n_contrib[p] = cnt;
             if (margin) margin[p] = mg;
+            if (order_margin) order_margin[p] = og;
             /* 3. adjoint */
             if (do_grad) {
                 const double* G = grad_color + 3 * p;

@@ -41,7 +41,7 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_composite.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64, P, P, P,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                         P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+                                         P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_composite.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -56,7 +56,8 @@ def composite(splats: dict, px: np.ndarray, py: np.ndarray, bg=(0.0, 0.0, 0.0), 
     """Composite the given pixel centres.
 
     splats: dict with xy [N,2], conic [N,3], opacity [N], rgb [N,3], depth [N], optional valid [N] bool.
-    Returns dict: color [M,3], t_final [M], last_id [M] (-1 if none), n_contrib [M], margin [M] and, if
+    Returns dict: color [M,3], t_final [M], last_id [M] (-1 if none), n_contrib [M], margin [M] (alpha and
+    termination decisions), order_margin [M] (relative gap of adjacent depths) and, if
     ``grad_color`` [M,3] is given, g_xy [N,2], g_conic [N,3], g_opacity [N], g_rgb [N,3].
     """
     lib = _load()
@@ -74,7 +75,8 @@ def composite(splats: dict, px: np.ndarray, py: np.ndarray, bg=(0.0, 0.0, 0.0), 
     last = np.zeros(m, np.int64)
     cnt = np.zeros(m, np.int32)
     margin = np.zeros(m)
-    out = {"color": color, "t_final": tf, "last_id": last, "n_contrib": cnt, "margin": margin}
+    order = np.zeros(m)
+    out = {"color": color, "t_final": tf, "last_id": last, "n_contrib": cnt, "margin": margin, "order_margin": order}
     g = [None] * 4
     gc = None
     if grad_color is not None:
@@ -83,7 +85,7 @@ def composite(splats: dict, px: np.ndarray, py: np.ndarray, bg=(0.0, 0.0, 0.0), 
         out.update(g_xy=g[0], g_conic=g[1], g_opacity=g[2], g_rgb=g[3])
     rc = lib.oracle_composite(n, _p(xy), _p(conic), _p(op), _p(rgb), _p(depth), _p(valid), m, _p(px), _p(py),
                               _p(bg), float(alpha_min), float(alpha_max), float(t_min), int(bool(reverse_t)),
-                              _p(gc), _p(color), _p(tf), _p(last), _p(cnt), _p(margin),
+                              _p(gc), _p(color), _p(tf), _p(last), _p(cnt), _p(margin), _p(order),
                               _p(g[0]), _p(g[1]), _p(g[2]), _p(g[3]), int(nthreads))
     if rc != 0:
         raise RuntimeError(f"oracle_composite failed ({rc})")
@@ -104,6 +106,6 @@ def composite_image(splats: dict, width: int, height: int, bg=(0.0, 0.0, 0.0), g
         gc = np.asarray(grad_image, np.float64).reshape(3, height * width).T
     r = composite(splats, px, py, bg, gc, **kw)
     r["image"] = r["color"].T.reshape(3, height, width)
-    for k in ("t_final", "last_id", "n_contrib", "margin"):
+    for k in ("t_final", "last_id", "n_contrib", "margin", "order_margin"):
         r[k] = r[k].reshape(height, width)
     return r

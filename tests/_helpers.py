@@ -6,7 +6,15 @@ import torch
 
 from paper_2412_04469_amd import synth
 
-MARGIN_FWD = 1e-4   # relative decision margin below which a pixel may decide differently in float32
+MARGIN_FWD = 1e-4   # relative alpha/termination margin below which float32 may decide differently
+MARGIN_ORDER = 1e-6  # relative depth gap below which independently computed float32 depths may swap
+
+
+def keep_mask(ref, order=True, margin=MARGIN_FWD):
+    k = ref["margin"] >= margin
+    if order:
+        k &= ref["order_margin"] >= MARGIN_ORDER
+    return k
 
 
 def small_scene(seed=10, n=3000, mean_std=1.0, ls_mu=-3.5, ls_std=0.5):

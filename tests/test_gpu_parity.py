@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from _helpers import MARGIN_FWD, cams_small, rel_l2, small_scene, splat_fields, to_dev
+from _helpers import MARGIN_FWD, cams_small, keep_mask, rel_l2, small_scene, splat_fields, to_dev
 from oracle import binning as OB
 from oracle import composite as OC
 from oracle import decode as OD
@@ -57,7 +57,7 @@ def test_project_parity(qgm, deg):
         np.testing.assert_allclose(g["conic"][valid] / scale, oc / scale, atol=5e-5)
         rect, nt, edges = OP.tile_rect(o["xy"].detach().numpy(), o["cov2d"].detach().numpy(),
                                        o["opacity"].detach().numpy(), valid, cam.width, cam.height, 16, 16)
-        near = (np.abs(edges - np.round(edges)) < 1e-3).any(1) & valid
+        near = (np.abs(edges - np.round(edges)) < 1e-4).any(1) & valid
         ok = ~near
         assert np.array_equal(g["rect"][ok], rect[ok])
         assert np.array_equal(g["ntiles"][ok], nt[ok])
@@ -161,14 +161,15 @@ def test_blend_fwd_parity_and_tiling_invariance(qgm, bg):
     sp = synth.random_splats(synth.rng_for(31), n, W, H, radius_px=(1.0, 10.0), opacity=(0.02, 0.99))
     cam = synth.make_camera((0, 0, -4), W, H)
     ref = OC.composite_image(sp, W, H, bg)
-    keep = ref["margin"] >= MARGIN_FWD
+    keep = keep_mask(ref, order=False, margin=1e-5)  # identical float32 records and depths on both sides
     assert keep.mean() > 0.99
     outs = []
     for tile in [(16, 16), (8, 8), (32, 8)]:
         rast = raster.Rasterizer(n, [cam], tile=tile, bg=bg)
         _blend_inputs(qg, rast, sp, W, H, tile)
         rast.bin()
-        assert not rast.ensure_capacity()
+        if rast.ensure_capacity():
+            rast.bin()
         rast.render()
         torch.cuda.synchronize()
         img = rast.images[0].cpu().numpy()
@@ -220,7 +221,7 @@ def test_chain_fwd_parity(qgm, tile):
     rast, _ = _gpu_chain(raster, sc, cams, tile, bg=bg)
     for v, cam in enumerate(cams):
         ref = OR.render(sc.planes().astype(np.float64), cam, bg)
-        keep = ref["margin"] >= MARGIN_FWD
+        keep = keep_mask(ref)
         assert keep.mean() > 0.995, keep.mean()
         img = rast.images[v].cpu().numpy()
         assert np.abs(img - ref["image"])[:, keep].max() <= 1e-4
@@ -248,7 +249,7 @@ def test_chain_bwd_parity(qgm, tile):
     for v, cam in enumerate(cams):
         ref0 = OR.render(sc.planes().astype(np.float64), cam, bg)
         G = rng.normal(size=(3, cam.height, cam.width)) / (3 * cam.width * cam.height)
-        G[:, ref0["margin"] < MARGIN_FWD] = 0.0
+        G[:, ~keep_mask(ref0)] = 0.0
         G = G.astype(np.float32)
         planes = torch.tensor(sc.planes().astype(np.float64), requires_grad=True)
         ref = OR.render(planes, cam, bg, grad_image=G.astype(np.float64))
