@@ -225,8 +225,21 @@ qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_
 qg_status qg_adam(int64_t count, float* param, const float* grad, float* m, float* v, float lr, float b1,
                   float b2, float eps, int32_t t, qg_stream stream);
 
-/* dst[i] = 0 for i < count (a fill kernel, safe under stream capture). */
+/* Zero `bytes` bytes at dst with a fill kernel (no memset node, so it is safe to capture). */
 qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Diagnostics: per-kernel timing with HIP events.                                                 */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * While enabled, every kernel the library launches (or, if `only` is not NULL, every kernel of that
+ * name) is bracketed by two HIP events recorded on the stream it is launched on.  qg_timing_report()
+ * waits for the recorded events, writes one line "name count total_ms" per kernel name into buf
+ * (NUL-terminated, truncated to len bytes), clears the record and returns the number of names.
+ * Off by default; not for use under stream capture.  `only` [host] is copied.
+ */
+qg_status qg_timing_enable(int32_t on, const char* only);
+int64_t qg_timing_report(char* buf, int64_t len);
 
 #ifdef __cplusplus
 }

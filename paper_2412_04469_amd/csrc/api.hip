@@ -1,6 +1,10 @@
 // Error state, argument tables and small utilities of libqg.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "qg_internal.h"
 
@@ -16,6 +20,51 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { g_err[0] = 0; }
+
+// ---- event timing -------------------------------------------------------------------------------
+namespace {
+struct TimedLaunch {
+    const char* name;
+    hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::string g_only;
+std::vector<TimedLaunch> g_launches;
+std::vector<hipEvent_t> g_pool;
+thread_local const char* t_name = nullptr;
+thread_local hipEvent_t t_start = nullptr;
+
+hipEvent_t get_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+void timing_begin(const char* name, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+    if (!g_only.empty() && g_only != name) return;
+    t_name = name;
+    t_start = get_event();
+    if (t_start) hipEventRecord(t_start, s);
+}
+
+void timing_end(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing || !t_start) return;
+    hipEvent_t stop = get_event();
+    if (!stop) return;
+    hipEventRecord(stop, s);
+    g_launches.push_back({t_name, t_start, stop});
+    t_start = nullptr;
+}
 
 bool tiling_ok(qg_tiling t) {
     return (t.tile_w == 8 && t.tile_h == 8) || (t.tile_w == 16 && t.tile_h == 16) ||
@@ -106,6 +155,41 @@ extern "C" const char* qg_last_error(void) { return g_err; }
 
 extern "C" int32_t qg_version(void) { return 1; }
 
+extern "C" qg_status qg_timing_enable(int32_t on, const char* only) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    g_only = only ? only : "";
+    return QG_OK;
+}
+
+extern "C" int64_t qg_timing_report(char* buf, int64_t len) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    std::map<std::string, std::pair<int64_t, double>> agg;
+    for (auto& l : g_launches) {
+        float ms = 0.f;
+        if (hipEventSynchronize(l.stop) == hipSuccess && hipEventElapsedTime(&ms, l.start, l.stop) == hipSuccess) {
+            auto& a = agg[l.name];
+            a.first += 1;
+            a.second += ms;
+        }
+        g_pool.push_back(l.start);
+        g_pool.push_back(l.stop);
+    }
+    g_launches.clear();
+    std::string out;
+    for (auto& kv : agg) {
+        char line[256];
+        snprintf(line, sizeof(line), "%s %lld %.6f\n", kv.first.c_str(), (long long)kv.second.first, kv.second.second);
+        out += line;
+    }
+    if (buf && len > 0) {
+        const size_t n = std::min<size_t>(out.size(), (size_t)len - 1);
+        std::memcpy(buf, out.data(), n);
+        buf[n] = 0;
+    }
+    return (int64_t)agg.size();
+}
+
 extern "C" int64_t qg_total_tiles(const qg_camera* cams, int32_t V, qg_tiling tiling) {
     ViewTable t;
     if (!make_view_table(cams, nullptr, V, tiling, false, &t)) return -1;
@@ -122,7 +206,10 @@ extern "C" qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream) {
     if (a % 4 == 0 && bytes % 4 == 0) {
         int64_t words = bytes / 4;
         int64_t blocks = std::min<int64_t>(ceil_div(words, 256), 65536);
-        k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)dst, words);
+        {
+            QG_TIMED("zero", s);
+            k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)dst, words);
+        }
     } else {
         k_zero_bytes<<<(unsigned)ceil_div(bytes, 256), 256, 0, s>>>((uint8_t*)dst, bytes);
     }

@@ -215,7 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI* __restrict__ in,
 }
 
 template <typename TI, typename TO>
-qg_status scan_excl(const TI* in, int64_t n, TO* out, TO* part, TO* total, hipStream_t s) {
+qg_status scan_excl(const TI* in, int64_t n, TO* out, TO* part, TO* total, hipStream_t s, const char* tag = "scan") {
+    QG_TIMED(tag, s);
     const int64_t nb = std::max<int64_t>(1, ceil_div(n, kScanTile));
     k_scan_reduce<TI, TO><<<(unsigned)nb, kBlock, 0, s>>>(in, n, part);
     k_scan_partials<TO><<<1, 1024, 0, s>>>(part, nb, total);
@@ -307,24 +308,35 @@ __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __r
 template <int IPT>
 qg_status radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                      const uint32_t* count_ptr, uint32_t count_fixed, int64_t max_count, int shift, uint32_t* hist,
-                     uint32_t* hist_scan, uint32_t* part, hipStream_t s) {
+                     uint32_t* hist_scan, uint32_t* part, hipStream_t s, const char* const* tags) {
     const int nblocks = (int)std::max<int64_t>(1, ceil_div(max_count, IPT * kBlock));
-    k_radix_hist<IPT><<<nblocks, kBlock, 0, s>>>(kin, count_ptr, count_fixed, shift, hist, nblocks);
-    qg_status st = scan_excl<uint32_t, uint32_t>(hist, (int64_t)kRadix * nblocks, hist_scan, part, nullptr, s);
+    {
+        QG_TIMED(tags[0], s);
+        k_radix_hist<IPT><<<nblocks, kBlock, 0, s>>>(kin, count_ptr, count_fixed, shift, hist, nblocks);
+    }
+    qg_status st = scan_excl<uint32_t, uint32_t>(hist, (int64_t)kRadix * nblocks, hist_scan, part, nullptr, s, tags[1]);
     if (st != QG_OK) return st;
-    k_radix_scatter<IPT><<<nblocks, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, shift, hist_scan,
-                                                   nblocks);
+    {
+        QG_TIMED(tags[2], s);
+        k_radix_scatter<IPT><<<nblocks, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, shift, hist_scan,
+                                                       nblocks);
+    }
     QG_LAUNCH_CHECK("radix_pass");
     return QG_OK;
 }
 
 qg_status radix_pass_any(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                          const uint32_t* count_ptr, uint32_t count_fixed, int64_t max_count, int shift,
-                         uint32_t* hist, uint32_t* hist_scan, uint32_t* part, hipStream_t s) {
+                         uint32_t* hist, uint32_t* hist_scan, uint32_t* part, hipStream_t s, const char* const* tags) {
     if (max_count <= (1 << 22))
-        return radix_pass<4>(kin, vin, kout, vout, count_ptr, count_fixed, max_count, shift, hist, hist_scan, part, s);
-    return radix_pass<16>(kin, vin, kout, vout, count_ptr, count_fixed, max_count, shift, hist, hist_scan, part, s);
+        return radix_pass<4>(kin, vin, kout, vout, count_ptr, count_fixed, max_count, shift, hist, hist_scan, part, s,
+                             tags);
+    return radix_pass<16>(kin, vin, kout, vout, count_ptr, count_fixed, max_count, shift, hist, hist_scan, part, s,
+                          tags);
 }
+
+const char* const kDepthTags[3] = {"sort_depth_hist", "sort_depth_scan", "sort_depth_scatter"};
+const char* const kTileTags[3] = {"sort_tile_hist", "sort_tile_scan", "sort_tile_scatter"};
 
 int64_t radix_blocks(int64_t max_count) {
     const int ipt = max_count <= (1 << 22) ? 4 : 16;
@@ -412,19 +424,26 @@ extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera
         return QG_OK;
     }
     // 1. depth keys and the 4-pass depth sort over (view, Gaussian) items
-    k_depth_keys<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(n, vt, w.dkA, w.dvA);
+    {
+        QG_TIMED("bin_depth_keys", s);
+        k_depth_keys<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(n, vt, w.dkA, w.dvA);
+    }
     QG_LAUNCH_CHECK("qg_bin depth keys");
     uint32_t *ka = w.dkA, *va = w.dvA, *kb = w.dkB, *vb = w.dvB;
     for (int pass = 0; pass < 4; ++pass) {
-        st = radix_pass_any(ka, va, kb, vb, nullptr, (uint32_t)items, items, 8 * pass, w.hist, w.hist_scan, w.part32, s);
+        st = radix_pass_any(ka, va, kb, vb, nullptr, (uint32_t)items, items, 8 * pass, w.hist, w.hist_scan, w.part32, s,
+                            kDepthTags);
         if (st != QG_OK) return st;
         std::swap(ka, kb);
         std::swap(va, vb);
     }
     const uint32_t* sorted_items = va;
     // 2. tile counts in depth order, scan, emission
-    k_gather_counts<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(items, n, vt, sorted_items, w.cnt);
-    st = scan_excl<uint32_t, uint64_t>(w.cnt, items, w.offs, w.part64, w.total64, s);
+    {
+        QG_TIMED("bin_counts", s);
+        k_gather_counts<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(items, n, vt, sorted_items, w.cnt);
+    }
+    st = scan_excl<uint32_t, uint64_t>(w.cnt, items, w.offs, w.part64, w.total64, s, "bin_count_scan");
     if (st != QG_OK) return st;
     k_finish_count<<<1, 1, 0, s>>>(w.total64, capacity, w.sort_count, num_pairs);
     QG_LAUNCH_CHECK("qg_bin count");
@@ -434,21 +453,27 @@ extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera
     const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
     uint32_t* vbuf0 = (tpasses % 2 == 1) ? w.tvB : vals;
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
-    k_emit<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(items, n, vt, sorted_items, w.cnt, w.offs, w.sort_count,
-                                                          w.tkA, vbuf0);
+    {
+        QG_TIMED("bin_emit", s);
+        k_emit<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(items, n, vt, sorted_items, w.cnt, w.offs,
+                                                              w.sort_count, w.tkA, vbuf0);
+    }
     QG_LAUNCH_CHECK("qg_bin emit");
     // 3. stable sort by tile id
     uint32_t *tk_in = w.tkA, *tk_out = w.tkB, *tv_in = vbuf0, *tv_out = vbuf1;
     for (int pass = 0; pass < tpasses; ++pass) {
         st = radix_pass_any(tk_in, tv_in, tk_out, tv_out, w.sort_count, 0u, capacity, 8 * pass, w.hist, w.hist_scan,
-                            w.part32, s);
+                            w.part32, s, kTileTags);
         if (st != QG_OK) return st;
         std::swap(tk_in, tk_out);
         std::swap(tv_in, tv_out);
     }
     // tk_in / tv_in hold the sorted pairs; tv_in == vals by construction
     // 4. tile ranges (and optional 64-bit keys)
-    k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges);
+    {
+        QG_TIMED("bin_ranges", s);
+        k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges);
+    }
     QG_LAUNCH_CHECK("qg_bin ranges");
     if (keys) {
         k_keys64<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, tv_in, w.sort_count, vt, keys);

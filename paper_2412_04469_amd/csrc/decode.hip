@@ -256,8 +256,11 @@ extern "C" qg_status qg_decode_residuals(int64_t n, int64_t ld, const float* pre
         return QG_OK;
     }
     const float shift = tau * logf(-gamma0 / gamma1);
-    k_decode_fwd<<<(unsigned)nb, kDecBlock, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
-                                                    gamma1, tau, shift, attrs_out, gate_out, lreg_partial);
+    {
+        QG_TIMED("decode_fwd", s);
+        k_decode_fwd<<<(unsigned)nb, kDecBlock, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
+                                                        gamma1, tau, shift, attrs_out, gate_out, lreg_partial);
+    }
     QG_LAUNCH_CHECK("qg_decode_residuals");
     return QG_OK;
 }
@@ -293,11 +296,17 @@ extern "C" qg_status qg_decode_residuals_bwd(int64_t n, int64_t ld, const float*
     const int64_t nb = bwd_blocks(n);
     const float shift = tau * logf(-gamma0 / gamma1);
     const float reg_scale = lambda_reg / (float)n;
-    k_decode_bwd<<<(unsigned)nb, kBB, 0, s>>>(n, ld, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau, shift,
-                                              reg_scale, grad_attrs, grad_latents, grad_pos_pre, grad_gate_logit,
-                                              (float*)ws);
+    {
+        QG_TIMED("decode_bwd", s);
+        k_decode_bwd<<<(unsigned)nb, kBB, 0, s>>>(n, ld, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau, shift,
+                                                  reg_scale, grad_attrs, grad_latents, grad_pos_pre, grad_gate_logit,
+                                                  (float*)ws);
+    }
     const int width = kH * kL + kM * kH;
-    k_reduce_parts<<<(unsigned)ceil_div(width, 256), 256, 0, s>>>((const float*)ws, nb, width, grad_W1, grad_W2);
+    {
+        QG_TIMED("decode_wreduce", s);
+        k_reduce_parts<<<(unsigned)ceil_div(width, 256), 256, 0, s>>>((const float*)ws, nb, width, grad_W1, grad_W2);
+    }
     QG_LAUNCH_CHECK("qg_decode_residuals_bwd");
     return QG_OK;
 }

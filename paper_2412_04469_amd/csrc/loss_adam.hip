@@ -88,7 +88,10 @@ extern "C" qg_status qg_l1_loss(int64_t count, const float* image, const float* 
     hipStream_t s = (hipStream_t)stream;
     const int64_t nb = qg_loss_blocks(count);
     const float gs = count > 0 ? scale / (float)count : 0.f;
-    k_l1<<<(unsigned)nb, kLBlock, 0, s>>>(count, image, gt, gs, grad_image, partials);
+    {
+        QG_TIMED("l1", s);
+        k_l1<<<(unsigned)nb, kLBlock, 0, s>>>(count, image, gt, gs, grad_image, partials);
+    }
     QG_LAUNCH_CHECK("qg_l1_loss");
     return QG_OK;
 }
@@ -96,7 +99,10 @@ extern "C" qg_status qg_l1_loss(int64_t count, const float* image, const float* 
 extern "C" qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_stream stream) {
     clear_error();
     QG_REQUIRE(count >= 0 && partials && out, "bad arguments");
-    k_loss_reduce<<<1, 64, 0, (hipStream_t)stream>>>(qg_loss_blocks(count), count, partials, out);
+    {
+        QG_TIMED("loss_reduce", (hipStream_t)stream);
+        k_loss_reduce<<<1, 64, 0, (hipStream_t)stream>>>(qg_loss_blocks(count), count, partials, out);
+    }
     QG_LAUNCH_CHECK("qg_loss_reduce");
     return QG_OK;
 }
@@ -110,8 +116,11 @@ extern "C" qg_status qg_adam(int64_t count, float* param, const float* grad, flo
     if (count == 0) return QG_OK;
     const float c1 = (float)(1.0 - std::pow((double)b1, t));
     const float c2 = (float)(1.0 - std::pow((double)b2, t));
-    k_adam<<<(unsigned)ceil_div(count, 256), 256, 0, (hipStream_t)stream>>>(count, param, grad, m, v, lr, b1, b2, eps,
-                                                                          c1, c2);
+    {
+        QG_TIMED("adam", (hipStream_t)stream);
+        k_adam<<<(unsigned)ceil_div(count, 256), 256, 0, (hipStream_t)stream>>>(count, param, grad, m, v, lr, b1, b2,
+                                                                              eps, c1, c2);
+    }
     QG_LAUNCH_CHECK("qg_adam");
     return QG_OK;
 }

@@ -435,8 +435,11 @@ qg_status project_bwd_launch(int64_t n, int64_t ld, const float* attrs, int sh_d
     ViewPtrs gv = {};
     if (grad_xy)
         for (int v = 0; v < vt.V; ++v) gv.p[v] = grad_xy[v];
-    k_project_bwd<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, ld, attrs, sh_degree, vt, dilation, grad2d,
-                                                             g2d_view_stride, grad_attrs, grad_xy_abs, gv);
+    {
+        QG_TIMED("project_bwd", s);
+        k_project_bwd<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, ld, attrs, sh_degree, vt, dilation, grad2d,
+                                                                 g2d_view_stride, grad_attrs, grad_xy_abs, gv);
+    }
     QG_LAUNCH_CHECK("project_bwd");
     return QG_OK;
 }
@@ -458,8 +461,11 @@ extern "C" qg_status qg_project(int64_t n, int64_t ld, const float* attrs, int32
     if (!make_view_table(cams, out, V, tiling, true, &vt)) return QG_ERR_ARG;
     if (n == 0) return QG_OK;
     hipStream_t s = (hipStream_t)stream;
-    k_project<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, ld, attrs, sh_degree, vt, dilation, tiling.tile_w,
-                                                         tiling.tile_h);
+    {
+        QG_TIMED("project", s);
+        k_project<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, ld, attrs, sh_degree, vt, dilation, tiling.tile_w,
+                                                             tiling.tile_h);
+    }
     QG_LAUNCH_CHECK("qg_project");
     return QG_OK;
 }

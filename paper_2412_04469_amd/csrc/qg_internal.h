@@ -70,4 +70,17 @@ bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V,
                      bool need_proj, ViewTable* out);
 bool tiling_ok(qg_tiling t);
 
+// Event timing around launches (no-ops unless qg_timing_enable(1)).
+void timing_begin(const char* name, hipStream_t s);
+void timing_end(hipStream_t s);
+
+struct TimedScope {
+    hipStream_t s;
+    TimedScope(const char* name, hipStream_t st) : s(st) { timing_begin(name, st); }
+    ~TimedScope() { timing_end(s); }
+};
+#define QG_CAT2_(a, b) a##b
+#define QG_CAT_(a, b) QG_CAT2_(a, b)
+#define QG_TIMED(name, stream) ::qg::TimedScope QG_CAT_(qg_timed_scope_, __LINE__)(name, stream)
+
 }  // namespace qg

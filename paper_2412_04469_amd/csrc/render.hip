@@ -311,7 +311,10 @@ template <int TW, int TH>
 qg_status launch_fwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* ranges, const float* bg,
                      const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp, hipStream_t s) {
     const int64_t per = ceil_div(vt.total_tiles, 8);
-    k_render_fwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp, per);
+    {
+        QG_TIMED("render_fwd", s);
+        k_render_fwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp, per);
+    }
     QG_LAUNCH_CHECK("qg_render_fwd");
     return QG_OK;
 }
@@ -321,8 +324,11 @@ qg_status launch_bwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* 
                      const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi, float* grad2d,
                      int64_t stride, hipStream_t s) {
     const int64_t per = ceil_div(vt.total_tiles, 8);
-    k_render_bwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
-                                                             grad2d, stride, per);
+    {
+        QG_TIMED("blend_bwd", s);
+        k_render_bwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
+                                                                 grad2d, stride, per);
+    }
     QG_LAUNCH_CHECK("qg_render_bwd");
     return QG_OK;
 }

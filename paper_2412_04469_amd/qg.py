@@ -78,6 +78,8 @@ def lib():
             "qg_l1_loss": ([i64, P, P, f32, P, P, P], i32),
             "qg_loss_reduce": ([i64, P, P, P], i32),
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
+            "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
+            "qg_timing_report": ([ctypes.c_char_p, i64], i64),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -128,6 +130,8 @@ def make_camera(cam) -> qg_camera:
 
 
 def camera_array(cams):
+    if isinstance(cams, ctypes.Array):
+        return cams
     arr = (qg_camera * len(cams))()
     for k, c in enumerate(cams):
         arr[k] = c if isinstance(c, qg_camera) else make_camera(c)
@@ -140,6 +144,8 @@ def tiling(tw=16, th=16) -> qg_tiling:
 
 def projected_array(bufs):
     """bufs: list of dicts with splat, depth, rect, ntiles, flags tensors."""
+    if isinstance(bufs, ctypes.Array):
+        return bufs
     arr = (qg_projected * len(bufs))()
     for k, b in enumerate(bufs):
         arr[k] = qg_projected(_ptr(b["splat"]), _ptr(b["depth"]), _ptr(b["rect"]), _ptr(b["ntiles"]), _ptr(b["flags"]))
@@ -147,6 +153,8 @@ def projected_array(bufs):
 
 
 def _ptr_array(xs):
+    if isinstance(xs, ctypes.Array):
+        return xs
     arr = (ctypes.c_void_p * len(xs))()
     for k, x in enumerate(xs):
         arr[k] = _ptr(x)
@@ -252,3 +260,18 @@ def qg_loss_reduce(count, partials, out, stream=None):
 def qg_adam(count, param, grad, m, v, lr, b1, b2, eps, t, stream=None):
     _check(lib().qg_adam(int(count), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr), float(b1), float(b2),
                          float(eps), int(t), _stream(stream)))
+
+
+def qg_timing_enable(on, only=None):
+    _check(lib().qg_timing_enable(int(bool(on)), None if only is None else only.encode()))
+
+
+def qg_timing_report():
+    """{name: (count, total_ms)} for the launches recorded since the last report (waits for them)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    lib().qg_timing_report(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

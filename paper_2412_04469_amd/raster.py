@@ -50,6 +50,22 @@ class Rasterizer:
         self._alloc_capacity(int(capacity))
         self.bwd_ws_bytes = qg.qg_render_bwd_workspace_size(self.n, self.V)
         self.bwd_ws = torch.empty(self.bwd_ws_bytes, dtype=torch.uint8, device=d)
+        self._tables()
+
+    def _tables(self):
+        """ctypes argument tables built once (the calls then only marshal scalars)."""
+        self.t_proj = qg.projected_array(self.proj)
+        self.t_img = qg._ptr_array(self.images)
+        self.t_tf = qg._ptr_array(self.tfinal)
+        self.t_last = qg._ptr_array(self.last)
+
+    def set_cameras(self, cams):
+        """Switch to other cameras of the same count and resolutions (buffers are reused)."""
+        assert len(cams) == self.V
+        for a, b in zip(cams, self.cams):
+            assert a.width == b.width and a.height == b.height
+        self.cams = list(cams)
+        self.qcams = qg.camera_array(self.cams)
 
     def _alloc_capacity(self, cap):
         self.capacity = int(min(cap, 2 ** 32 - 1))
@@ -61,16 +77,16 @@ class Rasterizer:
 
     # -- individual ABI steps -----------------------------------------------------------------
     def project(self, attrs, stream=None):
-        qg.qg_project(self.n, attrs.stride(0), attrs, self.sh_degree, self.qcams, self.tile, self.dilation, self.proj,
-                      stream)
+        qg.qg_project(self.n, attrs.stride(0), attrs, self.sh_degree, self.qcams, self.tile, self.dilation,
+                      self.t_proj, stream)
 
     def bin(self, stream=None):
-        qg.qg_bin(self.n, self.proj, self.qcams, self.tile, self.capacity, self.vals, self.keys, self.ranges,
+        qg.qg_bin(self.n, self.t_proj, self.qcams, self.tile, self.capacity, self.vals, self.keys, self.ranges,
                   self.num_pairs, self.bin_ws, self.bin_ws_bytes, stream)
 
     def render(self, stream=None):
-        qg.qg_render_fwd(self.proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.images, self.tfinal,
-                         self.last, stream)
+        qg.qg_render_fwd(self.t_proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.t_img, self.t_tf,
+                         self.t_last, stream)
 
     def ensure_capacity(self, margin=1.25) -> bool:
         """Host-synchronising check of the last bin; grows the buffers and returns True if it overflowed."""
@@ -92,7 +108,7 @@ class Rasterizer:
     def backward(self, attrs, grad_images, grad_attrs, grad_xy_abs=None, grad_xy=None, stream=None):
         """Accumulate dL/dattrs (+=) for dL/dimages."""
         qg.qg_render_bwd(self.n, attrs.stride(0), attrs, self.sh_degree, self.qcams, self.tile, self.dilation,
-                         self.proj, self.vals, self.ranges, self.bg, self.tfinal, self.last,
+                         self.t_proj, self.vals, self.ranges, self.bg, self.t_tf, self.t_last,
                          [g.contiguous() for g in grad_images], grad_attrs, grad_xy_abs, grad_xy, self.bwd_ws,
                          self.bwd_ws_bytes, stream)
 
