@@ -259,27 +259,62 @@ __global__ void k_finish_count(const uint64_t* __restrict__ total, int64_t capac
     *sort_count = t <= (uint64_t)capacity ? (uint32_t)t : 0u;
 }
 
-__global__ void k_emit(int64_t items, int64_t n, ViewTable vt, const uint32_t* __restrict__ sorted,
-                       const uint32_t* __restrict__ cnt, const uint64_t* __restrict__ offs,
-                       const uint32_t* __restrict__ sort_count, uint32_t* __restrict__ tkeys,
-                       uint32_t* __restrict__ tvals) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= items) return;
-    if (*sort_count == 0) return;  // overflow (or nothing to emit)
-    const uint32_t nt = cnt[k];
-    if (nt == 0) return;
-    const uint32_t item = sorted[k];
-    const int v = (int)(item / n);
-    const int64_t i = item - (int64_t)v * n;
-    const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[i];
-    const uint32_t gw = (uint32_t)vt.cam[v].grid_w, off0 = vt.cam[v].tile_off;
-    uint64_t o = offs[k];
-    for (int ty = r.y; ty < r.w; ++ty)
-        for (int tx = r.x; tx < r.z; ++tx) {
-            tkeys[o] = off0 + (uint32_t)ty * gw + (uint32_t)tx;
-            tvals[o] = (uint32_t)i;
-            ++o;
+// Emission, one thread per output pair (load-balanced whatever the rectangle sizes): a block owns 1024
+// consecutive output positions; the (view, Gaussian) items that cover them are consecutive in depth order
+// (every item with a non-empty rectangle owns at least one position, empty ones were sorted last), so the
+// block loads their offsets into LDS and each position finds its item by binary search there.
+constexpr int kEmitPer = 1024;
+
+__global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTable vt,
+                                              const uint32_t* __restrict__ sorted,
+                                              const uint64_t* __restrict__ offs,
+                                              const uint32_t* __restrict__ sort_count,
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+    __shared__ uint64_t s_off[kEmitPer];
+    __shared__ int64_t s_k0;
+    const uint64_t P = *sort_count;
+    const uint64_t base = (uint64_t)blockIdx.x * kEmitPer;
+    if (base >= P) return;
+    if (threadIdx.x == 0) {
+        // last k with offs[k] <= base
+        int64_t lo = 0, hi = items - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= base)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
+        s_k0 = lo;
+    }
+    __syncthreads();
+    const int64_t k0 = s_k0;
+    for (int t = threadIdx.x; t < kEmitPer; t += 256) {
+        const int64_t k = k0 + t;
+        s_off[t] = k < items ? offs[k] : ~0ull;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kEmitPer; t += 256) {
+        const uint64_t p = base + t;
+        if (p >= P) break;
+        int lo = 0, hi = kEmitPer - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t j = (uint32_t)(p - s_off[lo]);
+        const uint32_t item = sorted[k0 + lo];
+        const int v = (int)(item / n);
+        const int64_t i = item - (int64_t)v * n;
+        const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[i];
+        const uint32_t w = (uint32_t)(r.z - r.x);
+        const uint32_t ty = (uint32_t)r.y + j / w, tx = (uint32_t)r.x + j % w;
+        tkeys[p] = vt.cam[v].tile_off + ty * (uint32_t)vt.cam[v].grid_w + tx;
+        tvals[p] = (uint32_t)i;
+    }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ sort_count,
@@ -455,8 +490,8 @@ extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
     {
         QG_TIMED("bin_emit", s);
-        k_emit<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(items, n, vt, sorted_items, w.cnt, w.offs,
-                                                              w.sort_count, w.tkA, vbuf0);
+        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(items, n, vt, sorted_items, w.offs,
+                                                                      w.sort_count, w.tkA, vbuf0);
     }
     QG_LAUNCH_CHECK("qg_bin emit");
     // 3. stable sort by tile id

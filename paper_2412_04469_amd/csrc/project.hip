@@ -34,10 +34,12 @@ __device__ __forceinline__ void sh_consts(float* c) {
     c[9] = 1.4453057213202769f;
 }
 
-// Y[k] for k < (deg+1)^2.
+// Y[k] for k < (deg+1)^2, zero above.
 __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
     float c[10];
     sh_consts(c);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Y[k] = 0.f;
     Y[0] = c[0];
     if (deg < 1) return;
     Y[1] = -c[1] * y;
@@ -241,7 +243,8 @@ __global__ __launch_bounds__(256) void k_project(int64_t n, int64_t ld, const fl
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 float acc = 0.5f;
-                for (int k = 0; k < nb; ++k) acc += h[3 * k + ch] * Y[k];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc += h[3 * k + ch] * Y[k];
                 if (acc < 0.f) {
                     flags |= (uint8_t)(1u << ch);
                     acc = 0.f;
@@ -293,20 +296,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t n, int64_t ld, cons
     float dP[3] = {0.f, 0.f, 0.f};
     float dSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric gradient: xx, xy, xz, yy, yz, zz
     float dop = 0.f;
-    float dH[48];
-#pragma unroll
-    for (int k = 0; k < 48; ++k) dH[k] = 0.f;
-    float h[48];
-    bool have_h = false;
     float abs_acc = 0.f;
+    bool any_col = false;
+    // pass 1: geometry (position, covariance, opacity) over all views
     for (int v = 0; v < vt.V; ++v) {
         const ProjDev& pd = vt.proj[v];
         const uint8_t flags = pd.flags[i];
         if (flags & 0x80) continue;
         const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-        const float4 g0 = gr[0], g1 = gr[1], g2 = gr[2];
+        const float4 g0 = gr[0], g1 = gr[1];
         const float gx = g0.x, gy = g0.y, gA = g0.z, gB = g0.w, gC = g1.x, go = g1.y;
-        float gcol[3] = {g1.z, g1.w, g2.x};
+        any_col = true;
         const CamDev& cam = vt.cam[v];
         ViewProj vp;
         view_project(g, cam, dilation, vp);
@@ -316,33 +316,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t n, int64_t ld, cons
             gxyv.p[v][n + i] += gy;
         }
         dop += go;
-        // colour -> SH coefficients and view direction
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-            if (flags & (1u << ch)) gcol[ch] = 0.f;
-        if (gcol[0] != 0.f || gcol[1] != 0.f || gcol[2] != 0.f) {
-            if (!have_h) {
-                for (int k = 0; k < 3 * nb; ++k) h[k] = A[(11 + k) * ld + i];
-                have_h = true;
-            }
-            float vx = g.p[0] - cam.cpos[0], vy = g.p[1] - cam.cpos[1], vz = g.p[2] - cam.cpos[2];
-            float inv = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
-            float d[3] = {vx * inv, vy * inv, vz * inv};
-            float Y[16];
-            sh_basis(sh_deg, d[0], d[1], d[2], Y);
-            float w[16];
-            for (int k = 0; k < nb; ++k) {
-                dH[3 * k + 0] += gcol[0] * Y[k];
-                dH[3 * k + 1] += gcol[1] * Y[k];
-                dH[3 * k + 2] += gcol[2] * Y[k];
-                w[k] = gcol[0] * h[3 * k + 0] + gcol[1] * h[3 * k + 1] + gcol[2] * h[3 * k + 2];
-            }
-            float gd[3];
-            sh_grad(sh_deg, d[0], d[1], d[2], w, gd);
-            const float dotp = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) dP[k] += (gd[k] - d[k] * dotp) * inv;
-        }
         // conic -> Sigma' (a, b, c)
         const float a = vp.a, b = vp.b, c = vp.c;
         const float id = 1.f / vp.det, id2 = id * id;
@@ -381,6 +354,50 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t n, int64_t ld, cons
                 2.f * cam.fy * uy * iz3 * dJ12 - gx * cam.fx * ux * iz2 - gy * cam.fy * uy * iz2;
 #pragma unroll
         for (int k = 0; k < 3; ++k) dP[k] += R[k] * du[0] + R[3 + k] * du[1] + R[6 + k] * du[2];
+    }
+    // pass 2: SH colour -> coefficients and view direction (only if some view had a record)
+    if (any_col) {
+        float dH[48];
+        float h[48];
+#pragma unroll
+        for (int k = 0; k < 48; ++k) {
+            dH[k] = 0.f;
+            h[k] = k < 3 * nb ? A[(11 + k) * ld + i] : 0.f;
+        }
+        for (int v = 0; v < vt.V; ++v) {
+            const ProjDev& pd = vt.proj[v];
+            const uint8_t flags = pd.flags[i];
+            if (flags & 0x80) continue;
+            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
+            const float4 g1 = gr[1], g2 = gr[2];
+            float gcol[3] = {g1.z, g1.w, g2.x};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                if (flags & (1u << ch)) gcol[ch] = 0.f;
+            if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+            const CamDev& cam = vt.cam[v];
+            float vx = g.p[0] - cam.cpos[0], vy = g.p[1] - cam.cpos[1], vz = g.p[2] - cam.cpos[2];
+            float inv = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
+            float d[3] = {vx * inv, vy * inv, vz * inv};
+            float Y[16];
+            sh_basis(sh_deg, d[0], d[1], d[2], Y);
+            float w[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                dH[3 * k + 0] += gcol[0] * Y[k];
+                dH[3 * k + 1] += gcol[1] * Y[k];
+                dH[3 * k + 2] += gcol[2] * Y[k];
+                w[k] = gcol[0] * h[3 * k + 0] + gcol[1] * h[3 * k + 1] + gcol[2] * h[3 * k + 2];
+            }
+            float gd[3];
+            sh_grad(sh_deg, d[0], d[1], d[2], w, gd);
+            const float dotp = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dP[k] += (gd[k] - d[k] * dotp) * inv;
+        }
+#pragma unroll
+        for (int k = 0; k < 48; ++k)
+            if (k < 3 * nb) G[(11 + k) * ld + i] += dH[k];
     }
     if (gxy_abs) gxy_abs[i] += abs_acc;
     // Sigma = M M^T -> dM = 2 dSig M (dSig symmetric)
@@ -423,7 +440,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t n, int64_t ld, cons
     G[8 * ld + i] += dls[1];
     G[9 * ld + i] += dls[2];
     G[10 * ld + i] += dlogit;
-    for (int k = 0; k < 3 * nb; ++k) G[(11 + k) * ld + i] += dH[k];
 }
 
 }  // namespace

@@ -10,8 +10,8 @@
 // The adjoint walks the entries backwards from each pixel's last contributor and recomputes the
 // transmittance in reverse, T_i = T_{i+1} / (1 - alpha_i), starting from the stored final T, so no
 // per-pixel lists are kept.  Per entry, each lane first sums its PPL pixels, then the wave sums its
-// 64 lanes with DPP row shifts/broadcasts, and 9 lanes issue one float atomic each into the
-// Gaussian's 2D gradient record.
+// 64 lanes (DPP scans inside each 16-lane row, then the four row totals through LDS), and 9 lanes
+// issue one float atomic each into the Gaussian's 2D gradient record.
 //
 // The blend alpha is evaluated by one inline function used by both kernels, with explicit fused
 // multiply-adds, so the forward's skip/clamp/termination decisions are reproduced exactly.
@@ -90,12 +90,13 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     const int px = tx * TW + (lane % TW);
     const int py0 = ty * TH + lane / TW;
     const float fx = (float)px + 0.5f;
-    float T[PPL], C0[PPL], C1[PPL], C2[PPL];
+    float T[PPL], C0[PPL], C1[PPL], C2[PPL], fy[PPL];
     uint32_t last[PPL];
     bool run[PPL];
     const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
+        fy[k] = (float)(py0 + k * RPK) + 0.5f;
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = s;
@@ -126,22 +127,21 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
             bool any2 = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                const float dy = (float)(py0 + k * RPK) + 0.5f - a.y;
+                // branch-free: the same decisions as "skip if alpha < 1/255; stop before T' < 1e-4"
+                const float dy = fy[k] - a.y;
                 const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
                 const float al = fminf(kAlphaMax, raw);
-                if (run[k] && al >= kAlphaMin) {
-                    const float tn = T[k] * (1.f - al);
-                    if (tn < kTMin) {
-                        run[k] = false;
-                    } else {
-                        const float w = al * T[k];
-                        C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
-                        C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
-                        C2[k] = __builtin_fmaf(cb, w, C2[k]);
-                        T[k] = tn;
-                        last[k] = b + jj + 1;
-                    }
-                }
+                const bool ok = run[k] && al >= kAlphaMin;
+                const float tn = T[k] * (1.f - al);
+                const bool stop = ok && tn < kTMin;
+                const bool take = ok && !stop;
+                const float w = take ? al * T[k] : 0.f;
+                C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
+                C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
+                C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                T[k] = take ? tn : T[k];
+                last[k] = take ? b + jj + 1 : last[k];
+                run[k] = run[k] && !stop;
                 any2 |= run[k];
             }
             if (__ballot(any2) == 0) break;
@@ -167,21 +167,25 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     }
 }
 
-// ---- wave64 sum with DPP: inclusive row scans (shr 1,2,4,8), then row_bcast15 / row_bcast31; the total
-// ends in lane 63.
+// ---- wave64 sums of K values at once: DPP inclusive scans inside each 16-lane row (row_shr 1, 2, 4, 8,
+// interleaved over the K values so consecutive DPP operations never depend on each other), then the four
+// row totals go through LDS and are added by the lanes that issue the atomics.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_term(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-    v += dpp_term<0x111, 0xf>(v);  // row_shr:1
-    v += dpp_term<0x112, 0xf>(v);  // row_shr:2
-    v += dpp_term<0x114, 0xf>(v);  // row_shr:4
-    v += dpp_term<0x118, 0xf>(v);  // row_shr:8
-    v += dpp_term<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_term<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
+// In-row inclusive scans: afterwards lane 16r + 15 holds the sum of row r (lanes 16r .. 16r + 15).
+template <int K>
+__device__ __forceinline__ void row_sums(float (&v)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_term<0x111, 0xf>(v[k]);  // row_shr:1
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_term<0x112, 0xf>(v[k]);  // row_shr:2
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_term<0x114, 0xf>(v[k]);  // row_shr:4
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_term<0x118, 0xf>(v[k]);  // row_shr:8
 }
 
 template <int TW, int TH>
@@ -196,6 +200,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
     __shared__ float4 s_b[64];  // 2B', C', r, g
     __shared__ float4 s_c[64];  // b, A, B, C
     __shared__ uint32_t s_gid[64];
+    __shared__ float s_red[4][12];  // row totals of the 9 gradient components
     const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
     if (tile >= vt.total_tiles) return;
     const int v = view_of_tile(vt, (uint32_t)tile);
@@ -209,12 +214,16 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
     const uint32_t s = ranges[2 * tile];
     const int W = cam.width, H = cam.height;
     const size_t plane = (size_t)W * H;
-    float T[PPL], S0[PPL], S1[PPL], S2[PPL], G0[PPL], G1[PPL], G2[PPL];
+    // Per pixel: T (walked backwards from T_final), the image gradient G, and SG = sum_ch S_ch G_ch where S is
+    // the colour of everything behind the current entry (background included): dL/dalpha_i only needs
+    // T_i (c_i . G - SG_{i+1}), and SG_i = SG_{i+1} + alpha_i (c_i . G - SG_{i+1}).
+    float T[PPL], SG[PPL], G0[PPL], G1[PPL], G2[PPL], fy[PPL];
     uint32_t last[PPL];
     uint32_t maxlast = s;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int py = py0 + k * RPK;
+        fy[k] = (float)py + 0.5f;
         const bool in = px < W && py < H;
         const size_t o = (size_t)(in ? py : 0) * W + (in ? px : 0);
         T[k] = in ? tfinal.p[v][o] : 1.f;
@@ -222,9 +231,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
         G0[k] = in ? gimage.p[v][o] : 0.f;
         G1[k] = in ? gimage.p[v][plane + o] : 0.f;
         G2[k] = in ? gimage.p[v][2 * plane + o] : 0.f;
-        S0[k] = bg0;
-        S1[k] = bg1;
-        S2[k] = bg2;
+        SG[k] = bg0 * G0[k] + bg1 * G1[k] + bg2 * G2[k];
         maxlast = max(maxlast, last[k]);
     }
     // wave max of last
@@ -250,57 +257,55 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
             const float4 bb = s_b[jj];
             const float4 cc = s_c[jj];
             const float dx = fx - a.x;
-            float gx = 0.f, gy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+            const float Adx = cc.y * dx, Bdx = cc.z * dx;
+            // acc: gx, gy, gA, gB, gC, go, gr, gg, gb
+            float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             bool hit = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                if (pos < last[k]) {
-                    const float dy = (float)(py0 + k * RPK) + 0.5f - a.y;
-                    const float ek = blend_e(a.w, bb.x, bb.y, dx, dy);
-                    const float raw = a.z * ek;
-                    const float al = fminf(kAlphaMax, raw);
-                    if (al >= kAlphaMin) {
-                        hit = true;
-                        const float Ti = T[k] * __builtin_amdgcn_rcpf(1.f - al);
-                        const float w = al * Ti;
-                        gr = __builtin_fmaf(w, G0[k], gr);
-                        gg = __builtin_fmaf(w, G1[k], gg);
-                        gb = __builtin_fmaf(w, G2[k], gb);
-                        const float dLda = Ti * ((bb.z - S0[k]) * G0[k] + (bb.w - S1[k]) * G1[k] + (cc.x - S2[k]) * G2[k]);
-                        S0[k] = __builtin_fmaf(al, bb.z - S0[k], S0[k]);
-                        S1[k] = __builtin_fmaf(al, bb.w - S1[k], S1[k]);
-                        S2[k] = __builtin_fmaf(al, cc.x - S2[k], S2[k]);
-                        T[k] = Ti;
-                        if (raw <= kAlphaMax) {
-                            go = __builtin_fmaf(dLda, ek, go);
-                            const float dq = -0.5f * al * dLda;
-                            gx -= dq * 2.f * (cc.y * dx + cc.z * dy);
-                            gy -= dq * 2.f * (cc.z * dx + cc.w * dy);
-                            gA = __builtin_fmaf(dq, dx * dx, gA);
-                            gB = __builtin_fmaf(dq, 2.f * dx * dy, gB);
-                            gC = __builtin_fmaf(dq, dy * dy, gC);
-                        }
-                    }
-                }
+                // branch-free; the decisions (entry reached, alpha >= 1/255, clamp) repeat the forward's exactly
+                const float dy = fy[k] - a.y;
+                const float ek = blend_e(a.w, bb.x, bb.y, dx, dy);
+                const float raw = a.z * ek;
+                const float al = fminf(kAlphaMax, raw);
+                const bool on = pos < last[k] && al >= kAlphaMin;
+                hit |= on;
+                const float Ti = on ? T[k] * __builtin_amdgcn_rcpf(1.f - al) : T[k];
+                const float w = on ? al * Ti : 0.f;
+                acc[6] = __builtin_fmaf(w, G0[k], acc[6]);
+                acc[7] = __builtin_fmaf(w, G1[k], acc[7]);
+                acc[8] = __builtin_fmaf(w, G2[k], acc[8]);
+                const float cG = __builtin_fmaf(cc.x, G2[k], __builtin_fmaf(bb.w, G1[k], bb.z * G0[k]));
+                const float d = cG - SG[k];
+                SG[k] = __builtin_fmaf(on ? al : 0.f, d, SG[k]);
+                T[k] = Ti;
+                // geometric part: zero where the 0.99 clamp is active
+                const float dLda = (on && raw <= kAlphaMax) ? Ti * d : 0.f;
+                acc[5] = __builtin_fmaf(dLda, ek, acc[5]);
+                const float dq = -0.5f * al * dLda;  // dL/dq, q = A dx^2 + 2 B dx dy + C dy^2
+                const float dq2 = dq + dq;
+                acc[0] = __builtin_fmaf(-dq2, __builtin_fmaf(cc.z, dy, Adx), acc[0]);
+                acc[1] = __builtin_fmaf(-dq2, __builtin_fmaf(cc.w, dy, Bdx), acc[1]);
+                acc[2] = __builtin_fmaf(dq, dx * dx, acc[2]);
+                acc[3] = __builtin_fmaf(dq2, dx * dy, acc[3]);
+                acc[4] = __builtin_fmaf(dq, dy * dy, acc[4]);
             }
             if (__ballot(hit) == 0) continue;
-            gx = wave_sum_to_lane63(gx);
-            gy = wave_sum_to_lane63(gy);
-            gA = wave_sum_to_lane63(gA);
-            gB = wave_sum_to_lane63(gB);
-            gC = wave_sum_to_lane63(gC);
-            go = wave_sum_to_lane63(go);
-            gr = wave_sum_to_lane63(gr);
-            gg = wave_sum_to_lane63(gg);
-            gb = wave_sum_to_lane63(gb);
-            const float t0 = __shfl(gx, 63), t1 = __shfl(gy, 63), t2 = __shfl(gA, 63), t3 = __shfl(gB, 63),
-                        t4 = __shfl(gC, 63), t5 = __shfl(go, 63), t6 = __shfl(gr, 63), t7 = __shfl(gg, 63),
-                        t8 = __shfl(gb, 63);
+            row_sums<9>(acc);
+            if ((lane & 15) == 15) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) s_red[lane >> 4][k] = acc[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (lane < 9) {
-                const float val = lane == 0 ? t0 : lane == 1 ? t1 : lane == 2 ? t2 : lane == 3 ? t3 : lane == 4 ? t4
-                                : lane == 5 ? t5 : lane == 6 ? t6 : lane == 7 ? t7 : t8;
+                const float val = (s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]);
                 atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         __syncthreads();
         hi = lo;

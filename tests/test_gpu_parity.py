@@ -270,10 +270,10 @@ def test_chain_bwd_parity(qgm, tile):
                                sum(np.linalg.norm(x, axis=1) for x in gxy_ref), rtol=1e-3, atol=1e-9)
 
 
-def test_decode_parity(qgm):
+@pytest.mark.parametrize("n", [5000, 7, 70001])
+def test_decode_parity(qgm, n):
     qg, raster = qgm
     rng = synth.rng_for(40)
-    n = 5000
     prev = rng.normal(size=(59, n)).astype(np.float32)
     lat = rng.normal(0, 1.5, size=(8, n)).astype(np.float32)
     W1 = (rng.normal(size=(32, 8)) * 0.3).astype(np.float32)
