@@ -205,6 +205,43 @@ qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, int32_t sh_de
                         qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
+/* Fused per-Gaussian passes.                                                                      */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * qg_decode_project: qg_decode_residuals followed by qg_project in one pass (Eq. 4-8 then Eq. 1).  The
+ * decoded attributes stay on chip unless attrs_out ([59][ld], may be NULL) is given.  Arguments as in
+ * those two calls; lreg_partial has qg_decode_project_lreg_blocks(n) entries (block sums of Eq. 8's
+ * probabilities).  The projected records are bit-identical to the two-call path.
+ */
+int64_t qg_decode_project_lreg_blocks(int64_t n);
+qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L,
+                            const float* W1, const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
+                            const float* gate_logit, float gamma0, float gamma1, float tau, int32_t sh_degree,
+                            const qg_camera* cams, int32_t V, qg_tiling tiling, float dilation,
+                            const qg_projected* out, float* attrs_out, float* gate_out, float* lreg_partial,
+                            qg_stream stream);
+
+/*
+ * qg_render_decode_bwd: qg_render_bwd followed by qg_decode_residuals_bwd without materialising
+ * dL/d attrs: the blend adjoint (Eq. 2), then per Gaussian the decode (recomputed on the matrix cores),
+ * the projection adjoint (Eq. 1) and the decoder / gate backward (Eq. 5-8).  Gradient outputs as in
+ * qg_decode_residuals_bwd (+=), plus grad_xy_abs / grad_xy as in qg_render_bwd.  The other arguments
+ * must be those of the qg_decode_project / qg_bin / qg_render_fwd calls of this step.
+ * ws: qg_render_decode_bwd_workspace_size(n, V) bytes.  Results are bit-identical to the two-call path.
+ */
+size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V);
+qg_status qg_render_decode_bwd(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L,
+                               const float* W1, const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
+                               const float* gate_logit, float gamma0, float gamma1, float tau, float lambda_reg,
+                               int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                               float dilation, const qg_projected* proj, const uint32_t* vals,
+                               const uint32_t* tile_ranges, const float* bg, const float* const* T_final,
+                               const uint32_t* const* last, const float* const* grad_image, float* grad_latents,
+                               float* grad_W1, float* grad_W2, float* grad_pos_pre, float* grad_gate_logit,
+                               float* grad_xy_abs, float* const* grad_xy, void* ws, size_t ws_bytes,
+                               qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
 /* Loss (L1 term of Eq. 3), PSNR, Adam.                                                            */
 /* ---------------------------------------------------------------------------------------------- */
 /*

@@ -1,0 +1,301 @@
+// Fused per-Gaussian passes: decode + projection (forward) and projection adjoint + decode backward.
+//
+// The per-Gaussian chain is bound by HBM traffic.  Run as separate calls it writes the decoded 59-plane
+// attribute tensor, reads it back in the projection, and in the backward writes and re-reads its
+// gradient.  Here one wave owns 64 consecutive Gaussians: the decoder's products run on the matrix cores
+// for the 64 Gaussians (decoder_mfma.h), the residuals land in LDS, and each lane then projects its own
+// Gaussian (gauss_math.h) from prev + residual.  The backward does the same, keeps the attribute gradient
+// in the LDS slots of the residuals it no longer needs, and feeds it straight to the decoder backward.
+// Results equal qg_decode_residuals + qg_project and qg_render_bwd + qg_decode_residuals_bwd.
+#include <cmath>
+
+#include "decoder_mfma.h"
+#include "gauss_math.h"
+
+namespace qg {
+
+qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t* vals, const uint32_t* ranges,
+                           const float* bg, const float* const* T_final, const uint32_t* const* last,
+                           const float* const* grad_image, float* grad2d, int64_t stride, hipStream_t s);
+qg_status decode_reduce_launch(const float* part, int64_t nblocks, float* gW1, float* gW2, hipStream_t s);
+
+namespace {
+
+using namespace dec;
+
+constexpr int kChunk = 64;
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_decode_project(int64_t n, int64_t ld, const float* __restrict__ prev,
+                                                        const float* __restrict__ lat, const float* __restrict__ W1,
+                                                        const float* __restrict__ W2, const float* __restrict__ lp,
+                                                        const float* __restrict__ ga, float g0, float g1, float tau,
+                                                        float reg_shift, int sh_deg, ViewTable vt, float dilation,
+                                                        int tile_w, int tile_h, float* __restrict__ attrs_out,
+                                                        float* __restrict__ gate_out, float* __restrict__ lreg_part) {
+    __shared__ float s_res[4][kChunk][kM + 1];
+    __shared__ float s_red[4];
+    const int lane = __lane_id(), w = threadIdx.x / 64, c = lane % 16;
+    const int64_t nchunks = ceil_div(n, kChunk);
+    float preg = 0.f;
+    for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+        const int64_t base = ch * kChunk;
+        {
+            FwdOps ops;
+            load_fwd_ops(W1, W2, ops);
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                const int64_t g = base + 16 * sg + c;
+                const bool gv = g < n;
+                auto latf = [&](int k) { return gv ? rintf(lat[(int64_t)k * ld + g]) : 0.f; };
+                auto outf = [&](int m, float v) { s_res[w][16 * sg + c][m] = v; };
+                decode_group_fwd(ops, latf, outf);
+            }
+        }
+        wave_sync_lds();
+        const int64_t g = base + lane;
+        if (g < n) {
+            const float a = ga[g];
+            const float gg = gate_of(a, g0, g1, tau, nullptr, nullptr);
+            const float* rs = s_res[w][lane];
+            auto get = [&](int k) {
+                const float p = prev[(int64_t)k * ld + g];
+                return k < 3 ? __builtin_fmaf(gg, lp[(int64_t)k * ld + g], p) : p + rs[k - 3];
+            };
+            if (attrs_out) {
+#pragma unroll 8
+                for (int k = 0; k < QG_N_PLANES; ++k) attrs_out[(int64_t)k * ld + g] = get(k);
+            }
+            project_gauss(g, get, sh_deg, vt, dilation, tile_w, tile_h);
+            if (gate_out) gate_out[g] = gg;
+            preg += sigm(a - reg_shift);
+        }
+        wave_sync_lds();
+    }
+    if (lreg_part) {
+        for (int o = 32; o >= 1; o >>= 1) preg += __shfl_xor(preg, o);
+        if (lane == 0) s_red[w] = preg;
+        __syncthreads();
+        if (threadIdx.x == 0) lreg_part[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    }
+}
+
+struct ViewPtrsB {
+    float* p[QG_MAX_VIEWS];
+};
+
+__global__ __launch_bounds__(256) void k_project_decode_bwd(
+    int64_t n, int64_t ld, const float* __restrict__ prev, const float* __restrict__ lat, const float* __restrict__ W1,
+    const float* __restrict__ W2, const float* __restrict__ lp, const float* __restrict__ ga, float g0, float g1,
+    float tau, float reg_shift, float reg_scale, int sh_deg, ViewTable vt, float dilation,
+    const float* __restrict__ grad2d, int64_t stride, float* __restrict__ gxy_abs, ViewPtrsB gxyv,
+    float* __restrict__ g_lat, float* __restrict__ g_lp, float* __restrict__ g_ga, float* __restrict__ wpart) {
+    // s_buf[w][Gaussian][m]: residual r_m while projecting, then dL/dr_m (same slot, written after it is read)
+    __shared__ float s_buf[4][kChunk][kM + 1];
+    __shared__ float s_t[4][16][33];
+    __shared__ float s_w[kWidth];
+    const int lane = __lane_id(), w = threadIdx.x / 64, q = lane / 16, c = lane % 16;
+    for (int i = threadIdx.x; i < kWidth; i += 256) s_w[i] = 0.f;
+    BwdAcc acc;
+    zero_acc(acc);
+    ViewPtrs gv2;
+#pragma unroll
+    for (int v = 0; v < QG_MAX_VIEWS; ++v) gv2.p[v] = gxyv.p[v];
+    const int64_t nchunks = ceil_div(n, kChunk);
+    for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+        const int64_t base = ch * kChunk;
+        // 1. decode the chunk's residuals into LDS
+        {
+            FwdOps ops;
+            load_fwd_ops(W1, W2, ops);
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                const int64_t g = base + 16 * sg + c;
+                const bool gv = g < n;
+                auto latf = [&](int k) { return gv ? rintf(lat[(int64_t)k * ld + g]) : 0.f; };
+                auto outf = [&](int m, float v) { s_buf[w][16 * sg + c][m] = v; };
+                decode_group_fwd(ops, latf, outf);
+            }
+        }
+        wave_sync_lds();
+        // 2. projection adjoint per Gaussian; position and gate gradients
+        const int64_t g = base + lane;
+        if (g < n) {
+            const float a = ga[g];
+            float gh, gt;
+            const float gg = gate_of(a, g0, g1, tau, &gh, &gt);
+            float* rs = s_buf[w][lane];
+            auto get = [&](int k) {
+                const float p = prev[(int64_t)k * ld + g];
+                return k < 3 ? __builtin_fmaf(gg, lp[(int64_t)k * ld + g], p) : p + rs[k - 3];
+            };
+            float dpos[3] = {0.f, 0.f, 0.f};
+            auto put = [&](int k, float v) {
+                if (k < 3)
+                    dpos[k] = v;
+                else
+                    rs[k - 3] = v;
+            };
+            project_bwd_gauss(n, g, get, put, sh_deg, vt, dilation, grad2d, stride, gxy_abs, gv2);
+            const int nb = (sh_deg + 1) * (sh_deg + 1);
+            for (int m = 8 + 3 * nb; m < kM; ++m) rs[m] = 0.f;  // SH planes above the degree
+            float dot = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                dot = __builtin_fmaf(dpos[k], lp[(int64_t)k * ld + g], dot);
+                g_lp[(int64_t)k * ld + g] += gg * dpos[k];
+            }
+            float da = (gt > 0.f && gt < 1.f) ? dot * (g1 - g0) * gh * (1.f - gh) / tau : 0.f;
+            const float pr = sigm(a - reg_shift);
+            g_ga[g] += __builtin_fmaf(reg_scale, pr * (1.f - pr), da);
+        } else {
+            for (int m = 0; m < kM; ++m) s_buf[w][lane][m] = 0.f;
+        }
+        wave_sync_lds();
+        // 3. decoder backward from the gradient in LDS
+        {
+            BwdOps ops;
+            load_bwd_ops(W1, W2, ops);
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                const int64_t gA = base + 16 * sg + c;
+                const bool vA = gA < n;
+                auto latA = [&](int k) { return vA ? rintf(lat[(int64_t)k * ld + gA]) : 0.f; };
+                auto latN = [&](int k, int i) {
+                    const int64_t gN = base + 16 * sg + 4 * q + i;
+                    return gN < n ? rintf(lat[(int64_t)k * ld + gN]) : 0.f;
+                };
+                auto drA = [&](int m) { return s_buf[w][16 * sg + c][m]; };
+                auto drN = [&](int m, int i) { return m < kM ? s_buf[w][16 * sg + 4 * q + i][m] : 0.f; };
+                auto dlat = [&](int k, float v) {
+                    if (vA) g_lat[(int64_t)k * ld + gA] += v;
+                };
+                decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, s_t[w]);
+            }
+        }
+        wave_sync_lds();
+    }
+    for (int k = 0; k < 4; ++k) {
+        __syncthreads();
+        if (w == k) add_acc(acc, s_w);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_w[i];
+}
+
+int64_t fused_fwd_blocks(int64_t n) {
+    return std::min<int64_t>(std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)), 1024);
+}
+int64_t fused_bwd_blocks(int64_t n) {
+    return std::min<int64_t>(std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)), 512);
+}
+
+qg_status check_dec(int32_t L, int32_t Hd, int32_t M, float g0, float g1, float tau) {
+    QG_REQUIRE(L >= 1 && L <= 16, "L=%d outside [1, 16]", L);
+    QG_REQUIRE(Hd == 0 || Hd == 32, "Hd=%d must be 0 or 32", Hd);
+    QG_REQUIRE(M == 56, "M=%d must be 56", M);
+    QG_REQUIRE(g0 < 0.f && g1 > 1.f && tau > 0.f, "need gamma0 < 0, gamma1 > 1, tau > 0");
+    if (!(L == kL && Hd == kH)) {
+        set_error("decoder shape L=%d Hd=%d not built (supported: L=8, Hd=32)", L, Hd);
+        return QG_ERR_UNSUPPORTED;
+    }
+    return QG_OK;
+}
+
+}  // namespace
+}  // namespace qg
+
+using namespace qg;
+
+extern "C" int64_t qg_decode_project_lreg_blocks(int64_t n) { return fused_fwd_blocks(n); }
+
+extern "C" qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_attrs, const float* latents,
+                                       int32_t L, const float* W1, const float* W2, int32_t Hd, int32_t M,
+                                       const float* pos_pre, const float* gate_logit, float gamma0, float gamma1,
+                                       float tau, int32_t sh_degree, const qg_camera* cams, int32_t V,
+                                       qg_tiling tiling, float dilation, const qg_projected* out, float* attrs_out,
+                                       float* gate_out, float* lreg_partial, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0 && ld >= n && n < (1ll << 31), "n=%lld ld=%lld invalid", (long long)n, (long long)ld);
+    qg_status st = check_dec(L, Hd, M, gamma0, gamma1, tau);
+    if (st != QG_OK) return st;
+    QG_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree=%d outside [0, 3]", sh_degree);
+    QG_REQUIRE(dilation >= 0.f && std::isfinite(dilation), "dilation must be finite and >= 0");
+    QG_REQUIRE(n == 0 || (prev_attrs && latents && W1 && W2 && pos_pre && gate_logit), "a required pointer is NULL");
+    QG_REQUIRE(attrs_out != prev_attrs, "attrs_out may not alias prev_attrs");
+    ViewTable vt;
+    if (!make_view_table(cams, out, V, tiling, true, &vt)) return QG_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = fused_fwd_blocks(n);
+    if (n == 0) return lreg_partial ? qg_zero(lreg_partial, 4 * nb, stream) : QG_OK;
+    const float shift = tau * logf(-gamma0 / gamma1);
+    {
+        QG_TIMED("decode_project", s);
+        k_decode_project<<<(unsigned)nb, 256, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
+                                                      gamma1, tau, shift, sh_degree, vt, dilation, tiling.tile_w,
+                                                      tiling.tile_h, attrs_out, gate_out, lreg_partial);
+    }
+    QG_LAUNCH_CHECK("qg_decode_project");
+    return QG_OK;
+}
+
+extern "C" size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V) {
+    if (n < 0 || V < 1) return 0;
+    const size_t g2 = align_up((size_t)V * (size_t)(n > 0 ? n : 1) * QG_GRAD2D_STRIDE * sizeof(float));
+    return g2 + align_up((size_t)fused_bwd_blocks(n) * kWidth * sizeof(float));
+}
+
+extern "C" qg_status qg_render_decode_bwd(
+    int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L, const float* W1, const float* W2,
+    int32_t Hd, int32_t M, const float* pos_pre, const float* gate_logit, float gamma0, float gamma1, float tau,
+    float lambda_reg, int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling, float dilation,
+    const qg_projected* proj, const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
+    const float* const* T_final, const uint32_t* const* last, const float* const* grad_image, float* grad_latents,
+    float* grad_W1, float* grad_W2, float* grad_pos_pre, float* grad_gate_logit, float* grad_xy_abs,
+    float* const* grad_xy, void* ws, size_t ws_bytes, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0 && ld >= n && n < (1ll << 31), "n=%lld ld=%lld invalid", (long long)n, (long long)ld);
+    qg_status st = check_dec(L, Hd, M, gamma0, gamma1, tau);
+    if (st != QG_OK) return st;
+    QG_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree=%d outside [0, 3]", sh_degree);
+    QG_REQUIRE(dilation >= 0.f, "dilation < 0");
+    ViewTable vt;
+    if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
+    QG_REQUIRE(tile_ranges && bg && T_final && last && grad_image, "a required pointer is NULL");
+    QG_REQUIRE(n == 0 || (prev_attrs && latents && W1 && W2 && pos_pre && gate_logit && grad_latents && grad_W1 &&
+                          grad_W2 && grad_pos_pre && grad_gate_logit),
+               "a required pointer is NULL");
+    for (int v = 0; v < V; ++v)
+        QG_REQUIRE(T_final[v] && last[v] && grad_image[v], "view %d: an input pointer is NULL", v);
+    const size_t need = qg_render_decode_bwd_workspace_size(n, V);
+    QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    if (n == 0) return QG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    float* grad2d = (float*)ws;
+    const int64_t stride = n * QG_GRAD2D_STRIDE;
+    float* wpart = (float*)((char*)ws + align_up((size_t)V * (size_t)n * QG_GRAD2D_STRIDE * sizeof(float)));
+    st = qg_zero(grad2d, (int64_t)V * stride * 4, stream);
+    if (st != QG_OK) return st;
+    st = blend_bwd_launch(vt, tiling, vals, tile_ranges, bg, T_final, last, grad_image, grad2d, stride, s);
+    if (st != QG_OK) return st;
+    ViewPtrsB gv = {};
+    if (grad_xy)
+        for (int v = 0; v < V; ++v) gv.p[v] = grad_xy[v];
+    const int64_t nb = fused_bwd_blocks(n);
+    const float shift = tau * logf(-gamma0 / gamma1);
+    const float reg_scale = lambda_reg / (float)n;
+    {
+        QG_TIMED("project_decode_bwd", s);
+        k_project_decode_bwd<<<(unsigned)nb, 256, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit,
+                                                          gamma0, gamma1, tau, shift, reg_scale, sh_degree, vt,
+                                                          dilation, grad2d, stride, grad_xy_abs, gv, grad_latents,
+                                                          grad_pos_pre, grad_gate_logit, wpart);
+    }
+    QG_LAUNCH_CHECK("qg_render_decode_bwd");
+    return decode_reduce_launch(wpart, nb, grad_W1, grad_W2, s);
+}

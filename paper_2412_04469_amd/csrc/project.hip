@@ -8,280 +8,19 @@
 // are summed over views first and pushed through the quaternion/scale chain once.
 #include <cmath>
 
-#include "qg_internal.h"
+#include "gauss_math.h"
 
 namespace qg {
 
 namespace {
 
-// Real SH basis (l-major, m = -l..l, Condon-Shortley phase) written as polynomials of the unit
-// direction, and the constants as closed forms of sqrt((2l+1)/4pi (l-m)!/(l+m)!) times the
-// Legendre-derivative coefficients.
-constexpr float kPi = 3.14159265358979323846f;
-__device__ __forceinline__ void sh_consts(float* c) {
-    // c0 = 1/(2 sqrt(pi)), c1 = sqrt(3/(4 pi))
-    c[0] = 0.28209479177387814f;
-    c[1] = 0.48860251190291992f;
-    // degree 2: 1/2 sqrt(15/pi), 1/4 sqrt(5/pi), 1/4 sqrt(15/pi)
-    c[2] = 1.0925484305920792f;
-    c[3] = 0.31539156525252005f;
-    c[4] = 0.54627421529603959f;
-    // degree 3: 1/4 sqrt(35/(2pi)), 1/2 sqrt(105/pi), 1/4 sqrt(21/(2pi)), 1/4 sqrt(7/pi), 1/4 sqrt(105/pi)
-    c[5] = 0.59004358992664352f;
-    c[6] = 2.8906114426405538f;
-    c[7] = 0.45704579946446572f;
-    c[8] = 0.37317633259011546f;
-    c[9] = 1.4453057213202769f;
-}
-
-// Y[k] for k < (deg+1)^2, zero above.
-__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
-    float c[10];
-    sh_consts(c);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) Y[k] = 0.f;
-    Y[0] = c[0];
-    if (deg < 1) return;
-    Y[1] = -c[1] * y;
-    Y[2] = c[1] * z;
-    Y[3] = -c[1] * x;
-    if (deg < 2) return;
-    const float xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = c[2] * x * y;
-    Y[5] = -c[2] * y * z;
-    Y[6] = c[3] * (3.f * zz - 1.f);
-    Y[7] = -c[2] * x * z;
-    Y[8] = c[4] * (xx - yy);
-    if (deg < 3) return;
-    Y[9] = -c[5] * y * (3.f * xx - yy);
-    Y[10] = c[6] * x * y * z;
-    Y[11] = -c[7] * y * (5.f * zz - 1.f);
-    Y[12] = c[8] * z * (5.f * zz - 3.f);
-    Y[13] = -c[7] * x * (5.f * zz - 1.f);
-    Y[14] = c[9] * z * (xx - yy);
-    Y[15] = -c[5] * x * (xx - 3.f * yy);
-}
-
-// g = sum_k w[k] grad Y_k (gradient in R^3 of the polynomial forms above).
-__device__ __forceinline__ void sh_grad(int deg, float x, float y, float z, const float* w, float* g) {
-    float c[10];
-    sh_consts(c);
-    g[0] = g[1] = g[2] = 0.f;
-    if (deg < 1) return;
-    g[1] += -c[1] * w[1];
-    g[2] += c[1] * w[2];
-    g[0] += -c[1] * w[3];
-    if (deg < 2) return;
-    const float xx = x * x, yy = y * y, zz = z * z;
-    g[0] += c[2] * y * w[4];
-    g[1] += c[2] * x * w[4];
-    g[1] += -c[2] * z * w[5];
-    g[2] += -c[2] * y * w[5];
-    g[2] += 6.f * c[3] * z * w[6];
-    g[0] += -c[2] * z * w[7];
-    g[2] += -c[2] * x * w[7];
-    g[0] += 2.f * c[4] * x * w[8];
-    g[1] += -2.f * c[4] * y * w[8];
-    if (deg < 3) return;
-    g[0] += -c[5] * 6.f * x * y * w[9];
-    g[1] += -c[5] * (3.f * xx - 3.f * yy) * w[9];
-    g[0] += c[6] * y * z * w[10];
-    g[1] += c[6] * x * z * w[10];
-    g[2] += c[6] * x * y * w[10];
-    g[1] += -c[7] * (5.f * zz - 1.f) * w[11];
-    g[2] += -c[7] * 10.f * y * z * w[11];
-    g[2] += c[8] * (15.f * zz - 3.f) * w[12];
-    g[0] += -c[7] * (5.f * zz - 1.f) * w[13];
-    g[2] += -c[7] * 10.f * x * z * w[13];
-    g[0] += c[9] * 2.f * x * z * w[14];
-    g[1] += -c[9] * 2.f * y * z * w[14];
-    g[2] += c[9] * (xx - yy) * w[14];
-    g[0] += -c[5] * (3.f * xx - 3.f * yy) * w[15];
-    g[1] += c[5] * 6.f * x * y * w[15];
-}
-
-// Rotation matrix (row-major) of a unit quaternion (w, x, y, z).
-__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* R) {
-    R[0] = 1.f - 2.f * (y * y + z * z);
-    R[1] = 2.f * (x * y - w * z);
-    R[2] = 2.f * (x * z + w * y);
-    R[3] = 2.f * (x * y + w * z);
-    R[4] = 1.f - 2.f * (x * x + z * z);
-    R[5] = 2.f * (y * z - w * x);
-    R[6] = 2.f * (x * z - w * y);
-    R[7] = 2.f * (y * z + w * x);
-    R[8] = 1.f - 2.f * (x * x + y * y);
-}
-
-struct Gauss {
-    float p[3];
-    float q[4];      // normalised
-    float qnorm;
-    float s[3];      // exp(log-scale)
-    float Sig[6];    // xx, xy, xz, yy, yz, zz
-    float M[9];      // R(q) diag(s)
-    float Rq[9];
-    float opacity;
-    bool finite;
-};
-
-__device__ __forceinline__ void load_gauss(const float* __restrict__ A, int64_t ld, int64_t i, Gauss& g) {
-    float raw[11];
-#pragma unroll
-    for (int k = 0; k < 11; ++k) raw[k] = A[k * ld + i];
-    bool fin = true;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) fin = fin && isfinite(raw[k]);
-    g.p[0] = raw[0];
-    g.p[1] = raw[1];
-    g.p[2] = raw[2];
-    float qn = sqrtf(raw[3] * raw[3] + raw[4] * raw[4] + raw[5] * raw[5] + raw[6] * raw[6]);
-    fin = fin && qn > 0.f;
-    float inv = qn > 0.f ? 1.f / qn : 0.f;
-    g.qnorm = qn;
-    g.q[0] = raw[3] * inv;
-    g.q[1] = raw[4] * inv;
-    g.q[2] = raw[5] * inv;
-    g.q[3] = raw[6] * inv;
-    g.s[0] = expf(raw[7]);
-    g.s[1] = expf(raw[8]);
-    g.s[2] = expf(raw[9]);
-    g.opacity = 1.f / (1.f + expf(-raw[10]));
-    quat_rot(g.q[0], g.q[1], g.q[2], g.q[3], g.Rq);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g.M[r * 3 + c] = g.Rq[r * 3 + c] * g.s[c];
-    const float* M = g.M;
-    g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
-    g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
-    g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
-    g.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
-    g.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
-    g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
-    g.finite = fin;
-}
-
-// Per-view forward quantities.
-struct ViewProj {
-    float u[3];
-    float T0[3], T1[3];  // rows of J R_v
-    float a, b, c, det;  // Sigma' (dilated) and its determinant
-    float x, y;
-    bool ok;
-};
-
-__device__ __forceinline__ void sym_mul(const float* S, const float* v, float* o) {
-    o[0] = S[0] * v[0] + S[1] * v[1] + S[2] * v[2];
-    o[1] = S[1] * v[0] + S[3] * v[1] + S[4] * v[2];
-    o[2] = S[2] * v[0] + S[4] * v[1] + S[5] * v[2];
-}
-
-__device__ __forceinline__ void view_project(const Gauss& g, const CamDev& cam, float dilation, ViewProj& vp) {
-    const float* R = cam.R;
-    vp.u[0] = R[0] * g.p[0] + R[1] * g.p[1] + R[2] * g.p[2] + cam.t[0];
-    vp.u[1] = R[3] * g.p[0] + R[4] * g.p[1] + R[5] * g.p[2] + cam.t[1];
-    vp.u[2] = R[6] * g.p[0] + R[7] * g.p[1] + R[8] * g.p[2] + cam.t[2];
-    const float uz = vp.u[2];
-    vp.ok = g.finite && (uz > cam.z_near);
-    const float iz = vp.ok ? 1.f / uz : 1.f;
-    const float j00 = cam.fx * iz, j02 = -cam.fx * vp.u[0] * iz * iz;
-    const float j11 = cam.fy * iz, j12 = -cam.fy * vp.u[1] * iz * iz;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        vp.T0[k] = j00 * R[k] + j02 * R[6 + k];
-        vp.T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
-    }
-    float s0[3], s1[3];
-    sym_mul(g.Sig, vp.T0, s0);
-    sym_mul(g.Sig, vp.T1, s1);
-    vp.a = vp.T0[0] * s0[0] + vp.T0[1] * s0[1] + vp.T0[2] * s0[2] + dilation;
-    vp.b = vp.T0[0] * s1[0] + vp.T0[1] * s1[1] + vp.T0[2] * s1[2];
-    vp.c = vp.T1[0] * s1[0] + vp.T1[1] * s1[1] + vp.T1[2] * s1[2] + dilation;
-    vp.det = vp.a * vp.c - vp.b * vp.b;
-    vp.ok = vp.ok && vp.det > 0.f && vp.a > 0.f;
-    vp.x = cam.fx * vp.u[0] * iz + cam.cx;
-    vp.y = cam.fy * vp.u[1] * iz + cam.cy;
-}
-
 __global__ __launch_bounds__(256) void k_project(int64_t n, int64_t ld, const float* __restrict__ A, int sh_deg,
                                                  ViewTable vt, float dilation, int tile_w, int tile_h) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Gauss g;
-    load_gauss(A, ld, i, g);
-    const int nb = (sh_deg + 1) * (sh_deg + 1);
-    float h[48];
-#pragma unroll
-    for (int k = 0; k < 48; ++k) h[k] = (k < 3 * nb) ? A[(11 + k) * ld + i] : 0.f;
-    bool shfin = true;
-#pragma unroll
-    for (int k = 0; k < 48; ++k) shfin = shfin && isfinite(h[k]);
-    g.finite = g.finite && shfin;
-    const float op = g.opacity;
-    for (int v = 0; v < vt.V; ++v) {
-        const CamDev& cam = vt.cam[v];
-        const ProjDev& pd = vt.proj[v];
-        ViewProj vp;
-        view_project(g, cam, dilation, vp);
-        bool ok = vp.ok && op >= (1.f / 255.f);
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-        int4 rect = make_int4(0, 0, 0, 0);
-        int nt = 0;
-        uint8_t flags = 0x80;
-        if (ok) {
-            flags = 0;
-            const float id = 1.f / vp.det;
-            r0 = make_float4(vp.x, vp.y, op, 0.f);
-            r1 = make_float4(vp.c * id, -vp.b * id, vp.a * id, 0.f);
-            // colour
-            float dx = g.p[0] - cam.cpos[0], dy = g.p[1] - cam.cpos[1], dz = g.p[2] - cam.cpos[2];
-            float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-            float Y[16];
-            sh_basis(sh_deg, dx * inv, dy * inv, dz * inv, Y);
-            float col[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float acc = 0.5f;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc += h[3 * k + ch] * Y[k];
-                if (acc < 0.f) {
-                    flags |= (uint8_t)(1u << ch);
-                    acc = 0.f;
-                }
-                col[ch] = acc;
-            }
-            r2 = make_float4(col[0], col[1], col[2], 0.f);
-            // support: alpha >= 1/255 <=> q <= k^2 = 2 ln(255 o); half extents k sqrt(Sigma'_xx), k sqrt(Sigma'_yy)
-            const float k2 = 2.f * logf(255.f * op);
-            const float rx = sqrtf(k2 * vp.a), ry = sqrtf(k2 * vp.c);
-            float j0 = ceilf(vp.x - rx - 0.5f), j1 = floorf(vp.x + rx - 0.5f);
-            float i0 = ceilf(vp.y - ry - 0.5f), i1 = floorf(vp.y + ry - 0.5f);
-            j0 = fmaxf(j0, 0.f);
-            i0 = fmaxf(i0, 0.f);
-            j1 = fminf(j1, (float)(cam.width - 1));
-            i1 = fminf(i1, (float)(cam.height - 1));
-            if (j0 <= j1 && i0 <= i1) {
-                const int J0 = (int)j0, J1 = (int)j1, I0 = (int)i0, I1 = (int)i1;
-                rect = make_int4(J0 / tile_w, I0 / tile_h, J1 / tile_w + 1, I1 / tile_h + 1);
-                nt = (rect.z - rect.x) * (rect.w - rect.y);
-            }
-        }
-        float4* rec = reinterpret_cast<float4*>(pd.splat) + 3 * i;
-        rec[0] = r0;
-        rec[1] = r1;
-        rec[2] = r2;
-        pd.depth[i] = vp.u[2];
-        reinterpret_cast<int4*>(pd.rect)[i] = rect;
-        pd.ntiles[i] = nt;
-        pd.flags[i] = flags;
-    }
+    auto get = [&](int k) { return A[(int64_t)k * ld + i]; };
+    project_gauss(i, get, sh_deg, vt, dilation, tile_w, tile_h);
 }
-
-// Adjoint.  grad2d[v] holds per Gaussian: dx, dy, dA, dB, dC, dopacity, dr, dg, db (stride 12).
-struct ViewPtrs {
-    float* p[QG_MAX_VIEWS];
-};
 
 __global__ __launch_bounds__(256) void k_project_bwd(int64_t n, int64_t ld, const float* __restrict__ A, int sh_deg,
                                                      ViewTable vt, float dilation,
@@ -290,156 +29,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(int64_t n, int64_t ld, cons
                                                      ViewPtrs gxyv) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Gauss g;
-    load_gauss(A, ld, i, g);
-    const int nb = (sh_deg + 1) * (sh_deg + 1);
-    float dP[3] = {0.f, 0.f, 0.f};
-    float dSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric gradient: xx, xy, xz, yy, yz, zz
-    float dop = 0.f;
-    float abs_acc = 0.f;
-    bool any_col = false;
-    // pass 1: geometry (position, covariance, opacity) over all views
-    for (int v = 0; v < vt.V; ++v) {
-        const ProjDev& pd = vt.proj[v];
-        const uint8_t flags = pd.flags[i];
-        if (flags & 0x80) continue;
-        const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-        const float4 g0 = gr[0], g1 = gr[1];
-        const float gx = g0.x, gy = g0.y, gA = g0.z, gB = g0.w, gC = g1.x, go = g1.y;
-        any_col = true;
-        const CamDev& cam = vt.cam[v];
-        ViewProj vp;
-        view_project(g, cam, dilation, vp);
-        abs_acc += sqrtf(gx * gx + gy * gy);
-        if (gxyv.p[v]) {
-            gxyv.p[v][i] += gx;
-            gxyv.p[v][n + i] += gy;
-        }
-        dop += go;
-        // conic -> Sigma' (a, b, c)
-        const float a = vp.a, b = vp.b, c = vp.c;
-        const float id = 1.f / vp.det, id2 = id * id;
-        const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
-        const float gb = (2.f * b * c * gA - (a * c + b * b) * gB + 2.f * a * b * gC) * id2;
-        const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
-        // Sigma' = T Sigma T^T: symmetric gradient on Sigma and gradient on T rows
-        const float* T0 = vp.T0;
-        const float* T1 = vp.T1;
-        dSig[0] += ga * T0[0] * T0[0] + gb * T0[0] * T1[0] + gc * T1[0] * T1[0];
-        dSig[3] += ga * T0[1] * T0[1] + gb * T0[1] * T1[1] + gc * T1[1] * T1[1];
-        dSig[5] += ga * T0[2] * T0[2] + gb * T0[2] * T1[2] + gc * T1[2] * T1[2];
-        dSig[1] += ga * T0[0] * T0[1] + 0.5f * gb * (T0[0] * T1[1] + T1[0] * T0[1]) + gc * T1[0] * T1[1];
-        dSig[2] += ga * T0[0] * T0[2] + 0.5f * gb * (T0[0] * T1[2] + T1[0] * T0[2]) + gc * T1[0] * T1[2];
-        dSig[4] += ga * T0[1] * T0[2] + 0.5f * gb * (T0[1] * T1[2] + T1[1] * T0[2]) + gc * T1[1] * T1[2];
-        float s0[3], s1[3];
-        sym_mul(g.Sig, T0, s0);
-        sym_mul(g.Sig, T1, s1);
-        float dT0[3], dT1[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            dT0[k] = 2.f * ga * s0[k] + gb * s1[k];
-            dT1[k] = gb * s0[k] + 2.f * gc * s1[k];
-        }
-        const float* R = cam.R;
-        const float dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
-        const float dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
-        const float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
-        const float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
-        const float ux = vp.u[0], uy = vp.u[1], uz = vp.u[2];
-        const float iz = 1.f / uz, iz2 = iz * iz, iz3 = iz2 * iz;
-        float du[3];
-        du[0] = -cam.fx * iz2 * dJ02 + gx * cam.fx * iz;
-        du[1] = -cam.fy * iz2 * dJ12 + gy * cam.fy * iz;
-        du[2] = -cam.fx * iz2 * dJ00 + 2.f * cam.fx * ux * iz3 * dJ02 - cam.fy * iz2 * dJ11 +
-                2.f * cam.fy * uy * iz3 * dJ12 - gx * cam.fx * ux * iz2 - gy * cam.fy * uy * iz2;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dP[k] += R[k] * du[0] + R[3 + k] * du[1] + R[6 + k] * du[2];
-    }
-    // pass 2: SH colour -> coefficients and view direction (only if some view had a record)
-    if (any_col) {
-        float dH[48];
-        float h[48];
-#pragma unroll
-        for (int k = 0; k < 48; ++k) {
-            dH[k] = 0.f;
-            h[k] = k < 3 * nb ? A[(11 + k) * ld + i] : 0.f;
-        }
-        for (int v = 0; v < vt.V; ++v) {
-            const ProjDev& pd = vt.proj[v];
-            const uint8_t flags = pd.flags[i];
-            if (flags & 0x80) continue;
-            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-            const float4 g1 = gr[1], g2 = gr[2];
-            float gcol[3] = {g1.z, g1.w, g2.x};
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch)
-                if (flags & (1u << ch)) gcol[ch] = 0.f;
-            if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
-            const CamDev& cam = vt.cam[v];
-            float vx = g.p[0] - cam.cpos[0], vy = g.p[1] - cam.cpos[1], vz = g.p[2] - cam.cpos[2];
-            float inv = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
-            float d[3] = {vx * inv, vy * inv, vz * inv};
-            float Y[16];
-            sh_basis(sh_deg, d[0], d[1], d[2], Y);
-            float w[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                dH[3 * k + 0] += gcol[0] * Y[k];
-                dH[3 * k + 1] += gcol[1] * Y[k];
-                dH[3 * k + 2] += gcol[2] * Y[k];
-                w[k] = gcol[0] * h[3 * k + 0] + gcol[1] * h[3 * k + 1] + gcol[2] * h[3 * k + 2];
-            }
-            float gd[3];
-            sh_grad(sh_deg, d[0], d[1], d[2], w, gd);
-            const float dotp = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) dP[k] += (gd[k] - d[k] * dotp) * inv;
-        }
-#pragma unroll
-        for (int k = 0; k < 48; ++k)
-            if (k < 3 * nb) G[(11 + k) * ld + i] += dH[k];
-    }
-    if (gxy_abs) gxy_abs[i] += abs_acc;
-    // Sigma = M M^T -> dM = 2 dSig M (dSig symmetric)
-    const float S[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
-    float dM[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-            dM[r * 3 + cc] = 2.f * (S[r * 3 + 0] * g.M[0 + cc] + S[r * 3 + 1] * g.M[3 + cc] + S[r * 3 + 2] * g.M[6 + cc]);
-    // M = Rq diag(s)
-    float dls[3], dR[9];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-        float ds = dM[cc] * g.Rq[cc] + dM[3 + cc] * g.Rq[3 + cc] + dM[6 + cc] * g.Rq[6 + cc];
-        dls[cc] = ds * g.s[cc];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) dR[r * 3 + cc] = dM[r * 3 + cc] * g.s[cc];
-    }
-    const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
-    float dq[4];
-    dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
-                   2.f * x * dR[8]);
-    dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
-                   2.f * y * dR[8]);
-    dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
-                   x * dR[6] + y * dR[7]);
-    const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    const float iq = g.qnorm > 0.f ? 1.f / g.qnorm : 0.f;
-    const float dlogit = dop * g.opacity * (1.f - g.opacity);
-    G[0 * ld + i] += dP[0];
-    G[1 * ld + i] += dP[1];
-    G[2 * ld + i] += dP[2];
-    G[3 * ld + i] += (dq[0] - w * qd) * iq;
-    G[4 * ld + i] += (dq[1] - x * qd) * iq;
-    G[5 * ld + i] += (dq[2] - y * qd) * iq;
-    G[6 * ld + i] += (dq[3] - z * qd) * iq;
-    G[7 * ld + i] += dls[0];
-    G[8 * ld + i] += dls[1];
-    G[9 * ld + i] += dls[2];
-    G[10 * ld + i] += dlogit;
+    auto get = [&](int k) { return A[(int64_t)k * ld + i]; };
+    auto put = [&](int k, float v) { G[(int64_t)k * ld + i] += v; };
+    project_bwd_gauss(n, i, get, put, sh_deg, vt, dilation, grad2d, g2d_view_stride, gxy_abs, gxyv);
 }
 
 }  // namespace

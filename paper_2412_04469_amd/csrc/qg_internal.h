@@ -34,7 +34,7 @@ void clear_error();
 
 constexpr int kWave = 64;
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Camera in the form the kernels use (float32, by value in kernel arguments).

@@ -340,6 +340,21 @@ qg_status launch_bwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* 
 
 }  // namespace
 
+qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t* vals, const uint32_t* ranges,
+                           const float* bg, const float* const* T_final, const uint32_t* const* last,
+                           const float* const* grad_image, float* grad2d, int64_t stride, hipStream_t s) {
+    ViewPtrsCF tf = {}, gi = {};
+    ViewPtrsCU lp = {};
+    for (int v = 0; v < vt.V; ++v) {
+        tf.p[v] = T_final[v];
+        lp.p[v] = last[v];
+        gi.p[v] = grad_image[v];
+    }
+    if (tiling.tile_w == 16) return launch_bwd<16, 16>(vt, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    if (tiling.tile_w == 8) return launch_bwd<8, 8>(vt, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    return launch_bwd<32, 8>(vt, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+}
+
 }  // namespace qg
 
 using namespace qg;

@@ -84,6 +84,9 @@ class FrameFitter:
         self.grad_attrs = torch.zeros_like(self.prev)
         self.dws_bytes = qg.qg_decode_bwd_workspace_size(n, L, H, 56)
         self.dws = torch.empty(self.dws_bytes, dtype=torch.uint8, device=dev)
+        self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(n, 1)
+        self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
+        self.fused = True
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
                                bg=cfg.bg, device=dev, capacity=capacity)
         self.qcams = [qg.camera_array([c]) for c in self.cams]
@@ -127,17 +130,33 @@ class FrameFitter:
     def step(self, v, stream=None):
         """One optimiser iteration on training view v (enqueue only)."""
         c = self.cfg
-        self.decode(stream)
-        self.forward_view(v, stream)
-        qg.qg_l1_loss(self.count, self.rast.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
-        qg.qg_zero(self.grad_attrs, self.grad_attrs.numel() * 4, stream)
-        self.rast.backward(self.attrs, [self.grad_img], self.grad_attrs, stream=stream)
+        r = self.rast
+        if self.fused:
+            r.qcams = self.qcams[v]
+            qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
+                                 self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
+                                 r.t_proj, None, self.gate, None, stream)
+            r.bin(stream)
+            r.render(stream)
+        else:
+            self.decode(stream)
+            self.forward_view(v, stream)
+        qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
         for g in self.grads.values():
             qg.qg_zero(g, g.numel() * 4, stream)
-        qg.qg_decode_residuals_bwd(self.n, self.ld, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56, self.lp,
-                                   self.a, c.gamma0, c.gamma1, c.tau, self.grad_attrs, c.lambda_reg,
-                                   self.grads["lat"], self.grads["W1"], self.grads["W2"], self.grads["lp"],
-                                   self.grads["a"], self.dws, self.dws_bytes, stream)
+        if self.fused:
+            qg.qg_render_decode_bwd(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
+                                    self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
+                                    r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
+                                    [self.grad_img], self.grads["lat"], self.grads["W1"], self.grads["W2"],
+                                    self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream)
+        else:
+            qg.qg_zero(self.grad_attrs, self.grad_attrs.numel() * 4, stream)
+            r.backward(self.attrs, [self.grad_img], self.grad_attrs, stream=stream)
+            qg.qg_decode_residuals_bwd(self.n, self.ld, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56, self.lp,
+                                       self.a, c.gamma0, c.gamma1, c.tau, self.grad_attrs, c.lambda_reg,
+                                       self.grads["lat"], self.grads["W1"], self.grads["W2"], self.grads["lp"],
+                                       self.grads["a"], self.dws, self.dws_bytes, stream)
         self.t += 1
         b1, b2 = c.betas
         for k, p in self.params.items():

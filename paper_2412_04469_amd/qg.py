@@ -79,6 +79,12 @@ def lib():
             "qg_loss_reduce": ([i64, P, P, P], i32),
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
             "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
+            "qg_decode_project_lreg_blocks": ([i64], i64),
+            "qg_decode_project": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, i32, CAM, i32, qg_tiling,
+                                   f32, PRJ, P, P, P, P], i32),
+            "qg_render_decode_bwd_workspace_size": ([i64, i32], sz),
+            "qg_render_decode_bwd": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, f32, i32, CAM, i32,
+                                      qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P], i32),
             "qg_timing_report": ([ctypes.c_char_p, i64], i64),
         }
         for name, (args, res) in sig.items():
@@ -275,3 +281,39 @@ def qg_timing_report():
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def qg_decode_project_lreg_blocks(n):
+    return int(lib().qg_decode_project_lreg_blocks(int(n)))
+
+
+def qg_decode_project(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
+                      sh_degree, cams, tile, dilation, out, attrs_out=None, gate_out=None, lreg_partial=None,
+                      stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(out)
+    _check(lib().qg_decode_project(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), int(L), _ptr(W1), _ptr(W2),
+                                   int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
+                                   float(tau), int(sh_degree), ca, len(ca), tile, float(dilation), pa,
+                                   _ptr(attrs_out), _ptr(gate_out), _ptr(lreg_partial), _stream(stream)))
+
+
+def qg_render_decode_bwd_workspace_size(n, V):
+    return int(lib().qg_render_decode_bwd_workspace_size(int(n), int(V)))
+
+
+def qg_render_decode_bwd(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
+                         lambda_reg, sh_degree, cams, tile, dilation, proj, vals, tile_ranges, bg, T_final, last,
+                         grad_image, grad_latents, grad_W1, grad_W2, grad_pos_pre, grad_gate_logit, grad_xy_abs,
+                         grad_xy, ws, ws_bytes, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    bga = (ctypes.c_float * 3)(*[float(b) for b in bg])
+    gxy = None if grad_xy is None else _ptr_array(grad_xy)
+    _check(lib().qg_render_decode_bwd(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), int(L), _ptr(W1), _ptr(W2),
+                                      int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
+                                      float(tau), float(lambda_reg), int(sh_degree), ca, len(ca), tile,
+                                      float(dilation), pa, _ptr(vals), _ptr(tile_ranges), bga, _ptr_array(T_final),
+                                      _ptr_array(last), _ptr_array(grad_image), _ptr(grad_latents), _ptr(grad_W1),
+                                      _ptr(grad_W2), _ptr(grad_pos_pre), _ptr(grad_gate_logit), _ptr(grad_xy_abs),
+                                      gxy, _ptr(ws), int(ws_bytes), _stream(stream)))

@@ -340,3 +340,62 @@ def test_loss_and_adam_parity(qgm):
         pp, m, v = OA.adam_step(pp, gr.astype(np.float64), m, v, step, 0.01)
     torch.cuda.synchronize()
     np.testing.assert_allclose(dp.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("n,tile", [(3001, (16, 16)), (40, (8, 8)), (5000, (32, 8))])
+def test_fused_equals_two_call_path(qgm, n, tile):
+    """qg_decode_project == qg_decode_residuals + qg_project, and qg_render_decode_bwd ==
+    qg_render_bwd + qg_decode_residuals_bwd, bit for bit."""
+    qg, raster = qgm
+    rng = synth.rng_for(50 + n)
+    sc = synth.draw_scene(rng, n, 1.0, -3.5, 0.5)
+    cams = cams_small(96, 72)
+    prev = to_dev(sc.planes())
+    lat = to_dev(rng.normal(0, 1.2, size=(8, n)).astype(np.float32))
+    W1 = to_dev((rng.normal(size=(32, 8)) * 0.05).astype(np.float32))
+    W2 = to_dev((rng.normal(size=(56, 32)) * 0.02).astype(np.float32))
+    lp = to_dev(rng.normal(0, 0.02, size=(3, n)).astype(np.float32))
+    a = to_dev(rng.normal(0, 1.0, size=n).astype(np.float32))
+    hp = (-0.5, 1.01, 0.3)
+    bg = (0.1, 0.2, 0.3)
+    # two-call path
+    r1 = raster.Rasterizer(n, cams, tile=tile, bg=bg)
+    attrs = torch.empty_like(prev)
+    qg.qg_decode_residuals(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, attrs)
+    r1.forward(attrs)
+    # fused path
+    r2 = raster.Rasterizer(n, cams, tile=tile, bg=bg, capacity=r1.capacity)
+    attrs2 = torch.empty_like(prev)
+    qg.qg_decode_project(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, 3, r2.qcams, r2.tile, r2.dilation, r2.t_proj,
+                         attrs2)
+    r2.bin()
+    r2.render()
+    torch.cuda.synchronize()
+    assert torch.equal(attrs, attrs2)
+    for v in range(len(cams)):
+        for k in ("splat", "depth", "rect", "ntiles", "flags"):
+            assert torch.equal(r1.proj[v][k], r2.proj[v][k]), k
+        assert torch.equal(r1.images[v], r2.images[v])
+    G = [to_dev(rng.normal(size=(3, c.height, c.width)).astype(np.float32)) for c in cams]
+    lam = 0.01
+    names = ("lat", "W1", "W2", "lp", "a")
+    g1 = {k: torch.zeros_like(t) for k, t in zip(names, (lat, W1, W2, lp, a))}
+    ga1 = torch.zeros_like(prev)
+    gabs1 = torch.zeros(n, device="cuda")
+    r1.backward(attrs, G, ga1, gabs1)
+    wsb = qg.qg_decode_bwd_workspace_size(n, 8, 32, 56)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    qg.qg_decode_residuals_bwd(n, n, lat, 8, W1, W2, 32, 56, lp, a, *hp, ga1, lam, g1["lat"], g1["W1"], g1["W2"],
+                               g1["lp"], g1["a"], ws, wsb)
+    g2 = {k: torch.zeros_like(t) for k, t in zip(names, (lat, W1, W2, lp, a))}
+    gabs2 = torch.zeros(n, device="cuda")
+    wsb2 = qg.qg_render_decode_bwd_workspace_size(n, len(cams))
+    ws2 = torch.empty(wsb2, dtype=torch.uint8, device="cuda")
+    qg.qg_render_decode_bwd(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, 3, r2.qcams, r2.tile, r2.dilation,
+                            r2.t_proj, r2.vals, r2.ranges, bg, r2.t_tf, r2.t_last, G, g2["lat"], g2["W1"], g2["W2"],
+                            g2["lp"], g2["a"], gabs2, None, ws2, wsb2)
+    torch.cuda.synchronize()
+    # the blend adjoint uses float atomics, so equality is up to their summation order
+    for k in names:
+        assert rel_l2(g2[k].cpu().numpy(), g1[k].cpu().numpy()) <= 1e-5, k
+    assert rel_l2(gabs2.cpu().numpy(), gabs1.cpu().numpy()) <= 1e-5
