@@ -242,6 +242,29 @@ qg_status qg_render_decode_bwd(int64_t n, int64_t ld, const float* prev_attrs, c
                                qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
+/* Viewspace-gradient difference (Eq. 9) and gate initialisation (Eq. 10).                          */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * out[i] = scale * (a[i] - b[i]) for i < count.  With a = I_{t-1}, b = I_t and scale = 2 / (3 H W) this
+ * is dMSE_t/dI - dMSE_{t-1}/dI at any render I, so qg_render_bwd with this image gradient and grad_xy
+ * set yields one view's term of Eq. 9 (both gradients of Eq. 9 are taken at the same render, and the
+ * adjoint is linear in the image gradient).
+ */
+qg_status qg_scaled_diff(int64_t count, const float* a, const float* b, float scale, float* out, qg_stream stream);
+
+/*
+ * Gate initialisation (Eq. 10): with |d_i| the L2 norm of d[:, i] (d is [2][n], e.g. the view sum of
+ * Eq. 9's viewspace gradients; the result does not depend on its scale) and m the lower median of the
+ * norms (element (n-1)/2 after sorting, found exactly by radix select), p_i = |d_i| / (|d_i| + m)
+ * clamped to [1e-6, 1 - 1e-6] (0/0 gives 1e-6), and a_out[i] = logit(p_i) + tau ln(-gamma0/gamma1),
+ * the gate logit whose Eq. 8 probability is p_i.  p_out [n] and median_out [1] are optional.
+ * ws: qg_gate_init_workspace_size(n) bytes.
+ */
+size_t qg_gate_init_workspace_size(int64_t n);
+qg_status qg_gate_init(int64_t n, const float* d, float gamma0, float gamma1, float tau, float* a_out, float* p_out,
+                       float* median_out, void* ws, size_t ws_bytes, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
 /* Loss (L1 term of Eq. 3), PSNR, Adam.                                                            */
 /* ---------------------------------------------------------------------------------------------- */
 /*

@@ -205,3 +205,37 @@ def render_views(attrs: torch.Tensor, cams, cfg: FitConfig = FitConfig(), capaci
         rast.forward(attrs)
         out.append(rast.images[0].clone())
     return out
+
+
+def viewspace_gradient_difference(prev_attrs: torch.Tensor, cams, gt_prev, gt_cur, cfg: FitConfig = FitConfig(),
+                                  capacity=None):
+    """Sum over views of Eq. 9's bracket: d [2][n] (the 1/V factor of Eq. 9 is left out; Eq. 10 is scale-free).
+
+    Each view: render A_{t-1}, then one adjoint pass with image gradient 2 (I_{t-1} - I_t) / (3HW), reading
+    dL/dp' out of the adjoint."""
+    n = prev_attrs.shape[1]
+    dev = prev_attrs.device
+    rast = Rasterizer(n, [cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation, bg=cfg.bg,
+                      device=dev, capacity=capacity)
+    d = torch.zeros(2, n, device=dev)
+    scratch = torch.zeros_like(prev_attrs)
+    gimg = torch.empty_like(rast.images[0])
+    for v, c in enumerate(cams):
+        rast.set_cameras([c])
+        rast.forward(prev_attrs)
+        cnt = gimg.numel()
+        qg.qg_scaled_diff(cnt, gt_prev[v], gt_cur[v], 2.0 / cnt, gimg)
+        rast.backward(prev_attrs, [gimg], scratch, grad_xy=[d])
+    return d
+
+
+def gate_init(d: torch.Tensor, cfg: FitConfig = FitConfig()):
+    """Gate logits from d (Eq. 10), the Eq. 10 probabilities and the median norm."""
+    n = d.shape[1]
+    a = torch.empty(n, device=d.device)
+    p = torch.empty(n, device=d.device)
+    med = torch.empty(1, device=d.device)
+    wsb = qg.qg_gate_init_workspace_size(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=d.device)
+    qg.qg_gate_init(n, d, cfg.gamma0, cfg.gamma1, cfg.tau, a, p, med, ws, wsb)
+    return a, p, med

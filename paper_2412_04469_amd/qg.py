@@ -80,6 +80,9 @@ def lib():
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
             "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
             "qg_decode_project_lreg_blocks": ([i64], i64),
+            "qg_scaled_diff": ([i64, P, P, f32, P, P], i32),
+            "qg_gate_init_workspace_size": ([i64], sz),
+            "qg_gate_init": ([i64, P, f32, f32, f32, P, P, P, P, sz, P], i32),
             "qg_decode_project": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, i32, CAM, i32, qg_tiling,
                                    f32, PRJ, P, P, P, P], i32),
             "qg_render_decode_bwd_workspace_size": ([i64, i32], sz),
@@ -317,3 +320,16 @@ def qg_render_decode_bwd(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, 
                                       _ptr_array(last), _ptr_array(grad_image), _ptr(grad_latents), _ptr(grad_W1),
                                       _ptr(grad_W2), _ptr(grad_pos_pre), _ptr(grad_gate_logit), _ptr(grad_xy_abs),
                                       gxy, _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def qg_scaled_diff(count, a, b, scale, out, stream=None):
+    _check(lib().qg_scaled_diff(int(count), _ptr(a), _ptr(b), float(scale), _ptr(out), _stream(stream)))
+
+
+def qg_gate_init_workspace_size(n):
+    return int(lib().qg_gate_init_workspace_size(int(n)))
+
+
+def qg_gate_init(n, d, gamma0, gamma1, tau, a_out, p_out, median_out, ws, ws_bytes, stream=None):
+    _check(lib().qg_gate_init(int(n), _ptr(d), float(gamma0), float(gamma1), float(tau), _ptr(a_out), _ptr(p_out),
+                              _ptr(median_out), _ptr(ws), int(ws_bytes), _stream(stream)))

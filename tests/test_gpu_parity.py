@@ -399,3 +399,57 @@ def test_fused_equals_two_call_path(qgm, n, tile):
     for k in names:
         assert rel_l2(g2[k].cpu().numpy(), g1[k].cpu().numpy()) <= 1e-5, k
     assert rel_l2(gabs2.cpu().numpy(), gabs1.cpu().numpy()) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 100003])
+def test_gate_init_exact_median_and_logits(qgm, n):
+    qg, raster = qgm
+    from oracle import gate as OG
+    from paper_2412_04469_amd import fit
+    rng = synth.rng_for(60 + n)
+    x = rng.integers(0, 500, size=n).astype(np.float32)  # exact norms: sqrt(x^2) = x in float32
+    x[rng.uniform(size=n) < 0.05] = 0.0
+    d = np.stack([x * np.where(rng.uniform(size=n) < 0.5, -1, 1), np.zeros(n, np.float32)]).astype(np.float32)
+    a, p, med = fit.gate_init(to_dev(d))
+    torch.cuda.synchronize()
+    assert med.item() == np.sort(np.abs(x))[(n - 1) // 2]
+    p_ref, a_ref = OG.gate_init(d.T.astype(np.float64), -0.5, 1.01, 0.3)
+    np.testing.assert_allclose(p.cpu().numpy(), p_ref, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(a.cpu().numpy(), a_ref, rtol=1e-5, atol=1e-3)
+
+
+def test_viewspace_gradient_difference_parity(qgm):
+    """Eq. 9 on the GPU (one adjoint pass per view with image gradient 2 (I_{t-1} - I_t)/(3HW)) against the
+    oracle's adjoint; the oracle's one-pass form is itself pinned to the literal two-pass form."""
+    qg, raster = qgm
+    from oracle import gate as OG
+    from paper_2412_04469_amd import fit
+    sc = small_scene(seed=14, n=2500)
+    moved = sc.copy()
+    rng = synth.rng_for(61)
+    mv = rng.permutation(sc.n)[:250]
+    moved.means[mv] += rng.normal(0, 0.05, size=(250, 3)).astype(np.float32)
+    cams = cams_small(112, 84)
+    prev64 = sc.planes().astype(np.float64)
+    d_ref = np.zeros((sc.n, 2))
+    gt_prev, gt_cur = [], []
+    for cam in cams:
+        rp = OR.render(prev64, cam)
+        rc = OR.render(moved.planes().astype(np.float64), cam)
+        ip = rp["image"].astype(np.float32)
+        ic = rc["image"].astype(np.float32)
+        ic[:, ~keep_mask(rp)] = ip[:, ~keep_mask(rp)]  # no gradient where the render's decisions are marginal
+        gt_prev.append(ip)
+        gt_cur.append(ic)
+        planes = torch.tensor(prev64)
+        r = OR.render(planes, cam, grad_image=OG.dt_image_gradient(ip, ic))
+        d_ref += r["g_xy"]
+    d = fit.viewspace_gradient_difference(to_dev(sc.planes()), cams, [to_dev(x) for x in gt_prev],
+                                          [to_dev(x) for x in gt_cur])
+    torch.cuda.synchronize()
+    dg = d.cpu().numpy().T
+    assert np.abs(d_ref).max() > 0
+    assert rel_l2(dg, d_ref) <= 1e-3
+    a, p, med = fit.gate_init(d)
+    p_ref, _ = OG.gate_init(d_ref, -0.5, 1.01, 0.3)
+    assert rel_l2(p.cpu().numpy(), p_ref) <= 1e-2
