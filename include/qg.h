@@ -285,6 +285,22 @@ qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_
 qg_status qg_adam(int64_t count, float* param, const float* grad, float* m, float* v, float lr, float b1,
                   float b2, float eps, int32_t t, qg_stream stream);
 
+/*
+ * Several parameter groups in one launch (up to 8 segments), same update as qg_adam with a learning rate
+ * per segment.  If zero_grad is non-zero each gradient is set to 0 after it is read, so the next backward
+ * can accumulate (+=) into it without a separate zeroing pass.  segs [host].
+ */
+typedef struct {
+    float* param;
+    float* grad;
+    float* m;
+    float* v;
+    int64_t count;
+    float lr;
+} qg_adam_segment;
+qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, float b1, float b2, float eps, int32_t t,
+                        int32_t zero_grad, qg_stream stream);
+
 /* Zero `bytes` bytes at dst with a fill kernel (no memset node, so it is safe to capture). */
 qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream);
 

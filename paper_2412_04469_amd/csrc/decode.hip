@@ -148,19 +148,22 @@ __global__ __launch_bounds__(256) void k_decode_bwd(int64_t n, int64_t ld, const
     for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_w[i];
 }
 
-// out[o] += sum over blocks b, in order, of part[b][o]; 64 outputs per block, 4 interleaved partial chains
-// combined in a fixed order.
+// out[o] += sum over blocks b of part[b][o], in a fixed order: 32 outputs per block, 8 interleaved chains
+// (b = c, c + 8, ...) per output, combined in chain order.
 __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int64_t nblocks,
                                                       float* __restrict__ gW1, float* __restrict__ gW2) {
-    __shared__ float s[4][64];
-    const int o = blockIdx.x * 64 + threadIdx.x % 64;
-    const int c = threadIdx.x / 64;
+    __shared__ float s[8][32];
+    const int o = blockIdx.x * 32 + threadIdx.x % 32;
+    const int c = threadIdx.x / 32;
     float acc = 0.f;
-    for (int64_t b = c; b < nblocks; b += 4) acc += part[(size_t)b * kWidth + o];
-    s[c][threadIdx.x % 64] = acc;
+#pragma unroll 8
+    for (int64_t b = c; b < nblocks; b += 8) acc += part[(size_t)b * kWidth + o];
+    s[c][threadIdx.x % 32] = acc;
     __syncthreads();
     if (c == 0) {
-        const float t = ((s[0][threadIdx.x] + s[1][threadIdx.x]) + s[2][threadIdx.x]) + s[3][threadIdx.x];
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += s[k][threadIdx.x];
         if (o < kH * kL)
             gW1[o] += t;
         else
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
 
 qg_status decode_reduce_launch(const float* part, int64_t nblocks, float* gW1, float* gW2, hipStream_t s) {
     QG_TIMED("decode_wreduce", s);
-    k_reduce_parts<<<(unsigned)(kWidth / 64), 256, 0, s>>>(part, nblocks, gW1, gW2);
+    k_reduce_parts<<<(unsigned)(kWidth / 32), 256, 0, s>>>(part, nblocks, gW1, gW2);
     QG_LAUNCH_CHECK("decode weight reduce");
     return QG_OK;
 }

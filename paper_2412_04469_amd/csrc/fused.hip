@@ -25,6 +25,10 @@ using namespace dec;
 
 constexpr int kChunk = 64;
 
+// Element offset of plane k of Gaussian g in a [planes][ld] array, in 32 bits (the entry points check that
+// every plane offset fits): the loads then use an SGPR base and a 32-bit VGPR offset.
+__device__ __forceinline__ uint32_t pidx(int k, uint32_t ld, uint32_t g) { return (uint32_t)k * ld + g; }
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -42,35 +46,45 @@ __global__ __launch_bounds__(256) void k_decode_project(int64_t n, int64_t ld, c
     __shared__ float s_red[4];
     const int lane = __lane_id(), w = threadIdx.x / 64, c = lane % 16;
     const int64_t nchunks = ceil_div(n, kChunk);
+    const uint32_t ld32 = (uint32_t)ld;
     float preg = 0.f;
     for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
         const int64_t base = ch * kChunk;
+        const int64_t g = base + lane;
+        const bool gv = g < n;
+        const uint32_t g32 = (uint32_t)g;
+        // issue every attribute load of this lane's Gaussian first; they land while the decoder runs
+        float at[QG_N_PLANES];
+#pragma unroll
+        for (int k = 0; k < QG_N_PLANES; ++k) at[k] = gv ? prev[pidx(k, ld32, g32)] : 0.f;
+        float lpv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lpv[k] = gv ? lp[pidx(k, ld32, g32)] : 0.f;
+        const float a = gv ? ga[g] : 0.f;
         {
             FwdOps ops;
             load_fwd_ops(W1, W2, ops);
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
-                const int64_t g = base + 16 * sg + c;
-                const bool gv = g < n;
-                auto latf = [&](int k) { return gv ? rintf(lat[(int64_t)k * ld + g]) : 0.f; };
+                const int64_t gs = base + 16 * sg + c;
+                const bool vs = gs < n;
+                auto latf = [&](int k) { return vs ? rintf(lat[pidx(k, ld32, (uint32_t)gs)]) : 0.f; };
                 auto outf = [&](int m, float v) { s_res[w][16 * sg + c][m] = v; };
                 decode_group_fwd(ops, latf, outf);
             }
         }
         wave_sync_lds();
-        const int64_t g = base + lane;
-        if (g < n) {
-            const float a = ga[g];
+        if (gv) {
             const float gg = gate_of(a, g0, g1, tau, nullptr, nullptr);
-            const float* rs = s_res[w][lane];
-            auto get = [&](int k) {
-                const float p = prev[(int64_t)k * ld + g];
-                return k < 3 ? __builtin_fmaf(gg, lp[(int64_t)k * ld + g], p) : p + rs[k - 3];
-            };
+#pragma unroll
+            for (int k = 0; k < 3; ++k) at[k] = __builtin_fmaf(gg, lpv[k], at[k]);
+#pragma unroll
+            for (int k = 3; k < QG_N_PLANES; ++k) at[k] = at[k] + s_res[w][lane][k - 3];
             if (attrs_out) {
-#pragma unroll 8
-                for (int k = 0; k < QG_N_PLANES; ++k) attrs_out[(int64_t)k * ld + g] = get(k);
+#pragma unroll
+                for (int k = 0; k < QG_N_PLANES; ++k) attrs_out[pidx(k, ld32, g32)] = at[k];
             }
+            auto get = [&](int k) { return at[k]; };
             project_gauss(g, get, sh_deg, vt, dilation, tile_w, tile_h);
             if (gate_out) gate_out[g] = gg;
             preg += sigm(a - reg_shift);
@@ -95,45 +109,56 @@ __global__ __launch_bounds__(256) void k_project_decode_bwd(
     float tau, float reg_shift, float reg_scale, int sh_deg, ViewTable vt, float dilation,
     const float* __restrict__ grad2d, int64_t stride, float* __restrict__ gxy_abs, ViewPtrsB gxyv,
     float* __restrict__ g_lat, float* __restrict__ g_lp, float* __restrict__ g_ga, float* __restrict__ wpart) {
-    // s_buf[w][Gaussian][m]: residual r_m while projecting, then dL/dr_m (same slot, written after it is read)
+    // s_buf[w][Gaussian][m]: attribute plane 3 + m (prev, then + residual) while projecting, then dL/dr_m (the
+    // same slot, written only after its last read)
     __shared__ float s_buf[4][kChunk][kM + 1];
     __shared__ float s_t[4][16][33];
-    __shared__ float s_w[kWidth];
+    __shared__ float s_acc[4][kWidth];  // per-wave weight-gradient sums (kept out of registers)
     const int lane = __lane_id(), w = threadIdx.x / 64, q = lane / 16, c = lane % 16;
-    for (int i = threadIdx.x; i < kWidth; i += 256) s_w[i] = 0.f;
-    BwdAcc acc;
-    zero_acc(acc);
+    for (int i = lane; i < kWidth; i += 64) s_acc[w][i] = 0.f;
     ViewPtrs gv2;
 #pragma unroll
     for (int v = 0; v < QG_MAX_VIEWS; ++v) gv2.p[v] = gxyv.p[v];
     const int64_t nchunks = ceil_div(n, kChunk);
+    const uint32_t ld32 = (uint32_t)ld;
     for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
         const int64_t base = ch * kChunk;
-        // 1. decode the chunk's residuals into LDS
+        const int64_t g = base + lane;
+        const bool gv = g < n;
+        const uint32_t g32 = (uint32_t)g;
+        // 0. stage prev planes 3..58 (lane = Gaussian, coalesced rows); positions and gate in registers
+#pragma unroll 8
+        for (int m = 0; m < kM; ++m) s_buf[w][lane][m] = gv ? prev[pidx(3 + m, ld32, g32)] : 0.f;
+        float pos[3], lpv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            pos[k] = gv ? prev[pidx(k, ld32, g32)] : 0.f;
+            lpv[k] = gv ? lp[pidx(k, ld32, g32)] : 0.f;
+        }
+        const float a = gv ? ga[g] : 0.f;
+        wave_sync_lds();
+        // 1. add the decoded residuals in place
         {
             FwdOps ops;
             load_fwd_ops(W1, W2, ops);
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
-                const int64_t g = base + 16 * sg + c;
-                const bool gv = g < n;
-                auto latf = [&](int k) { return gv ? rintf(lat[(int64_t)k * ld + g]) : 0.f; };
-                auto outf = [&](int m, float v) { s_buf[w][16 * sg + c][m] = v; };
+                const int64_t gs = base + 16 * sg + c;
+                const bool vs = gs < n;
+                auto latf = [&](int k) { return vs ? rintf(lat[pidx(k, ld32, (uint32_t)gs)]) : 0.f; };
+                auto outf = [&](int m, float v) { s_buf[w][16 * sg + c][m] = s_buf[w][16 * sg + c][m] + v; };
                 decode_group_fwd(ops, latf, outf);
             }
         }
         wave_sync_lds();
         // 2. projection adjoint per Gaussian; position and gate gradients
-        const int64_t g = base + lane;
-        if (g < n) {
-            const float a = ga[g];
+        if (gv) {
             float gh, gt;
             const float gg = gate_of(a, g0, g1, tau, &gh, &gt);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pos[k] = __builtin_fmaf(gg, lpv[k], pos[k]);
             float* rs = s_buf[w][lane];
-            auto get = [&](int k) {
-                const float p = prev[(int64_t)k * ld + g];
-                return k < 3 ? __builtin_fmaf(gg, lp[(int64_t)k * ld + g], p) : p + rs[k - 3];
-            };
+            auto get = [&](int k) { return k < 3 ? pos[k] : rs[k - 3]; };
             float dpos[3] = {0.f, 0.f, 0.f};
             auto put = [&](int k, float v) {
                 if (k < 3)
@@ -147,8 +172,8 @@ __global__ __launch_bounds__(256) void k_project_decode_bwd(
             float dot = 0.f;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                dot = __builtin_fmaf(dpos[k], lp[(int64_t)k * ld + g], dot);
-                g_lp[(int64_t)k * ld + g] += gg * dpos[k];
+                dot = __builtin_fmaf(dpos[k], lpv[k], dot);
+                g_lp[pidx(k, ld32, g32)] += gg * dpos[k];
             }
             float da = (gt > 0.f && gt < 1.f) ? dot * (g1 - g0) * gh * (1.f - gh) / tau : 0.f;
             const float pr = sigm(a - reg_shift);
@@ -157,35 +182,36 @@ __global__ __launch_bounds__(256) void k_project_decode_bwd(
             for (int m = 0; m < kM; ++m) s_buf[w][lane][m] = 0.f;
         }
         wave_sync_lds();
-        // 3. decoder backward from the gradient in LDS
+        // 3. decoder backward from the gradient in LDS; this chunk's weight gradients go to s_acc[w]
         {
             BwdOps ops;
             load_bwd_ops(W1, W2, ops);
+            BwdAcc acc;
+            zero_acc(acc);
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
                 const int64_t gA = base + 16 * sg + c;
                 const bool vA = gA < n;
-                auto latA = [&](int k) { return vA ? rintf(lat[(int64_t)k * ld + gA]) : 0.f; };
+                auto latA = [&](int k) { return vA ? rintf(lat[pidx(k, ld32, (uint32_t)gA)]) : 0.f; };
                 auto latN = [&](int k, int i) {
                     const int64_t gN = base + 16 * sg + 4 * q + i;
-                    return gN < n ? rintf(lat[(int64_t)k * ld + gN]) : 0.f;
+                    return gN < n ? rintf(lat[pidx(k, ld32, (uint32_t)gN)]) : 0.f;
                 };
                 auto drA = [&](int m) { return s_buf[w][16 * sg + c][m]; };
                 auto drN = [&](int m, int i) { return m < kM ? s_buf[w][16 * sg + 4 * q + i][m] : 0.f; };
                 auto dlat = [&](int k, float v) {
-                    if (vA) g_lat[(int64_t)k * ld + gA] += v;
+                    if (vA) g_lat[pidx(k, ld32, (uint32_t)gA)] += v;
                 };
                 decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, s_t[w]);
             }
+            add_acc(acc, s_acc[w]);
         }
         wave_sync_lds();
     }
-    for (int k = 0; k < 4; ++k) {
-        __syncthreads();
-        if (w == k) add_acc(acc, s_w);
-    }
+    // block sum in a fixed wave order
     __syncthreads();
-    for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_w[i];
+    for (int i = threadIdx.x; i < kWidth; i += 256)
+        wpart[(size_t)blockIdx.x * kWidth + i] = ((s_acc[0][i] + s_acc[1][i]) + s_acc[2][i]) + s_acc[3][i];
 }
 
 int64_t fused_fwd_blocks(int64_t n) {
@@ -228,6 +254,7 @@ extern "C" qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_
     QG_REQUIRE(dilation >= 0.f && std::isfinite(dilation), "dilation must be finite and >= 0");
     QG_REQUIRE(n == 0 || (prev_attrs && latents && W1 && W2 && pos_pre && gate_logit), "a required pointer is NULL");
     QG_REQUIRE(attrs_out != prev_attrs, "attrs_out may not alias prev_attrs");
+    QG_REQUIRE((int64_t)QG_N_PLANES * ld < (1ll << 31), "59 * ld must be < 2^31 for the fused kernels");
     ViewTable vt;
     if (!make_view_table(cams, out, V, tiling, true, &vt)) return QG_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -264,6 +291,7 @@ extern "C" qg_status qg_render_decode_bwd(
     if (st != QG_OK) return st;
     QG_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree=%d outside [0, 3]", sh_degree);
     QG_REQUIRE(dilation >= 0.f, "dilation < 0");
+    QG_REQUIRE((int64_t)QG_N_PLANES * ld < (1ll << 31), "59 * ld must be < 2^31 for the fused kernels");
     ViewTable vt;
     if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
     QG_REQUIRE(tile_ranges && bg && T_final && last && grad_image, "a required pointer is NULL");

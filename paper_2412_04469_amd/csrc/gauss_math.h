@@ -8,6 +8,9 @@
 
 namespace qg {
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // Real SH basis (l-major, m = -l..l, Condon-Shortley phase) written as polynomials of the unit
 // direction, and the constants as closed forms of sqrt((2l+1)/4pi (l-m)!/(l+m)!) times the
 // Legendre-derivative coefficients.
@@ -131,7 +134,7 @@ __device__ __forceinline__ void load_gauss(const Get& get, Gauss& g) {
     g.p[2] = raw[2];
     float qn = sqrtf(raw[3] * raw[3] + raw[4] * raw[4] + raw[5] * raw[5] + raw[6] * raw[6]);
     fin = fin && qn > 0.f;
-    float inv = qn > 0.f ? 1.f / qn : 0.f;
+    float inv = qn > 0.f ? rcp(qn) : 0.f;
     g.qnorm = qn;
     g.q[0] = raw[3] * inv;
     g.q[1] = raw[4] * inv;
@@ -140,7 +143,7 @@ __device__ __forceinline__ void load_gauss(const Get& get, Gauss& g) {
     g.s[0] = expf(raw[7]);
     g.s[1] = expf(raw[8]);
     g.s[2] = expf(raw[9]);
-    g.opacity = 1.f / (1.f + expf(-raw[10]));
+    g.opacity = rcp(1.f + expf(-raw[10]));
     quat_rot(g.q[0], g.q[1], g.q[2], g.q[3], g.Rq);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -178,7 +181,7 @@ __device__ __forceinline__ void view_project(const Gauss& g, const CamDev& cam, 
     vp.u[2] = R[6] * g.p[0] + R[7] * g.p[1] + R[8] * g.p[2] + cam.t[2];
     const float uz = vp.u[2];
     vp.ok = g.finite && (uz > cam.z_near);
-    const float iz = vp.ok ? 1.f / uz : 1.f;
+    const float iz = vp.ok ? rcp(uz) : 1.f;
     const float j00 = cam.fx * iz, j02 = -cam.fx * vp.u[0] * iz * iz;
     const float j11 = cam.fy * iz, j12 = -cam.fy * vp.u[1] * iz * iz;
 #pragma unroll
@@ -213,6 +216,7 @@ __device__ __forceinline__ void project_gauss(int64_t i, const Get& get, int sh_
     for (int k = 0; k < 48; ++k) shfin = shfin && isfinite(h[k]);
     g.finite = g.finite && shfin;
     const float op = g.opacity;
+#pragma unroll 1
     for (int v = 0; v < vt.V; ++v) {
         const CamDev& cam = vt.cam[v];
         const ProjDev& pd = vt.proj[v];
@@ -225,12 +229,12 @@ __device__ __forceinline__ void project_gauss(int64_t i, const Get& get, int sh_
         uint8_t flags = 0x80;
         if (ok) {
             flags = 0;
-            const float id = 1.f / vp.det;
+            const float id = rcp(vp.det);
             r0 = make_float4(vp.x, vp.y, op, 0.f);
             r1 = make_float4(vp.c * id, -vp.b * id, vp.a * id, 0.f);
             // colour
             float dx = g.p[0] - cam.cpos[0], dy = g.p[1] - cam.cpos[1], dz = g.p[2] - cam.cpos[2];
-            float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+            float inv = rsq(dx * dx + dy * dy + dz * dz);
             float Y[16];
             sh_basis(sh_deg, dx * inv, dy * inv, dz * inv, Y);
             float col[3];
@@ -294,6 +298,7 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     float abs_acc = 0.f;
     bool any_col = false;
     // pass 1: geometry (position, covariance, opacity) over all views
+#pragma unroll 1
     for (int v = 0; v < vt.V; ++v) {
         const ProjDev& pd = vt.proj[v];
         const uint8_t flags = pd.flags[i];
@@ -313,7 +318,7 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
         dop += go;
         // conic -> Sigma' (a, b, c)
         const float a = vp.a, b = vp.b, c = vp.c;
-        const float id = 1.f / vp.det, id2 = id * id;
+        const float id = rcp(vp.det), id2 = id * id;
         const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
         const float gb = (2.f * b * c * gA - (a * c + b * b) * gB + 2.f * a * b * gC) * id2;
         const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
@@ -341,7 +346,7 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
         const float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
         const float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
         const float ux = vp.u[0], uy = vp.u[1], uz = vp.u[2];
-        const float iz = 1.f / uz, iz2 = iz * iz, iz3 = iz2 * iz;
+        const float iz = rcp(uz), iz2 = iz * iz, iz3 = iz2 * iz;
         float du[3];
         du[0] = -cam.fx * iz2 * dJ02 + gx * cam.fx * iz;
         du[1] = -cam.fy * iz2 * dJ12 + gy * cam.fy * iz;
@@ -359,7 +364,8 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
             dH[k] = 0.f;
             h[k] = k < 3 * nb ? get(11 + k) : 0.f;
         }
-        for (int v = 0; v < vt.V; ++v) {
+    #pragma unroll 1
+    for (int v = 0; v < vt.V; ++v) {
             const ProjDev& pd = vt.proj[v];
             const uint8_t flags = pd.flags[i];
             if (flags & 0x80) continue;
@@ -372,7 +378,7 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
             if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
             const CamDev& cam = vt.cam[v];
             float vx = g.p[0] - cam.cpos[0], vy = g.p[1] - cam.cpos[1], vz = g.p[2] - cam.cpos[2];
-            float inv = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
+            float inv = rsq(vx * vx + vy * vy + vz * vz);
             float d[3] = {vx * inv, vy * inv, vz * inv};
             float Y[16];
             sh_basis(sh_deg, d[0], d[1], d[2], Y);
@@ -426,7 +432,7 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
                    x * dR[6] + y * dR[7]);
     const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    const float iq = g.qnorm > 0.f ? 1.f / g.qnorm : 0.f;
+    const float iq = g.qnorm > 0.f ? rcp(g.qnorm) : 0.f;
     const float dlogit = dop * g.opacity * (1.f - g.opacity);
     put(0, dP[0]);
     put(1, dP[1]);

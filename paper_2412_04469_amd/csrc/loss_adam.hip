@@ -72,10 +72,71 @@ __global__ void k_adam(int64_t count, float* __restrict__ p, const float* __rest
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+struct AdamSegs {
+    float* p[8];
+    float* g[8];
+    float* m[8];
+    float* v[8];
+    float lr[8];
+    int64_t start[9];  // prefix of the segment lengths
+    int nseg;
+};
+
+// All parameter groups of one optimiser step in one launch; the gradient is cleared after it is read so the
+// next backward can accumulate into it without a separate zeroing pass.
+__global__ void k_adam_multi(AdamSegs S, float b1, float b2, float eps, float c1, float c2, int zero_grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.start[S.nseg]) return;
+    int s = 0;
+#pragma unroll 1
+    while (s + 1 < S.nseg && i >= S.start[s + 1]) ++s;
+    const int64_t j = i - S.start[s];
+    const float gi = S.g[s][j];
+    const float mi = b1 * S.m[s][j] + (1.f - b1) * gi;
+    const float vi = b2 * S.v[s][j] + (1.f - b2) * gi * gi;
+    S.m[s][j] = mi;
+    S.v[s][j] = vi;
+    S.p[s][j] -= S.lr[s] * (mi / c1) / (sqrtf(vi / c2) + eps);
+    if (zero_grad) S.g[s][j] = 0.f;
+}
+
 }  // namespace
 }  // namespace qg
 
 using namespace qg;
+
+extern "C" qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, float b1, float b2, float eps, int32_t t,
+                                   int32_t zero_grad, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(nseg >= 1 && nseg <= 8 && segs, "nseg must be in [1, 8]");
+    QG_REQUIRE(t >= 1, "t >= 1 required");
+    QG_REQUIRE(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f, "bad Adam constants");
+    AdamSegs S = {};
+    S.nseg = nseg;
+    S.start[0] = 0;
+    for (int k = 0; k < nseg; ++k) {
+        const qg_adam_segment& q = segs[k];
+        QG_REQUIRE(q.count >= 0, "segment %d: count < 0", k);
+        QG_REQUIRE(q.count == 0 || (q.param && q.grad && q.m && q.v), "segment %d: a pointer is NULL", k);
+        S.p[k] = q.param;
+        S.g[k] = q.grad;
+        S.m[k] = q.m;
+        S.v[k] = q.v;
+        S.lr[k] = q.lr;
+        S.start[k + 1] = S.start[k] + q.count;
+    }
+    const int64_t total = S.start[nseg];
+    if (total == 0) return QG_OK;
+    const float c1 = (float)(1.0 - std::pow((double)b1, t));
+    const float c2 = (float)(1.0 - std::pow((double)b2, t));
+    hipStream_t s = (hipStream_t)stream;
+    {
+        QG_TIMED("adam", s);
+        k_adam_multi<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(S, b1, b2, eps, c1, c2, zero_grad);
+    }
+    QG_LAUNCH_CHECK("qg_adam_multi");
+    return QG_OK;
+}
 
 extern "C" int64_t qg_loss_blocks(int64_t count) { return std::max<int64_t>(1, ceil_div(count, kLTile)); }
 

@@ -1,8 +1,8 @@
 """Per-frame residual fitting (Sec. 3.2-3.4, Eq. 4-11) driven entirely through the C ABI.
 
 One optimiser iteration on one training view (one epoch covers all views, Sec. 4.1) enqueues:
-    qg_decode_residuals -> qg_project -> qg_bin -> qg_render_fwd -> qg_l1_loss -> qg_render_bwd
-    -> qg_decode_residuals_bwd -> qg_adam (per parameter group)
+    qg_decode_project -> qg_bin -> qg_render_fwd -> qg_l1_loss -> qg_render_decode_bwd -> qg_adam_multi
+(or the unfused qg_decode_residuals -> qg_project -> ... -> qg_render_bwd -> qg_decode_residuals_bwd)
 on the current stream with no host synchronisation.  The fitted quantities per frame are the
 latents, the shared decoder weights, the pre-gate position residuals l_p and the gate logits a
 (Eq. 5-8); A_{t-1} stays fixed (Eq. 4).  Loss: L1 + lambda_reg * L_reg (Eq. 3 without D-SSIM, Eq. 11).
@@ -87,6 +87,10 @@ class FrameFitter:
         self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(n, 1)
         self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
         self.fused = True
+        keys = list(self.params)
+        self.adam_segs = qg.adam_segments([self.params[k] for k in keys], [self.grads[k] for k in keys],
+                                          [self.m[k] for k in keys], [self.v[k] for k in keys],
+                                          [self.lrs[k] for k in keys])
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
                                bg=cfg.bg, device=dev, capacity=capacity)
         self.qcams = [qg.camera_array([c]) for c in self.cams]
@@ -111,6 +115,7 @@ class FrameFitter:
         for k in self.params:
             self.m[k].zero_()
             self.v[k].zero_()
+            self.grads[k].zero_()
         self.t = 0
 
     # -- the step ------------------------------------------------------------------------------
@@ -142,8 +147,7 @@ class FrameFitter:
             self.decode(stream)
             self.forward_view(v, stream)
         qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
-        for g in self.grads.values():
-            qg.qg_zero(g, g.numel() * 4, stream)
+        # parameter gradients are zero here: they start zeroed and qg_adam_multi clears them after use
         if self.fused:
             qg.qg_render_decode_bwd(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                     self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
@@ -159,8 +163,7 @@ class FrameFitter:
                                        self.grads["a"], self.dws, self.dws_bytes, stream)
         self.t += 1
         b1, b2 = c.betas
-        for k, p in self.params.items():
-            qg.qg_adam(p.numel(), p, self.grads[k], self.m[k], self.v[k], self.lrs[k], b1, b2, c.eps, self.t, stream)
+        qg.qg_adam_multi(self.adam_segs, b1, b2, c.eps, self.t, True, stream)
 
     def loss_value(self, stream=None):
         """L1 of the last step (host sync)."""

@@ -40,6 +40,11 @@ class qg_tiling(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
 
 
+class qg_adam_segment(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("m", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("count", ctypes.c_int64), ("lr", ctypes.c_float)]
+
+
 class qg_projected(ctypes.Structure):
     _fields_ = [("splat", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("rect", ctypes.c_void_p),
                 ("ntiles", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
@@ -79,6 +84,7 @@ def lib():
             "qg_loss_reduce": ([i64, P, P, P], i32),
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
             "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
+            "qg_adam_multi": ([i32, ctypes.POINTER(qg_adam_segment), f32, f32, f32, i32, i32, P], i32),
             "qg_decode_project_lreg_blocks": ([i64], i64),
             "qg_scaled_diff": ([i64, P, P, f32, P, P], i32),
             "qg_gate_init_workspace_size": ([i64], sz),
@@ -333,3 +339,16 @@ def qg_gate_init_workspace_size(n):
 def qg_gate_init(n, d, gamma0, gamma1, tau, a_out, p_out, median_out, ws, ws_bytes, stream=None):
     _check(lib().qg_gate_init(int(n), _ptr(d), float(gamma0), float(gamma1), float(tau), _ptr(a_out), _ptr(p_out),
                               _ptr(median_out), _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def adam_segments(params, grads, ms, vs, lrs):
+    """Host table for qg_adam_multi from parallel lists of tensors and learning rates."""
+    arr = (qg_adam_segment * len(params))()
+    for k, (p, g, m, v, lr) in enumerate(zip(params, grads, ms, vs, lrs)):
+        arr[k] = qg_adam_segment(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr))
+    return arr
+
+
+def qg_adam_multi(segs, b1, b2, eps, t, zero_grad=True, stream=None):
+    _check(lib().qg_adam_multi(len(segs), segs, float(b1), float(b2), float(eps), int(t), int(bool(zero_grad)),
+                               _stream(stream)))

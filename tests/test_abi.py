@@ -61,6 +61,15 @@ def test_bad_arguments_are_rejected_before_launch():
     assert e.value.status == qg.QG_ERR_UNSUPPORTED
     with pytest.raises(qg.QGError):
         qg.qg_adam(10, 1, 1, 1, 1, 0.1, 0.9, 0.999, 1e-8, 0, stream=0)
+    seg = (qg.qg_adam_segment * 9)()
+    with pytest.raises(qg.QGError) as e:
+        qg.qg_adam_multi(seg, 0.9, 0.999, 1e-8, 1, stream=0)
+    assert "nseg" in str(e.value)
+    seg = (qg.qg_adam_segment * 1)()
+    seg[0] = qg.qg_adam_segment(None, None, None, None, 5, 0.1)
+    with pytest.raises(qg.QGError) as e:
+        qg.qg_adam_multi(seg, 0.9, 0.999, 1e-8, 1, stream=0)
+    assert "NULL" in str(e.value)
     views = [_cam() for _ in range(17)]
     assert qg.qg_total_tiles(views, qg.tiling(16, 16)) == -1
     assert qg.qg_total_tiles([_cam(100, 70)], qg.tiling(32, 8)) == 4 * 9

@@ -342,6 +342,40 @@ def test_loss_and_adam_parity(qgm):
     np.testing.assert_allclose(dp.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
 
 
+def test_adam_multi_parity(qgm):
+    """Several parameter groups in one launch: each segment follows the oracle's Adam with its own learning rate,
+    and its gradient is cleared after the step (uneven sizes, one empty segment)."""
+    qg, raster = qgm
+    from oracle import adam as OA
+    rng = synth.rng_for(43)
+    sizes, lrs = [1, 0, 1000, 257, 70001], [0.1, 0.5, 1.6e-4, 0.01, 1e-3]
+    ps = [rng.normal(size=n).astype(np.float32) for n in sizes]
+    dev_p = [to_dev(p) for p in ps]
+    dev_g = [torch.zeros(n, device="cuda") for n in sizes]
+    dev_m = [torch.zeros(n, device="cuda") for n in sizes]
+    dev_v = [torch.zeros(n, device="cuda") for n in sizes]
+    segs = qg.adam_segments(dev_p, dev_g, dev_m, dev_v, lrs)
+    ref = [(p.astype(np.float64), np.zeros(n), np.zeros(n)) for p, n in zip(ps, sizes)]
+    for step in range(1, 4):
+        grads = [rng.normal(size=n).astype(np.float32) for n in sizes]
+        for g, gd in zip(grads, dev_g):
+            gd.copy_(to_dev(g))
+        qg.qg_adam_multi(segs, 0.9, 0.999, 1e-8, step, zero_grad=True)
+        ref = [OA.adam_step(pp, g.astype(np.float64), m, v, step, lr) for (pp, m, v), g, lr in zip(ref, grads, lrs)]
+        torch.cuda.synchronize()
+        for gd in dev_g:
+            assert not gd.any().item()
+    for dp, (pp, _, _) in zip(dev_p, ref):
+        np.testing.assert_allclose(dp.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
+    # zero_grad off leaves the gradients in place
+    for gd in dev_g:
+        gd.fill_(1.0)
+    qg.qg_adam_multi(segs, 0.9, 0.999, 1e-8, 4, zero_grad=False)
+    torch.cuda.synchronize()
+    for gd in dev_g:
+        assert bool((gd == 1.0).all().item())
+
+
 @pytest.mark.parametrize("n,tile", [(3001, (16, 16)), (40, (8, 8)), (5000, (32, 8))])
 def test_fused_equals_two_call_path(qgm, n, tile):
     """qg_decode_project == qg_decode_residuals + qg_project, and qg_render_decode_bwd ==
