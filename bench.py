@@ -81,6 +81,13 @@ def parse():
     p.add_argument("--n", type=int, default=300_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-pixels", type=int, default=8192)
+    p.add_argument("--tile", default="16x16", choices=["8x8", "16x16", "32x8"])
+    p.add_argument("--no-batched", action="store_true", help="skip the batched multi-view step")
+    p.add_argument("--no-frame", action="store_true", help="skip the sec/frame measurement")
+    p.add_argument("--batched-steps", type=int, default=20)
+    p.add_argument("--tune", default="full", choices=["full", "quick", "none"],
+                   help="blend autotuning of the batched step: all 18 candidates, 6, or the default only")
+    p.add_argument("--frame-iters", type=int, default=500)
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run a plain copy of this many MiB first (counter calibration)")
     return p.parse_args()
@@ -133,6 +140,165 @@ def cpu_baseline(scene_planes, cam, n_pix, seed=7):
                       f"pixels"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_section(args):
+    """The batched multi-view step: 500 k Gaussians, 12 views of one timestep at three resolutions, every kernel
+    launched once for all views, the whole step (decode+projection, binning, heaviest-first schedule, blend,
+    12 losses, adjoint, Adam) replayed from one captured graph; blend schedule picked by the autotuner.
+    Beside it: the same 12 views processed one view per launch (sum of single-view step times)."""
+    import torch
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.autotune import autotune, candidates, time_steps
+    from paper_2412_04469_amd.fit import BatchedFitter, FitConfig, FrameFitter, render_views
+    wl = synth.workload_batched()
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    target = torch.as_tensor(wl.target_scene.planes()).to(dev)
+    gts = render_views(target, wl.cams, FitConfig())
+    torch.cuda.synchronize()
+    log(f"batched: ground truth for {len(wl.cams)} views rendered")
+
+    def make(tile, batch, persistent):
+        f = BatchedFitter(prev, wl.cams, gts, FitConfig(tile=tuple(tile)), batch=batch, persistent=persistent)
+        f.size_capacity()
+        return f
+
+    if args.tune == "full":
+        cands = candidates()
+    elif args.tune == "quick":
+        cands = [dict(tile=t, batch=64, persistent=p) for t in ((16, 16), (8, 8), (32, 8)) for p in (False, True)]
+    else:
+        cands = [dict(tile=(16, 16), batch=64, persistent=True)]
+    best, table = autotune(make, cands, steps=5, warmup=1, log=log)
+    f = make(**best)
+    ms = time_steps(f, args.batched_steps, 3)
+    overflow = f.overflowed()
+    px = sum(c.width * c.height for c in wl.cams)
+    pairs = int(f.rasts[0].num_pairs.item())
+    del f
+    torch.cuda.empty_cache()
+    # the same views, one view per launch sequence (single-view fit steps at each resolution)
+    per_view = 0.0
+    by_res = {}
+    for v, c in enumerate(wl.cams):
+        by_res.setdefault((c.width, c.height), []).append(v)
+    for res, vs in by_res.items():
+        ff = FrameFitter(prev, [wl.cams[v] for v in vs], [gts[v] for v in vs], FitConfig())
+        ff.size_capacity()
+        for i in range(2):
+            ff.step(i % len(vs))
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        reps = 2
+        t0.record()
+        for _ in range(reps):
+            for k in range(len(vs)):
+                ff.step(k)
+        t1.record()
+        torch.cuda.synchronize()
+        per_view += t0.elapsed_time(t1) / reps
+        del ff
+        torch.cuda.empty_cache()
+    log(f"batched: {ms:.3f} ms/step with {best}; per-view launches {per_view:.3f} ms")
+    return {"workload": wl.name, "n_gaussians": wl.scene.n, "views": len(wl.cams), "pixels": px,
+            "ms_per_step": round(ms, 4), "mpix_per_s": round(px / (ms * 1e-3) / 1e6, 1), "pairs": pairs,
+            "overflow": overflow, "schedule": {"tile": "%dx%d" % tuple(best["tile"]), "batch": best["batch"],
+                                               "persistent": best["persistent"]},
+            "autotune_ms": {"%dx%d/b%d/%s" % (c["tile"][0], c["tile"][1], c["batch"],
+                                              "persistent" if c["persistent"] else "grid"): round(t, 4)
+                            for c, t in table},
+            "per_view_launches_ms": round(per_view, 4),
+            "form": "one captured graph per step; loss = mean of per-view mean L1"}
+
+
+def _fit_to_target(fitter, step_fn, iters, check_every, eval_cam, gt_eval, gate_fn, target=None):
+    """Frame clock: gate initialisation then optimiser steps; PSNR on the held-out view every check_every steps
+    with the clock paused.  Returns (trajectory [(iteration, seconds, psnr)], seconds to the first check at or
+    above target, or None)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a_init = gate_fn()
+    fitter.reset_frame(a_init=a_init)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    traj, hit = [], None
+    it = 0
+    while it < iters:
+        t0 = time.perf_counter()
+        for _ in range(min(check_every, iters - it)):
+            step_fn(it)
+            it += 1
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        p = fitter.psnr(eval_cam, gt_eval)
+        traj.append((it, round(elapsed, 4), round(p, 3)))
+        if target is not None and hit is None and p >= target:
+            hit = elapsed
+            break
+    return traj, hit
+
+
+def frame_section(args):
+    """Seconds per frame to the target PSNR (the plain form's held-out PSNR after its full iteration count) on
+    the per-frame fit workload: the plain form (one view per step) and the batched form (10 views per step,
+    graph-replayed), both with the gate initialisation of Eq. 9-10 on the frame clock."""
+    import torch
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.fit import BatchedFitter, FitConfig, FrameFitter, GateInitializer, render_views
+    wl = synth.workload_fit(n=args.n)
+    cfg = FitConfig()
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    target = torch.as_tensor(wl.target_scene.planes()).to(dev)
+    gts_prev = render_views(prev, wl.cams, cfg)
+    gts = render_views(target, wl.cams, cfg)
+    held = wl.extras["held_out"]
+    gt_held = render_views(target, [held], cfg)[0]
+    V = len(wl.cams)
+
+    gi = GateInitializer(wl.scene.n, wl.cams, cfg)
+    gi(prev, gts_prev, gts)  # buffers warm (the pair capacity settles on the first pass)
+
+    def gate_fn():
+        return gi(prev, gts_prev, gts)
+
+    order = np.random.default_rng(0)
+    perm = np.concatenate([order.permutation(V) for _ in range(args.frame_iters // V + 2)])
+    plain = FrameFitter(prev, wl.cams, gts, cfg)
+    plain.size_capacity()
+    traj_p, _ = _fit_to_target(plain, lambda i: plain.step(int(perm[i])), args.frame_iters, 25, held, gt_held,
+                               gate_fn)
+    tgt = traj_p[-1][2]
+    hit_p = next(s for (i, s, p) in traj_p if p >= tgt)
+    log(f"frame: plain reaches {tgt:.3f} dB at {hit_p:.3f} s")
+    del plain
+    torch.cuda.empty_cache()
+    bat = BatchedFitter(prev, wl.cams, gts, cfg, persistent=True, eval_cam=held)
+    bat.size_capacity()
+    w0 = (bat.W1.clone(), bat.W2.clone())
+    bat.step()
+    bat.step()  # both view groups captured; the decoder is put back to its initial weights below
+    bat.W1.copy_(w0[0])
+    bat.W2.copy_(w0[1])
+    traj_b, hit_b = _fit_to_target(bat, lambda i: bat.step(), args.frame_iters, 25, held, gt_held, gate_fn,
+                                   target=tgt)
+    log(f"frame: batched {'reaches target at %.3f s' % hit_b if hit_b else 'does not reach the target'}")
+    ovf = bat.overflowed()
+    del bat
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "target_psnr_db": tgt, "iterations_plain": args.frame_iters,
+            "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p},
+            "batched": {"sec_per_frame": None if hit_b is None else round(hit_b, 4), "views_per_step": 10,
+                        "trajectory": traj_b, "overflow": ovf},
+            "protocol": "frame clock from gate initialisation (20 forward + 20 adjoint passes) through the optimiser "
+                        "steps; held-out PSNR every 25 steps with the clock paused"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -147,7 +313,7 @@ def main():
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
     wl = synth.workload_fit(n=args.n)
-    cfg = FitConfig()
+    cfg = FitConfig(tile=tuple(int(x) for x in args.tile.split("x")))
     dev = torch.device("cuda")
     prev = torch.as_tensor(wl.scene.planes()).to(dev)
     target = torch.as_tensor(wl.target_scene.planes()).to(dev)
@@ -215,12 +381,19 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "n_gaussians": args.n, "width": 1352, "height": 1014, "views": V,
-                   "tile": "16x16", "sh_degree": 3, "decoder": "8->32->56 SiLU", "pairs_max": P_max,
+                   "tile": args.tile, "sh_degree": 3, "decoder": "8->32->56 SiLU", "pairs_max": P_max,
                    "overflow": overflow},
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "launches_per_step": {k: counts[k] for k in sorted(counts)},
     }
+    del fitter
+    torch.cuda.empty_cache()
+    log(f"headline: {ms_step:.4f} ms/step")
+    if not args.no_batched:
+        result["batched"] = batched_section(args)
+    if not args.no_frame:
+        result["sec_per_frame"] = frame_section(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl.scene.planes(), wl.cams[0], args.cpu_pixels)
     print(json.dumps(result), flush=True)

@@ -66,9 +66,24 @@ typedef struct {
     float z_near;
 } qg_camera;
 
-/* Tile shape: one of 8x8, 16x16, 32x8 (tile_w x tile_h). */
+/*
+ * How the image plane is cut into tiles and how the blend kernels walk them.
+ *   tile_w x tile_h  one of 8x8, 16x16, 32x8.
+ *   batch            tile-list entries staged per LDS batch in the blend kernels: 32, 64 or 128 (0 = 64).
+ *                    Results do not depend on it.
+ *   reserved         must be 0.
+ *   schedule         optional device buffer written by qg_schedule_tiles for the current binning: the blend
+ *                    kernels then run a grid that is resident on the chip at once and take tiles from it,
+ *                    heaviest first.  NULL = one workgroup per tile.  Results do not depend on it, except
+ *                    for the order of the float atomics of the blend adjoint.  Calls that use one schedule
+ *                    buffer must not run concurrently.
+ * qg_project and qg_bin read only the tile shape.
+ */
 typedef struct {
     int32_t tile_w, tile_h;
+    int32_t batch;
+    int32_t reserved;
+    uint32_t* schedule;
 } qg_tiling;
 
 /*
@@ -187,6 +202,20 @@ qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* cams, int32_t
                         float* const* T_final, uint32_t* const* last, qg_stream stream);
 
 /*
+ * Heaviest-first tile order for the blend kernels (a scheduling aid; no arithmetic of the method).
+ * schedule [device] qg_schedule_words(total_tiles) words: 2 work counters, QG_SCHEDULE_BUCKETS bucket
+ * offsets, then the order of all tiles by decreasing entry count (on a log scale, 8 steps per octave;
+ * order within a step is arbitrary).  Build it after each qg_bin and pass it as qg_tiling.schedule to
+ * qg_render_fwd / qg_render_bwd / qg_render_decode_bwd; every such call leaves the counters at zero.
+ * Stream-ordered, no allocation, safe under graph capture.
+ */
+#define QG_SCHEDULE_BUCKETS 512
+#define QG_SCHEDULE_HEADER_WORDS (2 + QG_SCHEDULE_BUCKETS)
+int64_t qg_schedule_words(int64_t total_tiles);
+qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile_ranges, uint32_t* schedule,
+                            int64_t schedule_words, qg_stream stream);
+
+/*
  * Adjoint of qg_render_fwd followed by the adjoint of qg_project (Eq. 1-2), for the loss gradient
  * grad_image [V] -> [3][H][W].  The blend adjoint walks each pixel's entries in reverse from `last`,
  * recomputing T_i = T_{i+1} / (1 - alpha_i) from T_final (no per-pixel lists are stored).
@@ -289,6 +318,9 @@ qg_status qg_adam(int64_t count, float* param, const float* grad, float* m, floa
  * Several parameter groups in one launch (up to 8 segments), same update as qg_adam with a learning rate
  * per segment.  If zero_grad is non-zero each gradient is set to 0 after it is read, so the next backward
  * can accumulate (+=) into it without a separate zeroing pass.  segs [host].
+ * step_state: NULL to use the host step count t (>= 1); otherwise a device buffer of 3 words {int32 step,
+ * float 1 - b1^step, float 1 - b2^step}: the call increments the step on the device and uses it (t is
+ * ignored), so a captured graph can replay the update.  Start it at {0, 0, 0}.
  */
 typedef struct {
     float* param;
@@ -299,7 +331,7 @@ typedef struct {
     float lr;
 } qg_adam_segment;
 qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, float b1, float b2, float eps, int32_t t,
-                        int32_t zero_grad, qg_stream stream);
+                        int32_t* step_state, int32_t zero_grad, qg_stream stream);
 
 /* Zero `bytes` bytes at dst with a fill kernel (no memset node, so it is safe to capture). */
 qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream);

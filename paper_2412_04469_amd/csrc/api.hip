@@ -51,6 +51,8 @@ void timing_begin(const char* name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
     if (!g_only.empty() && g_only != name) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;  // not in graphs
     t_name = name;
     t_start = get_event();
     if (t_start) hipEventRecord(t_start, s);
@@ -67,8 +69,10 @@ void timing_end(hipStream_t s) {
 }
 
 bool tiling_ok(qg_tiling t) {
-    return (t.tile_w == 8 && t.tile_h == 8) || (t.tile_w == 16 && t.tile_h == 16) ||
-           (t.tile_w == 32 && t.tile_h == 8);
+    const bool shape = (t.tile_w == 8 && t.tile_h == 8) || (t.tile_w == 16 && t.tile_h == 16) ||
+                       (t.tile_w == 32 && t.tile_h == 8);
+    const bool batch = t.batch == 0 || t.batch == 32 || t.batch == 64 || t.batch == 128;
+    return shape && batch && t.reserved == 0;
 }
 
 bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V, qg_tiling tiling,
@@ -82,7 +86,8 @@ bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V,
         return false;
     }
     if (!tiling_ok(tiling)) {
-        set_error("unsupported tiling %dx%d (8x8, 16x16, 32x8)", tiling.tile_w, tiling.tile_h);
+        set_error("unsupported tiling %dx%d batch %d (8x8, 16x16, 32x8; batch 0, 32, 64, 128; reserved 0)",
+                  tiling.tile_w, tiling.tile_h, tiling.batch);
         return false;
     }
     if (need_proj && !proj) {

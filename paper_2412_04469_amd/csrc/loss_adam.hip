@@ -84,9 +84,23 @@ struct AdamSegs {
 
 // All parameter groups of one optimiser step in one launch; the gradient is cleared after it is read so the
 // next backward can accumulate into it without a separate zeroing pass.
-__global__ void k_adam_multi(AdamSegs S, float b1, float b2, float eps, float c1, float c2, int zero_grad) {
+// Device step counter: state[0] (int) is incremented, state[1], state[2] receive the bias corrections
+// 1 - b1^t, 1 - b2^t of the new step (computed in double, rounded once, as on the host path).
+__global__ void k_adam_tick(int32_t* __restrict__ state, float b1, float b2) {
+    const int32_t t = state[0] + 1;
+    state[0] = t;
+    reinterpret_cast<float*>(state)[1] = (float)(1.0 - pow((double)b1, (double)t));
+    reinterpret_cast<float*>(state)[2] = (float)(1.0 - pow((double)b2, (double)t));
+}
+
+__global__ void k_adam_multi(AdamSegs S, float b1, float b2, float eps, float c1, float c2, int zero_grad,
+                             const int32_t* __restrict__ state) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.start[S.nseg]) return;
+    if (state) {
+        c1 = reinterpret_cast<const float*>(state)[1];
+        c2 = reinterpret_cast<const float*>(state)[2];
+    }
     int s = 0;
 #pragma unroll 1
     while (s + 1 < S.nseg && i >= S.start[s + 1]) ++s;
@@ -106,10 +120,10 @@ __global__ void k_adam_multi(AdamSegs S, float b1, float b2, float eps, float c1
 using namespace qg;
 
 extern "C" qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, float b1, float b2, float eps, int32_t t,
-                                   int32_t zero_grad, qg_stream stream) {
+                                   int32_t* step_state, int32_t zero_grad, qg_stream stream) {
     clear_error();
     QG_REQUIRE(nseg >= 1 && nseg <= 8 && segs, "nseg must be in [1, 8]");
-    QG_REQUIRE(t >= 1, "t >= 1 required");
+    QG_REQUIRE(step_state || t >= 1, "t >= 1 required");
     QG_REQUIRE(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f, "bad Adam constants");
     AdamSegs S = {};
     S.nseg = nseg;
@@ -126,13 +140,14 @@ extern "C" qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, fl
         S.start[k + 1] = S.start[k] + q.count;
     }
     const int64_t total = S.start[nseg];
-    if (total == 0) return QG_OK;
-    const float c1 = (float)(1.0 - std::pow((double)b1, t));
-    const float c2 = (float)(1.0 - std::pow((double)b2, t));
+    const float c1 = step_state ? 1.f : (float)(1.0 - std::pow((double)b1, t));
+    const float c2 = step_state ? 1.f : (float)(1.0 - std::pow((double)b2, t));
     hipStream_t s = (hipStream_t)stream;
     {
         QG_TIMED("adam", s);
-        k_adam_multi<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(S, b1, b2, eps, c1, c2, zero_grad);
+        if (step_state) k_adam_tick<<<1, 1, 0, s>>>(step_state, b1, b2);
+        if (total > 0)
+            k_adam_multi<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(S, b1, b2, eps, c1, c2, zero_grad, step_state);
     }
     QG_LAUNCH_CHECK("qg_adam_multi");
     return QG_OK;

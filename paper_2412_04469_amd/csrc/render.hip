@@ -70,18 +70,14 @@ struct TileGeom {
     static constexpr int ROWS_PER_K = 64 / TW;  // rows advanced per pixel slot
 };
 
-template <int TW, int TH>
-__global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
-                                                   const uint32_t* __restrict__ ranges, float bg0, float bg1,
-                                                   float bg2, ViewPtrsF image, ViewPtrsF tfinal, ViewPtrsU lastp,
-                                                   int64_t per_xcd) {
+// Blend of one tile (one wave); BD entries are staged per LDS batch.
+template <int TW, int TH, int BD>
+__device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __restrict__ vals,
+                                         const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
+                                         const ViewPtrsF& image, const ViewPtrsF& tfinal, const ViewPtrsU& lastp,
+                                         int64_t tile, float4* s_a, float4* s_b, float* s_c) {
     constexpr int PPL = TileGeom<TW, TH>::PPL;
     constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
-    __shared__ float4 s_a[64];  // x, y, o, A'
-    __shared__ float4 s_b[64];  // 2B', C', r, g
-    __shared__ float s_c[64];   // b
-    const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
-    if (tile >= vt.total_tiles) return;
     const int v = view_of_tile(vt, (uint32_t)tile);
     const CamDev& cam = vt.cam[v];
     const int local = (int)(tile - cam.tile_off);
@@ -103,22 +99,26 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
         run[k] = px < cam.width && (py0 + k * RPK) < cam.height;
     }
     const float* __restrict__ splat = vt.proj[v].splat;
-    for (uint32_t b = s; b < e; b += 64) {
+    for (uint32_t b = s; b < e; b += BD) {
         bool any = false;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) any |= run[k];
         if (__ballot(any) == 0) break;
-        const uint32_t j = b + lane;
-        if (j < e) {
-            const uint32_t gid = vals[j];
-            const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
-            const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-            s_a[lane] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
-            s_b[lane] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
-            s_c[lane] = r2.z;
+#pragma unroll
+        for (int q = 0; q < (BD + 63) / 64; ++q) {
+            const int slot = q * 64 + lane;
+            const uint32_t j = b + (uint32_t)slot;
+            if (slot < BD && j < e) {
+                const uint32_t gid = vals[j];
+                const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
+                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                s_a[slot] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+                s_b[slot] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
+                s_c[slot] = r2.z;
+            }
         }
         __syncthreads();
-        const int cnt = (int)min(64u, e - b);
+        const int cnt = (int)min((uint32_t)BD, e - b);
         for (int jj = 0; jj < cnt; ++jj) {
             const float4 a = s_a[jj];
             const float4 bb = s_b[jj];
@@ -167,6 +167,54 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     }
 }
 
+// Work distribution.  Without a schedule: one workgroup per tile, XCD-aware order.  With a schedule (the
+// order of qg_schedule_tiles, heaviest tiles first): a grid that fits on the chip at once, each workgroup
+// taking the next tile from a device counter until the list is exhausted; the last workgroup to finish
+// puts both counters back to zero, so the schedule is ready for the next kernel without a reset.
+struct Sched {
+    const uint32_t* order;  // [total_tiles] or nullptr
+    uint32_t* ctr;          // [2]: next item, finished workgroups
+};
+
+__device__ __forceinline__ uint32_t next_item(uint32_t* ctr) {
+    uint32_t item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(ctr, 1u);
+    return __builtin_amdgcn_readfirstlane(item);
+}
+
+__device__ __forceinline__ void finish_sched(uint32_t* ctr) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(ctr + 1, 1u) == gridDim.x - 1) {
+            __threadfence();
+            atomicExch(ctr, 0u);
+            atomicExch(ctr + 1, 0u);
+        }
+    }
+}
+
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                                   float bg2, ViewPtrsF image, ViewPtrsF tfinal, ViewPtrsU lastp,
+                                                   int64_t per_xcd, Sched sc) {
+    __shared__ float4 s_a[BD];  // x, y, o, A'
+    __shared__ float4 s_b[BD];  // 2B', C', r, g
+    __shared__ float s_c[BD];   // b
+    if (sc.order == nullptr) {
+        const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
+        if (tile < vt.total_tiles)
+            fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c);
+        return;
+    }
+    for (;;) {
+        const uint32_t item = next_item(sc.ctr);
+        if (item >= (uint32_t)vt.total_tiles) break;
+        fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, sc.order[item], s_a, s_b, s_c);
+    }
+    finish_sched(sc.ctr);
+}
+
 // ---- wave64 sums of K values at once: DPP inclusive scans inside each 16-lane row (row_shr 1, 2, 4, 8,
 // interleaved over the K values so consecutive DPP operations never depend on each other), then the four
 // row totals go through LDS and are added by the lanes that issue the atomics.
@@ -188,21 +236,15 @@ __device__ __forceinline__ void row_sums(float (&v)[K]) {
     for (int k = 0; k < K; ++k) v[k] += dpp_term<0x118, 0xf>(v[k]);  // row_shr:8
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t* __restrict__ vals,
-                                                   const uint32_t* __restrict__ ranges, float bg0, float bg1,
-                                                   float bg2, ViewPtrsCF tfinal, ViewPtrsCU lastp, ViewPtrsCF gimage,
-                                                   float* __restrict__ grad2d, int64_t g2d_view_stride,
-                                                   int64_t per_xcd) {
+template <int TW, int TH, int BD>
+__device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __restrict__ vals,
+                                         const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
+                                         const ViewPtrsCF& tfinal, const ViewPtrsCU& lastp, const ViewPtrsCF& gimage,
+                                         float* __restrict__ grad2d, int64_t g2d_view_stride, int64_t tile,
+                                         float4* s_a, float4* s_b, float4* s_c, uint32_t* s_gid,
+                                         float (*s_red)[12]) {
     constexpr int PPL = TileGeom<TW, TH>::PPL;
     constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
-    __shared__ float4 s_a[64];  // x, y, o, A'
-    __shared__ float4 s_b[64];  // 2B', C', r, g
-    __shared__ float4 s_c[64];  // b, A, B, C
-    __shared__ uint32_t s_gid[64];
-    __shared__ float s_red[4][12];  // row totals of the 9 gradient components
-    const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
-    if (tile >= vt.total_tiles) return;
     const int v = view_of_tile(vt, (uint32_t)tile);
     const CamDev& cam = vt.cam[v];
     const int local = (int)(tile - cam.tile_off);
@@ -239,16 +281,20 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
     const float* __restrict__ splat = vt.proj[v].splat;
     float* __restrict__ g2 = grad2d + (int64_t)v * g2d_view_stride;
     for (uint32_t hi = maxlast; hi > s;) {
-        const uint32_t lo = hi - s > 64u ? hi - 64u : s;
-        const uint32_t j = lo + lane;
-        if (j < hi) {
-            const uint32_t gid = vals[j];
-            const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
-            const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-            s_a[lane] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
-            s_b[lane] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
-            s_c[lane] = make_float4(r2.z, r1.x, r1.y, r1.z);
-            s_gid[lane] = gid;
+        const uint32_t lo = hi - s > (uint32_t)BD ? hi - (uint32_t)BD : s;
+#pragma unroll
+        for (int q = 0; q < (BD + 63) / 64; ++q) {
+            const int slot = q * 64 + lane;
+            const uint32_t j = lo + (uint32_t)slot;
+            if (slot < BD && j < hi) {
+                const uint32_t gid = vals[j];
+                const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
+                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                s_a[slot] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+                s_b[slot] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
+                s_c[slot] = make_float4(r2.z, r1.x, r1.y, r1.z);
+                s_gid[slot] = gid;
+            }
         }
         __syncthreads();
         for (int jj = (int)(hi - lo) - 1; jj >= 0; --jj) {
@@ -312,30 +358,185 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
     }
 }
 
-template <int TW, int TH>
-qg_status launch_fwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* ranges, const float* bg,
-                     const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp, hipStream_t s) {
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                                   float bg2, ViewPtrsCF tfinal, ViewPtrsCU lastp, ViewPtrsCF gimage,
+                                                   float* __restrict__ grad2d, int64_t g2d_view_stride,
+                                                   int64_t per_xcd, Sched sc) {
+    __shared__ float4 s_a[BD];  // x, y, o, A'
+    __shared__ float4 s_b[BD];  // 2B', C', r, g
+    __shared__ float4 s_c[BD];  // b, A, B, C
+    __shared__ uint32_t s_gid[BD];
+    __shared__ float s_red[4][12];  // row totals of the 9 gradient components
+    if (sc.order == nullptr) {
+        const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
+        if (tile < vt.total_tiles)
+            bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride,
+                                 tile, s_a, s_b, s_c, s_gid, s_red);
+        return;
+    }
+    for (;;) {
+        const uint32_t item = next_item(sc.ctr);
+        if (item >= (uint32_t)vt.total_tiles) break;
+        bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride,
+                             sc.order[item], s_a, s_b, s_c, s_gid, s_red);
+    }
+    finish_sched(sc.ctr);
+}
+
+// Resident workgroups of a kernel on the whole device (the persistent grid size), cached per kernel.
+template <class K>
+int64_t resident_blocks(K kernel) {
+    static int64_t cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || cus <= 0 ||
+            per_cu <= 0)
+            return 0;
+        cached = (int64_t)cus * per_cu;
+    }
+    return cached;
+}
+
+inline Sched make_sched(const qg_tiling& t, int64_t total_tiles) {
+    Sched sc = {nullptr, nullptr};
+    if (t.schedule) {
+        sc.ctr = t.schedule;
+        sc.order = t.schedule + QG_SCHEDULE_HEADER_WORDS;
+    }
+    (void)total_tiles;
+    return sc;
+}
+
+template <int TW, int TH, int BD>
+qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
+                       const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp,
+                       hipStream_t s) {
     const int64_t per = ceil_div(vt.total_tiles, 8);
+    const Sched sc = make_sched(tiling, vt.total_tiles);
+    int64_t grid = per * 8;
+    if (sc.order) {
+        const int64_t res = resident_blocks(k_render_fwd<TW, TH, BD>);
+        QG_REQUIRE(res > 0, "occupancy query failed");
+        grid = std::min<int64_t>(vt.total_tiles, res);
+    }
     {
         QG_TIMED("render_fwd", s);
-        k_render_fwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp, per);
+        k_render_fwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp,
+                                                                per, sc);
     }
     QG_LAUNCH_CHECK("qg_render_fwd");
     return QG_OK;
 }
 
-template <int TW, int TH>
-qg_status launch_bwd(const ViewTable& vt, const uint32_t* vals, const uint32_t* ranges, const float* bg,
-                     const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi, float* grad2d,
-                     int64_t stride, hipStream_t s) {
+template <int TW, int TH, int BD>
+qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
+                       const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
+                       float* grad2d, int64_t stride, hipStream_t s) {
     const int64_t per = ceil_div(vt.total_tiles, 8);
+    const Sched sc = make_sched(tiling, vt.total_tiles);
+    int64_t grid = per * 8;
+    if (sc.order) {
+        const int64_t res = resident_blocks(k_render_bwd<TW, TH, BD>);
+        QG_REQUIRE(res > 0, "occupancy query failed");
+        grid = std::min<int64_t>(vt.total_tiles, res);
+    }
     {
         QG_TIMED("blend_bwd", s);
-        k_render_bwd<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
-                                                                 grad2d, stride, per);
+        k_render_bwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
+                                                                grad2d, stride, per, sc);
     }
     QG_LAUNCH_CHECK("qg_render_bwd");
     return QG_OK;
+}
+
+template <int TW, int TH>
+qg_status launch_fwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
+                       const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp,
+                       hipStream_t s) {
+    if (t.batch == 32) return launch_fwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, img, tf, lp, s);
+    if (t.batch == 128) return launch_fwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, img, tf, lp, s);
+    return launch_fwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, img, tf, lp, s);
+}
+
+template <int TW, int TH>
+qg_status launch_bwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
+                       const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
+                       float* grad2d, int64_t stride, hipStream_t s) {
+    if (t.batch == 32) return launch_bwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    if (t.batch == 128) return launch_bwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    return launch_bwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+}
+
+qg_status launch_fwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
+                     const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp, hipStream_t s) {
+    if (t.tile_w == 16) return launch_fwd_b<16, 16>(vt, t, vals, ranges, bg, img, tf, lp, s);
+    if (t.tile_w == 8) return launch_fwd_b<8, 8>(vt, t, vals, ranges, bg, img, tf, lp, s);
+    return launch_fwd_b<32, 8>(vt, t, vals, ranges, bg, img, tf, lp, s);
+}
+
+qg_status launch_bwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
+                     const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi, float* grad2d,
+                     int64_t stride, hipStream_t s) {
+    if (t.tile_w == 16) return launch_bwd_b<16, 16>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    if (t.tile_w == 8) return launch_bwd_b<8, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    return launch_bwd_b<32, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+}
+
+// ---- heaviest-first tile order --------------------------------------------------------------------
+// Tiles are bucketed by the length of their entry list on a log scale (float exponent and the top three
+// mantissa bits, 8 buckets per octave), buckets are laid out heaviest first, and tiles are scattered into
+// their bucket (order inside a bucket is arbitrary: every tile is blended by exactly one wave either way).
+constexpr int kSchedBuckets = QG_SCHEDULE_BUCKETS;
+
+__device__ __forceinline__ uint32_t sched_bucket(uint32_t len) {
+    if (len == 0) return kSchedBuckets - 1;
+    const uint32_t key = (__float_as_uint((float)len) >> 20) - (127u << 3);  // 8 * log2(len), >= 0
+    return (uint32_t)(kSchedBuckets - 2) - min(key, (uint32_t)(kSchedBuckets - 2));
+}
+
+__global__ void k_sched_clear(uint32_t* __restrict__ w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < QG_SCHEDULE_HEADER_WORDS) w[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sched_hist(int64_t total, const uint32_t* __restrict__ ranges,
+                                                    uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[kSchedBuckets];
+    for (int k = threadIdx.x; k < kSchedBuckets; k += blockDim.x) s_h[k] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total) atomicAdd(&s_h[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kSchedBuckets; k += blockDim.x)
+        if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
+}
+
+// Exclusive scan of the bucket counts in place (one workgroup of kSchedBuckets threads).
+__global__ __launch_bounds__(kSchedBuckets) void k_sched_scan(uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s[kSchedBuckets];
+    const int k = threadIdx.x;
+    const uint32_t c = hist[k];
+    s[k] = c;
+    __syncthreads();
+    for (int off = 1; off < kSchedBuckets; off <<= 1) {
+        const uint32_t add = k >= off ? s[k - off] : 0u;
+        __syncthreads();
+        s[k] += add;
+        __syncthreads();
+    }
+    hist[k] = s[k] - c;
+}
+
+__global__ void k_sched_scatter(int64_t total, const uint32_t* __restrict__ ranges, uint32_t* __restrict__ offs,
+                                uint32_t* __restrict__ order) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const uint32_t pos = atomicAdd(&offs[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    order[pos] = (uint32_t)t;
 }
 
 }  // namespace
@@ -350,9 +551,7 @@ qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t
         lp.p[v] = last[v];
         gi.p[v] = grad_image[v];
     }
-    if (tiling.tile_w == 16) return launch_bwd<16, 16>(vt, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
-    if (tiling.tile_w == 8) return launch_bwd<8, 8>(vt, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
-    return launch_bwd<32, 8>(vt, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    return launch_bwd(vt, tiling, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
 }
 
 }  // namespace qg
@@ -375,10 +574,7 @@ extern "C" qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* ca
         tf.p[v] = T_final[v];
         lp.p[v] = last[v];
     }
-    hipStream_t s = (hipStream_t)stream;
-    if (tiling.tile_w == 16) return launch_fwd<16, 16>(vt, vals, tile_ranges, bg, img, tf, lp, s);
-    if (tiling.tile_w == 8) return launch_fwd<8, 8>(vt, vals, tile_ranges, bg, img, tf, lp, s);
-    return launch_fwd<32, 8>(vt, vals, tile_ranges, bg, img, tf, lp, s);
+    return launch_fwd(vt, tiling, vals, tile_ranges, bg, img, tf, lp, (hipStream_t)stream);
 }
 
 extern "C" size_t qg_render_bwd_workspace_size(int64_t n, int32_t V) {
@@ -416,13 +612,36 @@ extern "C" qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, in
     const int64_t stride = n * QG_GRAD2D_STRIDE;
     qg_status st = qg_zero(grad2d, (int64_t)V * stride * 4, stream);
     if (st != QG_OK) return st;
-    if (tiling.tile_w == 16)
-        st = launch_bwd<16, 16>(vt, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
-    else if (tiling.tile_w == 8)
-        st = launch_bwd<8, 8>(vt, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
-    else
-        st = launch_bwd<32, 8>(vt, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
+    st = launch_bwd(vt, tiling, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
     if (st != QG_OK) return st;
     return project_bwd_launch(n, ld, attrs, sh_degree, vt, dilation, grad2d, stride, grad_attrs, grad_xy_abs,
                               grad_xy, s);
+}
+
+extern "C" int64_t qg_schedule_words(int64_t total_tiles) {
+    if (total_tiles < 0) return -1;
+    return QG_SCHEDULE_HEADER_WORDS + total_tiles;
+}
+
+extern "C" qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile_ranges, uint32_t* schedule,
+                                       int64_t schedule_words, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(total_tiles >= 1 && total_tiles < (1ll << 32), "total_tiles=%lld outside [1, 2^32)",
+               (long long)total_tiles);
+    QG_REQUIRE(tile_ranges && schedule, "a pointer is NULL");
+    QG_REQUIRE(schedule_words >= qg_schedule_words(total_tiles), "schedule buffer too small: %lld < %lld words",
+               (long long)schedule_words, (long long)qg_schedule_words(total_tiles));
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* hist = schedule + 2;
+    uint32_t* order = schedule + QG_SCHEDULE_HEADER_WORDS;
+    const unsigned grid = (unsigned)ceil_div(total_tiles, 256);
+    {
+        QG_TIMED("schedule", s);
+        k_sched_clear<<<(unsigned)ceil_div(QG_SCHEDULE_HEADER_WORDS, 256), 256, 0, s>>>(schedule);
+        k_sched_hist<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist);
+        k_sched_scan<<<1, kSchedBuckets, 0, s>>>(hist);
+        k_sched_scatter<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist, order);
+    }
+    QG_LAUNCH_CHECK("qg_schedule_tiles");
+    return QG_OK;
 }

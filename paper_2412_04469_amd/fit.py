@@ -51,18 +51,16 @@ def xavier_decoder(seed: int, L=8, H=32, M=56):
     return (rng.uniform(-a1, a1, size=(H, L)).astype(np.float32), rng.uniform(-a2, a2, size=(M, H)).astype(np.float32))
 
 
-class FrameFitter:
-    """Holds A_{t-1}, the residual parameters of frame t and their Adam state; all views share one resolution."""
+class ResidualState:
+    """A_{t-1} and the residual parameters of frame t (Eq. 4-8) with their gradients and Adam state."""
 
-    def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
-                 capacity=None, seed=0):
+    def __init__(self, prev_attrs: torch.Tensor, cfg: FitConfig = FitConfig(), W1=None, W2=None, seed=0):
         self.cfg = cfg
         self.prev = prev_attrs.contiguous()
         self.n = int(self.prev.shape[1])
         self.ld = int(self.prev.stride(0))
-        self.cams = list(cams)
-        self.gts = gts
         dev = self.prev.device
+        self.device = dev
         n, L, H = self.n, cfg.latent_dim, cfg.hidden
         if W1 is None:
             W1, W2 = xavier_decoder(seed, L, H, 56)
@@ -78,19 +76,75 @@ class FrameFitter:
         self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.t = 0
+        # device step counter {step, 1 - b1^step, 1 - b2^step} for updates that replay from a graph
+        self.step_state = torch.zeros(4, dtype=torch.int32, device=dev)
         self.attrs = torch.empty_like(self.prev)
         self.gate = torch.empty(max(n, 1), device=dev)
         self.lreg_part = torch.empty(qg.qg_decode_lreg_blocks(n), device=dev)
+        keys = list(self.params)
+        self.adam_segs = qg.adam_segments([self.params[k] for k in keys], [self.grads[k] for k in keys],
+                                          [self.m[k] for k in keys], [self.v[k] for k in keys],
+                                          [self.lrs[k] for k in keys])
+
+    def reset_frame(self, prev_attrs=None, gts=None, a_init=None, lat_init=None, lp_init=None):
+        """New frame: latents and position residuals restart at zero (or at the given initial values), the
+        decoder is warm-started, Adam restarts."""
+        if prev_attrs is not None:
+            self.prev.copy_(prev_attrs)
+        if gts is not None:
+            self.gts = gts
+        for dst, init in ((self.lat, lat_init), (self.lp, lp_init), (self.a, a_init)):
+            if init is None:
+                dst.zero_()
+            else:
+                dst.copy_(init)
+        for k in self.params:
+            self.m[k].zero_()
+            self.v[k].zero_()
+            self.grads[k].zero_()
+        self.step_state.zero_()
+        self.t = 0
+
+    def decode(self, stream=None):
+        c = self.cfg
+        qg.qg_decode_residuals(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
+                               self.lp, self.a, c.gamma0, c.gamma1, c.tau, self.attrs, self.gate, self.lreg_part,
+                               stream)
+
+    def _eval_psnr(self, rast, cam, gt, loss_part, loss_out, stream=None):
+        """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync)."""
+        self.decode(stream)
+        rast.set_cameras([cam])
+        rast.project(self.attrs, stream)
+        rast.bin(stream)
+        if rast.ensure_capacity():
+            rast.bin(stream)
+        rast.render(stream)
+        cnt = rast.images[0].numel()
+        qg.qg_l1_loss(cnt, rast.images[0], gt, 1.0, None, loss_part, stream)
+        qg.qg_loss_reduce(cnt, loss_part, loss_out, stream)
+        mse = float(loss_out[1].item())
+        return float("inf") if mse <= 0 else -10.0 * math.log10(mse)
+
+
+class FrameFitter(ResidualState):
+    """Single-view steps (the plain form): each optimiser iteration renders one training view."""
+
+    def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
+                 capacity=None, seed=0):
+        super().__init__(prev_attrs, cfg, W1, W2, seed)
+        self.cams = list(cams)
+        # one set of image buffers serves every view
+        assert all((c.width, c.height) == (self.cams[0].width, self.cams[0].height) for c in self.cams)
+        self.gts = gts
+        dev = self.device
+        n, L, H = self.n, cfg.latent_dim, cfg.hidden
         self.grad_attrs = torch.zeros_like(self.prev)
         self.dws_bytes = qg.qg_decode_bwd_workspace_size(n, L, H, 56)
         self.dws = torch.empty(self.dws_bytes, dtype=torch.uint8, device=dev)
         self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(n, 1)
         self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
         self.fused = True
-        keys = list(self.params)
-        self.adam_segs = qg.adam_segments([self.params[k] for k in keys], [self.grads[k] for k in keys],
-                                          [self.m[k] for k in keys], [self.v[k] for k in keys],
-                                          [self.lrs[k] for k in keys])
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
                                bg=cfg.bg, device=dev, capacity=capacity)
         self.qcams = [qg.camera_array([c]) for c in self.cams]
@@ -100,31 +154,7 @@ class FrameFitter:
         self.loss_part = torch.empty(2 * qg.qg_loss_blocks(self.count), dtype=torch.float64, device=dev)
         self.loss_out = torch.zeros(2, dtype=torch.float64, device=dev)
 
-    def reset_frame(self, prev_attrs=None, gts=None, a_init=None):
-        """New frame: latents and position residuals restart at zero, decoder is warm-started, Adam resets."""
-        if prev_attrs is not None:
-            self.prev.copy_(prev_attrs)
-        if gts is not None:
-            self.gts = gts
-        self.lat.zero_()
-        self.lp.zero_()
-        if a_init is None:
-            self.a.zero_()
-        else:
-            self.a.copy_(a_init)
-        for k in self.params:
-            self.m[k].zero_()
-            self.v[k].zero_()
-            self.grads[k].zero_()
-        self.t = 0
-
     # -- the step ------------------------------------------------------------------------------
-    def decode(self, stream=None):
-        c = self.cfg
-        qg.qg_decode_residuals(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
-                               self.lp, self.a, c.gamma0, c.gamma1, c.tau, self.attrs, self.gate, self.lreg_part,
-                               stream)
-
     def forward_view(self, v, stream=None):
         self.rast.qcams = self.qcams[v]
         self.rast.project(self.attrs, stream)
@@ -172,17 +202,7 @@ class FrameFitter:
 
     def psnr(self, cam, gt, stream=None):
         """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync)."""
-        self.decode(stream)
-        self.rast.qcams = qg.camera_array([cam])
-        self.rast.project(self.attrs, stream)
-        self.rast.bin(stream)
-        if self.rast.ensure_capacity():
-            self.rast.bin(stream)
-        self.rast.render(stream)
-        qg.qg_l1_loss(self.count, self.rast.images[0], gt, 1.0, None, self.loss_part, stream)
-        qg.qg_loss_reduce(self.count, self.loss_part, self.loss_out, stream)
-        mse = float(self.loss_out[1].item())
-        return float("inf") if mse <= 0 else -10.0 * math.log10(mse)
+        return self._eval_psnr(self.rast, cam, gt, self.loss_part, self.loss_out, stream)
 
     def size_capacity(self, margin=1.3):
         """Bin every view once (host syncs) and size the pair capacity for all of them."""
@@ -198,13 +218,148 @@ class FrameFitter:
         return worst
 
 
+def view_groups(V: int, max_views: int = qg.MAX_VIEWS):
+    """Consecutive groups of near-equal size, at most max_views each."""
+    g = -(-V // max_views)
+    base, extra = divmod(V, g)
+    out, s = [], 0
+    for i in range(g):
+        k = base + (1 if i < extra else 0)
+        out.append(list(range(s, s + k)))
+        s += k
+    return out
+
+
+class BatchedFitter(ResidualState):
+    """Multi-view steps: one optimiser iteration covers a group of training views (all views of the timestep
+    when there are at most 16; otherwise near-equal consecutive groups taken in turn).  Per step, one
+    decode+projection pass writes every view of the group, one binning sorts all of their (tile, depth) keys
+    in a shared tile index space (per-view tile offsets), one blend launch and one adjoint launch cover all of
+    their tiles, and the loss is the mean over the group's views of the per-view mean L1 (weight 1/V each).
+    The step has no host synchronisation and no host-dependent arguments (the Adam step count lives on the
+    device), so each group's step is captured once into a graph and replayed.  Blend scheduling (tile shape,
+    LDS batch depth, persistent heaviest-first order) is chosen per fitter; results do not depend on it."""
+
+    def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
+                 capacity=None, seed=0, batch=0, persistent=True, graph=True, eval_cam=None):
+        super().__init__(prev_attrs, cfg, W1, W2, seed)
+        self.cams = list(cams)
+        self.gts = gts
+        self.groups = view_groups(len(self.cams))
+        self.batch, self.persistent, self.use_graph = int(batch), bool(persistent), bool(graph)
+        dev = self.device
+        n = self.n
+        self.rasts = []
+        self.gimgs, self.loss_parts, self.counts = [], [], []
+        for g in self.groups:
+            r = Rasterizer(n, [self.cams[v] for v in g], tile=cfg.tile, sh_degree=cfg.sh_degree,
+                           dilation=cfg.dilation, bg=cfg.bg, device=dev, capacity=capacity, batch=batch,
+                           persistent=persistent)
+            self.rasts.append(r)
+            self.gimgs.append([torch.empty_like(im) for im in r.images])
+            self.counts.append([im.numel() for im in r.images])
+            self.loss_parts.append([torch.empty(2 * qg.qg_loss_blocks(im.numel()), dtype=torch.float64, device=dev)
+                                    for im in r.images])
+        self.t_gimg = [qg._ptr_array(gl) for gl in self.gimgs]
+        vmax = max(len(g) for g in self.groups)
+        self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(n, vmax)
+        self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
+        self.graphs = [None] * len(self.groups)
+        self.next_group = 0
+        ec = eval_cam if eval_cam is not None else self.cams[0]
+        self.eval_rast = Rasterizer(n, [ec], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
+                                    bg=cfg.bg, device=dev)
+        self.eval_part = torch.empty(2 * qg.qg_loss_blocks(self.eval_rast.images[0].numel()), dtype=torch.float64,
+                                     device=dev)
+        self.eval_out = torch.zeros(2, dtype=torch.float64, device=dev)
+
+    def _enqueue(self, gi, stream=None):
+        c = self.cfg
+        r = self.rasts[gi]
+        views = self.groups[gi]
+        qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
+                             self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
+                             r.t_proj, None, self.gate, None, stream)
+        r.bin(stream)
+        r.render(stream)
+        w = 1.0 / len(views)
+        for k, v in enumerate(views):
+            qg.qg_l1_loss(self.counts[gi][k], r.images[k], self.gts[v], w, self.gimgs[gi][k], self.loss_parts[gi][k],
+                          stream)
+        qg.qg_render_decode_bwd(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
+                                self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
+                                r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
+                                self.t_gimg[gi], self.grads["lat"], self.grads["W1"], self.grads["W2"],
+                                self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream)
+        b1, b2 = c.betas
+        qg.qg_adam_multi(self.adam_segs, b1, b2, c.eps, 0, True, stream, step_state=self.step_state)
+
+    def _capture(self, gi):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._enqueue(gi)
+        self.graphs[gi] = g
+
+    def step(self, stream=None):
+        """One optimiser iteration on the next view group (the first call of each group runs eagerly and then
+        captures its graph; later calls replay it)."""
+        gi = self.next_group
+        self.next_group = (gi + 1) % len(self.groups)
+        if self.use_graph and self.graphs[gi] is not None:
+            self.graphs[gi].replay()
+        else:
+            self._enqueue(gi, stream)
+            if self.use_graph:
+                torch.cuda.synchronize()
+                self._capture(gi)
+        self.t += 1
+
+    def invalidate(self):
+        """Drop the captured graphs (after buffers were re-allocated)."""
+        self.graphs = [None] * len(self.groups)
+
+    def overflowed(self):
+        """True if the last binning of some group exceeded its pair capacity (host sync)."""
+        return any(int(r.num_pairs.item()) > r.capacity for r in self.rasts)
+
+    def size_capacity(self, margin=1.3):
+        """Bin every group once (host syncs) and size each group's pair capacity; drops captured graphs."""
+        self.decode()
+        worst = []
+        for r in self.rasts:
+            r.project(self.attrs)
+            r.bin()
+            p = int(r.num_pairs.item())
+            worst.append(p)
+            if p * 1.05 > r.capacity:
+                r._alloc_capacity(int(p * margin))
+        self.invalidate()
+        return worst
+
+    def losses(self, gi=None):
+        """Per-view mean L1 of the last step of group gi (host sync)."""
+        gi = (self.next_group - 1) % len(self.groups) if gi is None else gi
+        out = []
+        for k, cnt in enumerate(self.counts[gi]):
+            qg.qg_loss_reduce(cnt, self.loss_parts[gi][k], self.eval_out)
+            out.append(float(self.eval_out[0].item()))
+        return out
+
+    def psnr(self, cam, gt, stream=None):
+        return self._eval_psnr(self.eval_rast, cam, gt, self.eval_part, self.eval_out, stream)
+
+
 def render_views(attrs: torch.Tensor, cams, cfg: FitConfig = FitConfig(), capacity=None):
     """Forward renders of ``attrs`` at each camera (used to make ground-truth frames of synthetic scenes)."""
     out = []
-    rast = Rasterizer(attrs.shape[1], [cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
-                      bg=cfg.bg, device=attrs.device, capacity=capacity)
+    rasts = {}  # one rasterizer per resolution: its image buffers are sized for it
     for c in cams:
-        rast.qcams = qg.camera_array([c])
+        key = (c.width, c.height)
+        if key not in rasts:
+            rasts[key] = Rasterizer(attrs.shape[1], [c], tile=cfg.tile, sh_degree=cfg.sh_degree,
+                                    dilation=cfg.dilation, bg=cfg.bg, device=attrs.device, capacity=capacity)
+        rast = rasts[key]
+        rast.set_cameras([c])
         rast.forward(attrs)
         out.append(rast.images[0].clone())
     return out
@@ -230,6 +385,39 @@ def viewspace_gradient_difference(prev_attrs: torch.Tensor, cams, gt_prev, gt_cu
         qg.qg_scaled_diff(cnt, gt_prev[v], gt_cur[v], 2.0 / cnt, gimg)
         rast.backward(prev_attrs, [gimg], scratch, grad_xy=[d])
     return d
+
+
+class GateInitializer:
+    """Eq. 9-10 once per frame with buffers kept across frames: per view, render A_{t-1} and run one adjoint
+    pass with image gradient 2 (I_{t-1} - I_t) / (3HW) to accumulate d, then the gate logits from d."""
+
+    def __init__(self, n, cams, cfg: FitConfig = FitConfig(), device="cuda", capacity=None):
+        self.cfg = cfg
+        self.cams = list(cams)
+        assert all((c.width, c.height) == (self.cams[0].width, self.cams[0].height) for c in self.cams)
+        self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
+                               bg=cfg.bg, device=device, capacity=capacity)
+        self.d = torch.zeros(2, n, device=device)
+        self.scratch = torch.zeros(59, n, device=device)
+        self.gimg = torch.empty_like(self.rast.images[0])
+        self.a = torch.empty(n, device=device)
+        self.p = torch.empty(n, device=device)
+        self.med = torch.empty(1, device=device)
+        self.ws_bytes = qg.qg_gate_init_workspace_size(n)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def __call__(self, prev_attrs, gt_prev, gt_cur):
+        c = self.cfg
+        n = prev_attrs.shape[1]
+        qg.qg_zero(self.d, self.d.numel() * 4)
+        cnt = self.gimg.numel()
+        for v, cam in enumerate(self.cams):
+            self.rast.set_cameras([cam])
+            self.rast.forward(prev_attrs)
+            qg.qg_scaled_diff(cnt, gt_prev[v], gt_cur[v], 2.0 / cnt, self.gimg)
+            self.rast.backward(prev_attrs, [self.gimg], self.scratch, grad_xy=[self.d])
+        qg.qg_gate_init(n, self.d, c.gamma0, c.gamma1, c.tau, self.a, self.p, self.med, self.ws, self.ws_bytes)
+        return self.a
 
 
 def gate_init(d: torch.Tensor, cfg: FitConfig = FitConfig()):

@@ -37,7 +37,8 @@ class qg_camera(ctypes.Structure):
 
 
 class qg_tiling(ctypes.Structure):
-    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("schedule", ctypes.c_void_p)]
 
 
 class qg_adam_segment(ctypes.Structure):
@@ -84,7 +85,7 @@ def lib():
             "qg_loss_reduce": ([i64, P, P, P], i32),
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
             "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
-            "qg_adam_multi": ([i32, ctypes.POINTER(qg_adam_segment), f32, f32, f32, i32, i32, P], i32),
+            "qg_adam_multi": ([i32, ctypes.POINTER(qg_adam_segment), f32, f32, f32, i32, P, i32, P], i32),
             "qg_decode_project_lreg_blocks": ([i64], i64),
             "qg_scaled_diff": ([i64, P, P, f32, P, P], i32),
             "qg_gate_init_workspace_size": ([i64], sz),
@@ -95,6 +96,8 @@ def lib():
             "qg_render_decode_bwd": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, f32, i32, CAM, i32,
                                       qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P], i32),
             "qg_timing_report": ([ctypes.c_char_p, i64], i64),
+            "qg_schedule_words": ([i64], i64),
+            "qg_schedule_tiles": ([i64, P, P, i64, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -153,8 +156,9 @@ def camera_array(cams):
     return arr
 
 
-def tiling(tw=16, th=16) -> qg_tiling:
-    return qg_tiling(int(tw), int(th))
+def tiling(tw=16, th=16, batch=0, schedule=None) -> qg_tiling:
+    """Tile shape, blend batch depth (0 = 64) and optional heaviest-first schedule buffer (device tensor)."""
+    return qg_tiling(int(tw), int(th), int(batch), 0, _ptr(schedule))
 
 
 def projected_array(bufs):
@@ -184,6 +188,15 @@ def qg_version():
 
 def qg_zero(dst, nbytes, stream=None):
     _check(lib().qg_zero(_ptr(dst), int(nbytes), _stream(stream)))
+
+
+def qg_schedule_words(total_tiles):
+    return int(lib().qg_schedule_words(int(total_tiles)))
+
+
+def qg_schedule_tiles(total_tiles, tile_ranges, schedule, stream=None):
+    _check(lib().qg_schedule_tiles(int(total_tiles), _ptr(tile_ranges), _ptr(schedule), int(schedule.numel()),
+                                   _stream(stream)))
 
 
 def qg_total_tiles(cams, tile):
@@ -349,6 +362,6 @@ def adam_segments(params, grads, ms, vs, lrs):
     return arr
 
 
-def qg_adam_multi(segs, b1, b2, eps, t, zero_grad=True, stream=None):
-    _check(lib().qg_adam_multi(len(segs), segs, float(b1), float(b2), float(eps), int(t), int(bool(zero_grad)),
-                               _stream(stream)))
+def qg_adam_multi(segs, b1, b2, eps, t, zero_grad=True, stream=None, step_state=None):
+    _check(lib().qg_adam_multi(len(segs), segs, float(b1), float(b2), float(eps), int(t), _ptr(step_state),
+                               int(bool(zero_grad)), _stream(stream)))

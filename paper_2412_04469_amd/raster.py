@@ -20,12 +20,14 @@ def _u32(shape, device):
 
 class Rasterizer:
     def __init__(self, n, cams, tile=(16, 16), sh_degree=3, dilation=0.3, bg=(0.0, 0.0, 0.0), device="cuda",
-                 capacity=None, want_keys=False):
+                 capacity=None, want_keys=False, batch=0, persistent=False):
         self.n = int(n)
         self.cams = list(cams)
         self.V = len(self.cams)
-        self.tile = qg.tiling(*tile)
         self.tile_wh = tuple(tile)
+        self.batch = int(batch)
+        self.persistent = bool(persistent)
+        self.tile = qg.tiling(*tile)
         self.sh_degree = int(sh_degree)
         self.dilation = float(dilation)
         self.bg = tuple(float(b) for b in bg)
@@ -44,6 +46,10 @@ class Rasterizer:
         self.last = [_u32((c.height, c.width), d) for c in self.cams]
         self.total_tiles = qg.qg_total_tiles(self.cams, self.tile)
         self.ranges = _u32((self.total_tiles, 2), d)
+        self.schedule = None
+        if self.persistent:
+            self.schedule = torch.zeros(qg.qg_schedule_words(self.total_tiles), dtype=torch.int32, device=d)
+        self.tile = qg.tiling(*tile, batch=self.batch, schedule=self.schedule)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=d)
         if capacity is None:
             capacity = max(1024, 16 * self.n * self.V)
@@ -83,6 +89,8 @@ class Rasterizer:
     def bin(self, stream=None):
         qg.qg_bin(self.n, self.t_proj, self.qcams, self.tile, self.capacity, self.vals, self.keys, self.ranges,
                   self.num_pairs, self.bin_ws, self.bin_ws_bytes, stream)
+        if self.schedule is not None:
+            qg.qg_schedule_tiles(self.total_tiles, self.ranges, self.schedule, stream)
 
     def render(self, stream=None):
         qg.qg_render_fwd(self.t_proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.t_img, self.t_tf,

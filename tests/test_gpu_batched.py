@@ -1,0 +1,209 @@
+"""Multi-view batching, blend scheduling and graph replay (GPU, through the C ABI).
+
+* Blend scheduling (LDS batch depth 32/64/128, persistent heaviest-first order) changes no result: images,
+  T_final and last are bit-identical, the adjoint equal up to the order of its float atomics.
+* A batched multi-view launch equals the per-view launches: images and T_final bit-identical, each tile's
+  entry list identical, each pixel's last contributor at the same position in its tile's list; the
+  attribute gradient equals the sum of the per-view gradients up to float atomic order.
+* A captured fit step replays to the same result as the same step run eagerly from the same state.
+"""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import rel_l2, small_scene, to_dev
+from paper_2412_04469_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qgm():
+    from paper_2412_04469_amd import qg, raster
+    qg.lib()
+    return qg, raster
+
+
+def uneven_cams():
+    """Three views of uneven resolution around the scene."""
+    return [synth.make_camera((0.0, 0.0, -4.0), 160, 120, f=160),
+            synth.make_camera((2.0, -0.5, -3.4), 96, 200, f=110),
+            synth.make_camera((-2.5, 0.4, -3.0), 70, 45, f=64)]
+
+
+def _render(raster, sc, cams, tile=(16, 16), batch=0, persistent=False):
+    rast = raster.Rasterizer(sc.n, cams, tile=tile, batch=batch, persistent=persistent, bg=(0.1, 0.2, 0.3))
+    attrs = to_dev(sc.planes())
+    rast.forward(attrs)
+    torch.cuda.synchronize()
+    return rast, attrs
+
+
+def _grad(rast, attrs, gis):
+    g = torch.zeros_like(attrs)
+    rast.backward(attrs, gis, g)
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
+
+
+def _grad_images(cams, seed):
+    rng = np.random.default_rng(seed)
+    return [to_dev(rng.normal(size=(3, c.height, c.width)) / (3 * c.width * c.height)) for c in cams]
+
+
+def test_schedule_is_heaviest_first_permutation(qgm):
+    qg, raster = qgm
+    sc = small_scene(seed=30, n=5000)
+    cams = uneven_cams()
+    rast, _ = _render(raster, sc, cams, persistent=True)
+    s = rast.schedule.cpu().numpy().view(np.uint32)
+    hdr = 2 + 512
+    assert s[0] == 0 and s[1] == 0  # the blend left the work counters at zero
+    order = s[hdr:hdr + rast.total_tiles].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(rast.total_tiles))
+    rg = rast.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    ln = (rg[:, 1] - rg[:, 0])[order]
+    assert ln[0] == ln.max() or ln[0] * 9 > ln.max() * 8  # within one bucket (1/8 octave) of the heaviest
+    # non-increasing up to the bucket width; empty tiles last
+    assert np.all(ln[1:] * 8 <= ln[:-1] * 9 + 8)
+    if (ln == 0).any():
+        first_empty = int(np.argmax(ln == 0))
+        assert np.all(ln[first_empty:] == 0)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_blend_scheduling_does_not_change_results(qgm, tile):
+    qg, raster = qgm
+    sc = small_scene(seed=31, n=4000)
+    cams = uneven_cams()
+    ref, attrs = _render(raster, sc, cams, tile)
+    gis = _grad_images(cams, 7)
+    g_ref = _grad(ref, attrs, gis)
+    for batch, persistent in [(32, False), (128, False), (64, True), (128, True), (32, True)]:
+        r, _ = _render(raster, sc, cams, tile, batch, persistent)
+        for rep in range(2):  # the persistent counters must be back at zero for the second launch
+            if rep:
+                r.render()
+                torch.cuda.synchronize()
+            for v in range(len(cams)):
+                assert torch.equal(r.images[v], ref.images[v]), (batch, persistent, v)
+                assert torch.equal(r.tfinal[v], ref.tfinal[v])
+                assert torch.equal(r.last[v], ref.last[v])
+        g = _grad(r, attrs, gis)
+        assert rel_l2(g, g_ref) <= 1e-5, (batch, persistent, rel_l2(g, g_ref))
+
+
+def _tile_of_pixels(cam, tw, th, off):
+    gw = -(-cam.width // tw)
+    ty = np.arange(cam.height) // th
+    tx = np.arange(cam.width) // tw
+    return off + ty[:, None] * gw + tx[None, :]
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_views_equal_single_views(qgm, persistent):
+    qg, raster = qgm
+    sc = small_scene(seed=32, n=6000)
+    cams = uneven_cams()
+    tw, th = 16, 16
+    bat, attrs = _render(raster, sc, cams, (tw, th), 64, persistent)
+    gis = _grad_images(cams, 8)
+    g_bat = _grad(bat, attrs, gis)
+    g_sum = np.zeros_like(g_bat)
+    brg = bat.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    bvals = bat.vals.cpu().numpy().view(np.uint32)
+    off = 0
+    for v, cam in enumerate(cams):
+        one, _ = _render(raster, sc, [cam], (tw, th))
+        assert torch.equal(bat.images[v], one.images[0])
+        assert torch.equal(bat.tfinal[v], one.tfinal[0])
+        org = one.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+        ovals = one.vals.cpu().numpy().view(np.uint32)
+        nt = org.shape[0]
+        for t in range(nt):  # each tile's entry list is the same Gaussians in the same order
+            a = bvals[brg[off + t, 0]:brg[off + t, 1]]
+            b = ovals[org[t, 0]:org[t, 1]]
+            assert np.array_equal(a, b), (v, t)
+        tb = _tile_of_pixels(cam, tw, th, off)
+        to = _tile_of_pixels(cam, tw, th, 0)
+        pos_b = bat.last[v].cpu().numpy().view(np.uint32).astype(np.int64) - brg[tb, 0]
+        pos_o = one.last[0].cpu().numpy().view(np.uint32).astype(np.int64) - org[to, 0]
+        assert np.array_equal(pos_b, pos_o)
+        g_sum += _grad(one, attrs, [gis[v]])
+        off += nt
+    assert off == bat.total_tiles
+    assert rel_l2(g_bat, g_sum) <= 1e-5
+
+
+def _fit_inputs(n=3000, seed=33):
+    from paper_2412_04469_amd.fit import FitConfig, render_views
+    base = small_scene(seed=seed, n=n)
+    rng = synth.rng_for(seed + 1)
+    moved = base.copy()
+    moved.means[: n // 10] += rng.normal(0, 0.05, size=(n // 10, 3)).astype(np.float32)
+    cams = uneven_cams()
+    prev = to_dev(base.planes())
+    gts = render_views(to_dev(moved.planes()), cams, FitConfig())
+    return prev, cams, gts
+
+
+def _state(f):
+    keys = ["lat", "lp", "a", "W1", "W2"]
+    return ([f.params[k].clone() for k in keys], [f.m[k].clone() for k in keys], [f.v[k].clone() for k in keys],
+            f.step_state.clone())
+
+
+def _restore(f, st):
+    keys = ["lat", "lp", "a", "W1", "W2"]
+    p, m, v, s = st
+    for k, a, b, c in zip(keys, p, m, v):
+        f.params[k].copy_(a)
+        f.m[k].copy_(b)
+        f.v[k].copy_(c)
+        f.grads[k].zero_()
+    f.step_state.copy_(s)
+
+
+def test_graph_replay_matches_eager_step(qgm):
+    qg, raster = qgm
+    from paper_2412_04469_amd.fit import BatchedFitter
+    prev, cams, gts = _fit_inputs()
+    f = BatchedFitter(prev, cams, gts, persistent=True, graph=True)
+    f.size_capacity()
+    f.step()  # eager first step, then capture
+    torch.cuda.synchronize()
+    assert f.graphs[0] is not None
+    keys = ["lat", "lp", "a", "W1", "W2"]
+    for rnd in range(3):
+        s0 = _state(f)
+        f._enqueue(0)  # the same step, eagerly
+        torch.cuda.synchronize()
+        eager_imgs = [im.clone() for im in f.rasts[0].images]
+        eager = _state(f)
+        _restore(f, s0)
+        f.step()  # graph replay
+        torch.cuda.synchronize()
+        assert not f.overflowed()
+        for a, b in zip(f.rasts[0].images, eager_imgs):
+            assert torch.equal(a, b), rnd
+        rep = _state(f)
+        assert torch.equal(rep[3], eager[3])  # device step counter advanced once
+        for k, p0, pe, pr in zip(keys, s0[0], eager[0], rep[0]):
+            de, dr = (pe - p0).cpu().numpy(), (pr - p0).cpu().numpy()
+            assert rel_l2(dr, de) <= 1e-3, (rnd, k, rel_l2(dr, de))
+    assert int(f.step_state[0].item()) == 1 + 3
+
+
+def test_batched_fit_reduces_loss(qgm):
+    qg, raster = qgm
+    from paper_2412_04469_amd.fit import BatchedFitter
+    prev, cams, gts = _fit_inputs(seed=35)
+    f = BatchedFitter(prev, cams, gts, persistent=True, graph=True)
+    f.size_capacity()
+    f.step()
+    first = np.mean(f.losses())
+    for _ in range(30):
+        f.step()
+    assert not f.overflowed()
+    last = np.mean(f.losses())
+    assert last < first, (first, last)

@@ -367,6 +367,24 @@ def test_adam_multi_parity(qgm):
             assert not gd.any().item()
     for dp, (pp, _, _) in zip(dev_p, ref):
         np.testing.assert_allclose(dp.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
+    # the device step counter gives the same updates as the host step count
+    dev_p2 = [to_dev(p) for p in ps]
+    dev_g2 = [torch.zeros(n, device="cuda") for n in sizes]
+    dev_m2 = [torch.zeros(n, device="cuda") for n in sizes]
+    dev_v2 = [torch.zeros(n, device="cuda") for n in sizes]
+    segs2 = qg.adam_segments(dev_p2, dev_g2, dev_m2, dev_v2, lrs)
+    state = torch.zeros(4, dtype=torch.int32, device="cuda")
+    rng2 = synth.rng_for(43)
+    [rng2.normal(size=n) for n in sizes]
+    for step in range(1, 4):
+        grads = [rng2.normal(size=n).astype(np.float32) for n in sizes]
+        for g, gd in zip(grads, dev_g2):
+            gd.copy_(to_dev(g))
+        qg.qg_adam_multi(segs2, 0.9, 0.999, 1e-8, 0, zero_grad=True, step_state=state)
+    torch.cuda.synchronize()
+    assert int(state[0].item()) == 3
+    for a, b in zip(dev_p2, dev_p):
+        assert torch.equal(a, b)
     # zero_grad off leaves the gradients in place
     for gd in dev_g:
         gd.fill_(1.0)
