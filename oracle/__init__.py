@@ -17,6 +17,8 @@ Modules
     adam      Adam update
     brute     an independent NumPy compositor for tiny scenes (pins ``composite``)
     render    the whole forward/backward chain glued together
+    proposal  features and the BF16-operand residual-proposal MLP with its backward (not a method of the
+              paper: the learned initialisation that replaces zero-initialised residuals)
 
 Parity status of each function is stated in its module docstring.
 """
