@@ -294,6 +294,44 @@ qg_status qg_gate_init(int64_t n, const float* d, float gamma0, float gamma1, fl
                        float* median_out, void* ws, size_t ws_bytes, qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
+/* Learned residual proposal (not a method of the paper: a learned replacement for zero-initialised  */
+/* residual parameters of frame t, Sec. 3.2 / Eq. 5-8; its analogue in the paper is Eq. 10).         */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * Features [24][ld_out] of n Gaussians from the reconstructions A1 = A_{t-1}, A2 = A_{t-2}, A3 = A_{t-3}
+ * ([59][ld] planes, only planes 0..9 are read: mean, quaternion, log-scale) and p [n] (the Eq. 10 gate
+ * probability of frame t):  [ mean of A1 (3) | A1 - A2 on planes 0..9 (10) | A2 - A3 on planes 0..9 (10) | p ].
+ */
+qg_status qg_proposal_features(int64_t n, int64_t ld, const float* A1, const float* A2, const float* A3,
+                               const float* p, float* out, int64_t ld_out, qg_stream stream);
+
+/*
+ * The network: y = (W3 h2 + b3) * out_std + out_mean, h2 = SiLU(W2 h1 + b2), h1 = SiLU(W1 x_s + b1),
+ * x_s = (x - in_mean) * in_rstd.  Outputs (12) = [ l_p (3) | gate logit a (1) | latents l_hat (8) ].
+ * Products on BF16 matrix cores with FP32 accumulation: the weights, x_s, h1, h2 (and in the backward the
+ * output gradient and both dL/d pre-activation tiles) are rounded to bfloat16, round to nearest even,
+ * from their float32 values; biases and pre-activations stay float32.
+ * params [device] QG_PROPOSAL_PARAMS float32: W1 [64][24] | b1 [64] | W2 [64][64] | b2 [64] | W3 [12][64] | b3 [12].
+ * stats  [device] 72 float32: in_mean [24] | in_rstd [24] | out_mean [12] | out_std [12].
+ */
+#define QG_PROPOSAL_PARAMS 6540
+qg_status qg_proposal_fwd(int64_t n, int64_t ld_in, const float* features, const float* params,
+                          const float* stats, float* out, int64_t ld_out, qg_stream stream);
+
+/*
+ * Gradient of the training loss L = (1/m) sum over m samples and 12 outputs of (y_s - t_s)^2, with
+ * standardised outputs y_s and targets t_s = (t - out_mean) / out_std, for samples idx[0..m) (device
+ * uint32 columns of features [24][ld] and targets [12][ld], or columns 0..m-1 when idx is NULL; an index
+ * >= n is skipped).
+ * grad (+=) [QG_PROPOSAL_PARAMS] in the params layout; loss_out [device, optional] receives L.
+ * Per-wave partials are summed in a fixed order (deterministic).  ws: qg_proposal_bwd_workspace_size() bytes.
+ */
+size_t qg_proposal_bwd_workspace_size(void);
+qg_status qg_proposal_bwd(int64_t m, const uint32_t* idx, int64_t n, int64_t ld, const float* features,
+                          const float* targets, const float* params, const float* stats, float* grad,
+                          float* loss_out, void* ws, size_t ws_bytes, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
 /* Loss (L1 term of Eq. 3), PSNR, Adam.                                                            */
 /* ---------------------------------------------------------------------------------------------- */
 /*

@@ -97,6 +97,10 @@ def lib():
                                       qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P], i32),
             "qg_timing_report": ([ctypes.c_char_p, i64], i64),
             "qg_schedule_words": ([i64], i64),
+            "qg_proposal_features": ([i64, i64, P, P, P, P, P, i64, P], i32),
+            "qg_proposal_fwd": ([i64, i64, P, P, P, P, i64, P], i32),
+            "qg_proposal_bwd_workspace_size": ([], sz),
+            "qg_proposal_bwd": ([i64, P, i64, i64, P, P, P, P, P, P, P, sz, P], i32),
             "qg_schedule_tiles": ([i64, P, P, i64, P], i32),
         }
         for name, (args, res) in sig.items():
@@ -188,6 +192,28 @@ def qg_version():
 
 def qg_zero(dst, nbytes, stream=None):
     _check(lib().qg_zero(_ptr(dst), int(nbytes), _stream(stream)))
+
+
+PROPOSAL_PARAMS = 6540
+
+
+def qg_proposal_features(n, ld, A1, A2, A3, p, out, ld_out, stream=None):
+    _check(lib().qg_proposal_features(int(n), int(ld), _ptr(A1), _ptr(A2), _ptr(A3), _ptr(p), _ptr(out), int(ld_out),
+                                      _stream(stream)))
+
+
+def qg_proposal_fwd(n, ld_in, features, params, stats, out, ld_out, stream=None):
+    _check(lib().qg_proposal_fwd(int(n), int(ld_in), _ptr(features), _ptr(params), _ptr(stats), _ptr(out),
+                                 int(ld_out), _stream(stream)))
+
+
+def qg_proposal_bwd_workspace_size():
+    return int(lib().qg_proposal_bwd_workspace_size())
+
+
+def qg_proposal_bwd(m, idx, n, ld, features, targets, params, stats, grad, loss_out, ws, ws_bytes, stream=None):
+    _check(lib().qg_proposal_bwd(int(m), _ptr(idx), int(n), int(ld), _ptr(features), _ptr(targets), _ptr(params),
+                                 _ptr(stats), _ptr(grad), _ptr(loss_out), _ptr(ws), int(ws_bytes), _stream(stream)))
 
 
 def qg_schedule_words(total_tiles):
