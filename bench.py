@@ -88,6 +88,9 @@ def parse():
     p.add_argument("--tune", default="full", choices=["full", "quick", "none"],
                    help="blend autotuning of the batched step: all 18 candidates, 6, or the default only")
     p.add_argument("--frame-iters", type=int, default=500)
+    p.add_argument("--proposal", default="single", choices=["none", "single", "both"],
+                   help="learned-proposal experiment: skip, judge with one view per step, or also batched")
+    p.add_argument("--proposal-frames", type=int, default=50)
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run a plain copy of this many MiB first (counter calibration)")
     return p.parse_args()
@@ -299,6 +302,41 @@ def frame_section(args):
                         "steps; held-out PSNR every 25 steps with the clock paused"}
 
 
+
+def proposal_section(args):
+    """The learned residual proposal on the 50-frame dynamic workload (300 k Gaussians, 10% moving, 20 views):
+    the plain streaming fit of frames 1..F records the targets and training data; the network is trained on the
+    first half of the frames and judged on the second half against the plain form's seconds per frame to
+    the same held-out PSNR."""
+    import torch
+    from paper_2412_04469_amd import stream, synth
+    from paper_2412_04469_amd.fit import FitConfig
+    F = args.proposal_frames
+    wl = synth.workload_dynamic(n=args.n)
+    seq = stream.Sequence(wl, FitConfig(), torch.device("cuda"))
+    t0 = time.perf_counter()
+    recs, hist = stream.run_plain(seq, F, args.frame_iters, 25, log=log)
+    plain_s = time.perf_counter() - t0
+    train_frames = list(range(1, F // 2 + 1))
+    judge_frames = list(range(F // 2 + 1, F + 1))
+    prop, losses, train_s = stream.train_proposal(hist, train_frames, log=log)
+    judged = stream.judge(seq, hist, recs, prop, judge_frames, args.frame_iters, 25, batched=False, log=log)
+    out = {"workload": wl.name, "frames": F, "train_frames": [1, F // 2], "judge_frames": [F // 2 + 1, F],
+           "plain_run_wall_s": round(plain_s, 1),
+           "train": {"steps": 800, "batch": 65536, "seconds": round(train_s, 3), "loss_first": losses[0][1],
+                     "loss_last": losses[-1][1]},
+           "proposal": stream.summarize(recs, judged, judge_frames),
+           "per_frame": [{"t": j["t"], "target": j["target"], "plain_s": p["sec"], "proposal_s": j["sec"],
+                          "used": j["used_proposal"]} for p, j in zip([r for r in recs if r["t"] in judge_frames],
+                                                                        judged)]}
+    if args.proposal == "both":
+        jb = stream.judge(seq, hist, recs, prop, judge_frames, args.frame_iters, 25, batched=True, log=log)
+        out["proposal_batched"] = stream.summarize(recs, jb, judge_frames)
+    del hist
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -394,6 +432,8 @@ def main():
         result["batched"] = batched_section(args)
     if not args.no_frame:
         result["sec_per_frame"] = frame_section(args)
+    if args.proposal != "none":
+        result["learned_proposal"] = proposal_section(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl.scene.planes(), wl.cams[0], args.cpu_pixels)
     print(json.dumps(result), flush=True)

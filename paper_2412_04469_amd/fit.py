@@ -244,7 +244,8 @@ class BatchedFitter(ResidualState):
                  capacity=None, seed=0, batch=0, persistent=True, graph=True, eval_cam=None):
         super().__init__(prev_attrs, cfg, W1, W2, seed)
         self.cams = list(cams)
-        self.gts = gts
+        # the captured steps read the ground truth from these buffers: new frames are copied into them
+        self.gts = [g.clone() for g in gts]
         self.groups = view_groups(len(self.cams))
         self.batch, self.persistent, self.use_graph = int(batch), bool(persistent), bool(graph)
         dev = self.device
@@ -272,6 +273,12 @@ class BatchedFitter(ResidualState):
         self.eval_part = torch.empty(2 * qg.qg_loss_blocks(self.eval_rast.images[0].numel()), dtype=torch.float64,
                                      device=dev)
         self.eval_out = torch.zeros(2, dtype=torch.float64, device=dev)
+
+    def reset_frame(self, prev_attrs=None, gts=None, a_init=None, lat_init=None, lp_init=None):
+        if gts is not None:
+            for dst, src in zip(self.gts, gts):
+                dst.copy_(src)
+        super().reset_frame(prev_attrs, None, a_init, lat_init, lp_init)
 
     def _enqueue(self, gi, stream=None):
         c = self.cfg

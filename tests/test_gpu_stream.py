@@ -1,0 +1,27 @@
+"""Streaming fit and learned-proposal pipeline on a small dynamic scene (GPU)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def test_stream_and_proposal_pipeline_small():
+    from paper_2412_04469_amd import stream, synth
+    from paper_2412_04469_amd.fit import FitConfig
+    wl = synth.workload_dynamic(n=4000, n_views=4, width=96, height=72)
+    seq = stream.Sequence(wl, FitConfig(), torch.device("cuda"))
+    recs, hist = stream.run_plain(seq, 6, iters=50, check_every=25)
+    assert [r["t"] for r in recs] == list(range(1, 7))
+    assert all(np.isfinite(r["target"]) and r["sec"] > 0 for r in recs)
+    assert all(hist["y"][t].shape == (12, 4000) for t in range(1, 7))
+    # the reconstruction of a frame differs from the previous one only where the fit moved it
+    assert not torch.equal(hist["A"][1], hist["A"][0])
+    prop, losses, _ = stream.train_proposal(hist, [1, 2, 3], steps=60, batch=4096)
+    assert losses[-1][1] < losses[0][1]
+    judged = stream.judge(seq, hist, recs, prop, [4, 5, 6], iters=50, check_every=25)
+    assert [j["t"] for j in judged] == [4, 5, 6]
+    s = stream.summarize(recs, judged, [4, 5, 6])
+    assert s["frames"] == [4, 6]
+    jb = stream.judge(seq, hist, recs, prop, [4, 5], iters=50, check_every=25, batched=True)
+    assert len(jb) == 2
