@@ -30,6 +30,10 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 // -0.5 * log2(e): exp(-q/2) = exp2(kFold * q)
 constexpr float kFold = -0.72134752044448170f;
+// Per-entry factor of the adjoint's sum number k (x, y, A, B, C, opacity, r, g, b): the position sums carry
+// m (B dy + A dx) and m (C dy + B dx) with dL/dx, dL/dy = +sum; the conic sums carry m dx^2, m dx dy, m dy^2
+// with dL/dA = -sum/2, dL/dB = -sum (B enters q twice), dL/dC = -sum/2.
+__device__ __forceinline__ float geom_scale(int k) { return k == 3 ? -1.f : ((k == 2 || k == 4) ? -0.5f : 1.f); }
 
 struct ViewPtrsF {
     float* p[QG_MAX_VIEWS];
@@ -86,23 +90,23 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
     const int px = tx * TW + (lane % TW);
     const int py0 = ty * TH + lane / TW;
     const float fx = (float)px + 0.5f;
+    // T > 0: the pixel is still compositing; the sign flips when it stops (or for pixels outside the image),
+    // so the running state needs no register of its own.  The final transmittance is |T|.
     float T[PPL], C0[PPL], C1[PPL], C2[PPL], fy[PPL];
     uint32_t last[PPL];
-    bool run[PPL];
     const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         fy[k] = (float)(py0 + k * RPK) + 0.5f;
-        T[k] = 1.f;
+        T[k] = (px < cam.width && (py0 + k * RPK) < cam.height) ? 1.f : -1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = s;
-        run[k] = px < cam.width && (py0 + k * RPK) < cam.height;
     }
     const float* __restrict__ splat = vt.proj[v].splat;
     for (uint32_t b = s; b < e; b += BD) {
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) any |= run[k];
+        for (int k = 0; k < PPL; ++k) any |= T[k] > 0.f;
         if (__ballot(any) == 0) break;
 #pragma unroll
         for (int q = 0; q < (BD + 63) / 64; ++q) {
@@ -131,18 +135,19 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
                 const float dy = fy[k] - a.y;
                 const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
                 const float al = fminf(kAlphaMax, raw);
-                const bool ok = run[k] && al >= kAlphaMin;
-                const float tn = T[k] * (1.f - al);
+                const bool running = T[k] > 0.f;
+                const bool ok = running && al >= kAlphaMin;
+                const float w = al * T[k];
+                const float tn = T[k] - w;  // T (1 - alpha)
                 const bool stop = ok && tn < kTMin;
                 const bool take = ok && !stop;
-                const float w = take ? al * T[k] : 0.f;
-                C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
-                C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
-                C2[k] = __builtin_fmaf(cb, w, C2[k]);
-                T[k] = take ? tn : T[k];
+                const float wt = take ? w : 0.f;
+                C0[k] = __builtin_fmaf(bb.z, wt, C0[k]);
+                C1[k] = __builtin_fmaf(bb.w, wt, C1[k]);
+                C2[k] = __builtin_fmaf(cb, wt, C2[k]);
+                T[k] = take ? tn : (stop ? -T[k] : T[k]);
                 last[k] = take ? b + jj + 1 : last[k];
-                run[k] = run[k] && !stop;
-                any2 |= run[k];
+                any2 |= running && !stop;
             }
             if (__ballot(any2) == 0) break;
         }
@@ -158,10 +163,11 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
         if (px < W && py < H) {
             const size_t o = (size_t)py * W + px;
             const size_t plane = (size_t)W * H;
-            img[o] = C0[k] + T[k] * bg0;
-            img[plane + o] = C1[k] + T[k] * bg1;
-            img[2 * plane + o] = C2[k] + T[k] * bg2;
-            tf[o] = T[k];
+            const float tk = fabsf(T[k]);
+            img[o] = C0[k] + tk * bg0;
+            img[plane + o] = C1[k] + tk * bg1;
+            img[2 * plane + o] = C2[k] + tk * bg2;
+            tf[o] = tk;
             lp[o] = last[k];
         }
     }
@@ -253,6 +259,7 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
     const int px = tx * TW + (lane % TW);
     const int py0 = ty * TH + lane / TW;
     const float fx = (float)px + 0.5f;
+    const float gscale = geom_scale(lane);
     const uint32_t s = ranges[2 * tile];
     const int W = cam.width, H = cam.height;
     const size_t plane = (size_t)W * H;
@@ -303,7 +310,7 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
             const float4 bb = s_b[jj];
             const float4 cc = s_c[jj];
             const float dx = fx - a.x;
-            const float Adx = cc.y * dx, Bdx = cc.z * dx;
+            const float Adx = cc.y * dx, Bdx = cc.z * dx, dxx = dx * dx;
             // acc: gx, gy, gA, gB, gC, go, gr, gg, gb
             float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             bool hit = false;
@@ -325,16 +332,17 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 const float d = cG - SG[k];
                 SG[k] = __builtin_fmaf(on ? al : 0.f, d, SG[k]);
                 T[k] = Ti;
-                // geometric part: zero where the 0.99 clamp is active
+                // geometric part: zero where the 0.99 clamp is active.  With m = alpha dL/dalpha,
+                // dL/dq = -m/2 (q = A dx^2 + 2 B dx dy + C dy^2); the constant factors -1/2 and -1 of the
+                // conic terms are applied once per entry after the wave sum (kGeomScale).
                 const float dLda = (on && raw <= kAlphaMax) ? Ti * d : 0.f;
                 acc[5] = __builtin_fmaf(dLda, ek, acc[5]);
-                const float dq = -0.5f * al * dLda;  // dL/dq, q = A dx^2 + 2 B dx dy + C dy^2
-                const float dq2 = dq + dq;
-                acc[0] = __builtin_fmaf(-dq2, __builtin_fmaf(cc.z, dy, Adx), acc[0]);
-                acc[1] = __builtin_fmaf(-dq2, __builtin_fmaf(cc.w, dy, Bdx), acc[1]);
-                acc[2] = __builtin_fmaf(dq, dx * dx, acc[2]);
-                acc[3] = __builtin_fmaf(dq2, dx * dy, acc[3]);
-                acc[4] = __builtin_fmaf(dq, dy * dy, acc[4]);
+                const float m = al * dLda;
+                acc[0] = __builtin_fmaf(m, __builtin_fmaf(cc.z, dy, Adx), acc[0]);
+                acc[1] = __builtin_fmaf(m, __builtin_fmaf(cc.w, dy, Bdx), acc[1]);
+                acc[2] = __builtin_fmaf(m, dxx, acc[2]);
+                acc[3] = __builtin_fmaf(m, dx * dy, acc[3]);
+                acc[4] = __builtin_fmaf(m, dy * dy, acc[4]);
             }
             if (__ballot(hit) == 0) continue;
             row_sums<9>(acc);
@@ -346,7 +354,8 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (lane < 9) {
-                const float val = (s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]);
+                const float val =
+                    gscale * ((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]));
                 atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
