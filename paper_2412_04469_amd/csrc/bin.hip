@@ -6,17 +6,22 @@
 // by the 32 depth bits, then by the tile bits.  All pairs of one (view, Gaussian) share the depth
 // digits, so the depth passes are run once per (view, Gaussian) before pairs are emitted (4 passes
 // over V*n items instead of 4 passes over P pairs), and only the tile bits are sorted over the pairs
-// (2 passes for up to 65,536 tiles).  Both sorts use the same stable 8-bit-digit pass:
-//   histogram per block -> exclusive scan of the digit-major histogram -> stable scatter, where the
-//   rank of an item inside its block is found with wave64 ballot matching on the digit bits and
-//   per-wave digit counters in LDS.
+// (2 passes for up to 65,536 tiles).
+//
+// Every pass is one kernel ("one sweep"): the global digit histograms of all passes are accumulated
+// while the keys are produced (depth keys, pair emission), and each pass kernel finds where its block's
+// items go by decoupled look-back: block b publishes its per-digit counts, adds up the counts (or the
+// already inclusive prefixes) of blocks b-1, b-2, ... and publishes its own inclusive prefix.  Blocks take
+// their logical index from a ticket counter when they start, so a block only ever waits for blocks that
+// are already running; every wait is bounded (a give-up sets an error word instead of hanging).  Inside a
+// block the rank of an item among equal digits is found with wave64 ballot matching on the digit bits and
+// per-wave digit counters in LDS, which keeps the sort stable.  The per-(view, Gaussian) tile counts are
+// scanned the same way, in one kernel.
 #include <algorithm>
 
 #include "qg_internal.h"
 
 namespace qg {
-
-qg_status bin_launch_checks();
 
 namespace {
 
@@ -24,6 +29,69 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+constexpr int kMaxPasses = 4;
+
+// Look-back state word: 2 flag bits over a 62-bit value.
+constexpr uint64_t kFlagAgg = 1ull << 62;  // value = this block's own count
+constexpr uint64_t kFlagInc = 2ull << 62;  // value = inclusive prefix over blocks 0..b
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr uint32_t kMaxSpin = 1u << 22;    // polls before a wait gives up (never reached when blocks progress)
+
+constexpr int kHistCopies = 16;  // global histograms are kept in 16 copies to spread atomic contention
+
+// Per-sort control block in the workspace (zeroed by k_bin_init for every call).
+struct SortCtl {
+    uint32_t ticket[kMaxPasses + 1];  // per pass, and one for the count scan
+    uint32_t err;                     // non-zero if a look-back wait gave up
+    uint32_t ghist[kMaxPasses][kHistCopies][kRadix];
+};
+
+__device__ __forceinline__ void store_state(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_state(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of block `bid` over blocks 0..bid-1 for one counter (this thread's), given the published
+// states at lb[j * stride].  The states of up to kWindow predecessors are loaded together, then consumed
+// nearest first until an inclusive prefix (done) or a state not yet published (re-load from there).
+// Gives up (recording it in *err) after kMaxSpin rounds without progress.
+constexpr int kWindow = 32;
+
+__device__ __forceinline__ uint64_t look_back(const uint64_t* lb, int64_t stride, uint32_t bid, uint32_t* err) {
+    uint64_t excl = 0;
+    int64_t j = (int64_t)bid - 1;  // nearest predecessor not yet consumed
+    uint32_t spins = 0;
+    while (j >= 0) {
+        uint64_t st[kWindow];
+#pragma unroll
+        for (int w = 0; w < kWindow; ++w) st[w] = j - w >= 0 ? load_state(lb + (j - w) * stride) : kFlagInc;
+        int used = 0;
+        bool done = false;
+#pragma unroll
+        for (int w = 0; w < kWindow; ++w) {
+            if (done || used < w) continue;  // stopped earlier in this window
+            const uint64_t f = st[w] & ~kValMask;
+            if (f == 0) continue;  // not published yet: used stays at w
+            excl += st[w] & kValMask;
+            used = w + 1;
+            done = f == kFlagInc;
+        }
+        if (done) break;
+        j -= used;
+        if (used == 0) {
+            if (++spins > kMaxSpin) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        } else {
+            spins = 0;
+        }
+    }
+    return excl;
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -39,41 +107,78 @@ __device__ __forceinline__ uint64_t match8(uint32_t d, bool valid) {
     return m;
 }
 
-// Item r of lane l in wave w of block b sits at b*TILE + w*(IPT*64) + r*64 + l (wave-contiguous,
-// so within a wave the rounds are in element order and waves are in element order).
-template <int IPT>
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* count_ptr,
-                                                        uint32_t count_fixed, int shift, uint32_t* __restrict__ hist,
-                                                        int nblocks) {
-    __shared__ uint32_t s_hist[kRadix];
-    const uint32_t count = count_ptr ? *count_ptr : count_fixed;
-    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
-    s_hist[tid] = 0;
-    __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * (IPT * kBlock) + (uint64_t)w * (IPT * kWave);
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    const int lane = __lane_id();
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint64_t idx = base + (uint64_t)r * kWave + lane;
-        const bool valid = idx < count;
-        const uint32_t d = valid ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
-        const uint64_t m = match8(d, valid);
-        if (valid && (m & lanemask_lt()) == 0) atomicAdd(&s_hist[d], (uint32_t)__popcll(m));
+    for (int o = 1; o < kWave; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
-    __syncthreads();
-    hist[(size_t)tid * nblocks + blockIdx.x] = s_hist[tid];
+    return x;
 }
 
-template <int IPT>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ kin,
-                                                           const uint32_t* __restrict__ vin,
-                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                           const uint32_t* count_ptr, uint32_t count_fixed, int shift,
-                                                           const uint32_t* __restrict__ offsets, int nblocks) {
-    __shared__ uint32_t s_cnt[kWaves][kRadix];
-    const uint32_t count = count_ptr ? *count_ptr : count_fixed;
-    const uint64_t blk0 = (uint64_t)blockIdx.x * (IPT * kBlock);
-    if (blk0 >= count) return;  // whole block empty (uniform)
+// Block-wide exclusive scan of one value per thread; *total = block sum.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T* s_w, T* total) {
     const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
+    T inc = wave_incl_scan(x);
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    T wbase = 0, tot = 0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+        if (k < w) wbase += s_w[k];
+        tot += s_w[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + inc - x;
+}
+
+// Adds this block's LDS digit histograms of `npass` passes (s_h[p][d]) into copy (block % 16) of the
+// global ones.
+__device__ __forceinline__ void flush_hists(const uint32_t (*s_h)[kRadix], int npass, SortCtl* ctl) {
+    const int copy = blockIdx.x % kHistCopies;
+    for (int p = 0; p < npass; ++p) {
+        const uint32_t c = s_h[p][threadIdx.x];
+        if (c) atomicAdd(&ctl->ghist[p][copy][threadIdx.x], c);
+    }
+}
+
+// Count of digit threadIdx.x in pass p (sum of the copies).
+__device__ __forceinline__ uint32_t digit_total(const SortCtl* ctl, int p) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) s += ctl->ghist[p][c][threadIdx.x];
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------------
+// One stable radix pass.  Item r of lane l in wave w of block b sits at b*TILE + w*(IPT*64) + r*64 + l
+// (wave-contiguous, so within a wave the rounds are in element order and waves are in element order).
+// lb_cur: [nblocks][256] look-back states of this pass (zero on entry); lb_next, if given, is the next
+// pass's array: every block clears its own slot there.
+// ------------------------------------------------------------------------------------------------
+template <int IPT>
+__global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                     const uint32_t* count_ptr, uint32_t count_fixed, int pass,
+                                                     SortCtl* ctl, uint64_t* lb_cur, uint64_t* lb_next) {
+    __shared__ uint32_t s_cnt[kWaves][kRadix];
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_bid;
+    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
+    if (tid == 0) s_bid = atomicAdd(&ctl->ticket[pass], 1u);
+    __syncthreads();
+    const uint32_t bid = s_bid;
+    if (lb_next) lb_next[(size_t)bid * kRadix + tid] = 0ull;
+    const uint32_t count = count_ptr ? *count_ptr : count_fixed;
+    const uint64_t blk0 = (uint64_t)bid * (IPT * kBlock);
+    if (blk0 >= count) return;  // no items here; no later block has any either, so nobody waits for this one
+    const int shift = kRadixBits * pass;
+    // global start of each digit: exclusive scan of the pass histogram
+    uint32_t dtot;
+    const uint32_t dbase = block_excl_scan<uint32_t>(digit_total(ctl, pass), s_w, &dtot);
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
     __syncthreads();
@@ -96,9 +201,22 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
         if (valid && (m & lanemask_lt()) == 0) atomicAdd(&s_cnt[w][d], (uint32_t)__popcll(m));
     }
     __syncthreads();
-    // per-wave starting positions: global digit offset of this block + earlier waves
+    // block total of digit tid, publish, look back, publish the inclusive prefix
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) tot += s_cnt[k][tid];
+    uint64_t* my = lb_cur + (size_t)bid * kRadix + tid;
+    uint64_t excl = 0;
+    if (bid == 0) {
+        store_state(my, kFlagInc | tot);
+    } else {
+        store_state(my, kFlagAgg | tot);
+        excl = look_back(lb_cur + tid, kRadix, bid, &ctl->err);
+        store_state(my, kFlagInc | (excl + tot));
+    }
+    // per-wave starting positions: digit start + earlier blocks + earlier waves
     {
-        uint32_t run = offsets[(size_t)tid * nblocks + blockIdx.x];
+        uint32_t run = dbase + (uint32_t)excl;
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) {
             const uint32_t c = s_cnt[k][tid];
@@ -128,200 +246,185 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 }
 
 // ------------------------------------------------------------------------------------------------
-// Exclusive scan (three kernels: block sums, scan of block sums, block-local scan + carry).
+// Binning kernels
 // ------------------------------------------------------------------------------------------------
+// Zeroes the tile ranges, both control blocks and the look-back arrays that the first kernel of each
+// sweep reads (one grid-stride pass over a list of word ranges).
+struct ZeroList {
+    uint32_t* p[8];
+    int64_t words[8];
+    int n;
+};
+
+__global__ void k_bin_init(ZeroList z) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < z.n; ++k)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.words[k]; i += stride) z.p[k][i] = 0u;
+}
+
+// Depth keys of every (view, Gaussian) item (non-visible items sort last) and the depth digit histograms
+// (grid-stride over a capped grid, so few blocks flush histograms).
+constexpr int kHistBlocks = 256;
+
+__global__ __launch_bounds__(kBlock) void k_depth_keys(int64_t n, ViewTable vt, uint32_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals, SortCtl* ctl) {
+    __shared__ uint32_t s_h[4][kRadix];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) s_h[p][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t items = n * vt.V;
+    for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < items;
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(item / n);
+        const int64_t i = item - (int64_t)v * n;
+        const ProjDev& p = vt.proj[v];
+        const uint32_t key = p.ntiles[i] > 0 ? __float_as_uint(p.depth[i]) : 0xFFFFFFFFu;
+        keys[item] = key;
+        vals[item] = (uint32_t)item;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) atomicAdd(&s_h[q][(key >> (8 * q)) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    flush_hists(s_h, 4, ctl);
+}
+
+// Exclusive scan (64-bit) of the tile counts of the items in depth order, in one kernel with look-back;
+// the block holding the last item also writes the total, the tile sort's count (0 on overflow) and the
+// caller's num_pairs.
 constexpr int kScanIPT = 16;
 constexpr int kScanTile = kBlock * kScanIPT;
 
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T x) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        T y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-// Block-wide exclusive scan of one value per thread; returns the exclusive prefix, *total = block sum.
-template <typename T>
-__device__ __forceinline__ T block_excl_scan(T x, T* s_w, T* total) {
-    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
-    T inc = wave_incl_scan(x);
-    if (lane == kWave - 1) s_w[w] = inc;
+__global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n, ViewTable vt,
+                                                       const uint32_t* __restrict__ sorted, uint64_t* __restrict__ offs,
+                                                       int64_t capacity, uint32_t* __restrict__ sort_count,
+                                                       int64_t* __restrict__ num_pairs, SortCtl* ctl,
+                                                       uint64_t* lb) {
+    __shared__ uint64_t s_w[kWaves];
+    __shared__ uint32_t s_bid;
+    __shared__ uint64_t s_excl;
+    if (threadIdx.x == 0) s_bid = atomicAdd(&ctl->ticket[kMaxPasses], 1u);
     __syncthreads();
-    T wbase = 0, tot = 0;
-    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
-        if (k < w) wbase += s_w[k];
-        tot += s_w[k];
+    const uint32_t bid = s_bid;
+    const int64_t base = (int64_t)bid * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+    uint64_t c[kScanIPT];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanIPT; ++r) {
+        const int64_t k = base + r;
+        uint64_t x = 0;
+        if (k < items) {
+            const uint32_t item = sorted[k];
+            const int v = (int)(item / n);
+            x = (uint64_t)vt.proj[v].ntiles[item - (int64_t)v * n];
+        }
+        c[r] = x;
+        acc += x;
+    }
+    uint64_t btot;
+    const uint64_t ex = block_excl_scan<uint64_t>(acc, s_w, &btot);
+    if (threadIdx.x == 0) {
+        uint64_t excl = 0;
+        if (bid == 0) {
+            store_state(lb, kFlagInc | btot);
+        } else {
+            store_state(lb + bid, kFlagAgg | btot);
+            excl = look_back(lb, 1, bid, &ctl->err);
+            store_state(lb + bid, kFlagInc | (excl + btot));
+        }
+        s_excl = excl;
+        if ((int64_t)(bid + 1) * kScanTile >= items) {  // the last block
+            const uint64_t t = excl + btot;
+            const bool failed = atomicAdd(&ctl->err, 0u) != 0;  // a depth pass or this scan gave up waiting
+            *num_pairs = failed ? -1 : (int64_t)t;
+            *sort_count = (!failed && t <= (uint64_t)capacity) ? (uint32_t)t : 0u;
+        }
     }
     __syncthreads();
-    *total = tot;
-    return wbase + inc - x;
-}
-
-template <typename TI, typename TO>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI* __restrict__ in, int64_t n, TO* __restrict__ part) {
-    __shared__ TO s_w[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    TO acc = 0;
-    for (int r = 0; r < kScanIPT; ++r) {
-        const int64_t idx = base + (int64_t)r * kBlock + threadIdx.x;
-        if (idx < n) acc += (TO)in[idx];
-    }
-    TO tot;
-    block_excl_scan<TO>(acc, s_w, &tot);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// Single block: in-place exclusive scan of part[0..nb); writes the grand total.
-template <typename TO>
-__global__ __launch_bounds__(1024) void k_scan_partials(TO* __restrict__ part, int64_t nb, TO* __restrict__ total_out) {
-    __shared__ TO s_w[1024 / kWave];
-    TO carry = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += blockDim.x) {
-        const int64_t idx = c0 + threadIdx.x;
-        TO x = idx < nb ? part[idx] : (TO)0;
-        TO tot;
-        TO ex = block_excl_scan<TO>(x, s_w, &tot);
-        if (idx < nb) part[idx] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
-template <typename TI, typename TO>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const TI* __restrict__ in, int64_t n, const TO* __restrict__ part,
-                                                      TO* __restrict__ out) {
-    __shared__ TO s_w[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
-    TO v[kScanIPT];
-    TO acc = 0;
+    uint64_t run = s_excl + ex;
 #pragma unroll
     for (int r = 0; r < kScanIPT; ++r) {
-        const int64_t idx = base + r;
-        v[r] = idx < n ? (TO)in[idx] : (TO)0;
-        acc += v[r];
+        const int64_t k = base + r;
+        if (k < items) offs[k] = run;
+        run += c[r];
     }
-    TO tot;
-    TO run = part[blockIdx.x] + block_excl_scan<TO>(acc, s_w, &tot);
-#pragma unroll
-    for (int r = 0; r < kScanIPT; ++r) {
-        const int64_t idx = base + r;
-        if (idx < n) out[idx] = run;
-        run += v[r];
-    }
-}
-
-template <typename TI, typename TO>
-qg_status scan_excl(const TI* in, int64_t n, TO* out, TO* part, TO* total, hipStream_t s, const char* tag = "scan") {
-    QG_TIMED(tag, s);
-    const int64_t nb = std::max<int64_t>(1, ceil_div(n, kScanTile));
-    k_scan_reduce<TI, TO><<<(unsigned)nb, kBlock, 0, s>>>(in, n, part);
-    k_scan_partials<TO><<<1, 1024, 0, s>>>(part, nb, total);
-    k_scan_down<TI, TO><<<(unsigned)nb, kBlock, 0, s>>>(in, n, part, out);
-    QG_LAUNCH_CHECK("scan");
-    return QG_OK;
-}
-
-inline int64_t scan_parts(int64_t n) { return std::max<int64_t>(1, ceil_div(n, kScanTile)); }
-
-// ------------------------------------------------------------------------------------------------
-// Binning kernels
-// ------------------------------------------------------------------------------------------------
-__global__ void k_depth_keys(int64_t n, ViewTable vt, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= n * vt.V) return;
-    const int v = (int)(item / n);
-    const int64_t i = item - (int64_t)v * n;
-    const ProjDev& p = vt.proj[v];
-    const int nt = p.ntiles[i];
-    keys[item] = nt > 0 ? __float_as_uint(p.depth[i]) : 0xFFFFFFFFu;
-    vals[item] = (uint32_t)item;
-}
-
-__global__ void k_gather_counts(int64_t items, int64_t n, ViewTable vt, const uint32_t* __restrict__ sorted,
-                                uint32_t* __restrict__ cnt) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= items) return;
-    const uint32_t item = sorted[k];
-    const int v = (int)(item / n);
-    const int64_t i = item - (int64_t)v * n;
-    cnt[k] = (uint32_t)vt.proj[v].ntiles[i];
-}
-
-// Converts the 64-bit total into the count the tile sort uses (0 on overflow) and the caller's num_pairs.
-__global__ void k_finish_count(const uint64_t* __restrict__ total, int64_t capacity, uint32_t* __restrict__ sort_count,
-                               int64_t* __restrict__ num_pairs) {
-    const uint64_t t = *total;
-    *num_pairs = (int64_t)t;
-    *sort_count = t <= (uint64_t)capacity ? (uint32_t)t : 0u;
 }
 
 // Emission, one thread per output pair (load-balanced whatever the rectangle sizes): a block owns 1024
 // consecutive output positions; the (view, Gaussian) items that cover them are consecutive in depth order
 // (every item with a non-empty rectangle owns at least one position, empty ones were sorted last), so the
-// block loads their offsets into LDS and each position finds its item by binary search there.
+// block loads their offsets into LDS and each position finds its item by binary search there.  Blocks loop
+// over chunks of a capped grid; the tile digit histograms of the following passes are accumulated on the
+// way and flushed once per block.
 constexpr int kEmitPer = 1024;
 
 __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTable vt,
                                               const uint32_t* __restrict__ sorted,
                                               const uint64_t* __restrict__ offs,
-                                              const uint32_t* __restrict__ sort_count,
-                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+                                              const uint32_t* __restrict__ sort_count, int tpasses,
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals,
+                                              SortCtl* ctl) {
     __shared__ uint64_t s_off[kEmitPer];
+    __shared__ uint32_t s_h[kMaxPasses][kRadix];
     __shared__ int64_t s_k0;
     const uint64_t P = *sort_count;
-    const uint64_t base = (uint64_t)blockIdx.x * kEmitPer;
-    if (base >= P) return;
-    if (threadIdx.x == 0) {
-        // last k with offs[k] <= base
-        int64_t lo = 0, hi = items - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (offs[mid] <= base)
-                lo = mid;
-            else
-                hi = mid - 1;
+#pragma unroll
+    for (int q = 0; q < kMaxPasses; ++q) s_h[q][threadIdx.x] = 0;
+    for (uint64_t chunk = blockIdx.x; chunk * kEmitPer < P; chunk += gridDim.x) {
+        const uint64_t base = chunk * kEmitPer;
+        __syncthreads();  // the previous chunk is done with s_off
+        if (threadIdx.x == 0) {
+            // last k with offs[k] <= base
+            int64_t lo = 0, hi = items - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (offs[mid] <= base)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            s_k0 = lo;
         }
-        s_k0 = lo;
+        __syncthreads();
+        const int64_t k0 = s_k0;
+        for (int t = threadIdx.x; t < kEmitPer; t += 256) {
+            const int64_t k = k0 + t;
+            s_off[t] = k < items ? offs[k] : ~0ull;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < kEmitPer; t += 256) {
+            const uint64_t p = base + t;
+            if (p >= P) break;
+            int lo = 0, hi = kEmitPer - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= p)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const uint32_t j = (uint32_t)(p - s_off[lo]);
+            const uint32_t item = sorted[k0 + lo];
+            const int v = (int)(item / n);
+            const int64_t i = item - (int64_t)v * n;
+            const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[i];
+            const uint32_t w = (uint32_t)(r.z - r.x);
+            const uint32_t ty = (uint32_t)r.y + j / w, tx = (uint32_t)r.x + j % w;
+            const uint32_t key = vt.cam[v].tile_off + ty * (uint32_t)vt.cam[v].grid_w + tx;
+            tkeys[p] = key;
+            tvals[p] = (uint32_t)i;
+            for (int q = 0; q < tpasses; ++q) atomicAdd(&s_h[q][(key >> (8 * q)) & 0xFFu], 1u);
+        }
     }
     __syncthreads();
-    const int64_t k0 = s_k0;
-    for (int t = threadIdx.x; t < kEmitPer; t += 256) {
-        const int64_t k = k0 + t;
-        s_off[t] = k < items ? offs[k] : ~0ull;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kEmitPer; t += 256) {
-        const uint64_t p = base + t;
-        if (p >= P) break;
-        int lo = 0, hi = kEmitPer - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= p)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const uint32_t j = (uint32_t)(p - s_off[lo]);
-        const uint32_t item = sorted[k0 + lo];
-        const int v = (int)(item / n);
-        const int64_t i = item - (int64_t)v * n;
-        const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[i];
-        const uint32_t w = (uint32_t)(r.z - r.x);
-        const uint32_t ty = (uint32_t)r.y + j / w, tx = (uint32_t)r.x + j % w;
-        tkeys[p] = vt.cam[v].tile_off + ty * (uint32_t)vt.cam[v].grid_w + tx;
-        tvals[p] = (uint32_t)i;
-    }
+    flush_hists(s_h, tpasses, ctl);
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ sort_count,
-                         uint32_t* __restrict__ ranges) {
+                         uint32_t* __restrict__ ranges, SortCtl* ctl, int64_t* __restrict__ num_pairs) {
     const uint32_t P = *sort_count;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
+    if (p == 0 && atomicAdd(&ctl->err, 0u) != 0) *num_pairs = -1;  // a tile pass gave up waiting
     const uint32_t t = tkeys[p];
     if (p == 0 || tkeys[p - 1] != t) ranges[2 * (size_t)t] = (uint32_t)p;
     if (p == (int64_t)P - 1 || tkeys[p + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)p + 1;
@@ -340,53 +443,35 @@ __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __r
     keys[p] = ((uint64_t)t << 32) | db;
 }
 
-template <int IPT>
-qg_status radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                     const uint32_t* count_ptr, uint32_t count_fixed, int64_t max_count, int shift, uint32_t* hist,
-                     uint32_t* hist_scan, uint32_t* part, hipStream_t s, const char* const* tags) {
-    const int nblocks = (int)std::max<int64_t>(1, ceil_div(max_count, IPT * kBlock));
+int ipt_for(int64_t max_count) { return max_count <= (1 << 16) ? 4 : 16; }
+int64_t sweep_blocks(int64_t max_count) { return std::max<int64_t>(1, ceil_div(max_count, ipt_for(max_count) * kBlock)); }
+
+qg_status sweep_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* count_ptr,
+                     uint32_t count_fixed, int64_t max_count, int pass, SortCtl* ctl, uint64_t* lb_cur,
+                     uint64_t* lb_next, hipStream_t s, const char* tag) {
+    const unsigned nb = (unsigned)sweep_blocks(max_count);
     {
-        QG_TIMED(tags[0], s);
-        k_radix_hist<IPT><<<nblocks, kBlock, 0, s>>>(kin, count_ptr, count_fixed, shift, hist, nblocks);
+        QG_TIMED(tag, s);
+        if (ipt_for(max_count) == 4)
+            k_onesweep<4><<<nb, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, pass, ctl, lb_cur, lb_next);
+        else
+            k_onesweep<16><<<nb, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, pass, ctl, lb_cur,
+                                                 lb_next);
     }
-    qg_status st = scan_excl<uint32_t, uint32_t>(hist, (int64_t)kRadix * nblocks, hist_scan, part, nullptr, s, tags[1]);
-    if (st != QG_OK) return st;
-    {
-        QG_TIMED(tags[2], s);
-        k_radix_scatter<IPT><<<nblocks, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, shift, hist_scan,
-                                                       nblocks);
-    }
-    QG_LAUNCH_CHECK("radix_pass");
+    QG_LAUNCH_CHECK("radix pass");
     return QG_OK;
-}
-
-qg_status radix_pass_any(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                         const uint32_t* count_ptr, uint32_t count_fixed, int64_t max_count, int shift,
-                         uint32_t* hist, uint32_t* hist_scan, uint32_t* part, hipStream_t s, const char* const* tags) {
-    if (max_count <= (1 << 22))
-        return radix_pass<4>(kin, vin, kout, vout, count_ptr, count_fixed, max_count, shift, hist, hist_scan, part, s,
-                             tags);
-    return radix_pass<16>(kin, vin, kout, vout, count_ptr, count_fixed, max_count, shift, hist, hist_scan, part, s,
-                          tags);
-}
-
-const char* const kDepthTags[3] = {"sort_depth_hist", "sort_depth_scan", "sort_depth_scatter"};
-const char* const kTileTags[3] = {"sort_tile_hist", "sort_tile_scan", "sort_tile_scatter"};
-
-int64_t radix_blocks(int64_t max_count) {
-    const int ipt = max_count <= (1 << 22) ? 4 : 16;
-    return std::max<int64_t>(1, ceil_div(max_count, ipt * kBlock));
 }
 
 struct BinWs {
     uint32_t *dkA, *dkB, *dvA, *dvB;  // depth sort, V*n
-    uint32_t* cnt;                    // V*n
     uint64_t* offs;                   // V*n
-    uint64_t* part64;                 // scan partials (64-bit)
-    uint64_t* total64;
     uint32_t* sort_count;
     uint32_t *tkA, *tkB, *tvB;        // tile sort, capacity
-    uint32_t *hist, *hist_scan, *part32;
+    SortCtl *ctl_depth, *ctl_tile;
+    uint64_t *lb_d0, *lb_d1;          // depth look-back, [blocks][256] each
+    uint64_t *lb_t0, *lb_t1;          // tile look-back
+    uint64_t* lb_scan;                // count-scan look-back, [blocks]
+    int64_t nb_depth, nb_tile, nb_scan;
     size_t bytes;
 };
 
@@ -401,22 +486,25 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     const int64_t items = n * V;
     const int64_t it1 = std::max<int64_t>(items, 1);
     const int64_t cap1 = std::max<int64_t>(capacity, 1);
+    w.nb_depth = sweep_blocks(it1);
+    w.nb_tile = sweep_blocks(cap1);
+    w.nb_scan = std::max<int64_t>(1, ceil_div(it1, kScanTile));
     w.dkA = (uint32_t*)take(4 * it1);
     w.dkB = (uint32_t*)take(4 * it1);
     w.dvA = (uint32_t*)take(4 * it1);
     w.dvB = (uint32_t*)take(4 * it1);
-    w.cnt = (uint32_t*)take(4 * it1);
     w.offs = (uint64_t*)take(8 * it1);
-    w.part64 = (uint64_t*)take(8 * scan_parts(it1));
-    w.total64 = (uint64_t*)take(8);
     w.sort_count = (uint32_t*)take(4);
     w.tkA = (uint32_t*)take(4 * cap1);
     w.tkB = (uint32_t*)take(4 * cap1);
     w.tvB = (uint32_t*)take(4 * cap1);
-    const int64_t hb = kRadix * std::max(radix_blocks(cap1), radix_blocks(it1));
-    w.hist = (uint32_t*)take(4 * hb);
-    w.hist_scan = (uint32_t*)take(4 * hb);
-    w.part32 = (uint32_t*)take(4 * scan_parts(hb));
+    w.ctl_depth = (SortCtl*)take(sizeof(SortCtl));
+    w.ctl_tile = (SortCtl*)take(sizeof(SortCtl));
+    w.lb_d0 = (uint64_t*)take(8 * kRadix * w.nb_depth);
+    w.lb_d1 = (uint64_t*)take(8 * kRadix * w.nb_depth);
+    w.lb_t0 = (uint64_t*)take(8 * kRadix * w.nb_tile);
+    w.lb_t1 = (uint64_t*)take(8 * kRadix * w.nb_tile);
+    w.lb_scan = (uint64_t*)take(8 * w.nb_scan);
     w.bytes = off;
     return w;
 }
@@ -449,65 +537,89 @@ extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera
     hipStream_t s = (hipStream_t)stream;
     const int64_t items = n * V;
     const int64_t T = vt.total_tiles;
-    qg_status st = qg_zero(tile_ranges, 8 * T, stream);
-    if (st != QG_OK) return st;
-    if (items == 0) {
-        st = qg_zero(w.total64, 8, stream);
-        if (st != QG_OK) return st;
-        k_finish_count<<<1, 1, 0, s>>>(w.total64, capacity, w.sort_count, num_pairs);
-        QG_LAUNCH_CHECK("qg_bin");
-        return QG_OK;
-    }
-    // 1. depth keys and the 4-pass depth sort over (view, Gaussian) items
-    {
-        QG_TIMED("bin_depth_keys", s);
-        k_depth_keys<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(n, vt, w.dkA, w.dvA);
-    }
-    QG_LAUNCH_CHECK("qg_bin depth keys");
-    uint32_t *ka = w.dkA, *va = w.dvA, *kb = w.dkB, *vb = w.dvB;
-    for (int pass = 0; pass < 4; ++pass) {
-        st = radix_pass_any(ka, va, kb, vb, nullptr, (uint32_t)items, items, 8 * pass, w.hist, w.hist_scan, w.part32, s,
-                            kDepthTags);
-        if (st != QG_OK) return st;
-        std::swap(ka, kb);
-        std::swap(va, vb);
-    }
-    const uint32_t* sorted_items = va;
-    // 2. tile counts in depth order, scan, emission
-    {
-        QG_TIMED("bin_counts", s);
-        k_gather_counts<<<(unsigned)ceil_div(items, 256), 256, 0, s>>>(items, n, vt, sorted_items, w.cnt);
-    }
-    st = scan_excl<uint32_t, uint64_t>(w.cnt, items, w.offs, w.part64, w.total64, s, "bin_count_scan");
-    if (st != QG_OK) return st;
-    k_finish_count<<<1, 1, 0, s>>>(w.total64, capacity, w.sort_count, num_pairs);
-    QG_LAUNCH_CHECK("qg_bin count");
-    if (capacity == 0) return QG_OK;
     int tbits = 1;
     while ((1ll << tbits) < T) ++tbits;
     const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
+    // 0. clear the ranges, the control blocks and the first look-back array of each sweep
+    {
+        ZeroList z{};
+        z.p[0] = tile_ranges;
+        z.words[0] = 2 * T;
+        z.p[1] = (uint32_t*)w.ctl_depth;
+        z.words[1] = sizeof(SortCtl) / 4;
+        z.p[2] = (uint32_t*)w.ctl_tile;
+        z.words[2] = sizeof(SortCtl) / 4;
+        z.p[3] = (uint32_t*)w.lb_d0;
+        z.words[3] = items > 0 ? 2 * kRadix * w.nb_depth : 0;
+        z.p[4] = (uint32_t*)w.lb_t0;
+        z.words[4] = capacity > 0 ? 2 * kRadix * w.nb_tile : 0;
+        z.p[5] = (uint32_t*)w.lb_scan;
+        z.words[5] = 2 * w.nb_scan;
+        z.p[6] = (uint32_t*)num_pairs;  // stays 0 for an empty input
+        z.words[6] = 2;
+        z.p[7] = w.sort_count;
+        z.words[7] = 1;
+        z.n = 8;
+        int64_t most = 0;
+        for (int k = 0; k < z.n; ++k) most = std::max(most, z.words[k]);
+        QG_TIMED("bin_init", s);
+        k_bin_init<<<(unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(most, 256), 1), 4096), 256, 0, s>>>(z);
+    }
+    QG_LAUNCH_CHECK("qg_bin init");
+    if (items == 0) return QG_OK;
+    // 1. depth keys (+ histograms) and the 4-pass depth sort over (view, Gaussian) items
+    {
+        QG_TIMED("bin_depth_keys", s);
+        k_depth_keys<<<(unsigned)std::min<int64_t>(ceil_div(items, kBlock), kHistBlocks), kBlock, 0, s>>>(
+            n, vt, w.dkA, w.dvA, w.ctl_depth);
+    }
+    QG_LAUNCH_CHECK("qg_bin depth keys");
+    uint32_t *ka = w.dkA, *va = w.dvA, *kb = w.dkB, *vb = w.dvB;
+    uint64_t *la = w.lb_d0, *lbb = w.lb_d1;
+    for (int pass = 0; pass < 4; ++pass) {
+        qg_status st = sweep_pass(ka, va, kb, vb, nullptr, (uint32_t)items, items, pass, w.ctl_depth, la,
+                                  pass < 3 ? lbb : nullptr, s, "sort_depth");
+        if (st != QG_OK) return st;
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        std::swap(la, lbb);
+    }
+    const uint32_t* sorted_items = va;
+    // 2. tile counts in depth order: one-kernel scan, total, overflow check
+    {
+        QG_TIMED("bin_count_scan", s);
+        k_count_scan<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.offs, capacity, w.sort_count,
+                                                             num_pairs, w.ctl_depth, w.lb_scan);
+    }
+    QG_LAUNCH_CHECK("qg_bin count");
+    if (capacity == 0) return QG_OK;
     uint32_t* vbuf0 = (tpasses % 2 == 1) ? w.tvB : vals;
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
     {
         QG_TIMED("bin_emit", s);
-        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(items, n, vt, sorted_items, w.offs,
-                                                                      w.sort_count, w.tkA, vbuf0);
+        k_emit<<<(unsigned)std::min<int64_t>(ceil_div(capacity, kEmitPer), 2 * kHistBlocks), 256, 0, s>>>(
+            items, n, vt, sorted_items, w.offs,
+                                                                      w.sort_count, tpasses, w.tkA, vbuf0,
+                                                                      w.ctl_tile);
     }
     QG_LAUNCH_CHECK("qg_bin emit");
     // 3. stable sort by tile id
     uint32_t *tk_in = w.tkA, *tk_out = w.tkB, *tv_in = vbuf0, *tv_out = vbuf1;
+    uint64_t *ta = w.lb_t0, *tb = w.lb_t1;
     for (int pass = 0; pass < tpasses; ++pass) {
-        st = radix_pass_any(tk_in, tv_in, tk_out, tv_out, w.sort_count, 0u, capacity, 8 * pass, w.hist, w.hist_scan,
-                            w.part32, s, kTileTags);
+        qg_status st = sweep_pass(tk_in, tv_in, tk_out, tv_out, w.sort_count, 0u, capacity, pass, w.ctl_tile, ta,
+                                  pass + 1 < tpasses ? tb : nullptr, s, "sort_tile");
         if (st != QG_OK) return st;
         std::swap(tk_in, tk_out);
         std::swap(tv_in, tv_out);
+        std::swap(ta, tb);
     }
     // tk_in / tv_in hold the sorted pairs; tv_in == vals by construction
     // 4. tile ranges (and optional 64-bit keys)
     {
         QG_TIMED("bin_ranges", s);
-        k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges);
+        k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges, w.ctl_tile,
+                                                                   num_pairs);
     }
     QG_LAUNCH_CHECK("qg_bin ranges");
     if (keys) {

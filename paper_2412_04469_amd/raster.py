@@ -99,6 +99,8 @@ class Rasterizer:
     def ensure_capacity(self, margin=1.25) -> bool:
         """Host-synchronising check of the last bin; grows the buffers and returns True if it overflowed."""
         p = int(self.num_pairs.item())
+        if p < 0:
+            raise qg.QGError(qg.QG_ERR_HIP, "qg_bin reported an internal sort failure (num_pairs = -1)")
         if p > self.capacity:
             self._alloc_capacity(int(math.ceil(p * margin)))
             return True

@@ -92,7 +92,9 @@ def _random_rects(rng, n, gw, gh, empty_frac=0.2, max_w=6):
 @pytest.mark.parametrize("tile,sizes,n", [((16, 16), [(100, 70)], 5000),
                                           ((8, 8), [(100, 70), (64, 64), (33, 17)], 3000),
                                           ((32, 8), [(300, 200), (50, 40)], 20000),
-                                          ((16, 16), [(1352, 1014)], 70000)])
+                                          ((16, 16), [(1352, 1014)], 70000),
+                                          # > 4M pairs (16 items per thread) and > 65,536 tiles (3 tile passes)
+                                          ((8, 8), [(1920, 1080), (1920, 1080), (1352, 1014)], 300000)])
 def test_bin_bit_exact(qgm, tile, sizes, n):
     qg, raster = qgm
     rng = synth.rng_for(20 + n)
@@ -122,11 +124,16 @@ def test_bin_bit_exact(qgm, tile, sizes, n):
     assert rast.ensure_capacity()
     rast.bin()
     torch.cuda.synchronize()
-    P = int(rast.num_pairs.item())
-    assert P == len(ks)
-    assert np.array_equal(rast.vals[:P].cpu().numpy().astype(np.uint32), vs)
-    assert np.array_equal(rast.keys[:P].cpu().numpy().view(np.uint64), ks)
-    assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
+    for rep in range(2):  # a second call on the same workspace must not see the first one's sort state
+        if rep:
+            rast.vals.zero_()
+            rast.bin()
+            torch.cuda.synchronize()
+        P = int(rast.num_pairs.item())
+        assert P == len(ks)
+        assert np.array_equal(rast.vals[:P].cpu().numpy().astype(np.uint32), vs)
+        assert np.array_equal(rast.keys[:P].cpu().numpy().view(np.uint64), ks)
+        assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
 
 
 def test_bin_empty(qgm):
