@@ -68,6 +68,32 @@ __device__ __forceinline__ float blend_e(float fa, float fb2, float fc, float dx
     return __builtin_amdgcn_exp2f(qf);
 }
 
+// Entry culling against the tile: false only if no pixel centre of the box [bx0, bx1] x [by0, by1] can get
+// alpha >= 1/255 from this splat, i.e. min over the box of q = A dx^2 + 2 B dx dy + C dy^2 exceeds
+// k^2 = 2 ln(255 o) (with a margin far above the float32 error of the blend's own evaluation of q).  The
+// minimum of a positive-definite quadratic over a box is 0 if the centre is inside, else it lies on an
+// edge, where the 1D minimiser is clamped to the edge.  Anything not finite or degenerate counts as a hit.
+__device__ __forceinline__ bool tile_hit(float x, float y, float o, float A, float B, float C, float bx0, float bx1,
+                                         float by0, float by1) {
+    if (255.f * o < 0.999f) return false;  // alpha <= o < 1/255 everywhere
+    if (!(A > 0.f && C > 0.f && A * C - B * B > 0.f)) return true;
+    const float lim = 2.f * __logf(fmaxf(255.f * o, 1.f)) * 1.002f + 0.02f;
+    const float dx0 = bx0 - x, dx1 = bx1 - x, dy0 = by0 - y, dy1 = by1 - y;
+    if (dx0 <= 0.f && dx1 >= 0.f && dy0 <= 0.f && dy1 >= 0.f) return true;
+    const float rc = -B / C, ra = -B / A;
+    float qmin = __builtin_huge_valf();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const float ex = s ? dx1 : dx0;  // edge x = const
+        const float ey_ = fminf(fmaxf(rc * ex, dy0), dy1);
+        qmin = fminf(qmin, __builtin_fmaf(__builtin_fmaf(C, ey_, 2.f * B * ex), ey_, A * ex * ex));
+        const float ey = s ? dy1 : dy0;  // edge y = const
+        const float ex_ = fminf(fmaxf(ra * ey, dx0), dx1);
+        qmin = fminf(qmin, __builtin_fmaf(__builtin_fmaf(A, ex_, 2.f * B * ey), ex_, C * ey * ey));
+    }
+    return !(qmin > lim);
+}
+
 template <int TW, int TH>
 struct TileGeom {
     static constexpr int PPL = TW * TH / 64;
@@ -79,7 +105,7 @@ template <int TW, int TH, int BD>
 __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
                                          const ViewPtrsF& image, const ViewPtrsF& tfinal, const ViewPtrsU& lastp,
-                                         int64_t tile, float4* s_a, float4* s_b, float* s_c) {
+                                         int64_t tile, float4* s_a, float4* s_b, float* s_c, uint32_t* s_pos) {
     constexpr int PPL = TileGeom<TW, TH>::PPL;
     constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
     const int v = view_of_tile(vt, (uint32_t)tile);
@@ -103,30 +129,46 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
         last[k] = s;
     }
     const float* __restrict__ splat = vt.proj[v].splat;
+    // pixel centres of this tile inside the image
+    const float bx0 = (float)(tx * TW) + 0.5f, bx1 = (float)min(tx * TW + TW, cam.width) - 0.5f;
+    const float by0 = (float)(ty * TH) + 0.5f, by1 = (float)min(ty * TH + TH, cam.height) - 0.5f;
     for (uint32_t b = s; b < e; b += BD) {
         bool any = false;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) any |= T[k] > 0.f;
         if (__ballot(any) == 0) break;
+        // stage the batch, keeping (in order) only the entries that can reach alpha >= 1/255 in this tile
+        int cnt = 0;
 #pragma unroll
         for (int q = 0; q < (BD + 63) / 64; ++q) {
             const int slot = q * 64 + lane;
             const uint32_t j = b + (uint32_t)slot;
+            bool hit = false;
+            float4 r0, r1, r2;
             if (slot < BD && j < e) {
                 const uint32_t gid = vals[j];
                 const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
-                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                s_a[slot] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
-                s_b[slot] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
-                s_c[slot] = r2.z;
+                r0 = r[0];
+                r1 = r[1];
+                r2 = r[2];
+                hit = tile_hit(r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, bx0, bx1, by0, by1);
             }
+            const uint64_t m = __ballot(hit);
+            if (hit) {
+                const int dst = cnt + (int)__popcll(m & ((1ull << lane) - 1ull));
+                s_a[dst] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+                s_b[dst] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
+                s_c[dst] = r2.z;
+                s_pos[dst] = j;
+            }
+            cnt += (int)__popcll(m);
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)BD, e - b);
         for (int jj = 0; jj < cnt; ++jj) {
             const float4 a = s_a[jj];
             const float4 bb = s_b[jj];
             const float cb = s_c[jj];
+            const uint32_t pos1 = s_pos[jj] + 1;
             const float dx = fx - a.x;
             bool any2 = false;
 #pragma unroll
@@ -146,7 +188,7 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
                 C1[k] = __builtin_fmaf(bb.w, wt, C1[k]);
                 C2[k] = __builtin_fmaf(cb, wt, C2[k]);
                 T[k] = take ? tn : (stop ? -T[k] : T[k]);
-                last[k] = take ? b + jj + 1 : last[k];
+                last[k] = take ? pos1 : last[k];
                 any2 |= running && !stop;
             }
             if (__ballot(any2) == 0) break;
@@ -207,16 +249,18 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     __shared__ float4 s_a[BD];  // x, y, o, A'
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float s_c[BD];   // b
+    __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     if (sc.order == nullptr) {
         const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
         if (tile < vt.total_tiles)
-            fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c);
+            fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c, s_pos);
         return;
     }
     for (;;) {
         const uint32_t item = next_item(sc.ctr);
         if (item >= (uint32_t)vt.total_tiles) break;
-        fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, sc.order[item], s_a, s_b, s_c);
+        fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, sc.order[item], s_a, s_b, s_c,
+                             s_pos);
     }
     finish_sched(sc.ctr);
 }
@@ -247,7 +291,7 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                                          const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
                                          const ViewPtrsCF& tfinal, const ViewPtrsCU& lastp, const ViewPtrsCF& gimage,
                                          float* __restrict__ grad2d, int64_t g2d_view_stride, int64_t tile,
-                                         float4* s_a, float4* s_b, float4* s_c, uint32_t* s_gid,
+                                         float4* s_a, float4* s_b, float4* s_c, uint32_t* s_gid, uint32_t* s_pos,
                                          float (*s_red)[12]) {
     constexpr int PPL = TileGeom<TW, TH>::PPL;
     constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
@@ -287,25 +331,41 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
     for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, o));
     const float* __restrict__ splat = vt.proj[v].splat;
     float* __restrict__ g2 = grad2d + (int64_t)v * g2d_view_stride;
+    // pixel centres of this tile inside the image (the forward's culling test, repeated exactly)
+    const float bx0 = (float)(tx * TW) + 0.5f, bx1 = (float)min(tx * TW + TW, W) - 0.5f;
+    const float by0 = (float)(ty * TH) + 0.5f, by1 = (float)min(ty * TH + TH, H) - 0.5f;
     for (uint32_t hi = maxlast; hi > s;) {
         const uint32_t lo = hi - s > (uint32_t)BD ? hi - (uint32_t)BD : s;
+        int cnt = 0;
 #pragma unroll
         for (int q = 0; q < (BD + 63) / 64; ++q) {
             const int slot = q * 64 + lane;
             const uint32_t j = lo + (uint32_t)slot;
+            bool hit = false;
+            float4 r0, r1, r2;
+            uint32_t gid = 0;
             if (slot < BD && j < hi) {
-                const uint32_t gid = vals[j];
+                gid = vals[j];
                 const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
-                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                s_a[slot] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
-                s_b[slot] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
-                s_c[slot] = make_float4(r2.z, r1.x, r1.y, r1.z);
-                s_gid[slot] = gid;
+                r0 = r[0];
+                r1 = r[1];
+                r2 = r[2];
+                hit = tile_hit(r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, bx0, bx1, by0, by1);
             }
+            const uint64_t m = __ballot(hit);
+            if (hit) {
+                const int dst = cnt + (int)__popcll(m & ((1ull << lane) - 1ull));
+                s_a[dst] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+                s_b[dst] = make_float4(2.f * kFold * r1.y, kFold * r1.z, r2.x, r2.y);
+                s_c[dst] = make_float4(r2.z, r1.x, r1.y, r1.z);
+                s_gid[dst] = gid;
+                s_pos[dst] = j;
+            }
+            cnt += (int)__popcll(m);
         }
         __syncthreads();
-        for (int jj = (int)(hi - lo) - 1; jj >= 0; --jj) {
-            const uint32_t pos = lo + (uint32_t)jj;
+        for (int jj = cnt - 1; jj >= 0; --jj) {
+            const uint32_t pos = s_pos[jj];
             const float4 a = s_a[jj];
             const float4 bb = s_b[jj];
             const float4 cc = s_c[jj];
@@ -377,19 +437,20 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float4 s_c[BD];  // b, A, B, C
     __shared__ uint32_t s_gid[BD];
+    __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     __shared__ float s_red[4][12];  // row totals of the 9 gradient components
     if (sc.order == nullptr) {
         const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
         if (tile < vt.total_tiles)
             bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride,
-                                 tile, s_a, s_b, s_c, s_gid, s_red);
+                                 tile, s_a, s_b, s_c, s_gid, s_pos, s_red);
         return;
     }
     for (;;) {
         const uint32_t item = next_item(sc.ctr);
         if (item >= (uint32_t)vt.total_tiles) break;
         bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride,
-                             sc.order[item], s_a, s_b, s_c, s_gid, s_red);
+                             sc.order[item], s_a, s_b, s_c, s_gid, s_pos, s_red);
     }
     finish_sched(sc.ctr);
 }
