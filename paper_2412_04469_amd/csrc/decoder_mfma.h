@@ -217,6 +217,26 @@ __device__ __forceinline__ void add_acc(const BwdAcc& acc, float* sw) {
     }
 }
 
+// As add_acc, for a buffer shared by the waves of a block (LDS float atomics; no ordering needed).
+__device__ __forceinline__ void add_acc_atomic(const BwdAcc& acc, float* sw) {
+    const int lane = __lane_id(), q = lane / 16, c = lane % 16;
+#pragma unroll
+    for (int mb = 0; mb < kMB; ++mb)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 16 * mb + 4 * q + i;
+                if (m < kM) atomicAdd(&sw[kH * kL + m * kH + 16 * jb + c], acc.W2[mb][jb][i]);
+            }
+    if (q < 2) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) atomicAdd(&sw[(16 * jb + c) * kL + 4 * q + i], acc.W1[jb][i]);
+    }
+}
+
 // Gate of Eq. 6-7.
 __device__ __forceinline__ float gate_of(float a, float g0, float g1, float tau, float* gh_out, float* gt_out) {
     const float gh = sigm(a / tau);

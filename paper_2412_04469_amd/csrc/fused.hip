@@ -103,7 +103,7 @@ struct ViewPtrsB {
     float* p[QG_MAX_VIEWS];
 };
 
-__global__ __launch_bounds__(256) void k_project_decode_bwd(
+__global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     int64_t n, int64_t ld, const float* __restrict__ prev, const float* __restrict__ lat, const float* __restrict__ W1,
     const float* __restrict__ W2, const float* __restrict__ lp, const float* __restrict__ ga, float g0, float g1,
     float tau, float reg_shift, float reg_scale, int sh_deg, ViewTable vt, float dilation,
@@ -113,9 +113,10 @@ __global__ __launch_bounds__(256) void k_project_decode_bwd(
     // same slot, written only after its last read)
     __shared__ float s_buf[4][kChunk][kM + 1];
     __shared__ float s_t[4][16][33];
-    __shared__ float s_acc[4][kWidth];  // per-wave weight-gradient sums (kept out of registers)
+    __shared__ float s_acc[kWidth];  // the block's decoder weight-gradient sums (LDS float atomics)
     const int lane = __lane_id(), w = threadIdx.x / 64, q = lane / 16, c = lane % 16;
-    for (int i = lane; i < kWidth; i += 64) s_acc[w][i] = 0.f;
+    for (int i = threadIdx.x; i < kWidth; i += 256) s_acc[i] = 0.f;
+    __syncthreads();
     ViewPtrs gv2;
 #pragma unroll
     for (int v = 0; v < QG_MAX_VIEWS; ++v) gv2.p[v] = gxyv.p[v];
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void k_project_decode_bwd(
             for (int m = 0; m < kM; ++m) s_buf[w][lane][m] = 0.f;
         }
         wave_sync_lds();
-        // 3. decoder backward from the gradient in LDS; this chunk's weight gradients go to s_acc[w]
+        // 3. decoder backward from the gradient in LDS; this chunk's weight gradients are added to s_acc
         {
             BwdOps ops;
             load_bwd_ops(W1, W2, ops);
@@ -204,14 +205,12 @@ __global__ __launch_bounds__(256) void k_project_decode_bwd(
                 };
                 decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, s_t[w]);
             }
-            add_acc(acc, s_acc[w]);
+            add_acc_atomic(acc, s_acc);
         }
         wave_sync_lds();
     }
-    // block sum in a fixed wave order
     __syncthreads();
-    for (int i = threadIdx.x; i < kWidth; i += 256)
-        wpart[(size_t)blockIdx.x * kWidth + i] = ((s_acc[0][i] + s_acc[1][i]) + s_acc[2][i]) + s_acc[3][i];
+    for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_acc[i];
 }
 
 int64_t fused_fwd_blocks(int64_t n) {

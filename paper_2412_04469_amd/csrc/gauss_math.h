@@ -357,13 +357,10 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     }
     // pass 2: SH colour -> coefficients and view direction (only if some view had a record)
     if (any_col) {
+        // the coefficients are read where they live (get) when needed, so only their gradients occupy registers
         float dH[48];
-        float h[48];
 #pragma unroll
-        for (int k = 0; k < 48; ++k) {
-            dH[k] = 0.f;
-            h[k] = k < 3 * nb ? get(11 + k) : 0.f;
-        }
+        for (int k = 0; k < 48; ++k) dH[k] = 0.f;
     #pragma unroll 1
     for (int v = 0; v < vt.V; ++v) {
             const ProjDev& pd = vt.proj[v];
@@ -388,7 +385,8 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
                 dH[3 * k + 0] += gcol[0] * Y[k];
                 dH[3 * k + 1] += gcol[1] * Y[k];
                 dH[3 * k + 2] += gcol[2] * Y[k];
-                w[k] = gcol[0] * h[3 * k + 0] + gcol[1] * h[3 * k + 1] + gcol[2] * h[3 * k + 2];
+                w[k] = k < nb ? gcol[0] * get(11 + 3 * k) + gcol[1] * get(12 + 3 * k) + gcol[2] * get(13 + 3 * k)
+                              : 0.f;
             }
             float gd[3];
             sh_grad(sh_deg, d[0], d[1], d[2], w, gd);
