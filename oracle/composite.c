@@ -26,7 +26,12 @@
  * termination) and, separately, the smallest relative gap between two adjacent depths on the path
  * (an order decision, which can only differ when the two sides compute depths independently).
  * Pixels with a tiny margin may legitimately decide differently in float32 and are excluded from
- * parity comparisons by the tests.
+ * parity comparisons by the tests.  The distance of an alpha decision is reduced by an estimate of the
+ * relative error of a float32 evaluation of alpha, (1/2) eps (|A| dx^2 + 2 |B dx dy| + |C| dy^2) with
+ * eps = 8 * 2^-24: q is a sum whose terms can be far larger than q itself (a large splat far from the
+ * pixel), and float32 resolves q only to a few units in the last place of its largest term.  The
+ * distance of a termination decision is reduced by the propagated relative error of T.  For ordinary
+ * splats the reduction is negligible.
  */
 #include <math.h>
 #include <stdint.h>
@@ -42,7 +47,10 @@ typedef struct {
     double alpha;   /* clamped/unclamped alpha as used */
     double gexp;    /* exp(-q/2) */
     double raw;     /* o * exp(-q/2) before the clamp */
+    double err;     /* estimated relative error of a float32 evaluation of raw */
 } cand_t;
+
+#define F32_EVAL_EPS (8.0 / 16777216.0)
 
 static int cmp_cand(const void* a, const void* b) {
     const cand_t* x = (const cand_t*)a;
@@ -108,6 +116,8 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
                 const double dx = x - xy[2 * i], dy = y - xy[2 * i + 1];
                 const double q = conic[3 * i] * dx * dx + 2.0 * conic[3 * i + 1] * dx * dy +
                                  conic[3 * i + 2] * dy * dy;
+                const double qabs = fabs(conic[3 * i]) * dx * dx + 2.0 * fabs(conic[3 * i + 1] * dx * dy) +
+                                    fabs(conic[3 * i + 2]) * dy * dy;
                 const double ge = exp(-0.5 * q);
                 const double raw = opacity[i] * ge;
                 const double a = raw < alpha_max ? raw : alpha_max;
@@ -118,6 +128,7 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
                 cand[nc].alpha = a;
                 cand[nc].gexp = ge;
                 cand[nc].raw = raw;
+                cand[nc].err = 0.5 * F32_EVAL_EPS * qabs + F32_EVAL_EPS;
                 ++nc;
             }
             qsort(cand, (size_t)nc, sizeof(cand_t), cmp_cand);
@@ -127,22 +138,25 @@ int oracle_composite(int64_t n, const double* xy, const double* conic, const dou
             int64_t last = -1;
             int32_t cnt = 0;
             double prev_depth = NAN;
+            double terr = 0.0; /* estimated relative error of T in float32 */
             for (k = 0; k < nc; ++k) {
                 const cand_t* c = &cand[k];
                 if (!isnan(prev_depth) && c->depth != 0.0)
                     og = fmin(og, fabs(c->depth - prev_depth) / fabs(c->depth));
                 prev_depth = c->depth;
-                if (alpha_min > 0.0) mg = fmin(mg, rel(c->raw, alpha_min));
-                if (isfinite(alpha_max)) mg = fmin(mg, rel(c->raw, alpha_max));
+                if (alpha_min > 0.0) mg = fmin(mg, rel(c->raw, alpha_min) - c->err);
+                if (isfinite(alpha_max)) mg = fmin(mg, rel(c->raw, alpha_max) - c->err);
                 nk = k + 1;
                 if (c->alpha < alpha_min) { cand[k].alpha = -1.0; continue; } /* skipped */
                 const double Tn = T * (1.0 - c->alpha);
-                if (t_min > 0.0) mg = fmin(mg, rel(Tn, t_min));
+                const double tn_err = terr + c->err * c->alpha / fmax(1.0 - c->alpha, 1e-300) + F32_EVAL_EPS;
+                if (t_min > 0.0) mg = fmin(mg, rel(Tn, t_min) - tn_err);
                 if (Tn < t_min) { nk = k; break; }
                 Tk[k] = T;
                 const double* col = rgb + 3 * c->idx;
                 for (int ch = 0; ch < 3; ++ch) C[ch] += col[ch] * c->alpha * T;
                 T = Tn;
+                terr = tn_err;
                 last = c->idx;
                 ++cnt;
             }

@@ -181,3 +181,29 @@ def test_empty_scene_is_background():
     r = C.composite_image(sp, 5, 4, (0.1, 0.2, 0.3), grad_image=np.ones((3, 4, 5)))
     np.testing.assert_array_equal(r["image"][:, 0, 0], [0.1, 0.2, 0.3])
     assert (r["t_final"] == 1).all() and (r["last_id"] == -1).all()
+
+
+def test_margin_accounts_for_float32_conditioning():
+    """A decision 2e-4 (relative) above 1/255 is comparable for a small splat near the pixel, but not for a huge
+    off-screen splat whose q is a small difference of large terms: there the float32 evaluation of alpha
+    is uncertain well beyond 2e-4, and the reported margin must fall below the tests' 1e-4 threshold."""
+    import numpy as np
+    from oracle import composite as OC
+    px, py = np.array([174.5]), np.array([224.5])
+    cases = {
+        "small": (np.array([[176.0, 223.0]]), np.array([[0.5, 0.1, 0.4]])),
+        "huge_offscreen": (np.array([[-15705.49, 5733.91]]), np.array([[1.91869853e-05, 5.41075904e-05, 1.52850623e-04]])),
+    }
+    margins = {}
+    for name, (xy, conic) in cases.items():
+        dx, dy = px[0] - xy[0, 0], py[0] - xy[0, 1]
+        q = conic[0, 0] * dx * dx + 2 * conic[0, 1] * dx * dy + conic[0, 2] * dy * dy
+        o = (1.0 / 255.0) * (1.0 + 2e-4) / np.exp(-0.5 * q)  # alpha exactly 2e-4 above 1/255
+        assert 0 < o < 0.99
+        sp = {"xy": xy, "conic": conic, "opacity": np.array([o]), "rgb": np.array([[0.3, 0.5, 0.7]]),
+              "depth": np.array([1.0])}
+        out = OC.composite(sp, px, py)
+        assert out["n_contrib"][0] == 1
+        margins[name] = out["margin"][0]
+    assert abs(margins["small"] - 2e-4) < 1e-5
+    assert margins["huge_offscreen"] < 1e-4
