@@ -32,6 +32,7 @@ __device__ __forceinline__ void sh_consts(float* c) {
 
 // Y[k] for k < (deg+1)^2, zero above.
 __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
+#pragma clang fp contract(off)
     float c[10];
     sh_consts(c);
 #pragma unroll
@@ -98,6 +99,7 @@ __device__ __forceinline__ void sh_grad(int deg, float x, float y, float z, cons
 
 // Rotation matrix (row-major) of a unit quaternion (w, x, y, z).
 __device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* R) {
+#pragma clang fp contract(off)
     R[0] = 1.f - 2.f * (y * y + z * z);
     R[1] = 2.f * (x * y - w * z);
     R[2] = 2.f * (x * z + w * y);
@@ -123,6 +125,7 @@ struct Gauss {
 
 template <class Get>
 __device__ __forceinline__ void load_gauss(const Get& get, Gauss& g) {
+#pragma clang fp contract(off)
     float raw[11];
 #pragma unroll
     for (int k = 0; k < 11; ++k) raw[k] = get(k);
@@ -160,51 +163,60 @@ __device__ __forceinline__ void load_gauss(const Get& get, Gauss& g) {
 }
 
 // Per-view forward quantities.
+// The 2D part of the projection -- J R_v, Sigma' = (J R_v) Sigma (J R_v)^T + h I, its inverse -- is computed
+// in double precision: near the camera and far off-axis J grows large and Sigma' gets ill-conditioned
+// (det(Sigma') is a small difference of two large products), which float32 resolves poorly.  On this chip
+// unpacked FP64 vector arithmetic issues at the same rate as unpacked FP32.  Stored records are float32.
 struct ViewProj {
     float u[3];
-    float T0[3], T1[3];  // rows of J R_v
-    float a, b, c, det;  // Sigma' (dilated) and its determinant
+    double T0[3], T1[3];  // rows of J R_v
+    double a, b, c, det;  // Sigma' (dilated) and its determinant
     float x, y;
     bool ok;
 };
 
-__device__ __forceinline__ void sym_mul(const float* S, const float* v, float* o) {
-    o[0] = S[0] * v[0] + S[1] * v[1] + S[2] * v[2];
-    o[1] = S[1] * v[0] + S[3] * v[1] + S[4] * v[2];
-    o[2] = S[2] * v[0] + S[4] * v[1] + S[5] * v[2];
+__device__ __forceinline__ void sym_mul(const float* S, const double* v, double* o) {
+#pragma clang fp contract(off)
+    o[0] = (double)S[0] * v[0] + (double)S[1] * v[1] + (double)S[2] * v[2];
+    o[1] = (double)S[1] * v[0] + (double)S[3] * v[1] + (double)S[4] * v[2];
+    o[2] = (double)S[2] * v[0] + (double)S[4] * v[1] + (double)S[5] * v[2];
 }
 
 __device__ __forceinline__ void view_project(const Gauss& g, const CamDev& cam, float dilation, ViewProj& vp) {
+    // no multiply-add contraction: every kernel that inlines this must produce the same bits
+#pragma clang fp contract(off)
     const float* R = cam.R;
     vp.u[0] = R[0] * g.p[0] + R[1] * g.p[1] + R[2] * g.p[2] + cam.t[0];
     vp.u[1] = R[3] * g.p[0] + R[4] * g.p[1] + R[5] * g.p[2] + cam.t[1];
     vp.u[2] = R[6] * g.p[0] + R[7] * g.p[1] + R[8] * g.p[2] + cam.t[2];
     const float uz = vp.u[2];
     vp.ok = g.finite && (uz > cam.z_near);
-    const float iz = vp.ok ? rcp(uz) : 1.f;
-    const float j00 = cam.fx * iz, j02 = -cam.fx * vp.u[0] * iz * iz;
-    const float j11 = cam.fy * iz, j12 = -cam.fy * vp.u[1] * iz * iz;
+    const double iz = vp.ok ? 1.0 / (double)uz : 1.0;
+    const double j00 = (double)cam.fx * iz, j02 = -(double)cam.fx * (double)vp.u[0] * iz * iz;
+    const double j11 = (double)cam.fy * iz, j12 = -(double)cam.fy * (double)vp.u[1] * iz * iz;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        vp.T0[k] = j00 * R[k] + j02 * R[6 + k];
-        vp.T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
+        vp.T0[k] = j00 * (double)R[k] + j02 * (double)R[6 + k];
+        vp.T1[k] = j11 * (double)R[3 + k] + j12 * (double)R[6 + k];
     }
-    float s0[3], s1[3];
+    double s0[3], s1[3];
     sym_mul(g.Sig, vp.T0, s0);
     sym_mul(g.Sig, vp.T1, s1);
-    vp.a = vp.T0[0] * s0[0] + vp.T0[1] * s0[1] + vp.T0[2] * s0[2] + dilation;
+    vp.a = vp.T0[0] * s0[0] + vp.T0[1] * s0[1] + vp.T0[2] * s0[2] + (double)dilation;
     vp.b = vp.T0[0] * s1[0] + vp.T0[1] * s1[1] + vp.T0[2] * s1[2];
-    vp.c = vp.T1[0] * s1[0] + vp.T1[1] * s1[1] + vp.T1[2] * s1[2] + dilation;
+    vp.c = vp.T1[0] * s1[0] + vp.T1[1] * s1[1] + vp.T1[2] * s1[2] + (double)dilation;
     vp.det = vp.a * vp.c - vp.b * vp.b;
-    vp.ok = vp.ok && vp.det > 0.f && vp.a > 0.f;
-    vp.x = cam.fx * vp.u[0] * iz + cam.cx;
-    vp.y = cam.fy * vp.u[1] * iz + cam.cy;
+    vp.ok = vp.ok && vp.det > 0.0 && vp.a > 0.0;
+    vp.x = (float)((double)cam.fx * (double)vp.u[0] * iz + (double)cam.cx);
+    vp.y = (float)((double)cam.fy * (double)vp.u[1] * iz + (double)cam.cy);
 }
 
 // Projects one Gaussian (attribute plane k read by get(k)) into every view of vt and writes its records.
 template <class Get>
 __device__ __forceinline__ void project_gauss(int64_t i, const Get& get, int sh_deg, const ViewTable& vt, float dilation,
                                               int tile_w, int tile_h) {
+    // the forward projection rounds identically in every kernel that inlines it (no contraction)
+#pragma clang fp contract(off)
     Gauss g;
     load_gauss(get, g);
     const int nb = (sh_deg + 1) * (sh_deg + 1);
@@ -229,9 +241,9 @@ __device__ __forceinline__ void project_gauss(int64_t i, const Get& get, int sh_
         uint8_t flags = 0x80;
         if (ok) {
             flags = 0;
-            const float id = rcp(vp.det);
+            const double id = 1.0 / vp.det;
             r0 = make_float4(vp.x, vp.y, op, 0.f);
-            r1 = make_float4(vp.c * id, -vp.b * id, vp.a * id, 0.f);
+            r1 = make_float4((float)(vp.c * id), (float)(-vp.b * id), (float)(vp.a * id), 0.f);
             // colour
             float dx = g.p[0] - cam.cpos[0], dy = g.p[1] - cam.cpos[1], dz = g.p[2] - cam.cpos[2];
             float inv = rsq(dx * dx + dy * dy + dz * dz);
@@ -252,7 +264,7 @@ __device__ __forceinline__ void project_gauss(int64_t i, const Get& get, int sh_
             r2 = make_float4(col[0], col[1], col[2], 0.f);
             // support: alpha >= 1/255 <=> q <= k^2 = 2 ln(255 o); half extents k sqrt(Sigma'_xx), k sqrt(Sigma'_yy)
             const float k2 = 2.f * logf(255.f * op);
-            const float rx = sqrtf(k2 * vp.a), ry = sqrtf(k2 * vp.c);
+            const float rx = sqrtf(k2 * (float)vp.a), ry = sqrtf(k2 * (float)vp.c);
             float j0 = ceilf(vp.x - rx - 0.5f), j1 = floorf(vp.x + rx - 0.5f);
             float i0 = ceilf(vp.y - ry - 0.5f), i1 = floorf(vp.y + ry - 0.5f);
             j0 = fmaxf(j0, 0.f);
@@ -292,8 +304,8 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     Gauss g;
     load_gauss(get, g);
     const int nb = (sh_deg + 1) * (sh_deg + 1);
-    float dP[3] = {0.f, 0.f, 0.f};
-    float dSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric gradient: xx, xy, xz, yy, yz, zz
+    double dPd[3] = {0.0, 0.0, 0.0};
+    double dSigd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // symmetric gradient: xx, xy, xz, yy, yz, zz
     float dop = 0.f;
     float abs_acc = 0.f;
     bool any_col = false;
@@ -316,45 +328,50 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
             gxyv.p[v][n + i] += gy;
         }
         dop += go;
-        // conic -> Sigma' (a, b, c)
-        const float a = vp.a, b = vp.b, c = vp.c;
-        const float id = rcp(vp.det), id2 = id * id;
-        const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
-        const float gb = (2.f * b * c * gA - (a * c + b * b) * gB + 2.f * a * b * gC) * id2;
-        const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+        // conic -> Sigma' (a, b, c), in double precision (see ViewProj)
+        const double a = vp.a, b = vp.b, c = vp.c;
+        const double id = 1.0 / vp.det, id2 = id * id;
+        const double dA = gA, dB = gB, dC = gC;
+        const double ga = (-c * c * dA + b * c * dB - b * b * dC) * id2;
+        const double gb = (2.0 * b * c * dA - (a * c + b * b) * dB + 2.0 * a * b * dC) * id2;
+        const double gc = (-b * b * dA + a * b * dB - a * a * dC) * id2;
         // Sigma' = T Sigma T^T: symmetric gradient on Sigma and gradient on T rows
-        const float* T0 = vp.T0;
-        const float* T1 = vp.T1;
-        dSig[0] += ga * T0[0] * T0[0] + gb * T0[0] * T1[0] + gc * T1[0] * T1[0];
-        dSig[3] += ga * T0[1] * T0[1] + gb * T0[1] * T1[1] + gc * T1[1] * T1[1];
-        dSig[5] += ga * T0[2] * T0[2] + gb * T0[2] * T1[2] + gc * T1[2] * T1[2];
-        dSig[1] += ga * T0[0] * T0[1] + 0.5f * gb * (T0[0] * T1[1] + T1[0] * T0[1]) + gc * T1[0] * T1[1];
-        dSig[2] += ga * T0[0] * T0[2] + 0.5f * gb * (T0[0] * T1[2] + T1[0] * T0[2]) + gc * T1[0] * T1[2];
-        dSig[4] += ga * T0[1] * T0[2] + 0.5f * gb * (T0[1] * T1[2] + T1[1] * T0[2]) + gc * T1[1] * T1[2];
-        float s0[3], s1[3];
+        const double* T0 = vp.T0;
+        const double* T1 = vp.T1;
+        dSigd[0] += ga * T0[0] * T0[0] + gb * T0[0] * T1[0] + gc * T1[0] * T1[0];
+        dSigd[3] += ga * T0[1] * T0[1] + gb * T0[1] * T1[1] + gc * T1[1] * T1[1];
+        dSigd[5] += ga * T0[2] * T0[2] + gb * T0[2] * T1[2] + gc * T1[2] * T1[2];
+        dSigd[1] += ga * T0[0] * T0[1] + 0.5 * gb * (T0[0] * T1[1] + T1[0] * T0[1]) + gc * T1[0] * T1[1];
+        dSigd[2] += ga * T0[0] * T0[2] + 0.5 * gb * (T0[0] * T1[2] + T1[0] * T0[2]) + gc * T1[0] * T1[2];
+        dSigd[4] += ga * T0[1] * T0[2] + 0.5 * gb * (T0[1] * T1[2] + T1[1] * T0[2]) + gc * T1[1] * T1[2];
+        double s0[3], s1[3];
         sym_mul(g.Sig, T0, s0);
         sym_mul(g.Sig, T1, s1);
-        float dT0[3], dT1[3];
+        double dT0[3], dT1[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            dT0[k] = 2.f * ga * s0[k] + gb * s1[k];
-            dT1[k] = gb * s0[k] + 2.f * gc * s1[k];
+            dT0[k] = 2.0 * ga * s0[k] + gb * s1[k];
+            dT1[k] = gb * s0[k] + 2.0 * gc * s1[k];
         }
         const float* R = cam.R;
-        const float dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
-        const float dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
-        const float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
-        const float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
-        const float ux = vp.u[0], uy = vp.u[1], uz = vp.u[2];
-        const float iz = rcp(uz), iz2 = iz * iz, iz3 = iz2 * iz;
-        float du[3];
-        du[0] = -cam.fx * iz2 * dJ02 + gx * cam.fx * iz;
-        du[1] = -cam.fy * iz2 * dJ12 + gy * cam.fy * iz;
-        du[2] = -cam.fx * iz2 * dJ00 + 2.f * cam.fx * ux * iz3 * dJ02 - cam.fy * iz2 * dJ11 +
-                2.f * cam.fy * uy * iz3 * dJ12 - gx * cam.fx * ux * iz2 - gy * cam.fy * uy * iz2;
+        const double dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+        const double dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+        const double dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+        const double dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+        const double ux = vp.u[0], uy = vp.u[1], uz = vp.u[2];
+        const double fx = cam.fx, fy = cam.fy, gxd = gx, gyd = gy;
+        const double iz = 1.0 / uz, iz2 = iz * iz, iz3 = iz2 * iz;
+        double du[3];
+        du[0] = -fx * iz2 * dJ02 + gxd * fx * iz;
+        du[1] = -fy * iz2 * dJ12 + gyd * fy * iz;
+        du[2] = -fx * iz2 * dJ00 + 2.0 * fx * ux * iz3 * dJ02 - fy * iz2 * dJ11 + 2.0 * fy * uy * iz3 * dJ12 -
+                gxd * fx * ux * iz2 - gyd * fy * uy * iz2;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) dP[k] += R[k] * du[0] + R[3 + k] * du[1] + R[6 + k] * du[2];
+        for (int k = 0; k < 3; ++k) dPd[k] += R[k] * du[0] + R[3 + k] * du[1] + R[6 + k] * du[2];
     }
+    float dP[3] = {(float)dPd[0], (float)dPd[1], (float)dPd[2]};
+    const float dSig[6] = {(float)dSigd[0], (float)dSigd[1], (float)dSigd[2],
+                           (float)dSigd[3], (float)dSigd[4], (float)dSigd[5]};
     // pass 2: SH colour -> coefficients and view direction (only if some view had a record)
     if (any_col) {
         // the coefficients are read where they live (get) when needed, so only their gradients occupy registers
