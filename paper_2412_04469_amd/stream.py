@@ -193,7 +193,7 @@ def judge(seq: Sequence, hist, plain_recs, prop: Proposal, frames, iters=500, ch
         if probe is not fitter:
             probe.W1.copy_(W1)
             probe.W2.copy_(W2)
-        perm = np.concatenate([order.permutation(V) for _ in range(iters // V + 2)])
+        perm = np.concatenate([order.permutation(V) for _ in range(int(budget * iters) // V + 2)])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         a_eq10 = gi(A, gts_prev, gts).clone()
