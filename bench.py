@@ -82,6 +82,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-pixels", type=int, default=8192)
     p.add_argument("--tile", default="16x16", choices=["8x8", "16x16", "32x8"])
+    p.add_argument("--batch", type=int, default=0, choices=[0, 32, 64, 128], help="blend LDS batch depth")
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-view step")
     p.add_argument("--no-frame", action="store_true", help="skip the sec/frame measurement")
     p.add_argument("--batched-steps", type=int, default=20)
@@ -351,7 +352,7 @@ def main():
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
     wl = synth.workload_fit(n=args.n)
-    cfg = FitConfig(tile=tuple(int(x) for x in args.tile.split("x")))
+    cfg = FitConfig(tile=tuple(int(x) for x in args.tile.split("x")), batch=args.batch)
     dev = torch.device("cuda")
     prev = torch.as_tensor(wl.scene.planes()).to(dev)
     target = torch.as_tensor(wl.target_scene.planes()).to(dev)

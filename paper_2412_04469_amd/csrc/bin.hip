@@ -135,6 +135,21 @@ __device__ __forceinline__ T block_excl_scan(T x, T* s_w, T* total) {
     return wbase + inc - x;
 }
 
+// Counts digit d of this lane into the LDS histogram h.  When every active lane of the wave holds the same
+// digit (the high digits of neighbouring keys usually agree) one lane adds the wave's count, instead of 64
+// atomics on one address.
+__device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d) {
+    const uint64_t active = __ballot(true);
+    const uint32_t first = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t same = __ballot(d == first);
+    if (same == active) {
+        if (__lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1))
+            atomicAdd(&h[first], (uint32_t)__popcll(active));
+    } else {
+        atomicAdd(&h[d], 1u);
+    }
+}
+
 // Adds this block's LDS digit histograms of `npass` passes (s_h[p][d]) into copy (block % 16) of the
 // global ones.
 __device__ __forceinline__ void flush_hists(const uint32_t (*s_h)[kRadix], int npass, SortCtl* ctl) {
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(int64_t n, ViewTable vt, 
         keys[item] = key;
         vals[item] = (uint32_t)item;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) atomicAdd(&s_h[q][(key >> (8 * q)) & 0xFFu], 1u);
+        for (int q = 0; q < 4; ++q) hist_add(s_h[q], (key >> (8 * q)) & 0xFFu);
     }
     __syncthreads();
     flush_hists(s_h, 4, ctl);
@@ -372,17 +387,20 @@ __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTabl
     for (uint64_t chunk = blockIdx.x; chunk * kEmitPer < P; chunk += gridDim.x) {
         const uint64_t base = chunk * kEmitPer;
         __syncthreads();  // the previous chunk is done with s_off
-        if (threadIdx.x == 0) {
-            // last k with offs[k] <= base
+        if (threadIdx.x < kWave) {
+            // last k with offs[k] <= base (offs is non-decreasing, offs[0] = 0): 64 probes per round, so the
+            // range shrinks 64-fold per dependent load
+            const int lane = (int)threadIdx.x;
             int64_t lo = 0, hi = items - 1;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (offs[mid] <= base)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+            while (hi > lo) {
+                const int64_t step = (hi - lo + kWave - 1) / kWave;
+                const int64_t pos = lo + (int64_t)(lane + 1) * step;
+                const bool le = pos <= hi && offs[pos] <= base;
+                const int cnt = (int)__popcll(__ballot(le));
+                lo += (int64_t)cnt * step;
+                hi = std::min<int64_t>(hi, lo + step - 1);
             }
-            s_k0 = lo;
+            if (lane == 0) s_k0 = lo;
         }
         __syncthreads();
         const int64_t k0 = s_k0;
@@ -412,7 +430,7 @@ __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTabl
             const uint32_t key = vt.cam[v].tile_off + ty * (uint32_t)vt.cam[v].grid_w + tx;
             tkeys[p] = key;
             tvals[p] = (uint32_t)i;
-            for (int q = 0; q < tpasses; ++q) atomicAdd(&s_h[q][(key >> (8 * q)) & 0xFFu], 1u);
+            for (int q = 0; q < tpasses; ++q) hist_add(s_h[q], (key >> (8 * q)) & 0xFFu);
         }
     }
     __syncthreads();
@@ -597,7 +615,7 @@ extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
     {
         QG_TIMED("bin_emit", s);
-        k_emit<<<(unsigned)std::min<int64_t>(ceil_div(capacity, kEmitPer), 2 * kHistBlocks), 256, 0, s>>>(
+        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(
             items, n, vt, sorted_items, w.offs,
                                                                       w.sort_count, tpasses, w.tkA, vbuf0,
                                                                       w.ctl_tile);

@@ -38,6 +38,7 @@ class FitConfig:
     latent_dim: int = 8
     hidden: int = 32
     tile: tuple = (16, 16)
+    batch: int = 0  # blend LDS batch depth (0 = 64)
     sh_degree: int = 3
     dilation: float = 0.3
     bg: tuple = (0.0, 0.0, 0.0)
@@ -146,7 +147,7 @@ class FrameFitter(ResidualState):
         self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
         self.fused = True
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
-                               bg=cfg.bg, device=dev, capacity=capacity)
+                               bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch)
         self.qcams = [qg.camera_array([c]) for c in self.cams]
         img = self.rast.images[0]
         self.count = img.numel()
