@@ -255,15 +255,20 @@ qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_attrs, cons
 
 /*
  * qg_render_decode_bwd: qg_render_bwd followed by qg_decode_residuals_bwd without materialising
- * dL/d attrs: the blend adjoint (Eq. 2), then per Gaussian the decode (recomputed on the matrix cores),
- * the projection adjoint (Eq. 1) and the decoder / gate backward (Eq. 5-8).  Gradient outputs as in
- * qg_decode_residuals_bwd (+=), plus grad_xy_abs / grad_xy as in qg_render_bwd.  The other arguments
- * must be those of the qg_decode_project / qg_bin / qg_render_fwd calls of this step.
- * ws: qg_render_decode_bwd_workspace_size(n, V) bytes.  Results are bit-identical to the two-call path.
+ * dL/d attrs: the blend adjoint (Eq. 2), then per Gaussian the decoded attributes, the projection adjoint
+ * (Eq. 1) and the decoder / gate backward (Eq. 5-8).  Gradient outputs as in qg_decode_residuals_bwd (+=),
+ * plus grad_xy_abs / grad_xy as in qg_render_bwd.  The other arguments must be those of the
+ * qg_decode_project / qg_bin / qg_render_fwd calls of this step.
+ *   attrs: [59][ld] the attributes qg_decode_project wrote to attrs_out in this step (read instead of
+ *          decoding the residuals again; prev_attrs may then be NULL), or NULL: the residuals are decoded
+ *          again from prev_attrs on the matrix cores.  Either way the results are the same.
+ * ws: qg_render_decode_bwd_workspace_size(n, V) bytes (about 48 V + 32 bytes per Gaussian).  Results equal
+ * the two-call path's up to the summation order of float atomics and of the weight-gradient partials.
  */
 size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V);
-qg_status qg_render_decode_bwd(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L,
-                               const float* W1, const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
+qg_status qg_render_decode_bwd(int64_t n, int64_t ld, const float* prev_attrs, const float* attrs,
+                               const float* latents, int32_t L, const float* W1, const float* W2, int32_t Hd,
+                               int32_t M, const float* pos_pre,
                                const float* gate_logit, float gamma0, float gamma1, float tau, float lambda_reg,
                                int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling,
                                float dilation, const qg_projected* proj, const uint32_t* vals,

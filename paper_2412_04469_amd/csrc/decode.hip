@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(int64_t n, int64_t ld, const
             auto dlat = [&](int k, float v) {
                 if (vA) g_lat[(int64_t)k * ld + gA] += v;
             };
-            decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, s_t[w]);
+            decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, TransposeBuf{s_t[w]});
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -150,20 +150,21 @@ __global__ __launch_bounds__(256) void k_decode_bwd(int64_t n, int64_t ld, const
 
 // out[o] += sum over blocks b of part[b][o], in a fixed order: 32 outputs per block, 8 interleaved chains
 // (b = c, c + 8, ...) per output, combined in chain order.
-__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int64_t nblocks,
-                                                      float* __restrict__ gW1, float* __restrict__ gW2) {
-    __shared__ float s[8][32];
-    const int o = blockIdx.x * 32 + threadIdx.x % 32;
-    const int c = threadIdx.x / 32;
+// Sum of the per-block partials, deterministic: a block owns 16 columns; its 64 row groups each sum every
+// 64th partial, then one thread per column adds the 64 group sums in order.
+__global__ __launch_bounds__(1024) void k_reduce_parts(const float* __restrict__ part, int64_t nblocks,
+                                                       float* __restrict__ gW1, float* __restrict__ gW2) {
+    __shared__ float s[64][17];
+    const int col = threadIdx.x % 16, rg = threadIdx.x / 16;
+    const int o = blockIdx.x * 16 + col;
     float acc = 0.f;
-#pragma unroll 8
-    for (int64_t b = c; b < nblocks; b += 8) acc += part[(size_t)b * kWidth + o];
-    s[c][threadIdx.x % 32] = acc;
+#pragma unroll 4
+    for (int64_t b = rg; b < nblocks; b += 64) acc += part[(size_t)b * kWidth + o];
+    s[rg][col] = acc;
     __syncthreads();
-    if (c == 0) {
+    if (threadIdx.x < 16) {
         float t = 0.f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) t += s[k][threadIdx.x];
+        for (int k = 0; k < 64; ++k) t += s[k][col];
         if (o < kH * kL)
             gW1[o] += t;
         else
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
 
 qg_status decode_reduce_launch(const float* part, int64_t nblocks, float* gW1, float* gW2, hipStream_t s) {
     QG_TIMED("decode_wreduce", s);
-    k_reduce_parts<<<(unsigned)(kWidth / 32), 256, 0, s>>>(part, nblocks, gW1, gW2);
+    k_reduce_parts<<<(unsigned)(kWidth / 16), 1024, 0, s>>>(part, nblocks, gW1, gW2);
     QG_LAUNCH_CHECK("decode weight reduce");
     return QG_OK;
 }

@@ -113,6 +113,12 @@ __device__ __forceinline__ void load_bwd_ops(const float* __restrict__ W1, const
     for (int ks = 0; ks < 8; ++ks) o.aW1T[ks] = c < kL ? W1[(4 * ks + q) * kL + c] : 0.f;
 }
 
+// A 16 x 33 LDS array as the transpose buffer of decode_group_bwd.
+struct TransposeBuf {
+    float (*t)[33];
+    __device__ __forceinline__ float& operator()(int r, int j) const { return t[r][j]; }
+};
+
 struct BwdAcc {
     f4 W2[kMB][2];  // dW2[16mb + 4q + i][16jb + c]
     f4 W1[2];       // dW1^T[4q + i][16jb + c] (rows < 8 used)
@@ -130,10 +136,11 @@ __device__ __forceinline__ void zero_acc(BwdAcc& a) {
 //   drA(m):    dL/dr_m of Gaussian c                         (A of dH = dR W2), m = 4ks + q
 //   drN(m, i): dL/dr_m of Gaussian 4q + i                    (A of dW2 += dR^T H), m = 16mb + c (0 if >= 56)
 //   dlat(k, v):receives dL/dlatent_k of Gaussian c for k = 4q + i < 8 (lanes q < 2)
-// tbuf: 16 x 33 floats of LDS owned by this wave (transpose of dpre).
-template <class LatA, class LatN, class DrA, class DrN, class DLat>
+// tb(r, j): a float& to LDS owned by this wave, r < 16, j < 32 (transpose of dpre); it is written only after
+// every drA/drN/latN read of the group, so it may alias their storage.
+template <class LatA, class LatN, class DrA, class DrN, class DLat, class TB>
 __device__ __forceinline__ void decode_group_bwd(const BwdOps& o, BwdAcc& acc, const LatA& latA, const LatN& latN,
-                                                 const DrA& drA, const DrN& drN, const DLat& dlat, float (*tbuf)[33]) {
+                                                 const DrA& drA, const DrN& drN, const DLat& dlat, const TB& tb) {
     const int lane = __lane_id(), q = lane / 16, c = lane % 16;
     // pre (layout N)
     f4 pre[2];
@@ -180,13 +187,13 @@ __device__ __forceinline__ void decode_group_bwd(const BwdOps& o, BwdAcc& acc, c
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) tbuf[4 * q + i][16 * jb + c] = dP[jb][i];
+        for (int i = 0; i < 4; ++i) tb(4 * q + i, 16 * jb + c) = dP[jb][i];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     f4 dL = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) dL = mfma(o.aW1T[ks], tbuf[c][4 * ks + q], dL);
+    for (int ks = 0; ks < 8; ++ks) dL = mfma(o.aW1T[ks], tb(c, 4 * ks + q), dL);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

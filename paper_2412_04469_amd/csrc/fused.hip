@@ -103,18 +103,77 @@ struct ViewPtrsB {
     float* p[QG_MAX_VIEWS];
 };
 
+// ---- backward: staging through LDS DMA ----------------------------------------------------------
+// The backward keeps a chunk's per-Gaussian inputs in LDS, plane by plane (64 floats a plane).  They are
+// copied there by global->LDS loads, which take no registers, so every plane of a chunk is in flight at once
+// and the chunk waits on memory once.  A plane is stored rotated by a multiple of 16 slots (slot
+// (g + rot) % 64 holds Gaussian g of the chunk): the decoder's column accesses, 16 Gaussians x 4 planes per
+// instruction, then spread over the banks instead of landing four deep on one.
+__device__ __forceinline__ int rot_at(int m) { return 16 * ((m + (m >> 2)) & 3); }
+__device__ __forceinline__ int slot_at(int m, int g) { return m * kChunk + ((g + rot_at(m)) & (kChunk - 1)); }
+__device__ __forceinline__ int slot_lat(int k, int g) { return k * kChunk + ((g + 16 * (k & 3)) & (kChunk - 1)); }
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// The lane index, opaque to the optimiser: the LDS addresses derived from it are formed in the phase that uses
+// them instead of all at once at the top of the kernel.
+__device__ __forceinline__ int lane_here() {
+    int l = __lane_id();
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
+// Plane `plane` of the chunk's 64 Gaussians from src ([planes][ld]) into dst[0..63], rotated by rot: lane l
+// fetches Gaussian base + ((l - rot) mod 64), at a uniform address plus a lane offset.  In the last, partial
+// chunk (kFull == false) lanes past the last Gaussian fetch Gaussian n - 1 instead (their results are never
+// stored, but their values reach the decoder's products, so they must be finite data).
+template <bool kFull>
+__device__ __forceinline__ void stage_plane(const float* __restrict__ src, int64_t ld, int plane, int64_t base,
+                                            int64_t n, int lane, int rot, float* dst) {
+    const uint32_t off = (uint32_t)(lane - rot) & (kChunk - 1);
+    const float* row = src + (int64_t)plane * ld + base;
+    const float* p = kFull ? row + off : row + (base + off < n ? off : n - 1 - base);
+    __builtin_amdgcn_global_load_lds(p, (lds_ptr)dst, 4, 0, 0);
+}
+
+// Every input plane of a chunk: attribute planes 3..58 (of prev, or of the decoded attributes), the latents,
+// the incoming g_lp and g_ga.
+template <bool kFull>
+__device__ __forceinline__ void stage_chunk(const float* __restrict__ prev, const float* __restrict__ lat,
+                                            const float* g_lp, const float* g_ga, int64_t ld, int64_t base, int64_t n,
+                                            float* at, float* sl, float* so) {
+    const int l0 = lane_here();
+#pragma unroll
+    for (int m = 0; m < kM; ++m) stage_plane<kFull>(prev, ld, 3 + m, base, n, l0, rot_at(m), at + m * kChunk);
+#pragma unroll
+    for (int k = 0; k < kL; ++k) stage_plane<kFull>(lat, ld, k, base, n, l0, 16 * (k & 3), sl + k * kChunk);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) stage_plane<kFull>(g_lp, ld, k, base, n, l0, 0, so + k * kChunk);
+    stage_plane<kFull>(g_ga, ld, 0, base, n, l0, 0, so + 3 * kChunk);
+}
+
+// kDecoded: `prev` holds the decoded attributes of this step (prev + residual, positions with the gate
+// applied), so the residuals are not decoded again.
+template <bool kDecoded>
 __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     int64_t n, int64_t ld, const float* __restrict__ prev, const float* __restrict__ lat, const float* __restrict__ W1,
     const float* __restrict__ W2, const float* __restrict__ lp, const float* __restrict__ ga, float g0, float g1,
     float tau, float reg_shift, float reg_scale, int sh_deg, ViewTable vt, float dilation,
     const float* __restrict__ grad2d, int64_t stride, float* __restrict__ gxy_abs, ViewPtrsB gxyv,
     float* __restrict__ g_lat, float* __restrict__ g_lp, float* __restrict__ g_ga, float* __restrict__ wpart) {
-    // s_buf[w][Gaussian][m]: attribute plane 3 + m (prev, then + residual) while projecting, then dL/dr_m (the
-    // same slot, written only after its last read)
-    __shared__ float s_buf[4][kChunk][kM + 1];
-    __shared__ float s_t[4][16][33];
+    // per wave:
+    //   s_at:  attribute planes 3..58 (prev + residual while projecting), then dL/dr in the same slots
+    //   s_lat: the latents as stored, then dL/dlatent
+    //   s_old: the incoming g_lp (3 planes) and g_ga (1 plane), slot = Gaussian
+    __shared__ float s_at[4][kM * kChunk];
+    __shared__ float s_lat[4][kL * kChunk];
+    __shared__ float s_old[4][4 * kChunk];
     __shared__ float s_acc[kWidth];  // the block's decoder weight-gradient sums (LDS float atomics)
-    const int lane = __lane_id(), w = threadIdx.x / 64, q = lane / 16, c = lane % 16;
+    const int lane = __lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    float* const at = s_at[w];
+    float* const sl = s_lat[w];
+    float* const so = s_old[w];
     for (int i = threadIdx.x; i < kWidth; i += 256) s_acc[i] = 0.f;
     __syncthreads();
     ViewPtrs gv2;
@@ -122,14 +181,18 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     for (int v = 0; v < QG_MAX_VIEWS; ++v) gv2.p[v] = gxyv.p[v];
     const int64_t nchunks = ceil_div(n, kChunk);
     const uint32_t ld32 = (uint32_t)ld;
-    for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+    // one chunk per wave: straight-line code, so nothing is kept in registers across chunks
+    const int64_t ch = (int64_t)blockIdx.x * 4 + w;
+    if (ch < nchunks) {
         const int64_t base = ch * kChunk;
         const int64_t g = base + lane;
         const bool gv = g < n;
         const uint32_t g32 = (uint32_t)g;
-        // 0. stage prev planes 3..58 (lane = Gaussian, coalesced rows); positions and gate in registers
-#pragma unroll 8
-        for (int m = 0; m < kM; ++m) s_buf[w][lane][m] = gv ? prev[pidx(3 + m, ld32, g32)] : 0.f;
+        // 0. stage the chunk
+        if (base + kChunk <= n)
+            stage_chunk<true>(prev, lat, g_lp, g_ga, ld, base, n, at, sl, so);
+        else
+            stage_chunk<false>(prev, lat, g_lp, g_ga, ld, base, n, at, sl, so);
         float pos[3], lpv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -137,77 +200,88 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
             lpv[k] = gv ? lp[pidx(k, ld32, g32)] : 0.f;
         }
         const float a = gv ? ga[g] : 0.f;
+        __builtin_amdgcn_s_waitcnt(0);
         wave_sync_lds();
         // 1. add the decoded residuals in place
-        {
+        if (!kDecoded) {
+            const int c1 = lane_here() % 16;
             FwdOps ops;
             load_fwd_ops(W1, W2, ops);
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
-                const int64_t gs = base + 16 * sg + c;
-                const bool vs = gs < n;
-                auto latf = [&](int k) { return vs ? rintf(lat[pidx(k, ld32, (uint32_t)gs)]) : 0.f; };
-                auto outf = [&](int m, float v) { s_buf[w][16 * sg + c][m] = s_buf[w][16 * sg + c][m] + v; };
+                const int gs = 16 * sg + c1;
+                auto latf = [&](int k) { return rintf(sl[slot_lat(k, gs)]); };
+                auto outf = [&](int m, float v) { at[slot_at(m, gs)] += v; };
                 decode_group_fwd(ops, latf, outf);
             }
         }
         wave_sync_lds();
         // 2. projection adjoint per Gaussian; position and gate gradients
         if (gv) {
+            const int l2 = lane_here();
             float gh, gt;
             const float gg = gate_of(a, g0, g1, tau, &gh, &gt);
+            if (!kDecoded) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) pos[k] = __builtin_fmaf(gg, lpv[k], pos[k]);
-            float* rs = s_buf[w][lane];
-            auto get = [&](int k) { return k < 3 ? pos[k] : rs[k - 3]; };
+                for (int k = 0; k < 3; ++k) pos[k] = __builtin_fmaf(gg, lpv[k], pos[k]);
+            }
+            auto get = [&](int k) { return k < 3 ? pos[k] : at[slot_at(k - 3, l2)]; };
             float dpos[3] = {0.f, 0.f, 0.f};
             auto put = [&](int k, float v) {
                 if (k < 3)
                     dpos[k] = v;
                 else
-                    rs[k - 3] = v;
+                    at[slot_at(k - 3, l2)] = v;
             };
-            project_bwd_gauss(n, g, get, put, sh_deg, vt, dilation, grad2d, stride, gxy_abs, gv2);
+            project_bwd_gauss<true>(n, g, get, put, sh_deg, vt, dilation, grad2d, stride, gxy_abs, gv2);
             const int nb = (sh_deg + 1) * (sh_deg + 1);
-            for (int m = 8 + 3 * nb; m < kM; ++m) rs[m] = 0.f;  // SH planes above the degree
+            for (int m = 8 + 3 * nb; m < kM; ++m) at[slot_at(m, l2)] = 0.f;  // SH planes above the degree
             float dot = 0.f;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 dot = __builtin_fmaf(dpos[k], lpv[k], dot);
-                g_lp[pidx(k, ld32, g32)] += gg * dpos[k];
+                g_lp[pidx(k, ld32, g32)] = so[k * kChunk + l2] + gg * dpos[k];
             }
             float da = (gt > 0.f && gt < 1.f) ? dot * (g1 - g0) * gh * (1.f - gh) / tau : 0.f;
             const float pr = sigm(a - reg_shift);
-            g_ga[g] += __builtin_fmaf(reg_scale, pr * (1.f - pr), da);
+            g_ga[g] = so[3 * kChunk + l2] + __builtin_fmaf(reg_scale, pr * (1.f - pr), da);
         } else {
-            for (int m = 0; m < kM; ++m) s_buf[w][lane][m] = 0.f;
+            const int l2 = lane_here();
+#pragma unroll
+            for (int m = 0; m < kM; ++m) at[slot_at(m, l2)] = 0.f;
         }
         wave_sync_lds();
-        // 3. decoder backward from the gradient in LDS; this chunk's weight gradients are added to s_acc
+        // 3. decoder backward from the gradient in LDS; this chunk's weight gradients are added to s_acc and
+        //    dL/dlatent replaces the latents in s_lat
+        float glat[kL];
+#pragma unroll
+        for (int k = 0; k < kL; ++k) glat[k] = gv ? g_lat[pidx(k, ld32, g32)] : 0.f;
         {
+            const int l3 = lane_here(), q3 = l3 / 16, c3 = l3 % 16;
             BwdOps ops;
             load_bwd_ops(W1, W2, ops);
             BwdAcc acc;
             zero_acc(acc);
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
-                const int64_t gA = base + 16 * sg + c;
-                const bool vA = gA < n;
-                auto latA = [&](int k) { return vA ? rintf(lat[pidx(k, ld32, (uint32_t)gA)]) : 0.f; };
-                auto latN = [&](int k, int i) {
-                    const int64_t gN = base + 16 * sg + 4 * q + i;
-                    return gN < n ? rintf(lat[pidx(k, ld32, (uint32_t)gN)]) : 0.f;
-                };
-                auto drA = [&](int m) { return s_buf[w][16 * sg + c][m]; };
-                auto drN = [&](int m, int i) { return m < kM ? s_buf[w][16 * sg + 4 * q + i][m] : 0.f; };
-                auto dlat = [&](int k, float v) {
-                    if (vA) g_lat[pidx(k, ld32, (uint32_t)gA)] += v;
-                };
-                decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, s_t[w]);
+                const int gA = 16 * sg + c3;
+                auto latA = [&](int k) { return rintf(sl[slot_lat(k, gA)]); };
+                auto latN = [&](int k, int i) { return rintf(sl[slot_lat(k, 16 * sg + 4 * q3 + i)]); };
+                auto drA = [&](int m) { return at[slot_at(m, gA)]; };
+                auto drN = [&](int m, int i) { return m < kM ? at[slot_at(m, 16 * sg + 4 * q3 + i)] : 0.f; };
+                auto dlat = [&](int k, float v) { sl[slot_lat(k, gA)] = v; };
+                // transpose buffer: planes 0..31 of this group's Gaussians, dead once the group's reads are done
+                auto tb = [&](int r, int j) -> float& { return at[slot_at(j, 16 * sg + r)]; };
+                decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, tb);
             }
             add_acc_atomic(acc, s_acc);
         }
         wave_sync_lds();
+        if (gv) {
+            const int l4 = lane_here();
+#pragma unroll
+            for (int k = 0; k < kL; ++k) g_lat[pidx(k, ld32, g32)] = glat[k] + sl[slot_lat(k, l4)];
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_acc[i];
@@ -216,9 +290,7 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
 int64_t fused_fwd_blocks(int64_t n) {
     return std::min<int64_t>(std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)), 1024);
 }
-int64_t fused_bwd_blocks(int64_t n) {
-    return std::min<int64_t>(std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)), 512);
-}
+int64_t fused_bwd_blocks(int64_t n) { return std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)); }
 
 qg_status check_dec(int32_t L, int32_t Hd, int32_t M, float g0, float g1, float tau) {
     QG_REQUIRE(L >= 1 && L <= 16, "L=%d outside [1, 16]", L);
@@ -277,7 +349,8 @@ extern "C" size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V) {
 }
 
 extern "C" qg_status qg_render_decode_bwd(
-    int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L, const float* W1, const float* W2,
+    int64_t n, int64_t ld, const float* prev_attrs, const float* attrs, const float* latents, int32_t L,
+    const float* W1, const float* W2,
     int32_t Hd, int32_t M, const float* pos_pre, const float* gate_logit, float gamma0, float gamma1, float tau,
     float lambda_reg, int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling, float dilation,
     const qg_projected* proj, const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
@@ -294,8 +367,8 @@ extern "C" qg_status qg_render_decode_bwd(
     ViewTable vt;
     if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
     QG_REQUIRE(tile_ranges && bg && T_final && last && grad_image, "a required pointer is NULL");
-    QG_REQUIRE(n == 0 || (prev_attrs && latents && W1 && W2 && pos_pre && gate_logit && grad_latents && grad_W1 &&
-                          grad_W2 && grad_pos_pre && grad_gate_logit),
+    QG_REQUIRE(n == 0 || ((prev_attrs || attrs) && latents && W1 && W2 && pos_pre && gate_logit && grad_latents &&
+                          grad_W1 && grad_W2 && grad_pos_pre && grad_gate_logit),
                "a required pointer is NULL");
     for (int v = 0; v < V; ++v)
         QG_REQUIRE(T_final[v] && last[v] && grad_image[v], "view %d: an input pointer is NULL", v);
@@ -318,10 +391,15 @@ extern "C" qg_status qg_render_decode_bwd(
     const float reg_scale = lambda_reg / (float)n;
     {
         QG_TIMED("project_decode_bwd", s);
-        k_project_decode_bwd<<<(unsigned)nb, 256, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit,
-                                                          gamma0, gamma1, tau, shift, reg_scale, sh_degree, vt,
-                                                          dilation, grad2d, stride, grad_xy_abs, gv, grad_latents,
-                                                          grad_pos_pre, grad_gate_logit, wpart);
+        if (attrs)
+            k_project_decode_bwd<true><<<(unsigned)nb, 256, 0, s>>>(
+                n, ld, attrs, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau, shift, reg_scale, sh_degree, vt,
+                dilation, grad2d, stride, grad_xy_abs, gv, grad_latents, grad_pos_pre, grad_gate_logit, wpart);
+        else
+            k_project_decode_bwd<false><<<(unsigned)nb, 256, 0, s>>>(
+                n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau, shift, reg_scale,
+                sh_degree, vt, dilation, grad2d, stride, grad_xy_abs, gv, grad_latents, grad_pos_pre, grad_gate_logit,
+                wpart);
     }
     QG_LAUNCH_CHECK("qg_render_decode_bwd");
     return decode_reduce_launch(wpart, nb, grad_W1, grad_W2, s);

@@ -296,7 +296,11 @@ struct ViewPtrs {
 // dr, dg, db (stride 12).  Attribute plane k is read by get(k); the gradient of plane k is handed to
 // put(k, value) exactly once for planes 0..10 and the planes 11 .. 11+3(deg+1)^2-1, after every get of
 // that plane.
-template <class Get, class Put>
+// kShSlots: get and put address one storage slot per plane (put overwrites what get returns).  The SH
+// coefficient gradients are then summed over the views in those slots, after a first sweep over the views
+// that has read the coefficients for the view-direction gradient, instead of in 48 registers; the sums are
+// formed in the same order, so the results are the same.
+template <bool kShSlots = false, class Get, class Put>
 __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Get& get, const Put& put, int sh_deg,
                                                   const ViewTable& vt, float dilation,
                                                   const float* __restrict__ grad2d, int64_t g2d_view_stride,
@@ -313,10 +317,11 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
 #pragma unroll 1
     for (int v = 0; v < vt.V; ++v) {
         const ProjDev& pd = vt.proj[v];
-        const uint8_t flags = pd.flags[i];
-        if (flags & 0x80) continue;
+        // the record is read with the flags (it exists, zero or not, for every Gaussian): one round trip
         const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
         const float4 g0 = gr[0], g1 = gr[1];
+        const uint8_t flags = pd.flags[i];
+        if (flags & 0x80) continue;
         const float gx = g0.x, gy = g0.y, gA = g0.z, gB = g0.w, gC = g1.x, go = g1.y;
         any_col = true;
         const CamDev& cam = vt.cam[v];
@@ -373,7 +378,64 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     const float dSig[6] = {(float)dSigd[0], (float)dSigd[1], (float)dSigd[2],
                            (float)dSigd[3], (float)dSigd[4], (float)dSigd[5]};
     // pass 2: SH colour -> coefficients and view direction (only if some view had a record)
-    if (any_col) {
+    if (kShSlots && any_col) {
+        // sweep 1: view-direction gradient, reading the coefficients
+#pragma unroll 1
+        for (int v = 0; v < vt.V; ++v) {
+            const ProjDev& pd = vt.proj[v];
+            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
+            const float4 g1 = gr[1], g2 = gr[2];
+            const uint8_t flags = pd.flags[i];
+            if (flags & 0x80) continue;
+            float gcol[3] = {g1.z, g1.w, g2.x};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                if (flags & (1u << ch)) gcol[ch] = 0.f;
+            if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+            const CamDev& cam = vt.cam[v];
+            float vx = g.p[0] - cam.cpos[0], vy = g.p[1] - cam.cpos[1], vz = g.p[2] - cam.cpos[2];
+            float inv = rsq(vx * vx + vy * vy + vz * vz);
+            float d[3] = {vx * inv, vy * inv, vz * inv};
+            float w[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                w[k] = k < nb ? gcol[0] * get(11 + 3 * k) + gcol[1] * get(12 + 3 * k) + gcol[2] * get(13 + 3 * k)
+                              : 0.f;
+            float gd[3];
+            sh_grad(sh_deg, d[0], d[1], d[2], w, gd);
+            const float dotp = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dP[k] += (gd[k] - d[k] * dotp) * inv;
+        }
+        // sweep 2: the coefficients are dead; their slots sum gcol * Y over the views
+#pragma unroll
+        for (int k = 0; k < 48; ++k)
+            if (k < 3 * nb) put(11 + k, 0.f);
+#pragma unroll 1
+        for (int v = 0; v < vt.V; ++v) {
+            const ProjDev& pd = vt.proj[v];
+            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
+            const float4 g1 = gr[1], g2 = gr[2];
+            const uint8_t flags = pd.flags[i];
+            if (flags & 0x80) continue;
+            float gcol[3] = {g1.z, g1.w, g2.x};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                if (flags & (1u << ch)) gcol[ch] = 0.f;
+            if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+            const CamDev& cam = vt.cam[v];
+            float vx = g.p[0] - cam.cpos[0], vy = g.p[1] - cam.cpos[1], vz = g.p[2] - cam.cpos[2];
+            float inv = rsq(vx * vx + vy * vy + vz * vz);
+            float Y[16];
+            sh_basis(sh_deg, vx * inv, vy * inv, vz * inv, Y);
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < nb) {
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) put(11 + 3 * k + ch, get(11 + 3 * k + ch) + gcol[ch] * Y[k]);
+                }
+        }
+    } else if (any_col) {
         // the coefficients are read where they live (get) when needed, so only their gradients occupy registers
         float dH[48];
 #pragma unroll

@@ -171,7 +171,7 @@ class FrameFitter(ResidualState):
             r.qcams = self.qcams[v]
             qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                  self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
-                                 r.t_proj, None, self.gate, None, stream)
+                                 r.t_proj, self.attrs, self.gate, None, stream)
             r.bin(stream)
             r.render(stream)
         else:
@@ -184,7 +184,8 @@ class FrameFitter(ResidualState):
                                     self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
                                     r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
                                     [self.grad_img], self.grads["lat"], self.grads["W1"], self.grads["W2"],
-                                    self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream)
+                                    self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream,
+                                    attrs=self.attrs)
         else:
             qg.qg_zero(self.grad_attrs, self.grad_attrs.numel() * 4, stream)
             r.backward(self.attrs, [self.grad_img], self.grad_attrs, stream=stream)
@@ -287,7 +288,7 @@ class BatchedFitter(ResidualState):
         views = self.groups[gi]
         qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                              self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
-                             r.t_proj, None, self.gate, None, stream)
+                             r.t_proj, self.attrs, self.gate, None, stream)
         r.bin(stream)
         r.render(stream)
         w = 1.0 / len(views)
@@ -298,7 +299,8 @@ class BatchedFitter(ResidualState):
                                 self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
                                 r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
                                 self.t_gimg[gi], self.grads["lat"], self.grads["W1"], self.grads["W2"],
-                                self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream)
+                                self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream,
+                                attrs=self.attrs)
         b1, b2 = c.betas
         qg.qg_adam_multi(self.adam_segs, b1, b2, c.eps, 0, True, stream, step_state=self.step_state)
 

@@ -93,7 +93,7 @@ def lib():
             "qg_decode_project": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, i32, CAM, i32, qg_tiling,
                                    f32, PRJ, P, P, P, P], i32),
             "qg_render_decode_bwd_workspace_size": ([i64, i32], sz),
-            "qg_render_decode_bwd": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, f32, i32, CAM, i32,
+            "qg_render_decode_bwd": ([i64, i64, P, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, f32, i32, CAM, i32,
                                       qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P], i32),
             "qg_timing_report": ([ctypes.c_char_p, i64], i64),
             "qg_schedule_words": ([i64], i64),
@@ -353,12 +353,13 @@ def qg_render_decode_bwd_workspace_size(n, V):
 def qg_render_decode_bwd(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
                          lambda_reg, sh_degree, cams, tile, dilation, proj, vals, tile_ranges, bg, T_final, last,
                          grad_image, grad_latents, grad_W1, grad_W2, grad_pos_pre, grad_gate_logit, grad_xy_abs,
-                         grad_xy, ws, ws_bytes, stream=None):
+                         grad_xy, ws, ws_bytes, stream=None, attrs=None):
     ca = camera_array(cams)
     pa = projected_array(proj)
     bga = (ctypes.c_float * 3)(*[float(b) for b in bg])
     gxy = None if grad_xy is None else _ptr_array(grad_xy)
-    _check(lib().qg_render_decode_bwd(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), int(L), _ptr(W1), _ptr(W2),
+    _check(lib().qg_render_decode_bwd(int(n), int(ld), _ptr(prev_attrs), _ptr(attrs), _ptr(latents), int(L), _ptr(W1),
+                                      _ptr(W2),
                                       int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
                                       float(tau), float(lambda_reg), int(sh_degree), ca, len(ca), tile,
                                       float(dilation), pa, _ptr(vals), _ptr(tile_ranges), bga, _ptr_array(T_final),
