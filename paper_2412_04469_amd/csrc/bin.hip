@@ -57,7 +57,7 @@ __device__ __forceinline__ uint64_t load_state(const uint64_t* p) {
 // states at lb[j * stride].  The states of up to kWindow predecessors are loaded together, then consumed
 // nearest first until an inclusive prefix (done) or a state not yet published (re-load from there).
 // Gives up (recording it in *err) after kMaxSpin rounds without progress.
-constexpr int kWindow = 32;
+constexpr int kWindow = 8;
 
 __device__ __forceinline__ uint64_t look_back(const uint64_t* lb, int64_t stride, uint32_t bid, uint32_t* err) {
     uint64_t excl = 0;
@@ -171,6 +171,9 @@ __device__ __forceinline__ uint32_t digit_total(const SortCtl* ctl, int p) {
 // ------------------------------------------------------------------------------------------------
 // One stable radix pass.  Item r of lane l in wave w of block b sits at b*TILE + w*(IPT*64) + r*64 + l
 // (wave-contiguous, so within a wave the rounds are in element order and waves are in element order).
+// The block first orders its items by digit in LDS (stable), then writes them out in that order: each
+// digit's items land at consecutive output positions, so neighbouring threads write neighbouring words
+// instead of every item being a scattered 4-byte write.
 // lb_cur: [nblocks][256] look-back states of this pass (zero on entry); lb_next, if given, is the next
 // pass's array: every block clears its own slot there.
 // ------------------------------------------------------------------------------------------------
@@ -182,6 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
     __shared__ uint32_t s_cnt[kWaves][kRadix];
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_bid;
+    __shared__ uint32_t s_goff[kRadix];  // output position - block-local position, per digit
+    __shared__ uint32_t s_key[IPT * kBlock], s_val[IPT * kBlock];
     const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
     if (tid == 0) s_bid = atomicAdd(&ctl->ticket[pass], 1u);
     __syncthreads();
@@ -214,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t m = match8(d, valid);
         if (valid && (m & lanemask_lt()) == 0) atomicAdd(&s_cnt[w][d], (uint32_t)__popcll(m));
+        __builtin_amdgcn_sched_barrier(0);  // one round at a time: the rounds' masks are not kept live together
     }
     __syncthreads();
     // block total of digit tid, publish, look back, publish the inclusive prefix
@@ -229,9 +235,12 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
         excl = look_back(lb_cur + tid, kRadix, bid, &ctl->err);
         store_state(my, kFlagInc | (excl + tot));
     }
-    // per-wave starting positions: digit start + earlier blocks + earlier waves
+    // block-local start of digit tid (digits in order), and per-wave local starts within it
+    uint32_t ntot;
+    const uint32_t lbase = block_excl_scan<uint32_t>(tot, s_w, &ntot);
+    s_goff[tid] = dbase + (uint32_t)excl - lbase;
     {
-        uint32_t run = dbase + (uint32_t)excl;
+        uint32_t run = lbase;
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) {
             const uint32_t c = s_cnt[k][tid];
@@ -254,8 +263,21 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
         start = __shfl(start, leader < 0 ? 0 : leader);
         if (valid) {
             const uint32_t pos = start + rank;
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            s_key[pos] = key[r];
+            s_val[pos] = val[r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    // phase 3: the block's items in digit order (ntot of them) to their output positions
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t i = (uint32_t)(r * kBlock + tid);
+        if (i < ntot) {
+            const uint32_t k = s_key[i];
+            const uint32_t pos = i + s_goff[(k >> shift) & (kRadix - 1)];
+            kout[pos] = k;
+            vout[pos] = s_val[i];
         }
     }
 }
