@@ -211,14 +211,18 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
         key[r] = valid ? kin[idx] : 0u;
         val[r] = valid ? vin[idx] : 0u;
     }
-    // phase 1: per-wave digit counts
+    // phase 1: per-wave digit counts; each item keeps its rank among the equal digits of its round, the
+    // round's count of that digit and the lowest lane holding it (8 | 8 | 16 bits)
+    uint32_t info[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
         const bool valid = idx < count;
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t m = match8(d, valid);
-        if (valid && (m & lanemask_lt()) == 0) atomicAdd(&s_cnt[w][d], (uint32_t)__popcll(m));
+        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt()), cnt = (uint32_t)__popcll(m);
+        if (valid && rank == 0) atomicAdd(&s_cnt[w][d], cnt);
+        info[r] = rank | (cnt << 8) | ((uint32_t)(__ffsll((unsigned long long)m) - 1) << 16);
         __builtin_amdgcn_sched_barrier(0);  // one round at a time: the rounds' masks are not kept live together
     }
     __syncthreads();
@@ -255,12 +259,10 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
         const bool valid = idx < count;
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t m = match8(d, valid);
-        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
-        const int leader = __ffsll((unsigned long long)m) - 1;
+        const uint32_t rank = info[r] & 0xffu;
         uint32_t start = 0;
-        if (valid && rank == 0) start = atomicAdd(&s_cnt[w][d], (uint32_t)__popcll(m));
-        start = __shfl(start, leader < 0 ? 0 : leader);
+        if (valid && rank == 0) start = atomicAdd(&s_cnt[w][d], (info[r] >> 8) & 0xffu);
+        start = __shfl(start, valid ? (int)(info[r] >> 16) : 0);  // a valid lane's digit group holds itself
         if (valid) {
             const uint32_t pos = start + rank;
             s_key[pos] = key[r];
