@@ -10,22 +10,49 @@ constexpr int kLBlock = 256;
 constexpr int kLIPT = 16;
 constexpr int64_t kLTile = (int64_t)kLBlock * kLIPT;
 
+__device__ __forceinline__ float l1_term(float x, float y, float gscale, float& sa, float& sb) {
+    const float d = x - y;
+    sa += fabsf(d);
+    const float c = fminf(1.f, fmaxf(0.f, x)) - y;
+    sb = __builtin_fmaf(c, c, sb);
+    return d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
+}
+
+// A block covers kLTile consecutive elements.  vec: every pointer is 16-byte aligned; a block lying wholly
+// inside the range then moves them as float4 (thread t takes quads t, t + 256, ...).
 __global__ __launch_bounds__(kLBlock) void k_l1(int64_t count, const float* __restrict__ img,
                                                 const float* __restrict__ gt, float gscale,
-                                                float* __restrict__ grad, double* __restrict__ part) {
+                                                float* __restrict__ grad, double* __restrict__ part, int vec) {
     __shared__ double s_a[kLBlock / kWave], s_b[kLBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * kLTile;
     float sa = 0.f, sb = 0.f;
+    if (vec && base + kLTile <= count) {
+        const float4* I = reinterpret_cast<const float4*>(img + base);
+        const float4* T = reinterpret_cast<const float4*>(gt + base);
+        float4* D = reinterpret_cast<float4*>(grad + base);
+        float4 x[kLIPT / 4], y[kLIPT / 4];
 #pragma unroll
-    for (int r = 0; r < kLIPT; ++r) {
-        const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
-        if (i < count) {
-            const float x = img[i], y = gt[i];
-            const float d = x - y;
-            sa += fabsf(d);
-            const float c = fminf(1.f, fmaxf(0.f, x)) - y;
-            sb = __builtin_fmaf(c, c, sb);
-            if (grad) grad[i] = d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
+        for (int r = 0; r < kLIPT / 4; ++r) {
+            x[r] = I[r * kLBlock + threadIdx.x];
+            y[r] = T[r * kLBlock + threadIdx.x];
+        }
+#pragma unroll
+        for (int r = 0; r < kLIPT / 4; ++r) {
+            float4 gr;
+            gr.x = l1_term(x[r].x, y[r].x, gscale, sa, sb);
+            gr.y = l1_term(x[r].y, y[r].y, gscale, sa, sb);
+            gr.z = l1_term(x[r].z, y[r].z, gscale, sa, sb);
+            gr.w = l1_term(x[r].w, y[r].w, gscale, sa, sb);
+            if (grad) D[r * kLBlock + threadIdx.x] = gr;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kLIPT; ++r) {
+            const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
+            if (i < count) {
+                const float gr = l1_term(img[i], gt[i], gscale, sa, sb);
+                if (grad) grad[i] = gr;
+            }
         }
     }
     double da = sa, db = sb;
@@ -78,7 +105,9 @@ struct AdamSegs {
     float* m[8];
     float* v[8];
     float lr[8];
-    int64_t start[9];  // prefix of the segment lengths
+    int64_t count[8];
+    int64_t qstart[9];  // prefix of the segment lengths in quads of 4 elements
+    int vec[8];         // all four arrays of the segment 16-byte aligned: whole quads move as float4
     int nseg;
 };
 
@@ -93,25 +122,53 @@ __global__ void k_adam_tick(int32_t* __restrict__ state, float b1, float b2) {
     reinterpret_cast<float*>(state)[2] = (float)(1.0 - pow((double)b2, (double)t));
 }
 
+__device__ __forceinline__ void adam_one(float& p, float& m, float& v, float g, float lr, float b1, float b2, float eps,
+                                         float c1, float c2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    p -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// One thread per quad of 4 consecutive elements of a segment (16-byte loads and stores where aligned).
 __global__ void k_adam_multi(AdamSegs S, float b1, float b2, float eps, float c1, float c2, int zero_grad,
                              const int32_t* __restrict__ state) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.start[S.nseg]) return;
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= S.qstart[S.nseg]) return;
     if (state) {
         c1 = reinterpret_cast<const float*>(state)[1];
         c2 = reinterpret_cast<const float*>(state)[2];
     }
     int s = 0;
 #pragma unroll 1
-    while (s + 1 < S.nseg && i >= S.start[s + 1]) ++s;
-    const int64_t j = i - S.start[s];
-    const float gi = S.g[s][j];
-    const float mi = b1 * S.m[s][j] + (1.f - b1) * gi;
-    const float vi = b2 * S.v[s][j] + (1.f - b2) * gi * gi;
-    S.m[s][j] = mi;
-    S.v[s][j] = vi;
-    S.p[s][j] -= S.lr[s] * (mi / c1) / (sqrtf(vi / c2) + eps);
-    if (zero_grad) S.g[s][j] = 0.f;
+    while (s + 1 < S.nseg && qi >= S.qstart[s + 1]) ++s;
+    const int64_t j0 = (qi - S.qstart[s]) * 4;
+    const float lr = S.lr[s];
+    if (S.vec[s] && j0 + 4 <= S.count[s]) {
+        float4* P = reinterpret_cast<float4*>(S.p[s] + j0);
+        float4* G = reinterpret_cast<float4*>(S.g[s] + j0);
+        float4* M = reinterpret_cast<float4*>(S.m[s] + j0);
+        float4* V = reinterpret_cast<float4*>(S.v[s] + j0);
+        const float4 g = *G;
+        float4 p = *P, m = *M, v = *V;
+        adam_one(p.x, m.x, v.x, g.x, lr, b1, b2, eps, c1, c2);
+        adam_one(p.y, m.y, v.y, g.y, lr, b1, b2, eps, c1, c2);
+        adam_one(p.z, m.z, v.z, g.z, lr, b1, b2, eps, c1, c2);
+        adam_one(p.w, m.w, v.w, g.w, lr, b1, b2, eps, c1, c2);
+        *P = p;
+        *M = m;
+        *V = v;
+        if (zero_grad) *G = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        const int64_t j1 = j0 + 4 < S.count[s] ? j0 + 4 : S.count[s];
+        for (int64_t j = j0; j < j1; ++j) {
+            float p = S.p[s][j], m = S.m[s][j], v = S.v[s][j];
+            adam_one(p, m, v, S.g[s][j], lr, b1, b2, eps, c1, c2);
+            S.p[s][j] = p;
+            S.m[s][j] = m;
+            S.v[s][j] = v;
+            if (zero_grad) S.g[s][j] = 0.f;
+        }
+    }
 }
 
 }  // namespace
@@ -127,7 +184,7 @@ extern "C" qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, fl
     QG_REQUIRE(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f, "bad Adam constants");
     AdamSegs S = {};
     S.nseg = nseg;
-    S.start[0] = 0;
+    S.qstart[0] = 0;
     for (int k = 0; k < nseg; ++k) {
         const qg_adam_segment& q = segs[k];
         QG_REQUIRE(q.count >= 0, "segment %d: count < 0", k);
@@ -137,9 +194,12 @@ extern "C" qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, fl
         S.m[k] = q.m;
         S.v[k] = q.v;
         S.lr[k] = q.lr;
-        S.start[k + 1] = S.start[k] + q.count;
+        S.count[k] = q.count;
+        S.qstart[k + 1] = S.qstart[k] + ceil_div(q.count, (int64_t)4);
+        auto al16 = [](const float* x) { return ((uintptr_t)x & 15u) == 0; };
+        S.vec[k] = al16(q.param) && al16(q.grad) && al16(q.m) && al16(q.v);
     }
-    const int64_t total = S.start[nseg];
+    const int64_t total = S.qstart[nseg];
     const float c1 = step_state ? 1.f : (float)(1.0 - std::pow((double)b1, t));
     const float c2 = step_state ? 1.f : (float)(1.0 - std::pow((double)b2, t));
     hipStream_t s = (hipStream_t)stream;
@@ -166,7 +226,9 @@ extern "C" qg_status qg_l1_loss(int64_t count, const float* image, const float* 
     const float gs = count > 0 ? scale / (float)count : 0.f;
     {
         QG_TIMED("l1", s);
-        k_l1<<<(unsigned)nb, kLBlock, 0, s>>>(count, image, gt, gs, grad_image, partials);
+        auto al16 = [](const void* x) { return ((uintptr_t)x & 15u) == 0; };
+        const int vec = al16(image) && al16(gt) && al16(grad_image);
+        k_l1<<<(unsigned)nb, kLBlock, 0, s>>>(count, image, gt, gs, grad_image, partials, vec);
     }
     QG_LAUNCH_CHECK("qg_l1_loss");
     return QG_OK;

@@ -403,8 +403,9 @@ def test_adam_multi_parity(qgm):
 
 @pytest.mark.parametrize("n,tile", [(3001, (16, 16)), (40, (8, 8)), (5000, (32, 8))])
 def test_fused_equals_two_call_path(qgm, n, tile):
-    """qg_decode_project == qg_decode_residuals + qg_project, and qg_render_decode_bwd ==
-    qg_render_bwd + qg_decode_residuals_bwd, bit for bit."""
+    """qg_decode_project == qg_decode_residuals + qg_project bit for bit; qg_render_decode_bwd ==
+    qg_render_bwd + qg_decode_residuals_bwd, with or without the decoded attributes, up to the order of
+    float atomics."""
     qg, raster = qgm
     rng = synth.rng_for(50 + n)
     sc = synth.draw_scene(rng, n, 1.0, -3.5, 0.5)
@@ -453,11 +454,19 @@ def test_fused_equals_two_call_path(qgm, n, tile):
     qg.qg_render_decode_bwd(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, 3, r2.qcams, r2.tile, r2.dilation,
                             r2.t_proj, r2.vals, r2.ranges, bg, r2.t_tf, r2.t_last, G, g2["lat"], g2["W1"], g2["W2"],
                             g2["lp"], g2["a"], gabs2, None, ws2, wsb2)
+    # the adjoint given the decoded attributes of the forward (no second decode) gives the same gradients
+    g3 = {k: torch.zeros_like(t) for k, t in zip(names, (lat, W1, W2, lp, a))}
+    gabs3 = torch.zeros(n, device="cuda")
+    qg.qg_render_decode_bwd(n, n, None, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, 3, r2.qcams, r2.tile, r2.dilation,
+                            r2.t_proj, r2.vals, r2.ranges, bg, r2.t_tf, r2.t_last, G, g3["lat"], g3["W1"], g3["W2"],
+                            g3["lp"], g3["a"], gabs3, None, ws2, wsb2, attrs=attrs2)
     torch.cuda.synchronize()
     # the blend adjoint uses float atomics, so equality is up to their summation order
     for k in names:
         assert rel_l2(g2[k].cpu().numpy(), g1[k].cpu().numpy()) <= 1e-5, k
+        assert rel_l2(g3[k].cpu().numpy(), g2[k].cpu().numpy()) <= 1e-5, k
     assert rel_l2(gabs2.cpu().numpy(), gabs1.cpu().numpy()) <= 1e-5
+    assert rel_l2(gabs3.cpu().numpy(), gabs2.cpu().numpy()) <= 1e-5
 
 
 @pytest.mark.parametrize("n", [1, 2, 1000, 100003])
