@@ -265,15 +265,18 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     finish_sched(sc.ctr);
 }
 
-// ---- wave64 sums of K values at once: DPP inclusive scans inside each 16-lane row (row_shr 1, 2, 4, 8,
-// interleaved over the K values so consecutive DPP operations never depend on each other), then the four
-// row totals go through LDS and are added by the lanes that issue the atomics.
+// ---- wave64 sums of K values at once: DPP inclusive scans inside each 8-lane half row (row_shr 1, 2, 4,
+// interleaved over the K values so consecutive DPP operations never depend on each other), then the eight
+// half-row totals go through LDS and are added by the lanes that issue the atomics.  (A fourth DPP step
+// would cost the whole wave two instructions per value; the extra four adds run on those few lanes.)
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_term(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
 
-// In-row inclusive scans: afterwards lane 16r + 15 holds the sum of row r (lanes 16r .. 16r + 15).
+// Scans with shifts 1, 2, 4 inside each 16-lane row (zeros shifted in at the row start): afterwards lane l
+// holds the sum of the 8 lanes l - 7 .. l of its row that exist, so lane 8h + 7 holds exactly the sum of
+// lanes 8h .. 8h + 7.
 template <int K>
 __device__ __forceinline__ void row_sums(float (&v)[K]) {
 #pragma unroll
@@ -282,8 +285,6 @@ __device__ __forceinline__ void row_sums(float (&v)[K]) {
     for (int k = 0; k < K; ++k) v[k] += dpp_term<0x112, 0xf>(v[k]);  // row_shr:2
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += dpp_term<0x114, 0xf>(v[k]);  // row_shr:4
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp_term<0x118, 0xf>(v[k]);  // row_shr:8
 }
 
 template <int TW, int TH, int BD>
@@ -406,16 +407,17 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
             }
             if (__ballot(hit) == 0) continue;
             row_sums<9>(acc);
-            if ((lane & 15) == 15) {
+            if ((lane & 7) == 7) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) s_red[lane >> 4][k] = acc[k];
+                for (int k = 0; k < 9; ++k) s_red[lane >> 3][k] = acc[k];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (lane < 9) {
                 const float val =
-                    gscale * ((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]));
+                    gscale * (((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane])) +
+                              ((s_red[4][lane] + s_red[5][lane]) + (s_red[6][lane] + s_red[7][lane])));
                 atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -438,7 +440,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t*
     __shared__ float4 s_c[BD];  // b, A, B, C
     __shared__ uint32_t s_gid[BD];
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
-    __shared__ float s_red[4][12];  // row totals of the 9 gradient components
+    __shared__ float s_red[8][12];  // half-row totals of the 9 gradient components
     if (sc.order == nullptr) {
         const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
         if (tile < vt.total_tiles)
