@@ -130,7 +130,9 @@ __device__ __forceinline__ void zero_acc(BwdAcc& a) {
     a.W1[0] = a.W1[1] = f4{0.f, 0.f, 0.f, 0.f};
 }
 
-// Backward of 16 Gaussians (columns/rows as in the layouts above).
+// Backward of 16 Gaussians (columns/rows as in the layouts above), in two halves so that a caller can run
+// the first half of several groups before the second half of any (one LDS barrier between them instead of
+// one per group, and the groups' dL chains interleave).
 //   latA(k):   rounded latent k of Gaussian c                (row layout of pre = L W1^T)
 //   latN(k, i):rounded latent k of Gaussian 4q + i           (A of dW1^T += L^T dpre)
 //   drA(m):    dL/dr_m of Gaussian c                         (A of dH = dR W2), m = 4ks + q
@@ -138,9 +140,10 @@ __device__ __forceinline__ void zero_acc(BwdAcc& a) {
 //   dlat(k, v):receives dL/dlatent_k of Gaussian c for k = 4q + i < 8 (lanes q < 2)
 // tb(r, j): a float& to LDS owned by this wave, r < 16, j < 32 (transpose of dpre); it is written only after
 // every drA/drN/latN read of the group, so it may alias their storage.
-template <class LatA, class LatN, class DrA, class DrN, class DLat, class TB>
-__device__ __forceinline__ void decode_group_bwd(const BwdOps& o, BwdAcc& acc, const LatA& latA, const LatN& latN,
-                                                 const DrA& drA, const DrN& drN, const DLat& dlat, const TB& tb) {
+// First half: the weight-gradient products into acc and dpre^T into tb.
+template <class LatA, class LatN, class DrA, class DrN, class TB>
+__device__ __forceinline__ void decode_group_bwd_a(const BwdOps& o, BwdAcc& acc, const LatA& latA, const LatN& latN,
+                                                   const DrA& drA, const DrN& drN, const TB& tb) {
     const int lane = __lane_id(), q = lane / 16, c = lane % 16;
     // pre (layout N)
     f4 pre[2];
@@ -183,24 +186,40 @@ __device__ __forceinline__ void decode_group_bwd(const BwdOps& o, BwdAcc& acc, c
         acc.W1[0] = mfma(al, dP[0][i], acc.W1[0]);
         acc.W1[1] = mfma(al, dP[1][i], acc.W1[1]);
     }
-    // dL^T = W1^T dpre^T: dpre transposed to (feature 4ks + q, Gaussian c) through LDS
+    // dpre transposed to (feature 4ks + q, Gaussian c) through LDS
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) tb(4 * q + i, 16 * jb + c) = dP[jb][i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Second half (after an LDS barrier of the wave): dL^T = W1^T dpre^T from tb.
+template <class DLat, class TB>
+__device__ __forceinline__ void decode_group_bwd_b(const BwdOps& o, const DLat& dlat, const TB& tb) {
+    const int lane = __lane_id(), q = lane / 16, c = lane % 16;
     f4 dL = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) dL = mfma(o.aW1T[ks], tb(c, 4 * ks + q), dL);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (q < 2) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) dlat(4 * q + i, dL[i]);
     }
+}
+
+__device__ __forceinline__ void wave_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Both halves for one group.
+template <class LatA, class LatN, class DrA, class DrN, class DLat, class TB>
+__device__ __forceinline__ void decode_group_bwd(const BwdOps& o, BwdAcc& acc, const LatA& latA, const LatN& latN,
+                                                 const DrA& drA, const DrN& drN, const DLat& dlat, const TB& tb) {
+    decode_group_bwd_a(o, acc, latA, latN, drA, drN, tb);
+    wave_lds_barrier();
+    decode_group_bwd_b(o, dlat, tb);
+    wave_lds_barrier();
 }
 
 // Adds this wave's accumulators into a block buffer sw[2048] (W1 [32][8] then W2 [56][32]); the caller

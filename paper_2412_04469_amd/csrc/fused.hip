@@ -262,6 +262,9 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
             load_bwd_ops(W1, W2, ops);
             BwdAcc acc;
             zero_acc(acc);
+            // first halves of the four groups, one barrier, then the four dL chains together.  The transpose
+            // buffer of group sg is planes 0..31 of its own Gaussians' slots, dead once that group's reads are
+            // done; dL/dlatent goes to the group's own latent slots, read by nothing after its first half.
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
                 const int gA = 16 * sg + c3;
@@ -269,10 +272,16 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
                 auto latN = [&](int k, int i) { return rintf(sl[slot_lat(k, 16 * sg + 4 * q3 + i)]); };
                 auto drA = [&](int m) { return at[slot_at(m, gA)]; };
                 auto drN = [&](int m, int i) { return m < kM ? at[slot_at(m, 16 * sg + 4 * q3 + i)] : 0.f; };
-                auto dlat = [&](int k, float v) { sl[slot_lat(k, gA)] = v; };
-                // transpose buffer: planes 0..31 of this group's Gaussians, dead once the group's reads are done
                 auto tb = [&](int r, int j) -> float& { return at[slot_at(j, 16 * sg + r)]; };
-                decode_group_bwd(ops, acc, latA, latN, drA, drN, dlat, tb);
+                decode_group_bwd_a(ops, acc, latA, latN, drA, drN, tb);
+            }
+            wave_sync_lds();
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                const int gA = 16 * sg + c3;
+                auto dlat = [&](int k, float v) { sl[slot_lat(k, gA)] = v; };
+                auto tb = [&](int r, int j) -> float& { return at[slot_at(j, 16 * sg + r)]; };
+                decode_group_bwd_b(ops, dlat, tb);
             }
             add_acc_atomic(acc, s_acc);
         }

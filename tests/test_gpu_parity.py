@@ -401,8 +401,9 @@ def test_adam_multi_parity(qgm):
         assert bool((gd == 1.0).all().item())
 
 
-@pytest.mark.parametrize("n,tile", [(3001, (16, 16)), (40, (8, 8)), (5000, (32, 8))])
-def test_fused_equals_two_call_path(qgm, n, tile):
+@pytest.mark.parametrize("n,tile,deg", [(3001, (16, 16), 3), (40, (8, 8), 3), (5000, (32, 8), 3), (3001, (16, 16), 1),
+                                       (777, (16, 16), 0)])
+def test_fused_equals_two_call_path(qgm, n, tile, deg):
     """qg_decode_project == qg_decode_residuals + qg_project bit for bit; qg_render_decode_bwd ==
     qg_render_bwd + qg_decode_residuals_bwd, with or without the decoded attributes, up to the order of
     float atomics."""
@@ -419,14 +420,14 @@ def test_fused_equals_two_call_path(qgm, n, tile):
     hp = (-0.5, 1.01, 0.3)
     bg = (0.1, 0.2, 0.3)
     # two-call path
-    r1 = raster.Rasterizer(n, cams, tile=tile, bg=bg)
+    r1 = raster.Rasterizer(n, cams, tile=tile, bg=bg, sh_degree=deg)
     attrs = torch.empty_like(prev)
     qg.qg_decode_residuals(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, attrs)
     r1.forward(attrs)
     # fused path
-    r2 = raster.Rasterizer(n, cams, tile=tile, bg=bg, capacity=r1.capacity)
+    r2 = raster.Rasterizer(n, cams, tile=tile, bg=bg, capacity=r1.capacity, sh_degree=deg)
     attrs2 = torch.empty_like(prev)
-    qg.qg_decode_project(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, 3, r2.qcams, r2.tile, r2.dilation, r2.t_proj,
+    qg.qg_decode_project(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, deg, r2.qcams, r2.tile, r2.dilation, r2.t_proj,
                          attrs2)
     r2.bin()
     r2.render()
@@ -451,13 +452,13 @@ def test_fused_equals_two_call_path(qgm, n, tile):
     gabs2 = torch.zeros(n, device="cuda")
     wsb2 = qg.qg_render_decode_bwd_workspace_size(n, len(cams))
     ws2 = torch.empty(wsb2, dtype=torch.uint8, device="cuda")
-    qg.qg_render_decode_bwd(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, 3, r2.qcams, r2.tile, r2.dilation,
+    qg.qg_render_decode_bwd(n, n, prev, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, deg, r2.qcams, r2.tile, r2.dilation,
                             r2.t_proj, r2.vals, r2.ranges, bg, r2.t_tf, r2.t_last, G, g2["lat"], g2["W1"], g2["W2"],
                             g2["lp"], g2["a"], gabs2, None, ws2, wsb2)
     # the adjoint given the decoded attributes of the forward (no second decode) gives the same gradients
     g3 = {k: torch.zeros_like(t) for k, t in zip(names, (lat, W1, W2, lp, a))}
     gabs3 = torch.zeros(n, device="cuda")
-    qg.qg_render_decode_bwd(n, n, None, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, 3, r2.qcams, r2.tile, r2.dilation,
+    qg.qg_render_decode_bwd(n, n, None, lat, 8, W1, W2, 32, 56, lp, a, *hp, lam, deg, r2.qcams, r2.tile, r2.dilation,
                             r2.t_proj, r2.vals, r2.ranges, bg, r2.t_tf, r2.t_last, G, g3["lat"], g3["W1"], g3["W2"],
                             g3["lp"], g3["a"], gabs3, None, ws2, wsb2, attrs=attrs2)
     torch.cuda.synchronize()
