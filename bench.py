@@ -13,6 +13,7 @@ inside the timed region itself (only that kernel is bracketed there).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -76,8 +77,8 @@ def copy_probe(mib):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=40)
-    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=300_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-pixels", type=int, default=8192)
@@ -89,9 +90,13 @@ def parse():
     p.add_argument("--tune", default="full", choices=["full", "quick", "none"],
                    help="blend autotuning of the batched step: all 18 candidates, 6, or the default only")
     p.add_argument("--frame-iters", type=int, default=500)
-    p.add_argument("--proposal", default="single", choices=["none", "single", "both"],
+    p.add_argument("--proposal", default="both", choices=["none", "single", "both"],
                    help="learned-proposal experiment: skip, judge with one view per step, or also batched")
     p.add_argument("--proposal-frames", type=int, default=50)
+    p.add_argument("--batched-views", type=int, default=16,
+                   help="views per batched optimiser step in the sec/frame sections (16: all 20 views in two groups)")
+    p.add_argument("--batched-lr-scale", type=float, default=1.0,
+                   help="learning-rate factor of the batched steps in the sec/frame sections")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run a plain copy of this many MiB first (counter calibration)")
     return p.parse_args()
@@ -282,13 +287,15 @@ def frame_section(args):
     log(f"frame: plain reaches {tgt:.3f} dB at {hit_p:.3f} s")
     del plain
     torch.cuda.empty_cache()
-    bat = BatchedFitter(prev, wl.cams, gts, cfg, persistent=True, eval_cam=held)
+    bcfg = dataclasses.replace(cfg, group_views=args.batched_views, batched_lr_scale=args.batched_lr_scale)
+    bat = BatchedFitter(prev, wl.cams, gts, bcfg, persistent=True, eval_cam=held)
     bat.size_capacity()
     w0 = (bat.W1.clone(), bat.W2.clone())
-    bat.step()
-    bat.step()  # both view groups captured; the decoder is put back to its initial weights below
+    for _ in bat.groups:  # every view group's step captured; the decoder is put back to its initial weights below
+        bat.step()
     bat.W1.copy_(w0[0])
     bat.W2.copy_(w0[1])
+    vps = max(len(g) for g in bat.groups)
     traj_b, hit_b = _fit_to_target(bat, lambda i: bat.step(), args.frame_iters, 25, held, gt_held, gate_fn,
                                    target=tgt)
     log(f"frame: batched {'reaches target at %.3f s' % hit_b if hit_b else 'does not reach the target'}")
@@ -297,7 +304,8 @@ def frame_section(args):
     torch.cuda.empty_cache()
     return {"workload": wl.name, "target_psnr_db": tgt, "iterations_plain": args.frame_iters,
             "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p},
-            "batched": {"sec_per_frame": None if hit_b is None else round(hit_b, 4), "views_per_step": 10,
+            "batched": {"sec_per_frame": None if hit_b is None else round(hit_b, 4),
+                        "views_per_step": vps, "lr_scale": args.batched_lr_scale,
                         "trajectory": traj_b, "overflow": ovf},
             "protocol": "frame clock from gate initialisation (20 forward + 20 adjoint passes) through the optimiser "
                         "steps; held-out PSNR every 25 steps with the clock paused"}
@@ -311,7 +319,7 @@ def proposal_section(args):
     the same held-out PSNR."""
     import torch
     from paper_2412_04469_amd import stream, synth
-    from paper_2412_04469_amd.fit import FitConfig
+    from paper_2412_04469_amd.fit import FitConfig, view_groups
     F = args.proposal_frames
     wl = synth.workload_dynamic(n=args.n)
     seq = stream.Sequence(wl, FitConfig(), torch.device("cuda"))
@@ -331,8 +339,13 @@ def proposal_section(args):
                           "used": j["used_proposal"]} for p, j in zip([r for r in recs if r["t"] in judge_frames],
                                                                         judged)]}
     if args.proposal == "both":
-        jb = stream.judge(seq, hist, recs, prop, judge_frames, args.frame_iters, 25, batched=True, log=log)
+        bcfg = dataclasses.replace(FitConfig(), group_views=args.batched_views, batched_lr_scale=args.batched_lr_scale)
+        jb = stream.judge(seq, hist, recs, prop, judge_frames, args.frame_iters, 25, batched=True, log=log,
+                          batched_cfg=bcfg)
         out["proposal_batched"] = stream.summarize(recs, jb, judge_frames)
+        out["proposal_batched"]["views_per_step"] = max(len(g) for g in view_groups(len(wl.cams),
+                                                                                  min(args.batched_views, 16)))
+        out["proposal_batched"]["lr_scale"] = args.batched_lr_scale
     del hist
     torch.cuda.empty_cache()
     return out
@@ -415,6 +428,18 @@ def main():
                 "units_per_launch": args.n, "work_per_unit": f"{BYTES_PER_GAUSS.get(dominant)} B per Gaussian"}
     roof["avg_launch_ms"] = round(dom_avg_ms, 4)
 
+    # per-step distribution: the same number of steps again, each bracketed by its own events (outside the
+    # timed region above, so the headline is not perturbed by the extra event records)
+    pairs_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i, (e0, e1) in enumerate(pairs_ev):
+        e0.record(stream)
+        fitter.step((first + args.steps + i) % V)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in pairs_ev])
+    dist = {"p10": round(float(np.percentile(per, 10)), 4), "p50": round(float(np.percentile(per, 50)), 4),
+            "p90": round(float(np.percentile(per, 90)), 4), "steps": int(args.steps)}
+
     result = {
         "metric": METRIC, "value": round(ms_step, 4), "unit": "ms/step", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": False, "scaling": "weak",
@@ -423,6 +448,7 @@ def main():
                    "tile": args.tile, "sh_degree": 3, "decoder": "8->32->56 SiLU", "pairs_max": P_max,
                    "overflow": overflow},
         "roofline": roof,
+        "step_ms_distribution": dist,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "launches_per_step": {k: counts[k] for k in sorted(counts)},
     }

@@ -42,6 +42,10 @@ class FitConfig:
     sh_degree: int = 3
     dilation: float = 0.3
     bg: tuple = (0.0, 0.0, 0.0)
+    # batched steps (BatchedFitter): at most this many views per optimiser step, and a factor on every learning
+    # rate (a step over several views has a lower-variance gradient and can take a longer step)
+    group_views: int = 16
+    batched_lr_scale: float = 1.0
 
 
 def xavier_decoder(seed: int, L=8, H=32, M=56):
@@ -55,7 +59,8 @@ def xavier_decoder(seed: int, L=8, H=32, M=56):
 class ResidualState:
     """A_{t-1} and the residual parameters of frame t (Eq. 4-8) with their gradients and Adam state."""
 
-    def __init__(self, prev_attrs: torch.Tensor, cfg: FitConfig = FitConfig(), W1=None, W2=None, seed=0):
+    def __init__(self, prev_attrs: torch.Tensor, cfg: FitConfig = FitConfig(), W1=None, W2=None, seed=0,
+                 lr_scale=1.0):
         self.cfg = cfg
         self.prev = prev_attrs.contiguous()
         self.n = int(self.prev.shape[1])
@@ -71,8 +76,8 @@ class ResidualState:
         self.lp = torch.zeros(3, n, device=dev)
         self.a = torch.zeros(n, device=dev)
         self.params = {"lat": self.lat, "lp": self.lp, "a": self.a, "W1": self.W1, "W2": self.W2}
-        self.lrs = {"lat": cfg.lr_latent, "lp": cfg.lr_pos, "a": cfg.lr_gate, "W1": cfg.lr_decoder,
-                    "W2": cfg.lr_decoder}
+        self.lrs = {k: lr * lr_scale for k, lr in (("lat", cfg.lr_latent), ("lp", cfg.lr_pos), ("a", cfg.lr_gate),
+                                                   ("W1", cfg.lr_decoder), ("W2", cfg.lr_decoder))}
         self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
@@ -244,11 +249,11 @@ class BatchedFitter(ResidualState):
 
     def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
                  capacity=None, seed=0, batch=0, persistent=True, graph=True, eval_cam=None):
-        super().__init__(prev_attrs, cfg, W1, W2, seed)
+        super().__init__(prev_attrs, cfg, W1, W2, seed, lr_scale=cfg.batched_lr_scale)
         self.cams = list(cams)
         # the captured steps read the ground truth from these buffers: new frames are copied into them
         self.gts = [g.clone() for g in gts]
-        self.groups = view_groups(len(self.cams))
+        self.groups = view_groups(len(self.cams), min(int(cfg.group_views), qg.MAX_VIEWS))
         self.batch, self.persistent, self.use_graph = int(batch), bool(persistent), bool(graph)
         dev = self.device
         n = self.n

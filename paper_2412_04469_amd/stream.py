@@ -160,15 +160,16 @@ def _train_loss(fitter, views):
 
 
 def judge(seq: Sequence, hist, plain_recs, prop: Proposal, frames, iters=500, check_every=25, batched=False,
-          log=None, capacity_margin=1.3, budget=2.0):
+          log=None, capacity_margin=1.3, budget=2.0, batched_cfg=None):
     """Proposal-initialised fitting on the given frames, from the plain run's A_{t-1} and decoder; each frame
-    may run up to budget x iters steps to reach the plain form's target."""
+    may run up to budget x iters steps to reach the plain form's target.  batched_cfg: the FitConfig of the
+    batched fitter (views per step, learning-rate scale), the sequence's by default."""
     cfg, dev, wl = seq.cfg, seq.dev, seq.wl
     targets = {r["t"]: r["target"] for r in plain_recs}
     A0 = hist["A"][frames[0] - 1]
     gts0, _ = seq.gts(frames[0] - 1)
     if batched:
-        fitter = BatchedFitter(A0, wl.cams, gts0, cfg, eval_cam=seq.held)
+        fitter = BatchedFitter(A0, wl.cams, gts0, batched_cfg or cfg, eval_cam=seq.held)
         fitter.size_capacity(capacity_margin)
         probe = FrameFitter(A0, wl.cams, gts0, cfg)  # single-view renders for the fallback check
         probe.size_capacity(capacity_margin)
