@@ -35,20 +35,23 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(256) void k_decode_project(int64_t n, int64_t ld, const float* __restrict__ prev,
+// Two waves per block, one chunk of 64 Gaussians per wave (straight-line code): 29 KB of LDS per block lets
+// three waves share a SIMD.
+__global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, const float* __restrict__ prev,
                                                         const float* __restrict__ lat, const float* __restrict__ W1,
                                                         const float* __restrict__ W2, const float* __restrict__ lp,
                                                         const float* __restrict__ ga, float g0, float g1, float tau,
                                                         float reg_shift, int sh_deg, ViewTable vt, float dilation,
                                                         int tile_w, int tile_h, float* __restrict__ attrs_out,
                                                         float* __restrict__ gate_out, float* __restrict__ lreg_part) {
-    __shared__ float s_res[4][kChunk][kM + 1];
-    __shared__ float s_red[4];
+    __shared__ float s_res[2][kChunk][kM + 1];
+    __shared__ float s_red[2];
     const int lane = __lane_id(), w = threadIdx.x / 64, c = lane % 16;
     const int64_t nchunks = ceil_div(n, kChunk);
     const uint32_t ld32 = (uint32_t)ld;
     float preg = 0.f;
-    for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+    const int64_t ch = (int64_t)blockIdx.x * 2 + w;
+    if (ch < nchunks) {
         const int64_t base = ch * kChunk;
         const int64_t g = base + lane;
         const bool gv = g < n;
@@ -89,13 +92,12 @@ __global__ __launch_bounds__(256) void k_decode_project(int64_t n, int64_t ld, c
             if (gate_out) gate_out[g] = gg;
             preg += sigm(a - reg_shift);
         }
-        wave_sync_lds();
     }
     if (lreg_part) {
         for (int o = 32; o >= 1; o >>= 1) preg += __shfl_xor(preg, o);
         if (lane == 0) s_red[w] = preg;
         __syncthreads();
-        if (threadIdx.x == 0) lreg_part[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+        if (threadIdx.x == 0) lreg_part[blockIdx.x] = s_red[0] + s_red[1];
     }
 }
 
@@ -296,9 +298,7 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_acc[i];
 }
 
-int64_t fused_fwd_blocks(int64_t n) {
-    return std::min<int64_t>(std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)), 1024);
-}
+int64_t fused_fwd_blocks(int64_t n) { return std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 2)); }
 int64_t fused_bwd_blocks(int64_t n) { return std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 4)); }
 
 qg_status check_dec(int32_t L, int32_t Hd, int32_t M, float g0, float g1, float tau) {
@@ -343,7 +343,7 @@ extern "C" qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_
     const float shift = tau * logf(-gamma0 / gamma1);
     {
         QG_TIMED("decode_project", s);
-        k_decode_project<<<(unsigned)nb, 256, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
+        k_decode_project<<<(unsigned)nb, 128, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
                                                       gamma1, tau, shift, sh_degree, vt, dilation, tiling.tile_w,
                                                       tiling.tile_h, attrs_out, gate_out, lreg_partial);
     }
