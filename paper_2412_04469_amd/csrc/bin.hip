@@ -95,6 +95,42 @@ __device__ __forceinline__ uint64_t look_back(const uint64_t* lb, int64_t stride
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
+// As look_back for one counter, by a whole wave: lane l reads the state of predecessor j - l, so one round
+// covers 64 predecessors.  The lanes up to the nearest inclusive prefix (or up to the first state not yet
+// published, which ends the round) are summed by a wave reduction.  Every lane returns the prefix.
+__device__ __forceinline__ uint64_t look_back_wave(const uint64_t* lb, uint32_t bid, uint32_t* err) {
+    const int lane = __lane_id();
+    uint64_t excl = 0;
+    int64_t j = (int64_t)bid - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const int64_t p = j - lane;
+        const uint64_t st = p >= 0 ? load_state(lb + p) : kFlagInc;
+        const uint64_t f = st & ~kValMask;
+        const uint64_t unpub = __ballot(f == 0), inc = __ballot(f == kFlagInc);
+        // lanes before the first unpublished state and up to (including) the first inclusive one
+        const int first_unpub = unpub ? __ffsll((unsigned long long)unpub) - 1 : 64;
+        const int first_inc = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+        const bool done = first_inc < first_unpub;
+        const int used = done ? first_inc + 1 : first_unpub;
+        uint64_t v = lane < used ? (st & kValMask) : 0;
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        excl += v;
+        if (done) break;
+        j -= used;
+        if (used == 0) {
+            if (++spins > kMaxSpin) {
+                if (lane == 0) atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        } else {
+            spins = 0;
+        }
+    }
+    return excl;
+}
+
 // Lanes of this wave holding the same digit (among active, valid lanes).
 __device__ __forceinline__ uint64_t match8(uint32_t d, bool valid) {
     uint64_t m = __ballot(valid);
@@ -361,16 +397,19 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n,
     }
     uint64_t btot;
     const uint64_t ex = block_excl_scan<uint64_t>(acc, s_w, &btot);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {  // wave 0 looks back
         uint64_t excl = 0;
         if (bid == 0) {
-            store_state(lb, kFlagInc | btot);
+            if (threadIdx.x == 0) store_state(lb, kFlagInc | btot);
         } else {
-            store_state(lb + bid, kFlagAgg | btot);
-            excl = look_back(lb, 1, bid, &ctl->err);
-            store_state(lb + bid, kFlagInc | (excl + btot));
+            if (threadIdx.x == 0) store_state(lb + bid, kFlagAgg | btot);
+            excl = look_back_wave(lb, bid, &ctl->err);
+            if (threadIdx.x == 0) store_state(lb + bid, kFlagInc | (excl + btot));
         }
-        s_excl = excl;
+        if (threadIdx.x == 0) s_excl = excl;
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t excl = s_excl;
         if ((int64_t)(bid + 1) * kScanTile >= items) {  // the last block
             const uint64_t t = excl + btot;
             const bool failed = atomicAdd(&ctl->err, 0u) != 0;  // a depth pass or this scan gave up waiting
