@@ -4,9 +4,11 @@
 // attribute tensor, reads it back in the projection, and in the backward writes and re-reads its
 // gradient.  Here one wave owns 64 consecutive Gaussians: the decoder's products run on the matrix cores
 // for the 64 Gaussians (decoder_mfma.h), the residuals land in LDS, and each lane then projects its own
-// Gaussian (gauss_math.h) from prev + residual.  The backward does the same, keeps the attribute gradient
-// in the LDS slots of the residuals it no longer needs, and feeds it straight to the decoder backward.
-// Results equal qg_decode_residuals + qg_project and qg_render_bwd + qg_decode_residuals_bwd.
+// Gaussian (gauss_math.h) from prev + residual.  The backward stages the chunk's attribute planes in LDS
+// (the forward's decoded attributes when the caller kept them, else prev with the residuals decoded again),
+// projects back through them per lane, keeps the attribute gradient in the same LDS slots and feeds it
+// straight to the decoder backward.  Results equal qg_decode_residuals + qg_project and qg_render_bwd +
+// qg_decode_residuals_bwd.
 #include <cmath>
 
 #include "decoder_mfma.h"
