@@ -70,6 +70,19 @@ def test_bad_arguments_are_rejected_before_launch():
     with pytest.raises(qg.QGError) as e:
         qg.qg_adam_multi(seg, 0.9, 0.999, 1e-8, 1, stream=0)
     assert "NULL" in str(e.value)
+    # the fused adjoint needs the attributes from somewhere: prev_attrs or the forward's decoded attributes
+    P = dict(splat=1, depth=1, rect=1, ntiles=1, flags=1)
+    ws = qg.qg_render_decode_bwd_workspace_size(10, 1)
+    with pytest.raises(qg.QGError) as e:
+        qg.qg_render_decode_bwd(10, 10, None, 1, 8, 1, 1, 32, 56, 1, 1, -0.5, 1.01, 0.3, 0.01, 3, [_cam()],
+                                qg.tiling(16, 16), 0.3, [P], 1, 1, (0, 0, 0), [1], [1], [1], 1, 1, 1, 1, 1, None, None,
+                                1, ws, stream=0, attrs=None)
+    assert e.value.status == qg.QG_ERR_ARG and "NULL" in str(e.value)
+    with pytest.raises(qg.QGError) as e:  # a workspace smaller than the query is refused
+        qg.qg_render_decode_bwd(10, 10, None, 1, 8, 1, 1, 32, 56, 1, 1, -0.5, 1.01, 0.3, 0.01, 3, [_cam()],
+                                qg.tiling(16, 16), 0.3, [P], 1, 1, (0, 0, 0), [1], [1], [1], 1, 1, 1, 1, 1, None, None,
+                                1, ws - 1, stream=0, attrs=1)
+    assert "workspace" in str(e.value)
     views = [_cam() for _ in range(17)]
     assert qg.qg_total_tiles(views, qg.tiling(16, 16)) == -1
     assert qg.qg_total_tiles([_cam(100, 70)], qg.tiling(32, 8)) == 4 * 9
