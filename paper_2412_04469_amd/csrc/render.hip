@@ -374,17 +374,34 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
             const float Adx = cc.y * dx, Bdx = cc.z * dx, dxx = dx * dx;
             // acc: gx, gy, gA, gB, gC, go, gr, gg, gb
             float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            // pass 1: alpha and T_i of every pixel; branch-free, and the decisions (entry reached, alpha >= 1/255,
+            // clamp) repeat the forward's exactly
+            float ekv[PPL], rawv[PPL], alv[PPL], dyv[PPL];
+            bool onv[PPL];
             bool hit = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                // branch-free; the decisions (entry reached, alpha >= 1/255, clamp) repeat the forward's exactly
                 const float dy = fy[k] - a.y;
                 const float ek = blend_e(a.w, bb.x, bb.y, dx, dy);
                 const float raw = a.z * ek;
                 const float al = fminf(kAlphaMax, raw);
                 const bool on = pos < last[k] && al >= kAlphaMin;
                 hit |= on;
-                const float Ti = on ? T[k] * __builtin_amdgcn_rcpf(1.f - al) : T[k];
+                T[k] = on ? T[k] * __builtin_amdgcn_rcpf(1.f - al) : T[k];
+                ekv[k] = ek;
+                rawv[k] = raw;
+                alv[k] = al;
+                dyv[k] = dy;
+                onv[k] = on;
+            }
+            if (__ballot(hit) == 0) continue;
+            // pass 2: gradients and the suffix colour, skipping a pixel slot in which no lane's pixel is on (a
+            // wide tile's splat often covers only some of the slot rows)
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                if (__ballot(onv[k]) == 0) continue;
+                const bool on = onv[k];
+                const float al = alv[k], dy = dyv[k], Ti = T[k];
                 const float w = on ? al * Ti : 0.f;
                 acc[6] = __builtin_fmaf(w, G0[k], acc[6]);
                 acc[7] = __builtin_fmaf(w, G1[k], acc[7]);
@@ -392,12 +409,11 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 const float cG = __builtin_fmaf(cc.x, G2[k], __builtin_fmaf(bb.w, G1[k], bb.z * G0[k]));
                 const float d = cG - SG[k];
                 SG[k] = __builtin_fmaf(on ? al : 0.f, d, SG[k]);
-                T[k] = Ti;
                 // geometric part: zero where the 0.99 clamp is active.  With m = alpha dL/dalpha,
                 // dL/dq = -m/2 (q = A dx^2 + 2 B dx dy + C dy^2); the constant factors -1/2 and -1 of the
                 // conic terms are applied once per entry after the wave sum (kGeomScale).
-                const float dLda = (on && raw <= kAlphaMax) ? Ti * d : 0.f;
-                acc[5] = __builtin_fmaf(dLda, ek, acc[5]);
+                const float dLda = (on && rawv[k] <= kAlphaMax) ? Ti * d : 0.f;
+                acc[5] = __builtin_fmaf(dLda, ekv[k], acc[5]);
                 const float m = al * dLda;
                 acc[0] = __builtin_fmaf(m, __builtin_fmaf(cc.z, dy, Adx), acc[0]);
                 acc[1] = __builtin_fmaf(m, __builtin_fmaf(cc.w, dy, Bdx), acc[1]);
@@ -405,7 +421,6 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 acc[3] = __builtin_fmaf(m, dx * dy, acc[3]);
                 acc[4] = __builtin_fmaf(m, dy * dy, acc[4]);
             }
-            if (__ballot(hit) == 0) continue;
             row_sums<9>(acc);
             if ((lane & 7) == 7) {
 #pragma unroll
