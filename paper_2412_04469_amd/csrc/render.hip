@@ -395,24 +395,23 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 onv[k] = on;
             }
             if (__ballot(hit) == 0) continue;
-            // pass 2: gradients and the suffix colour, skipping a pixel slot in which no lane's pixel is on (a
-            // wide tile's splat often covers only some of the slot rows)
+            // pass 2: gradients and the suffix colour, only in the lanes whose pixel is on (an off pixel would add
+            // exact zeros); the branch is on the exec mask, so a pixel slot no lane reaches costs nothing
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                if (__ballot(onv[k]) == 0) continue;
-                const bool on = onv[k];
+                if (!onv[k]) continue;
                 const float al = alv[k], dy = dyv[k], Ti = T[k];
-                const float w = on ? al * Ti : 0.f;
+                const float w = al * Ti;
                 acc[6] = __builtin_fmaf(w, G0[k], acc[6]);
                 acc[7] = __builtin_fmaf(w, G1[k], acc[7]);
                 acc[8] = __builtin_fmaf(w, G2[k], acc[8]);
                 const float cG = __builtin_fmaf(cc.x, G2[k], __builtin_fmaf(bb.w, G1[k], bb.z * G0[k]));
                 const float d = cG - SG[k];
-                SG[k] = __builtin_fmaf(on ? al : 0.f, d, SG[k]);
+                SG[k] = __builtin_fmaf(al, d, SG[k]);
                 // geometric part: zero where the 0.99 clamp is active.  With m = alpha dL/dalpha,
                 // dL/dq = -m/2 (q = A dx^2 + 2 B dx dy + C dy^2); the constant factors -1/2 and -1 of the
                 // conic terms are applied once per entry after the wave sum (kGeomScale).
-                const float dLda = (on && rawv[k] <= kAlphaMax) ? Ti * d : 0.f;
+                const float dLda = rawv[k] <= kAlphaMax ? Ti * d : 0.f;
                 acc[5] = __builtin_fmaf(dLda, ekv[k], acc[5]);
                 const float m = al * dLda;
                 acc[0] = __builtin_fmaf(m, __builtin_fmaf(cc.z, dy, Adx), acc[0]);
@@ -444,8 +443,10 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
     }
 }
 
+// At most 96 VGPRs, for five waves per SIMD: the kernel is VALU-issue-bound and the extra wave hides the latency
+// of its LDS reads and transcendentals better than the registers it costs.
 template <int TW, int TH, int BD>
-__global__ __launch_bounds__(64) void k_render_bwd(ViewTable vt, const uint32_t* __restrict__ vals,
+__global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, float bg0, float bg1,
                                                    float bg2, ViewPtrsCF tfinal, ViewPtrsCU lastp, ViewPtrsCF gimage,
                                                    float* __restrict__ grad2d, int64_t g2d_view_stride,
