@@ -173,23 +173,25 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
             bool any2 = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                // branch-free: the same decisions as "skip if alpha < 1/255; stop before T' < 1e-4"
+                // skip if alpha < 1/255; stop before T' < 1e-4.  The branches are on the exec mask: lanes
+                // that skip the entry do no work, and a pixel slot where no lane takes it costs nothing more.
                 const float dy = fy[k] - a.y;
                 const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
                 const float al = fminf(kAlphaMax, raw);
-                const bool running = T[k] > 0.f;
-                const bool ok = running && al >= kAlphaMin;
-                const float w = al * T[k];
-                const float tn = T[k] - w;  // T (1 - alpha)
-                const bool stop = ok && tn < kTMin;
-                const bool take = ok && !stop;
-                const float wt = take ? w : 0.f;
-                C0[k] = __builtin_fmaf(bb.z, wt, C0[k]);
-                C1[k] = __builtin_fmaf(bb.w, wt, C1[k]);
-                C2[k] = __builtin_fmaf(cb, wt, C2[k]);
-                T[k] = take ? tn : (stop ? -T[k] : T[k]);
-                last[k] = take ? pos1 : last[k];
-                any2 |= running && !stop;
+                if (T[k] > 0.f && al >= kAlphaMin) {
+                    const float w = al * T[k];
+                    const float tn = T[k] - w;  // T (1 - alpha)
+                    if (tn < kTMin) {
+                        T[k] = -T[k];  // stopped: this entry and all later ones are not taken
+                    } else {
+                        C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
+                        C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
+                        C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                        T[k] = tn;
+                        last[k] = pos1;
+                    }
+                }
+                any2 |= T[k] > 0.f;
             }
             if (__ballot(any2) == 0) break;
         }
