@@ -373,9 +373,10 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
             const float4 bb = s_b[jj];
             const float4 cc = s_c[jj];
             const float dx = fx - a.x;
-            const float Adx = cc.y * dx, Bdx = cc.z * dx, dxx = dx * dx;
             // acc: gx, gy, gA, gB, gC, go, gr, gg, gb
             float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            // the lane's moments sum m, sum m dy, sum m dy^2 over its pixels (dx is the same for all of them)
+            float M0 = 0.f, M1 = 0.f, M2 = 0.f;
             // pass 1: alpha and T_i of every pixel; branch-free, and the decisions (entry reached, alpha >= 1/255,
             // clamp) repeat the forward's exactly
             float ekv[PPL], rawv[PPL], alv[PPL], dyv[PPL];
@@ -416,12 +417,18 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 const float dLda = rawv[k] <= kAlphaMax ? Ti * d : 0.f;
                 acc[5] = __builtin_fmaf(dLda, ekv[k], acc[5]);
                 const float m = al * dLda;
-                acc[0] = __builtin_fmaf(m, __builtin_fmaf(cc.z, dy, Adx), acc[0]);
-                acc[1] = __builtin_fmaf(m, __builtin_fmaf(cc.w, dy, Bdx), acc[1]);
-                acc[2] = __builtin_fmaf(m, dxx, acc[2]);
-                acc[3] = __builtin_fmaf(m, dx * dy, acc[3]);
-                acc[4] = __builtin_fmaf(m, dy * dy, acc[4]);
+                const float mdy = m * dy;
+                M0 += m;
+                M1 += mdy;
+                M2 = __builtin_fmaf(mdy, dy, M2);
             }
+            // the lane's sums of m (A dx + B dy), m (B dx + C dy), m dx^2, m dx dy, m dy^2 (cc.y, cc.z, cc.w = A, B,
+            // C of the unfolded conic)
+            acc[0] = __builtin_fmaf(cc.z, M1, cc.y * dx * M0);
+            acc[1] = __builtin_fmaf(cc.w, M1, cc.z * dx * M0);
+            acc[2] = dx * dx * M0;
+            acc[3] = dx * M1;
+            acc[4] = M2;
             row_sums<9>(acc);
             if ((lane & 7) == 7) {
 #pragma unroll
