@@ -103,10 +103,6 @@ __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, c
     }
 }
 
-struct ViewPtrsB {
-    float* p[QG_MAX_VIEWS];
-};
-
 // ---- backward: staging through LDS DMA ----------------------------------------------------------
 // The backward keeps a chunk's per-Gaussian inputs in LDS, plane by plane (64 floats a plane).  They are
 // copied there by global->LDS loads, which take no registers, so every plane of a chunk is in flight at once
@@ -156,6 +152,16 @@ __device__ __forceinline__ void stage_chunk(const float* __restrict__ prev, cons
     stage_plane<kFull>(g_ga, ld, 0, base, n, l0, 0, so + 3 * kChunk);
 }
 
+// Pins the loaded values in registers, so that the compiler cannot fold a later choice between them and a
+// load from memory into a load through a chosen pointer (which would put them in scratch memory).
+__device__ __forceinline__ void in_vgprs(BwdPre& p) {
+    float* f[] = {&p.r0.g0.x, &p.r0.g0.y, &p.r0.g0.z, &p.r0.g0.w, &p.r0.g1.x, &p.r0.g1.y, &p.r0.g1.z,
+                  &p.r0.g1.w, &p.r0.g2.x, &p.r0.g2.y, &p.r0.g2.z, &p.r0.g2.w, &p.gabs};
+#pragma unroll
+    for (float* x : f) asm volatile("" : "+v"(*x));
+    asm volatile("" : "+v"(p.r0.flags));
+}
+
 // kDecoded: `prev` holds the decoded attributes of this step (prev + residual, positions with the gate
 // applied), so the residuals are not decoded again.
 template <bool kDecoded>
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     int64_t n, int64_t ld, const float* __restrict__ prev, const float* __restrict__ lat, const float* __restrict__ W1,
     const float* __restrict__ W2, const float* __restrict__ lp, const float* __restrict__ ga, float g0, float g1,
     float tau, float reg_shift, float reg_scale, int sh_deg, ViewTable vt, float dilation,
-    const float* __restrict__ grad2d, int64_t stride, float* __restrict__ gxy_abs, ViewPtrsB gxyv,
+    const float* __restrict__ grad2d, int64_t stride, float* __restrict__ gxy_abs, ViewPtrs gxyv,
     float* __restrict__ g_lat, float* __restrict__ g_lp, float* __restrict__ g_ga, float* __restrict__ wpart) {
     // per wave:
     //   s_at:  attribute planes 3..58 (prev + residual while projecting), then dL/dr in the same slots
@@ -180,9 +186,6 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     float* const so = s_old[w];
     for (int i = threadIdx.x; i < kWidth; i += 256) s_acc[i] = 0.f;
     __syncthreads();
-    ViewPtrs gv2;
-#pragma unroll
-    for (int v = 0; v < QG_MAX_VIEWS; ++v) gv2.p[v] = gxyv.p[v];
     const int64_t nchunks = ceil_div(n, kChunk);
     const uint32_t ld32 = (uint32_t)ld;
     // one chunk per wave: straight-line code, so nothing is kept in registers across chunks
@@ -204,7 +207,11 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
             lpv[k] = gv ? lp[pidx(k, ld32, g32)] : 0.f;
         }
         const float a = gv ? ga[g] : 0.f;
+        // view 0's gradient record and the old |grad xy| sum, loaded with the chunk (one wait for HBM)
+        BwdPre pre{};
+        if (gv) pre = load_bwd_pre(vt, grad2d, stride, gxy_abs, g);
         __builtin_amdgcn_s_waitcnt(0);
+        in_vgprs(pre);
         wave_sync_lds();
         // 1. add the decoded residuals in place
         if (!kDecoded) {
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
                 else
                     at[slot_at(k - 3, l2)] = v;
             };
-            project_bwd_gauss<true>(n, g, get, put, sh_deg, vt, dilation, grad2d, stride, gxy_abs, gv2);
+            project_bwd_gauss<true, true>(n, g, get, put, sh_deg, vt, dilation, grad2d, stride, gxy_abs, gxyv, pre);
             const int nb = (sh_deg + 1) * (sh_deg + 1);
             for (int m = 8 + 3 * nb; m < kM; ++m) at[slot_at(m, l2)] = 0.f;  // SH planes above the degree
             float dot = 0.f;
@@ -394,7 +401,7 @@ extern "C" qg_status qg_render_decode_bwd(
     if (st != QG_OK) return st;
     st = blend_bwd_launch(vt, tiling, vals, tile_ranges, bg, T_final, last, grad_image, grad2d, stride, s);
     if (st != QG_OK) return st;
-    ViewPtrsB gv = {};
+    ViewPtrs gv = {};
     if (grad_xy)
         for (int v = 0; v < V; ++v) gv.p[v] = grad_xy[v];
     const int64_t nb = fused_bwd_blocks(n);

@@ -292,6 +292,40 @@ struct ViewPtrs {
     float* p[QG_MAX_VIEWS];
 };
 
+// One view's 2D gradient record of a Gaussian (12 floats, see project_bwd_gauss) and its projection flags.
+struct GradRec {
+    float4 g0, g1, g2;
+    uint32_t flags;
+};
+
+__device__ __forceinline__ GradRec load_grad_rec(const ViewTable& vt, const float* __restrict__ grad2d,
+                                                 int64_t g2d_view_stride, int v, int64_t i) {
+    const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
+    GradRec r;
+    r.g0 = gr[0];
+    r.g1 = gr[1];
+    r.g2 = gr[2];
+    r.flags = vt.proj[v].flags[i];
+    return r;
+}
+
+// What project_bwd_gauss<.., kPre> takes from its caller instead of loading it: the record of view 0 and the
+// old value of gxy_abs[i].  A caller that issues these loads together with its other loads waits for HBM
+// once, where the passes over the views would otherwise wait once per pass.
+struct BwdPre {
+    GradRec r0;
+    float gabs;
+};
+
+__device__ __forceinline__ BwdPre load_bwd_pre(const ViewTable& vt, const float* __restrict__ grad2d,
+                                               int64_t g2d_view_stride, const float* __restrict__ gxy_abs,
+                                               int64_t i) {
+    BwdPre p;
+    p.r0 = load_grad_rec(vt, grad2d, g2d_view_stride, 0, i);
+    p.gabs = gxy_abs ? gxy_abs[i] : 0.f;
+    return p;
+}
+
 // Adjoint of project_gauss for one Gaussian.  grad2d[v] holds per Gaussian: dx, dy, dA, dB, dC, dopacity,
 // dr, dg, db (stride 12).  Attribute plane k is read by get(k); the gradient of plane k is handed to
 // put(k, value) exactly once for planes 0..10 and the planes 11 .. 11+3(deg+1)^2-1, after every get of
@@ -300,11 +334,23 @@ struct ViewPtrs {
 // coefficient gradients are then summed over the views in those slots, after a first sweep over the views
 // that has read the coefficients for the view-direction gradient, instead of in 48 registers; the sums are
 // formed in the same order, so the results are the same.
-template <bool kShSlots = false, class Get, class Put>
+// kPre: view 0's record and the old gxy_abs[i] come from pre (load_bwd_pre) instead of memory.
+template <bool kShSlots = false, bool kPre = false, class Get, class Put>
 __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Get& get, const Put& put, int sh_deg,
                                                   const ViewTable& vt, float dilation,
                                                   const float* __restrict__ grad2d, int64_t g2d_view_stride,
-                                                  float* __restrict__ gxy_abs, const ViewPtrs& gxyv) {
+                                                  float* __restrict__ gxy_abs, const ViewPtrs& gxyv,
+                                                  BwdPre pre = BwdPre{}) {
+    // Each pass over the views carries the next view's record: it is loaded at the top of the previous
+    // iteration (before anything can skip the rest of it), so its wait overlaps that view's work.
+    auto first_rec = [&]() {
+        GradRec r{};
+        if (kPre)
+            r = pre.r0;
+        else if (vt.V > 0)
+            r = load_grad_rec(vt, grad2d, g2d_view_stride, 0, i);
+        return r;
+    };
     Gauss g;
     load_gauss(get, g);
     const int nb = (sh_deg + 1) * (sh_deg + 1);
@@ -314,13 +360,13 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     float abs_acc = 0.f;
     bool any_col = false;
     // pass 1: geometry (position, covariance, opacity) over all views
+    GradRec nxt = first_rec();
 #pragma unroll 1
     for (int v = 0; v < vt.V; ++v) {
-        const ProjDev& pd = vt.proj[v];
-        // the record is read with the flags (it exists, zero or not, for every Gaussian): one round trip
-        const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-        const float4 g0 = gr[0], g1 = gr[1];
-        const uint8_t flags = pd.flags[i];
+        const GradRec r = nxt;
+        if (v + 1 < vt.V) nxt = load_grad_rec(vt, grad2d, g2d_view_stride, v + 1, i);
+        const float4 g0 = r.g0, g1 = r.g1;
+        const uint32_t flags = r.flags;
         if (flags & 0x80) continue;
         const float gx = g0.x, gy = g0.y, gA = g0.z, gB = g0.w, gC = g1.x, go = g1.y;
         any_col = true;
@@ -380,12 +426,13 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
     // pass 2: SH colour -> coefficients and view direction (only if some view had a record)
     if (kShSlots && any_col) {
         // sweep 1: view-direction gradient, reading the coefficients
+        nxt = first_rec();
 #pragma unroll 1
         for (int v = 0; v < vt.V; ++v) {
-            const ProjDev& pd = vt.proj[v];
-            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-            const float4 g1 = gr[1], g2 = gr[2];
-            const uint8_t flags = pd.flags[i];
+            const GradRec r = nxt;
+            if (v + 1 < vt.V) nxt = load_grad_rec(vt, grad2d, g2d_view_stride, v + 1, i);
+            const float4 g1 = r.g1, g2 = r.g2;
+            const uint32_t flags = r.flags;
             if (flags & 0x80) continue;
             float gcol[3] = {g1.z, g1.w, g2.x};
 #pragma unroll
@@ -411,12 +458,13 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
 #pragma unroll
         for (int k = 0; k < 48; ++k)
             if (k < 3 * nb) put(11 + k, 0.f);
+        nxt = first_rec();
 #pragma unroll 1
         for (int v = 0; v < vt.V; ++v) {
-            const ProjDev& pd = vt.proj[v];
-            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-            const float4 g1 = gr[1], g2 = gr[2];
-            const uint8_t flags = pd.flags[i];
+            const GradRec r = nxt;
+            if (v + 1 < vt.V) nxt = load_grad_rec(vt, grad2d, g2d_view_stride, v + 1, i);
+            const float4 g1 = r.g1, g2 = r.g2;
+            const uint32_t flags = r.flags;
             if (flags & 0x80) continue;
             float gcol[3] = {g1.z, g1.w, g2.x};
 #pragma unroll
@@ -440,13 +488,14 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
         float dH[48];
 #pragma unroll
         for (int k = 0; k < 48; ++k) dH[k] = 0.f;
-    #pragma unroll 1
-    for (int v = 0; v < vt.V; ++v) {
-            const ProjDev& pd = vt.proj[v];
-            const uint8_t flags = pd.flags[i];
+        nxt = first_rec();
+#pragma unroll 1
+        for (int v = 0; v < vt.V; ++v) {
+            const GradRec r = nxt;
+            if (v + 1 < vt.V) nxt = load_grad_rec(vt, grad2d, g2d_view_stride, v + 1, i);
+            const float4 g1 = r.g1, g2 = r.g2;
+            const uint32_t flags = r.flags;
             if (flags & 0x80) continue;
-            const float4* gr = reinterpret_cast<const float4*>(grad2d + (int64_t)v * g2d_view_stride) + 3 * i;
-            const float4 g1 = gr[1], g2 = gr[2];
             float gcol[3] = {g1.z, g1.w, g2.x};
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch)
@@ -481,7 +530,7 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
         for (int k = 0; k < 48; ++k)
             if (k < 3 * nb) put(11 + k, 0.f);
     }
-    if (gxy_abs) gxy_abs[i] += abs_acc;
+    if (gxy_abs) gxy_abs[i] = (kPre ? pre.gabs : gxy_abs[i]) + abs_acc;
     // Sigma = M M^T -> dM = 2 dSig M (dSig symmetric)
     const float S[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
     float dM[9];
