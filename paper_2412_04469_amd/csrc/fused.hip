@@ -210,8 +210,15 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
         // view 0's gradient record and the old |grad xy| sum, loaded with the chunk (one wait for HBM)
         BwdPre pre{};
         if (gv) pre = load_bwd_pre(vt, grad2d, stride, gxy_abs, g);
+        // the incoming dL/dlatent, from a clamped index (a lane past n loads Gaussian n-1 and stores nothing)
+        float glat[kL];
+        const uint32_t gc = gv ? g32 : (uint32_t)(n - 1);
+#pragma unroll
+        for (int k = 0; k < kL; ++k) glat[k] = g_lat[pidx(k, ld32, gc)];
         __builtin_amdgcn_s_waitcnt(0);
         in_vgprs(pre);
+#pragma unroll
+        for (int k = 0; k < kL; ++k) asm volatile("" : "+v"(glat[k]));
         wave_sync_lds();
         // 1. add the decoded residuals in place
         if (!kDecoded) {
@@ -264,9 +271,6 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
         wave_sync_lds();
         // 3. decoder backward from the gradient in LDS; this chunk's weight gradients are added to s_acc and
         //    dL/dlatent replaces the latents in s_lat
-        float glat[kL];
-#pragma unroll
-        for (int k = 0; k < kL; ++k) glat[k] = gv ? g_lat[pidx(k, ld32, g32)] : 0.f;
         {
             const int l3 = lane_here(), q3 = l3 / 16, c3 = l3 % 16;
             BwdOps ops;

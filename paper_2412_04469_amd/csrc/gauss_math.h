@@ -476,12 +476,28 @@ __device__ __forceinline__ void project_bwd_gauss(int64_t n, int64_t i, const Ge
             float inv = rsq(vx * vx + vy * vy + vz * vz);
             float Y[16];
             sh_basis(sh_deg, vx * inv, vy * inv, vz * inv, Y);
+            // four coefficients (12 slots) at a time: all reads of a group before its writes, so the group
+            // waits for storage once
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k < nb) {
+            for (int k0 = 0; k0 < 16; k0 += 4) {
+                if (k0 >= nb) break;
+                if (k0 + 4 <= nb) {
+                    float cur[12];
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) put(11 + 3 * k + ch, get(11 + 3 * k + ch) + gcol[ch] * Y[k]);
+                    for (int j = 0; j < 12; ++j) cur[j] = get(11 + 3 * k0 + j);
+#pragma unroll
+                    for (int j = 0; j < 12; ++j) put(11 + 3 * k0 + j, cur[j] + gcol[j % 3] * Y[k0 + j / 3]);
+                } else {
+                    // a partial last group (degree 0 or 2)
+#pragma unroll
+                    for (int k = k0; k < k0 + 4; ++k)
+                        if (k < nb) {
+#pragma unroll
+                            for (int ch = 0; ch < 3; ++ch)
+                                put(11 + 3 * k + ch, get(11 + 3 * k + ch) + gcol[ch] * Y[k]);
+                        }
                 }
+            }
         }
     } else if (any_col) {
         // the coefficients are read where they live (get) when needed, so only their gradients occupy registers
