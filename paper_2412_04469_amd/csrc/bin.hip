@@ -211,13 +211,14 @@ __device__ __forceinline__ uint32_t digit_total(const SortCtl* ctl, int p) {
 // digit's items land at consecutive output positions, so neighbouring threads write neighbouring words
 // instead of every item being a scattered 4-byte write.
 // lb_cur: [nblocks][256] look-back states of this pass (zero on entry); lb_next, if given, is the next
-// pass's array: every block clears its own slot there.
+// pass's array: every block clears its own slot there.  A block with items issues their loads and the
+// reads of the pass histogram together, so that they share one wait for memory.
 // ------------------------------------------------------------------------------------------------
 template <int IPT>
 __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                     const uint32_t* count_ptr, uint32_t count_fixed, int pass,
-                                                     SortCtl* ctl, uint64_t* lb_cur, uint64_t* lb_next) {
+                                                     const uint32_t* __restrict__ count_ptr, uint32_t count_fixed,
+                                                     int pass, SortCtl* ctl, uint64_t* lb_cur, uint64_t* lb_next) {
     __shared__ uint32_t s_cnt[kWaves][kRadix];
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_bid;
@@ -231,13 +232,6 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
     const uint32_t count = count_ptr ? *count_ptr : count_fixed;
     const uint64_t blk0 = (uint64_t)bid * (IPT * kBlock);
     if (blk0 >= count) return;  // no items here; no later block has any either, so nobody waits for this one
-    const int shift = kRadixBits * pass;
-    // global start of each digit: exclusive scan of the pass histogram
-    uint32_t dtot;
-    const uint32_t dbase = block_excl_scan<uint32_t>(digit_total(ctl, pass), s_w, &dtot);
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
-    __syncthreads();
     const uint64_t base = blk0 + (uint64_t)w * (IPT * kWave);
     uint32_t key[IPT], val[IPT];
 #pragma unroll
@@ -247,6 +241,14 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
         key[r] = valid ? kin[idx] : 0u;
         val[r] = valid ? vin[idx] : 0u;
     }
+    const uint32_t dcount = digit_total(ctl, pass);  // count of digit tid in this pass, over all blocks
+    const int shift = kRadixBits * pass;
+    // global start of each digit: exclusive scan of the pass histogram
+    uint32_t dtot;
+    const uint32_t dbase = block_excl_scan<uint32_t>(dcount, s_w, &dtot);
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
+    __syncthreads();
     // phase 1: per-wave digit counts; each item keeps its rank among the equal digits of its round, the
     // round's count of that digit and the lowest lane holding it (8 | 8 | 16 bits)
     uint32_t info[IPT];
