@@ -86,6 +86,9 @@ def parse():
     p.add_argument("--batch", type=int, default=0, choices=[0, 32, 64, 128], help="blend LDS batch depth")
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-view step")
     p.add_argument("--no-frame", action="store_true", help="skip the sec/frame measurement")
+    p.add_argument("--no-masked", action="store_true", help="skip the masked-training measurement")
+    p.add_argument("--mask-fraction", type=float, default=0.65,
+                   help="fraction of a frame's iterations that are masked (0.30 N3DV, 0.65 Immersive)")
     p.add_argument("--batched-steps", type=int, default=20)
     p.add_argument("--tune", default="full", choices=["full", "quick", "none"],
                    help="blend autotuning of the batched step: all 18 candidates, 6, or the default only")
@@ -312,6 +315,90 @@ def frame_section(args):
 
 
 
+def masked_section(args):
+    """Adaptive masked training (Sec. 3.3) on the localised-change fit workload: seconds per frame to the plain
+    form's held-out PSNR for the plain form and for the masked form (the first mask_fraction of the iterations
+    render and backpropagate only the tiles that hold dilated-mask pixels), with the mask construction (the
+    dynamic split, one dynamic-only mask pass and one dilation per view) on the masked form's frame clock; the
+    fraction of tiles flagged per view and the time of a plain and of a masked step."""
+    import torch
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, GateInitializer, render_views
+    wl = synth.workload_fit_local(n=args.n)
+    cfg = FitConfig(mask_fraction=args.mask_fraction)
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    target = torch.as_tensor(wl.target_scene.planes()).to(dev)
+    gts_prev = render_views(prev, wl.cams, cfg)
+    gts = render_views(target, wl.cams, cfg)
+    held = wl.extras["held_out"]
+    gt_held = render_views(target, [held], cfg)[0]
+    V = len(wl.cams)
+    gi = GateInitializer(wl.scene.n, wl.cams, cfg)
+    gi(prev, gts_prev, gts)
+    masks = gi.masks(prev)  # buffers warm
+    torch.cuda.synchronize()
+    flagged = [round(float(f.float().mean().item()), 4) for (_, f) in masks]
+    pixels = [round(float(m.float().mean().item()), 4) for (m, _) in masks]
+    dyn = int(gi.dyn.sum().item())
+    order = np.random.default_rng(0)
+    perm = np.concatenate([order.permutation(V) for _ in range(args.frame_iters // V + 2)])
+    m_iters = int(math.ceil(args.mask_fraction * args.frame_iters))
+
+    plain = FrameFitter(prev, wl.cams, gts, cfg)
+    plain.size_capacity()
+
+    def gate_plain():
+        return gi(prev, gts_prev, gts)
+
+    traj_p, _ = _fit_to_target(plain, lambda i: plain.step(int(perm[i])), args.frame_iters, 25, held, gt_held,
+                               gate_plain)
+    tgt = traj_p[-1][2]
+    hit_p = next(s for (i, s, p) in traj_p if p >= tgt)
+    log(f"masked: plain reaches {tgt:.3f} dB at {hit_p:.3f} s")
+    del plain
+    torch.cuda.empty_cache()
+
+    fm = FrameFitter(prev, wl.cams, gts, cfg)
+    fm.size_capacity()
+
+    def gate_masked():
+        a = gi(prev, gts_prev, gts)
+        fm.set_masks(gi.masks(prev))
+        return a
+
+    traj_m, hit_m = _fit_to_target(fm, lambda i: fm.step(int(perm[i]), masked=i < m_iters), args.frame_iters, 25,
+                                   held, gt_held, gate_masked, target=tgt)
+    log(f"masked: masked form {'reaches target at %.3f s' % hit_m if hit_m else 'does not reach the target'}")
+    # step times on the same fitter (its state after the run; the views cycle)
+    stream = torch.cuda.current_stream()
+
+    def step_ms(masked, k=40):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(k):
+            fm.step(i % V, masked=masked)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    step_ms(True, 5)
+    ms_masked = step_ms(True)
+    ms_plain = step_ms(False)
+    del fm
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "target_psnr_db": tgt, "iterations": args.frame_iters,
+            "mask_fraction": args.mask_fraction, "masked_iterations": m_iters, "t_d": cfg.t_d,
+            "dilation_px": cfg.mask_dilate, "dynamic_gaussians": dyn,
+            "flagged_tile_fraction_per_view": flagged, "mask_pixel_fraction_per_view": pixels,
+            "step_ms": {"plain": round(ms_plain, 4), "masked": round(ms_masked, 4)},
+            "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p},
+            "masked": {"sec_per_frame": None if hit_m is None else round(hit_m, 4), "trajectory": traj_m},
+            "protocol": "frame clock from gate initialisation (and, masked form, the masks) through the optimiser "
+                        "steps; held-out PSNR every 25 steps with the clock paused"}
+
+
 def proposal_section(args):
     """The learned residual proposal on the 50-frame dynamic workload (300 k Gaussians, 10% moving, 20 views):
     the plain streaming fit of frames 1..F records the targets and training data; the network is trained on the
@@ -459,6 +546,8 @@ def main():
         result["batched"] = batched_section(args)
     if not args.no_frame:
         result["sec_per_frame"] = frame_section(args)
+    if not args.no_masked:
+        result["masked_training"] = masked_section(args)
     if args.proposal != "none":
         result["learned_proposal"] = proposal_section(args)
     if not args.no_cpu_baseline:

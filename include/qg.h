@@ -302,6 +302,61 @@ qg_status qg_gate_init(int64_t n, const float* d, float gamma0, float gamma1, fl
                        float* median_out, void* ws, size_t ws_bytes, qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
+/* Adaptive masked training (Sec. 3.3 "Adaptive Masked Training"; implementation details in the     */
+/* appendix: t_d = 0.001, a 48 x 48 dilation, masking for a fraction of a frame's iterations).       */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * Static/dynamic split: dynamic[i] = 1 if sqrt((sx d[i])^2 + (sy d[n + i])^2) > t_d, evaluated in double
+ * precision from the float d, else 0.  d is [2][n], e.g. the view sum of Eq. 9's viewspace gradients in
+ * pixels; sx = W / (2V), sy = H / (2V) turn it into Eq. 9's mean in normalised device coordinates, the
+ * units of the 3D-GS viewspace gradient the threshold t_d = 0.001 refers to.  Errors: QG_ERR_ARG for n < 0,
+ * sx or sy <= 0, t_d < 0 or a NULL pointer with n > 0.
+ */
+qg_status qg_dynamic_flags(int64_t n, const float* d, double sx, double sy, double t_d, uint8_t* dynamic,
+                           qg_stream stream);
+
+/*
+ * Image mask of each view: mask[v][y*W + x] = 1 if the render of the dynamic Gaussians alone reaches pixel
+ * (x, y), i.e. some entry of the pixel's tile list (vals, tile_ranges of a qg_bin of all Gaussians) with
+ * dynamic[gid] = 1 has blend alpha min(0.99, o exp(-q/2)) >= 1/255 there, evaluated exactly as in
+ * qg_render_fwd (in a dynamic-only render the first such splat always contributes).  proj, cams, V,
+ * tiling: as for qg_render_fwd.  mask[v]: device buffer of W_v * H_v bytes, fully written.
+ */
+qg_status qg_dynamic_mask(const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                          const uint32_t* vals, const uint32_t* tile_ranges, const uint8_t* dynamic,
+                          uint8_t* const* mask, qg_stream stream);
+
+/*
+ * Box dilation by a k x k kernel (k = 48 in the paper): dilated[v][y*W + x] = 1 if mask[v] has a set pixel in
+ * [x - k/2, x + k - 1 - k/2] x [y - k/2, y + k - 1 - k/2] (clipped to the image; integer division), else 0.
+ * tmp[v] (W_v * H_v bytes, distinct from mask[v] and dilated[v]) holds the row pass.  tile_flags
+ * [total tiles of the view set, global tile index as in qg_bin] = 1 if the tile contains a set dilated
+ * pixel inside the image, else 0: the tiles a masked iteration renders.  Errors: QG_ERR_ARG for k outside
+ * [1, 1024], a bad view set or a NULL / aliased buffer.
+ */
+qg_status qg_dilate_mask(const qg_camera* cams, int32_t V, qg_tiling tiling, int32_t k, const uint8_t* const* mask,
+                         uint8_t* const* tmp, uint8_t* const* dilated, uint8_t* tile_flags, qg_stream stream);
+
+/*
+ * Masked iteration: every tile t with tile_flags[t] = 0 gets the empty range [start, start) in tile_ranges
+ * (call after qg_bin, before the blend kernels).  qg_render_fwd then writes the background there
+ * (T_final = 1) and the blend adjoint adds nothing for it, which is exact when the image gradient is zero on
+ * those tiles (qg_l1_loss_masked with the dilated mask).
+ */
+qg_status qg_mask_tile_ranges(int64_t total_tiles, uint32_t* tile_ranges, const uint8_t* tile_flags,
+                              qg_stream stream);
+
+/*
+ * qg_l1_loss restricted to the pixels set in mask [plane bytes; element i of the image, [C][plane] planar,
+ * uses mask[i % plane]]: elements of unset pixels get grad_image = 0 and add nothing to the partial sums.
+ * The gradient scale stays scale / count (the full image's normalisation, the masked-iteration reading), so
+ * qg_loss_reduce(count, ...) gives sum over masked elements of |image - gt| / count.  count must be a
+ * multiple of plane.
+ */
+qg_status qg_l1_loss_masked(int64_t count, int64_t plane, const float* image, const float* gt, const uint8_t* mask,
+                            float scale, float* grad_image, double* partials, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
 /* Learned residual proposal (not a method of the paper: a learned replacement for zero-initialised  */
 /* residual parameters of frame t, Sec. 3.2 / Eq. 5-8; its analogue in the paper is Eq. 10).         */
 /* ---------------------------------------------------------------------------------------------- */

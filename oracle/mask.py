@@ -6,7 +6,9 @@ The paper splits the Gaussians into static and dynamic ones by a threshold t_d o
 image mask with a 48 x 48 kernel, and for a fraction of a frame's iterations renders and backpropagates
 only there.  Readings taken here where the text leaves a choice open:
 
-* dynamic: ||d_i|| / V > t_d, with d the view sum of Eq. 9's bracket (so d / V is Eq. 9's mean), t_d = 0.001;
+* dynamic: ||d_i|| / V > t_d, with d the view sum of Eq. 9's bracket (so d / V is Eq. 9's mean) taken in
+  normalised device coordinates, the units of the viewspace gradient of the 3D-GS rasterizer the method builds
+  on (pixel gradients times W/2 and H/2), t_d = 0.001;
 * the image mask of a view: the pixels the dynamic-only render reaches (T_final < 1), i.e. where some dynamic
   splat has alpha >= 1/255;
 * dilation by a k x k box (k = 48): pixel (x, y) is set if the mask has a set pixel in
@@ -31,10 +33,13 @@ ALPHA_MIN = 1.0 / 255.0
 ALPHA_MAX = 0.99
 
 
-def dynamic_flags(d: np.ndarray, n_views: int, t_d: float = 1e-3) -> np.ndarray:
-    """d [2][N] (view sum of Eq. 9's bracket) -> bool [N]: sqrt(dx^2 + dy^2) / V > t_d."""
+def dynamic_flags(d: np.ndarray, n_views: int, width: int, height: int, t_d: float = 1e-3) -> np.ndarray:
+    """d [2][N] (view sum of Eq. 9's bracket, in pixels) -> bool [N]: the norm of the view mean in normalised
+    device coordinates, ||(dx W/2, dy H/2)|| / V, exceeds t_d."""
     d = np.asarray(d, np.float64)
-    return np.sqrt(d[0] * d[0] + d[1] * d[1]) * (1.0 / n_views) > t_d
+    x = d[0] * ((width / 2.0) / n_views)
+    y = d[1] * ((height / 2.0) / n_views)
+    return np.sqrt(x * x + y * y) > t_d
 
 
 def footprint(xy, conic, opacity, width: int, height: int) -> np.ndarray:

@@ -18,6 +18,29 @@ __device__ __forceinline__ float l1_term(float x, float y, float gscale, float& 
     return d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
 }
 
+// The block's two sums (in double) to part[2b], part[2b + 1], in a fixed order.
+__device__ __forceinline__ void l1_block_partials(float sa, float sb, double* s_a, double* s_b, double* part) {
+    double da = sa, db = sb;
+    for (int o = 32; o >= 1; o >>= 1) {
+        da += __shfl_xor(da, o);
+        db += __shfl_xor(db, o);
+    }
+    if (__lane_id() == 0) {
+        s_a[threadIdx.x / kWave] = da;
+        s_b[threadIdx.x / kWave] = db;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0, tb = 0;
+        for (int w = 0; w < kLBlock / kWave; ++w) {
+            ta += s_a[w];
+            tb += s_b[w];
+        }
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tb;
+    }
+}
+
 // A block covers kLTile consecutive elements.  vec: every pointer is 16-byte aligned; a block lying wholly
 // inside the range then moves them as float4 (thread t takes quads t, t + 256, ...).
 __global__ __launch_bounds__(kLBlock) void k_l1(int64_t count, const float* __restrict__ img,
@@ -55,25 +78,28 @@ __global__ __launch_bounds__(kLBlock) void k_l1(int64_t count, const float* __re
             }
         }
     }
-    double da = sa, db = sb;
-    for (int o = 32; o >= 1; o >>= 1) {
-        da += __shfl_xor(da, o);
-        db += __shfl_xor(db, o);
-    }
-    if (__lane_id() == 0) {
-        s_a[threadIdx.x / kWave] = da;
-        s_b[threadIdx.x / kWave] = db;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double ta = 0, tb = 0;
-        for (int w = 0; w < kLBlock / kWave; ++w) {
-            ta += s_a[w];
-            tb += s_b[w];
+    l1_block_partials(sa, sb, s_a, s_b, part);
+}
+
+// As k_l1 over the elements whose pixel (index mod plane) is set in mask; the others get a zero gradient and
+// add nothing to the sums.  The scale stays 1/count (the masked-iteration reading of Sec. 3.3: the loss of
+// the rendered pixels at the full image's normalisation).
+__global__ __launch_bounds__(kLBlock) void k_l1_masked(int64_t count, int64_t plane, const float* __restrict__ img,
+                                                       const float* __restrict__ gt,
+                                                       const uint8_t* __restrict__ mask, float gscale,
+                                                       float* __restrict__ grad, double* __restrict__ part) {
+    __shared__ double s_a[kLBlock / kWave], s_b[kLBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kLTile;
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int r = 0; r < kLIPT; ++r) {
+        const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
+        if (i < count) {
+            const float gr = mask[i % plane] ? l1_term(img[i], gt[i], gscale, sa, sb) : 0.f;
+            if (grad) grad[i] = gr;
         }
-        part[2 * blockIdx.x] = ta;
-        part[2 * blockIdx.x + 1] = tb;
     }
+    l1_block_partials(sa, sb, s_a, s_b, part);
 }
 
 __global__ void k_loss_reduce(int64_t nb, int64_t count, const double* __restrict__ part, double* __restrict__ out) {
@@ -231,6 +257,25 @@ extern "C" qg_status qg_l1_loss(int64_t count, const float* image, const float* 
         k_l1<<<(unsigned)nb, kLBlock, 0, s>>>(count, image, gt, gs, grad_image, partials, vec);
     }
     QG_LAUNCH_CHECK("qg_l1_loss");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_l1_loss_masked(int64_t count, int64_t plane, const float* image, const float* gt,
+                                       const uint8_t* mask, float scale, float* grad_image, double* partials,
+                                       qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(count >= 0 && plane >= 1 && count % plane == 0, "count=%lld must be a multiple of plane=%lld >= 1",
+               (long long)count, (long long)plane);
+    QG_REQUIRE(partials, "partials is NULL");
+    QG_REQUIRE(count == 0 || (image && gt && mask), "image/gt/mask NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = qg_loss_blocks(count);
+    const float gs = count > 0 ? scale / (float)count : 0.f;
+    {
+        QG_TIMED("l1", s);
+        k_l1_masked<<<(unsigned)nb, kLBlock, 0, s>>>(count, plane, image, gt, mask, gs, grad_image, partials);
+    }
+    QG_LAUNCH_CHECK("qg_l1_loss_masked");
     return QG_OK;
 }
 

@@ -636,6 +636,162 @@ __global__ void k_sched_scatter(int64_t total, const uint32_t* __restrict__ rang
     order[pos] = (uint32_t)t;
 }
 
+// ---- adaptive masked training (Sec. 3.3, "Adaptive Masked Training") -------------------------------
+struct ViewPtrsB8 {
+    uint8_t* p[QG_MAX_VIEWS];
+};
+struct ViewPtrsCB8 {
+    const uint8_t* p[QG_MAX_VIEWS];
+};
+
+// Gaussians whose score ||(sx d_x, sy d_y)|| exceeds t_d are dynamic; decided in double precision.
+__global__ void k_dyn_flags(int64_t n, const float* __restrict__ d, double sx, double sy, double t_d,
+                            uint8_t* __restrict__ dyn) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = (double)d[i] * sx, y = (double)d[n + i] * sy;
+    dyn[i] = sqrt(x * x + y * y) > t_d ? 1 : 0;
+}
+
+// Image mask of each view: the pixels that a render of the dynamic Gaussians alone reaches.  In such a
+// render the first splat with alpha >= 1/255 at a pixel always contributes (T' >= 0.01 > 1e-4 after it), so
+// the mask is the union over the tile's dynamic entries of the blend forward's own alpha test, evaluated
+// with the same operands.  Entries are staged 64 at a time; only the dynamic ones are kept.
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_dyn_mask(ViewTable vt, const uint32_t* __restrict__ vals,
+                                                 const uint32_t* __restrict__ ranges, const uint8_t* __restrict__ dyn,
+                                                 ViewPtrsB8 mask, int64_t per_xcd) {
+    constexpr int PPL = TileGeom<TW, TH>::PPL;
+    constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
+    __shared__ float4 s_a[64];   // x, y, opacity, A'
+    __shared__ float2 s_b[64];   // 2B', C'
+    const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
+    if (tile >= vt.total_tiles) return;
+    const int v = view_of_tile(vt, (uint32_t)tile);
+    const CamDev& cam = vt.cam[v];
+    const int local = (int)(tile - cam.tile_off);
+    const int tx = local % cam.grid_w, ty = local / cam.grid_w;
+    const int lane = threadIdx.x;
+    const int px = tx * TW + (lane % TW);
+    const int py0 = ty * TH + lane / TW;
+    const float fx = (float)px + 0.5f;
+    float fy[PPL];
+    bool hit[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        fy[k] = (float)(py0 + k * RPK) + 0.5f;
+        hit[k] = false;
+    }
+    const uint32_t b0 = ranges[2 * tile], e = ranges[2 * tile + 1];
+    const float* __restrict__ splat = vt.proj[v].splat;
+    for (uint32_t b = b0; b < e; b += 64) {
+        const uint32_t j = b + (uint32_t)lane;
+        bool keep = false;
+        float4 r0, r1;
+        if (j < e) {
+            const uint32_t gid = vals[j];
+            if (dyn[gid]) {
+                const float4* r = reinterpret_cast<const float4*>(splat) + 3 * (size_t)gid;
+                r0 = r[0];
+                r1 = r[1];
+                keep = true;
+            }
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int dst = (int)__popcll(m & ((1ull << lane) - 1ull));
+            s_a[dst] = make_float4(r0.x, r0.y, r0.z, kFold * r1.x);
+            s_b[dst] = make_float2(2.f * kFold * r1.y, kFold * r1.z);
+        }
+        __syncthreads();
+        const int cnt = (int)__popcll(m);
+        for (int jj = 0; jj < cnt; ++jj) {
+            const float4 a = s_a[jj];
+            const float2 bb = s_b[jj];
+            const float dx = fx - a.x;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const float dy = fy[k] - a.y;
+                const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
+                hit[k] = hit[k] || fminf(kAlphaMax, raw) >= kAlphaMin;
+            }
+        }
+        __syncthreads();
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) all = all && hit[k];
+        if (__ballot(!all) == 0) break;
+    }
+    uint8_t* out = mask.p[v];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int py = py0 + k * RPK;
+        if (px < cam.width && py < cam.height) out[(size_t)py * cam.width + px] = hit[k] ? 1 : 0;
+    }
+}
+
+// Box dilation, separable: out[y][x] = 1 if in has a set pixel at x + [lo, hi] (rows) or y + [lo, hi]
+// (columns), clipped to the image.
+__global__ void k_dilate_rows(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, int W, int H, int lo,
+                              int hi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)W * H) return;
+    const int x = (int)(i % W);
+    const uint8_t* row = in + (i - x);
+    const int x0 = max(0, x + lo), x1 = min(W - 1, x + hi);
+    uint8_t any = 0;
+    for (int xx = x0; xx <= x1; ++xx) any |= row[xx];
+    out[i] = any ? 1 : 0;
+}
+
+__global__ void k_dilate_cols(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, int W, int H, int lo,
+                              int hi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)W * H) return;
+    const int x = (int)(i % W), y = (int)(i / W);
+    const int y0 = max(0, y + lo), y1 = min(H - 1, y + hi);
+    uint8_t any = 0;
+    for (int yy = y0; yy <= y1; ++yy) any |= in[(size_t)yy * W + x];
+    out[i] = any ? 1 : 0;
+}
+
+// Tile t is rendered in a masked iteration if its pixels (inside the image) include a set dilated pixel.
+__global__ __launch_bounds__(64) void k_tile_flags(ViewTable vt, ViewPtrsCB8 dil, int TW, int TH,
+                                                   uint8_t* __restrict__ flags) {
+    const int64_t tile = blockIdx.x;
+    if (tile >= vt.total_tiles) return;
+    const int v = view_of_tile(vt, (uint32_t)tile);
+    const CamDev& cam = vt.cam[v];
+    const int local = (int)(tile - cam.tile_off);
+    const int tx = local % cam.grid_w, ty = local / cam.grid_w;
+    bool any = false;
+    for (int q = threadIdx.x; q < TW * TH; q += 64) {
+        const int x = tx * TW + q % TW, y = ty * TH + q / TW;
+        if (x < cam.width && y < cam.height && dil.p[v][(size_t)y * cam.width + x]) any = true;
+    }
+    const uint64_t m = __ballot(any);
+    if (threadIdx.x == 0) flags[tile] = m ? 1 : 0;
+}
+
+// A tile that is not rendered gets an empty range [start, start): the blend forward then writes the
+// background there and the adjoint adds nothing.
+__global__ void k_mask_ranges(int64_t total, uint32_t* __restrict__ ranges, const uint8_t* __restrict__ flags) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total && !flags[t]) ranges[2 * t + 1] = ranges[2 * t];
+}
+
+template <int TW, int TH>
+qg_status launch_dyn_mask(const ViewTable& vt, const uint32_t* vals, const uint32_t* ranges, const uint8_t* dyn,
+                          const ViewPtrsB8& mask, hipStream_t s) {
+    const int64_t per = ceil_div(vt.total_tiles, 8);
+    {
+        QG_TIMED("dynamic_mask", s);
+        k_dyn_mask<TW, TH><<<(unsigned)(per * 8), 64, 0, s>>>(vt, vals, ranges, dyn, mask, per);
+    }
+    QG_LAUNCH_CHECK("qg_dynamic_mask");
+    return QG_OK;
+}
+
 }  // namespace
 
 qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t* vals, const uint32_t* ranges,
@@ -740,5 +896,76 @@ extern "C" qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile
         k_sched_scatter<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist, order);
     }
     QG_LAUNCH_CHECK("qg_schedule_tiles");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_dynamic_flags(int64_t n, const float* d, double sx, double sy, double t_d, uint8_t* dynamic,
+                                      qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0, "n < 0");
+    QG_REQUIRE(sx > 0.0 && sy > 0.0 && t_d >= 0.0, "need sx, sy > 0 and t_d >= 0");
+    if (n == 0) return QG_OK;
+    QG_REQUIRE(d && dynamic, "a pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    k_dyn_flags<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, d, sx, sy, t_d, dynamic);
+    QG_LAUNCH_CHECK("qg_dynamic_flags");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_dynamic_mask(const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                                     const uint32_t* vals, const uint32_t* tile_ranges, const uint8_t* dynamic,
+                                     uint8_t* const* mask, qg_stream stream) {
+    clear_error();
+    ViewTable vt;
+    if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
+    QG_REQUIRE(tile_ranges && dynamic && mask, "a required pointer is NULL");
+    ViewPtrsB8 mp = {};
+    for (int v = 0; v < V; ++v) {
+        QG_REQUIRE(mask[v], "view %d: mask is NULL", v);
+        mp.p[v] = mask[v];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (tiling.tile_w == 16) return launch_dyn_mask<16, 16>(vt, vals, tile_ranges, dynamic, mp, s);
+    if (tiling.tile_w == 8) return launch_dyn_mask<8, 8>(vt, vals, tile_ranges, dynamic, mp, s);
+    return launch_dyn_mask<32, 8>(vt, vals, tile_ranges, dynamic, mp, s);
+}
+
+extern "C" qg_status qg_dilate_mask(const qg_camera* cams, int32_t V, qg_tiling tiling, int32_t k,
+                                    const uint8_t* const* mask, uint8_t* const* tmp, uint8_t* const* dilated,
+                                    uint8_t* tile_flags, qg_stream stream) {
+    clear_error();
+    ViewTable vt;
+    if (!make_view_table(cams, nullptr, V, tiling, false, &vt)) return QG_ERR_ARG;
+    QG_REQUIRE(k >= 1 && k <= 1024, "k=%d outside [1, 1024]", k);
+    QG_REQUIRE(mask && tmp && dilated && tile_flags, "a required pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int lo = -(k / 2), hi = k - 1 - k / 2;
+    ViewPtrsCB8 dp = {};
+    for (int v = 0; v < V; ++v) {
+        QG_REQUIRE(mask[v] && tmp[v] && dilated[v], "view %d: a buffer is NULL", v);
+        QG_REQUIRE(mask[v] != tmp[v] && tmp[v] != dilated[v], "view %d: tmp must differ from mask and dilated", v);
+        const int W = cams[v].width, H = cams[v].height;
+        const unsigned grid = (unsigned)ceil_div((int64_t)W * H, 256);
+        k_dilate_rows<<<grid, 256, 0, s>>>(mask[v], tmp[v], W, H, lo, hi);
+        k_dilate_cols<<<grid, 256, 0, s>>>(tmp[v], dilated[v], W, H, lo, hi);
+        dp.p[v] = dilated[v];
+    }
+    k_tile_flags<<<(unsigned)vt.total_tiles, 64, 0, s>>>(vt, dp, tiling.tile_w, tiling.tile_h, tile_flags);
+    QG_LAUNCH_CHECK("qg_dilate_mask");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_mask_tile_ranges(int64_t total_tiles, uint32_t* tile_ranges, const uint8_t* tile_flags,
+                                         qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(total_tiles >= 1 && total_tiles < (1ll << 32), "total_tiles=%lld outside [1, 2^32)",
+               (long long)total_tiles);
+    QG_REQUIRE(tile_ranges && tile_flags, "a pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        QG_TIMED("mask_ranges", s);
+        k_mask_ranges<<<(unsigned)ceil_div(total_tiles, 256), 256, 0, s>>>(total_tiles, tile_ranges, tile_flags);
+    }
+    QG_LAUNCH_CHECK("qg_mask_tile_ranges");
     return QG_OK;
 }

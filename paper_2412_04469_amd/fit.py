@@ -46,6 +46,12 @@ class FitConfig:
     # rate (a step over several views has a lower-variance gradient and can take a longer step)
     group_views: int = 16
     batched_lr_scale: float = 1.0
+    # adaptive masked training (Sec. 3.3; appendix): dynamic if the view-mean score ||d|| exceeds t_d; the
+    # dynamic-only render's mask is dilated by a mask_dilate x mask_dilate box; the first mask_fraction of a
+    # frame's iterations render and backpropagate only the tiles holding masked pixels
+    t_d: float = 1e-3
+    mask_dilate: int = 48
+    mask_fraction: float = 0.0
 
 
 def xavier_decoder(seed: int, L=8, H=32, M=56):
@@ -168,8 +174,13 @@ class FrameFitter(ResidualState):
         self.rast.render(stream)
         return self.rast.images[0]
 
-    def step(self, v, stream=None):
-        """One optimiser iteration on training view v (enqueue only)."""
+    def set_masks(self, masks):
+        """Per-view (dilated pixel mask [H][W] u8, tile flags u8) from GateInitializer.masks, for masked steps."""
+        self.masks = masks
+
+    def step(self, v, stream=None, masked=False):
+        """One optimiser iteration on training view v (enqueue only).  masked: render and backpropagate only the
+        tiles flagged in view v's mask, with the L1 over its masked pixels (Sec. 3.3)."""
         c = self.cfg
         r = self.rast
         if self.fused:
@@ -178,11 +189,19 @@ class FrameFitter(ResidualState):
                                  self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
                                  r.t_proj, self.attrs, self.gate, None, stream)
             r.bin(stream)
+            if masked:
+                qg.qg_mask_tile_ranges(r.total_tiles, r.ranges, self.masks[v][1], stream)
             r.render(stream)
         else:
+            assert not masked, "masked steps use the fused path"
             self.decode(stream)
             self.forward_view(v, stream)
-        qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
+        if masked:
+            pix = self.masks[v][0]
+            qg.qg_l1_loss_masked(self.count, pix.numel(), r.images[0], self.gts[v], pix, 1.0, self.grad_img,
+                                 self.loss_part, stream)
+        else:
+            qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
         # parameter gradients are zero here: they start zeroed and qg_adam_multi clears them after use
         if self.fused:
             qg.qg_render_decode_bwd(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
@@ -433,6 +452,32 @@ class GateInitializer:
             self.rast.backward(prev_attrs, [self.gimg], self.scratch, grad_xy=[self.d])
         qg.qg_gate_init(n, self.d, c.gamma0, c.gamma1, c.tau, self.a, self.p, self.med, self.ws, self.ws_bytes)
         return self.a
+
+    def masks(self, prev_attrs):
+        """Adaptive masked training (Sec. 3.3), after __call__ has accumulated d: the dynamic Gaussians
+        (||d|| / V > t_d, d in normalised device coordinates: pixels times (W/2, H/2)), then per view the pixels their render alone reaches (tile lists of A_{t-1}), dilated
+        by the mask_dilate box, and the flags of the tiles holding them.  Returns [(pixel mask, tile flags)]."""
+        c = self.cfg
+        n = prev_attrs.shape[1]
+        dev = prev_attrs.device
+        if not hasattr(self, "dyn"):
+            self.dyn = torch.empty(n, dtype=torch.uint8, device=dev)
+            cam0 = self.cams[0]
+            self.raw = torch.empty(cam0.height, cam0.width, dtype=torch.uint8, device=dev)
+            self.tmp = torch.empty_like(self.raw)
+            self.mask_bufs = [(torch.empty_like(self.raw), torch.empty(self.rast.total_tiles, dtype=torch.uint8,
+                                                                       device=dev)) for _ in self.cams]
+        cam0, V = self.cams[0], len(self.cams)
+        qg.qg_dynamic_flags(n, self.d, (cam0.width / 2.0) / V, (cam0.height / 2.0) / V, c.t_d, self.dyn)
+        r = self.rast
+        for v, cam in enumerate(self.cams):
+            r.set_cameras([cam])
+            r.project(prev_attrs)
+            r.bin()
+            qg.qg_dynamic_mask(r.t_proj, r.qcams, r.tile, r.vals, r.ranges, self.dyn, [self.raw])
+            pix, flags = self.mask_bufs[v]
+            qg.qg_dilate_mask(r.qcams, r.tile, c.mask_dilate, [self.raw], [self.tmp], [pix], flags)
+        return self.mask_bufs
 
 
 def gate_init(d: torch.Tensor, cfg: FitConfig = FitConfig()):

@@ -82,6 +82,11 @@ def lib():
                               i32),
             "qg_loss_blocks": ([i64], i64),
             "qg_l1_loss": ([i64, P, P, f32, P, P, P], i32),
+            "qg_l1_loss_masked": ([i64, i64, P, P, P, f32, P, P, P], i32),
+            "qg_dynamic_flags": ([i64, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P], i32),
+            "qg_dynamic_mask": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P], i32),
+            "qg_dilate_mask": ([CAM, i32, qg_tiling, i32, P, P, P, P, P], i32),
+            "qg_mask_tile_ranges": ([i64, P, P, P], i32),
             "qg_loss_reduce": ([i64, P, P, P], i32),
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
             "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
@@ -305,6 +310,32 @@ def qg_loss_blocks(count):
 def qg_l1_loss(count, image, gt, scale, grad_image, partials, stream=None):
     _check(lib().qg_l1_loss(int(count), _ptr(image), _ptr(gt), float(scale), _ptr(grad_image), _ptr(partials),
                             _stream(stream)))
+
+
+def qg_l1_loss_masked(count, plane, image, gt, mask, scale, grad_image, partials, stream=None):
+    _check(lib().qg_l1_loss_masked(int(count), int(plane), _ptr(image), _ptr(gt), _ptr(mask), float(scale),
+                                   _ptr(grad_image), _ptr(partials), _stream(stream)))
+
+
+def qg_dynamic_flags(n, d, sx, sy, t_d, dynamic, stream=None):
+    _check(lib().qg_dynamic_flags(int(n), _ptr(d), float(sx), float(sy), float(t_d), _ptr(dynamic), _stream(stream)))
+
+
+def qg_dynamic_mask(proj, cams, tile, vals, tile_ranges, dynamic, mask, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    _check(lib().qg_dynamic_mask(pa, ca, len(cams), tile, _ptr(vals), _ptr(tile_ranges), _ptr(dynamic),
+                                 _ptr_array(mask), _stream(stream)))
+
+
+def qg_dilate_mask(cams, tile, k, mask, tmp, dilated, tile_flags, stream=None):
+    ca = camera_array(cams)
+    _check(lib().qg_dilate_mask(ca, len(cams), tile, int(k), _ptr_array(mask), _ptr_array(tmp), _ptr_array(dilated),
+                                _ptr(tile_flags), _stream(stream)))
+
+
+def qg_mask_tile_ranges(total_tiles, tile_ranges, tile_flags, stream=None):
+    _check(lib().qg_mask_tile_ranges(int(total_tiles), _ptr(tile_ranges), _ptr(tile_flags), _stream(stream)))
 
 
 def qg_loss_reduce(count, partials, out, stream=None):

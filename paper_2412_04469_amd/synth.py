@@ -203,6 +203,30 @@ def workload_fit(n: int = 300_000, width: int = 1352, height: int = 1014, n_view
     return Workload("gauss300k_1352x1014_20view_fit", sc, cams, gt, extras={"held_out": held})
 
 
+def workload_fit_local(n: int = 300_000, width: int = 1352, height: int = 1014, n_views: int = 20,
+                       frac_move: float = 0.02) -> Workload:
+    """The per-frame fit scene and cameras of workload_fit with spatially localised change (a moving object in a
+    static scene): the frac_move of the Gaussians nearest to the point (0.8, 0.4, 0.0) are moved by u*A
+    (u uniform on S^2, A ~ U(0.05, 0.3)) and half of those also get their SH DC shifted by N(0, 0.1)."""
+    rng = rng_for(1)
+    sc = draw_scene(rng, n, 2.0, -4.0, 0.5)
+    rng2 = rng_for(5)
+    gt = sc.copy()
+    centre = np.array([0.8, 0.4, 0.0])
+    k = int(round(frac_move * n))
+    dist = np.linalg.norm(sc.means.astype(np.float64) - centre, axis=1)
+    mv = np.sort(np.argsort(dist, kind="stable")[:k])
+    u = rng2.normal(size=(k, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    amp = rng2.uniform(0.05, 0.3, size=k)
+    gt.means[mv] = (sc.means[mv].astype(np.float64) + u * amp[:, None]).astype(np.float32)
+    cc = mv[rng2.permutation(k)[:k // 2]]
+    gt.sh[cc, 0, :] = (sc.sh[cc, 0, :].astype(np.float64) + rng2.normal(0.0, 0.1, size=(len(cc), 3))).astype(np.float32)
+    cams = arc_cameras(n_views, 5.0, 120.0, width, height)
+    held = make_camera((0.0, 0.0, -5.0), width, height)
+    return Workload("gauss300k_1352x1014_20view_fit_local", sc, cams, gt, extras={"held_out": held, "moved": mv})
+
+
 def workload_batched(n: int = 500_000) -> Workload:
     """12 views of one timestep on the 120 degree arc at uneven resolutions: even k at 1352x1014,
     k in {1,5,7,11} at 1920x1080, k in {3,9} at 960x540; f = W per view."""

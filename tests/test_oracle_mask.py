@@ -104,10 +104,17 @@ def test_single_dynamic_splat_footprint_count():
 
 def test_dynamic_flags_threshold_is_strict_on_the_view_mean():
     V, t = 4, 1e-3
-    # norms 3-4-5 triangles: 5e-3 / 4 > 1e-3; 4e-3 / 4 == 1e-3 is not dynamic; 0 is static
+    # a 2 x 2 image makes the NDC factor 1: norms 5e-3 / 4 > 1e-3; 4e-3 / 4 == 1e-3 is not dynamic; 0 is static
     d = np.array([[3e-3, 0.0, 0.0, -2.4e-3], [4e-3, 4e-3, 0.0, 3.2e-3]])
-    assert list(M.dynamic_flags(d, V, t)) == [True, False, False, False]
-    assert list(M.dynamic_flags(d, 1, t)) == [True, True, False, True]
+    assert list(M.dynamic_flags(d, V, 2, 2, t)) == [True, False, False, False]
+    assert list(M.dynamic_flags(d, 1, 2, 2, t)) == [True, True, False, True]
+
+
+def test_dynamic_flags_use_ndc_units_per_axis():
+    """A 1-pixel gradient is 2/W (x) or 2/H (y) in NDC: at W = 4, H = 2 the x component counts twice."""
+    d = np.array([[1e-3, 0.0], [0.0, 1e-3]])
+    assert list(M.dynamic_flags(d, 1, 4, 2, 1e-3)) == [True, False]
+    assert list(M.dynamic_flags(d, 1, 1352, 1014, 0.6)) == [True, False]  # 0.676 and 0.507
 
 
 def test_masked_iterations():
