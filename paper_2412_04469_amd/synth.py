@@ -204,15 +204,16 @@ def workload_fit(n: int = 300_000, width: int = 1352, height: int = 1014, n_view
 
 
 def workload_fit_local(n: int = 300_000, width: int = 1352, height: int = 1014, n_views: int = 20,
-                       frac_move: float = 0.02) -> Workload:
+                       frac_move: float = 0.003, centre=(0.5, 0.3, -2.5)) -> Workload:
     """The per-frame fit scene and cameras of workload_fit with spatially localised change (a moving object in a
-    static scene): the frac_move of the Gaussians nearest to the point (0.8, 0.4, 0.0) are moved by u*A
-    (u uniform on S^2, A ~ U(0.05, 0.3)) and half of those also get their SH DC shifted by N(0, 0.1)."""
+    static scene): the frac_move of the Gaussians nearest to `centre` (on the camera side of the cloud, so the
+    object is visible) are moved by u*A (u uniform on S^2, A ~ U(0.05, 0.3)) and half of those also get their
+    SH DC shifted by N(0, 0.1)."""
     rng = rng_for(1)
     sc = draw_scene(rng, n, 2.0, -4.0, 0.5)
     rng2 = rng_for(5)
     gt = sc.copy()
-    centre = np.array([0.8, 0.4, 0.0])
+    centre = np.asarray(centre, np.float64)
     k = int(round(frac_move * n))
     dist = np.linalg.norm(sc.means.astype(np.float64) - centre, axis=1)
     mv = np.sort(np.argsort(dist, kind="stable")[:k])
