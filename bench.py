@@ -44,7 +44,7 @@ BYTES_PER_GAUSS = {"project": 236.0 + 73.0, "decode_fwd": 524.0, "decode_bwd": 3
 # device copy run in the same process (--copy-probe-mib).  The figure is reported only while the kernel's source
 # file still has the hash it had when the counters were taken.
 TRAFFIC = {
-    "blend_bwd": {"bytes_per_launch": 107755653, "source": "paper_2412_04469_amd/csrc/render.hip", "sha": "fcca498f3338e206",
+    "blend_bwd": {"bytes_per_launch": 107759153, "source": "paper_2412_04469_amd/csrc/render.hip", "sha": "413ffcac759c2e13",
                   "profile": "profiles/blend_bwd_traffic_gauss300k_1352x1014.md"},
 }
 
