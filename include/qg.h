@@ -404,6 +404,19 @@ qg_status qg_proposal_bwd(int64_t m, const uint32_t* idx, int64_t n, int64_t ld,
  * them in a fixed order into out[0] = L1, out[1] = MSE of the clamped image (PSNR = -10 log10 MSE).
  */
 int64_t qg_loss_blocks(int64_t count);
+
+/*
+ * D-SSIM term of Eq. 3 for an image [C][H][W] (planar float32) against gt: SSIM per pixel and channel under an
+ * 11 x 11 Gaussian window (sigma 1.5, taps normalised to sum 1, zero padding outside the image), C1 = 0.01^2,
+ * C2 = 0.03^2; D-SSIM = 1 - mean SSIM.  dssim_out (device, 1 double, may be NULL) receives D-SSIM, summed in
+ * a fixed order.  grad_image (may be NULL) is incremented (+=) by weight * dD-SSIM/dimage, so an L1
+ * gradient written first with scale (1 - weight) yields Eq. 3's (1 - lambda) L1 + lambda D-SSIM (the
+ * paper does not give lambda; 3D-GS uses 0.2).  ws: qg_ssim_workspace_size(C, H, W) bytes.
+ * Errors: QG_ERR_ARG for bad sizes, NULL image/gt, both outputs NULL or a short workspace.
+ */
+size_t qg_ssim_workspace_size(int32_t C, int32_t H, int32_t W);
+qg_status qg_ssim_loss(int32_t C, int32_t H, int32_t W, const float* image, const float* gt, float weight,
+                       float* grad_image, double* dssim_out, void* ws, size_t ws_bytes, qg_stream stream);
 qg_status qg_l1_loss(int64_t count, const float* image, const float* gt, float scale, float* grad_image,
                      double* partials, qg_stream stream);
 qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_stream stream);

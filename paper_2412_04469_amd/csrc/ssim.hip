@@ -1,0 +1,215 @@
+// D-SSIM term of the image loss (Eq. 3): SSIM under an 11 x 11 Gaussian window (sigma 1.5, zero padding,
+// C1 = 0.01^2, C2 = 0.03^2), its mean over pixels and channels, and the gradient of weight * (1 - mean SSIM)
+// with respect to the rendered image.
+//
+// Forward (k_ssim_fwd): a block owns a 32 x 8 tile of one channel.  It stages x and y with a 5-pixel halo in
+// LDS (zero outside the image), runs the window's horizontal pass for the five moments (x, y, x^2, y^2, xy)
+// over the halo rows, then the vertical pass, one output pixel per thread.  From mu_x, E[x^2], E[xy] (and the
+// same of y) it forms SSIM and the per-pixel partials of the loss with respect to mu_x, E[x^2] and E[xy]:
+//   dS/dmu_x = 2 mu_y (A2 - A1) / (B1 B2) - 2 mu_x S (1/B1 - 1/B2),  dS/dE[x^2] = -S / B2,
+//   dS/dE[xy] = 2 A1 / (B1 B2),
+// with A1 = 2 mu_x mu_y + C1, A2 = 2 sigma_xy + C2, B1 = mu_x^2 + mu_y^2 + C1, B2 = sigma_x^2 + sigma_y^2 + C2.
+// Backward (k_ssim_bwd): each moment is a zero-padded correlation with the symmetric window, so its adjoint
+// blurs the partial maps with the same window; dL/dx = blur(P_mu) + 2 x blur(P_xx) + y blur(P_xy).
+#include <cmath>
+
+#include "qg_internal.h"
+
+namespace qg {
+namespace {
+
+constexpr int kSR = 5;             // window radius (11 taps)
+constexpr int kSW = 2 * kSR + 1;
+constexpr int kSTW = 32, kSTH = 8;  // output tile
+constexpr int kSIW = kSTW + 2 * kSR, kSIH = kSTH + 2 * kSR;  // staged input tile
+constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
+
+struct Taps {
+    float g[kSW];
+};
+
+// Stage n planes of a tile with halo into s[n][kSIH][kSIW] (zero outside the image).
+template <int N>
+__device__ __forceinline__ void stage(const float* const (&src)[N], float (*s)[kSIH][kSIW], int x0, int y0, int W,
+                                      int H) {
+    for (int i = threadIdx.x; i < kSIH * kSIW; i += blockDim.x) {
+        const int r = i / kSIW, c = i % kSIW;
+        const int x = x0 - kSR + c, y = y0 - kSR + r;
+        const bool in = x >= 0 && x < W && y >= 0 && y < H;
+        const size_t o = in ? (size_t)y * W + x : 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) s[k][r][c] = in ? src[k][o] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ssim_fwd(int C, int H, int W, const float* __restrict__ img,
+                                                  const float* __restrict__ gt, Taps t, float dscale,
+                                                  float* __restrict__ pmu, float* __restrict__ pxx,
+                                                  float* __restrict__ pxy, double* __restrict__ part) {
+    __shared__ float s_in[2][kSIH][kSIW];
+    __shared__ float s_h[5][kSIH][kSTW];
+    __shared__ double s_red[4];
+    const int gx = (W + kSTW - 1) / kSTW;
+    const int tile = blockIdx.x, ch = blockIdx.y;
+    const int x0 = (tile % gx) * kSTW, y0 = (tile / gx) * kSTH;
+    const size_t plane = (size_t)H * W, base = (size_t)ch * plane;
+    const float* const src[2] = {img + base, gt + base};
+    stage<2>(src, s_in, x0, y0, W, H);
+    __syncthreads();
+    // horizontal pass over all staged rows, output columns only
+    for (int i = threadIdx.x; i < kSIH * kSTW; i += blockDim.x) {
+        const int r = i / kSTW, c = i % kSTW;
+        float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSW; ++k) {
+            const float x = s_in[0][r][c + k], y = s_in[1][r][c + k], w = t.g[k];
+            a = __builtin_fmaf(w, x, a);
+            b = __builtin_fmaf(w, y, b);
+            aa = __builtin_fmaf(w, x * x, aa);
+            bb = __builtin_fmaf(w, y * y, bb);
+            ab = __builtin_fmaf(w, x * y, ab);
+        }
+        s_h[0][r][c] = a;
+        s_h[1][r][c] = b;
+        s_h[2][r][c] = aa;
+        s_h[3][r][c] = bb;
+        s_h[4][r][c] = ab;
+    }
+    __syncthreads();
+    const int c = threadIdx.x % kSTW, r = threadIdx.x / kSTW;
+    const int x = x0 + c, y = y0 + r;
+    double sv = 0.0;
+    if (x < W && y < H) {
+        float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < kSW; ++k) {
+            const float w = t.g[k];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) m[q] = __builtin_fmaf(w, s_h[q][r + k][c], m[q]);
+        }
+        const float mx = m[0], my = m[1];
+        const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+        const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
+        const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
+        const float iD = 1.f / (B1 * B2);
+        const float S = A1 * A2 * iD;
+        sv = S;
+        if (pmu) {
+            const size_t o = base + (size_t)y * W + x;
+            // dL/dS = -dscale (dscale = weight / (C H W))
+            pmu[o] = -dscale * (2.f * my * (A2 - A1) * iD - 2.f * mx * S * (1.f / B1 - 1.f / B2));
+            pxx[o] = -dscale * (-S / B2);
+            pxy[o] = -dscale * (2.f * A1 * iD);
+        }
+    }
+    // block sum of SSIM (fixed order)
+    for (int o = 32; o >= 1; o >>= 1) sv += __shfl_xor(sv, o);
+    if (__lane_id() == 0) s_red[threadIdx.x / 64] = sv;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(size_t)ch * gridDim.x + tile] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_ssim_bwd(int C, int H, int W, const float* __restrict__ img,
+                                                  const float* __restrict__ gt, Taps t,
+                                                  const float* __restrict__ pmu, const float* __restrict__ pxx,
+                                                  const float* __restrict__ pxy, float* __restrict__ grad) {
+    __shared__ float s_in[3][kSIH][kSIW];
+    __shared__ float s_h[3][kSIH][kSTW];
+    const int gx = (W + kSTW - 1) / kSTW;
+    const int tile = blockIdx.x, ch = blockIdx.y;
+    const int x0 = (tile % gx) * kSTW, y0 = (tile / gx) * kSTH;
+    const size_t plane = (size_t)H * W, base = (size_t)ch * plane;
+    const float* const src[3] = {pmu + base, pxx + base, pxy + base};
+    stage<3>(src, s_in, x0, y0, W, H);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSIH * kSTW; i += blockDim.x) {
+        const int r = i / kSTW, c = i % kSTW;
+        float a = 0.f, b = 0.f, d = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSW; ++k) {
+            const float w = t.g[k];
+            a = __builtin_fmaf(w, s_in[0][r][c + k], a);
+            b = __builtin_fmaf(w, s_in[1][r][c + k], b);
+            d = __builtin_fmaf(w, s_in[2][r][c + k], d);
+        }
+        s_h[0][r][c] = a;
+        s_h[1][r][c] = b;
+        s_h[2][r][c] = d;
+    }
+    __syncthreads();
+    const int c = threadIdx.x % kSTW, r = threadIdx.x / kSTW;
+    const int x = x0 + c, y = y0 + r;
+    if (x < W && y < H) {
+        float m[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < kSW; ++k) {
+            const float w = t.g[k];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) m[q] = __builtin_fmaf(w, s_h[q][r + k][c], m[q]);
+        }
+        const size_t o = base + (size_t)y * W + x;
+        grad[o] += m[0] + 2.f * img[o] * m[1] + gt[o] * m[2];
+    }
+}
+
+// out[0] = 1 - (sum of the block sums in order) / count.
+__global__ void k_ssim_reduce(int64_t nparts, int64_t count, const double* __restrict__ part,
+                              double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int64_t k = 0; k < nparts; ++k) s += part[k];
+    out[0] = 1.0 - s / (double)count;
+}
+
+int64_t ssim_tiles(int H, int W) { return (int64_t)((W + kSTW - 1) / kSTW) * ((H + kSTH - 1) / kSTH); }
+
+}  // namespace
+}  // namespace qg
+
+using namespace qg;
+
+extern "C" size_t qg_ssim_workspace_size(int32_t C, int32_t H, int32_t W) {
+    if (C < 1 || H < 1 || W < 1) return 0;
+    const size_t n = (size_t)C * H * W;
+    return 3 * align_up(n * sizeof(float)) + align_up((size_t)C * ssim_tiles(H, W) * sizeof(double));
+}
+
+extern "C" qg_status qg_ssim_loss(int32_t C, int32_t H, int32_t W, const float* image, const float* gt, float weight,
+                                  float* grad_image, double* dssim_out, void* ws, size_t ws_bytes,
+                                  qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(C >= 1 && C <= 65535 && H >= 1 && W >= 1, "C=%d H=%d W=%d invalid", C, H, W);
+    QG_REQUIRE(image && gt, "image/gt NULL");
+    QG_REQUIRE(grad_image || dssim_out, "nothing to compute: grad_image and dssim_out are both NULL");
+    const size_t need = qg_ssim_workspace_size(C, H, W);
+    QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    const int64_t ntiles = ssim_tiles(H, W);
+    QG_REQUIRE(ntiles < (1ll << 31), "image too large");
+    hipStream_t s = (hipStream_t)stream;
+    Taps t;
+    {
+        double g[kSW], sum = 0.0;
+        for (int k = 0; k < kSW; ++k) {
+            const double d = (double)(k - kSR);
+            g[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+            sum += g[k];
+        }
+        for (int k = 0; k < kSW; ++k) t.g[k] = (float)(g[k] / sum);
+    }
+    const size_t n = (size_t)C * H * W;
+    float* pmu = (float*)ws;
+    float* pxx = (float*)((char*)ws + align_up(n * sizeof(float)));
+    float* pxy = (float*)((char*)ws + 2 * align_up(n * sizeof(float)));
+    double* part = (double*)((char*)ws + 3 * align_up(n * sizeof(float)));
+    const float dscale = (float)((double)weight / (double)n);
+    const dim3 grid((unsigned)ntiles, (unsigned)C);
+    {
+        QG_TIMED("ssim", s);
+        k_ssim_fwd<<<grid, 256, 0, s>>>(C, H, W, image, gt, t, dscale, grad_image ? pmu : nullptr, pxx, pxy, part);
+        if (grad_image) k_ssim_bwd<<<grid, 256, 0, s>>>(C, H, W, image, gt, t, pmu, pxx, pxy, grad_image);
+        if (dssim_out) k_ssim_reduce<<<1, 64, 0, s>>>((int64_t)C * ntiles, (int64_t)n, part, dssim_out);
+    }
+    QG_LAUNCH_CHECK("qg_ssim_loss");
+    return QG_OK;
+}

@@ -52,6 +52,8 @@ class FitConfig:
     t_d: float = 1e-3
     mask_dilate: int = 48
     mask_fraction: float = 0.0
+    # Eq. 3's D-SSIM weight lambda (not given in the paper; 3D-GS uses 0.2); 0 fits the L1 term alone
+    lambda_dssim: float = 0.0
 
 
 def xavier_decoder(seed: int, L=8, H=32, M=56):
@@ -165,6 +167,11 @@ class FrameFitter(ResidualState):
         self.grad_img = torch.empty_like(img)
         self.loss_part = torch.empty(2 * qg.qg_loss_blocks(self.count), dtype=torch.float64, device=dev)
         self.loss_out = torch.zeros(2, dtype=torch.float64, device=dev)
+        if cfg.lambda_dssim > 0.0:
+            C, H, W = img.shape
+            self.ssim_ws_bytes = qg.qg_ssim_workspace_size(C, H, W)
+            self.ssim_ws = torch.empty(self.ssim_ws_bytes, dtype=torch.uint8, device=dev)
+            self.dssim_out = torch.zeros(1, dtype=torch.float64, device=dev)
 
     # -- the step ------------------------------------------------------------------------------
     def forward_view(self, v, stream=None):
@@ -197,9 +204,17 @@ class FrameFitter(ResidualState):
             self.decode(stream)
             self.forward_view(v, stream)
         if masked:
+            assert c.lambda_dssim == 0.0, "masked steps fit the L1 term"
             pix = self.masks[v][0]
             qg.qg_l1_loss_masked(self.count, pix.numel(), r.images[0], self.gts[v], pix, 1.0, self.grad_img,
                                  self.loss_part, stream)
+        elif c.lambda_dssim > 0.0:
+            # Eq. 3: (1 - lambda) L1 + lambda D-SSIM (the D-SSIM gradient is added to the L1 one)
+            qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0 - c.lambda_dssim, self.grad_img,
+                          self.loss_part, stream)
+            C, H, W = r.images[0].shape
+            qg.qg_ssim_loss(C, H, W, r.images[0], self.gts[v], c.lambda_dssim, self.grad_img, self.dssim_out,
+                            self.ssim_ws, self.ssim_ws_bytes, stream)
         else:
             qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
         # parameter gradients are zero here: they start zeroed and qg_adam_multi clears them after use

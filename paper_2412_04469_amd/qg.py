@@ -83,6 +83,8 @@ def lib():
             "qg_loss_blocks": ([i64], i64),
             "qg_l1_loss": ([i64, P, P, f32, P, P, P], i32),
             "qg_l1_loss_masked": ([i64, i64, P, P, P, f32, P, P, P], i32),
+            "qg_ssim_workspace_size": ([i32, i32, i32], sz),
+            "qg_ssim_loss": ([i32, i32, i32, P, P, f32, P, P, P, sz, P], i32),
             "qg_dynamic_flags": ([i64, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P], i32),
             "qg_dynamic_mask": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P], i32),
             "qg_dilate_mask": ([CAM, i32, qg_tiling, i32, P, P, P, P, P], i32),
@@ -315,6 +317,15 @@ def qg_l1_loss(count, image, gt, scale, grad_image, partials, stream=None):
 def qg_l1_loss_masked(count, plane, image, gt, mask, scale, grad_image, partials, stream=None):
     _check(lib().qg_l1_loss_masked(int(count), int(plane), _ptr(image), _ptr(gt), _ptr(mask), float(scale),
                                    _ptr(grad_image), _ptr(partials), _stream(stream)))
+
+
+def qg_ssim_workspace_size(C, H, W):
+    return int(lib().qg_ssim_workspace_size(int(C), int(H), int(W)))
+
+
+def qg_ssim_loss(C, H, W, image, gt, weight, grad_image, dssim_out, ws, ws_bytes, stream=None):
+    _check(lib().qg_ssim_loss(int(C), int(H), int(W), _ptr(image), _ptr(gt), float(weight), _ptr(grad_image),
+                              _ptr(dssim_out), _ptr(ws), int(ws_bytes), _stream(stream)))
 
 
 def qg_dynamic_flags(n, d, sx, sy, t_d, dynamic, stream=None):

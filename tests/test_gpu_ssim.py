@@ -1,0 +1,87 @@
+"""GPU parity of the D-SSIM term of Eq. 3 against the FP64 oracle: the value, its gradient, and the mix
+with the L1 term."""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import rel_l2, to_dev
+from oracle import ssim as OS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qg():
+    from paper_2412_04469_amd import qg
+    return qg
+
+
+def _gpu(qg, img, gt, weight=1.0, grad0=None):
+    C, H, W = img.shape
+    wsb = qg.qg_ssim_workspace_size(C, H, W)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = to_dev(np.zeros_like(img) if grad0 is None else grad0)
+    qg.qg_ssim_loss(C, H, W, to_dev(img), to_dev(gt), weight, g, out, ws, wsb)
+    torch.cuda.synchronize()
+    return float(out.item()), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(3, 97, 131), (1, 40, 33), (3, 8, 300), (2, 61, 7)])
+def test_dssim_value_and_gradient(qg, shape):
+    rng = np.random.default_rng(sum(shape))
+    img = rng.random(shape).astype(np.float32)
+    gt = np.clip(img + rng.normal(0, 0.1, shape), 0, 1).astype(np.float32)
+    val, grad = _gpu(qg, img, gt)
+    want, gwant = OS.dssim(img, gt)
+    assert abs(val - want) <= 1e-5, (val, want)
+    assert rel_l2(grad, gwant) <= 1e-4, rel_l2(grad, gwant)
+
+
+def test_near_constant_images(qg):
+    """Variances of 1e-6 against means of 0.5: E[x^2] - mu^2 loses digits in float32, which C2 absorbs."""
+    rng = np.random.default_rng(9)
+    img = (0.5 + rng.normal(0, 1e-3, (3, 50, 64))).astype(np.float32)
+    gt = (0.5 + rng.normal(0, 1e-3, (3, 50, 64))).astype(np.float32)
+    val, grad = _gpu(qg, img, gt)
+    want, gwant = OS.dssim(img, gt)
+    assert abs(val - want) <= 1e-5
+    assert rel_l2(grad, gwant) <= 2e-3
+
+
+def test_identical_images(qg):
+    img = np.random.default_rng(4).random((3, 33, 45)).astype(np.float32)
+    val, grad = _gpu(qg, img, img)
+    assert abs(val) <= 1e-6 and np.abs(grad).max() <= 1e-8
+
+
+def test_eq3_mix_with_l1(qg):
+    """qg_l1_loss with scale 1 - lambda, then qg_ssim_loss with weight lambda adding to the same gradient."""
+    rng = np.random.default_rng(5)
+    C, H, W = 3, 70, 90
+    img = rng.random((C, H, W)).astype(np.float32)
+    gt = rng.random((C, H, W)).astype(np.float32)
+    lam = 0.2
+    g = torch.empty(C, H, W, device="cuda")
+    parts = torch.empty(2 * qg.qg_loss_blocks(C * H * W), dtype=torch.float64, device="cuda")
+    qg.qg_l1_loss(C * H * W, to_dev(img), to_dev(gt), 1.0 - lam, g, parts)
+    _, grad = _gpu(qg, img, gt, lam, g.cpu().numpy())
+    _, gwant = OS.loss_eq3(img, gt, lam)
+    assert rel_l2(grad, gwant) <= 1e-5
+
+
+def test_fitter_with_dssim_term(qg):
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, render_views
+    wl = synth.workload_fit_local(n=4000, width=160, height=120, n_views=3, frac_move=0.05)
+    cfg = FitConfig(lambda_dssim=0.2)
+    prev = to_dev(wl.scene.planes())
+    gts = render_views(to_dev(wl.target_scene.planes()), wl.cams, cfg)
+    f = FrameFitter(prev, wl.cams, gts, cfg)
+    f.size_capacity()
+    f.step(0)
+    first = float(f.dssim_out.item())
+    for i in range(60):
+        f.step(i % 3)
+    f.step(0)
+    assert 0.0 < float(f.dssim_out.item()) < first
