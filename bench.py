@@ -87,6 +87,7 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-view step")
     p.add_argument("--no-frame", action="store_true", help="skip the sec/frame measurement")
     p.add_argument("--no-masked", action="store_true", help="skip the masked-training measurement")
+    p.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM step measurement")
     p.add_argument("--mask-fraction", type=float, default=0.65,
                    help="fraction of a frame's iterations that are masked (0.30 N3DV, 0.65 Immersive)")
     p.add_argument("--mask-td", type=float, default=3e-6,
@@ -315,6 +316,50 @@ def frame_section(args):
             "protocol": "frame clock from gate initialisation (20 forward + 20 adjoint passes) through the optimiser "
                         "steps; held-out PSNR every 25 steps with the clock paused"}
 
+
+
+def dssim_section(args):
+    """The fit step with Eq. 3's D-SSIM term (lambda = 0.2, the 3D-GS value; the paper gives none) on the fit
+    workload: ms per step, and the SSIM forward + adjoint kernels against the HBM roofline.  Their
+    algorithmic traffic is 48 B per pixel and channel: forward reads x, y and writes three partial maps;
+    the adjoint reads the three maps, x and y and updates the image gradient."""
+    import torch
+    from paper_2412_04469_amd import qg, synth
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, render_views
+    wl = synth.workload_fit(n=args.n)
+    cfg = FitConfig(lambda_dssim=0.2)
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    gts = render_views(torch.as_tensor(wl.target_scene.planes()).to(dev), wl.cams, cfg)
+    f = FrameFitter(prev, wl.cams, gts, cfg)
+    f.size_capacity()
+    V = len(wl.cams)
+    qg.qg_timing_enable(True)
+    for i in range(20):
+        f.step(i % V)
+    torch.cuda.synchronize()
+    rep = qg.qg_timing_report()
+    qg.qg_timing_enable(False)
+    ssim_calls, ssim_ms = rep.get("ssim", (0, 0.0))
+    stream = torch.cuda.current_stream()
+    k = 100
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(k):
+        f.step(i % V)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / k
+    elems = 3 * wl.cams[0].width * wl.cams[0].height
+    per = ssim_ms / max(ssim_calls, 1)
+    gbs = 48.0 * elems / (per * 1e-3) / 1e9 if per > 0 else None
+    del f
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "lambda": cfg.lambda_dssim, "ms_per_step": round(ms, 4), "steps": k,
+            "ssim_ms_per_launch": round(per, 4), "ssim_bytes_per_launch": 48 * elems,
+            "ssim_achieved_gbs": None if gbs is None else round(gbs, 1), "hbm_peak_gbs": PEAK_HBM_GBS,
+            "note": "ssim_ms_per_launch from event-bracketed warm-up steps (forward, adjoint and reduce)"}
 
 
 def masked_section(args):
@@ -555,6 +600,8 @@ def main():
         result["sec_per_frame"] = frame_section(args)
     if not args.no_masked:
         result["masked_training"] = masked_section(args)
+    if not args.no_dssim:
+        result["dssim"] = dssim_section(args)
     if args.proposal != "none":
         result["learned_proposal"] = proposal_section(args)
     if not args.no_cpu_baseline:

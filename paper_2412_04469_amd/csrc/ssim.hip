@@ -153,13 +153,20 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(int C, int H, int W, const flo
     }
 }
 
-// out[0] = 1 - (sum of the block sums in order) / count.
-__global__ void k_ssim_reduce(int64_t nparts, int64_t count, const double* __restrict__ part,
-                              double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int64_t k = 0; k < nparts; ++k) s += part[k];
-    out[0] = 1.0 - s / (double)count;
+// out[0] = 1 - (sum of the block sums) / count, in a fixed order: thread t adds parts t, t + 256, ... in turn,
+// then a pairwise tree over the 256 thread sums.
+__global__ __launch_bounds__(256) void k_ssim_reduce(int64_t nparts, int64_t count, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < nparts; k += 256) a += part[k];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = 1.0 - s[0] / (double)count;
 }
 
 int64_t ssim_tiles(int H, int W) { return (int64_t)((W + kSTW - 1) / kSTW) * ((H + kSTH - 1) / kSTH); }
@@ -208,7 +215,7 @@ extern "C" qg_status qg_ssim_loss(int32_t C, int32_t H, int32_t W, const float* 
         QG_TIMED("ssim", s);
         k_ssim_fwd<<<grid, 256, 0, s>>>(C, H, W, image, gt, t, dscale, grad_image ? pmu : nullptr, pxx, pxy, part);
         if (grad_image) k_ssim_bwd<<<grid, 256, 0, s>>>(C, H, W, image, gt, t, pmu, pxx, pxy, grad_image);
-        if (dssim_out) k_ssim_reduce<<<1, 64, 0, s>>>((int64_t)C * ntiles, (int64_t)n, part, dssim_out);
+        if (dssim_out) k_ssim_reduce<<<1, 256, 0, s>>>((int64_t)C * ntiles, (int64_t)n, part, dssim_out);
     }
     QG_LAUNCH_CHECK("qg_ssim_loss");
     return QG_OK;
