@@ -264,7 +264,8 @@ def frame_section(args):
     graph-replayed), both with the gate initialisation of Eq. 9-10 on the frame clock."""
     import torch
     from paper_2412_04469_amd import synth
-    from paper_2412_04469_amd.fit import BatchedFitter, FitConfig, FrameFitter, GateInitializer, render_views
+    from paper_2412_04469_amd.fit import (BatchedFitter, FitConfig, FrameFitter, GateInitializer, frame_storage,
+                                          render_views)
     wl = synth.workload_fit(n=args.n)
     cfg = FitConfig()
     dev = torch.device("cuda")
@@ -291,6 +292,8 @@ def frame_section(args):
     tgt = traj_p[-1][2]
     hit_p = next(s for (i, s, p) in traj_p if p >= tgt)
     log(f"frame: plain reaches {tgt:.3f} dB at {hit_p:.3f} s")
+    storage = frame_storage(plain)
+    log(f"frame: storage {storage['mb_per_frame']:.4f} MB")
     del plain
     torch.cuda.empty_cache()
     bcfg = dataclasses.replace(cfg, group_views=args.batched_views, batched_lr_scale=args.batched_lr_scale)
@@ -309,6 +312,7 @@ def frame_section(args):
     del bat
     torch.cuda.empty_cache()
     return {"workload": wl.name, "target_psnr_db": tgt, "iterations_plain": args.frame_iters,
+            "storage_plain": storage,
             "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p},
             "batched": {"sec_per_frame": None if hit_b is None else round(hit_b, 4),
                         "views_per_step": vps, "lr_scale": args.batched_lr_scale,

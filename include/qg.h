@@ -357,6 +357,34 @@ qg_status qg_l1_loss_masked(int64_t count, int64_t plane, const float* image, co
                             float scale, float* grad_image, double* partials, qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
+/* Storage of a frame's residuals (the compression back end after the fit): the quantised latents   */
+/* (Sec. 3.2; the decoder reads rint(l_hat)) entropy coded with one model per latent dimension.     */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * symbols[i*L + k] = rint(latents[k*ld + i]) as int8 (device, [n*L], Gaussian-major); hist[k*256 + s + 128]
+ * (device, uint32 [L][256], cleared here) counts symbol s of dimension k; *overflow (device) counts values
+ * outside [-128, 127], which are stored as 0 (the caller treats a non-zero count as an error).  L <= 16.
+ */
+qg_status qg_latent_symbols(int64_t n, int64_t ld, const float* latents, int32_t L, int8_t* symbols, uint32_t* hist,
+                            uint32_t* overflow, qg_stream stream);
+
+/*
+ * Host-side byte-wise rANS (Duda's asymmetric numeral systems, range variant; 32-bit state in [2^23, 2^31),
+ * byte renormalisation) over count = n*L int8 symbols, symbol i coded with model i mod L.  Each model's
+ * probabilities are its histogram row (hist, host, uint32 [L][256]) quantised to 2^16: every present symbol
+ * at least 1, the rest in proportion with the remainder given to (or taken from) the most frequent symbols,
+ * a deterministic function of the counts, so the decoder rebuilds it from the same histogram.  All pointers
+ * are host memory.  encode: out holds at most qg_rans_bound(count) bytes; *out_bytes receives the length.
+ * decode: reads exactly in_bytes and writes count symbols.  Errors: QG_ERR_ARG for bad sizes, a symbol with
+ * a zero count, a short buffer, or (decode) a stream that does not end exactly.
+ */
+size_t qg_rans_bound(int64_t count);
+qg_status qg_rans_encode(int64_t count, int32_t L, const int8_t* symbols, const uint32_t* hist, uint8_t* out,
+                         size_t capacity, size_t* out_bytes);
+qg_status qg_rans_decode(int64_t count, int32_t L, const uint8_t* in, size_t in_bytes, const uint32_t* hist,
+                         int8_t* symbols);
+
+/* ---------------------------------------------------------------------------------------------- */
 /* Learned residual proposal (not a method of the paper: a learned replacement for zero-initialised  */
 /* residual parameters of frame t, Sec. 3.2 / Eq. 5-8; its analogue in the paper is Eq. 10).         */
 /* ---------------------------------------------------------------------------------------------- */

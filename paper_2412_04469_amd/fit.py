@@ -259,6 +259,31 @@ class FrameFitter(ResidualState):
         return worst
 
 
+def frame_storage(state: ResidualState, stream=None) -> dict:
+    """Bytes that store frame t's residuals after its fit: the quantised latents rANS-coded with one model per
+    latent dimension (the models as (symbol, 16-bit frequency) pairs), the position residuals of the Gaussians
+    whose gate is non-zero as (uint32 index, 3 float32) records, and the float32 decoder weights."""
+    n, L = state.n, state.cfg.latent_dim
+    dev = state.lat.device
+    sym = torch.empty(n * L, dtype=torch.int8, device=dev)
+    hist = torch.empty(L * 256, dtype=torch.int32, device=dev)
+    ovf = torch.zeros(1, dtype=torch.int32, device=dev)
+    qg.qg_latent_symbols(n, state.lat.stride(0), state.lat, L, sym, hist, ovf, stream)
+    nz = int((state.gate != 0).sum().item())
+    if int(ovf.item()) != 0:
+        raise ValueError("latent symbols outside [-128, 127]")
+    sym_h = np.ascontiguousarray(sym.cpu().numpy())
+    hist_h = np.ascontiguousarray(hist.cpu().numpy().astype(np.uint32).reshape(L, 256))
+    coded = qg.qg_rans_encode(L, sym_h, hist_h)
+    model = int(sum(1 + 3 * int((row > 0).sum()) for row in hist_h))
+    coo = nz * 16
+    dec = 4 * (state.W1.numel() + state.W2.numel())
+    total = coded.size + model + coo + dec
+    return {"latent_bytes": int(coded.size), "model_bytes": model, "position_coo_bytes": coo, "nonzero_gates": nz,
+            "decoder_bytes": dec, "total_bytes": int(total), "mb_per_frame": round(total / 1e6, 4),
+            "latent_bits_per_symbol": round(8.0 * coded.size / max(n * L, 1), 4)}
+
+
 def view_groups(V: int, max_views: int = qg.MAX_VIEWS):
     """Consecutive groups of near-equal size, at most max_views each."""
     g = -(-V // max_views)

@@ -84,6 +84,10 @@ def lib():
             "qg_l1_loss": ([i64, P, P, f32, P, P, P], i32),
             "qg_l1_loss_masked": ([i64, i64, P, P, P, f32, P, P, P], i32),
             "qg_ssim_workspace_size": ([i32, i32, i32], sz),
+            "qg_latent_symbols": ([i64, i64, P, i32, P, P, P, P], i32),
+            "qg_rans_bound": ([i64], sz),
+            "qg_rans_encode": ([i64, i32, P, P, P, sz, ctypes.POINTER(ctypes.c_size_t)], i32),
+            "qg_rans_decode": ([i64, i32, P, sz, P, P], i32),
             "qg_ssim_loss": ([i32, i32, i32, P, P, f32, P, P, P, sz, P], i32),
             "qg_dynamic_flags": ([i64, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P], i32),
             "qg_dynamic_mask": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P], i32),
@@ -317,6 +321,32 @@ def qg_l1_loss(count, image, gt, scale, grad_image, partials, stream=None):
 def qg_l1_loss_masked(count, plane, image, gt, mask, scale, grad_image, partials, stream=None):
     _check(lib().qg_l1_loss_masked(int(count), int(plane), _ptr(image), _ptr(gt), _ptr(mask), float(scale),
                                    _ptr(grad_image), _ptr(partials), _stream(stream)))
+
+
+def qg_latent_symbols(n, ld, latents, L, symbols, hist, overflow, stream=None):
+    _check(lib().qg_latent_symbols(int(n), int(ld), _ptr(latents), int(L), _ptr(symbols), _ptr(hist), _ptr(overflow),
+                                   _stream(stream)))
+
+
+def _host(a):
+    """Host pointer of a C-contiguous numpy array."""
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def qg_rans_encode(L, symbols, hist):
+    """symbols: int8 numpy [count]; hist: uint32 numpy [L][256] -> coded bytes (numpy uint8)."""
+    count = int(symbols.size)
+    out = np.empty(int(lib().qg_rans_bound(count)), np.uint8)
+    nb = ctypes.c_size_t(0)
+    _check(lib().qg_rans_encode(count, int(L), _host(symbols), _host(hist), _host(out), out.size, ctypes.byref(nb)))
+    return out[:nb.value].copy()
+
+
+def qg_rans_decode(count, L, data, hist):
+    out = np.empty(int(count), np.int8)
+    _check(lib().qg_rans_decode(int(count), int(L), _host(data), int(data.size), _host(hist), _host(out)))
+    return out
 
 
 def qg_ssim_workspace_size(C, H, W):
