@@ -2,10 +2,10 @@
 // C1 = 0.01^2, C2 = 0.03^2), its mean over pixels and channels, and the gradient of weight * (1 - mean SSIM)
 // with respect to the rendered image.
 //
-// Forward (k_ssim_fwd): a block owns a 32 x 8 tile of one channel.  It stages x and y with a 5-pixel halo in
+// Forward (k_ssim_fwd): a block owns a 32 x 32 tile of one channel.  It stages x and y with a 5-pixel halo in
 // LDS (zero outside the image), runs the window's horizontal pass for the five moments (x, y, x^2, y^2, xy)
 // over the halo rows, then the vertical pass, one output pixel per thread.  From mu_x, E[x^2], E[xy] (and the
-// same of y) it forms SSIM and the per-pixel partials of the loss with respect to mu_x, E[x^2] and E[xy]:
+// same of y), each thread taking four output pixels of a column, it forms SSIM and the per-pixel partials of the loss with respect to mu_x, E[x^2] and E[xy]:
 //   dS/dmu_x = 2 mu_y (A2 - A1) / (B1 B2) - 2 mu_x S (1/B1 - 1/B2),  dS/dE[x^2] = -S / B2,
 //   dS/dE[xy] = 2 A1 / (B1 B2),
 // with A1 = 2 mu_x mu_y + C1, A2 = 2 sigma_xy + C2, B1 = mu_x^2 + mu_y^2 + C1, B2 = sigma_x^2 + sigma_y^2 + C2.
@@ -20,7 +20,7 @@ namespace {
 
 constexpr int kSR = 5;             // window radius (11 taps)
 constexpr int kSW = 2 * kSR + 1;
-constexpr int kSTW = 32, kSTH = 8;  // output tile
+constexpr int kSTW = 32, kSTH = 32;  // output tile (4 rows of 32 per thread group of 256)
 constexpr int kSIW = kSTW + 2 * kSR, kSIH = kSTH + 2 * kSR;  // staged input tile
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
@@ -76,10 +76,11 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(int C, int H, int W, const flo
         s_h[4][r][c] = ab;
     }
     __syncthreads();
-    const int c = threadIdx.x % kSTW, r = threadIdx.x / kSTW;
-    const int x = x0 + c, y = y0 + r;
     double sv = 0.0;
-    if (x < W && y < H) {
+    for (int rr = threadIdx.x / kSTW; rr < kSTH; rr += 256 / kSTW) {
+        const int c = threadIdx.x % kSTW, r = rr;
+        const int x = x0 + c, y = y0 + r;
+        if (x >= W || y >= H) continue;
         float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < kSW; ++k) {
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(int C, int H, int W, const flo
         const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
         const float iD = 1.f / (B1 * B2);
         const float S = A1 * A2 * iD;
-        sv = S;
+        sv += (double)S;
         if (pmu) {
             const size_t o = base + (size_t)y * W + x;
             // dL/dS = -dscale (dscale = weight / (C H W))
@@ -138,9 +139,10 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(int C, int H, int W, const flo
         s_h[2][r][c] = d;
     }
     __syncthreads();
-    const int c = threadIdx.x % kSTW, r = threadIdx.x / kSTW;
-    const int x = x0 + c, y = y0 + r;
-    if (x < W && y < H) {
+    for (int rr = threadIdx.x / kSTW; rr < kSTH; rr += 256 / kSTW) {
+        const int c = threadIdx.x % kSTW, r = rr;
+        const int x = x0 + c, y = y0 + r;
+        if (x >= W || y >= H) continue;
         float m[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < kSW; ++k) {
