@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kLBlock) void k_l1_masked(int64_t count, int64_t pl
     for (int r = 0; r < kLIPT; ++r) {
         const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
         if (i < count) {
-            const float gr = mask[i % plane] ? l1_term(img[i], gt[i], gscale, sa, sb) : 0.f;
+            const float gr = mask[(uint32_t)i % (uint32_t)plane] ? l1_term(img[i], gt[i], gscale, sa, sb) : 0.f;
             if (grad) grad[i] = gr;
         }
     }
@@ -266,6 +266,7 @@ extern "C" qg_status qg_l1_loss_masked(int64_t count, int64_t plane, const float
     clear_error();
     QG_REQUIRE(count >= 0 && plane >= 1 && count % plane == 0, "count=%lld must be a multiple of plane=%lld >= 1",
                (long long)count, (long long)plane);
+    QG_REQUIRE(count < (1ll << 32), "count=%lld must be < 2^32", (long long)count);
     QG_REQUIRE(partials, "partials is NULL");
     QG_REQUIRE(count == 0 || (image && gt && mask), "image/gt/mask NULL");
     hipStream_t s = (hipStream_t)stream;
