@@ -497,8 +497,8 @@ def proposal_section(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
-              f"note, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is implemented for one GPU, "
+              f"and its sharding by view across GPUs is described, not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2412_04469_amd import qg, synth
