@@ -87,6 +87,10 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-view step")
     p.add_argument("--no-frame", action="store_true", help="skip the sec/frame measurement")
     p.add_argument("--no-masked", action="store_true", help="skip the masked-training measurement")
+    p.add_argument("--proposal-batched-views", type=int, default=4,
+                   help="views per step of the proposal's batched form (0: --batched-views)")
+    p.add_argument("--proposal-batched-lr-scale", type=float, default=2.5,
+                   help="learning-rate factor of the proposal's batched form (0: --batched-lr-scale)")
     p.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM step measurement")
     p.add_argument("--mask-fraction", type=float, default=0.65,
                    help="fraction of a frame's iterations that are masked (0.30 N3DV, 0.65 Immersive)")
@@ -482,13 +486,14 @@ def proposal_section(args):
                           "used": j["used_proposal"]} for p, j in zip([r for r in recs if r["t"] in judge_frames],
                                                                         judged)]}
     if args.proposal == "both":
-        bcfg = dataclasses.replace(FitConfig(), group_views=args.batched_views, batched_lr_scale=args.batched_lr_scale)
+        pv = args.proposal_batched_views or args.batched_views
+        pl = args.proposal_batched_lr_scale or args.batched_lr_scale
+        bcfg = dataclasses.replace(FitConfig(), group_views=pv, batched_lr_scale=pl)
         jb = stream.judge(seq, hist, recs, prop, judge_frames, args.frame_iters, 25, batched=True, log=log,
                           batched_cfg=bcfg)
         out["proposal_batched"] = stream.summarize(recs, jb, judge_frames)
-        out["proposal_batched"]["views_per_step"] = max(len(g) for g in view_groups(len(wl.cams),
-                                                                                  min(args.batched_views, 16)))
-        out["proposal_batched"]["lr_scale"] = args.batched_lr_scale
+        out["proposal_batched"]["views_per_step"] = max(len(g) for g in view_groups(len(wl.cams), min(pv, 16)))
+        out["proposal_batched"]["lr_scale"] = pl
     del hist
     torch.cuda.empty_cache()
     return out
