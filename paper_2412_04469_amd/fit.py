@@ -70,7 +70,9 @@ class ResidualState:
     def __init__(self, prev_attrs: torch.Tensor, cfg: FitConfig = FitConfig(), W1=None, W2=None, seed=0,
                  lr_scale=1.0):
         self.cfg = cfg
-        self.prev = prev_attrs.contiguous()
+        # a copy of its own: reset_frame writes each new frame's A_{t-1} here, which must not reach the caller's
+        # tensor (a streaming history would otherwise be overwritten)
+        self.prev = prev_attrs.detach().clone(memory_format=torch.contiguous_format)
         self.n = int(self.prev.shape[1])
         self.ld = int(self.prev.stride(0))
         dev = self.prev.device

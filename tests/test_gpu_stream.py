@@ -25,3 +25,20 @@ def test_stream_and_proposal_pipeline_small():
     assert s["frames"] == [4, 6]
     jb = stream.judge(seq, hist, recs, prop, [4, 5], iters=50, check_every=25, batched=True)
     assert len(jb) == 2
+
+
+def test_fitter_does_not_alias_its_initial_attributes():
+    """reset_frame(prev_attrs=...) writes the fitter's own copy of A_{t-1}, never the tensor it was built from
+    (a streaming history handed to a fitter must stay intact)."""
+    import torch
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, render_views
+    wl = synth.workload_fit_local(n=2000, width=96, height=64, n_views=2, frac_move=0.05)
+    cfg = FitConfig()
+    A0 = torch.as_tensor(wl.scene.planes()).cuda()
+    keep = A0.clone()
+    gts = render_views(A0, wl.cams, cfg)
+    f = FrameFitter(A0, wl.cams, gts, cfg)
+    f.reset_frame(prev_attrs=torch.as_tensor(wl.target_scene.planes()).cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(A0, keep)
