@@ -59,7 +59,7 @@ def test_dynamic_mask_parity(qgm, tile):
         assert 0.05 < want.mean() < 0.95, want.mean()
 
 
-def _two_views(tile):
+def _two_views():
     return [synth.make_camera((0.0, 0.0, -4.0), 200, 150, f=200), synth.make_camera((1.0, 0.0, -4.0), 120, 90, f=120)]
 
 
@@ -67,7 +67,7 @@ def _two_views(tile):
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
 def test_dilate_and_tile_flags_exact(qgm, tile, k):
     qg, _ = qgm
-    cams = _two_views(tile)
+    cams = _two_views()
     rng = np.random.default_rng(k)
     masks, want_d, want_f = [], [], []
     for c in cams:
