@@ -440,7 +440,8 @@ int64_t qg_loss_blocks(int64_t count);
  * a fixed order.  grad_image (may be NULL) is incremented (+=) by weight * dD-SSIM/dimage, so an L1
  * gradient written first with scale (1 - weight) yields Eq. 3's (1 - lambda) L1 + lambda D-SSIM (the
  * paper does not give lambda; 3D-GS uses 0.2).  ws: qg_ssim_workspace_size(C, H, W) bytes.
- * Errors: QG_ERR_ARG for bad sizes, NULL image/gt, both outputs NULL or a short workspace.
+ * Errors: QG_ERR_ARG for bad sizes (H * W must be below 2^31), NULL image/gt, both outputs NULL or a short
+ * workspace.
  */
 size_t qg_ssim_workspace_size(int32_t C, int32_t H, int32_t W);
 qg_status qg_ssim_loss(int32_t C, int32_t H, int32_t W, const float* image, const float* gt, float weight,
