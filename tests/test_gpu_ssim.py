@@ -38,6 +38,24 @@ def test_dssim_value_and_gradient(qg, shape):
     assert rel_l2(grad, gwant) <= 1e-4, rel_l2(grad, gwant)
 
 
+def test_dssim_full_view_1352x1014(qg):
+    """The image size of the fit workload's views (1352 x 1014 x 3): 32 x 43 tiles with a ragged last row and
+    column of tiles, launched as the fit launches it."""
+    shape = (3, 1014, 1352)
+    rng = np.random.default_rng(1352)
+    img = rng.random(shape).astype(np.float32)
+    gt = np.clip(img + rng.normal(0, 0.1, shape), 0, 1).astype(np.float32)
+    val, grad = _gpu(qg, img, gt, weight=0.2)
+    want, gwant = OS.dssim(img, gt)
+    assert abs(val - want) <= 1e-5, (val, want)
+    assert rel_l2(grad, 0.2 * gwant) <= 1e-4, rel_l2(grad, 0.2 * gwant)
+    # element-wise on the border rows and columns, where the zero padding enters the window
+    for sl in [(slice(None), slice(0, 6)), (slice(None), slice(-6, None)),
+               (slice(None), slice(None), slice(0, 6)), (slice(None), slice(None), slice(-6, None))]:
+        d = np.abs(grad[sl] - 0.2 * gwant[sl]).max()
+        assert d <= 1e-4 * np.abs(0.2 * gwant).max(), d
+
+
 def test_near_constant_images(qg):
     """Variances of 1e-6 against means of 0.5: E[x^2] - mu^2 loses digits in float32, which C2 absorbs."""
     rng = np.random.default_rng(9)
