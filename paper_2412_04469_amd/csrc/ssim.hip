@@ -3,10 +3,10 @@
 // with respect to the rendered image.
 //
 // Forward (k_ssim_fwd): a block owns a 32 x 32 tile of one channel.  It stages x and y with a 5-pixel halo in
-// LDS (zero outside the image), runs the window's horizontal pass for the five moments (x, y, x^2, y^2, xy)
+// LDS (zero outside the image), runs the window's horizontal pass for the four moments (x, y, x^2 + y^2, xy)
 // over the halo rows (a thread makes 4 adjacent columns from 16 staged values read as four 16-byte words),
 // then the vertical pass (a thread makes 4 rows of one column from the 14 staged rows they read).  From mu_x,
-// E[x^2], E[xy] (and the same of y) it forms SSIM and the per-pixel partials of the loss with respect to mu_x,
+// mu_y, E[x^2] + E[y^2] and E[xy] it forms SSIM and the per-pixel partials of the loss with respect to mu_x,
 // E[x^2] and E[xy]:
 //   dS/dmu_x = 2 mu_y (A2 - A1) / (B1 B2) - 2 mu_x S (1/B1 - 1/B2),  dS/dE[x^2] = -S / B2,
 //   dS/dE[xy] = 2 A1 / (B1 B2),
@@ -87,7 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_ssim_fwd(int C, int H, int W, cons
                                                        float* __restrict__ pmu, float* __restrict__ pxx,
                                                        float* __restrict__ pxy, double* __restrict__ part) {
     __shared__ __align__(16) float s_in[2][kSIH][kSIWP];
-    __shared__ __align__(16) float s_h[5][kSIH][kSTW];
+    // SSIM needs E[x^2] and E[y^2] only as their sum (sigma_x^2 + sigma_y^2 in B2), so four moments are blurred
+    __shared__ __align__(16) float s_h[4][kSIH][kSTW];
     __shared__ double s_red[kThreads / 64];
     const int gx = (W + kSTW - 1) / kSTW;
     const int tile = blockIdx.x, ch = blockIdx.y;
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_ssim_fwd(int C, int H, int W, cons
         float x[16], y[16];
         row16(s_in[0], r, c0, x);
         row16(s_in[1], r, c0, y);
-        float a[4] = {}, b[4] = {}, aa[4] = {}, bb[4] = {}, ab[4] = {};
+        float a[4] = {}, b[4] = {}, sq[4] = {}, ab[4] = {};
 #pragma unroll
         for (int k = 0; k < kSW; ++k) {
             const float w = t.g[k];
@@ -111,32 +112,30 @@ __global__ __launch_bounds__(kThreads) void k_ssim_fwd(int C, int H, int W, cons
                 const float xv = x[o + k], yv = y[o + k];
                 a[o] = __builtin_fmaf(w, xv, a[o]);
                 b[o] = __builtin_fmaf(w, yv, b[o]);
-                aa[o] = __builtin_fmaf(w, xv * xv, aa[o]);
-                bb[o] = __builtin_fmaf(w, yv * yv, bb[o]);
+                sq[o] = __builtin_fmaf(w, __builtin_fmaf(xv, xv, yv * yv), sq[o]);
                 ab[o] = __builtin_fmaf(w, xv * yv, ab[o]);
             }
         }
         store4(&s_h[0][r][c0], a);
         store4(&s_h[1][r][c0], b);
-        store4(&s_h[2][r][c0], aa);
-        store4(&s_h[3][r][c0], bb);
-        store4(&s_h[4][r][c0], ab);
+        store4(&s_h[2][r][c0], sq);
+        store4(&s_h[3][r][c0], ab);
     }
     __syncthreads();
     // vertical pass: column c, output rows r0 .. r0 + 3 from staged rows r0 .. r0 + 13
     const int c = threadIdx.x % kSTW, r0 = (threadIdx.x / kSTW) * kRowsPT;
-    float m[kRowsPT][5] = {};
+    float m[kRowsPT][4] = {};
 #pragma unroll
     for (int j = 0; j < kVRows; ++j) {
-        float h[5];
+        float h[4];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) h[q] = s_h[q][r0 + j][c];
+        for (int q = 0; q < 4; ++q) h[q] = s_h[q][r0 + j][c];
 #pragma unroll
         for (int o = 0; o < kRowsPT; ++o) {
             const int k = j - o;
             if (k >= 0 && k < kSW) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) m[o][q] = __builtin_fmaf(t.g[k], h[q], m[o][q]);
+                for (int q = 0; q < 4; ++q) m[o][q] = __builtin_fmaf(t.g[k], h[q], m[o][q]);
             }
         }
     }
@@ -147,9 +146,9 @@ __global__ __launch_bounds__(kThreads) void k_ssim_fwd(int C, int H, int W, cons
         const int y = y0 + r0 + o;
         if (x >= W || y >= H) continue;
         const float mx = m[o][0], my = m[o][1];
-        const float sxx = m[o][2] - mx * mx, syy = m[o][3] - my * my, sxy = m[o][4] - mx * my;
+        const float sxy = m[o][3] - mx * my;
         const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
-        const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
+        const float B1 = mx * mx + my * my + kC1, B2 = (m[o][2] - (mx * mx + my * my)) + kC2;
         // one division: 1/B1 = B2 iD, 1/B2 = B1 iD
         const float iD = 1.f / (B1 * B2);
         const float S = A1 * A2 * iD;
