@@ -88,6 +88,39 @@ def test_bad_arguments_are_rejected_before_launch():
     assert qg.qg_total_tiles([_cam(100, 70)], qg.tiling(32, 8)) == 4 * 9
 
 
+def _rejects(call, *words, status=None):
+    with pytest.raises(qg.QGError) as e:
+        call()
+    assert e.value.status == (qg.QG_ERR_ARG if status is None else status), str(e.value)
+    for w in words:
+        assert w in str(e.value), (w, str(e.value))
+
+
+def test_mask_ssim_and_symbol_calls_reject_bad_arguments_before_launch():
+    # D-SSIM: sizes, outputs, workspace, and the 2^31-pixel plane limit of its 32-bit staging offsets
+    ws = qg.qg_ssim_workspace_size(3, 40, 50)
+    _rejects(lambda: qg.qg_ssim_loss(0, 40, 50, 1, 1, 0.2, 1, 1, 1, ws, stream=0), "C=0")
+    _rejects(lambda: qg.qg_ssim_loss(3, 40, 50, None, 1, 0.2, 1, 1, 1, ws, stream=0), "NULL")
+    _rejects(lambda: qg.qg_ssim_loss(3, 40, 50, 1, 1, 0.2, None, None, 1, ws, stream=0), "nothing to compute")
+    _rejects(lambda: qg.qg_ssim_loss(3, 40, 50, 1, 1, 0.2, 1, 1, 1, ws - 1, stream=0), "workspace")
+    big = qg.qg_ssim_workspace_size(1, 1 << 16, 1 << 15)
+    _rejects(lambda: qg.qg_ssim_loss(1, 1 << 16, 1 << 15, 1, 1, 0.2, 1, 1, 1, big, stream=0), "too large")
+    assert qg.qg_ssim_workspace_size(0, 1, 1) == 0
+    # masked L1: whole planes, 32-bit pixel count
+    _rejects(lambda: qg.qg_l1_loss_masked(10, 3, 1, 1, 1, 1.0, 1, 1, stream=0), "multiple")
+    _rejects(lambda: qg.qg_l1_loss_masked(3 << 32, 3, 1, 1, 1, 1.0, 1, 1, stream=0), "2^32")
+    _rejects(lambda: qg.qg_l1_loss_masked(12, 3, 1, 1, None, 1.0, 1, 1, stream=0), "NULL")
+    # the dynamic split, dilation and tile ranges of masked training
+    _rejects(lambda: qg.qg_dynamic_flags(10, 1, 0.0, 1.0, 1e-3, 1, stream=0), "sx")
+    _rejects(lambda: qg.qg_dynamic_flags(10, 1, 1.0, 1.0, -1.0, 1, stream=0), "t_d")
+    _rejects(lambda: qg.qg_dilate_mask([_cam()], qg.tiling(16, 16), 0, [1], [1], [1], 1, stream=0), "k=0")
+    _rejects(lambda: qg.qg_dilate_mask([_cam()], qg.tiling(16, 16), 48, [1], [None], [1], 1, stream=0), "NULL")
+    _rejects(lambda: qg.qg_mask_tile_ranges(0, 1, 1, stream=0), "total_tiles")
+    # latent symbols: L in [1, 16], ld >= n
+    _rejects(lambda: qg.qg_latent_symbols(10, 10, 1, 17, 1, 1, 1, stream=0), "L=17")
+    _rejects(lambda: qg.qg_latent_symbols(10, 5, 1, 8, 1, 1, 1, stream=0), "ld=5")
+
+
 def test_workspace_queries():
     assert qg.qg_bin_workspace_size(1000, 2, 50000, 100) > 0
     assert qg.qg_render_bwd_workspace_size(1000, 3) >= 3 * 1000 * 12 * 4
