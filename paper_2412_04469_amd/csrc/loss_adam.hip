@@ -83,20 +83,48 @@ __global__ __launch_bounds__(kLBlock) void k_l1(int64_t count, const float* __re
 
 // As k_l1 over the elements whose pixel (index mod plane) is set in mask; the others get a zero gradient and
 // add nothing to the sums.  The scale stays 1/count (the masked-iteration reading of Sec. 3.3: the loss of
-// the rendered pixels at the full image's normalisation).
+// the rendered pixels at the full image's normalisation).  vec: as in k_l1, and in addition plane is a
+// multiple of 4 and mask 4-byte aligned, so a float4 of elements never crosses a plane boundary and its four
+// mask bytes are one aligned word (byte k for element k).  The elements are visited in k_l1's order, so with
+// every pixel set the sums are k_l1's.
 __global__ __launch_bounds__(kLBlock) void k_l1_masked(int64_t count, int64_t plane, const float* __restrict__ img,
                                                        const float* __restrict__ gt,
                                                        const uint8_t* __restrict__ mask, float gscale,
-                                                       float* __restrict__ grad, double* __restrict__ part) {
+                                                       float* __restrict__ grad, double* __restrict__ part, int vec) {
     __shared__ double s_a[kLBlock / kWave], s_b[kLBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * kLTile;
     float sa = 0.f, sb = 0.f;
+    if (vec && base + kLTile <= count) {
+        const float4* I = reinterpret_cast<const float4*>(img + base);
+        const float4* T = reinterpret_cast<const float4*>(gt + base);
+        float4* D = reinterpret_cast<float4*>(grad + base);
+        float4 x[kLIPT / 4], y[kLIPT / 4];
+        uint32_t mk[kLIPT / 4];
 #pragma unroll
-    for (int r = 0; r < kLIPT; ++r) {
-        const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
-        if (i < count) {
-            const float gr = mask[(uint32_t)i % (uint32_t)plane] ? l1_term(img[i], gt[i], gscale, sa, sb) : 0.f;
-            if (grad) grad[i] = gr;
+        for (int r = 0; r < kLIPT / 4; ++r) {
+            const int q = r * kLBlock + threadIdx.x;
+            x[r] = I[q];
+            y[r] = T[q];
+            const uint32_t pix = (uint32_t)(base + 4 * q) % (uint32_t)plane;  // count < 2^32
+            mk[r] = *reinterpret_cast<const uint32_t*>(mask + pix);
+        }
+#pragma unroll
+        for (int r = 0; r < kLIPT / 4; ++r) {
+            float4 gr;
+            gr.x = (mk[r] & 0xffu) ? l1_term(x[r].x, y[r].x, gscale, sa, sb) : 0.f;
+            gr.y = (mk[r] & 0xff00u) ? l1_term(x[r].y, y[r].y, gscale, sa, sb) : 0.f;
+            gr.z = (mk[r] & 0xff0000u) ? l1_term(x[r].z, y[r].z, gscale, sa, sb) : 0.f;
+            gr.w = (mk[r] & 0xff000000u) ? l1_term(x[r].w, y[r].w, gscale, sa, sb) : 0.f;
+            if (grad) D[r * kLBlock + threadIdx.x] = gr;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kLIPT; ++r) {
+            const int64_t i = base + (int64_t)r * kLBlock + threadIdx.x;
+            if (i < count) {
+                const float gr = mask[(uint32_t)i % (uint32_t)plane] ? l1_term(img[i], gt[i], gscale, sa, sb) : 0.f;
+                if (grad) grad[i] = gr;
+            }
         }
     }
     l1_block_partials(sa, sb, s_a, s_b, part);
@@ -274,7 +302,10 @@ extern "C" qg_status qg_l1_loss_masked(int64_t count, int64_t plane, const float
     const float gs = count > 0 ? scale / (float)count : 0.f;
     {
         QG_TIMED("l1", s);
-        k_l1_masked<<<(unsigned)nb, kLBlock, 0, s>>>(count, plane, image, gt, mask, gs, grad_image, partials);
+        auto al16 = [](const void* x) { return ((uintptr_t)x & 15u) == 0; };
+        const int vec = al16(image) && al16(gt) && al16(grad_image) && plane % 4 == 0 &&
+                        ((uintptr_t)mask & 3u) == 0;
+        k_l1_masked<<<(unsigned)nb, kLBlock, 0, s>>>(count, plane, image, gt, mask, gs, grad_image, partials, vec);
     }
     QG_LAUNCH_CHECK("qg_l1_loss_masked");
     return QG_OK;

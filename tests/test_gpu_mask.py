@@ -92,10 +92,11 @@ def test_dilate_and_tile_flags_exact(qgm, tile, k):
     assert 0 < np.concatenate(want_f).sum() < total
 
 
-def test_masked_l1_parity(qgm):
+@pytest.mark.parametrize("H,W", [(97, 131),   # plane not a multiple of 4: per-element path
+                                 (64, 100)])  # float4 path on 4 whole blocks, per-element tail
+def test_masked_l1_parity(qgm, H, W):
     qg, _ = qgm
-    rng = np.random.default_rng(8)
-    H, W = 97, 131
+    rng = np.random.default_rng(8 + H)
     img = rng.random((3, H, W)).astype(np.float32)
     gt = rng.random((3, H, W)).astype(np.float32)
     gt[:, 10, :20] = img[:, 10, :20]  # zero differences: sign 0
@@ -111,6 +112,20 @@ def test_masked_l1_parity(qgm):
     gg = grad.cpu().numpy()
     assert np.array_equal(gg == 0.0, g == 0.0)
     np.testing.assert_allclose(gg, g, rtol=1e-7, atol=0)
+    # every pixel set: the unmasked loss; on the float4 path its sums, in the same order, bit for bit
+    ones = torch.ones((H, W), dtype=torch.uint8, device="cuda")
+    out1 = torch.empty(2, dtype=torch.float64, device="cuda")
+    qg.qg_l1_loss_masked(count, H * W, to_dev(img), to_dev(gt), ones, 1.0, grad, parts)
+    qg.qg_loss_reduce(count, parts, out1)
+    g1 = grad.clone()
+    out2 = torch.empty(2, dtype=torch.float64, device="cuda")
+    qg.qg_l1_loss(count, to_dev(img), to_dev(gt), 1.0, grad, parts)
+    qg.qg_loss_reduce(count, parts, out2)
+    assert torch.equal(g1, grad)
+    if (H * W) % 4 == 0:
+        assert torch.equal(out1, out2)
+    else:
+        assert torch.allclose(out1, out2, rtol=1e-6, atol=0)
 
 
 def _masked_run(qg, raster, sc, cams, tile, bg, gts, pix, flags):
