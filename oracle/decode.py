@@ -8,8 +8,7 @@ where a = log(alpha) is the learnable gate parameter, and the L0 surrogate of Eq
 Readings (listed in the design notes):
     * rounding is round-half-to-even (torch.round);
     * the decoder is one shared bias-free two-layer MLP with SiLU, latent 8 -> hidden 32 -> 56 outputs
-      (rotation 4, log-scale 3, opacity logit 1, SH 48), so zero latents decode to a zero residual
-      ("linear" mode: D l, a single matrix, is also offered);
+      (rotation 4, log-scale 3, opacity logit 1, SH 48), so zero latents decode to a zero residual;
     * residuals are added in the stored parameter space (mean, raw quaternion, log-scale, logit, SH);
     * L_reg is the mean over Gaussians (``reduction='sum'`` gives Eq. 8 literally);
     * the gate is deterministic as Eq. 6 is written (no noise sample).

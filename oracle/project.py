@@ -20,8 +20,11 @@ Readings where the paper is silent (listed in the design notes):
       [p' - r, p' + r]; the tile rectangle is the set of tiles holding a covered pixel, clipped to the image.
 
 Pinned by closed forms (on-axis and off-axis Sigma'), Monte-Carlo convergence of the projected sample
-covariance, rigid-motion invariance, SH quadrature, and (for the rectangle) a brute-force check that
-every pixel with alpha >= 1/255 lies in a tile of the rectangle.  Gradients come from torch autograd
+covariance, rigid-motion invariance, SH quadrature, textbook degree-1..3 SH values along the direction from a
+rotated, translated camera's centre to the mean (a reversed direction flips the odd degrees), and for the
+rectangle: a brute-force check that every pixel with alpha >= 1/255 lies in a tile of the rectangle
+(containment), the exact rectangles of an isotropic splat whose support disc is known in closed form (one at
+the image border), and a parametric sampling of the support ellipse's extent (tightness).  Gradients come from torch autograd
 applied to these plain formulas.
 """
 from __future__ import annotations
@@ -96,7 +99,7 @@ def project(means, quats, log_scales, logits, sh, cam, sh_degree: int = 3, dilat
     conic = torch.stack([c / dets, -b / dets, a / dets], -1)
     xy = torch.stack([fx * uxs / uzs + float(cam.cx), fy * uys / uzs + float(cam.cy)], -1)
     opacity = torch.sigmoid(logits)
-    cc = torch.as_tensor(cam.center())
+    cc = -(R.T @ t)  # camera centre c_v = -R^T t (u = R p + t vanishes there)
     v = means - cc
     dirs = v / torch.linalg.vector_norm(v, dim=-1, keepdim=True)
     nb = (sh_degree + 1) ** 2

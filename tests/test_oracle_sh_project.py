@@ -169,3 +169,129 @@ def test_culling():
     assert not bool(pr["valid"][0])  # sigmoid(-7) < 1/255
     pr = P.project(*_one([0, 0, 2.0], [1, 0, 0, 0], np.log([0.1] * 3), logit=-5.0), cam, 3, 0.3)
     assert bool(pr["valid"][0])
+
+
+def _pose(centre, axis, ang):
+    """World->camera (R, t) of a camera at ``centre`` rotated by ``ang`` about ``axis`` (t = -R centre)."""
+    R = _rot(axis, ang)
+    return R, -R @ np.asarray(centre, np.float64)
+
+
+# Textbook real SH with the Condon-Shortley phase, written out per (l, m) on a unit vector (x, y, z):
+# index k = l^2 + l + m.
+_SH_TEXTBOOK = {
+    1: lambda x, y, z: -math.sqrt(3 / (4 * math.pi)) * y,                             # Y_1^-1
+    2: lambda x, y, z: math.sqrt(3 / (4 * math.pi)) * z,                              # Y_1^0
+    3: lambda x, y, z: -math.sqrt(3 / (4 * math.pi)) * x,                             # Y_1^1
+    4: lambda x, y, z: 0.5 * math.sqrt(15 / math.pi) * x * y,                         # Y_2^-2
+    6: lambda x, y, z: 0.25 * math.sqrt(5 / math.pi) * (3 * z * z - 1),               # Y_2^0
+    9: lambda x, y, z: -0.25 * math.sqrt(35 / (2 * math.pi)) * (3 * x * x - y * y) * y,  # Y_3^-3
+    12: lambda x, y, z: 0.25 * math.sqrt(7 / math.pi) * (5 * z ** 3 - 3 * z),          # Y_3^0
+}
+
+
+@pytest.mark.parametrize("k", sorted(_SH_TEXTBOOK))
+def test_sh_colour_along_camera_to_mean_direction(k):
+    """Colour of one SH coefficient set, for a camera that is rotated and translated: c = max(0, h Y_k(dir) + 0.5)
+    with dir the unit vector from the camera centre -R^T t to the mean.  The odd degrees change sign if the
+    direction is reversed, and the value depends on the camera centre, not on the camera's axis."""
+    centre = np.array([0.7, -1.2, 2.0])
+    R, t = _pose(centre, [0.3, 1.0, -0.4], 0.9)
+    cam = _cam(R=R, t=t)
+    fwd = R.T @ np.array([0.3, 0.3, 1.0])  # off the optical axis, in front of the camera
+    u = fwd / np.linalg.norm(fwd)
+    mean = centre + 3.0 * u
+    l = int(math.isqrt(k))
+    h = np.zeros((1, 16, 3)); h[0, k] = [0.8, -0.6, 1.7]
+    # float64 camera: synth.Camera keeps what it is given
+    cam = synth.Camera(cam.fx, cam.fy, cam.cx, cam.cy, R, t, cam.width, cam.height, cam.z_near)
+    pr = P.project(*_one(mean, [1, 0, 0, 0], np.log([0.05] * 3), sh=h), cam, 3, 0.3)
+    assert bool(pr["valid"][0])
+    y = _SH_TEXTBOOK[k](*u)
+    assert abs(y) > 0.05  # the pin is informative
+    want = np.maximum(0.0, h[0, k] * y + 0.5)
+    np.testing.assert_allclose(pr["rgb_pre"][0].numpy(), h[0, k] * y + 0.5, atol=1e-12)
+    np.testing.assert_allclose(pr["rgb"][0].numpy(), want, atol=1e-12)
+    if l % 2 == 1:
+        flipped = h[0, k] * _SH_TEXTBOOK[k](*(-u)) + 0.5
+        assert np.abs(flipped - (h[0, k] * y + 0.5)).max() > 0.05
+    # a lower degree ignores the coefficient
+    pr0 = P.project(*_one(mean, [1, 0, 0, 0], np.log([0.05] * 3), sh=h), cam, l - 1, 0.3)
+    np.testing.assert_allclose(pr0["rgb"][0].numpy(), 0.5, atol=1e-15)
+
+
+def _iso_splat(cx, cy, w=80, h=72):
+    """sigma' = 4 px isotropic with no dilation (f s / z = 64 * 0.125 / 2), opacity 1/2, centred at (cx, cy)."""
+    cam = _cam(f=(64.0, 64.0), c=(cx, cy), w=w, h=h)
+    pr = P.project(*_one([0, 0, 2.0], [1, 0, 0, 0], np.log([0.125] * 3), logit=0.0), cam, 0, 0.0)
+    return pr, cam
+
+
+@pytest.mark.parametrize("tile,want", [((8, 8), (2, 2, 6, 6)), ((16, 16), (1, 1, 3, 3)), ((32, 8), (0, 2, 2, 6))])
+def test_rectangle_exact_for_isotropic_splat(tile, want):
+    """alpha >= 1/255 holds exactly on the disc of radius 4 sqrt(2 ln 127.5) = 12.4555 px; centred on the pixel
+    centre (32.5, 32.5) its covered pixel columns and rows are 20..44, so the tile rectangle is known exactly.
+    A rectangle one tile too large or too small fails."""
+    pr, cam = _iso_splat(32.5, 32.5)
+    np.testing.assert_allclose(pr["cov2d"][0].numpy(), [16.0, 0.0, 16.0], rtol=1e-14, atol=1e-14)
+    j0, j1, i0, i1, empty, _ = P.pixel_rect(pr["xy"].numpy(), pr["cov2d"].numpy(), pr["opacity"].numpy(),
+                                            pr["valid"].numpy(), cam.width, cam.height)
+    assert (int(j0[0]), int(j1[0]), int(i0[0]), int(i1[0]), bool(empty[0])) == (20, 44, 20, 44, False)
+    rect, nt, _ = P.tile_rect(pr["xy"].numpy(), pr["cov2d"].numpy(), pr["opacity"].numpy(), pr["valid"].numpy(),
+                              cam.width, cam.height, *tile)
+    assert tuple(int(v) for v in rect[0]) == want
+    assert int(nt[0]) == (want[2] - want[0]) * (want[3] - want[1])
+    # the covered pixels found by brute force span exactly those columns and rows (489 of them)
+    jj, ii = np.meshgrid(np.arange(cam.width) + 0.5, np.arange(cam.height) + 0.5)
+    q = ((jj - 32.5) ** 2 + (ii - 32.5) ** 2) / 16.0
+    hit = np.argwhere(0.5 * np.exp(-0.5 * q) >= 1 / 255)
+    assert len(hit) == 489
+    assert (hit[:, 1].min(), hit[:, 1].max(), hit[:, 0].min(), hit[:, 0].max()) == (20, 44, 20, 44)
+
+
+def test_rectangle_exact_clipped_and_offscreen():
+    """The same splat at (5.5, 60.5) in an 80 x 72 image: columns 0..17 and rows 48..71 after clipping, 16 x 16
+    tiles (0, 3)-(2, 5).  Entirely off-screen: an empty rectangle and no tiles."""
+    pr, cam = _iso_splat(5.5, 60.5)
+    args = (pr["xy"].numpy(), pr["cov2d"].numpy(), pr["opacity"].numpy(), pr["valid"].numpy(), cam.width, cam.height)
+    j0, j1, i0, i1, empty, _ = P.pixel_rect(*args)
+    assert (int(j0[0]), int(j1[0]), int(i0[0]), int(i1[0]), bool(empty[0])) == (0, 17, 48, 71, False)
+    rect, nt, _ = P.tile_rect(*args, 16, 16)
+    assert tuple(int(v) for v in rect[0]) == (0, 3, 2, 5) and int(nt[0]) == 4
+    pr, cam = _iso_splat(-13.0, 30.0)  # support reaches x = -0.54 < 0: no pixel centre
+    args = (pr["xy"].numpy(), pr["cov2d"].numpy(), pr["opacity"].numpy(), pr["valid"].numpy(), cam.width, cam.height)
+    rect, nt, _ = P.tile_rect(*args, 16, 16)
+    assert (rect[0] == 0).all() and int(nt[0]) == 0
+
+
+def test_rectangle_tight_against_sampled_support_ellipse():
+    """Tightness on a random scene: the support ellipse d^T conic d <= 2 ln(255 o) is traced as d = k L (cos t,
+    sin t) with L L^T = Sigma' (Cholesky), and its sampled extent gives the pixel-centre columns and rows and the
+    tiles; the oracle's rectangles must equal them (cases within 1e-3 px of a pixel-centre boundary skipped)."""
+    rng = synth.rng_for(201)
+    sc = synth.draw_scene(rng, 400, 1.0, -3.0, 0.6)
+    cam = synth.make_camera((0.2, -0.1, -4.0), 120, 90, f=110)
+    pr = P.project(*P.scene_tensors(sc), cam)
+    xy, cov, o, valid = (pr[k].detach().numpy() for k in ("xy", "cov2d", "opacity", "valid"))
+    ts = np.linspace(0.0, 2 * math.pi, 1 << 15, endpoint=False)
+    circ = np.stack([np.cos(ts), np.sin(ts)])
+    for tw, th in ((8, 8), (16, 16), (32, 8)):
+        rect, nt, _ = P.tile_rect(xy, cov, o, valid, cam.width, cam.height, tw, th)
+        checked = 0
+        for i in np.flatnonzero(valid):
+            S = np.array([[cov[i, 0], cov[i, 1]], [cov[i, 1], cov[i, 2]]])
+            k = math.sqrt(2 * math.log(255 * o[i]))
+            pts = k * (np.linalg.cholesky(S) @ circ)
+            lo_x, hi_x = xy[i, 0] + pts[0].min(), xy[i, 0] + pts[0].max()
+            lo_y, hi_y = xy[i, 1] + pts[1].min(), xy[i, 1] + pts[1].max()
+            edges = np.array([lo_x - 0.5, hi_x - 0.5, lo_y - 0.5, hi_y - 0.5])
+            if (np.abs(edges - np.round(edges)) < 1e-3).any():
+                continue
+            j0, j1 = max(math.ceil(edges[0]), 0), min(math.floor(edges[1]), cam.width - 1)
+            i0, i1 = max(math.ceil(edges[2]), 0), min(math.floor(edges[3]), cam.height - 1)
+            if j0 > j1 or i0 > i1:
+                assert int(nt[i]) == 0 and (rect[i] == 0).all()
+                continue
+            assert tuple(int(v) for v in rect[i]) == (j0 // tw, i0 // th, j1 // tw + 1, i1 // th + 1), i
+            checked += 1
+        assert checked > 100
