@@ -196,7 +196,7 @@ def batched_section(args):
     ms = time_steps(f, args.batched_steps, 3)
     overflow = f.overflowed()
     px = sum(c.width * c.height for c in wl.cams)
-    pairs = int(f.rasts[0].num_pairs.item())
+    pairs = f.rasts[0].pair_count()
     del f
     torch.cuda.empty_cache()
     # the same views, one view per launch sequence (single-view fit steps at each resolution)
@@ -541,7 +541,7 @@ def main():
         fitter.forward_view(v)
         evals.append(eval_count(fitter.rast))
     torch.cuda.synchronize()
-    assert int(fitter.rast.num_pairs.item()) <= fitter.rast.capacity
+    assert not fitter.rast.overflowed()
 
     # timed region: only the dominant kernel is bracketed by library events
     qg.qg_timing_enable(True, dominant)
@@ -557,7 +557,7 @@ def main():
     ms_total = start.elapsed_time(stop)
     dom = qg.qg_timing_report().get(dominant, (0, 0.0))
     qg.qg_timing_enable(False)
-    overflow = int(fitter.rast.num_pairs.item()) > fitter.rast.capacity
+    overflow = fitter.rast.overflowed()
     ms_step = ms_total / args.steps
     dom_avg_ms = dom[1] / max(dom[0], 1)
     views = [(first + i) % V for i in range(args.steps)]

@@ -255,7 +255,7 @@ class FrameFitter(ResidualState):
             self.rast.qcams = self.qcams[v]
             self.rast.project(self.attrs)
             self.rast.bin()
-            worst = max(worst, int(self.rast.num_pairs.item()))
+            worst = max(worst, self.rast.pair_count())
         if worst * 1.05 > self.rast.capacity:
             self.rast._alloc_capacity(int(worst * margin))
         return worst
@@ -396,7 +396,7 @@ class BatchedFitter(ResidualState):
 
     def overflowed(self):
         """True if the last binning of some group exceeded its pair capacity (host sync)."""
-        return any(int(r.num_pairs.item()) > r.capacity for r in self.rasts)
+        return any([r.overflowed() for r in self.rasts])
 
     def size_capacity(self, margin=1.3):
         """Bin every group once (host syncs) and size each group's pair capacity; drops captured graphs."""
@@ -405,7 +405,7 @@ class BatchedFitter(ResidualState):
         for r in self.rasts:
             r.project(self.attrs)
             r.bin()
-            p = int(r.num_pairs.item())
+            p = r.pair_count()
             worst.append(p)
             if p * 1.05 > r.capacity:
                 r._alloc_capacity(int(p * margin))
@@ -516,6 +516,8 @@ class GateInitializer:
             r.set_cameras([cam])
             r.project(prev_attrs)
             r.bin()
+            if r.ensure_capacity():
+                r.bin()
             qg.qg_dynamic_mask(r.t_proj, r.qcams, r.tile, r.vals, r.ranges, self.dyn, [self.raw])
             pix, flags = self.mask_bufs[v]
             qg.qg_dilate_mask(r.qcams, r.tile, c.mask_dilate, [self.raw], [self.tmp], [pix], flags)

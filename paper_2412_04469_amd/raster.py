@@ -96,11 +96,21 @@ class Rasterizer:
         qg.qg_render_fwd(self.t_proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.t_img, self.t_tf,
                          self.t_last, stream)
 
-    def ensure_capacity(self, margin=1.25) -> bool:
-        """Host-synchronising check of the last bin; grows the buffers and returns True if it overflowed."""
+    def pair_count(self) -> int:
+        """Pair count of the last qg_bin (host sync).  Raises QGError if the sort reported that a workgroup gave
+        up waiting for its predecessors (num_pairs < 0): the tile lists of that binning are invalid."""
         p = int(self.num_pairs.item())
         if p < 0:
-            raise qg.QGError(qg.QG_ERR_HIP, "qg_bin reported an internal sort failure (num_pairs = -1)")
+            raise qg.QGError(qg.QG_ERR_HIP, f"qg_bin reported an internal sort failure (num_pairs = {p})")
+        return p
+
+    def overflowed(self) -> bool:
+        """True if the last qg_bin found more pairs than the capacity (host sync; raises as pair_count)."""
+        return self.pair_count() > self.capacity
+
+    def ensure_capacity(self, margin=1.25) -> bool:
+        """Host-synchronising check of the last bin; grows the buffers and returns True if it overflowed."""
+        p = self.pair_count()
         if p > self.capacity:
             self._alloc_capacity(int(math.ceil(p * margin)))
             return True

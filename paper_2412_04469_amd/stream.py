@@ -52,8 +52,8 @@ class Sequence:
 
 def _check_capacity(fitter):
     r = fitter.rast if hasattr(fitter, "rast") else None
-    if r is not None and int(r.num_pairs.item()) > r.capacity:
-        r._alloc_capacity(int(int(r.num_pairs.item()) * 1.3))
+    if r is not None and r.overflowed():
+        r._alloc_capacity(int(r.pair_count() * 1.3))
         return True
     if hasattr(fitter, "rasts") and fitter.overflowed():
         fitter.size_capacity()
