@@ -188,6 +188,25 @@ qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera* cams, int
                  int64_t capacity, uint32_t* vals, uint64_t* keys, uint32_t* tile_ranges, int64_t* num_pairs,
                  void* ws, size_t ws_bytes, qg_stream stream);
 
+/*
+ * qg_bin without a workspace argument, for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation).  Arguments, results and errors are those
+ * of qg_bin; the caller still passes and owns vals, keys, tile_ranges and num_pairs.  The workspace is a
+ * device array of QG_BIN_NOALLOC_SCRATCH_BYTES bytes held by the library: one copy per device, kept until the
+ * process ends, its address looked up on the first call on each device (make that first call outside stream
+ * capture).  The call allocates and frees nothing.
+ *   Limit: a call whose qg_bin_workspace_size(n, V, capacity, .) exceeds QG_BIN_NOALLOC_SCRATCH_BYTES returns
+ *   QG_ERR_ARG with nothing enqueued (64 MiB holds e.g. 300k Gaussians, one view, capacity 3.5M pairs).
+ *   Sharing: every call on a device uses that device's one array, which keeps the last call's contents (each
+ *   call clears what it needs zeroed itself).  Calls that overlap in time on one device -- on different
+ *   streams or from different host threads -- race on it and give wrong results: serialise them.
+ */
+#define QG_BIN_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t qg_bin_noalloc_max_bytes(void);
+qg_status qg_bin_noalloc(int64_t n, const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                         int64_t capacity, uint32_t* vals, uint64_t* keys, uint32_t* tile_ranges,
+                         int64_t* num_pairs, qg_stream stream);
+
 /* ---------------------------------------------------------------------------------------------- */
 /* Front-to-back alpha compositing (Eq. 2).                                                        */
 /* ---------------------------------------------------------------------------------------------- */

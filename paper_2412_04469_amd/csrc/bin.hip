@@ -18,6 +18,7 @@
 // per-wave digit counters in LDS, which keeps the sort stable.  The per-(view, Gaussian) tile counts are
 // scanned the same way, in one kernel.
 #include <algorithm>
+#include <mutex>
 
 #include "qg_internal.h"
 
@@ -598,26 +599,36 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
 
 using namespace qg;
 
+// The workspace of qg_bin_noalloc.  Each device the library runs on holds its own copy for the life of the
+// process; host code takes that copy's address from hipGetSymbolAddress and never uses the array's name, which
+// in host code is only a stand-in for it.
+static __device__ __align__(256) unsigned char scratch[QG_BIN_NOALLOC_SCRATCH_BYTES];
+
 extern "C" size_t qg_bin_workspace_size(int64_t n, int32_t V, int64_t capacity, int64_t total_tiles) {
     (void)total_tiles;
     if (n < 0 || V < 1 || capacity < 0) return 0;
     return bin_ws_layout(nullptr, n, V, capacity).bytes;
 }
 
-extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
-                            int64_t capacity, uint32_t* vals, uint64_t* keys, uint32_t* tile_ranges,
-                            int64_t* num_pairs, void* ws, size_t ws_bytes, qg_stream stream) {
-    clear_error();
+namespace qg {
+namespace {
+
+// Argument checks shared by qg_bin and qg_bin_noalloc (nothing is enqueued on failure).
+qg_status bin_check(int64_t n, const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                    int64_t capacity, const uint32_t* vals, const uint32_t* tile_ranges, const int64_t* num_pairs,
+                    ViewTable* vt) {
     QG_REQUIRE(n >= 0 && n < (1ll << 31), "n=%lld outside [0, 2^31)", (long long)n);
     QG_REQUIRE(capacity >= 0 && capacity <= 0xFFFFFFFFll, "capacity=%lld outside [0, 2^32)", (long long)capacity);
-    ViewTable vt;
-    if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
+    if (!make_view_table(cams, proj, V, tiling, true, vt)) return QG_ERR_ARG;
     QG_REQUIRE((int64_t)n * V < (1ll << 32), "n*V too large");
     QG_REQUIRE(tile_ranges && num_pairs, "tile_ranges and num_pairs are required");
     QG_REQUIRE(capacity == 0 || vals, "vals is NULL");
+    return QG_OK;
+}
+
+qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, uint32_t* vals, uint64_t* keys,
+                  uint32_t* tile_ranges, int64_t* num_pairs, void* ws, hipStream_t s) {
     BinWs w = bin_ws_layout((char*)ws, n, V, capacity);
-    QG_REQUIRE(ws && ws_bytes >= w.bytes, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
-    hipStream_t s = (hipStream_t)stream;
     const int64_t items = n * V;
     const int64_t T = vt.total_tiles;
     int tbits = 1;
@@ -710,4 +721,70 @@ extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera
         QG_LAUNCH_CHECK("qg_bin keys");
     }
     return QG_OK;
+}
+
+// ---- the scratch-free variant -----------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once per device.
+qg_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("qg_bin_noalloc: hipGetDevice failed: %s", hipGetErrorString(e));
+        return QG_ERR_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("qg_bin_noalloc: device %d outside [0, %d)", dev, kMaxDevices);
+        return QG_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("qg_bin_noalloc: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+            return QG_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QG_OK;
+}
+
+}  // namespace
+}  // namespace qg
+
+extern "C" size_t qg_bin_noalloc_max_bytes(void) { return QG_BIN_NOALLOC_SCRATCH_BYTES; }
+
+extern "C" qg_status qg_bin(int64_t n, const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                            int64_t capacity, uint32_t* vals, uint64_t* keys, uint32_t* tile_ranges,
+                            int64_t* num_pairs, void* ws, size_t ws_bytes, qg_stream stream) {
+    clear_error();
+    ViewTable vt;
+    qg_status st = bin_check(n, proj, cams, V, tiling, capacity, vals, tile_ranges, num_pairs, &vt);
+    if (st != QG_OK) return st;
+    const size_t need = bin_ws_layout(nullptr, n, V, capacity).bytes;
+    QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    return bin_run(n, vt, V, capacity, vals, keys, tile_ranges, num_pairs, ws, (hipStream_t)stream);
+}
+
+extern "C" qg_status qg_bin_noalloc(int64_t n, const qg_projected* proj, const qg_camera* cams, int32_t V,
+                                    qg_tiling tiling, int64_t capacity, uint32_t* vals, uint64_t* keys,
+                                    uint32_t* tile_ranges, int64_t* num_pairs, qg_stream stream) {
+    clear_error();
+    ViewTable vt;
+    qg_status st = bin_check(n, proj, cams, V, tiling, capacity, vals, tile_ranges, num_pairs, &vt);
+    if (st != QG_OK) return st;
+    const size_t need = bin_ws_layout(nullptr, n, V, capacity).bytes;
+    QG_REQUIRE(need <= (size_t)QG_BIN_NOALLOC_SCRATCH_BYTES,
+               "qg_bin_noalloc: n=%lld, V=%d, capacity=%lld need %zu bytes of scratch, above the %zu of the "
+               "library's array (use qg_bin with a workspace)",
+               (long long)n, V, (long long)capacity, need, (size_t)QG_BIN_NOALLOC_SCRATCH_BYTES);
+    void* ptr = nullptr;
+    st = scratch_for_current_device(&ptr);
+    if (st != QG_OK) return st;
+    return bin_run(n, vt, V, capacity, vals, keys, tile_ranges, num_pairs, ptr, (hipStream_t)stream);
 }

@@ -76,6 +76,8 @@ def lib():
             "qg_project": ([i64, i64, P, i32, CAM, i32, qg_tiling, f32, PRJ, P], i32),
             "qg_bin_workspace_size": ([i64, i32, i64, i64], sz),
             "qg_bin": ([i64, PRJ, CAM, i32, qg_tiling, i64, P, P, P, P, P, sz, P], i32),
+            "qg_bin_noalloc": ([i64, PRJ, CAM, i32, qg_tiling, i64, P, P, P, P, P], i32),
+            "qg_bin_noalloc_max_bytes": ([], sz),
             "qg_render_fwd": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P, P, P], i32),
             "qg_render_bwd_workspace_size": ([i64, i32], sz),
             "qg_render_bwd": ([i64, i64, P, i32, CAM, i32, qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, sz, P],
@@ -283,6 +285,17 @@ def qg_bin(n, proj, cams, tile, capacity, vals, keys, tile_ranges, num_pairs, ws
     pa = projected_array(proj)
     _check(lib().qg_bin(int(n), pa, ca, len(cams), tile, int(capacity), _ptr(vals), _ptr(keys), _ptr(tile_ranges),
                         _ptr(num_pairs), _ptr(ws), int(ws_bytes), _stream(stream)))
+
+
+def qg_bin_noalloc_max_bytes():
+    return int(lib().qg_bin_noalloc_max_bytes())
+
+
+def qg_bin_noalloc(n, proj, cams, tile, capacity, vals, keys, tile_ranges, num_pairs, stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    _check(lib().qg_bin_noalloc(int(n), pa, ca, len(cams), tile, int(capacity), _ptr(vals), _ptr(keys),
+                                _ptr(tile_ranges), _ptr(num_pairs), _stream(stream)))
 
 
 def qg_render_fwd(proj, cams, tile, vals, tile_ranges, bg, image, T_final, last, stream=None):
