@@ -107,6 +107,11 @@ def parse():
                    help="views per batched optimiser step in the sec/frame sections (16: all 20 views in two groups)")
     p.add_argument("--batched-lr-scale", type=float, default=1.0,
                    help="learning-rate factor of the batched steps in the sec/frame sections")
+    p.add_argument("--no-configs", action="store_true", help="skip the small and dense-overlap workload steps")
+    p.add_argument("--no-densify", action="store_true", help="skip the per-frame densification measurement")
+    p.add_argument("--config-steps", type=int, default=20, help="timed steps of the small and dense workloads")
+    p.add_argument("--oracle-small-reps", type=int, default=10)
+    p.add_argument("--oracle-small-only", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run a plain copy of this many MiB first (counter calibration)")
     return p.parse_args()
@@ -151,12 +156,64 @@ def cpu_baseline(scene_planes, cam, n_pix, seed=7):
     total = run(n_pix)
     per_px = max(total - fixed, 0.0) / (n_pix - 16)
     step_s = fixed + per_px * W * H
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = cpu_threads()
     return {"value": round(step_s * 1e3, 1), "unit": "ms/step", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, one {W}x{H} view of {scene_planes.shape[1]} Gaussians: projection + autograd "
                       f"backward ({fixed:.2f} s) and compositing forward + adjoint at {n_pix} sampled pixels, each "
                       f"scanning every Gaussian ({total:.2f} s in all); per-pixel cost extrapolated to {W * H} "
                       f"pixels"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_small_config(reps):
+    """The FP64 oracle on the whole small workload (10 k Gaussians, one 256x256 view): projection, per-pixel
+    compositing over every Gaussian, its adjoint and the projection's autograd backward; median of reps runs."""
+    import torch
+    from oracle import render as OR
+    from paper_2412_04469_amd import synth
+    wl = synth.workload_small()
+    cam = wl.cams[0]
+    planes0 = wl.scene.planes().astype(np.float64)
+    g = np.sign(np.random.default_rng(3).normal(size=(3, cam.height, cam.width))) / (3.0 * cam.width * cam.height)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        planes = torch.tensor(planes0, requires_grad=True)
+        OR.render(planes, cam, (0.0, 0.0, 0.0), grad_image=g)
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)) * 1e3
+
+
+def cpu_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline_extras(reps):
+    """The small workload's oracle step at the default thread count (median of reps) and at one thread (one run,
+    in a child process started with OMP_NUM_THREADS=1; it touches no GPU)."""
+    import subprocess
+    out = {"cpu_model": cpu_model(), "small_config": {"workload": "gauss10k_256x256_1view",
+                                                       "ms_median": round(oracle_small_config(reps), 1),
+                                                       "runs": reps, "threads": cpu_threads()}}
+    env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-small-only"], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        out["small_config_one_thread_ms"] = json.loads(r.stdout.strip().splitlines()[-1])["ms"]
+    else:
+        out["small_config_one_thread_ms"] = None
+        log(f"one-thread oracle run failed: {r.stderr[-300:]}")
+    return out
 
 
 def log(msg):
@@ -234,6 +291,100 @@ def batched_section(args):
             "form": "one captured graph per step; loss = mean of per-view mean L1"}
 
 
+def attribute_step_section(wl, steps, warmup, tile=(16, 16)):
+    """A plain rasterizer optimiser step (AttributeFitter: project -> bin -> blend -> L1 -> adjoint -> Adam over
+    all views of the workload in one multi-view launch per call), replayed from a captured graph: ms per step,
+    and the per-kernel breakdown from event-bracketed eager steps."""
+    import torch
+    from paper_2412_04469_amd import qg
+    from paper_2412_04469_amd.fit import AttributeFitter, FitConfig, render_views
+    cfg = FitConfig(tile=tile)
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    gts = render_views(torch.as_tensor(wl.target_scene.planes()).to(dev), wl.cams, cfg)
+    f = AttributeFitter(prev, wl.cams, gts, cfg)
+    pairs = f.size_capacity()
+    qg.qg_timing_enable(True)
+    for _ in range(warmup):
+        f._enqueue()
+    torch.cuda.synchronize()
+    rep = qg.qg_timing_report()
+    qg.qg_timing_enable(False)
+    per = {k: ms / max(warmup, 1) for k, (c, ms) in rep.items()}
+    f.step()  # captures the graph
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        f.step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ovf = f.overflowed()
+    loss = f.loss()
+    items = wl.scene.n * len(wl.cams)
+    tiles = f.rast.total_tiles
+    tpasses = max(1, math.ceil(math.ceil(math.log2(max(tiles, 2))) / 8))
+    sort_ms = per.get("sort_tile", 0.0) + per.get("sort_depth", 0.0)
+    # algorithmic bytes of the radix passes: 16 B per pair per tile pass, 16 B per (view, Gaussian) per depth pass
+    sort_bytes = 16.0 * pairs * tpasses + 16.0 * items * 4
+    out = {"workload": wl.name, "n_gaussians": wl.scene.n, "views": len(wl.cams),
+           "pixels": sum(c.width * c.height for c in wl.cams), "tile": "%dx%d" % tile, "ms_per_step": round(ms, 4),
+           "steps": steps, "pairs": pairs, "overflow": ovf, "l1_after": round(loss, 6),
+           "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per.items(), key=lambda kv: -kv[1])},
+           "radix_passes": {"ms_per_step": round(sort_ms, 4), "algorithmic_bytes": sort_bytes,
+                            "achieved_gbs": round(sort_bytes / (sort_ms * 1e-3) / 1e9, 1) if sort_ms > 0 else None,
+                            "hbm_peak_gbs": PEAK_HBM_GBS},
+           "form": "one captured graph per step (fwd + bwd + Adam over all 59 attribute planes, all views)"}
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
+def configs_section(args):
+    """The small workload (10 k Gaussians, one 256x256 view) and the dense-overlap workload (1 M Gaussians, four
+    1920x1080 views, log-scales N(-3, 0.5)) as plain rasterizer steps."""
+    from paper_2412_04469_amd import synth
+    out = {}
+    out["small"] = attribute_step_section(synth.workload_small(), max(args.config_steps, 100), 10)
+    log(f"configs: small {out['small']['ms_per_step']:.4f} ms/step")
+    out["dense"] = attribute_step_section(synth.workload_dense(), args.config_steps, 3)
+    log(f"configs: dense {out['dense']['ms_per_step']:.4f} ms/step")
+    return out
+
+
+def render_fps(state, rast, cams, reps=3):
+    """Render speed of a fitted frame: decode of the frame's residuals plus projection, binning and blend of one
+    view, each frame bracketed by events; median over reps rounds of every camera."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for c in cams:  # the pair capacity settles first (host sync outside the measurement)
+        state.decode()
+        rast.set_cameras([c])
+        rast.forward(state.attrs)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        for c in cams:
+            rast.set_cameras([c])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            state.decode()
+            rast.project(state.attrs)
+            rast.bin()
+            rast.render()
+            e1.record(stream)
+            times.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in times])
+    assert not rast.overflowed()
+    med = float(np.median(ms))
+    return {"fps_median": round(1e3 / med, 1), "ms_median": round(med, 4), "ms_p90": round(float(np.percentile(ms, 90)), 4),
+            "frames": len(ms), "protocol": "decode of the frame's residuals + projection, binning and blend of one "
+                                           "1352x1014 view, median over 3 rounds of the 21 cameras"}
+
+
 def _fit_to_target(fitter, step_fn, iters, check_every, eval_cam, gt_eval, gate_fn, target=None):
     """Frame clock: gate initialisation then optimiser steps; PSNR on the held-out view every check_every steps
     with the clock paused.  Returns (trajectory [(iteration, seconds, psnr)], seconds to the first check at or
@@ -298,6 +449,8 @@ def frame_section(args):
     log(f"frame: plain reaches {tgt:.3f} dB at {hit_p:.3f} s")
     storage = frame_storage(plain)
     log(f"frame: storage {storage['mb_per_frame']:.4f} MB")
+    fps = render_fps(plain, plain.rast, list(wl.cams) + [held])
+    log(f"frame: render {fps['fps_median']} FPS")
     del plain
     torch.cuda.empty_cache()
     bcfg = dataclasses.replace(cfg, group_views=args.batched_views, batched_lr_scale=args.batched_lr_scale)
@@ -316,7 +469,7 @@ def frame_section(args):
     del bat
     torch.cuda.empty_cache()
     return {"workload": wl.name, "target_psnr_db": tgt, "iterations_plain": args.frame_iters,
-            "storage_plain": storage,
+            "storage_plain": storage, "render": fps,
             "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p},
             "batched": {"sec_per_frame": None if hit_b is None else round(hit_b, 4),
                         "views_per_step": vps, "lr_scale": args.batched_lr_scale,
@@ -324,6 +477,71 @@ def frame_section(args):
             "protocol": "frame clock from gate initialisation (20 forward + 20 adjoint passes) through the optimiser "
                         "steps; held-out PSNR every 25 steps with the clock paused"}
 
+
+
+def densify_section(args, target):
+    """Per-frame densification (the 3D-GS stage the paper runs inside every frame's fit, here at the paper's
+    N3DV schedule: after epochs 6, 8, ..., 20 of 25, gradient threshold 0.00125) on the fit workload, against
+    the same fit without it: seconds to the plain form's target PSNR, final PSNR, the Gaussian count after each
+    stage, and the seconds the stages themselves take (plan, expansion, new buffers and capacity: part of the
+    frame clock)."""
+    import torch
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.fit import (FitConfig, FrameFitter, GateInitializer, camera_extent, densify_fitter,
+                                          densify_iterations, render_views)
+    wl = synth.workload_fit(n=args.n)
+    cfg = FitConfig(densify=True)
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    target_scene = torch.as_tensor(wl.target_scene.planes()).to(dev)
+    gts_prev = render_views(prev, wl.cams, cfg)
+    gts = render_views(target_scene, wl.cams, cfg)
+    held = wl.extras["held_out"]
+    gt_held = render_views(target_scene, [held], cfg)[0]
+    V = len(wl.cams)
+    extent = camera_extent(wl.cams)
+    stages = set(densify_iterations(cfg, V, args.frame_iters // V))
+    gi = GateInitializer(wl.scene.n, wl.cams, cfg)
+    gi(prev, gts_prev, gts)
+    order = np.random.default_rng(0)
+    perm = np.concatenate([order.permutation(V) for _ in range(args.frame_iters // V + 2)])
+    f = FrameFitter(prev, wl.cams, gts, cfg)
+    f.size_capacity()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.reset_frame(a_init=gi(prev, gts_prev, gts))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    traj, hit, log_n, stage_s = [], None, [], 0.0
+    it = 0
+    while it < args.frame_iters:
+        t0 = time.perf_counter()
+        for _ in range(min(25, args.frame_iters - it)):
+            if it in stages:
+                ts = time.perf_counter()
+                f, counts = densify_fitter(f, extent, rnd=it)
+                torch.cuda.synchronize()
+                stage_s += time.perf_counter() - ts
+                log_n.append(dict(counts, iteration=it))
+            f.step(int(perm[it]))
+            it += 1
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        p = f.psnr(held, gt_held)
+        traj.append((it, round(elapsed, 4), round(p, 3)))
+        if hit is None and p >= target:
+            hit = elapsed
+    log(f"densify: {f.n} Gaussians at the end, {traj[-1][2]:.3f} dB, target {'reached at %.3f s' % hit if hit else 'not reached'}")
+    n_end = f.n
+    del f
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "target_psnr_db": target, "iterations": args.frame_iters,
+            "threshold": cfg.densify_threshold, "extent": round(extent, 4),
+            "max_scale": round(cfg.percent_dense * extent, 5), "stages": log_n, "n_end": n_end,
+            "stage_seconds": round(stage_s, 4), "sec_to_target": None if hit is None else round(hit, 4),
+            "sec_per_frame": traj[-1][1], "final_psnr_db": traj[-1][2], "trajectory": traj,
+            "protocol": "frame clock from gate initialisation through the optimiser steps and densification stages; "
+                        "held-out PSNR every 25 steps with the clock paused"}
 
 
 def dssim_section(args):
@@ -499,8 +717,26 @@ def proposal_section(args):
     return out
 
 
+# The paper's own per-frame figures (one NVIDIA A100; whole QUEEN pipeline at ~3.1 M Gaussians with D-SSIM,
+# densification and framework overhead; its datasets are not available here, so these are context, not targets).
+PAPER_CONTEXT = {
+    "hardware": "1x NVIDIA A100 (paper)",
+    "train_sec_per_frame": {"N3DV QUEEN-s": 4.65, "N3DV QUEEN-m": 5.96, "N3DV QUEEN-l": 7.9,
+                            "Immersive QUEEN-l": 19.7},
+    "render_fps": {"N3DV QUEEN-s": 345, "N3DV QUEEN-m": 321, "N3DV QUEEN-l": 248, "Immersive QUEEN-l": 183},
+    "plain_residual_baseline": {"N3DV": {"sec_per_frame": 7.29, "fps": 214},
+                                "Immersive": {"sec_per_frame": 20.85, "fps": 276}},
+    "sources": "Tab. 1 (N3DV), Tab. 1 (Immersive), Tab. 2 first row",
+    "differences": "~3.1 M Gaussians (10x this workload), SH degree 2 on N3DV, D-SSIM in the loss, densification, "
+                   "6-15 epochs per frame; real footage instead of synthetic scenes",
+}
+
+
 def main():
     args = parse()
+    if args.oracle_small_only:  # child process of cpu_baseline_extras: CPU only
+        print(json.dumps({"ms": round(oracle_small_config(1), 1)}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is implemented for one GPU, "
               f"and its sharding by view across GPUs is described, not implemented.", file=sys.stderr)
@@ -575,6 +811,15 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for(dominant), "kernel": dominant,
                 "units_per_launch": args.n, "work_per_unit": f"{BYTES_PER_GAUSS.get(dominant)} B per Gaussian"}
     roof["avg_launch_ms"] = round(dom_avg_ms, 4)
+    # the blend forward against the same FP32 peak (its launch time from the event-bracketed warm-up steps)
+    fwd_ms = per_step.get("render_fwd", 0.0) / max(counts.get("render_fwd", 1.0), 1e-9)
+    blend_fwd = None
+    if fwd_ms > 0:
+        tf = FLOP_PER_EVAL["render_fwd"] * mean_evals / (fwd_ms * 1e-3) / 1e12
+        blend_fwd = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / PEAK_FP32_TFLOPS, 4), "avg_launch_ms": round(fwd_ms, 4),
+                     "units_per_launch": mean_evals, "work_per_unit": "23.0 flop per evaluated pair",
+                     "timing": "event-bracketed warm-up steps"}
 
     # per-step distribution: the same number of steps again, each bracketed by its own events (outside the
     # timed region above, so the headline is not perturbed by the extra event records)
@@ -596,6 +841,7 @@ def main():
                    "tile": args.tile, "sh_degree": 3, "decoder": "8->32->56 SiLU", "pairs_max": P_max,
                    "overflow": overflow},
         "roofline": roof,
+        "roofline_blend_fwd": blend_fwd,
         "step_ms_distribution": dist,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "launches_per_step": {k: counts[k] for k in sorted(counts)},
@@ -603,10 +849,15 @@ def main():
     del fitter
     torch.cuda.empty_cache()
     log(f"headline: {ms_step:.4f} ms/step")
+    result["paper_context"] = PAPER_CONTEXT
+    if not args.no_configs:
+        result["configs"] = configs_section(args)
     if not args.no_batched:
         result["batched"] = batched_section(args)
     if not args.no_frame:
         result["sec_per_frame"] = frame_section(args)
+    if not args.no_densify and "sec_per_frame" in result:
+        result["densify"] = densify_section(args, result["sec_per_frame"]["target_psnr_db"])
     if not args.no_masked:
         result["masked_training"] = masked_section(args)
     if not args.no_dssim:
@@ -615,6 +866,7 @@ def main():
         result["learned_proposal"] = proposal_section(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl.scene.planes(), wl.cams[0], args.cpu_pixels)
+        result["cpu_baseline"].update(cpu_baseline_extras(args.oracle_small_reps))
     print(json.dumps(result), flush=True)
 
 

@@ -14,7 +14,8 @@
  *     returns a thread-local message for the last non-OK status.  Nothing throws across the ABI.
  *   - Gradient outputs are accumulated (+=): the caller zeroes them once per step.
  *   - Float data are IEEE float32.  Results of the forward calls are bit-reproducible run to run;
- *     backward calls accumulate with float32 atomics (run-to-run differences ~1e-6 relative).
+ *     backward calls accumulate with float32 atomics (run-to-run differences ~1e-6 relative) unless
+ *     deterministic mode is on (qg_set_deterministic below).
  *
  * Attribute layout (the Gaussian attribute set A = {p, q, s, o, h} of Sec. 3.1): 59 float32
  * planes of length n with plane stride ld >= n ("[59][ld]"):
@@ -52,6 +53,24 @@ typedef void* qg_stream; /* hipStream_t */
 const char* qg_last_error(void);
 /* ABI version (incremented on incompatible change). */
 int32_t qg_version(void);
+
+/*
+ * Deterministic mode of the adjoints (qg_render_bwd, qg_render_decode_bwd).  Off by default; QG_DETERMINISTIC=1 in
+ * the environment turns it on when the library first reads the setting, and qg_set_deterministic(on) overrides
+ * that.  In this mode the blend adjoint writes the wave-reduced partial derivatives of each (tile, entry) pair to
+ * a per-pair buffer instead of adding them into the Gaussian's record with float atomics; a second kernel then
+ * adds each (view, Gaussian)'s pairs in a fixed order (the tiles of its rectangle, row-major), and the fused
+ * adjoint keeps one decoder weight-gradient row per 64 Gaussians, summed in a fixed order.  Gradients are then
+ * the same bits on every run (and differ from the default mode only in rounding order).
+ * Workspace: while the mode is on, both adjoint calls need qg_deterministic_workspace_size(n, capacity) bytes
+ * appended to their usual workspace, where capacity is the one passed to the qg_bin call whose tile lists are
+ * differentiated (one set of partials per pair slot).  The calls return QG_ERR_ARG if the workspace has no room
+ * for them; pair slots at or beyond the room they find are dropped, so size it with the bin capacity.
+ * The setting is process-wide; change it only while no adjoint call is being enqueued.
+ */
+qg_status qg_set_deterministic(int32_t on);
+int32_t qg_get_deterministic(void);
+size_t qg_deterministic_workspace_size(int64_t n, int64_t capacity);
 
 /*
  * Pinhole camera (Sec. 3.1: intrinsics K and viewing transform W), OpenCV axes (x right, y down,
@@ -115,7 +134,10 @@ typedef struct {
  *   the decoder is a shared bias-free MLP (L -> Hd -> M) with SiLU; M = 56 maps onto planes 3..58
  *   (rotation 4, log-scale 3, opacity logit 1, SH 48).  Built shape: L = 8, Hd = 32, M = 56; other
  *   shapes return QG_ERR_UNSUPPORTED.
- *   g = min(1, max(0, sigmoid(a / tau) (gamma1 - gamma0) + gamma0))      (Eq. 6-7)
+ *   g = min(1, max(0, sigmoid((a + e) / tau) (gamma1 - gamma0) + gamma0))      (Eq. 6-7)
+ *   with e = gate_noise[i] if gate_noise is given (the stochastic hard concrete gate Eq. 6 cites: e is a
+ *   logistic sample log u - log(1 - u), e.g. from qg_gate_noise), else e = 0 (the gate as Eq. 6 is written).
+ *   The backward and the fused calls take the same gate_noise; Eq. 8's regulariser does not depend on it.
  *   lreg_partial receives one float per 256-Gaussian block: the block's sum of
  *   sigmoid(a - tau ln(-gamma0/gamma1)) (Eq. 8); the caller reduces (qg_decode_lreg_blocks()).
  * Sizes: n >= 0, ld >= n; latents [L][ld]; W1 [Hd][L], W2 [M][Hd]; pos_pre (l_p) [3][ld]; gate_logit (a) [n];
@@ -124,10 +146,28 @@ typedef struct {
  */
 qg_status qg_decode_residuals(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L,
                               const float* W1, const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
-                              const float* gate_logit, float gamma0, float gamma1, float tau, float* attrs_out,
+                              const float* gate_logit, const float* gate_noise, float gamma0, float gamma1,
+                              float tau, float* attrs_out,
                               float* gate_out, float* lreg_partial, qg_stream stream);
 
 int64_t qg_decode_lreg_blocks(int64_t n);
+
+/*
+ * Eq. 8's regulariser as the mean over the n Gaussians (the reading under which lambda_reg = 0.01 is comparable
+ * with an image loss): out[0] = (sum of the nblocks block sums lreg_partial) / n, summed in a fixed order on the
+ * device (0 for n = 0).  nblocks = qg_decode_lreg_blocks(n) after qg_decode_residuals, or
+ * qg_decode_project_lreg_blocks(n) after qg_decode_project.  out: device float [1].
+ */
+qg_status qg_decode_lreg_mean(int64_t n, const float* lreg_partial, int64_t nblocks, float* out, qg_stream stream);
+
+/*
+ * Adjoint of qg_decode_lreg_mean with respect to the gate logits a (Eq. 8):
+ *   grad_gate_logit[i] (+=) weight[0] * s_i (1 - s_i) / n,  s_i = sigmoid(a_i - tau ln(-gamma0 / gamma1)),
+ * with weight a DEVICE float [1] (dLoss/dL_reg, e.g. lambda_reg as produced by autograd), so the caller does not
+ * read it back to the host.  Same gate hyper-parameter rules as qg_decode_residuals.
+ */
+qg_status qg_decode_lreg_bwd(int64_t n, const float* gate_logit, float gamma0, float gamma1, float tau,
+                             const float* weight, float* grad_gate_logit, qg_stream stream);
 
 /*
  * Backward of qg_decode_residuals for loss = f(attrs_out) + lambda_reg * mean_i sigmoid(a_i - tau ln(-g0/g1)):
@@ -142,7 +182,8 @@ int64_t qg_decode_lreg_blocks(int64_t n);
 size_t qg_decode_bwd_workspace_size(int64_t n, int32_t L, int32_t Hd, int32_t M);
 qg_status qg_decode_residuals_bwd(int64_t n, int64_t ld, const float* latents, int32_t L, const float* W1,
                                   const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
-                                  const float* gate_logit, float gamma0, float gamma1, float tau,
+                                  const float* gate_logit, const float* gate_noise, float gamma0, float gamma1,
+                                  float tau,
                                   const float* grad_attrs, float lambda_reg, float* grad_latents, float* grad_W1,
                                   float* grad_W2, float* grad_pos_pre, float* grad_gate_logit, void* ws,
                                   size_t ws_bytes, qg_stream stream);
@@ -267,7 +308,8 @@ qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, int32_t sh_de
 int64_t qg_decode_project_lreg_blocks(int64_t n);
 qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, int32_t L,
                             const float* W1, const float* W2, int32_t Hd, int32_t M, const float* pos_pre,
-                            const float* gate_logit, float gamma0, float gamma1, float tau, int32_t sh_degree,
+                            const float* gate_logit, const float* gate_noise, float gamma0, float gamma1, float tau,
+                            int32_t sh_degree,
                             const qg_camera* cams, int32_t V, qg_tiling tiling, float dilation,
                             const qg_projected* out, float* attrs_out, float* gate_out, float* lreg_partial,
                             qg_stream stream);
@@ -288,7 +330,8 @@ size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V);
 qg_status qg_render_decode_bwd(int64_t n, int64_t ld, const float* prev_attrs, const float* attrs,
                                const float* latents, int32_t L, const float* W1, const float* W2, int32_t Hd,
                                int32_t M, const float* pos_pre,
-                               const float* gate_logit, float gamma0, float gamma1, float tau, float lambda_reg,
+                               const float* gate_logit, const float* gate_noise, float gamma0, float gamma1,
+                               float tau, float lambda_reg,
                                int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling,
                                float dilation, const qg_projected* proj, const uint32_t* vals,
                                const uint32_t* tile_ranges, const float* bg, const float* const* T_final,
@@ -374,6 +417,63 @@ qg_status qg_mask_tile_ranges(int64_t total_tiles, uint32_t* tile_ranges, const 
  */
 qg_status qg_l1_loss_masked(int64_t count, int64_t plane, const float* image, const float* gt, const uint8_t* mask,
                             float scale, float* grad_image, double* partials, qg_stream stream);
+
+/* ---------------------------------------------------------------------------------------------- */
+/* The stochastic hard concrete gate (Eq. 6 cites it) and per-frame densification (the 3D-GS stage the */
+/* paper runs at every time step: Sec. 3.4; implementation details: epochs 6 to 80%, every 2 epochs, */
+/* gradient threshold 0.00125).                                                                     */
+/* ---------------------------------------------------------------------------------------------- */
+/*
+ * Random draws come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) with key (seed low word, seed high
+ * word); a uniform is u = ((w >> 9) + 1/2) / 2^23 of a 32-bit output word w, in (0, 1).
+ *
+ * qg_gate_noise: noise[i] = log u_i - log(1 - u_i), u_i from word 0 of Philox(counter (i, s, 0x67617465, 0)),
+ * with s = step_state[0] if step_state (device int32, e.g. qg_adam_multi's step counter, so a replayed graph draws
+ * afresh) is given, else s = step.  Pass the result as gate_noise to the decode calls of that step.
+ */
+qg_status qg_gate_noise(int64_t n, uint64_t seed, int32_t step, const int32_t* step_state, float* noise,
+                        qg_stream stream);
+
+/*
+ * One iteration's densification statistic for one view: for every Gaussian with ntiles[i] > 0 (visible in the
+ * view), accum[i] += |(sx grad_xy[0][i], sy grad_xy[1][i])| and count[i] += 1.  grad_xy [2][n] is dL/dp' of the
+ * view in pixels (qg_render_bwd / qg_render_decode_bwd's grad_xy); sx = W/2, sy = H/2 turn it into normalised
+ * device coordinates, the units of 3D-GS's gradient threshold.
+ */
+qg_status qg_densify_accumulate(int64_t n, const float* grad_xy, const int32_t* ntiles, float sx, float sy,
+                                float* accum, float* count, qg_stream stream);
+
+/*
+ * The densification plan from the statistic and the current (decoded) attributes attrs [59][ld], decided in
+ * double precision: action[i] = 3 (prune) if sigmoid(logit) < min_opacity; else, with score accum/count (0 if
+ * count = 0), 0 (keep) if score < threshold, 1 (clone) if exp(max log-scale) <= max_scale, 2 (split) otherwise.
+ * offsets [n + 1] (device int64): the exclusive scan of the child counts (0 prune, 1 keep, 2 clone or split),
+ * offsets[n] = the new count n'.  The new set keeps each Gaussian's children in place, in parent order.
+ * ws: qg_densify_plan_workspace_size(n) bytes.
+ */
+size_t qg_densify_plan_workspace_size(int64_t n);
+qg_status qg_densify_plan(int64_t n, const float* accum, const float* count, const float* attrs, int64_t ld,
+                          double threshold, double max_scale, double min_opacity, uint8_t* action, int64_t* offsets,
+                          void* ws, size_t ws_bytes, qg_stream stream);
+
+/*
+ * Expands nplanes planes src [nplanes][ld_src] of n Gaussians into dst [nplanes][ld_dst] (ld_dst >= n') through the
+ * plan: every child gets its parent's value (mode 0), or, for optimiser moments (mode 1), only the first child of a
+ * kept or cloned Gaussian keeps it and new Gaussians start at 0.  dst may not alias src.
+ */
+qg_status qg_densify_expand(int64_t n, const uint8_t* action, const int64_t* offsets, int32_t nplanes,
+                            const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int32_t mode,
+                            qg_stream stream);
+
+/*
+ * Split children, after the expansion of the stored attributes into prev_out [59][ld_out]: child c (0, 1) of a
+ * split Gaussian i gets mean += R(q_i) (s_i * z_c) and log-scale -= ln 1.6, with q_i, s_i the parent's decoded
+ * rotation (normalised) and scale (decoded [59][ld]) and z_0, z_1 standard normal 3-vectors by Box-Muller
+ * (r = sqrt(-2 ln u_even), angle 2 pi u_odd) on the words of Philox(counter (i, round, 0x73706C74, 0)) and
+ * Philox(counter (i, round, 0x73706C74, 1)).
+ */
+qg_status qg_densify_split(int64_t n, const uint8_t* action, const int64_t* offsets, const float* decoded, int64_t ld,
+                           uint64_t seed, int32_t round, float* prev_out, int64_t ld_out, qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
 /* Storage of a frame's residuals (the compression back end after the fit): the quantised latents   */

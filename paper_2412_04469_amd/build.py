@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libqg.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "project.hip", "bin.hip", "render.hip", "decode.hip", "fused.hip", "gate_init.hip", "loss_adam.hip",
-           "proposal.hip", "ssim.hip", "entropy.hip"]
+           "proposal.hip", "ssim.hip", "entropy.hip", "densify.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

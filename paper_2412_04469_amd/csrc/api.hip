@@ -1,5 +1,7 @@
 // Error state, argument tables and small utilities of libqg.
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -66,6 +68,20 @@ void timing_end(hipStream_t s) {
     hipEventRecord(stop, s);
     g_launches.push_back({t_name, t_start, stop});
     t_start = nullptr;
+}
+
+// ---- deterministic mode ---------------------------------------------------------------------------------
+namespace {
+std::once_flag g_det_once;
+std::atomic<int> g_det{0};
+}  // namespace
+
+bool deterministic_mode() {
+    std::call_once(g_det_once, [] {
+        const char* e = std::getenv("QG_DETERMINISTIC");
+        if (e && std::strcmp(e, "1") == 0) g_det.store(1);
+    });
+    return g_det.load() != 0;
 }
 
 bool tiling_ok(qg_tiling t) {
@@ -158,7 +174,16 @@ using namespace qg;
 
 extern "C" const char* qg_last_error(void) { return g_err; }
 
-extern "C" int32_t qg_version(void) { return 1; }
+extern "C" int32_t qg_version(void) { return 2; }
+
+extern "C" qg_status qg_set_deterministic(int32_t on) {
+    clear_error();
+    deterministic_mode();  // the environment's setting is read first, so this call overrides it
+    g_det.store(on ? 1 : 0);
+    return QG_OK;
+}
+
+extern "C" int32_t qg_get_deterministic(void) { return deterministic_mode() ? 1 : 0; }
 
 extern "C" qg_status qg_timing_enable(int32_t on, const char* only) {
     std::lock_guard<std::mutex> lk(g_tmu);

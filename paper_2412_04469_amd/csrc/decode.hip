@@ -31,9 +31,10 @@ int64_t bwd_blocks(int64_t n) {
 __global__ __launch_bounds__(256) void k_decode_fwd(int64_t n, int64_t ld, const float* __restrict__ prev,
                                                     const float* __restrict__ lat, const float* __restrict__ W1,
                                                     const float* __restrict__ W2, const float* __restrict__ lp,
-                                                    const float* __restrict__ ga, float g0, float g1, float tau,
-                                                    float reg_shift, float* __restrict__ out,
-                                                    float* __restrict__ gate_out, float* __restrict__ lreg_part) {
+                                                    const float* __restrict__ ga, const float* __restrict__ gnoise,
+                                                    float g0, float g1, float tau, float reg_shift,
+                                                    float* __restrict__ out, float* __restrict__ gate_out,
+                                                    float* __restrict__ lreg_part) {
     __shared__ float s_res[4][kChunk][kM + 1];
     __shared__ float s_red[4];
     const int lane = __lane_id(), w = threadIdx.x / 64, c = lane % 16;
@@ -59,7 +60,8 @@ __global__ __launch_bounds__(256) void k_decode_fwd(int64_t n, int64_t ld, const
 #pragma unroll 8
             for (int m = 0; m < kM; ++m) out[(int64_t)(3 + m) * ld + g] = prev[(int64_t)(3 + m) * ld + g] + s_res[w][lane][m];
             const float a = ga[g];
-            const float gg = gate_of(a, g0, g1, tau, nullptr, nullptr);
+            // the stochastic gate adds its logistic sample to log(alpha) inside the sigmoid (Eq. 6)
+            const float gg = gate_of(gnoise ? a + gnoise[g] : a, g0, g1, tau, nullptr, nullptr);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 out[(int64_t)k * ld + g] = __builtin_fmaf(gg, lp[(int64_t)k * ld + g], prev[(int64_t)k * ld + g]);
@@ -81,7 +83,8 @@ __global__ __launch_bounds__(256) void k_decode_fwd(int64_t n, int64_t ld, const
 __global__ __launch_bounds__(256) void k_decode_bwd(int64_t n, int64_t ld, const float* __restrict__ lat,
                                                     const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ lp, const float* __restrict__ ga,
-                                                    float g0, float g1, float tau, float reg_shift, float reg_scale,
+                                                    const float* __restrict__ gnoise, float g0, float g1, float tau,
+                                                    float reg_shift, float reg_scale,
                                                     const float* __restrict__ GA, float* __restrict__ g_lat,
                                                     float* __restrict__ g_lp, float* __restrict__ g_ga,
                                                     float* __restrict__ wpart) {
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(int64_t n, int64_t ld, const
         if (gv) {
             const float a = ga[g];
             float gh, gt;
-            const float gg = gate_of(a, g0, g1, tau, &gh, &gt);
+            const float gg = gate_of(gnoise ? a + gnoise[g] : a, g0, g1, tau, &gh, &gt);
             float dot = 0.f;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -172,6 +175,31 @@ __global__ __launch_bounds__(1024) void k_reduce_parts(const float* __restrict__
     }
 }
 
+// Eq. 8 as a mean: out[0] = (sum of the nb block sums) / n, in a fixed order (strided per-thread sums in double,
+// then a tree over the 256 threads).
+__global__ __launch_bounds__(256) void k_lreg_mean(const float* __restrict__ part, int64_t nb, int64_t n,
+                                                   float* __restrict__ out) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) acc += (double)part[b];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = n > 0 ? (float)(s[0] / (double)n) : 0.f;
+}
+
+// Adjoint of the mean with respect to the gate logits, the weight dLoss/dL_reg read from the device.
+__global__ void k_lreg_bwd(int64_t n, const float* __restrict__ a, float reg_shift, const float* __restrict__ weight,
+                           float inv_n, float* __restrict__ ga) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float pr = sigm(a[i] - reg_shift);
+    ga[i] += (weight[0] * inv_n) * (pr * (1.f - pr));
+}
+
 }  // namespace
 
 qg_status decode_reduce_launch(const float* part, int64_t nblocks, float* gW1, float* gW2, hipStream_t s) {
@@ -207,9 +235,9 @@ extern "C" int64_t qg_decode_lreg_blocks(int64_t n) { return fwd_blocks(n); }
 
 extern "C" qg_status qg_decode_residuals(int64_t n, int64_t ld, const float* prev_attrs, const float* latents,
                                          int32_t L, const float* W1, const float* W2, int32_t Hd, int32_t M,
-                                         const float* pos_pre, const float* gate_logit, float gamma0, float gamma1,
-                                         float tau, float* attrs_out, float* gate_out, float* lreg_partial,
-                                         qg_stream stream) {
+                                         const float* pos_pre, const float* gate_logit, const float* gate_noise,
+                                         float gamma0, float gamma1, float tau, float* attrs_out, float* gate_out,
+                                         float* lreg_partial, qg_stream stream) {
     clear_error();
     QG_REQUIRE(n >= 0 && ld >= n, "n=%lld ld=%lld: need 0 <= n <= ld", (long long)n, (long long)ld);
     qg_status st = check_decoder(L, Hd, M);
@@ -228,8 +256,8 @@ extern "C" qg_status qg_decode_residuals(int64_t n, int64_t ld, const float* pre
     const float shift = tau * logf(-gamma0 / gamma1);
     {
         QG_TIMED("decode_fwd", s);
-        k_decode_fwd<<<(unsigned)nb, 256, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
-                                                  gamma1, tau, shift, attrs_out, gate_out, lreg_partial);
+        k_decode_fwd<<<(unsigned)nb, 256, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gate_noise,
+                                                  gamma0, gamma1, tau, shift, attrs_out, gate_out, lreg_partial);
     }
     QG_LAUNCH_CHECK("qg_decode_residuals");
     return QG_OK;
@@ -245,8 +273,9 @@ extern "C" size_t qg_decode_bwd_workspace_size(int64_t n, int32_t L, int32_t Hd,
 
 extern "C" qg_status qg_decode_residuals_bwd(int64_t n, int64_t ld, const float* latents, int32_t L,
                                              const float* W1, const float* W2, int32_t Hd, int32_t M,
-                                             const float* pos_pre, const float* gate_logit, float gamma0,
-                                             float gamma1, float tau, const float* grad_attrs, float lambda_reg,
+                                             const float* pos_pre, const float* gate_logit, const float* gate_noise,
+                                             float gamma0, float gamma1, float tau, const float* grad_attrs,
+                                             float lambda_reg,
                                              float* grad_latents, float* grad_W1, float* grad_W2,
                                              float* grad_pos_pre, float* grad_gate_logit, void* ws, size_t ws_bytes,
                                              qg_stream stream) {
@@ -268,10 +297,43 @@ extern "C" qg_status qg_decode_residuals_bwd(int64_t n, int64_t ld, const float*
     const float reg_scale = lambda_reg / (float)n;
     {
         QG_TIMED("decode_bwd", s);
-        k_decode_bwd<<<(unsigned)nb, 256, 0, s>>>(n, ld, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau,
-                                                  shift, reg_scale, grad_attrs, grad_latents, grad_pos_pre,
+        k_decode_bwd<<<(unsigned)nb, 256, 0, s>>>(n, ld, latents, W1, W2, pos_pre, gate_logit, gate_noise, gamma0,
+                                                  gamma1, tau, shift, reg_scale, grad_attrs, grad_latents, grad_pos_pre,
                                                   grad_gate_logit, (float*)ws);
     }
     QG_LAUNCH_CHECK("qg_decode_residuals_bwd");
     return decode_reduce_launch((const float*)ws, nb, grad_W1, grad_W2, s);
+}
+
+extern "C" qg_status qg_decode_lreg_mean(int64_t n, const float* lreg_partial, int64_t nblocks, float* out,
+                                         qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0 && nblocks >= 0, "n=%lld nblocks=%lld must be >= 0", (long long)n, (long long)nblocks);
+    QG_REQUIRE(out && (nblocks == 0 || lreg_partial), "a required pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        QG_TIMED("decode_lreg_mean", s);
+        k_lreg_mean<<<1, 256, 0, s>>>(lreg_partial, nblocks, n, out);
+    }
+    QG_LAUNCH_CHECK("qg_decode_lreg_mean");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_decode_lreg_bwd(int64_t n, const float* gate_logit, float gamma0, float gamma1, float tau,
+                                        const float* weight, float* grad_gate_logit, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0, "n=%lld < 0", (long long)n);
+    qg_status st = check_gate(gamma0, gamma1, tau);
+    if (st != QG_OK) return st;
+    QG_REQUIRE(n == 0 || (gate_logit && weight && grad_gate_logit), "a required pointer is NULL");
+    if (n == 0) return QG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const float shift = tau * logf(-gamma0 / gamma1);
+    {
+        QG_TIMED("decode_lreg_bwd", s);
+        k_lreg_bwd<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, gate_logit, shift, weight, 1.f / (float)n,
+                                                               grad_gate_logit);
+    }
+    QG_LAUNCH_CHECK("qg_decode_lreg_bwd");
+    return QG_OK;
 }

@@ -243,6 +243,26 @@ __device__ __forceinline__ void add_acc(const BwdAcc& acc, float* sw) {
     }
 }
 
+// Writes this wave's accumulators to its own row dst[2048] (every element exactly once, by one lane).
+__device__ __forceinline__ void store_acc(const BwdAcc& acc, float* __restrict__ dst) {
+    const int lane = __lane_id(), q = lane / 16, c = lane % 16;
+#pragma unroll
+    for (int mb = 0; mb < kMB; ++mb)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 16 * mb + 4 * q + i;
+                if (m < kM) dst[kH * kL + m * kH + 16 * jb + c] = acc.W2[mb][jb][i];
+            }
+    if (q < 2) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dst[(16 * jb + c) * kL + 4 * q + i] = acc.W1[jb][i];
+    }
+}
+
 // As add_acc, for a buffer shared by the waves of a block (LDS float atomics; no ordering needed).
 __device__ __forceinline__ void add_acc_atomic(const BwdAcc& acc, float* sw) {
     const int lane = __lane_id(), q = lane / 16, c = lane % 16;

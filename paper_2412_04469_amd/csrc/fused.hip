@@ -18,7 +18,8 @@ namespace qg {
 
 qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t* vals, const uint32_t* ranges,
                            const float* bg, const float* const* T_final, const uint32_t* const* last,
-                           const float* const* grad_image, float* grad2d, int64_t stride, hipStream_t s);
+                           const float* const* grad_image, float* grad2d, int64_t stride, int64_t n, PairPart pp,
+                           hipStream_t s);
 qg_status decode_reduce_launch(const float* part, int64_t nblocks, float* gW1, float* gW2, hipStream_t s);
 
 namespace {
@@ -42,8 +43,10 @@ __device__ __forceinline__ void wave_sync_lds() {
 __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, const float* __restrict__ prev,
                                                         const float* __restrict__ lat, const float* __restrict__ W1,
                                                         const float* __restrict__ W2, const float* __restrict__ lp,
-                                                        const float* __restrict__ ga, float g0, float g1, float tau,
-                                                        float reg_shift, int sh_deg, ViewTable vt, float dilation,
+                                                        const float* __restrict__ ga,
+                                                        const float* __restrict__ gnoise, float g0, float g1,
+                                                        float tau, float reg_shift, int sh_deg, ViewTable vt,
+                                                        float dilation,
                                                         int tile_w, int tile_h, float* __restrict__ attrs_out,
                                                         float* __restrict__ gate_out, float* __restrict__ lreg_part) {
     __shared__ float s_res[2][kChunk][kM + 1];
@@ -66,6 +69,7 @@ __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, c
 #pragma unroll
         for (int k = 0; k < 3; ++k) lpv[k] = gv ? lp[pidx(k, ld32, g32)] : 0.f;
         const float a = gv ? ga[g] : 0.f;
+        const float an = (gv && gnoise) ? a + gnoise[g] : a;  // stochastic gate: log(alpha) + logistic sample
         {
             FwdOps ops;
             load_fwd_ops(W1, W2, ops);
@@ -80,7 +84,7 @@ __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, c
         }
         wave_sync_lds();
         if (gv) {
-            const float gg = gate_of(a, g0, g1, tau, nullptr, nullptr);
+            const float gg = gate_of(an, g0, g1, tau, nullptr, nullptr);
 #pragma unroll
             for (int k = 0; k < 3; ++k) at[k] = __builtin_fmaf(gg, lpv[k], at[k]);
 #pragma unroll
@@ -164,11 +168,14 @@ __device__ __forceinline__ void in_vgprs(BwdPre& p) {
 
 // kDecoded: `prev` holds the decoded attributes of this step (prev + residual, positions with the gate
 // applied), so the residuals are not decoded again.
-template <bool kDecoded>
+// kDet: each wave writes its weight-gradient accumulators to its own row of wpart (row = chunk) instead of adding
+// them into the block's LDS sums with float atomics, so the fixed-order reduce over the rows is deterministic.
+template <bool kDecoded, bool kDet>
 __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
     int64_t n, int64_t ld, const float* __restrict__ prev, const float* __restrict__ lat, const float* __restrict__ W1,
-    const float* __restrict__ W2, const float* __restrict__ lp, const float* __restrict__ ga, float g0, float g1,
-    float tau, float reg_shift, float reg_scale, int sh_deg, ViewTable vt, float dilation,
+    const float* __restrict__ W2, const float* __restrict__ lp, const float* __restrict__ ga,
+    const float* __restrict__ gnoise, float g0, float g1, float tau, float reg_shift, float reg_scale, int sh_deg,
+    ViewTable vt, float dilation,
     const float* __restrict__ grad2d, int64_t stride, float* __restrict__ gxy_abs, ViewPtrs gxyv,
     float* __restrict__ g_lat, float* __restrict__ g_lp, float* __restrict__ g_ga, float* __restrict__ wpart) {
     // per wave:
@@ -207,6 +214,7 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
             lpv[k] = gv ? lp[pidx(k, ld32, g32)] : 0.f;
         }
         const float a = gv ? ga[g] : 0.f;
+        const float an = (gv && gnoise) ? a + gnoise[g] : a;  // stochastic gate: log(alpha) + logistic sample
         // view 0's gradient record and the old |grad xy| sum, loaded with the chunk (one wait for HBM)
         BwdPre pre{};
         if (gv) pre = load_bwd_pre(vt, grad2d, stride, gxy_abs, g);
@@ -238,7 +246,7 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
         if (gv) {
             const int l2 = lane_here();
             float gh, gt;
-            const float gg = gate_of(a, g0, g1, tau, &gh, &gt);
+            const float gg = gate_of(an, g0, g1, tau, &gh, &gt);
             if (!kDecoded) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) pos[k] = __builtin_fmaf(gg, lpv[k], pos[k]);
@@ -298,7 +306,10 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
                 auto tb = [&](int r, int j) -> float& { return at[slot_at(j, 16 * sg + r)]; };
                 decode_group_bwd_b(ops, dlat, tb);
             }
-            add_acc_atomic(acc, s_acc);
+            if constexpr (kDet)
+                store_acc(acc, wpart + (size_t)ch * kWidth);
+            else
+                add_acc_atomic(acc, s_acc);
         }
         wave_sync_lds();
         if (gv) {
@@ -307,8 +318,10 @@ __global__ __launch_bounds__(256, 2) void k_project_decode_bwd(
             for (int k = 0; k < kL; ++k) g_lat[pidx(k, ld32, g32)] = glat[k] + sl[slot_lat(k, l4)];
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_acc[i];
+    if constexpr (!kDet) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kWidth; i += 256) wpart[(size_t)blockIdx.x * kWidth + i] = s_acc[i];
+    }
 }
 
 int64_t fused_fwd_blocks(int64_t n) { return std::max<int64_t>(1, ceil_div(ceil_div(n, kChunk), 2)); }
@@ -335,8 +348,9 @@ extern "C" int64_t qg_decode_project_lreg_blocks(int64_t n) { return fused_fwd_b
 
 extern "C" qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_attrs, const float* latents,
                                        int32_t L, const float* W1, const float* W2, int32_t Hd, int32_t M,
-                                       const float* pos_pre, const float* gate_logit, float gamma0, float gamma1,
-                                       float tau, int32_t sh_degree, const qg_camera* cams, int32_t V,
+                                       const float* pos_pre, const float* gate_logit, const float* gate_noise,
+                                       float gamma0, float gamma1, float tau, int32_t sh_degree,
+                                       const qg_camera* cams, int32_t V,
                                        qg_tiling tiling, float dilation, const qg_projected* out, float* attrs_out,
                                        float* gate_out, float* lreg_partial, qg_stream stream) {
     clear_error();
@@ -356,12 +370,23 @@ extern "C" qg_status qg_decode_project(int64_t n, int64_t ld, const float* prev_
     const float shift = tau * logf(-gamma0 / gamma1);
     {
         QG_TIMED("decode_project", s);
-        k_decode_project<<<(unsigned)nb, 128, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0,
-                                                      gamma1, tau, shift, sh_degree, vt, dilation, tiling.tile_w,
+        k_decode_project<<<(unsigned)nb, 128, 0, s>>>(n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit,
+                                                      gate_noise, gamma0, gamma1, tau, shift, sh_degree, vt, dilation, tiling.tile_w,
                                                       tiling.tile_h, attrs_out, gate_out, lreg_partial);
     }
     QG_LAUNCH_CHECK("qg_decode_project");
     return QG_OK;
+}
+
+namespace qg {
+size_t det_weight_part_bytes(int64_t n) {
+    return align_up((size_t)std::max<int64_t>(1, ceil_div(n, kChunk)) * kWidth * sizeof(float));
+}
+}  // namespace qg
+
+extern "C" size_t qg_deterministic_workspace_size(int64_t n, int64_t capacity) {
+    if (n < 0 || capacity < 0) return 0;
+    return det_weight_part_bytes(n) + align_up((size_t)std::max<int64_t>(capacity, 1) * kPairPart * sizeof(float));
 }
 
 extern "C" size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V) {
@@ -373,8 +398,9 @@ extern "C" size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V) {
 extern "C" qg_status qg_render_decode_bwd(
     int64_t n, int64_t ld, const float* prev_attrs, const float* attrs, const float* latents, int32_t L,
     const float* W1, const float* W2,
-    int32_t Hd, int32_t M, const float* pos_pre, const float* gate_logit, float gamma0, float gamma1, float tau,
-    float lambda_reg, int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling, float dilation,
+    int32_t Hd, int32_t M, const float* pos_pre, const float* gate_logit, const float* gate_noise, float gamma0,
+    float gamma1, float tau, float lambda_reg, int32_t sh_degree, const qg_camera* cams, int32_t V, qg_tiling tiling,
+    float dilation,
     const qg_projected* proj, const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
     const float* const* T_final, const uint32_t* const* last, const float* const* grad_image, float* grad_latents,
     float* grad_W1, float* grad_W2, float* grad_pos_pre, float* grad_gate_logit, float* grad_xy_abs,
@@ -401,9 +427,19 @@ extern "C" qg_status qg_render_decode_bwd(
     float* grad2d = (float*)ws;
     const int64_t stride = n * QG_GRAD2D_STRIDE;
     float* wpart = (float*)((char*)ws + align_up((size_t)V * (size_t)n * QG_GRAD2D_STRIDE * sizeof(float)));
+    const bool det = deterministic_mode();
+    PairPart pp{nullptr, 0};
+    float* wdet = nullptr;
+    if (det) {
+        const size_t wb = det_weight_part_bytes(n);
+        QG_REQUIRE(ws_bytes >= need + wb + align_up(kPairPart * 4), "deterministic mode: workspace %zu has no room "
+                   "for the partials (add qg_deterministic_workspace_size)", ws_bytes);
+        wdet = (float*)((char*)ws + need);
+        pp = pair_part_in((char*)ws + need + wb, ws_bytes - need - wb);
+    }
     st = qg_zero(grad2d, (int64_t)V * stride * 4, stream);
     if (st != QG_OK) return st;
-    st = blend_bwd_launch(vt, tiling, vals, tile_ranges, bg, T_final, last, grad_image, grad2d, stride, s);
+    st = blend_bwd_launch(vt, tiling, vals, tile_ranges, bg, T_final, last, grad_image, grad2d, stride, n, pp, s);
     if (st != QG_OK) return st;
     ViewPtrs gv = {};
     if (grad_xy)
@@ -413,16 +449,23 @@ extern "C" qg_status qg_render_decode_bwd(
     const float reg_scale = lambda_reg / (float)n;
     {
         QG_TIMED("project_decode_bwd", s);
-        if (attrs)
-            k_project_decode_bwd<true><<<(unsigned)nb, 256, 0, s>>>(
-                n, ld, attrs, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau, shift, reg_scale, sh_degree, vt,
-                dilation, grad2d, stride, grad_xy_abs, gv, grad_latents, grad_pos_pre, grad_gate_logit, wpart);
+        const float* src = attrs ? attrs : prev_attrs;
+        float* wp = det ? wdet : wpart;
+#define QG_PDB_ARGS                                                                                                 \
+    n, ld, src, latents, W1, W2, pos_pre, gate_logit, gate_noise, gamma0, gamma1, tau, shift, reg_scale, sh_degree,   \
+        vt, dilation,                                                                                                 \
+        grad2d, stride, grad_xy_abs, gv, grad_latents, grad_pos_pre, grad_gate_logit, wp
+        if (attrs && !det)
+            k_project_decode_bwd<true, false><<<(unsigned)nb, 256, 0, s>>>(QG_PDB_ARGS);
+        else if (attrs)
+            k_project_decode_bwd<true, true><<<(unsigned)nb, 256, 0, s>>>(QG_PDB_ARGS);
+        else if (!det)
+            k_project_decode_bwd<false, false><<<(unsigned)nb, 256, 0, s>>>(QG_PDB_ARGS);
         else
-            k_project_decode_bwd<false><<<(unsigned)nb, 256, 0, s>>>(
-                n, ld, prev_attrs, latents, W1, W2, pos_pre, gate_logit, gamma0, gamma1, tau, shift, reg_scale,
-                sh_degree, vt, dilation, grad2d, stride, grad_xy_abs, gv, grad_latents, grad_pos_pre, grad_gate_logit,
-                wpart);
+            k_project_decode_bwd<false, true><<<(unsigned)nb, 256, 0, s>>>(QG_PDB_ARGS);
+#undef QG_PDB_ARGS
     }
     QG_LAUNCH_CHECK("qg_render_decode_bwd");
-    return decode_reduce_launch(wpart, nb, grad_W1, grad_W2, s);
+    // deterministic mode: one row per 64-Gaussian chunk, reduced in a fixed order like the block rows
+    return decode_reduce_launch(det ? wdet : wpart, det ? ceil_div(n, kChunk) : nb, grad_W1, grad_W2, s);
 }

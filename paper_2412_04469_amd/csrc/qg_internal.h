@@ -70,6 +70,25 @@ bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V,
                      bool need_proj, ViewTable* out);
 bool tiling_ok(qg_tiling t);
 
+// Deterministic mode of the adjoints (QG_DETERMINISTIC=1 in the environment, or qg_set_deterministic).
+bool deterministic_mode();
+
+// Per-(tile, entry) partial sums of the blend adjoint in deterministic mode: kPairPart floats per position of
+// the sorted pair list, for positions below cap.
+constexpr int kPairPart = 9;
+struct PairPart {
+    float* part;
+    uint32_t cap;
+};
+inline PairPart pair_part_in(char* base, size_t bytes) {
+    const size_t c = bytes / (kPairPart * sizeof(float));
+    return PairPart{(float*)base, (uint32_t)(c < 0xFFFFFFFFull ? c : 0xFFFFFFFFull)};
+}
+
+// Bytes of the per-chunk decoder weight-gradient rows that deterministic mode appends to the adjoint workspaces
+// (ahead of the pair partials).
+size_t det_weight_part_bytes(int64_t n);
+
 // Event timing around launches (no-ops unless qg_timing_enable(1)).
 void timing_begin(const char* name, hipStream_t s);
 void timing_end(hipStream_t s);

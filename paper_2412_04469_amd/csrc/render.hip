@@ -15,6 +15,9 @@
 //
 // The blend alpha is evaluated by one inline function used by both kernels, with explicit fused
 // multiply-adds, so the forward's skip/clamp/termination decisions are reproduced exactly.
+#include <map>
+#include <mutex>
+
 #include "qg_internal.h"
 
 namespace qg {
@@ -293,9 +296,9 @@ template <int TW, int TH, int BD>
 __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
                                          const ViewPtrsCF& tfinal, const ViewPtrsCU& lastp, const ViewPtrsCF& gimage,
-                                         float* __restrict__ grad2d, int64_t g2d_view_stride, int64_t tile,
-                                         float4* s_a, float4* s_b, float4* s_c, uint32_t* s_gid, uint32_t* s_pos,
-                                         float (*s_red)[12]) {
+                                         float* __restrict__ grad2d, int64_t g2d_view_stride, PairPart pp,
+                                         int64_t tile, float4* s_a, float4* s_b, float4* s_c, uint32_t* s_gid,
+                                         uint32_t* s_pos, float (*s_red)[12]) {
     constexpr int PPL = TileGeom<TW, TH>::PPL;
     constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
     const int v = view_of_tile(vt, (uint32_t)tile);
@@ -441,7 +444,10 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 const float val =
                     gscale * (((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane])) +
                               ((s_red[4][lane] + s_red[5][lane]) + (s_red[6][lane] + s_red[7][lane])));
-                atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
+                if (pp.part == nullptr)
+                    atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
+                else if (pos < pp.cap)  // deterministic mode: this (tile, entry)'s sums, added up later in order
+                    pp.part[(size_t)pos * kPairPart + lane] = val;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
                                                    const uint32_t* __restrict__ ranges, float bg0, float bg1,
                                                    float bg2, ViewPtrsCF tfinal, ViewPtrsCU lastp, ViewPtrsCF gimage,
                                                    float* __restrict__ grad2d, int64_t g2d_view_stride,
-                                                   int64_t per_xcd, Sched sc) {
+                                                   PairPart pp, int64_t per_xcd, Sched sc) {
     __shared__ float4 s_a[BD];  // x, y, o, A'
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float4 s_c[BD];  // b, A, B, C
@@ -469,33 +475,36 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
     if (sc.order == nullptr) {
         const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
         if (tile < vt.total_tiles)
-            bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride,
+            bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp,
                                  tile, s_a, s_b, s_c, s_gid, s_pos, s_red);
         return;
     }
     for (;;) {
         const uint32_t item = next_item(sc.ctr);
         if (item >= (uint32_t)vt.total_tiles) break;
-        bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride,
+        bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp,
                              sc.order[item], s_a, s_b, s_c, s_gid, s_pos, s_red);
     }
     finish_sched(sc.ctr);
 }
 
-// Resident workgroups of a kernel on the whole device (the persistent grid size), cached per kernel.
-template <class K>
-int64_t resident_blocks(K kernel) {
-    static int64_t cached = 0;
-    if (cached == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || cus <= 0 ||
-            per_cu <= 0)
-            return 0;
-        cached = (int64_t)cus * per_cu;
-    }
-    return cached;
+// Resident workgroups of a kernel on the whole current device (the persistent grid size), cached per
+// (kernel, device): every template instantiation is a different kernel with its own occupancy.
+int64_t resident_blocks(const void* kernel) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int64_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({kernel, dev});
+    if (it != cache.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || cus <= 0 || per_cu <= 0)
+        return 0;
+    const int64_t r = (int64_t)cus * per_cu;
+    cache[{kernel, dev}] = r;
+    return r;
 }
 
 inline Sched make_sched(const qg_tiling& t, int64_t total_tiles) {
@@ -516,7 +525,7 @@ qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
     const Sched sc = make_sched(tiling, vt.total_tiles);
     int64_t grid = per * 8;
     if (sc.order) {
-        const int64_t res = resident_blocks(k_render_fwd<TW, TH, BD>);
+        const int64_t res = resident_blocks(reinterpret_cast<const void*>(k_render_fwd<TW, TH, BD>));
         QG_REQUIRE(res > 0, "occupancy query failed");
         grid = std::min<int64_t>(vt.total_tiles, res);
     }
@@ -532,19 +541,19 @@ qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
 template <int TW, int TH, int BD>
 qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
-                       float* grad2d, int64_t stride, hipStream_t s) {
+                       float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
     const int64_t per = ceil_div(vt.total_tiles, 8);
     const Sched sc = make_sched(tiling, vt.total_tiles);
     int64_t grid = per * 8;
     if (sc.order) {
-        const int64_t res = resident_blocks(k_render_bwd<TW, TH, BD>);
+        const int64_t res = resident_blocks(reinterpret_cast<const void*>(k_render_bwd<TW, TH, BD>));
         QG_REQUIRE(res > 0, "occupancy query failed");
         grid = std::min<int64_t>(vt.total_tiles, res);
     }
     {
         QG_TIMED("blend_bwd", s);
         k_render_bwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
-                                                                grad2d, stride, per, sc);
+                                                                grad2d, stride, pp, per, sc);
     }
     QG_LAUNCH_CHECK("qg_render_bwd");
     return QG_OK;
@@ -562,10 +571,10 @@ qg_status launch_fwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* 
 template <int TW, int TH>
 qg_status launch_bwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
-                       float* grad2d, int64_t stride, hipStream_t s) {
-    if (t.batch == 32) return launch_bwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
-    if (t.batch == 128) return launch_bwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
-    return launch_bwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+                       float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
+    if (t.batch == 32) return launch_bwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+    if (t.batch == 128) return launch_bwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+    return launch_bwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
 }
 
 qg_status launch_fwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
@@ -575,12 +584,74 @@ qg_status launch_fwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* va
     return launch_fwd_b<32, 8>(vt, t, vals, ranges, bg, img, tf, lp, s);
 }
 
+qg_status launch_bwd_tiles(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
+                           const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
+                           float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
+    if (t.tile_w == 16) return launch_bwd_b<16, 16>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+    if (t.tile_w == 8) return launch_bwd_b<8, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+    return launch_bwd_b<32, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+}
+
+// Deterministic mode, second pass: the 2D gradient record of (view v, Gaussian i) is the sum of its
+// (tile, entry) partials over the tiles of its rectangle in row-major order, each entry found in its tile's
+// list by binary search on the list's order (depth bits, then Gaussian index).  A fixed order, so the record is
+// the same bits on every run.
+__global__ __launch_bounds__(256) void k_det_gather(int64_t n, ViewTable vt, const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ ranges, PairPart pp,
+                                                    float* __restrict__ grad2d, int64_t stride) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= n * vt.V) return;
+    const int v = (int)(item / n);
+    const int64_t i = item - (int64_t)v * n;
+    const ProjDev& p = vt.proj[v];
+    if (p.ntiles[i] <= 0) return;
+    const int4 r = reinterpret_cast<const int4*>(p.rect)[i];
+    const uint32_t key = __float_as_uint(p.depth[i]);
+    const CamDev& cam = vt.cam[v];
+    float acc[kPairPart];
+#pragma unroll
+    for (int k = 0; k < kPairPart; ++k) acc[k] = 0.f;
+    for (int ty = r.y; ty < r.w; ++ty)
+        for (int tx = r.x; tx < r.z; ++tx) {
+            const size_t t = (size_t)cam.tile_off + (size_t)ty * cam.grid_w + tx;
+            uint32_t lo = ranges[2 * t], hi = ranges[2 * t + 1];
+            const uint32_t end = hi;
+            while (lo < hi) {  // first entry whose (depth bits, index) is not below (key, i)
+                const uint32_t mid = lo + (hi - lo) / 2;
+                const uint32_t g = vals[mid];
+                const uint32_t kg = __float_as_uint(p.depth[g]);
+                if (kg < key || (kg == key && g < (uint32_t)i))
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo < end && vals[lo] == (uint32_t)i && lo < pp.cap) {
+#pragma unroll
+                for (int k = 0; k < kPairPart; ++k) acc[k] += pp.part[(size_t)lo * kPairPart + k];
+            }
+        }
+    float* rec = grad2d + (int64_t)v * stride + (size_t)i * QG_GRAD2D_STRIDE;
+#pragma unroll
+    for (int k = 0; k < kPairPart; ++k) rec[k] = acc[k];
+}
+
+// The blend adjoint into the zeroed 2D gradient records: float atomics across tiles, or, with a pair-partial
+// buffer (deterministic mode), per-(tile, entry) sums and then a fixed-order gather.
 qg_status launch_bwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
                      const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi, float* grad2d,
-                     int64_t stride, hipStream_t s) {
-    if (t.tile_w == 16) return launch_bwd_b<16, 16>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
-    if (t.tile_w == 8) return launch_bwd_b<8, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
-    return launch_bwd_b<32, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+                     int64_t stride, int64_t n, PairPart pp, hipStream_t s) {
+    if (pp.part) {
+        qg_status st = qg_zero(pp.part, (int64_t)pp.cap * kPairPart * 4, s);
+        if (st != QG_OK) return st;
+    }
+    qg_status st = launch_bwd_tiles(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+    if (st != QG_OK || !pp.part || n == 0) return st;
+    {
+        QG_TIMED("blend_bwd_gather", s);
+        k_det_gather<<<(unsigned)ceil_div(n * vt.V, 256), 256, 0, s>>>(n, vt, vals, ranges, pp, grad2d, stride);
+    }
+    QG_LAUNCH_CHECK("deterministic gather");
+    return QG_OK;
 }
 
 // ---- heaviest-first tile order --------------------------------------------------------------------
@@ -796,7 +867,8 @@ qg_status launch_dyn_mask(const ViewTable& vt, const uint32_t* vals, const uint3
 
 qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t* vals, const uint32_t* ranges,
                            const float* bg, const float* const* T_final, const uint32_t* const* last,
-                           const float* const* grad_image, float* grad2d, int64_t stride, hipStream_t s) {
+                           const float* const* grad_image, float* grad2d, int64_t stride, int64_t n, PairPart pp,
+                           hipStream_t s) {
     ViewPtrsCF tf = {}, gi = {};
     ViewPtrsCU lp = {};
     for (int v = 0; v < vt.V; ++v) {
@@ -804,7 +876,7 @@ qg_status blend_bwd_launch(const ViewTable& vt, qg_tiling tiling, const uint32_t
         lp.p[v] = last[v];
         gi.p[v] = grad_image[v];
     }
-    return launch_bwd(vt, tiling, vals, ranges, bg, tf, lp, gi, grad2d, stride, s);
+    return launch_bwd(vt, tiling, vals, ranges, bg, tf, lp, gi, grad2d, stride, n, pp, s);
 }
 
 }  // namespace qg
@@ -851,6 +923,13 @@ extern "C" qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, in
     QG_REQUIRE(n == 0 || (attrs && grad_attrs), "attrs/grad_attrs NULL");
     const size_t need = qg_render_bwd_workspace_size(n, V);
     QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    PairPart pp{nullptr, 0};
+    if (deterministic_mode()) {
+        const size_t wb = det_weight_part_bytes(n);  // unused here; the layout is that of qg_render_decode_bwd
+        QG_REQUIRE(ws_bytes >= need + wb + align_up(kPairPart * 4), "deterministic mode: workspace %zu has no room "
+                   "for the pair partials (add qg_deterministic_workspace_size)", ws_bytes);
+        pp = pair_part_in((char*)ws + need + wb, ws_bytes - need - wb);
+    }
     ViewPtrsCF tf = {}, gi = {};
     ViewPtrsCU lp = {};
     for (int v = 0; v < V; ++v) {
@@ -865,7 +944,7 @@ extern "C" qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, in
     const int64_t stride = n * QG_GRAD2D_STRIDE;
     qg_status st = qg_zero(grad2d, (int64_t)V * stride * 4, stream);
     if (st != QG_OK) return st;
-    st = launch_bwd(vt, tiling, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, s);
+    st = launch_bwd(vt, tiling, vals, tile_ranges, bg, tf, lp, gi, grad2d, stride, n, pp, s);
     if (st != QG_OK) return st;
     return project_bwd_launch(n, ld, attrs, sh_degree, vt, dilation, grad2d, stride, grad_attrs, grad_xy_abs,
                               grad_xy, s);

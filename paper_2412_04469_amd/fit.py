@@ -54,6 +54,21 @@ class FitConfig:
     mask_fraction: float = 0.0
     # Eq. 3's D-SSIM weight lambda (not given in the paper; 3D-GS uses 0.2); 0 fits the L1 term alone
     lambda_dssim: float = 0.0
+    # the stochastic hard concrete gate (Eq. 6 as written is deterministic; this draws the gate's logistic noise
+    # per Gaussian and step from a counter-based generator seeded by gate_seed); evaluation stays deterministic
+    stochastic_gate: bool = False
+    gate_seed: int = 2412
+    # per-frame densification (3D-GS's stage run inside each frame's fit; implementation details of the paper:
+    # from epoch 6 until 80% of the epochs, every 2 epochs, gradient threshold 0.00125), clone below
+    # percent_dense x the camera extent, split above, prune opacity below min_opacity (FrameFitter.densify)
+    densify: bool = False
+    densify_threshold: float = 0.00125
+    densify_start_epoch: int = 6
+    densify_stop_frac: float = 0.8
+    densify_every: int = 2
+    percent_dense: float = 0.01
+    min_opacity: float = 0.005
+    densify_seed: int = 4469
 
 
 def xavier_decoder(seed: int, L=8, H=32, M=56):
@@ -96,6 +111,8 @@ class ResidualState:
         self.step_state = torch.zeros(4, dtype=torch.int32, device=dev)
         self.attrs = torch.empty_like(self.prev)
         self.gate = torch.empty(max(n, 1), device=dev)
+        # the stochastic gate's logistic noise of the current step (None: the deterministic gate of Eq. 6)
+        self.noise = torch.empty(max(n, 1), device=dev) if cfg.stochastic_gate else None
         self.lreg_part = torch.empty(qg.qg_decode_lreg_blocks(n), device=dev)
         keys = list(self.params)
         self.adam_segs = qg.adam_segments([self.params[k] for k in keys], [self.grads[k] for k in keys],
@@ -121,11 +138,12 @@ class ResidualState:
         self.step_state.zero_()
         self.t = 0
 
-    def decode(self, stream=None):
+    def decode(self, stream=None, gate_noise=None):
+        """The decoded attributes of frame t (the deterministic gate unless gate_noise is given)."""
         c = self.cfg
         qg.qg_decode_residuals(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                self.lp, self.a, c.gamma0, c.gamma1, c.tau, self.attrs, self.gate, self.lreg_part,
-                               stream)
+                               stream, gate_noise=gate_noise)
 
     def _eval_psnr(self, rast, cam, gt, loss_part, loss_out, stream=None):
         """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync)."""
@@ -158,11 +176,15 @@ class FrameFitter(ResidualState):
         self.grad_attrs = torch.zeros_like(self.prev)
         self.dws_bytes = qg.qg_decode_bwd_workspace_size(n, L, H, 56)
         self.dws = torch.empty(self.dws_bytes, dtype=torch.uint8, device=dev)
-        self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(n, 1)
-        self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
         self.fused = True
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
                                bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch)
+        if cfg.densify:  # the densification statistic and the per-view viewspace gradient it is taken from
+            self.d_accum = torch.zeros(max(n, 1), device=dev)
+            self.d_count = torch.zeros(max(n, 1), device=dev)
+            self.d_gxy = torch.zeros(2, max(n, 1), device=dev)
+        self._alloc_fws()
+        self.rast.capacity_listeners.append(self._alloc_fws)
         self.qcams = [qg.camera_array([c]) for c in self.cams]
         img = self.rast.images[0]
         self.count = img.numel()
@@ -174,6 +196,11 @@ class FrameFitter(ResidualState):
             self.ssim_ws_bytes = qg.qg_ssim_workspace_size(C, H, W)
             self.ssim_ws = torch.empty(self.ssim_ws_bytes, dtype=torch.uint8, device=dev)
             self.dssim_out = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def _alloc_fws(self):
+        """The fused adjoint's workspace (plus the deterministic-mode partials, sized by the pair capacity)."""
+        self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(self.n, 1) + self.rast.det_ws_bytes()
+        self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=self.device)
 
     # -- the step ------------------------------------------------------------------------------
     def forward_view(self, v, stream=None):
@@ -192,18 +219,20 @@ class FrameFitter(ResidualState):
         tiles flagged in view v's mask, with the L1 over its masked pixels (Sec. 3.3)."""
         c = self.cfg
         r = self.rast
+        if self.noise is not None:
+            qg.qg_gate_noise(self.n, c.gate_seed, self.t, self.noise, stream=stream)
         if self.fused:
             r.qcams = self.qcams[v]
             qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                  self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
-                                 r.t_proj, self.attrs, self.gate, None, stream)
+                                 r.t_proj, self.attrs, self.gate, None, stream, gate_noise=self.noise)
             r.bin(stream)
             if masked:
                 qg.qg_mask_tile_ranges(r.total_tiles, r.ranges, self.masks[v][1], stream)
             r.render(stream)
         else:
             assert not masked, "masked steps use the fused path"
-            self.decode(stream)
+            self.decode(stream, gate_noise=self.noise)
             self.forward_view(v, stream)
         if masked:
             assert c.lambda_dssim == 0.0, "masked steps fit the L1 term"
@@ -220,20 +249,28 @@ class FrameFitter(ResidualState):
         else:
             qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
         # parameter gradients are zero here: they start zeroed and qg_adam_multi clears them after use
+        gxy = None
+        if c.densify:
+            qg.qg_zero(self.d_gxy, self.d_gxy.numel() * 4, stream)
+            gxy = [self.d_gxy]
         if self.fused:
             qg.qg_render_decode_bwd(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                     self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
                                     r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
                                     [self.grad_img], self.grads["lat"], self.grads["W1"], self.grads["W2"],
-                                    self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream,
-                                    attrs=self.attrs)
+                                    self.grads["lp"], self.grads["a"], None, gxy, self.fws, self.fws_bytes, stream,
+                                    attrs=self.attrs, gate_noise=self.noise)
         else:
             qg.qg_zero(self.grad_attrs, self.grad_attrs.numel() * 4, stream)
-            r.backward(self.attrs, [self.grad_img], self.grad_attrs, stream=stream)
+            r.backward(self.attrs, [self.grad_img], self.grad_attrs, grad_xy=gxy, stream=stream)
             qg.qg_decode_residuals_bwd(self.n, self.ld, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56, self.lp,
                                        self.a, c.gamma0, c.gamma1, c.tau, self.grad_attrs, c.lambda_reg,
                                        self.grads["lat"], self.grads["W1"], self.grads["W2"], self.grads["lp"],
-                                       self.grads["a"], self.dws, self.dws_bytes, stream)
+                                       self.grads["a"], self.dws, self.dws_bytes, stream, gate_noise=self.noise)
+        if c.densify:
+            cam = self.cams[v]
+            qg.qg_densify_accumulate(self.n, self.d_gxy, r.proj[0]["ntiles"], cam.width / 2.0, cam.height / 2.0,
+                                     self.d_accum, self.d_count, stream)
         self.t += 1
         b1, b2 = c.betas
         qg.qg_adam_multi(self.adam_segs, b1, b2, c.eps, self.t, True, stream)
@@ -259,6 +296,61 @@ class FrameFitter(ResidualState):
         if worst * 1.05 > self.rast.capacity:
             self.rast._alloc_capacity(int(worst * margin))
         return worst
+
+
+def densify_iterations(cfg: FitConfig, iters_per_epoch: int, epochs: int):
+    """Iterations (counted before the step runs) at which a frame's fit densifies: the starts of epochs
+    densify_start_epoch, + densify_every, ... up to densify_stop_frac of the epochs."""
+    last = int(math.floor(cfg.densify_stop_frac * epochs))
+    return [e * iters_per_epoch for e in range(cfg.densify_start_epoch, last + 1, cfg.densify_every)]
+
+
+def camera_extent(cams) -> float:
+    """3D-GS's scene extent: 1.1 x the largest distance of a camera centre from their mean."""
+    c = np.stack([cam.center() for cam in cams])
+    return 1.1 * float(np.linalg.norm(c - c.mean(0), axis=1).max())
+
+
+def densify_fitter(f: "FrameFitter", extent: float, rnd: int, stream=None):
+    """The densification stage inside a frame's fit (3D-GS's clone / split / prune on the viewspace-gradient
+    statistic accumulated since the last stage).  Returns (a new FrameFitter over the new Gaussian set, the
+    action counts).  Every per-Gaussian array is expanded through the plan on the device: A_{t-1}, the residual
+    parameters (copied to every child, so a child decodes like its parent) and their Adam moments (zero for new
+    Gaussians); split children then get their offset and scale change; the decoder, its moments and the step
+    count carry over.  One host read (the new count), then fresh buffers and capacity for the new size."""
+    c = f.cfg
+    n, dev = f.n, f.device
+    f.decode(stream)  # the current decoded attributes (deterministic gate) decide scales and opacities
+    action = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    wsb = qg.qg_densify_plan_workspace_size(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    qg.qg_densify_plan(n, f.d_accum, f.d_count, f.attrs, f.ld, c.densify_threshold, c.percent_dense * extent,
+                       c.min_opacity, action, offsets, ws, wsb, stream)
+    n2 = int(offsets[n].item())
+    counts = torch.bincount(action[:n].to(torch.int64), minlength=4).tolist()
+    prev2 = torch.empty(59, max(n2, 1), device=dev)
+    qg.qg_densify_expand(n, action, offsets, 59, f.prev, f.ld, prev2, prev2.stride(0), 0, stream)
+    qg.qg_densify_split(n, action, offsets, f.attrs, f.ld, c.densify_seed, rnd, prev2, prev2.stride(0), stream)
+    g = FrameFitter(prev2[:, :n2], f.cams, f.gts, c, W1=f.W1.clone(), W2=f.W2.clone(),
+                    capacity=int(f.rast.capacity * max(n2, 1) / max(n, 1)) + 1024)
+    for k in ("lat", "lp", "a"):
+        src, dst = f.params[k], g.params[k]
+        planes = 1 if src.dim() == 1 else src.shape[0]
+        lds, ldd = (src.shape[-1], dst.shape[-1])
+        qg.qg_densify_expand(n, action, offsets, planes, src, lds, dst, ldd, 0, stream)
+        for mom_src, mom_dst in ((f.m[k], g.m[k]), (f.v[k], g.v[k])):
+            qg.qg_densify_expand(n, action, offsets, planes, mom_src, lds, mom_dst, ldd, 1, stream)
+    for k in ("W1", "W2"):
+        g.m[k].copy_(f.m[k])
+        g.v[k].copy_(f.v[k])
+    g.t = f.t
+    g.step_state.copy_(f.step_state)
+    if getattr(f, "masks", None) is not None:
+        g.set_masks(f.masks)
+    g.size_capacity()
+    return g, {"keep": counts[0], "clone": counts[1], "split": counts[2], "prune": counts[3], "n_before": n,
+               "n_after": n2}
 
 
 def frame_storage(state: ResidualState, stream=None) -> dict:
@@ -330,9 +422,9 @@ class BatchedFitter(ResidualState):
             self.loss_parts.append([torch.empty(2 * qg.qg_loss_blocks(im.numel()), dtype=torch.float64, device=dev)
                                     for im in r.images])
         self.t_gimg = [qg._ptr_array(gl) for gl in self.gimgs]
-        vmax = max(len(g) for g in self.groups)
-        self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(n, vmax)
-        self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=dev)
+        self._alloc_fws()
+        for r in self.rasts:
+            r.capacity_listeners.append(self._alloc_fws)
         self.graphs = [None] * len(self.groups)
         self.next_group = 0
         ec = eval_cam if eval_cam is not None else self.cams[0]
@@ -341,6 +433,15 @@ class BatchedFitter(ResidualState):
         self.eval_part = torch.empty(2 * qg.qg_loss_blocks(self.eval_rast.images[0].numel()), dtype=torch.float64,
                                      device=dev)
         self.eval_out = torch.zeros(2, dtype=torch.float64, device=dev)
+
+    def _alloc_fws(self):
+        """One fused-adjoint workspace for every group (deterministic-mode partials sized by the largest pair
+        capacity); captured graphs hold its address, so they are dropped."""
+        vmax = max(len(g) for g in self.groups)
+        self.fws_bytes = (qg.qg_render_decode_bwd_workspace_size(self.n, vmax) +
+                          max(r.det_ws_bytes() for r in self.rasts))
+        self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=self.device)
+        self.graphs = [None] * len(self.groups)
 
     def reset_frame(self, prev_attrs=None, gts=None, a_init=None, lat_init=None, lp_init=None):
         if gts is not None:
@@ -352,9 +453,11 @@ class BatchedFitter(ResidualState):
         c = self.cfg
         r = self.rasts[gi]
         views = self.groups[gi]
+        if self.noise is not None:  # drawn from the device step counter, so each replay draws afresh
+            qg.qg_gate_noise(self.n, c.gate_seed, 0, self.noise, step_state=self.step_state, stream=stream)
         qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                              self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
-                             r.t_proj, self.attrs, self.gate, None, stream)
+                             r.t_proj, self.attrs, self.gate, None, stream, gate_noise=self.noise)
         r.bin(stream)
         r.render(stream)
         w = 1.0 / len(views)
@@ -366,7 +469,7 @@ class BatchedFitter(ResidualState):
                                 r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
                                 self.t_gimg[gi], self.grads["lat"], self.grads["W1"], self.grads["W2"],
                                 self.grads["lp"], self.grads["a"], None, None, self.fws, self.fws_bytes, stream,
-                                attrs=self.attrs)
+                                attrs=self.attrs, gate_noise=self.noise)
         b1, b2 = c.betas
         qg.qg_adam_multi(self.adam_segs, b1, b2, c.eps, 0, True, stream, step_state=self.step_state)
 
@@ -423,6 +526,93 @@ class BatchedFitter(ResidualState):
 
     def psnr(self, cam, gt, stream=None):
         return self._eval_psnr(self.eval_rast, cam, gt, self.eval_part, self.eval_out, stream)
+
+
+class AttributeFitter:
+    """Direct fit of the attribute planes (no residual decoder): the plain differentiable-rasterizer step that the
+    small, batched and dense-overlap workloads time.  One optimiser iteration covers all cameras of the fitter in
+    one multi-view launch of each call: qg_project -> qg_bin -> qg_render_fwd -> per-view qg_l1_loss (weight 1/V)
+    -> qg_render_bwd -> qg_adam_multi over five parameter groups (means, quaternions, log-scales, opacity logits,
+    SH) with the 3D-GS learning rates.  The step has no host synchronisation, so it is captured once as a graph
+    and replayed; the pair capacity is sized beforehand (size_capacity)."""
+
+    LRS = (1.6e-4, 1e-3, 5e-3, 5e-2, 2.5e-3)  # means, rotation, scale, opacity, SH
+    PLANES = ((0, 3), (3, 7), (7, 10), (10, 11), (11, 59))
+
+    def __init__(self, attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), capacity=None, graph=True):
+        self.cfg = cfg
+        self.attrs = attrs.detach().clone(memory_format=torch.contiguous_format)
+        self.n = int(self.attrs.shape[1])
+        dev = self.attrs.device
+        self.device = dev
+        self.cams = list(cams)
+        self.gts = [g.clone() for g in gts]
+        self.rast = Rasterizer(self.n, self.cams, tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
+                               bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch)
+        self.grad = torch.zeros_like(self.attrs)
+        self.m = torch.zeros_like(self.attrs)
+        self.v = torch.zeros_like(self.attrs)
+        self.step_state = torch.zeros(4, dtype=torch.int32, device=dev)
+        ld = self.attrs.stride(0)
+        segs = []
+        for (lo, hi), lr in zip(self.PLANES, self.LRS):
+            sl = slice(lo * ld, hi * ld)
+            segs.append((self.attrs.view(-1)[sl], self.grad.view(-1)[sl], self.m.view(-1)[sl], self.v.view(-1)[sl],
+                         lr))
+        self.adam_segs = qg.adam_segments(*[[sg[k] for sg in segs] for k in range(5)])
+        self.gimgs = [torch.empty_like(im) for im in self.rast.images]
+        self.counts = [im.numel() for im in self.rast.images]
+        self.loss_parts = [torch.empty(2 * qg.qg_loss_blocks(c), dtype=torch.float64, device=dev)
+                           for c in self.counts]
+        self.use_graph = bool(graph)
+        self.graph = None
+
+    def size_capacity(self, margin=1.3):
+        """Bin once (host sync) and size the pair capacity; drops a captured graph."""
+        r = self.rast
+        r.project(self.attrs)
+        r.bin()
+        p = r.pair_count()
+        if p * 1.05 > r.capacity:
+            r._alloc_capacity(int(p * margin))
+        self.graph = None
+        return p
+
+    def _enqueue(self, stream=None):
+        r = self.rast
+        r.project(self.attrs, stream)
+        r.bin(stream)
+        r.render(stream)
+        w = 1.0 / len(self.cams)
+        for k in range(len(self.cams)):
+            qg.qg_l1_loss(self.counts[k], r.images[k], self.gts[k], w, self.gimgs[k], self.loss_parts[k], stream)
+        r.backward(self.attrs, self.gimgs, self.grad, stream=stream)
+        b1, b2 = self.cfg.betas
+        qg.qg_adam_multi(self.adam_segs, b1, b2, self.cfg.eps, 0, True, stream, step_state=self.step_state)
+
+    def step(self, stream=None):
+        if self.use_graph and self.graph is not None:
+            self.graph.replay()
+            return
+        self._enqueue(stream)
+        if self.use_graph:
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                self._enqueue()
+            self.graph = g
+
+    def overflowed(self):
+        return self.rast.overflowed()
+
+    def loss(self):
+        """Mean over views of the per-view mean L1 of the last step (host sync)."""
+        out = torch.zeros(2, dtype=torch.float64, device=self.device)
+        tot = 0.0
+        for c, part in zip(self.counts, self.loss_parts):
+            qg.qg_loss_reduce(c, part, out)
+            tot += float(out[0].item())
+        return tot / len(self.counts)
 
 
 def render_views(attrs: torch.Tensor, cams, cfg: FitConfig = FitConfig(), capacity=None):

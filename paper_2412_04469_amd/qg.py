@@ -66,13 +66,18 @@ def lib():
         sig = {
             "qg_last_error": ([], ctypes.c_char_p),
             "qg_version": ([], i32),
+            "qg_set_deterministic": ([i32], i32),
+            "qg_get_deterministic": ([], i32),
+            "qg_deterministic_workspace_size": ([i64, i64], sz),
             "qg_zero": ([P, i64, P], i32),
             "qg_total_tiles": ([CAM, i32, qg_tiling], i64),
-            "qg_decode_residuals": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, P, P, P, P], i32),
+            "qg_decode_residuals": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, P, f32, f32, f32, P, P, P, P], i32),
             "qg_decode_lreg_blocks": ([i64], i64),
+            "qg_decode_lreg_mean": ([i64, P, i64, P, P], i32),
+            "qg_decode_lreg_bwd": ([i64, P, f32, f32, f32, P, P, P], i32),
             "qg_decode_bwd_workspace_size": ([i64, i32, i32, i32], sz),
-            "qg_decode_residuals_bwd": ([i64, i64, P, i32, P, P, i32, i32, P, P, f32, f32, f32, P, f32, P, P, P, P, P,
-                                         P, sz, P], i32),
+            "qg_decode_residuals_bwd": ([i64, i64, P, i32, P, P, i32, i32, P, P, P, f32, f32, f32, P, f32, P, P, P, P,
+                                         P, P, sz, P], i32),
             "qg_project": ([i64, i64, P, i32, CAM, i32, qg_tiling, f32, PRJ, P], i32),
             "qg_bin_workspace_size": ([i64, i32, i64, i64], sz),
             "qg_bin": ([i64, PRJ, CAM, i32, qg_tiling, i64, P, P, P, P, P, sz, P], i32),
@@ -103,11 +108,11 @@ def lib():
             "qg_scaled_diff": ([i64, P, P, f32, P, P], i32),
             "qg_gate_init_workspace_size": ([i64], sz),
             "qg_gate_init": ([i64, P, f32, f32, f32, P, P, P, P, sz, P], i32),
-            "qg_decode_project": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, i32, CAM, i32, qg_tiling,
-                                   f32, PRJ, P, P, P, P], i32),
+            "qg_decode_project": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, P, f32, f32, f32, i32, CAM, i32,
+                                   qg_tiling, f32, PRJ, P, P, P, P], i32),
             "qg_render_decode_bwd_workspace_size": ([i64, i32], sz),
-            "qg_render_decode_bwd": ([i64, i64, P, P, P, i32, P, P, i32, i32, P, P, f32, f32, f32, f32, i32, CAM, i32,
-                                      qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P], i32),
+            "qg_render_decode_bwd": ([i64, i64, P, P, P, i32, P, P, i32, i32, P, P, P, f32, f32, f32, f32, i32, CAM,
+                                      i32, qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P], i32),
             "qg_timing_report": ([ctypes.c_char_p, i64], i64),
             "qg_schedule_words": ([i64], i64),
             "qg_proposal_features": ([i64, i64, P, P, P, P, P, i64, P], i32),
@@ -115,6 +120,13 @@ def lib():
             "qg_proposal_bwd_workspace_size": ([], sz),
             "qg_proposal_bwd": ([i64, P, i64, i64, P, P, P, P, P, P, P, sz, P], i32),
             "qg_schedule_tiles": ([i64, P, P, i64, P], i32),
+            "qg_gate_noise": ([i64, ctypes.c_uint64, i32, P, P, P], i32),
+            "qg_densify_accumulate": ([i64, P, P, f32, f32, P, P, P], i32),
+            "qg_densify_plan_workspace_size": ([i64], sz),
+            "qg_densify_plan": ([i64, P, P, P, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P, sz,
+                                 P], i32),
+            "qg_densify_expand": ([i64, P, P, i32, P, i64, P, i64, i32, P], i32),
+            "qg_densify_split": ([i64, P, P, P, i64, ctypes.c_uint64, i32, P, i64, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -244,9 +256,10 @@ def qg_total_tiles(cams, tile):
 
 
 def qg_decode_residuals(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
-                        attrs_out, gate_out=None, lreg_partial=None, stream=None):
+                        attrs_out, gate_out=None, lreg_partial=None, stream=None, gate_noise=None):
     _check(lib().qg_decode_residuals(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), int(L), _ptr(W1), _ptr(W2),
-                                     int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
+                                     int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), _ptr(gate_noise),
+                                     float(gamma0), float(gamma1),
                                      float(tau), _ptr(attrs_out), _ptr(gate_out), _ptr(lreg_partial),
                                      _stream(stream)))
 
@@ -255,15 +268,25 @@ def qg_decode_lreg_blocks(n):
     return int(lib().qg_decode_lreg_blocks(int(n)))
 
 
+def qg_decode_lreg_mean(n, lreg_partial, nblocks, out, stream=None):
+    _check(lib().qg_decode_lreg_mean(int(n), _ptr(lreg_partial), int(nblocks), _ptr(out), _stream(stream)))
+
+
+def qg_decode_lreg_bwd(n, gate_logit, gamma0, gamma1, tau, weight, grad_gate_logit, stream=None):
+    _check(lib().qg_decode_lreg_bwd(int(n), _ptr(gate_logit), float(gamma0), float(gamma1), float(tau), _ptr(weight),
+                                    _ptr(grad_gate_logit), _stream(stream)))
+
+
 def qg_decode_bwd_workspace_size(n, L, Hd, M):
     return int(lib().qg_decode_bwd_workspace_size(int(n), int(L), int(Hd), int(M)))
 
 
 def qg_decode_residuals_bwd(n, ld, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau, grad_attrs,
                             lambda_reg, grad_latents, grad_W1, grad_W2, grad_pos_pre, grad_gate_logit, ws, ws_bytes,
-                            stream=None):
+                            stream=None, gate_noise=None):
     _check(lib().qg_decode_residuals_bwd(int(n), int(ld), _ptr(latents), int(L), _ptr(W1), _ptr(W2), int(Hd), int(M),
-                                         _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1), float(tau),
+                                         _ptr(pos_pre), _ptr(gate_logit), _ptr(gate_noise), float(gamma0),
+                                         float(gamma1), float(tau),
                                          _ptr(grad_attrs), float(lambda_reg), _ptr(grad_latents), _ptr(grad_W1),
                                          _ptr(grad_W2), _ptr(grad_pos_pre), _ptr(grad_gate_logit), _ptr(ws),
                                          int(ws_bytes), _stream(stream)))
@@ -274,6 +297,18 @@ def qg_project(n, ld, attrs, sh_degree, cams, tile, dilation, out, stream=None):
     pa = projected_array(out)
     _check(lib().qg_project(int(n), int(ld), _ptr(attrs), int(sh_degree), ca, len(cams), tile, float(dilation), pa,
                             _stream(stream)))
+
+
+def qg_set_deterministic(on):
+    _check(lib().qg_set_deterministic(1 if on else 0))
+
+
+def qg_get_deterministic():
+    return bool(lib().qg_get_deterministic())
+
+
+def qg_deterministic_workspace_size(n, capacity):
+    return int(lib().qg_deterministic_workspace_size(int(n), int(capacity)))
 
 
 def qg_bin_workspace_size(n, V, capacity, total_tiles):
@@ -422,11 +457,12 @@ def qg_decode_project_lreg_blocks(n):
 
 def qg_decode_project(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
                       sh_degree, cams, tile, dilation, out, attrs_out=None, gate_out=None, lreg_partial=None,
-                      stream=None):
+                      stream=None, gate_noise=None):
     ca = camera_array(cams)
     pa = projected_array(out)
     _check(lib().qg_decode_project(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), int(L), _ptr(W1), _ptr(W2),
-                                   int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
+                                   int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), _ptr(gate_noise),
+                                   float(gamma0), float(gamma1),
                                    float(tau), int(sh_degree), ca, len(ca), tile, float(dilation), pa,
                                    _ptr(attrs_out), _ptr(gate_out), _ptr(lreg_partial), _stream(stream)))
 
@@ -438,15 +474,16 @@ def qg_render_decode_bwd_workspace_size(n, V):
 def qg_render_decode_bwd(n, ld, prev_attrs, latents, L, W1, W2, Hd, M, pos_pre, gate_logit, gamma0, gamma1, tau,
                          lambda_reg, sh_degree, cams, tile, dilation, proj, vals, tile_ranges, bg, T_final, last,
                          grad_image, grad_latents, grad_W1, grad_W2, grad_pos_pre, grad_gate_logit, grad_xy_abs,
-                         grad_xy, ws, ws_bytes, stream=None, attrs=None):
+                         grad_xy, ws, ws_bytes, stream=None, attrs=None, gate_noise=None):
     ca = camera_array(cams)
     pa = projected_array(proj)
     bga = (ctypes.c_float * 3)(*[float(b) for b in bg])
     gxy = None if grad_xy is None else _ptr_array(grad_xy)
     _check(lib().qg_render_decode_bwd(int(n), int(ld), _ptr(prev_attrs), _ptr(attrs), _ptr(latents), int(L), _ptr(W1),
                                       _ptr(W2),
-                                      int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), float(gamma0), float(gamma1),
-                                      float(tau), float(lambda_reg), int(sh_degree), ca, len(ca), tile,
+                                      int(Hd), int(M), _ptr(pos_pre), _ptr(gate_logit), _ptr(gate_noise),
+                                      float(gamma0), float(gamma1), float(tau), float(lambda_reg), int(sh_degree), ca,
+                                      len(ca), tile,
                                       float(dilation), pa, _ptr(vals), _ptr(tile_ranges), bga, _ptr_array(T_final),
                                       _ptr_array(last), _ptr_array(grad_image), _ptr(grad_latents), _ptr(grad_W1),
                                       _ptr(grad_W2), _ptr(grad_pos_pre), _ptr(grad_gate_logit), _ptr(grad_xy_abs),
@@ -477,3 +514,35 @@ def adam_segments(params, grads, ms, vs, lrs):
 def qg_adam_multi(segs, b1, b2, eps, t, zero_grad=True, stream=None, step_state=None):
     _check(lib().qg_adam_multi(len(segs), segs, float(b1), float(b2), float(eps), int(t), _ptr(step_state),
                                int(bool(zero_grad)), _stream(stream)))
+
+
+def qg_gate_noise(n, seed, step, noise, step_state=None, stream=None):
+    _check(lib().qg_gate_noise(int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), _ptr(step_state), _ptr(noise),
+                               _stream(stream)))
+
+
+def qg_densify_accumulate(n, grad_xy, ntiles, sx, sy, accum, count, stream=None):
+    _check(lib().qg_densify_accumulate(int(n), _ptr(grad_xy), _ptr(ntiles), float(sx), float(sy), _ptr(accum),
+                                       _ptr(count), _stream(stream)))
+
+
+def qg_densify_plan_workspace_size(n):
+    return int(lib().qg_densify_plan_workspace_size(int(n)))
+
+
+def qg_densify_plan(n, accum, count, attrs, ld, threshold, max_scale, min_opacity, action, offsets, ws, ws_bytes,
+                    stream=None):
+    _check(lib().qg_densify_plan(int(n), _ptr(accum), _ptr(count), _ptr(attrs), int(ld), float(threshold),
+                                 float(max_scale), float(min_opacity), _ptr(action), _ptr(offsets), _ptr(ws),
+                                 int(ws_bytes), _stream(stream)))
+
+
+def qg_densify_expand(n, action, offsets, nplanes, src, ld_src, dst, ld_dst, mode, stream=None):
+    _check(lib().qg_densify_expand(int(n), _ptr(action), _ptr(offsets), int(nplanes), _ptr(src), int(ld_src), _ptr(dst),
+                                   int(ld_dst), int(mode), _stream(stream)))
+
+
+def qg_densify_split(n, action, offsets, decoded, ld, seed, rnd, prev_out, ld_out, stream=None):
+    _check(lib().qg_densify_split(int(n), _ptr(action), _ptr(offsets), _ptr(decoded), int(ld),
+                                  int(seed) & 0xFFFFFFFFFFFFFFFF, int(rnd), _ptr(prev_out), int(ld_out),
+                                  _stream(stream)))

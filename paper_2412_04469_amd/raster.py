@@ -51,11 +51,10 @@ class Rasterizer:
             self.schedule = torch.zeros(qg.qg_schedule_words(self.total_tiles), dtype=torch.int32, device=d)
         self.tile = qg.tiling(*tile, batch=self.batch, schedule=self.schedule)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=d)
+        self.capacity_listeners = []  # called after the pair capacity changed (workspaces that depend on it)
         if capacity is None:
             capacity = max(1024, 16 * self.n * self.V)
         self._alloc_capacity(int(capacity))
-        self.bwd_ws_bytes = qg.qg_render_bwd_workspace_size(self.n, self.V)
-        self.bwd_ws = torch.empty(self.bwd_ws_bytes, dtype=torch.uint8, device=d)
         self._tables()
 
     def _tables(self):
@@ -80,6 +79,15 @@ class Rasterizer:
         self.keys = torch.empty(max(self.capacity, 1), dtype=torch.int64, device=d) if self.want_keys else None
         self.bin_ws_bytes = qg.qg_bin_workspace_size(self.n, self.V, self.capacity, self.total_tiles)
         self.bin_ws = torch.empty(self.bin_ws_bytes, dtype=torch.uint8, device=d)
+        # the adjoint's workspace; in deterministic mode it also holds one set of partials per pair slot
+        self.bwd_ws_bytes = qg.qg_render_bwd_workspace_size(self.n, self.V) + self.det_ws_bytes()
+        self.bwd_ws = torch.empty(self.bwd_ws_bytes, dtype=torch.uint8, device=d)
+        for f in getattr(self, "capacity_listeners", ()):
+            f()
+
+    def det_ws_bytes(self) -> int:
+        """Workspace the adjoint calls need on top of their own in deterministic mode (0 when it is off)."""
+        return qg.qg_deterministic_workspace_size(self.n, self.capacity) if qg.qg_get_deterministic() else 0
 
     # -- individual ABI steps -----------------------------------------------------------------
     def project(self, attrs, stream=None):
@@ -166,7 +174,8 @@ class DecodeFn(torch.autograd.Function):
         part = torch.empty(nb, device=prev.device)
         qg.qg_decode_residuals(n, prev.stride(0), prev, latents, latents.shape[0], W1, W2, W1.shape[0], W2.shape[0],
                                l_p, a, gamma0, gamma1, tau, out, gate, part)
-        lreg = part.sum() / max(n, 1)
+        lreg = torch.empty((), device=prev.device)  # Eq. 8 as a mean over the Gaussians, reduced on the device
+        qg.qg_decode_lreg_mean(n, part, nb, lreg)
         ctx.save_for_backward(latents, W1, W2, l_p, a)
         ctx.hp = (gamma0, gamma1, tau, n, prev.stride(0))
         return out, lreg
@@ -176,7 +185,6 @@ class DecodeFn(torch.autograd.Function):
         latents, W1, W2, l_p, a = ctx.saved_tensors
         gamma0, gamma1, tau, n, ld = ctx.hp
         g_out = torch.zeros((59, ld), device=a.device) if g_out is None else g_out.contiguous()
-        lam = float(g_lreg) if g_lreg is not None else 0.0
         gl = torch.zeros_like(latents)
         gW1 = torch.zeros_like(W1)
         gW2 = torch.zeros_like(W2)
@@ -185,5 +193,7 @@ class DecodeFn(torch.autograd.Function):
         wsb = qg.qg_decode_bwd_workspace_size(n, latents.shape[0], W1.shape[0], W2.shape[0])
         ws = torch.empty(wsb, dtype=torch.uint8, device=a.device)
         qg.qg_decode_residuals_bwd(n, ld, latents, latents.shape[0], W1, W2, W1.shape[0], W2.shape[0], l_p, a, gamma0,
-                                   gamma1, tau, g_out, lam, gl, gW1, gW2, glp, ga, ws, wsb)
+                                   gamma1, tau, g_out, 0.0, gl, gW1, gW2, glp, ga, ws, wsb)
+        if g_lreg is not None:  # the weight of L_reg stays on the device (no host sync)
+            qg.qg_decode_lreg_bwd(n, a, gamma0, gamma1, tau, g_lreg.reshape(1).contiguous(), ga)
         return gl, gW1, gW2, glp, ga, None, None, None, None

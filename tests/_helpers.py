@@ -11,9 +11,12 @@ MARGIN_ORDER = 1e-6  # relative depth gap below which independently computed flo
 
 
 def keep_mask(ref, order=True, margin=MARGIN_FWD):
+    """Pixels whose oracle decisions are far enough from their thresholds to be compared; prints how many are
+    left out."""
     k = ref["margin"] >= margin
     if order:
         k &= ref["order_margin"] >= MARGIN_ORDER
+    print(f"[margins] {int(k.size - k.sum())} of {k.size} pixels excluded", flush=True)
     return k
 
 

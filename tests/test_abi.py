@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(qg.LIB_PATH)
     for nm in names:
         assert hasattr(lib, nm), nm
-    assert qg.qg_version() == 1
+    assert qg.qg_version() == 2
 
 
 def _cam(w=64, h=48):

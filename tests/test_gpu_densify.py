@@ -1,0 +1,214 @@
+"""The stochastic hard concrete gate and per-frame densification on the GPU, against the oracle.
+
+* gate noise: the same Philox counters on both sides give the same uniforms; the logistic samples agree to
+  float32 rounding, from a host step count and from the device step counter;
+* decode with the noisy gate (forward and backward, two-call and fused forms) against the oracle's decode;
+* densification: statistic, plan (actions and offsets exact), expansion (exact copies), split children
+  (mean offset and scale change) against oracle/densify.py on the same float32 inputs; then the whole stage on
+  a fitter, whose children decode like their parents.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from _helpers import cams_small, rel_l2, small_scene, to_dev
+from oracle import decode as OD
+from oracle import densify as ODS
+from oracle import philox as PX
+from paper_2412_04469_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qgm():
+    from paper_2412_04469_amd import qg, raster
+    qg.lib()
+    return qg, raster
+
+
+@pytest.mark.parametrize("n,seed,step", [(1, 0, 0), (5000, 2412, 7), (100003, (1 << 40) + 5, 123456)])
+def test_gate_noise_matches_oracle(qgm, n, seed, step):
+    qg, _ = qgm
+    out = torch.empty(n, device="cuda")
+    qg.qg_gate_noise(n, seed, step, out)
+    st = torch.tensor([step, 0, 0, 0], dtype=torch.int32, device="cuda")
+    out2 = torch.empty(n, device="cuda")
+    qg.qg_gate_noise(n, seed, -1, out2, step_state=st)  # the device counter wins over the host step
+    torch.cuda.synchronize()
+    ref = OD.logistic_noise(PX.gate_uniforms(n, seed, step)).numpy()
+    g = out.cpu().numpy().astype(np.float64)
+    assert np.abs(g - ref).max() <= 2e-6 * max(1.0, np.abs(ref).max())
+    assert torch.equal(out, out2)
+
+
+def test_stochastic_gate_decode_parity(qgm):
+    qg, raster = qgm
+    n = 3001
+    rng = synth.rng_for(81)
+    prev = rng.normal(size=(59, n)).astype(np.float32)
+    lat = rng.normal(0, 1.5, size=(8, n)).astype(np.float32)
+    W1 = (rng.normal(size=(32, 8)) * 0.3).astype(np.float32)
+    W2 = (rng.normal(size=(56, 32)) * 0.2).astype(np.float32)
+    lp = rng.normal(0, 0.1, size=(3, n)).astype(np.float32)
+    a = rng.normal(0, 1.0, size=n).astype(np.float32)
+    hp = (-0.5, 1.01, 0.3)
+    G = rng.normal(size=(59, n)).astype(np.float32)
+    d = {k: to_dev(x) for k, x in dict(prev=prev, lat=lat, W1=W1, W2=W2, lp=lp, a=a, G=G).items()}
+    noise = torch.empty(n, device="cuda")
+    qg.qg_gate_noise(n, 17, 3, noise)
+    out = torch.empty_like(d["prev"])
+    gate = torch.empty(n, device="cuda")
+    qg.qg_decode_residuals(n, n, d["prev"], d["lat"], 8, d["W1"], d["W2"], 32, 56, d["lp"], d["a"], *hp, out, gate,
+                           gate_noise=noise)
+    grads = [torch.zeros_like(d[k]) for k in ("lat", "W1", "W2", "lp", "a")]
+    wsb = qg.qg_decode_bwd_workspace_size(n, 8, 32, 56)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    qg.qg_decode_residuals_bwd(n, n, d["lat"], 8, d["W1"], d["W2"], 32, 56, d["lp"], d["a"], *hp, d["G"], 0.01,
+                               *grads, ws, wsb, gate_noise=noise)
+    torch.cuda.synchronize()
+    e = torch.tensor(noise.cpu().numpy().astype(np.float64))
+    t = lambda x: torch.tensor(x.astype(np.float64), requires_grad=True)
+    tl, tW1, tW2, tlp, ta = t(lat), t(W1), t(W2), t(lp), t(a)
+    ref, g_ref, lreg = OD.decode(torch.tensor(prev.astype(np.float64)), tl, tW1, tW2, tlp, ta, *hp, noise=e)
+    ((ref * torch.tensor(G.astype(np.float64))).sum() + 0.01 * lreg).backward()
+    np.testing.assert_allclose(gate.cpu().numpy(), g_ref.detach().numpy(), rtol=1e-6, atol=2e-7)
+    rn = ref.detach().numpy()
+    assert (np.abs(out.cpu().numpy() - rn) / (np.abs(rn - prev) + np.abs(prev) + 1.0)).max() < 2e-6
+    for name, gg, rr in zip(("lat", "W1", "W2", "lp", "a"), grads, (tl, tW1, tW2, tlp, ta)):
+        assert rel_l2(gg.cpu().numpy(), rr.grad.numpy()) <= 1e-5, name
+    # the noisy gate differs from the deterministic one, and the fused forward agrees with the two-call one
+    g_det = OD.gate(torch.tensor(a.astype(np.float64)), *hp).numpy()
+    assert np.abs(gate.cpu().numpy() - g_det).max() > 0.1
+    cams = cams_small(64, 48)
+    r = raster.Rasterizer(n, cams)
+    out2 = torch.empty_like(out)
+    qg.qg_decode_project(n, n, d["prev"], d["lat"], 8, d["W1"], d["W2"], 32, 56, d["lp"], d["a"], *hp, 3, r.qcams,
+                         r.tile, r.dilation, r.t_proj, out2, gate_noise=noise)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+
+
+def _densify_inputs(n, rng):
+    prev = rng.normal(size=(59, n)).astype(np.float32)
+    dec = (prev + rng.normal(0, 0.1, size=(59, n))).astype(np.float32)
+    dec[7:10] = np.log(rng.uniform(0.005, 0.2, size=(3, n))).astype(np.float32)
+    dec[10] = rng.normal(0, 3.0, size=n).astype(np.float32)  # some opacities below 0.005
+    accum = rng.uniform(0, 0.01, size=n).astype(np.float32)
+    count = rng.integers(0, 6, size=n).astype(np.float32)
+    return prev, dec, accum, count
+
+
+def test_densify_kernels_against_oracle(qgm):
+    qg, _ = qgm
+    n = 20011
+    rng = np.random.default_rng(5)
+    prev, dec, accum, count = _densify_inputs(n, rng)
+    thr, max_scale = 0.00125, 0.05
+    # the statistic of one view
+    gxy = rng.normal(0, 1e-3, size=(2, n)).astype(np.float32)
+    nt = rng.integers(0, 3, size=n).astype(np.int32)
+    d_acc, d_cnt = to_dev(accum), to_dev(count)
+    qg.qg_densify_accumulate(n, to_dev(gxy), to_dev(nt, torch.int32), 676.0, 507.0, d_acc, d_cnt)
+    torch.cuda.synchronize()
+    r_acc, r_cnt = ODS.accumulate(accum, count, gxy, nt, 676.0, 507.0)
+    np.testing.assert_allclose(d_acc.cpu().numpy(), r_acc, rtol=2e-6)
+    assert np.array_equal(d_cnt.cpu().numpy(), r_cnt)
+    # the plan from identical float32 inputs
+    acc32, cnt32 = d_acc.cpu().numpy(), d_cnt.cpu().numpy()
+    act = torch.empty(n, dtype=torch.uint8, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    wsb = qg.qg_densify_plan_workspace_size(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    d_dec = to_dev(dec)
+    qg.qg_densify_plan(n, d_acc, d_cnt, d_dec, n, thr, max_scale, ODS.MIN_OPACITY, act, off, ws, wsb)
+    torch.cuda.synchronize()
+    r_act = ODS.plan(acc32, cnt32, dec[7:10], dec[10], thr, max_scale)
+    g_act = act.cpu().numpy().astype(np.int64)
+    assert np.array_equal(g_act, r_act)
+    k = ODS.children(r_act)
+    assert np.array_equal(off.cpu().numpy(), np.concatenate([[0], np.cumsum(k)]))
+    print("actions:", np.bincount(r_act, minlength=4).tolist())
+    assert (np.bincount(r_act, minlength=4) > 50).all()
+    n2 = int(off[n].item())
+    # expansion and split against the oracle's stage on the same inputs
+    params = [rng.normal(size=(8, n)).astype(np.float32), rng.normal(size=(3, n)).astype(np.float32),
+              rng.normal(size=(1, n)).astype(np.float32)]
+    moments = [rng.normal(size=(8, n)).astype(np.float32), rng.uniform(size=(8, n)).astype(np.float32)]
+    r_prev, r_par, r_mom, parent = ODS.apply(r_act, prev, dec, params, moments, seed=99, rnd=3)
+    assert len(parent) == n2
+    d_prev2 = torch.empty(59, n2, device="cuda")
+    qg.qg_densify_expand(n, act, off, 59, to_dev(prev), n, d_prev2, n2, 0)
+    qg.qg_densify_split(n, act, off, d_dec, n, 99, 3, d_prev2, n2)
+    outs = []
+    for arr, mode in [(p, 0) for p in params] + [(m, 1) for m in moments]:
+        dst = torch.empty(arr.shape[0], n2, device="cuda")
+        qg.qg_densify_expand(n, act, off, arr.shape[0], to_dev(arr), n, dst, n2, mode)
+        outs.append(dst)
+    torch.cuda.synchronize()
+    for got, want in zip(outs, r_par + r_mom):
+        assert np.array_equal(got.cpu().numpy(), want.astype(np.float32))
+    gp = d_prev2.cpu().numpy()
+    split = r_act[parent] == ODS.SPLIT
+    assert np.array_equal(gp[:, ~split], r_prev[:, ~split].astype(np.float32))
+    assert np.array_equal(gp[3:7, split], r_prev[3:7, split].astype(np.float32))
+    assert np.array_equal(gp[10:, split], r_prev[10:, split].astype(np.float32))
+    np.testing.assert_allclose(gp[7:10, split], r_prev[7:10, split], atol=1e-6)
+    off_g = gp[0:3, split] - prev[0:3, parent[split]]
+    off_r = r_prev[0:3, split] - prev[0:3, parent[split]]
+    assert rel_l2(off_g, off_r) <= 1e-5
+    assert np.abs(off_g - off_r).max() <= 1e-5 * max(1.0, np.abs(off_r).max())
+
+
+def test_densify_stage_on_a_fitter(qgm):
+    """Steps accumulate the statistic; the stage's new fitter decodes every kept or cloned child exactly like
+    its parent and every split child like the split of its parent."""
+    qg, raster = qgm
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, camera_extent, densify_fitter
+    sc = small_scene(seed=83, n=4000, ls_mu=-3.0)
+    cams = cams_small(128, 96)
+    cfg = FitConfig(densify=True, densify_threshold=2e-5, stochastic_gate=True)
+    prev = to_dev(sc.planes())
+    moved = sc.planes().copy()
+    moved[0:3] += np.random.default_rng(1).normal(0, 0.05, size=(3, sc.n)).astype(np.float32)
+    gts = []
+    for c in cams:
+        r = raster.Rasterizer(sc.n, [c])
+        r.forward(to_dev(moved))
+        gts.append(r.images[0].clone())
+    f = FrameFitter(prev, cams, gts, cfg)
+    f.size_capacity()
+    for i in range(12):
+        f.step(i % len(cams))
+    torch.cuda.synchronize()
+    assert f.d_count.sum().item() > 0 and f.d_accum.sum().item() > 0
+    # a threshold at the median score of the visited Gaussians, so that the stage has work of every kind
+    acc, cnt = f.d_accum.cpu().numpy().astype(np.float64), f.d_count.cpu().numpy().astype(np.float64)
+    score = acc[cnt > 0] / cnt[cnt > 0]
+    cfg = dataclasses.replace(cfg, densify_threshold=float(np.median(score)))
+    f.cfg = cfg
+    f.decode()
+    dec_parent = f.attrs.cpu().numpy().astype(np.float64)
+    extent = camera_extent(cams)
+    ref_act = ODS.plan(f.d_accum.cpu().numpy(), f.d_count.cpu().numpy(), dec_parent[7:10], dec_parent[10],
+                       cfg.densify_threshold, cfg.percent_dense * extent)
+    g, counts = densify_fitter(f, extent, rnd=0)
+    torch.cuda.synchronize()
+    print("densify:", counts)
+    assert counts["n_after"] == int(ODS.children(ref_act).sum()) == g.n
+    assert counts["clone"] + counts["split"] > 0
+    parent = np.repeat(np.arange(sc.n), ODS.children(ref_act))
+    g.decode()
+    dec_child = g.attrs.cpu().numpy().astype(np.float64)
+    split = ref_act[parent] == ODS.SPLIT
+    assert np.array_equal(dec_child[:, ~split], dec_parent[:, parent[~split]])
+    np.testing.assert_allclose(dec_child[7:10, split], dec_parent[7:10, parent[split]] - math.log(1.6), atol=1e-5)
+    # the new fitter steps on (capacity sized, graphs not involved) and its statistic starts at zero
+    assert g.d_count.sum().item() == 0
+    for i in range(4):
+        g.step(i % len(cams))
+    torch.cuda.synchronize()
+    assert np.isfinite(g.loss_value())

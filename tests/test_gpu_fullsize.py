@@ -8,6 +8,8 @@
 * The dense-overlap workload (1 M Gaussians, log-scales N(-3, 0.5), 4 views at 1920x1080, one multi-view call):
   sampled pixels and attribute gradients against the oracle, no capacity overflow.
 * Its 2 k-Gaussian 64x64 sub-scene: whole-image attribute gradients against the oracle.
+* The batched 12-view workload (500 k Gaussians at three resolutions) in one multi-view call per step: sampled
+  pixels of three views and the residual-parameter gradients of a sparse image gradient over them.
 Pixels whose oracle decision margin is below the usual thresholds are left out (and counted).
 """
 import numpy as np
@@ -28,7 +30,9 @@ def _candidates(rng, cam, m):
 
 
 def _keep(ref):
-    return (ref["margin"] >= MARGIN_FWD) & (ref["order_margin"] >= MARGIN_ORDER)
+    k = (ref["margin"] >= MARGIN_FWD) & (ref["order_margin"] >= MARGIN_ORDER)
+    print(f"[margins] {int(k.size - k.sum())} of {k.size} pixels excluded", flush=True)
+    return k
 
 
 def _groups(g):
@@ -157,3 +161,67 @@ def test_dense_subscene_whole_image_gradients():
     gg, gr = _groups(g.cpu().numpy()), _groups(tp.grad.numpy())
     for k in gg:
         assert rel_l2(gg[k], gr[k]) <= 1e-3, (k, rel_l2(gg[k], gr[k]))
+
+
+def test_batched_workload_fullsize_sampled_parity():
+    """The 12-view batched step at full size (500 k Gaussians; views at 1352x1014, 1920x1080 and 960x540) in the
+    launch configuration the benchmark times (one fused decode+projection, one binning, one blend and one fused
+    adjoint for all twelve views): sampled pixels of one view of each resolution against the oracle, and the
+    residual-parameter gradients of a sparse image gradient spread over those three views."""
+    from paper_2412_04469_amd import qg
+    from paper_2412_04469_amd.fit import BatchedFitter, FitConfig
+    wl = synth.workload_batched()
+    n = wl.scene.n
+    cfg = FitConfig()
+    rng = np.random.default_rng(17)
+    prev = wl.scene.planes()
+    lat = rng.normal(0, 1.0, (8, n)).astype(np.float32)
+    lp = rng.normal(0, 0.01, (3, n)).astype(np.float32)
+    a = rng.normal(0, 1.0, n).astype(np.float32)
+    gts = [torch.zeros(3, c.height, c.width, device="cuda") for c in wl.cams]
+    f = BatchedFitter(to_dev(prev), wl.cams, gts, cfg, persistent=False, graph=False)
+    assert len(f.groups) == 1 and len(f.groups[0]) == 12
+    f.lat.copy_(to_dev(lat))
+    f.lp.copy_(to_dev(lp))
+    f.a.copy_(to_dev(a))
+    f.size_capacity()
+    r = f.rasts[0]
+    hp = (cfg.gamma0, cfg.gamma1, cfg.tau)
+    qg.qg_decode_project(n, f.ld, f.prev, f.lat, 8, f.W1, f.W2, 32, 56, f.lp, f.a, *hp, cfg.sh_degree, r.qcams, r.tile,
+                         cfg.dilation, r.t_proj, f.attrs, f.gate, None)
+    r.bin()
+    assert not r.overflowed()
+    r.render()
+    torch.cuda.synchronize()
+    t = {k: torch.tensor(v.astype(np.float64), requires_grad=True)
+         for k, v in (("lat", lat), ("W1", f.W1.cpu().numpy()), ("W2", f.W2.cpu().numpy()), ("lp", lp), ("a", a))}
+    attrs, _, lreg = OD.decode(torch.tensor(prev.astype(np.float64)), t["lat"], t["W1"], t["W2"], t["lp"], t["a"], *hp)
+    Gs = [torch.zeros(3, c.height, c.width, device="cuda") for c in wl.cams]
+    picks = []
+    for v in (0, 1, 3):  # 1352x1014, 1920x1080, 960x540
+        cam = wl.cams[v]
+        px, py = _candidates(rng, cam, 160)
+        ref = OR.render(attrs.detach(), cam, cfg.bg, pixels=(px + 0.5, py + 0.5))
+        keep = _keep(ref)
+        print(f"view {v} ({cam.width}x{cam.height}): {int((~keep).sum())} of {keep.size} sampled pixels excluded")
+        assert keep.mean() > 0.95, keep.mean()
+        got = r.images[v].cpu().numpy()[:, py, px].T
+        assert np.abs(got - ref["color"])[keep].max() <= 1e-4
+        assert np.abs(r.tfinal[v].cpu().numpy()[py, px] - ref["t_final"])[keep].max() <= 1e-4
+        sel = np.flatnonzero(keep)[:48]
+        gsel = rng.choice([-1.0, 1.0], size=(len(sel), 3))
+        Gs[v][:, py[sel], px[sel]] = torch.tensor(gsel.T, dtype=torch.float32, device="cuda")
+        picks.append((cam, px[sel], py[sel], gsel))
+    lam = cfg.lambda_reg
+    qg.qg_render_decode_bwd(n, f.ld, f.prev, f.lat, 8, f.W1, f.W2, 32, 56, f.lp, f.a, *hp, lam, cfg.sh_degree,
+                            r.qcams, r.tile, cfg.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last, Gs,
+                            f.grads["lat"], f.grads["W1"], f.grads["W2"], f.grads["lp"], f.grads["a"], None, None,
+                            f.fws, f.fws_bytes, attrs=f.attrs)
+    torch.cuda.synchronize()
+    leaf = attrs.detach().clone().requires_grad_(True)  # the three views' gradients, then one pass through decode
+    for cam, px, py, gsel in picks:
+        OR.render(leaf, cam, cfg.bg, pixels=(px + 0.5, py + 0.5), grad_image=gsel)
+    ((attrs * leaf.grad).sum() + lam * lreg).backward()
+    for k in ("lat", "W1", "W2", "lp", "a"):
+        err = rel_l2(f.grads[k].cpu().numpy(), t[k].grad.numpy())
+        assert err <= 1e-3, (k, err)

@@ -54,6 +54,7 @@ def test_dynamic_mask_parity(qgm, tile):
         got = masks[v].cpu().numpy()
         assert set(np.unique(got)) <= {0, 1}
         keep = r["margin"] >= MARGIN_FWD
+        print(f"[margins] view {v}: {int(keep.size - keep.sum())} of {keep.size} pixels excluded", flush=True)
         assert keep.mean() > 0.99, keep.mean()
         assert np.array_equal(got.astype(bool)[keep], want[keep])
         assert 0.05 < want.mean() < 0.95, want.mean()

@@ -42,3 +42,28 @@ def test_fitter_does_not_alias_its_initial_attributes():
     f.reset_frame(prev_attrs=torch.as_tensor(wl.target_scene.planes()).cuda())
     torch.cuda.synchronize()
     assert torch.equal(A0, keep)
+
+
+def test_proposal_reaches_the_plain_target_in_fewer_iterations():
+    """What the trained residual proposal gains: on a small dynamic scene (10% of the Gaussians on sinusoids),
+    the network is trained on the plain fits of frames 1-8 and judged on frames 9-16; proposal-initialised
+    frames reach each frame's plain target PSNR in fewer optimiser iterations on average than the plain,
+    zero-initialised fit.  Iterations are counted (not time), with the adjoints in deterministic mode so the
+    counts do not depend on the order of float atomics."""
+    from paper_2412_04469_amd import qg, stream, synth
+    from paper_2412_04469_amd.fit import FitConfig
+    qg.qg_set_deterministic(True)
+    try:
+        wl = synth.workload_dynamic(n=20000, n_views=8, width=160, height=120)
+        seq = stream.Sequence(wl, FitConfig(), torch.device("cuda"))
+        recs, hist = stream.run_plain(seq, 16, iters=120, check_every=5)
+        prop, losses, _ = stream.train_proposal(hist, list(range(1, 9)), steps=400, batch=16384)
+        assert losses[-1][1] < losses[0][1]
+        judged = stream.judge(seq, hist, recs, prop, list(range(9, 17)), iters=120, check_every=5)
+        s = stream.summarize(recs, judged, list(range(9, 17)))
+        print("proposal:", s, flush=True)
+        assert s["frames_reaching_target"] == 8
+        assert s["frames_using_proposal"] >= 6
+        assert s["mean_iters_to_target"] < s["plain_mean_iters_to_target"]
+    finally:
+        qg.qg_set_deterministic(False)

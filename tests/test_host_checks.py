@@ -52,3 +52,15 @@ def test_fitters_and_stream_reject_a_failed_sort():
     ff.rast.num_pairs[0] = ff.rast.capacity + 5000  # a true overflow grows the buffers instead
     want = ff.rast.capacity + 5000
     assert S._check_capacity(ff) and ff.rast.capacity >= want
+
+
+def test_attribute_fitter_builds_its_tables_on_the_host():
+    from paper_2412_04469_amd.fit import AttributeFitter
+    cams, prev, gts = _setup(n=40, views=2)
+    f = AttributeFitter(prev, cams, gts, FitConfig(), graph=False)
+    assert len(f.adam_segs) == 5
+    ld = prev.shape[1]
+    assert [f.adam_segs[k].count for k in range(5)] == [3 * ld, 4 * ld, 3 * ld, ld, 48 * ld]
+    f.rast.num_pairs[0] = -1
+    with pytest.raises(qg.QGError):
+        f.overflowed()
