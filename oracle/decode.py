@@ -9,6 +9,8 @@ Readings (listed in the design notes):
     * rounding is round-half-to-even (torch.round);
     * the decoder is one shared bias-free two-layer MLP with SiLU, latent 8 -> hidden 32 -> 56 outputs
       (rotation 4, log-scale 3, opacity logit 1, SH 48), so zero latents decode to a zero residual;
+      paper mode (linear_decode) is Eq. 5 as written: one linear decoder per category with the latent
+      dimensions of the quantisation table;
     * residuals are added in the stored parameter space (mean, raw quaternion, log-scale, logit, SH);
     * L_reg is the mean over Gaussians (``reduction='sum'`` gives Eq. 8 literally);
     * the gate is deterministic as Eq. 6 is written (no noise sample).  A stochastic flag follows the hard
@@ -53,6 +55,38 @@ def gate(a: torch.Tensor, gamma0: float, gamma1: float, tau: float, noise=None) 
 def l_reg(a: torch.Tensor, gamma0: float, gamma1: float, tau: float, reduction: str = "mean") -> torch.Tensor:
     p = torch.sigmoid(a - tau * math.log(-gamma0 / gamma1))
     return p.mean() if reduction == "mean" else p.sum()
+
+
+# Paper mode (Eq. 5 as written, Sec. 3.2.1 and the quantisation table): one shared linear decoder per attribute
+# category, r_c = D_c rint(l_c), with the table's latent dimensions (N3DV: rotation 6, scaling 8, opacity 3,
+# colour base 8, colour frequencies 4; Immersive has 12 for the frequencies).  Output planes of each category
+# in the 59-plane layout: rotation 3..6, scaling 7..9, opacity 10, colour base (SH degree 0) 11..13, colour
+# frequencies (higher SH) 14..58.
+PAPER_CATEGORIES = (("rotation", 3, 4), ("scaling", 7, 3), ("opacity", 10, 1), ("color_base", 11, 3),
+                    ("color_freq", 14, 45))
+PAPER_DIMS_N3DV = (6, 8, 3, 8, 4)
+PAPER_DIMS_IMMERSIVE = (6, 8, 3, 8, 12)
+
+
+def linear_decode(latents: torch.Tensor, Ds, dims=PAPER_DIMS_N3DV) -> torch.Tensor:
+    """Residual planes [56, N] (planes 3..58) of latents [sum(dims), N] through the per-category decoders
+    Ds = [D_c [M_c, L_c]] (straight-through rounding of the latents)."""
+    l = ste_round(latents)
+    out, k = [], 0
+    for (name, plane, M), L, D in zip(PAPER_CATEGORIES, dims, Ds):
+        assert tuple(D.shape) == (M, L), (name, tuple(D.shape))
+        out.append(D @ l[k:k + L])
+        k += L
+    return torch.cat(out, 0)
+
+
+def decode_linear(prev: torch.Tensor, latents: torch.Tensor, Ds, l_p: torch.Tensor, a: torch.Tensor,
+                  gamma0: float, gamma1: float, tau: float, dims=PAPER_DIMS_N3DV, noise=None):
+    """Paper-mode decode: as decode() with the per-category linear decoders.  Returns (attrs, g, L_reg mean)."""
+    r = linear_decode(latents, Ds, dims)
+    g = gate(a, gamma0, gamma1, tau, noise)
+    out = prev + torch.cat([g[None, :] * l_p, r], 0)
+    return out, g, l_reg(a, gamma0, gamma1, tau)
 
 
 def decode(prev: torch.Tensor, latents: torch.Tensor, W1: torch.Tensor, W2: torch.Tensor, l_p: torch.Tensor,

@@ -203,3 +203,42 @@ def test_adam_matches_torch():
         opt.step()
         th, m, v = A.adam_step(th, g, m, v, step, 0.05)
     np.testing.assert_allclose(th, t_th.detach().numpy(), rtol=1e-13, atol=1e-14)
+
+
+def test_paper_mode_linear_decoder():
+    """Eq. 5 as written: r_c = D_c rint(l_c) per category, the quantisation table's latent dimensions; pinned by
+    torch.nn.functional.linear per block, the block structure (a category's latents move only its own planes),
+    zero latents -> zero residual, and the straight-through gradient."""
+    import torch.nn.functional as F
+    dims = D.PAPER_DIMS_N3DV
+    assert sum(dims) == 29 and sum(D.PAPER_DIMS_IMMERSIVE) == 37
+    assert [m for _, _, m in D.PAPER_CATEGORIES] == [4, 3, 1, 3, 45]
+    assert [p for _, p, _ in D.PAPER_CATEGORIES] == [3, 7, 10, 11, 14]
+    rng = np.random.default_rng(3)
+    n = 50
+    lat = torch.tensor(rng.normal(0, 2, size=(29, n)), requires_grad=True)
+    Ds = [torch.tensor(rng.normal(size=(m, L)), requires_grad=True) for (_, _, m), L in zip(D.PAPER_CATEGORIES, dims)]
+    r = D.linear_decode(lat, Ds, dims)
+    assert r.shape == (56, n)
+    lr = torch.round(lat.detach())
+    ref, k = [], 0
+    for (_, _, m), L, Dc in zip(D.PAPER_CATEGORIES, dims, Ds):
+        ref.append(F.linear(lr[k:k + L].T, Dc.detach()).T)
+        k += L
+    assert torch.allclose(r, torch.cat(ref, 0), rtol=1e-14, atol=1e-12)
+    # block structure: the opacity latents (rows 14..16) move only plane 10 (row 7 of the residual)
+    lat2 = lat.detach().clone()
+    lat2[14:17] += 3.0
+    r2 = D.linear_decode(lat2, [d.detach() for d in Ds], dims)
+    diff = (r2 - r.detach()).abs().sum(1)
+    assert diff[7] > 0 and diff[:7].sum() == 0 and diff[8:].sum() == 0
+    assert D.linear_decode(torch.zeros(29, 4, dtype=torch.float64), Ds, dims).abs().max() == 0
+    # straight-through gradients: dL/dl_c = D_c^T dL/dr_c, dL/dD_c = dL/dr_c rint(l_c)^T
+    G = torch.tensor(rng.normal(size=(56, n)))
+    (r * G).sum().backward()
+    k, row = 0, 0
+    for (_, _, m), L, Dc in zip(D.PAPER_CATEGORIES, dims, Ds):
+        assert torch.allclose(lat.grad[k:k + L], Dc.detach().T @ G[row:row + m], rtol=1e-12)
+        assert torch.allclose(Dc.grad, G[row:row + m] @ lr[k:k + L].T, rtol=1e-12)
+        k += L
+        row += m
