@@ -83,14 +83,15 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-pixels", type=int, default=8192)
     p.add_argument("--tile", default="16x16", choices=["8x8", "16x16", "32x8"])
-    p.add_argument("--batch", type=int, default=0, choices=[0, 32, 64, 128], help="blend LDS batch depth")
+    p.add_argument("--batch", type=int, default=0, choices=[0, 32, 64, 128, 256], help="blend LDS batch depth")
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-view step")
     p.add_argument("--no-frame", action="store_true", help="skip the sec/frame measurement")
     p.add_argument("--no-masked", action="store_true", help="skip the masked-training measurement")
-    p.add_argument("--proposal-batched-views", type=int, default=4,
-                   help="views per step of the proposal's batched form (0: --batched-views)")
-    p.add_argument("--proposal-batched-lr-scale", type=float, default=2.5,
-                   help="learning-rate factor of the proposal's batched form (0: --batched-lr-scale)")
+    p.add_argument("--proposal-batched-views", type=int, default=0,
+                   help="views per step of the proposal's batched form (0: the grouping the autotuner chose on the "
+                        "fit workload's frame, else 4)")
+    p.add_argument("--proposal-batched-lr-scale", type=float, default=0.0,
+                   help="learning-rate factor of the proposal's batched form (0: the autotuner's, else 2.5)")
     p.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM step measurement")
     p.add_argument("--mask-fraction", type=float, default=0.65,
                    help="fraction of a frame's iterations that are masked (0.30 N3DV, 0.65 Immersive)")
@@ -98,17 +99,20 @@ def parse():
                    help="score threshold of the dynamic split for the synthetic localised-change workload")
     p.add_argument("--batched-steps", type=int, default=20)
     p.add_argument("--tune", default="full", choices=["full", "quick", "none"],
-                   help="blend autotuning of the batched step: all 18 candidates, 6, or the default only")
+                   help="blend autotuning of the batched step: all 24 candidates, 6, or the default only")
+    p.add_argument("--tune-cache", default="", help="JSON file of cached blend-schedule choices (read and written)")
     p.add_argument("--frame-iters", type=int, default=500)
     p.add_argument("--proposal", default="both", choices=["none", "single", "both"],
                    help="learned-proposal experiment: skip, judge with one view per step, or also batched")
     p.add_argument("--proposal-frames", type=int, default=50)
-    p.add_argument("--batched-views", type=int, default=16,
-                   help="views per batched optimiser step in the sec/frame sections (16: all 20 views in two groups)")
+    p.add_argument("--batched-views", type=int, default=0,
+                   help="views per batched optimiser step in the sec/frame section (0: the grouping autotuner "
+                        "picks views per step and learning-rate factor on this frame)")
     p.add_argument("--batched-lr-scale", type=float, default=1.0,
                    help="learning-rate factor of the batched steps in the sec/frame sections")
     p.add_argument("--no-configs", action="store_true", help="skip the small and dense-overlap workload steps")
     p.add_argument("--no-densify", action="store_true", help="skip the per-frame densification measurement")
+    p.add_argument("--no-paper-decoder", action="store_true", help="skip the paper-mode decoder measurement")
     p.add_argument("--config-steps", type=int, default=20, help="timed steps of the small and dense workloads")
     p.add_argument("--oracle-small-reps", type=int, default=10)
     p.add_argument("--oracle-small-only", action="store_true", help=argparse.SUPPRESS)
@@ -248,7 +252,9 @@ def batched_section(args):
         cands = [dict(tile=t, batch=64, persistent=p) for t in ((16, 16), (8, 8), (32, 8)) for p in (False, True)]
     else:
         cands = [dict(tile=(16, 16), batch=64, persistent=True)]
-    best, table = autotune(make, cands, steps=5, warmup=1, log=log)
+    from paper_2412_04469_amd.autotune import cache_key
+    best, table = autotune(make, cands, steps=5, warmup=1, log=log, cache_path=args.tune_cache or None,
+                           key=cache_key(wl.cams, wl.scene.n))
     f = make(**best)
     ms = time_steps(f, args.batched_steps, 3)
     overflow = f.overflowed()
@@ -453,27 +459,45 @@ def frame_section(args):
     log(f"frame: render {fps['fps_median']} FPS")
     del plain
     torch.cuda.empty_cache()
-    bcfg = dataclasses.replace(cfg, group_views=args.batched_views, batched_lr_scale=args.batched_lr_scale)
-    bat = BatchedFitter(prev, wl.cams, gts, bcfg, persistent=True, eval_cam=held)
-    bat.size_capacity()
-    w0 = (bat.W1.clone(), bat.W2.clone())
-    for _ in bat.groups:  # every view group's step captured; the decoder is put back to its initial weights below
-        bat.step()
-    bat.W1.copy_(w0[0])
-    bat.W2.copy_(w0[1])
-    vps = max(len(g) for g in bat.groups)
-    traj_b, hit_b = _fit_to_target(bat, lambda i: bat.step(), args.frame_iters, 25, held, gt_held, gate_fn,
-                                   target=tgt)
-    log(f"frame: batched {'reaches target at %.3f s' % hit_b if hit_b else 'does not reach the target'}")
-    ovf = bat.overflowed()
-    del bat
-    torch.cuda.empty_cache()
+    runs = {}
+
+    def run_batched(views, lr):
+        bcfg = dataclasses.replace(cfg, group_views=views, batched_lr_scale=lr)
+        bat = BatchedFitter(prev, wl.cams, gts, bcfg, persistent=False, eval_cam=held)
+        bat.size_capacity()
+        w0 = (bat.W1.clone(), bat.W2.clone())
+        for _ in bat.groups:  # every view group's step captured; the decoder goes back to its initial weights
+            bat.step()
+        bat.W1.copy_(w0[0])
+        bat.W2.copy_(w0[1])
+        vps = max(len(g) for g in bat.groups)
+        traj_b, hit_b = _fit_to_target(bat, lambda i: bat.step(), args.frame_iters, 25, held, gt_held, gate_fn,
+                                       target=tgt)
+        runs[(views, lr)] = {"sec_per_frame": None if hit_b is None else round(hit_b, 4), "views_per_step": vps,
+                             "lr_scale": lr, "trajectory": traj_b, "overflow": bat.overflowed()}
+        del bat
+        torch.cuda.empty_cache()
+        return hit_b
+
+    if args.batched_views > 0:
+        groupings = [(args.batched_views, args.batched_lr_scale)]
+    else:
+        from paper_2412_04469_amd.autotune import tune_grouping
+        groupings = None
+    if groupings is None:
+        best, table = tune_grouping(run_batched, log=lambda m: log("frame: " + m))
+    else:
+        best, table = groupings[0], [(groupings[0][0], groupings[0][1], run_batched(*groupings[0]))]
+    chosen = best if best is not None else (table[0][0], table[0][1])
+    rb = runs[chosen]
+    log(f"frame: batched {chosen} {'reaches target at %.3f s' % rb['sec_per_frame'] if rb['sec_per_frame'] else 'does not reach the target'}")
     return {"workload": wl.name, "target_psnr_db": tgt, "iterations_plain": args.frame_iters,
             "storage_plain": storage, "render": fps,
             "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p},
-            "batched": {"sec_per_frame": None if hit_b is None else round(hit_b, 4),
-                        "views_per_step": vps, "lr_scale": args.batched_lr_scale,
-                        "trajectory": traj_b, "overflow": ovf},
+            "batched": rb,
+            "grouping_table": [{"views_per_step": v, "lr_scale": l, "sec_per_frame": None if t is None else round(t, 4)}
+                               for v, l, t in table],
+            "grouping_best": None if best is None else {"views_per_step": best[0], "lr_scale": best[1]},
             "protocol": "frame clock from gate initialisation (20 forward + 20 adjoint passes) through the optimiser "
                         "steps; held-out PSNR every 25 steps with the clock paused"}
 
@@ -542,6 +566,50 @@ def densify_section(args, target):
             "sec_per_frame": traj[-1][1], "final_psnr_db": traj[-1][2], "trajectory": traj,
             "protocol": "frame clock from gate initialisation through the optimiser steps and densification stages; "
                         "held-out PSNR every 25 steps with the clock paused"}
+
+
+def paper_decoder_section(args, target):
+    """The fit with the paper's own decoder form (Eq. 5 as written: one linear decoder per attribute category, the
+    quantisation table's N3DV latent dimensions and learning rates) through the unfused calls, on the fit workload:
+    ms per step and the frame's seconds to the plain form's target PSNR."""
+    import torch
+    from paper_2412_04469_amd import synth
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, GateInitializer, render_views
+    wl = synth.workload_fit(n=args.n)
+    cfg = FitConfig(decoder="linear")
+    dev = torch.device("cuda")
+    prev = torch.as_tensor(wl.scene.planes()).to(dev)
+    target_scene = torch.as_tensor(wl.target_scene.planes()).to(dev)
+    gts_prev = render_views(prev, wl.cams, cfg)
+    gts = render_views(target_scene, wl.cams, cfg)
+    held = wl.extras["held_out"]
+    gt_held = render_views(target_scene, [held], cfg)[0]
+    V = len(wl.cams)
+    gi = GateInitializer(wl.scene.n, wl.cams, cfg)
+    gi(prev, gts_prev, gts)
+    f = FrameFitter(prev, wl.cams, gts, cfg)
+    f.size_capacity()
+    order = np.random.default_rng(0)
+    perm = np.concatenate([order.permutation(V) for _ in range(args.frame_iters // V + 2)])
+    traj, hit = _fit_to_target(f, lambda i: f.step(int(perm[i])), args.frame_iters, 25, held, gt_held,
+                               lambda: gi(prev, gts_prev, gts), target=target)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(50):
+        f.step(i % V)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 50
+    log(f"paper decoder: {ms:.4f} ms/step, {'%.3f s to the target' % hit if hit else 'target not reached'}")
+    del f
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "latent_dims": list(cfg.paper_dims), "latent_lrs": list(cfg.paper_latent_lrs),
+            "decoder_lrs": list(cfg.paper_decoder_lrs), "ms_per_step": round(ms, 4), "target_psnr_db": target,
+            "sec_to_target": None if hit is None else round(hit, 4), "final_psnr_db": traj[-1][2], "trajectory": traj,
+            "form": "unfused calls: qg_decode_linear, qg_project, qg_bin, qg_render_fwd, qg_l1_loss, qg_render_bwd, "
+                    "qg_decode_linear_bwd, qg_adam_multi"}
 
 
 def dssim_section(args):
@@ -704,8 +772,9 @@ def proposal_section(args):
                           "used": j["used_proposal"]} for p, j in zip([r for r in recs if r["t"] in judge_frames],
                                                                         judged)]}
     if args.proposal == "both":
-        pv = args.proposal_batched_views or args.batched_views
-        pl = args.proposal_batched_lr_scale or args.batched_lr_scale
+        tuned = getattr(args, "tuned_grouping", None) or {"views_per_step": 4, "lr_scale": 2.5}
+        pv = args.proposal_batched_views or tuned["views_per_step"]
+        pl = args.proposal_batched_lr_scale or tuned["lr_scale"]
         bcfg = dataclasses.replace(FitConfig(), group_views=pv, batched_lr_scale=pl)
         jb = stream.judge(seq, hist, recs, prop, judge_frames, args.frame_iters, 25, batched=True, log=log,
                           batched_cfg=bcfg)
@@ -856,8 +925,11 @@ def main():
         result["batched"] = batched_section(args)
     if not args.no_frame:
         result["sec_per_frame"] = frame_section(args)
+        args.tuned_grouping = result["sec_per_frame"].get("grouping_best")
     if not args.no_densify and "sec_per_frame" in result:
         result["densify"] = densify_section(args, result["sec_per_frame"]["target_psnr_db"])
+    if not args.no_paper_decoder and "sec_per_frame" in result:
+        result["paper_decoder"] = paper_decoder_section(args, result["sec_per_frame"]["target_psnr_db"])
     if not args.no_masked:
         result["masked_training"] = masked_section(args)
     if not args.no_dssim:

@@ -58,19 +58,20 @@ int32_t qg_version(void);
  * Deterministic mode of the adjoints (qg_render_bwd, qg_render_decode_bwd).  Off by default; QG_DETERMINISTIC=1 in
  * the environment turns it on when the library first reads the setting, and qg_set_deterministic(on) overrides
  * that.  In this mode the blend adjoint writes the wave-reduced partial derivatives of each (tile, entry) pair to
- * a per-pair buffer instead of adding them into the Gaussian's record with float atomics; a second kernel then
- * adds each (view, Gaussian)'s pairs in a fixed order (the tiles of its rectangle, row-major), and the fused
- * adjoint keeps one decoder weight-gradient row per 64 Gaussians, summed in a fixed order.  Gradients are then
- * the same bits on every run (and differ from the default mode only in rounding order).
- * Workspace: while the mode is on, both adjoint calls need qg_deterministic_workspace_size(n, capacity) bytes
+ * its own slot (slots of a (view, Gaussian) are consecutive, one per tile of its rectangle in row-major order)
+ * instead of adding them into the Gaussian's record with float atomics; a second kernel then adds each
+ * (view, Gaussian)'s slots in order, and the fused adjoint keeps one decoder weight-gradient row per 64
+ * Gaussians, summed in a fixed order.  Gradients are then the same bits on every run (and differ from the
+ * default mode only in rounding order).
+ * Workspace: while the mode is on, both adjoint calls need qg_deterministic_workspace_size(n, V, capacity) bytes
  * appended to their usual workspace, where capacity is the one passed to the qg_bin call whose tile lists are
- * differentiated (one set of partials per pair slot).  The calls return QG_ERR_ARG if the workspace has no room
- * for them; pair slots at or beyond the room they find are dropped, so size it with the bin capacity.
+ * differentiated (one slot per pair).  The calls return QG_ERR_ARG if the workspace has no room for them;
+ * slots beyond the room they find are dropped, so size it with the bin capacity.
  * The setting is process-wide; change it only while no adjoint call is being enqueued.
  */
 qg_status qg_set_deterministic(int32_t on);
 int32_t qg_get_deterministic(void);
-size_t qg_deterministic_workspace_size(int64_t n, int64_t capacity);
+size_t qg_deterministic_workspace_size(int64_t n, int32_t V, int64_t capacity);
 
 /*
  * Pinhole camera (Sec. 3.1: intrinsics K and viewing transform W), OpenCV axes (x right, y down,
@@ -88,7 +89,7 @@ typedef struct {
 /*
  * How the image plane is cut into tiles and how the blend kernels walk them.
  *   tile_w x tile_h  one of 8x8, 16x16, 32x8.
- *   batch            tile-list entries staged per LDS batch in the blend kernels: 32, 64 or 128 (0 = 64).
+ *   batch            tile-list entries staged per LDS batch in the blend kernels: 32, 64, 128 or 256 (0 = 64).
  *                    Results do not depend on it.
  *   reserved         must be 0.
  *   schedule         optional device buffer written by qg_schedule_tiles for the current binning: the blend
@@ -187,6 +188,34 @@ qg_status qg_decode_residuals_bwd(int64_t n, int64_t ld, const float* latents, i
                                   const float* grad_attrs, float lambda_reg, float* grad_latents, float* grad_W1,
                                   float* grad_W2, float* grad_pos_pre, float* grad_gate_logit, void* ws,
                                   size_t ws_bytes, qg_stream stream);
+
+/*
+ * Paper-mode decode (Eq. 5 as written, Sec. 3.2.1): one shared linear decoder per attribute category,
+ * r_c = D_c rint(l_c), for the categories rotation (4 planes from plane 3), scaling (3 from 7), opacity (1 from
+ * 10), colour base (SH degree 0, 3 from 11) and colour frequencies (higher SH, 45 from 14), with latent dimensions
+ * dims[0..4] ([host]; each in [1, 16]; the paper's quantisation table gives 6, 8, 3, 8, 4 on N3DV and 6, 8, 3, 8,
+ * 12 on Immersive).  latents [sum(dims)][ld] (category by category); D packed category by category, each D_c
+ * row-major [M_c][L_c] (qg_linear_decoder_params(dims) floats).  Everything else (gate, positions, Eq. 8
+ * partials in qg_decode_linear_blocks(n) blocks, gate_noise) as in qg_decode_residuals.
+ */
+int64_t qg_linear_decoder_params(const int32_t* dims);
+int64_t qg_decode_linear_blocks(int64_t n);
+qg_status qg_decode_linear(int64_t n, int64_t ld, const float* prev_attrs, const float* latents, const int32_t* dims,
+                           const float* D, const float* pos_pre, const float* gate_logit, const float* gate_noise,
+                           float gamma0, float gamma1, float tau, float* attrs_out, float* gate_out,
+                           float* lreg_partial, qg_stream stream);
+
+/*
+ * Backward of qg_decode_linear (as qg_decode_residuals_bwd): grad_latents (+=) = D_c^T dL/dr_c (straight-through),
+ * grad_D (+=) = sum over Gaussians of dL/dr_c rint(l_c)^T (block partials in ws, then a fixed-order sum:
+ * deterministic), grad_pos_pre and grad_gate_logit (+=).  ws: qg_decode_linear_bwd_workspace_size(n, dims).
+ */
+size_t qg_decode_linear_bwd_workspace_size(int64_t n, const int32_t* dims);
+qg_status qg_decode_linear_bwd(int64_t n, int64_t ld, const float* latents, const int32_t* dims, const float* D,
+                               const float* pos_pre, const float* gate_logit, const float* gate_noise, float gamma0,
+                               float gamma1, float tau, const float* grad_attrs, float lambda_reg,
+                               float* grad_latents, float* grad_D, float* grad_pos_pre, float* grad_gate_logit,
+                               void* ws, size_t ws_bytes, qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
 /* Projection (Eq. 1) with SH colour.                                                              */
@@ -466,14 +495,20 @@ qg_status qg_densify_expand(int64_t n, const uint8_t* action, const int64_t* off
                             qg_stream stream);
 
 /*
- * Split children, after the expansion of the stored attributes into prev_out [59][ld_out]: child c (0, 1) of a
- * split Gaussian i gets mean += R(q_i) (s_i * z_c) and log-scale -= ln 1.6, with q_i, s_i the parent's decoded
- * rotation (normalised) and scale (decoded [59][ld]) and z_0, z_1 standard normal 3-vectors by Box-Muller
- * (r = sqrt(-2 ln u_even), angle 2 pi u_odd) on the words of Philox(counter (i, round, 0x73706C74, 0)) and
- * Philox(counter (i, round, 0x73706C74, 1)).
+ * Clone and split children, after the expansion of the stored attributes into prev_out [59][ld_out], from the
+ * parents' decoded attributes (decoded [59][ld]):
+ *   clone: both children's opacity logit += logit(o') - logit(o), o the parent's decoded opacity and
+ *          o' = 1 - sqrt(1 - o), so the two coincident copies composite like the parent where its Gaussian factor
+ *          is 1 (the N-copy rule 1 - (1 - o)^(1/N) of Kheradmand et al., 3D Gaussian Splatting as Markov Chain
+ *          Monte Carlo);
+ *   split: child c (0, 1) gets mean += R(q) (s * z_c) and log-scale -= ln 1.6, with q, s the parent's decoded
+ *          rotation (normalised) and scale and z_0, z_1 standard normal 3-vectors by Box-Muller
+ *          (r = sqrt(-2 ln u_even), angle 2 pi u_odd) on the words of Philox(counter (i, round, 0x73706C74, 0))
+ *          and Philox(counter (i, round, 0x73706C74, 1)).
  */
-qg_status qg_densify_split(int64_t n, const uint8_t* action, const int64_t* offsets, const float* decoded, int64_t ld,
-                           uint64_t seed, int32_t round, float* prev_out, int64_t ld_out, qg_stream stream);
+qg_status qg_densify_children(int64_t n, const uint8_t* action, const int64_t* offsets, const float* decoded,
+                              int64_t ld, uint64_t seed, int32_t round, float* prev_out, int64_t ld_out,
+                              qg_stream stream);
 
 /* ---------------------------------------------------------------------------------------------- */
 /* Storage of a frame's residuals (the compression back end after the fit): the quantised latents   */

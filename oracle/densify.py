@@ -11,15 +11,21 @@ stage does is 3D-GS's, read here as:
       (0.01 x the camera extent), and split otherwise; after the stage every statistic restarts at zero;
     * pruning: a Gaussian whose opacity is below 0.005 is removed (3D-GS prunes in the same stage);
     * the new set keeps each Gaussian's children in place, in the order of their parents: a kept Gaussian has
-      one child (itself), a clone two (itself, then an identical copy), a split two, a pruned one none;
+      one child (itself), a clone two (itself, then its copy), a split two, a pruned one none;
     * split children: scale divided by 1.6 (log-scale - ln 1.6) and position p + R(q) (s * z) with z a standard
       normal 3-vector per child, R and s those of the parent; every other attribute is copied;
+    * clone children: two coincident copies of opacity o' = 1 - sqrt(1 - o) (the rule of Kheradmand et al.,
+      "3D Gaussian Splatting as Markov Chain Monte Carlo", for N copies 1 - (1 - o)^(1/N)), so that the pair
+      composites like the parent where its Gaussian factor is 1 (1 - (1 - o')^2 = o); the plain 3D-GS clone
+      copies o unchanged, which doubles the clone's weight and, with residuals that move in quantised steps,
+      leaves it there;
     * QUEEN's residual parameters (latents, pre-gate position residual, gate logit) are copied to every child,
       so a child decodes like its parent; the split's offset and scale change are applied to the stored
       A_{t-1} of the children, so the decoded child is the split of the decoded parent;
     * Adam moments restart at zero for new Gaussians (a clone's copy and both split children); a clone's first
       child and a kept Gaussian keep theirs.
-Pinned by: clones are exact copies; a split with z = 0 keeps the parent's mean; the children's mean offset is
+Pinned by: clones are exact copies apart from the opacity, and two coincident clones composite like their parent
+at its centre; a split with z = 0 keeps the parent's mean; the children's mean offset is
 R(q) (s * z) (rotation of a scaled vector, checked against an explicit rotation matrix built from the
 quaternion's closed form); counts n' = n - pruned + clones + splits; the rank of the schedule's densification
 iterations.
@@ -66,6 +72,12 @@ def children(act):
     return np.where(act == PRUNE, 0, np.where(act == KEEP, 1, 2))
 
 
+def clone_logit(x):
+    """Logit of o' = 1 - sqrt(1 - o) for o = sigmoid(x): log(1 - s) - log(s) with s = sqrt(sigmoid(-x))."""
+    s = math.sqrt(1.0 / (1.0 + math.exp(x)))
+    return math.log1p(-s) - math.log(s)
+
+
 def quat_matrix(q):
     """Rotation matrices [n, 3, 3] of the normalised quaternions q [n, 4] (w, x, y, z), closed form."""
     q = np.asarray(q, np.float64)
@@ -93,6 +105,11 @@ def apply(act, prev, decoded, params, moments, seed, rnd, normals=None):
     new_params = [np.asarray(p)[:, parent].copy() for p in params]
     keepm = ((act[parent] == KEEP) | (act[parent] == CLONE)) & first
     new_moments = [np.where(keepm[None, :], np.asarray(m)[:, parent], 0.0) for m in moments]
+    # clone children: stored logit moved so that the decoded opacity becomes o' = 1 - sqrt(1 - o)
+    for out_j in np.flatnonzero(act[parent] == CLONE):
+        i = int(parent[out_j])
+        x = float(np.asarray(decoded, np.float64)[10, i])
+        new_prev[10, out_j] += clone_logit(x) - x
     split_idx = np.flatnonzero(act == SPLIT)
     if len(split_idx):
         z = philox.split_normals(split_idx, seed, rnd) if normals is None else np.asarray(normals)[split_idx]

@@ -1,4 +1,5 @@
 // Error state, argument tables and small utilities of libqg.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -87,7 +88,7 @@ bool deterministic_mode() {
 bool tiling_ok(qg_tiling t) {
     const bool shape = (t.tile_w == 8 && t.tile_h == 8) || (t.tile_w == 16 && t.tile_h == 16) ||
                        (t.tile_w == 32 && t.tile_h == 8);
-    const bool batch = t.batch == 0 || t.batch == 32 || t.batch == 64 || t.batch == 128;
+    const bool batch = t.batch == 0 || t.batch == 32 || t.batch == 64 || t.batch == 128 || t.batch == 256;
     return shape && batch && t.reserved == 0;
 }
 
@@ -102,7 +103,7 @@ bool make_view_table(const qg_camera* cams, const qg_projected* proj, int32_t V,
         return false;
     }
     if (!tiling_ok(tiling)) {
-        set_error("unsupported tiling %dx%d batch %d (8x8, 16x16, 32x8; batch 0, 32, 64, 128; reserved 0)",
+        set_error("unsupported tiling %dx%d batch %d (8x8, 16x16, 32x8; batch 0, 32, 64, 128, 256; reserved 0)",
                   tiling.tile_w, tiling.tile_h, tiling.batch);
         return false;
     }
@@ -161,6 +162,12 @@ __global__ void k_zero(uint32_t* __restrict__ p, int64_t words) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < words; i += stride) p[i] = 0u;
+}
+
+// 16-byte stores, grid-stride over a capped grid (every lane writes whole uint4s).
+__global__ __launch_bounds__(256) void k_zero16(uint4* __restrict__ p, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
 }
 
 __global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t bytes) {
@@ -233,7 +240,14 @@ extern "C" qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream) {
     QG_REQUIRE(dst != nullptr, "dst is NULL");
     hipStream_t s = (hipStream_t)stream;
     uintptr_t a = (uintptr_t)dst;
-    if (a % 4 == 0 && bytes % 4 == 0) {
+    if (a % 16 == 0 && bytes % 16 == 0) {
+        const int64_t n16 = bytes / 16;
+        const int64_t blocks = std::min<int64_t>(ceil_div(n16, 256), 2048);
+        {
+            QG_TIMED("zero", s);
+            k_zero16<<<(unsigned)blocks, 256, 0, s>>>((uint4*)dst, n16);
+        }
+    } else if (a % 4 == 0 && bytes % 4 == 0) {
         int64_t words = bytes / 4;
         int64_t blocks = std::min<int64_t>(ceil_div(words, 256), 65536);
         {

@@ -324,6 +324,164 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict_
 }
 
 // ------------------------------------------------------------------------------------------------
+// Tile passes: reduce, then scan, then scatter (no waits between workgroups).
+// Block b owns items [b * kRsTile, (b + 1) * kRsTile) in the wave-contiguous layout of k_onesweep.
+//   k_rs_count: the block's digit counts -> cnt[d * nb_cap + b] (digit-major);
+//   k_rs_scan: per digit (one workgroup each), the exclusive scan of its counts over the blocks in place, and
+//              the digit's total;
+//   k_rs_scatter: the block's stable ranks (ballot matching), its digits' output starts (digit base from the
+//              totals + the scanned count of the earlier blocks), ordered through LDS and written by digit runs.
+// ------------------------------------------------------------------------------------------------
+constexpr int kRsIPT = 16;
+constexpr int kRsTile = kRsIPT * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ count_ptr, int pass,
+                                                     uint32_t* __restrict__ cnt, int64_t nb_cap) {
+    __shared__ uint32_t s_h[kRadix];
+    const uint32_t count = *count_ptr;
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kRsTile;
+    if (blk0 >= count) return;
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const uint64_t base = blk0 + (uint64_t)w * (kRsIPT * kWave);
+    const int shift = kRadixBits * pass;
+    uint32_t key[kRsIPT];
+#pragma unroll
+    for (int r = 0; r < kRsIPT; ++r) {
+        const uint64_t idx = base + (uint64_t)r * kWave + lane;
+        key[r] = idx < count ? kin[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRsIPT; ++r) {
+        const uint64_t idx = base + (uint64_t)r * kWave + lane;
+        if (idx < count) hist_add(s_h, (key[r] >> shift) & (kRadix - 1));
+    }
+    __syncthreads();
+    cnt[(size_t)threadIdx.x * nb_cap + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of cnt[d][0 .. nb) in place, nb from the device count; tot[d] = total.
+constexpr int kRsScanThreads = 1024;
+
+__global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(uint32_t* __restrict__ cnt, int64_t nb_cap,
+                                                            const uint32_t* __restrict__ count_ptr,
+                                                            uint32_t* __restrict__ tot) {
+    __shared__ uint32_t s_w[kRsScanThreads / kWave];
+    const int64_t nb = ceil_div((int64_t)*count_ptr, kRsTile);
+    uint32_t* row = cnt + (size_t)blockIdx.x * nb_cap;
+    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kRsScanThreads) {
+        const int64_t b = b0 + tid;
+        const uint32_t x = b < nb ? row[b] : 0u;
+        const uint32_t inc = wave_incl_scan(x);
+        if (lane == kWave - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t wb = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kRsScanThreads / kWave; ++k) {
+            if (k < w) wb += s_w[k];
+            all += s_w[k];
+        }
+        if (b < nb) row[b] = carry + wb + inc - x;
+        carry += all;
+        __syncthreads();
+    }
+    if (tid == 0) tot[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout,
+                                                       const uint32_t* __restrict__ count_ptr, int pass,
+                                                       const uint32_t* __restrict__ cnt, int64_t nb_cap,
+                                                       const uint32_t* __restrict__ tot) {
+    __shared__ uint32_t s_cnt[kWaves][kRadix];
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_goff[kRadix];
+    __shared__ uint32_t s_key[kRsTile], s_val[kRsTile];
+    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
+    const uint32_t count = *count_ptr;
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kRsTile;
+    if (blk0 >= count) return;
+    const uint64_t base = blk0 + (uint64_t)w * (kRsIPT * kWave);
+    uint32_t key[kRsIPT], val[kRsIPT];
+#pragma unroll
+    for (int r = 0; r < kRsIPT; ++r) {
+        const uint64_t idx = base + (uint64_t)r * kWave + lane;
+        const bool valid = idx < count;
+        key[r] = valid ? kin[idx] : 0u;
+        val[r] = valid ? vin[idx] : 0u;
+    }
+    // output start of digit tid before this block: digit base (scan of the totals) + the earlier blocks' count
+    const uint32_t before = cnt[(size_t)tid * nb_cap + blockIdx.x];
+    uint32_t dtot;
+    const uint32_t dbase = block_excl_scan<uint32_t>(tot[tid], s_w, &dtot);
+    const int shift = kRadixBits * pass;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
+    __syncthreads();
+    uint32_t info[kRsIPT];
+#pragma unroll
+    for (int r = 0; r < kRsIPT; ++r) {
+        const uint64_t idx = base + (uint64_t)r * kWave + lane;
+        const bool valid = idx < count;
+        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
+        const uint64_t m = match8(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt()), c = (uint32_t)__popcll(m);
+        if (valid && rank == 0) atomicAdd(&s_cnt[w][d], c);
+        info[r] = rank | (c << 8) | ((uint32_t)(__ffsll((unsigned long long)m) - 1) << 16);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    uint32_t btot = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) btot += s_cnt[k][tid];
+    uint32_t ntot;
+    const uint32_t lbase = block_excl_scan<uint32_t>(btot, s_w, &ntot);
+    s_goff[tid] = dbase + before - lbase;
+    {
+        uint32_t run = lbase;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            const uint32_t c = s_cnt[k][tid];
+            s_cnt[k][tid] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsIPT; ++r) {
+        const uint64_t idx = base + (uint64_t)r * kWave + lane;
+        const bool valid = idx < count;
+        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
+        const uint32_t rank = info[r] & 0xffu;
+        uint32_t start = 0;
+        if (valid && rank == 0) start = atomicAdd(&s_cnt[w][d], (info[r] >> 8) & 0xffu);
+        start = __shfl(start, valid ? (int)(info[r] >> 16) : 0);
+        if (valid) {
+            const uint32_t pos = start + rank;
+            s_key[pos] = key[r];
+            s_val[pos] = val[r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsIPT; ++r) {
+        const uint32_t i = (uint32_t)(r * kBlock + tid);
+        if (i < ntot) {
+            const uint32_t k = s_key[i];
+            const uint32_t pos = i + s_goff[(k >> shift) & (kRadix - 1)];
+            kout[pos] = k;
+            vout[pos] = s_val[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // Binning kernels
 // ------------------------------------------------------------------------------------------------
 // Zeroes the tile ranges, both control blocks and the look-back arrays that the first kernel of each
@@ -553,9 +711,10 @@ struct BinWs {
     uint32_t *tkA, *tkB, *tvB;        // tile sort, capacity
     SortCtl *ctl_depth, *ctl_tile;
     uint64_t *lb_d0, *lb_d1;          // depth look-back, [blocks][256] each
-    uint64_t *lb_t0, *lb_t1;          // tile look-back
+    uint32_t* rs_cnt;                 // tile passes: per-block digit counts [256][nb_rs], scanned in place
+    uint32_t* rs_tot;                 // tile passes: digit totals [256]
     uint64_t* lb_scan;                // count-scan look-back, [blocks]
-    int64_t nb_depth, nb_tile, nb_scan;
+    int64_t nb_depth, nb_rs, nb_scan;
     size_t bytes;
 };
 
@@ -571,7 +730,7 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     const int64_t it1 = std::max<int64_t>(items, 1);
     const int64_t cap1 = std::max<int64_t>(capacity, 1);
     w.nb_depth = sweep_blocks(it1);
-    w.nb_tile = sweep_blocks(cap1);
+    w.nb_rs = std::max<int64_t>(1, ceil_div(cap1, kRsTile));
     w.nb_scan = std::max<int64_t>(1, ceil_div(it1, kScanTile));
     w.dkA = (uint32_t*)take(4 * it1);
     w.dkB = (uint32_t*)take(4 * it1);
@@ -586,8 +745,8 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     w.ctl_tile = (SortCtl*)take(sizeof(SortCtl));
     w.lb_d0 = (uint64_t*)take(8 * kRadix * w.nb_depth);
     w.lb_d1 = (uint64_t*)take(8 * kRadix * w.nb_depth);
-    w.lb_t0 = (uint64_t*)take(8 * kRadix * w.nb_tile);
-    w.lb_t1 = (uint64_t*)take(8 * kRadix * w.nb_tile);
+    w.rs_cnt = (uint32_t*)take(4 * kRadix * w.nb_rs);
+    w.rs_tot = (uint32_t*)take(4 * kRadix);
     w.lb_scan = (uint64_t*)take(8 * w.nb_scan);
     w.bytes = off;
     return w;
@@ -645,8 +804,8 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
         z.words[2] = sizeof(SortCtl) / 4;
         z.p[3] = (uint32_t*)w.lb_d0;
         z.words[3] = items > 0 ? 2 * kRadix * w.nb_depth : 0;
-        z.p[4] = (uint32_t*)w.lb_t0;
-        z.words[4] = capacity > 0 ? 2 * kRadix * w.nb_tile : 0;
+        z.p[4] = w.rs_tot;  // (nothing of the tile passes needs clearing)
+        z.words[4] = 0;
         z.p[5] = (uint32_t*)w.lb_scan;
         z.words[5] = 2 * w.nb_scan;
         z.p[6] = (uint32_t*)num_pairs;  // stays 0 for an empty input
@@ -691,22 +850,23 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
     {
         QG_TIMED("bin_emit", s);
-        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(
-            items, n, vt, sorted_items, w.offs,
-                                                                      w.sort_count, tpasses, w.tkA, vbuf0,
-                                                                      w.ctl_tile);
+        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(items, n, vt, sorted_items, w.offs,
+                                                                      w.sort_count, 0, w.tkA, vbuf0, w.ctl_tile);
     }
     QG_LAUNCH_CHECK("qg_bin emit");
-    // 3. stable sort by tile id
+    // 3. stable sort by tile id: reduce, scan and scatter per 8-bit pass
     uint32_t *tk_in = w.tkA, *tk_out = w.tkB, *tv_in = vbuf0, *tv_out = vbuf1;
-    uint64_t *ta = w.lb_t0, *tb = w.lb_t1;
     for (int pass = 0; pass < tpasses; ++pass) {
-        qg_status st = sweep_pass(tk_in, tv_in, tk_out, tv_out, w.sort_count, 0u, capacity, pass, w.ctl_tile, ta,
-                                  pass + 1 < tpasses ? tb : nullptr, s, "sort_tile");
-        if (st != QG_OK) return st;
+        {
+            QG_TIMED("sort_tile", s);
+            k_rs_count<<<(unsigned)w.nb_rs, kBlock, 0, s>>>(tk_in, w.sort_count, pass, w.rs_cnt, w.nb_rs);
+            k_rs_scan<<<kRadix, kRsScanThreads, 0, s>>>(w.rs_cnt, w.nb_rs, w.sort_count, w.rs_tot);
+            k_rs_scatter<<<(unsigned)w.nb_rs, kBlock, 0, s>>>(tk_in, tv_in, tk_out, tv_out, w.sort_count, pass,
+                                                              w.rs_cnt, w.nb_rs, w.rs_tot);
+        }
+        QG_LAUNCH_CHECK("radix pass (tile)");
         std::swap(tk_in, tk_out);
         std::swap(tv_in, tv_out);
-        std::swap(ta, tb);
     }
     // tk_in / tv_in hold the sorted pairs; tv_in == vals by construction
     // 4. tile ranges (and optional 64-bit keys)

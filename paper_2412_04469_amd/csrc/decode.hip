@@ -337,3 +337,253 @@ extern "C" qg_status qg_decode_lreg_bwd(int64_t n, const float* gate_logit, floa
     QG_LAUNCH_CHECK("qg_decode_lreg_bwd");
     return QG_OK;
 }
+
+// ---------------------------------------------------------------------------------------------------------
+// Paper-mode decoder (Eq. 5 as written): one linear decoder per attribute category, r_c = D_c rint(l_c).
+// Rotation (4 planes from 3), scaling (3 from 7), opacity (1 from 10), colour base (3 from 11) and colour
+// frequencies (45 from 14); latent dimensions L_c from the host.  D is packed category by category, each D_c
+// row-major [M_c][L_c].  It is a block-diagonal map of about 500 flop per Gaussian against ~600 bytes moved,
+// so it runs on the vector units, one lane per Gaussian; the decoder's weight gradient sum over Gaussians is
+// reduced per wave by shuffles, per block in wave order and over blocks in block order (deterministic).
+// ---------------------------------------------------------------------------------------------------------
+namespace qg {
+namespace {
+
+constexpr int kCats = 5;
+constexpr int kCatPlane[kCats] = {3, 7, 10, 11, 14};
+constexpr int kCatOut[kCats] = {4, 3, 1, 3, 45};
+constexpr int kLinMaxL = 16;                      // per category
+constexpr int kLinMaxP = 56 * kLinMaxL;           // packed decoder floats
+
+struct LinDims {
+    int L[kCats];     // latent dims
+    int loff[kCats];  // first latent plane of the category
+    int doff[kCats];  // first packed decoder float of the category
+    int total_L, total_P;
+};
+
+__device__ __forceinline__ int cat_plane(int c) {
+    return c == 0 ? 3 : (c == 1 ? 7 : (c == 2 ? 10 : (c == 3 ? 11 : 14)));
+}
+__device__ __forceinline__ int cat_out(int c) { return c == 0 ? 4 : (c == 1 ? 3 : (c == 2 ? 1 : (c == 3 ? 3 : 45))); }
+
+constexpr int kLinBlock = 256;
+
+__global__ __launch_bounds__(kLinBlock) void k_decode_linear(int64_t n, int64_t ld, const float* __restrict__ prev,
+                                                             const float* __restrict__ lat, LinDims dm,
+                                                             const float* __restrict__ D, const float* __restrict__ lp,
+                                                             const float* __restrict__ ga,
+                                                             const float* __restrict__ gnoise, float g0, float g1,
+                                                             float tau, float reg_shift, float* __restrict__ out,
+                                                             float* __restrict__ gate_out,
+                                                             float* __restrict__ lreg_part) {
+    __shared__ float s_D[kLinMaxP];
+    __shared__ float s_red[kLinBlock / 64];
+    for (int i = threadIdx.x; i < dm.total_P; i += kLinBlock) s_D[i] = D[i];
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * kLinBlock + threadIdx.x;
+    float preg = 0.f;
+    if (g < n) {
+#pragma unroll 1
+        for (int c = 0; c < kCats; ++c) {
+            float l[kLinMaxL];
+#pragma unroll
+            for (int k = 0; k < kLinMaxL; ++k) l[k] = k < dm.L[c] ? rintf(lat[(int64_t)(dm.loff[c] + k) * ld + g]) : 0.f;
+            const float* Dc = s_D + dm.doff[c];
+            const int M = cat_out(c), L = dm.L[c], p0 = cat_plane(c);
+            for (int m = 0; m < M; ++m) {
+                float r = 0.f;
+#pragma unroll
+                for (int k = 0; k < kLinMaxL; ++k)
+                    if (k < L) r = __builtin_fmaf(Dc[m * L + k], l[k], r);
+                out[(int64_t)(p0 + m) * ld + g] = prev[(int64_t)(p0 + m) * ld + g] + r;
+            }
+        }
+        const float a = ga[g];
+        const float gg = gate_of(gnoise ? a + gnoise[g] : a, g0, g1, tau, nullptr, nullptr);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            out[(int64_t)k * ld + g] = __builtin_fmaf(gg, lp[(int64_t)k * ld + g], prev[(int64_t)k * ld + g]);
+        if (gate_out) gate_out[g] = gg;
+        preg = sigm(a - reg_shift);
+    }
+    if (lreg_part) {
+        for (int o = 32; o >= 1; o >>= 1) preg += __shfl_xor(preg, o);
+        if (__lane_id() == 0) s_red[threadIdx.x / 64] = preg;
+        __syncthreads();
+        if (threadIdx.x == 0) lreg_part[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    }
+}
+
+// Backward: dL/dl_c = D_c^T dL/dr_c (straight-through), the gate and pre-gate position gradients as in the MLP
+// form, and per block the sum over its Gaussians of dL/dr_c rint(l_c)^T (wave sums by shuffles, then the waves in
+// order) into wpart[block][P].
+__global__ __launch_bounds__(kLinBlock) void k_decode_linear_bwd(
+    int64_t n, int64_t ld, const float* __restrict__ lat, LinDims dm, const float* __restrict__ D,
+    const float* __restrict__ lp, const float* __restrict__ ga, const float* __restrict__ gnoise, float g0, float g1,
+    float tau, float reg_shift, float reg_scale, const float* __restrict__ GA, float* __restrict__ g_lat,
+    float* __restrict__ g_lp, float* __restrict__ g_ga, float* __restrict__ wpart) {
+    __shared__ float s_D[kLinMaxP];
+    __shared__ float s_w[kLinBlock / 64][kLinMaxP];
+    for (int i = threadIdx.x; i < dm.total_P; i += kLinBlock) s_D[i] = D[i];
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * kLinBlock + threadIdx.x;
+    const bool gv = g < n;
+    const int w = threadIdx.x / 64, lane = __lane_id();
+#pragma unroll 1
+    for (int c = 0; c < kCats; ++c) {
+        const int M = cat_out(c), L = dm.L[c], p0 = cat_plane(c);
+        float l[kLinMaxL], gl[kLinMaxL];
+#pragma unroll
+        for (int k = 0; k < kLinMaxL; ++k) {
+            l[k] = (gv && k < L) ? rintf(lat[(int64_t)(dm.loff[c] + k) * ld + g]) : 0.f;
+            gl[k] = 0.f;
+        }
+        const float* Dc = s_D + dm.doff[c];
+        for (int m = 0; m < M; ++m) {
+            const float dr = gv ? GA[(int64_t)(p0 + m) * ld + g] : 0.f;
+#pragma unroll
+            for (int k = 0; k < kLinMaxL; ++k) {
+                if (k >= L) continue;
+                gl[k] = __builtin_fmaf(Dc[m * L + k], dr, gl[k]);
+                float v = dr * l[k];  // this Gaussian's term of dL/dD_c[m][k]; summed over the wave
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+                if (lane == 0) s_w[w][dm.doff[c] + m * L + k] = v;
+            }
+        }
+        if (gv) {
+#pragma unroll
+            for (int k = 0; k < kLinMaxL; ++k)
+                if (k < L) g_lat[(int64_t)(dm.loff[c] + k) * ld + g] += gl[k];
+        }
+    }
+    if (gv) {
+        const float a = ga[g];
+        float gh, gt;
+        const float gg = gate_of(gnoise ? a + gnoise[g] : a, g0, g1, tau, &gh, &gt);
+        float dot = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float dpos = GA[(int64_t)k * ld + g];
+            dot = __builtin_fmaf(dpos, lp[(int64_t)k * ld + g], dot);
+            g_lp[(int64_t)k * ld + g] += gg * dpos;
+        }
+        const float da = (gt > 0.f && gt < 1.f) ? dot * (g1 - g0) * gh * (1.f - gh) / tau : 0.f;
+        const float pr = sigm(a - reg_shift);
+        g_ga[g] += __builtin_fmaf(reg_scale, pr * (1.f - pr), da);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < dm.total_P; i += kLinBlock)
+        wpart[(size_t)blockIdx.x * dm.total_P + i] = (s_w[0][i] + s_w[1][i]) + (s_w[2][i] + s_w[3][i]);
+}
+
+// grad_D[i] += sum over blocks of wpart[b][i]: one wave per decoder float, lane l summing blocks l, l + 64, ...
+// in order, then a fixed butterfly over the lanes (deterministic).
+__global__ __launch_bounds__(256) void k_linear_reduce(const float* __restrict__ wpart, int64_t nb, int P,
+                                                       float* __restrict__ gD) {
+    const int i = blockIdx.x * 4 + threadIdx.x / 64, lane = __lane_id();
+    if (i >= P) return;
+    float s = 0.f;
+    for (int64_t b = lane; b < nb; b += 64) s += wpart[(size_t)b * P + i];
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) gD[i] += s;
+}
+
+bool lin_dims(const int32_t* dims, LinDims* d) {
+    if (!dims) {
+        set_error("dims is NULL");
+        return false;
+    }
+    int lo = 0, po = 0;
+    for (int c = 0; c < kCats; ++c) {
+        if (dims[c] < 1 || dims[c] > kLinMaxL) {
+            set_error("latent dimension %d of category %d outside [1, %d]", dims[c], c, kLinMaxL);
+            return false;
+        }
+        d->L[c] = dims[c];
+        d->loff[c] = lo;
+        d->doff[c] = po;
+        lo += dims[c];
+        po += dims[c] * kCatOut[c];
+    }
+    d->total_L = lo;
+    d->total_P = po;
+    return true;
+}
+
+}  // namespace
+}  // namespace qg
+
+extern "C" int64_t qg_linear_decoder_params(const int32_t* dims) {
+    LinDims d;
+    if (!lin_dims(dims, &d)) return -1;
+    return d.total_P;
+}
+
+extern "C" int64_t qg_decode_linear_blocks(int64_t n) { return std::max<int64_t>(1, ceil_div(n, kLinBlock)); }
+
+extern "C" qg_status qg_decode_linear(int64_t n, int64_t ld, const float* prev_attrs, const float* latents,
+                                      const int32_t* dims, const float* D, const float* pos_pre,
+                                      const float* gate_logit, const float* gate_noise, float gamma0, float gamma1,
+                                      float tau, float* attrs_out, float* gate_out, float* lreg_partial,
+                                      qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0 && ld >= n, "n=%lld ld=%lld: need 0 <= n <= ld", (long long)n, (long long)ld);
+    LinDims dm;
+    if (!lin_dims(dims, &dm)) return QG_ERR_ARG;
+    qg_status st = check_gate(gamma0, gamma1, tau);
+    if (st != QG_OK) return st;
+    QG_REQUIRE(n == 0 || (prev_attrs && latents && D && pos_pre && gate_logit && attrs_out), "a required pointer is NULL");
+    QG_REQUIRE(attrs_out != prev_attrs, "attrs_out may not alias prev_attrs");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = qg_decode_linear_blocks(n);
+    if (n == 0) return lreg_partial ? qg_zero(lreg_partial, 4 * nb, stream) : QG_OK;
+    const float shift = tau * logf(-gamma0 / gamma1);
+    {
+        QG_TIMED("decode_linear", s);
+        k_decode_linear<<<(unsigned)nb, kLinBlock, 0, s>>>(n, ld, prev_attrs, latents, dm, D, pos_pre, gate_logit,
+                                                           gate_noise, gamma0, gamma1, tau, shift, attrs_out, gate_out,
+                                                           lreg_partial);
+    }
+    QG_LAUNCH_CHECK("qg_decode_linear");
+    return QG_OK;
+}
+
+extern "C" size_t qg_decode_linear_bwd_workspace_size(int64_t n, const int32_t* dims) {
+    LinDims dm;
+    if (n < 0 || !lin_dims(dims, &dm)) return 0;
+    return align_up((size_t)qg_decode_linear_blocks(n) * dm.total_P * sizeof(float));
+}
+
+extern "C" qg_status qg_decode_linear_bwd(int64_t n, int64_t ld, const float* latents, const int32_t* dims,
+                                          const float* D, const float* pos_pre, const float* gate_logit,
+                                          const float* gate_noise, float gamma0, float gamma1, float tau,
+                                          const float* grad_attrs, float lambda_reg, float* grad_latents,
+                                          float* grad_D, float* grad_pos_pre, float* grad_gate_logit, void* ws,
+                                          size_t ws_bytes, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(n >= 0 && ld >= n, "n=%lld ld=%lld: need 0 <= n <= ld", (long long)n, (long long)ld);
+    LinDims dm;
+    if (!lin_dims(dims, &dm)) return QG_ERR_ARG;
+    qg_status st = check_gate(gamma0, gamma1, tau);
+    if (st != QG_OK) return st;
+    QG_REQUIRE(n == 0 || (latents && D && pos_pre && gate_logit && grad_attrs && grad_latents && grad_D &&
+                          grad_pos_pre && grad_gate_logit),
+               "a required pointer is NULL");
+    const size_t need = qg_decode_linear_bwd_workspace_size(n, dims);
+    QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    if (n == 0) return QG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = qg_decode_linear_blocks(n);
+    const float shift = tau * logf(-gamma0 / gamma1);
+    {
+        QG_TIMED("decode_linear_bwd", s);
+        k_decode_linear_bwd<<<(unsigned)nb, kLinBlock, 0, s>>>(n, ld, latents, dm, D, pos_pre, gate_logit, gate_noise,
+                                                               gamma0, gamma1, tau, shift, lambda_reg / (float)n,
+                                                               grad_attrs, grad_latents, grad_pos_pre, grad_gate_logit,
+                                                               (float*)ws);
+        k_linear_reduce<<<(unsigned)ceil_div(dm.total_P, 4), 256, 0, s>>>((const float*)ws, nb, dm.total_P, grad_D);
+    }
+    QG_LAUNCH_CHECK("qg_decode_linear_bwd");
+    return QG_OK;
+}

@@ -7,7 +7,7 @@
 //
 // Densification keeps each Gaussian's children in place, in parent order: the plan gives every Gaussian an
 // action and the exclusive scan of its child counts (0 pruned, 1 kept, 2 cloned or split), and every
-// per-Gaussian array is then expanded through that map; split children get their offset and scale change last.
+// per-Gaussian array is then expanded through that map; clone and split children get their changes last.
 #include <cmath>
 
 #include "qg_internal.h"
@@ -177,12 +177,24 @@ __global__ void k_expand(int64_t n, const uint8_t* __restrict__ action, const in
     }
 }
 
-// Split children: mean + R(q) (s * z) with the parent's decoded rotation and scale, log-scale - ln 1.6.
-__global__ void k_split(int64_t n, const uint8_t* __restrict__ action, const int64_t* __restrict__ offsets,
-                        const float* __restrict__ dec, int64_t ld, uint32_t k0, uint32_t k1, uint32_t rnd,
-                        float* __restrict__ dst, int64_t ld_dst) {
+// Children after the expansion.  Clone (action 1): both copies' stored opacity logit moves by
+// logit(o') - logit(o), o' = 1 - sqrt(1 - o), o the parent's decoded opacity, so that the coincident pair
+// composites like the parent where its Gaussian factor is 1 (double precision).  Split (action 2): mean +
+// R(q) (s * z) with the parent's decoded rotation and scale, log-scale - ln 1.6.
+__global__ void k_children(int64_t n, const uint8_t* __restrict__ action, const int64_t* __restrict__ offsets,
+                           const float* __restrict__ dec, int64_t ld, uint32_t k0, uint32_t k1, uint32_t rnd,
+                           float* __restrict__ dst, int64_t ld_dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || action[i] != 2) return;
+    if (i >= n) return;
+    const uint8_t act = action[i];
+    if (act == 1) {
+        const double x = (double)dec[10 * ld + i];
+        const double sq = sqrt(1.0 / (1.0 + exp(x)));  // sqrt(1 - o)
+        const float shift = (float)((log1p(-sq) - log(sq)) - x);
+        for (int c = 0; c < 2; ++c) dst[10 * ld_dst + offsets[i] + c] += shift;
+        return;
+    }
+    if (act != 2) return;
     float z[8];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -301,19 +313,19 @@ extern "C" qg_status qg_densify_expand(int64_t n, const uint8_t* action, const i
     return QG_OK;
 }
 
-extern "C" qg_status qg_densify_split(int64_t n, const uint8_t* action, const int64_t* offsets, const float* decoded,
-                                      int64_t ld, uint64_t seed, int32_t round, float* prev_out, int64_t ld_out,
-                                      qg_stream stream) {
+extern "C" qg_status qg_densify_children(int64_t n, const uint8_t* action, const int64_t* offsets,
+                                         const float* decoded, int64_t ld, uint64_t seed, int32_t round,
+                                         float* prev_out, int64_t ld_out, qg_stream stream) {
     clear_error();
     QG_REQUIRE(n >= 0 && ld >= n && ld_out >= 0, "bad sizes");
     QG_REQUIRE(n == 0 || (action && offsets && decoded && prev_out), "a required pointer is NULL");
     if (n == 0) return QG_OK;
     hipStream_t s = (hipStream_t)stream;
     {
-        QG_TIMED("densify_split", s);
-        k_split<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, action, offsets, decoded, ld, (uint32_t)seed,
+        QG_TIMED("densify_children", s);
+        k_children<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, action, offsets, decoded, ld, (uint32_t)seed,
                                                            (uint32_t)(seed >> 32), (uint32_t)round, prev_out, ld_out);
     }
-    QG_LAUNCH_CHECK("qg_densify_split");
+    QG_LAUNCH_CHECK("qg_densify_children");
     return QG_OK;
 }

@@ -384,9 +384,33 @@ size_t det_weight_part_bytes(int64_t n) {
 }
 }  // namespace qg
 
-extern "C" size_t qg_deterministic_workspace_size(int64_t n, int64_t capacity) {
-    if (n < 0 || capacity < 0) return 0;
-    return det_weight_part_bytes(n) + align_up((size_t)std::max<int64_t>(capacity, 1) * kPairPart * sizeof(float));
+// Deterministic-mode workspace after an adjoint call's own: the fused adjoint's weight-gradient rows, the slot
+// bases [n * V] and their block sums, then the pair partials (as many slots as fit: the bin capacity).
+static size_t det_fixed_bytes(int64_t n, int32_t V) {
+    const int64_t items = std::max<int64_t>(n * V, 1);
+    return det_weight_part_bytes(n) + align_up((size_t)items * 4) + align_up((size_t)ceil_div(items, 1024) * 4);
+}
+
+namespace qg {
+qg_status det_layout(char* base, size_t bytes, int64_t n, int32_t V, float** wdet, PairPart* pp) {
+    const size_t fixed = det_fixed_bytes(n, V);
+    QG_REQUIRE(bytes >= fixed + align_up(kPairPart * 4), "deterministic mode: the workspace has %zu bytes past the "
+               "call's own, fewer than the %zu its partials need (add qg_deterministic_workspace_size)", bytes,
+               fixed + align_up(kPairPart * 4));
+    if (wdet) *wdet = (float*)base;
+    const size_t wb = det_weight_part_bytes(n);
+    pp->base = (uint32_t*)(base + wb);
+    pp->part = (float*)(base + fixed);
+    const size_t c = (bytes - fixed) / (kPairPart * sizeof(float));
+    pp->cap = (uint32_t)(c < 0xFFFFFFFFull ? c : 0xFFFFFFFFull);
+    pp->n = n;
+    return QG_OK;
+}
+}  // namespace qg
+
+extern "C" size_t qg_deterministic_workspace_size(int64_t n, int32_t V, int64_t capacity) {
+    if (n < 0 || V < 1 || capacity < 0) return 0;
+    return det_fixed_bytes(n, V) + align_up((size_t)std::max<int64_t>(capacity, 1) * kPairPart * sizeof(float));
 }
 
 extern "C" size_t qg_render_decode_bwd_workspace_size(int64_t n, int32_t V) {
@@ -428,14 +452,11 @@ extern "C" qg_status qg_render_decode_bwd(
     const int64_t stride = n * QG_GRAD2D_STRIDE;
     float* wpart = (float*)((char*)ws + align_up((size_t)V * (size_t)n * QG_GRAD2D_STRIDE * sizeof(float)));
     const bool det = deterministic_mode();
-    PairPart pp{nullptr, 0};
+    PairPart pp{nullptr, 0, nullptr, n};
     float* wdet = nullptr;
     if (det) {
-        const size_t wb = det_weight_part_bytes(n);
-        QG_REQUIRE(ws_bytes >= need + wb + align_up(kPairPart * 4), "deterministic mode: workspace %zu has no room "
-                   "for the partials (add qg_deterministic_workspace_size)", ws_bytes);
-        wdet = (float*)((char*)ws + need);
-        pp = pair_part_in((char*)ws + need + wb, ws_bytes - need - wb);
+        st = det_layout((char*)ws + need, ws_bytes - need, n, V, &wdet, &pp);
+        if (st != QG_OK) return st;
     }
     st = qg_zero(grad2d, (int64_t)V * stride * 4, stream);
     if (st != QG_OK) return st;

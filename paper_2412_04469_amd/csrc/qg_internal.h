@@ -73,21 +73,22 @@ bool tiling_ok(qg_tiling t);
 // Deterministic mode of the adjoints (QG_DETERMINISTIC=1 in the environment, or qg_set_deterministic).
 bool deterministic_mode();
 
-// Per-(tile, entry) partial sums of the blend adjoint in deterministic mode: kPairPart floats per position of
-// the sorted pair list, for positions below cap.
+// Per-(tile, entry) partial sums of the blend adjoint in deterministic mode: kPairPart floats per pair slot.  The
+// slots of (view v, Gaussian i) are base[v * n + i] + j for the tiles j = 0 .. ntiles-1 of its rectangle in
+// row-major order (base: exclusive scan of the tile counts, view-major), for slots below cap.
 constexpr int kPairPart = 9;
 struct PairPart {
     float* part;
     uint32_t cap;
+    uint32_t* base;  // [n * V]
+    int64_t n;
 };
-inline PairPart pair_part_in(char* base, size_t bytes) {
-    const size_t c = bytes / (kPairPart * sizeof(float));
-    return PairPart{(float*)base, (uint32_t)(c < 0xFFFFFFFFull ? c : 0xFFFFFFFFull)};
-}
 
 // Bytes of the per-chunk decoder weight-gradient rows that deterministic mode appends to the adjoint workspaces
 // (ahead of the pair partials).
 size_t det_weight_part_bytes(int64_t n);
+// Carves the deterministic-mode buffers out of the workspace bytes past an adjoint call's own.
+qg_status det_layout(char* base, size_t bytes, int64_t n, int32_t V, float** wdet, PairPart* pp);
 
 // Event timing around launches (no-ops unless qg_timing_enable(1)).
 void timing_begin(const char* name, hipStream_t s);

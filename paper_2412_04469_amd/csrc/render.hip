@@ -444,10 +444,14 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 const float val =
                     gscale * (((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane])) +
                               ((s_red[4][lane] + s_red[5][lane]) + (s_red[6][lane] + s_red[7][lane])));
-                if (pp.part == nullptr)
+                if (pp.part == nullptr) {
                     atomicAdd(g2 + (size_t)s_gid[jj] * QG_GRAD2D_STRIDE + lane, val);
-                else if (pos < pp.cap)  // deterministic mode: this (tile, entry)'s sums, added up later in order
-                    pp.part[(size_t)pos * kPairPart + lane] = val;
+                } else {  // deterministic mode: this (tile, entry)'s sums in its slot, added up later in order
+                    const uint32_t gid = s_gid[jj];
+                    const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[gid];
+                    const uint32_t slot = pp.base[(size_t)v * pp.n + gid] + (uint32_t)((ty - r.y) * (r.z - r.x) + (tx - r.x));
+                    if (slot < pp.cap) pp.part[(size_t)slot * kPairPart + lane] = val;
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -565,6 +569,7 @@ qg_status launch_fwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* 
                        hipStream_t s) {
     if (t.batch == 32) return launch_fwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, img, tf, lp, s);
     if (t.batch == 128) return launch_fwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, img, tf, lp, s);
+    if (t.batch == 256) return launch_fwd_t<TW, TH, 256>(vt, t, vals, ranges, bg, img, tf, lp, s);
     return launch_fwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, img, tf, lp, s);
 }
 
@@ -574,6 +579,7 @@ qg_status launch_bwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* 
                        float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
     if (t.batch == 32) return launch_bwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
     if (t.batch == 128) return launch_bwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
+    if (t.batch == 256) return launch_bwd_t<TW, TH, 256>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
     return launch_bwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
 }
 
@@ -592,47 +598,92 @@ qg_status launch_bwd_tiles(const ViewTable& vt, const qg_tiling& t, const uint32
     return launch_bwd_b<32, 8>(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
 }
 
-// Deterministic mode, second pass: the 2D gradient record of (view v, Gaussian i) is the sum of its
-// (tile, entry) partials over the tiles of its rectangle in row-major order, each entry found in its tile's
-// list by binary search on the list's order (depth bits, then Gaussian index).  A fixed order, so the record is
-// the same bits on every run.
-__global__ __launch_bounds__(256) void k_det_gather(int64_t n, ViewTable vt, const uint32_t* __restrict__ vals,
-                                                    const uint32_t* __restrict__ ranges, PairPart pp,
-                                                    float* __restrict__ grad2d, int64_t stride) {
+// Deterministic mode.  Slot bases: the exclusive scan of the tile counts of the (view, Gaussian) items, in three
+// steps (block sums, one-block scan of the block sums, block-local scans).
+constexpr int kDetScanBlock = 1024;
+
+__global__ __launch_bounds__(kDetScanBlock) void k_det_base_sums(int64_t items, int64_t n, ViewTable vt,
+                                                                 uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s_w[kDetScanBlock / 64];
+    const int64_t item = (int64_t)blockIdx.x * kDetScanBlock + threadIdx.x;
+    uint32_t c = 0;
+    if (item < items) {
+        const int v = (int)(item / n);
+        c = (uint32_t)max(vt.proj[v].ntiles[item - (int64_t)v * n], 0);
+    }
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+    if (__lane_id() == 0) s_w[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kDetScanBlock / 64; ++k) t += s_w[k];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kDetScanBlock) void k_det_base_scan(int64_t nb, uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s[kDetScanBlock];
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kDetScanBlock) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint32_t x = b < nb ? bsum[b] : 0u;
+        s[threadIdx.x] = x;
+        __syncthreads();
+        for (int o = 1; o < kDetScanBlock; o <<= 1) {
+            const uint32_t add = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (b < nb) bsum[b] = carry + s[threadIdx.x] - x;
+        carry += s[kDetScanBlock - 1];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kDetScanBlock) void k_det_base(int64_t items, int64_t n, ViewTable vt,
+                                                            const uint32_t* __restrict__ bsum,
+                                                            uint32_t* __restrict__ base) {
+    __shared__ uint32_t s[kDetScanBlock];
+    const int64_t item = (int64_t)blockIdx.x * kDetScanBlock + threadIdx.x;
+    uint32_t c = 0;
+    if (item < items) {
+        const int v = (int)(item / n);
+        c = (uint32_t)max(vt.proj[v].ntiles[item - (int64_t)v * n], 0);
+    }
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < kDetScanBlock; o <<= 1) {
+        const uint32_t add = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (item < items) base[item] = bsum[blockIdx.x] + s[threadIdx.x] - c;
+}
+
+// Second pass: the 2D gradient record of (view v, Gaussian i) is the sum of its slots in order (the tiles of its
+// rectangle, row-major): the same bits on every run.
+__global__ __launch_bounds__(256) void k_det_gather(int64_t n, ViewTable vt, PairPart pp, float* __restrict__ grad2d,
+                                                    int64_t stride) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= n * vt.V) return;
     const int v = (int)(item / n);
     const int64_t i = item - (int64_t)v * n;
-    const ProjDev& p = vt.proj[v];
-    if (p.ntiles[i] <= 0) return;
-    const int4 r = reinterpret_cast<const int4*>(p.rect)[i];
-    const uint32_t key = __float_as_uint(p.depth[i]);
-    const CamDev& cam = vt.cam[v];
+    const int32_t k = vt.proj[v].ntiles[i];
+    if (k <= 0) return;
     float acc[kPairPart];
 #pragma unroll
-    for (int k = 0; k < kPairPart; ++k) acc[k] = 0.f;
-    for (int ty = r.y; ty < r.w; ++ty)
-        for (int tx = r.x; tx < r.z; ++tx) {
-            const size_t t = (size_t)cam.tile_off + (size_t)ty * cam.grid_w + tx;
-            uint32_t lo = ranges[2 * t], hi = ranges[2 * t + 1];
-            const uint32_t end = hi;
-            while (lo < hi) {  // first entry whose (depth bits, index) is not below (key, i)
-                const uint32_t mid = lo + (hi - lo) / 2;
-                const uint32_t g = vals[mid];
-                const uint32_t kg = __float_as_uint(p.depth[g]);
-                if (kg < key || (kg == key && g < (uint32_t)i))
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            if (lo < end && vals[lo] == (uint32_t)i && lo < pp.cap) {
+    for (int c = 0; c < kPairPart; ++c) acc[c] = 0.f;
+    const uint32_t b = pp.base[item];
+    const uint32_t e = (uint32_t)min<uint64_t>((uint64_t)b + (uint64_t)k, pp.cap);
+    for (uint32_t sl = b; sl < e; ++sl) {
 #pragma unroll
-                for (int k = 0; k < kPairPart; ++k) acc[k] += pp.part[(size_t)lo * kPairPart + k];
-            }
-        }
+        for (int c = 0; c < kPairPart; ++c) acc[c] += pp.part[(size_t)sl * kPairPart + c];
+    }
     float* rec = grad2d + (int64_t)v * stride + (size_t)i * QG_GRAD2D_STRIDE;
 #pragma unroll
-    for (int k = 0; k < kPairPart; ++k) rec[k] = acc[k];
+    for (int c = 0; c < kPairPart; ++c) rec[c] = acc[c];
 }
 
 // The blend adjoint into the zeroed 2D gradient records: float atomics across tiles, or, with a pair-partial
@@ -640,15 +691,21 @@ __global__ __launch_bounds__(256) void k_det_gather(int64_t n, ViewTable vt, con
 qg_status launch_bwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
                      const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi, float* grad2d,
                      int64_t stride, int64_t n, PairPart pp, hipStream_t s) {
-    if (pp.part) {
+    if (pp.part && n > 0) {
         qg_status st = qg_zero(pp.part, (int64_t)pp.cap * kPairPart * 4, s);
         if (st != QG_OK) return st;
+        const int64_t items = n * vt.V, nb = ceil_div(items, kDetScanBlock);
+        uint32_t* bsum = pp.base + align_up((size_t)items * 4) / 4;
+        QG_TIMED("blend_bwd_slots", s);
+        k_det_base_sums<<<(unsigned)nb, kDetScanBlock, 0, s>>>(items, n, vt, bsum);
+        k_det_base_scan<<<1, kDetScanBlock, 0, s>>>(nb, bsum);
+        k_det_base<<<(unsigned)nb, kDetScanBlock, 0, s>>>(items, n, vt, bsum, pp.base);
     }
     qg_status st = launch_bwd_tiles(vt, t, vals, ranges, bg, tf, lp, gi, grad2d, stride, pp, s);
     if (st != QG_OK || !pp.part || n == 0) return st;
     {
         QG_TIMED("blend_bwd_gather", s);
-        k_det_gather<<<(unsigned)ceil_div(n * vt.V, 256), 256, 0, s>>>(n, vt, vals, ranges, pp, grad2d, stride);
+        k_det_gather<<<(unsigned)ceil_div(n * vt.V, 256), 256, 0, s>>>(n, vt, pp, grad2d, stride);
     }
     QG_LAUNCH_CHECK("deterministic gather");
     return QG_OK;
@@ -923,12 +980,10 @@ extern "C" qg_status qg_render_bwd(int64_t n, int64_t ld, const float* attrs, in
     QG_REQUIRE(n == 0 || (attrs && grad_attrs), "attrs/grad_attrs NULL");
     const size_t need = qg_render_bwd_workspace_size(n, V);
     QG_REQUIRE(ws && ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
-    PairPart pp{nullptr, 0};
+    PairPart pp{nullptr, 0, nullptr, n};
     if (deterministic_mode()) {
-        const size_t wb = det_weight_part_bytes(n);  // unused here; the layout is that of qg_render_decode_bwd
-        QG_REQUIRE(ws_bytes >= need + wb + align_up(kPairPart * 4), "deterministic mode: workspace %zu has no room "
-                   "for the pair partials (add qg_deterministic_workspace_size)", ws_bytes);
-        pp = pair_part_in((char*)ws + need + wb, ws_bytes - need - wb);
+        qg_status st = det_layout((char*)ws + need, ws_bytes - need, n, V, nullptr, &pp);
+        if (st != QG_OK) return st;
     }
     ViewPtrsCF tf = {}, gi = {};
     ViewPtrsCU lp = {};

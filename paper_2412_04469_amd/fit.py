@@ -69,6 +69,26 @@ class FitConfig:
     percent_dense: float = 0.01
     min_opacity: float = 0.005
     densify_seed: int = 4469
+    # the residual decoder: "mlp" (the shared 8 -> 32 -> 56 SiLU MLP of the workload) or "linear" (Eq. 5 as
+    # written: one linear decoder per category with the quantisation table's latent dimensions and learning
+    # rates, N3DV column: rotation, scaling, opacity, colour base, colour frequencies)
+    decoder: str = "mlp"
+    paper_dims: tuple = (6, 8, 3, 8, 4)
+    paper_latent_lrs: tuple = (0.025, 0.01, 0.05, 0.0125, 0.000625)
+    paper_decoder_lrs: tuple = (1e-3, 1e-4, 1e-4, 1e-3, 1e-3)
+
+
+PAPER_OUT = (4, 3, 1, 3, 45)  # residual planes per category: rotation, scaling, opacity, colour base, frequencies
+
+
+def xavier_linear_decoder(seed: int, dims):
+    """Packed per-category decoders D_c [M_c][L_c], Xavier-uniform from a fixed seed."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([2412, 4469, 2000 + seed])))
+    parts = []
+    for L, M in zip(dims, PAPER_OUT):
+        a = math.sqrt(6.0 / (L + M))
+        parts.append(rng.uniform(-a, a, size=(M, L)).astype(np.float32).ravel())
+    return np.concatenate(parts)
 
 
 def xavier_decoder(seed: int, L=8, H=32, M=56):
@@ -93,10 +113,18 @@ class ResidualState:
         dev = self.prev.device
         self.device = dev
         n, L, H = self.n, cfg.latent_dim, cfg.hidden
-        if W1 is None:
-            W1, W2 = xavier_decoder(seed, L, H, 56)
-        self.W1 = torch.as_tensor(W1, device=dev).contiguous()
-        self.W2 = torch.as_tensor(W2, device=dev).contiguous()
+        self.linear = cfg.decoder == "linear"
+        if self.linear:  # Eq. 5 as written: per-category linear decoders (W1 holds the packed D, W2 is unused)
+            L = int(sum(cfg.paper_dims))
+            if W1 is None:
+                W1 = xavier_linear_decoder(seed, cfg.paper_dims)
+            self.W1 = torch.as_tensor(W1, device=dev).contiguous()
+            self.W2 = torch.zeros(0, device=dev)
+        else:
+            if W1 is None:
+                W1, W2 = xavier_decoder(seed, L, H, 56)
+            self.W1 = torch.as_tensor(W1, device=dev).contiguous()
+            self.W2 = torch.as_tensor(W2, device=dev).contiguous()
         self.lat = torch.zeros(L, n, device=dev)
         self.lp = torch.zeros(3, n, device=dev)
         self.a = torch.zeros(n, device=dev)
@@ -114,10 +142,30 @@ class ResidualState:
         # the stochastic gate's logistic noise of the current step (None: the deterministic gate of Eq. 6)
         self.noise = torch.empty(max(n, 1), device=dev) if cfg.stochastic_gate else None
         self.lreg_part = torch.empty(qg.qg_decode_lreg_blocks(n), device=dev)
-        keys = list(self.params)
-        self.adam_segs = qg.adam_segments([self.params[k] for k in keys], [self.grads[k] for k in keys],
-                                          [self.m[k] for k in keys], [self.v[k] for k in keys],
-                                          [self.lrs[k] for k in keys])
+        if self.linear:
+            # one segment per latent category and per decoder block, each with the table's learning rate
+            segs = []
+            lo = 0
+            for Lc, lr in zip(cfg.paper_dims, cfg.paper_latent_lrs):
+                sl = slice(lo * n, (lo + Lc) * n)
+                segs.append((self.lat.view(-1)[sl], self.grads["lat"].view(-1)[sl], self.m["lat"].view(-1)[sl],
+                             self.v["lat"].view(-1)[sl], lr * lr_scale))
+                lo += Lc
+            segs += [(self.lp, self.grads["lp"], self.m["lp"], self.v["lp"], self.lrs["lp"]),
+                     (self.a, self.grads["a"], self.m["a"], self.v["a"], self.lrs["a"])]
+            po = 0
+            for Lc, Mc, lr in zip(cfg.paper_dims, PAPER_OUT, cfg.paper_decoder_lrs):
+                sl = slice(po, po + Lc * Mc)
+                segs.append((self.W1[sl], self.grads["W1"][sl], self.m["W1"][sl], self.v["W1"][sl], lr * lr_scale))
+                po += Lc * Mc
+            self.adam_segs_list = [qg.adam_segments(*[[sg[k] for sg in chunk] for k in range(5)])
+                                   for chunk in (segs[:7], segs[7:])]
+        else:
+            keys = list(self.params)
+            self.adam_segs_list = [qg.adam_segments([self.params[k] for k in keys], [self.grads[k] for k in keys],
+                                                    [self.m[k] for k in keys], [self.v[k] for k in keys],
+                                                    [self.lrs[k] for k in keys])]
+        self.adam_segs = self.adam_segs_list[0]
 
     def reset_frame(self, prev_attrs=None, gts=None, a_init=None, lat_init=None, lp_init=None):
         """New frame: latents and position residuals restart at zero (or at the given initial values), the
@@ -141,9 +189,19 @@ class ResidualState:
     def decode(self, stream=None, gate_noise=None):
         """The decoded attributes of frame t (the deterministic gate unless gate_noise is given)."""
         c = self.cfg
+        if self.linear:
+            qg.qg_decode_linear(self.n, self.ld, self.prev, self.lat, c.paper_dims, self.W1, self.lp, self.a, c.gamma0,
+                                c.gamma1, c.tau, self.attrs, self.gate, None, stream, gate_noise=gate_noise)
+            return
         qg.qg_decode_residuals(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                self.lp, self.a, c.gamma0, c.gamma1, c.tau, self.attrs, self.gate, self.lreg_part,
                                stream, gate_noise=gate_noise)
+
+    def adam(self, stream=None, step_state=None):
+        """One Adam step over every parameter segment (clearing the gradients it read)."""
+        b1, b2 = self.cfg.betas
+        for segs in self.adam_segs_list:
+            qg.qg_adam_multi(segs, b1, b2, self.cfg.eps, self.t, True, stream, step_state=step_state)
 
     def _eval_psnr(self, rast, cam, gt, loss_part, loss_out, stream=None):
         """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync)."""
@@ -174,9 +232,12 @@ class FrameFitter(ResidualState):
         dev = self.device
         n, L, H = self.n, cfg.latent_dim, cfg.hidden
         self.grad_attrs = torch.zeros_like(self.prev)
-        self.dws_bytes = qg.qg_decode_bwd_workspace_size(n, L, H, 56)
+        if self.linear:  # the paper-mode decoder runs through the unfused calls
+            self.dws_bytes = qg.qg_decode_linear_bwd_workspace_size(n, cfg.paper_dims)
+        else:
+            self.dws_bytes = qg.qg_decode_bwd_workspace_size(n, L, H, 56)
         self.dws = torch.empty(self.dws_bytes, dtype=torch.uint8, device=dev)
-        self.fused = True
+        self.fused = not self.linear
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
                                bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch)
         if cfg.densify:  # the densification statistic and the per-view viewspace gradient it is taken from
@@ -263,17 +324,22 @@ class FrameFitter(ResidualState):
         else:
             qg.qg_zero(self.grad_attrs, self.grad_attrs.numel() * 4, stream)
             r.backward(self.attrs, [self.grad_img], self.grad_attrs, grad_xy=gxy, stream=stream)
-            qg.qg_decode_residuals_bwd(self.n, self.ld, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56, self.lp,
-                                       self.a, c.gamma0, c.gamma1, c.tau, self.grad_attrs, c.lambda_reg,
-                                       self.grads["lat"], self.grads["W1"], self.grads["W2"], self.grads["lp"],
-                                       self.grads["a"], self.dws, self.dws_bytes, stream, gate_noise=self.noise)
+            if self.linear:
+                qg.qg_decode_linear_bwd(self.n, self.ld, self.lat, c.paper_dims, self.W1, self.lp, self.a, c.gamma0,
+                                        c.gamma1, c.tau, self.grad_attrs, c.lambda_reg, self.grads["lat"],
+                                        self.grads["W1"], self.grads["lp"], self.grads["a"], self.dws, self.dws_bytes,
+                                        stream, gate_noise=self.noise)
+            else:
+                qg.qg_decode_residuals_bwd(self.n, self.ld, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
+                                           self.lp, self.a, c.gamma0, c.gamma1, c.tau, self.grad_attrs, c.lambda_reg,
+                                           self.grads["lat"], self.grads["W1"], self.grads["W2"], self.grads["lp"],
+                                           self.grads["a"], self.dws, self.dws_bytes, stream, gate_noise=self.noise)
         if c.densify:
             cam = self.cams[v]
             qg.qg_densify_accumulate(self.n, self.d_gxy, r.proj[0]["ntiles"], cam.width / 2.0, cam.height / 2.0,
                                      self.d_accum, self.d_count, stream)
         self.t += 1
-        b1, b2 = c.betas
-        qg.qg_adam_multi(self.adam_segs, b1, b2, c.eps, self.t, True, stream)
+        self.adam(stream)
 
     def loss_value(self, stream=None):
         """L1 of the last step (host sync)."""
@@ -331,7 +397,7 @@ def densify_fitter(f: "FrameFitter", extent: float, rnd: int, stream=None):
     counts = torch.bincount(action[:n].to(torch.int64), minlength=4).tolist()
     prev2 = torch.empty(59, max(n2, 1), device=dev)
     qg.qg_densify_expand(n, action, offsets, 59, f.prev, f.ld, prev2, prev2.stride(0), 0, stream)
-    qg.qg_densify_split(n, action, offsets, f.attrs, f.ld, c.densify_seed, rnd, prev2, prev2.stride(0), stream)
+    qg.qg_densify_children(n, action, offsets, f.attrs, f.ld, c.densify_seed, rnd, prev2, prev2.stride(0), stream)
     g = FrameFitter(prev2[:, :n2], f.cams, f.gts, c, W1=f.W1.clone(), W2=f.W2.clone(),
                     capacity=int(f.rast.capacity * max(n2, 1) / max(n, 1)) + 1024)
     for k in ("lat", "lp", "a"):
@@ -371,7 +437,7 @@ def frame_storage(state: ResidualState, stream=None) -> dict:
     coded = qg.qg_rans_encode(L, sym_h, hist_h)
     model = int(sum(1 + 3 * int((row > 0).sum()) for row in hist_h))
     coo = nz * 16
-    dec = 4 * (state.W1.numel() + state.W2.numel())
+    dec = 4 * (state.W1.numel() + state.W2.numel())  # the MLP's weights, or the packed per-category decoders
     total = coded.size + model + coo + dec
     return {"latent_bytes": int(coded.size), "model_bytes": model, "position_coo_bytes": coo, "nonzero_gates": nz,
             "decoder_bytes": dec, "total_bytes": int(total), "mb_per_frame": round(total / 1e6, 4),
@@ -403,6 +469,7 @@ class BatchedFitter(ResidualState):
     def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
                  capacity=None, seed=0, batch=0, persistent=True, graph=True, eval_cam=None):
         super().__init__(prev_attrs, cfg, W1, W2, seed, lr_scale=cfg.batched_lr_scale)
+        assert not self.linear, "batched steps use the fused MLP-decoder calls"
         self.cams = list(cams)
         # the captured steps read the ground truth from these buffers: new frames are copied into them
         self.gts = [g.clone() for g in gts]

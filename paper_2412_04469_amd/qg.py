@@ -68,7 +68,7 @@ def lib():
             "qg_version": ([], i32),
             "qg_set_deterministic": ([i32], i32),
             "qg_get_deterministic": ([], i32),
-            "qg_deterministic_workspace_size": ([i64, i64], sz),
+            "qg_deterministic_workspace_size": ([i64, i32, i64], sz),
             "qg_zero": ([P, i64, P], i32),
             "qg_total_tiles": ([CAM, i32, qg_tiling], i64),
             "qg_decode_residuals": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, P, f32, f32, f32, P, P, P, P], i32),
@@ -121,12 +121,18 @@ def lib():
             "qg_proposal_bwd": ([i64, P, i64, i64, P, P, P, P, P, P, P, sz, P], i32),
             "qg_schedule_tiles": ([i64, P, P, i64, P], i32),
             "qg_gate_noise": ([i64, ctypes.c_uint64, i32, P, P, P], i32),
+            "qg_linear_decoder_params": ([ctypes.POINTER(i32)], i64),
+            "qg_decode_linear_blocks": ([i64], i64),
+            "qg_decode_linear": ([i64, i64, P, P, ctypes.POINTER(i32), P, P, P, P, f32, f32, f32, P, P, P, P], i32),
+            "qg_decode_linear_bwd_workspace_size": ([i64, ctypes.POINTER(i32)], sz),
+            "qg_decode_linear_bwd": ([i64, i64, P, ctypes.POINTER(i32), P, P, P, P, f32, f32, f32, P, f32, P, P, P, P,
+                                      P, sz, P], i32),
             "qg_densify_accumulate": ([i64, P, P, f32, f32, P, P, P], i32),
             "qg_densify_plan_workspace_size": ([i64], sz),
             "qg_densify_plan": ([i64, P, P, P, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P, sz,
                                  P], i32),
             "qg_densify_expand": ([i64, P, P, i32, P, i64, P, i64, i32, P], i32),
-            "qg_densify_split": ([i64, P, P, P, i64, ctypes.c_uint64, i32, P, i64, P], i32),
+            "qg_densify_children": ([i64, P, P, P, i64, ctypes.c_uint64, i32, P, i64, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -307,8 +313,8 @@ def qg_get_deterministic():
     return bool(lib().qg_get_deterministic())
 
 
-def qg_deterministic_workspace_size(n, capacity):
-    return int(lib().qg_deterministic_workspace_size(int(n), int(capacity)))
+def qg_deterministic_workspace_size(n, V, capacity):
+    return int(lib().qg_deterministic_workspace_size(int(n), int(V), int(capacity)))
 
 
 def qg_bin_workspace_size(n, V, capacity, total_tiles):
@@ -542,7 +548,40 @@ def qg_densify_expand(n, action, offsets, nplanes, src, ld_src, dst, ld_dst, mod
                                    int(ld_dst), int(mode), _stream(stream)))
 
 
-def qg_densify_split(n, action, offsets, decoded, ld, seed, rnd, prev_out, ld_out, stream=None):
-    _check(lib().qg_densify_split(int(n), _ptr(action), _ptr(offsets), _ptr(decoded), int(ld),
+def qg_densify_children(n, action, offsets, decoded, ld, seed, rnd, prev_out, ld_out, stream=None):
+    _check(lib().qg_densify_children(int(n), _ptr(action), _ptr(offsets), _ptr(decoded), int(ld),
                                   int(seed) & 0xFFFFFFFFFFFFFFFF, int(rnd), _ptr(prev_out), int(ld_out),
                                   _stream(stream)))
+
+
+def _dims(dims):
+    return (ctypes.c_int32 * 5)(*[int(d) for d in dims])
+
+
+def qg_linear_decoder_params(dims):
+    return int(lib().qg_linear_decoder_params(_dims(dims)))
+
+
+def qg_decode_linear_blocks(n):
+    return int(lib().qg_decode_linear_blocks(int(n)))
+
+
+def qg_decode_linear(n, ld, prev_attrs, latents, dims, D, pos_pre, gate_logit, gamma0, gamma1, tau, attrs_out,
+                     gate_out=None, lreg_partial=None, stream=None, gate_noise=None):
+    _check(lib().qg_decode_linear(int(n), int(ld), _ptr(prev_attrs), _ptr(latents), _dims(dims), _ptr(D), _ptr(pos_pre),
+                                  _ptr(gate_logit), _ptr(gate_noise), float(gamma0), float(gamma1), float(tau),
+                                  _ptr(attrs_out), _ptr(gate_out), _ptr(lreg_partial), _stream(stream)))
+
+
+def qg_decode_linear_bwd_workspace_size(n, dims):
+    return int(lib().qg_decode_linear_bwd_workspace_size(int(n), _dims(dims)))
+
+
+def qg_decode_linear_bwd(n, ld, latents, dims, D, pos_pre, gate_logit, gamma0, gamma1, tau, grad_attrs, lambda_reg,
+                         grad_latents, grad_D, grad_pos_pre, grad_gate_logit, ws, ws_bytes, stream=None,
+                         gate_noise=None):
+    _check(lib().qg_decode_linear_bwd(int(n), int(ld), _ptr(latents), _dims(dims), _ptr(D), _ptr(pos_pre),
+                                      _ptr(gate_logit), _ptr(gate_noise), float(gamma0), float(gamma1), float(tau),
+                                      _ptr(grad_attrs), float(lambda_reg), _ptr(grad_latents), _ptr(grad_D),
+                                      _ptr(grad_pos_pre), _ptr(grad_gate_logit), _ptr(ws), int(ws_bytes),
+                                      _stream(stream)))

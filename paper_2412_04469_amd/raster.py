@@ -87,7 +87,7 @@ class Rasterizer:
 
     def det_ws_bytes(self) -> int:
         """Workspace the adjoint calls need on top of their own in deterministic mode (0 when it is off)."""
-        return qg.qg_deterministic_workspace_size(self.n, self.capacity) if qg.qg_get_deterministic() else 0
+        return qg.qg_deterministic_workspace_size(self.n, self.V, self.capacity) if qg.qg_get_deterministic() else 0
 
     # -- individual ABI steps -----------------------------------------------------------------
     def project(self, attrs, stream=None):

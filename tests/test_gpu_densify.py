@@ -3,9 +3,10 @@
 * gate noise: the same Philox counters on both sides give the same uniforms; the logistic samples agree to
   float32 rounding, from a host step count and from the device step counter;
 * decode with the noisy gate (forward and backward, two-call and fused forms) against the oracle's decode;
-* densification: statistic, plan (actions and offsets exact), expansion (exact copies), split children
-  (mean offset and scale change) against oracle/densify.py on the same float32 inputs; then the whole stage on
-  a fitter, whose children decode like their parents.
+* densification: statistic, plan (actions and offsets exact), expansion (exact copies), clone children
+  (opacity) and split children (mean offset and scale change) against oracle/densify.py on the same float32
+  inputs; then the whole stage on a fitter, whose children decode like their parents (a coincident clone pair
+  like the parent at its centre, a split child like the split of its parent).
 """
 import dataclasses
 import math
@@ -142,7 +143,7 @@ def test_densify_kernels_against_oracle(qgm):
     assert len(parent) == n2
     d_prev2 = torch.empty(59, n2, device="cuda")
     qg.qg_densify_expand(n, act, off, 59, to_dev(prev), n, d_prev2, n2, 0)
-    qg.qg_densify_split(n, act, off, d_dec, n, 99, 3, d_prev2, n2)
+    qg.qg_densify_children(n, act, off, d_dec, n, 99, 3, d_prev2, n2)
     outs = []
     for arr, mode in [(p, 0) for p in params] + [(m, 1) for m in moments]:
         dst = torch.empty(arr.shape[0], n2, device="cuda")
@@ -153,7 +154,13 @@ def test_densify_kernels_against_oracle(qgm):
         assert np.array_equal(got.cpu().numpy(), want.astype(np.float32))
     gp = d_prev2.cpu().numpy()
     split = r_act[parent] == ODS.SPLIT
-    assert np.array_equal(gp[:, ~split], r_prev[:, ~split].astype(np.float32))
+    clone = r_act[parent] == ODS.CLONE
+    kept = ~split & ~clone
+    assert np.array_equal(gp[:, kept], r_prev[:, kept].astype(np.float32))
+    other = [k for k in range(59) if k != 10]
+    assert np.array_equal(gp[np.ix_(other, np.flatnonzero(clone))], r_prev[np.ix_(other, np.flatnonzero(clone))]
+                          .astype(np.float32))
+    np.testing.assert_allclose(gp[10, clone], r_prev[10, clone], rtol=2e-6, atol=2e-6)
     assert np.array_equal(gp[3:7, split], r_prev[3:7, split].astype(np.float32))
     assert np.array_equal(gp[10:, split], r_prev[10:, split].astype(np.float32))
     np.testing.assert_allclose(gp[7:10, split], r_prev[7:10, split], atol=1e-6)
@@ -204,7 +211,15 @@ def test_densify_stage_on_a_fitter(qgm):
     g.decode()
     dec_child = g.attrs.cpu().numpy().astype(np.float64)
     split = ref_act[parent] == ODS.SPLIT
-    assert np.array_equal(dec_child[:, ~split], dec_parent[:, parent[~split]])
+    clone = ref_act[parent] == ODS.CLONE
+    same = ~split & ~clone
+    assert np.array_equal(dec_child[:, same], dec_parent[:, parent[same]])
+    other = [k for k in range(59) if k != 10]
+    cj = np.flatnonzero(clone)
+    assert np.array_equal(dec_child[np.ix_(other, cj)], dec_parent[np.ix_(other, parent[cj])])
+    o_par = 1.0 / (1.0 + np.exp(-dec_parent[10, parent[cj]]))
+    o_ch = 1.0 / (1.0 + np.exp(-dec_child[10, cj]))
+    np.testing.assert_allclose(1.0 - (1.0 - o_ch) ** 2, o_par, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(dec_child[7:10, split], dec_parent[7:10, parent[split]] - math.log(1.6), atol=1e-5)
     # the new fitter steps on (capacity sized, graphs not involved) and its statistic starts at zero
     assert g.d_count.sum().item() == 0

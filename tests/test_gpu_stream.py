@@ -45,25 +45,27 @@ def test_fitter_does_not_alias_its_initial_attributes():
 
 
 def test_proposal_reaches_the_plain_target_in_fewer_iterations():
-    """What the trained residual proposal gains: on a small dynamic scene (10% of the Gaussians on sinusoids),
-    the network is trained on the plain fits of frames 1-8 and judged on frames 9-16; proposal-initialised
-    frames reach each frame's plain target PSNR in fewer optimiser iterations on average than the plain,
-    zero-initialised fit.  Iterations are counted (not time), with the adjoints in deterministic mode so the
-    counts do not depend on the order of float atomics."""
+    """What the trained residual proposal gains, on the 50-frame dynamic workload's first 30 frames (300 k
+    Gaussians, 10% on sinusoids, 20 views at 1352x1014): the network is trained on the plain fits of frames 1-25
+    and judged on frames 26-30; proposal-initialised frames reach each frame's plain target PSNR (the plain fit's
+    held-out PSNR after 500 iterations) in fewer optimiser iterations on average than the plain, zero-initialised
+    fit.  Iterations are counted (not time), with the adjoints in deterministic mode so that the counts do not
+    depend on the order of float atomics."""
     from paper_2412_04469_amd import qg, stream, synth
     from paper_2412_04469_amd.fit import FitConfig
     qg.qg_set_deterministic(True)
     try:
-        wl = synth.workload_dynamic(n=20000, n_views=8, width=160, height=120)
+        wl = synth.workload_dynamic()
         seq = stream.Sequence(wl, FitConfig(), torch.device("cuda"))
-        recs, hist = stream.run_plain(seq, 16, iters=120, check_every=5)
-        prop, losses, _ = stream.train_proposal(hist, list(range(1, 9)), steps=400, batch=16384)
+        say = lambda m: print(m, flush=True)  # one line per frame
+        recs, hist = stream.run_plain(seq, 30, iters=500, check_every=25, log=say)
+        prop, losses, _ = stream.train_proposal(hist, list(range(1, 26)), log=say)
         assert losses[-1][1] < losses[0][1]
-        judged = stream.judge(seq, hist, recs, prop, list(range(9, 17)), iters=120, check_every=5)
-        s = stream.summarize(recs, judged, list(range(9, 17)))
+        judged = stream.judge(seq, hist, recs, prop, list(range(26, 31)), iters=500, check_every=25, log=say)
+        s = stream.summarize(recs, judged, list(range(26, 31)))
         print("proposal:", s, flush=True)
-        assert s["frames_reaching_target"] == 8
-        assert s["frames_using_proposal"] >= 6
+        assert s["frames_reaching_target"] == 5
+        assert s["frames_using_proposal"] >= 4
         assert s["mean_iters_to_target"] < s["plain_mean_iters_to_target"]
     finally:
         qg.qg_set_deterministic(False)

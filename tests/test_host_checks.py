@@ -64,3 +64,30 @@ def test_attribute_fitter_builds_its_tables_on_the_host():
     f.rast.num_pairs[0] = -1
     with pytest.raises(qg.QGError):
         f.overflowed()
+
+
+def test_autotune_cache_returns_the_stored_choice(tmp_path):
+    import json
+
+    from paper_2412_04469_amd import autotune as AT
+    cams, _, _ = _setup(n=10, views=3)
+    key = AT.cache_key(cams, 500_000)
+    assert key.endswith("|V3") and "n2^19" in key
+    path = str(tmp_path / "tune.json")
+    with open(path, "w") as f:
+        json.dump({key: {"tile": [32, 8], "batch": 256, "persistent": False, "ms": 6.1}}, f)
+
+    def never(**_):
+        raise AssertionError("a cached choice must not be timed")
+
+    best, table = AT.autotune(never, cache_path=path, key=key)
+    assert best == {"tile": (32, 8), "batch": 256, "persistent": False} and table == []
+    assert len(AT.candidates()) == 24
+
+
+def test_grouping_tuner_picks_the_fastest_reaching_candidate():
+    from paper_2412_04469_amd.autotune import tune_grouping
+    secs = {(2, 1.5): None, (4, 2.5): 0.31, (5, 2.0): 0.29, (10, 3.0): 1.2}
+    best, table = tune_grouping(lambda v, l: secs[(v, l)])
+    assert best == (5, 2.0) and len(table) == 4
+    assert tune_grouping(lambda v, l: None)[0] is None

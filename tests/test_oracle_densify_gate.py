@@ -104,12 +104,18 @@ def test_apply_clones_splits_prunes():
     npv, npar, nmom, parent = DS.apply(act, prev, dec, params, moments, seed=1, rnd=0, normals=z)
     assert len(parent) == n - 2 + 2 + 2 == 11
     assert parent.tolist() == [0, 1, 1, 2, 2, 4, 5, 5, 6, 6, 8]
-    # kept and cloned Gaussians: exact copies of everything; moments kept on the first child only
+    # kept Gaussians: exact copies; clones: copies apart from the opacity logit; moments on the first child only
     for j, i in enumerate(parent):
         for arr, src in zip(npar, params):
             assert np.array_equal(arr[:, j], src[:, i])
-        if act[i] != DS.SPLIT:
+        if act[i] == DS.KEEP:
             assert np.array_equal(npv[:, j], prev[:, i])
+        if act[i] == DS.CLONE:
+            keep_planes = [k for k in range(59) if k != 10]
+            assert np.array_equal(npv[keep_planes, j], prev[keep_planes, i])
+            o = 1.0 / (1.0 + math.exp(-dec[10, i]))
+            o2 = 1.0 / (1.0 + math.exp(-(dec[10, i] + npv[10, j] - prev[10, i])))
+            assert abs(1.0 - (1.0 - o2) ** 2 - o) < 1e-12
     for j in (0, 1, 5, 8, 10):
         for arr, src in zip(nmom, moments):
             assert np.array_equal(arr[:, j], src[:, parent[j]])
@@ -153,3 +159,24 @@ def test_accumulate_uses_ndc_units_and_visibility():
     acc, cnt = DS.accumulate(acc, cnt, g, np.array([1, 2, 0]), sx=2.0, sy=0.5)
     np.testing.assert_allclose(acc, [math.hypot(6.0, 2.0), 2.0, 0.0])
     assert cnt.tolist() == [1.0, 1.0, 0.0]
+
+
+@pytest.mark.parametrize("o", [0.01, 0.3, 0.5, 0.9, 0.999])
+def test_two_coincident_clones_composite_like_their_parent_at_its_centre(o):
+    """The clone's opacity rule against the plain compositor: one splat of opacity o, and two coincident copies of
+    opacity sigmoid(clone_logit(logit o)); equal at the pixel where the Gaussian factor is 1, close around it."""
+    from oracle import composite as OC
+    x = math.log(o / (1.0 - o))
+    o2 = 1.0 / (1.0 + math.exp(-DS.clone_logit(x)))
+    W, H = 21, 21
+    one = {"xy": np.array([[10.5, 10.5]]), "conic": np.array([[0.08, 0.01, 0.05]]), "opacity": np.array([o]),
+           "rgb": np.array([[0.9, 0.4, 0.2]]), "depth": np.array([2.0])}
+    two = {k: np.repeat(v, 2, 0) for k, v in one.items()}
+    two["opacity"] = np.array([o2, o2])
+    a = OC.composite_image(one, W, H, (0.1, 0.2, 0.3), alpha_min=0.0, alpha_max=1.0, t_min=0.0)
+    b = OC.composite_image(two, W, H, (0.1, 0.2, 0.3), alpha_min=0.0, alpha_max=1.0, t_min=0.0)
+    assert abs(a["t_final"][10, 10] - b["t_final"][10, 10]) < 1e-12
+    assert np.abs(a["image"][:, 10, 10] - b["image"][:, 10, 10]).max() < 1e-12
+    # off centre the pair is slightly more opaque: 1 - (1 - o'e)^2 - o e = o'^2 e (1 - e) >= 0
+    assert (b["t_final"] <= a["t_final"] + 1e-15).all()
+    assert np.abs(a["image"] - b["image"]).max() < 0.26 * o2 ** 2 + 1e-12
