@@ -81,12 +81,15 @@ class FitConfig:
 PAPER_OUT = (4, 3, 1, 3, 45)  # residual planes per category: rotation, scaling, opacity, colour base, frequencies
 
 
-def xavier_linear_decoder(seed: int, dims):
-    """Packed per-category decoders D_c [M_c][L_c], Xavier-uniform from a fixed seed."""
+def xavier_linear_decoder(seed: int, dims, gain=0.1):
+    """Packed per-category decoders D_c [M_c][L_c], uniform within gain x the Xavier bound, from a fixed seed.
+    With integer latents a latent unit moves an attribute by a column of D_c; at the full Xavier bound (~1 for the
+    opacity block) every latent that first rounds to +-1 jumps its Gaussian far, and the fit diverges, while a
+    tenth of it gives steps of a few hundredths."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([2412, 4469, 2000 + seed])))
     parts = []
     for L, M in zip(dims, PAPER_OUT):
-        a = math.sqrt(6.0 / (L + M))
+        a = gain * math.sqrt(6.0 / (L + M))
         parts.append(rng.uniform(-a, a, size=(M, L)).astype(np.float32).ravel())
     return np.concatenate(parts)
 
