@@ -683,6 +683,18 @@ def masked_section(args):
     flagged = [round(float(f.float().mean().item()), 4) for (_, f) in masks]
     pixels = [round(float(m.float().mean().item()), 4) for (m, _) in masks]
     dyn = int(gi.dyn.sum().item())
+    # the same split at the paper's threshold (t_d = 1e-3), reported beside the one used: the score is
+    # ||d|| / V in normalised device coordinates, the quantity the flags kernel compares
+    from paper_2412_04469_amd import qg
+    cam0 = wl.cams[0]
+    sx, sy = (cam0.width / 2.0) / V, (cam0.height / 2.0) / V
+    dyn_paper = torch.empty_like(gi.dyn)
+    qg.qg_dynamic_flags(wl.scene.n, gi.d, sx, sy, 1e-3, dyn_paper)
+    score = torch.hypot(gi.d[0].double() * sx, gi.d[1].double() * sy)
+    paper_td = {"t_d": 1e-3, "dynamic_gaussians": int(dyn_paper.sum().item()),
+                "score_max": float(score.max().item()),
+                "score_p999": float(torch.quantile(score.float(), 0.999).item()),
+                "note": "with no dynamic Gaussian no pixel is masked, so masked iterations equal plain ones"}
     order = np.random.default_rng(0)
     perm = np.concatenate([order.permutation(V) for _ in range(args.frame_iters // V + 2)])
     m_iters = int(math.ceil(args.mask_fraction * args.frame_iters))
@@ -734,7 +746,7 @@ def masked_section(args):
     torch.cuda.empty_cache()
     return {"workload": wl.name, "target_psnr_db": tgt, "iterations": args.frame_iters,
             "mask_fraction": args.mask_fraction, "masked_iterations": m_iters, "t_d": cfg.t_d,
-            "dilation_px": cfg.mask_dilate, "dynamic_gaussians": dyn,
+            "dilation_px": cfg.mask_dilate, "dynamic_gaussians": dyn, "paper_t_d": paper_td,
             "flagged_tile_fraction_per_view": flagged, "mask_pixel_fraction_per_view": pixels,
             "step_ms": {"plain": round(ms_plain, 4), "masked": round(ms_masked, 4)},
             "plain": {"sec_per_frame": traj_p[-1][1], "final_psnr_db": traj_p[-1][2],

@@ -240,15 +240,16 @@ qg_status qg_project(int64_t n, int64_t ld, const float* attrs, int32_t sh_degre
  * the 64-bit key (global tile id << 32) | float32 bits of depth, ties by Gaussian index -- the
  * per-tile depth order of Eq. 2.  Global tile id of view v = sum of the earlier views' tile counts +
  * ty * grid_w(v) + tx.  The sort is a stable LSD radix sort: the 32 depth bits are sorted once per
- * (view, Gaussian) before pairs are emitted, then the tile bits over the pairs; each 8-bit pass is one
- * kernel (digit offsets by decoupled look-back between workgroups).
+ * (view, Gaussian) before pairs are emitted, then the tile bits over the pairs; each 8-bit pass counts,
+ * scans and scatters in three kernels, with no waits between workgroups.  The per-(view, Gaussian) tile
+ * counts are scanned in one kernel by decoupled look-back between workgroups, whose waits are bounded.
  *   vals        [capacity] uint32 sorted Gaussian indices (within their view).
  *   keys        [capacity] uint64 sorted keys (optional, NULL to skip).
  *   tile_ranges [total_tiles][2] uint32 half-open spans into vals ([0,0) for an empty tile).
  *   num_pairs   [1] int64: the pair count P.  If P > capacity nothing is emitted, tile_ranges are all
  *               empty, and the caller must not render this step; re-run with capacity >= P.  -1 reports
- *               that a workgroup of the sort gave up waiting for its predecessors (an internal failure;
- *               the results of the call are invalid).
+ *               that a workgroup of the count scan gave up waiting for its predecessors (an internal
+ *               failure; the results of the call are invalid).
  *   ws          qg_bin_workspace_size(n, V, capacity, total_tiles) bytes.
  * capacity <= 2^32 - 1.  total_tiles = sum over views of ceil(W/tile_w) * ceil(H/tile_h).
  */

@@ -8,15 +8,15 @@
 // over V*n items instead of 4 passes over P pairs), and only the tile bits are sorted over the pairs
 // (2 passes for up to 65,536 tiles).
 //
-// Every pass is one kernel ("one sweep"): the global digit histograms of all passes are accumulated
-// while the keys are produced (depth keys, pair emission), and each pass kernel finds where its block's
-// items go by decoupled look-back: block b publishes its per-digit counts, adds up the counts (or the
-// already inclusive prefixes) of blocks b-1, b-2, ... and publishes its own inclusive prefix.  Blocks take
-// their logical index from a ticket counter when they start, so a block only ever waits for blocks that
-// are already running; every wait is bounded (a give-up sets an error word instead of hanging).  Inside a
-// block the rank of an item among equal digits is found with wave64 ballot matching on the digit bits and
-// per-wave digit counters in LDS, which keeps the sort stable.  The per-(view, Gaussian) tile counts are
-// scanned the same way, in one kernel.
+// Every 8-bit pass is reduce-then-scan, three kernels with no waits between workgroups: each block counts
+// its items' digits, one workgroup per digit scans those counts over the blocks, and each block then
+// places its items (stable ranks by wave64 ballot matching on the digit bits, per-wave digit counters in
+// LDS), orders them by digit in LDS and writes them out in digit runs.  The first depth pass makes its keys
+// from the projection on the fly.  The per-(view, Gaussian) tile counts are scanned in one kernel by
+// decoupled look-back: block b publishes its count, adds up the counts (or the already inclusive prefixes)
+// of blocks b-1, b-2, ... and publishes its own inclusive prefix.  Blocks take their logical index from a
+// ticket counter when they start, so a block only ever waits for blocks that are already running, and
+// every wait is bounded (a give-up sets an error word, reported as num_pairs = -1, instead of hanging).
 #include <algorithm>
 #include <mutex>
 
@@ -30,21 +30,16 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kMaxPasses = 4;
-
 // Look-back state word: 2 flag bits over a 62-bit value.
 constexpr uint64_t kFlagAgg = 1ull << 62;  // value = this block's own count
 constexpr uint64_t kFlagInc = 2ull << 62;  // value = inclusive prefix over blocks 0..b
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr uint32_t kMaxSpin = 1u << 22;    // polls before a wait gives up (never reached when blocks progress)
 
-constexpr int kHistCopies = 16;  // global histograms are kept in 16 copies to spread atomic contention
-
-// Per-sort control block in the workspace (zeroed by k_bin_init for every call).
-struct SortCtl {
-    uint32_t ticket[kMaxPasses + 1];  // per pass, and one for the count scan
-    uint32_t err;                     // non-zero if a look-back wait gave up
-    uint32_t ghist[kMaxPasses][kHistCopies][kRadix];
+// Control block of the count scan in the workspace (zeroed by k_bin_init for every call).
+struct ScanCtl {
+    uint32_t ticket;  // logical block index of the count scan
+    uint32_t err;     // non-zero if a look-back wait gave up
 };
 
 __device__ __forceinline__ void store_state(uint64_t* p, uint64_t v) {
@@ -54,50 +49,10 @@ __device__ __forceinline__ uint64_t load_state(const uint64_t* p) {
     return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of block `bid` over blocks 0..bid-1 for one counter (this thread's), given the published
-// states at lb[j * stride].  The states of up to kWindow predecessors are loaded together, then consumed
-// nearest first until an inclusive prefix (done) or a state not yet published (re-load from there).
-// Gives up (recording it in *err) after kMaxSpin rounds without progress.
-constexpr int kWindow = 8;
-
-__device__ __forceinline__ uint64_t look_back(const uint64_t* lb, int64_t stride, uint32_t bid, uint32_t* err) {
-    uint64_t excl = 0;
-    int64_t j = (int64_t)bid - 1;  // nearest predecessor not yet consumed
-    uint32_t spins = 0;
-    while (j >= 0) {
-        uint64_t st[kWindow];
-#pragma unroll
-        for (int w = 0; w < kWindow; ++w) st[w] = j - w >= 0 ? load_state(lb + (j - w) * stride) : kFlagInc;
-        int used = 0;
-        bool done = false;
-#pragma unroll
-        for (int w = 0; w < kWindow; ++w) {
-            if (done || used < w) continue;  // stopped earlier in this window
-            const uint64_t f = st[w] & ~kValMask;
-            if (f == 0) continue;  // not published yet: used stays at w
-            excl += st[w] & kValMask;
-            used = w + 1;
-            done = f == kFlagInc;
-        }
-        if (done) break;
-        j -= used;
-        if (used == 0) {
-            if (++spins > kMaxSpin) {
-                atomicOr(err, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        } else {
-            spins = 0;
-        }
-    }
-    return excl;
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
-// As look_back for one counter, by a whole wave: lane l reads the state of predecessor j - l, so one round
-// covers 64 predecessors.  The lanes up to the nearest inclusive prefix (or up to the first state not yet
+// Exclusive prefix of block `bid` over blocks 0..bid-1, given the published states at lb[0 .. bid), by a
+// whole wave: lane l reads the state of predecessor j - l, so one round covers 64 predecessors.  The lanes up to the nearest inclusive prefix (or up to the first state not yet
 // published, which ends the round) are summed by a wave reduction.  Every lane returns the prefix.
 __device__ __forceinline__ uint64_t look_back_wave(const uint64_t* lb, uint32_t bid, uint32_t* err) {
     const int lane = __lane_id();
@@ -187,174 +142,69 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d) {
     }
 }
 
-// Adds this block's LDS digit histograms of `npass` passes (s_h[p][d]) into copy (block % 16) of the
-// global ones.
-__device__ __forceinline__ void flush_hists(const uint32_t (*s_h)[kRadix], int npass, SortCtl* ctl) {
-    const int copy = blockIdx.x % kHistCopies;
-    for (int p = 0; p < npass; ++p) {
-        const uint32_t c = s_h[p][threadIdx.x];
-        if (c) atomicAdd(&ctl->ghist[p][copy][threadIdx.x], c);
-    }
-}
-
-// Count of digit threadIdx.x in pass p (sum of the copies).
-__device__ __forceinline__ uint32_t digit_total(const SortCtl* ctl, int p) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int c = 0; c < kHistCopies; ++c) s += ctl->ghist[p][c][threadIdx.x];
-    return s;
-}
-
 // ------------------------------------------------------------------------------------------------
-// One stable radix pass.  Item r of lane l in wave w of block b sits at b*TILE + w*(IPT*64) + r*64 + l
-// (wave-contiguous, so within a wave the rounds are in element order and waves are in element order).
-// The block first orders its items by digit in LDS (stable), then writes them out in that order: each
-// digit's items land at consecutive output positions, so neighbouring threads write neighbouring words
-// instead of every item being a scattered 4-byte write.
-// lb_cur: [nblocks][256] look-back states of this pass (zero on entry); lb_next, if given, is the next
-// pass's array: every block clears its own slot there.  A block with items issues their loads and the
-// reads of the pass histogram together, so that they share one wait for memory.
-// ------------------------------------------------------------------------------------------------
-template <int IPT>
-__global__ __launch_bounds__(kBlock) void k_onesweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                     const uint32_t* __restrict__ count_ptr, uint32_t count_fixed,
-                                                     int pass, SortCtl* ctl, uint64_t* lb_cur, uint64_t* lb_next) {
-    __shared__ uint32_t s_cnt[kWaves][kRadix];
-    __shared__ uint32_t s_w[kWaves];
-    __shared__ uint32_t s_bid;
-    __shared__ uint32_t s_goff[kRadix];  // output position - block-local position, per digit
-    __shared__ uint32_t s_key[IPT * kBlock], s_val[IPT * kBlock];
-    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
-    if (tid == 0) s_bid = atomicAdd(&ctl->ticket[pass], 1u);
-    __syncthreads();
-    const uint32_t bid = s_bid;
-    if (lb_next) lb_next[(size_t)bid * kRadix + tid] = 0ull;
-    const uint32_t count = count_ptr ? *count_ptr : count_fixed;
-    const uint64_t blk0 = (uint64_t)bid * (IPT * kBlock);
-    if (blk0 >= count) return;  // no items here; no later block has any either, so nobody waits for this one
-    const uint64_t base = blk0 + (uint64_t)w * (IPT * kWave);
-    uint32_t key[IPT], val[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint64_t idx = base + (uint64_t)r * kWave + lane;
-        const bool valid = idx < count;
-        key[r] = valid ? kin[idx] : 0u;
-        val[r] = valid ? vin[idx] : 0u;
-    }
-    const uint32_t dcount = digit_total(ctl, pass);  // count of digit tid in this pass, over all blocks
-    const int shift = kRadixBits * pass;
-    // global start of each digit: exclusive scan of the pass histogram
-    uint32_t dtot;
-    const uint32_t dbase = block_excl_scan<uint32_t>(dcount, s_w, &dtot);
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
-    __syncthreads();
-    // phase 1: per-wave digit counts; each item keeps its rank among the equal digits of its round, the
-    // round's count of that digit and the lowest lane holding it (8 | 8 | 16 bits)
-    uint32_t info[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint64_t idx = base + (uint64_t)r * kWave + lane;
-        const bool valid = idx < count;
-        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t m = match8(d, valid);
-        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt()), cnt = (uint32_t)__popcll(m);
-        if (valid && rank == 0) atomicAdd(&s_cnt[w][d], cnt);
-        info[r] = rank | (cnt << 8) | ((uint32_t)(__ffsll((unsigned long long)m) - 1) << 16);
-        __builtin_amdgcn_sched_barrier(0);  // one round at a time: the rounds' masks are not kept live together
-    }
-    __syncthreads();
-    // block total of digit tid, publish, look back, publish the inclusive prefix
-    uint32_t tot = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) tot += s_cnt[k][tid];
-    uint64_t* my = lb_cur + (size_t)bid * kRadix + tid;
-    uint64_t excl = 0;
-    if (bid == 0) {
-        store_state(my, kFlagInc | tot);
-    } else {
-        store_state(my, kFlagAgg | tot);
-        excl = look_back(lb_cur + tid, kRadix, bid, &ctl->err);
-        store_state(my, kFlagInc | (excl + tot));
-    }
-    // block-local start of digit tid (digits in order), and per-wave local starts within it
-    uint32_t ntot;
-    const uint32_t lbase = block_excl_scan<uint32_t>(tot, s_w, &ntot);
-    s_goff[tid] = dbase + (uint32_t)excl - lbase;
-    {
-        uint32_t run = lbase;
-#pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
-            const uint32_t c = s_cnt[k][tid];
-            s_cnt[k][tid] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-    // phase 2: stable ranks and scatter
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint64_t idx = base + (uint64_t)r * kWave + lane;
-        const bool valid = idx < count;
-        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
-        const uint32_t rank = info[r] & 0xffu;
-        uint32_t start = 0;
-        if (valid && rank == 0) start = atomicAdd(&s_cnt[w][d], (info[r] >> 8) & 0xffu);
-        start = __shfl(start, valid ? (int)(info[r] >> 16) : 0);  // a valid lane's digit group holds itself
-        if (valid) {
-            const uint32_t pos = start + rank;
-            s_key[pos] = key[r];
-            s_val[pos] = val[r];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads();
-    // phase 3: the block's items in digit order (ntot of them) to their output positions
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t i = (uint32_t)(r * kBlock + tid);
-        if (i < ntot) {
-            const uint32_t k = s_key[i];
-            const uint32_t pos = i + s_goff[(k >> shift) & (kRadix - 1)];
-            kout[pos] = k;
-            vout[pos] = s_val[i];
-        }
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
-// Tile passes: reduce, then scan, then scatter (no waits between workgroups).
-// Block b owns items [b * kRsTile, (b + 1) * kRsTile) in the wave-contiguous layout of k_onesweep.
+// One stable 8-bit radix pass: reduce, then scan, then scatter.
+// Block b owns IPT * 256 consecutive items; item r of lane l in wave w sits at b*TILE + w*(IPT*64) + r*64 + l
+// (wave-contiguous, so within a wave the rounds are in element order and the waves are in element order).
 //   k_rs_count: the block's digit counts -> cnt[d * nb_cap + b] (digit-major);
 //   k_rs_scan: per digit (one workgroup each), the exclusive scan of its counts over the blocks in place, and
 //              the digit's total;
 //   k_rs_scatter: the block's stable ranks (ballot matching), its digits' output starts (digit base from the
-//              totals + the scanned count of the earlier blocks), ordered through LDS and written by digit runs.
+//              totals + the scanned count of the earlier blocks), ordered through LDS and written by digit runs,
+//              so neighbouring threads write neighbouring words.
+// The item count is read on the device (count_ptr) or given (count_ptr == nullptr: count_fixed).  With
+// kGen (the first depth pass) there is no input array: item k = v*n + i is (view v, Gaussian i), its key the
+// bits of its depth (0xFFFFFFFF, last, if its rectangle is empty) and its value k.
 // ------------------------------------------------------------------------------------------------
-constexpr int kRsIPT = 16;
-constexpr int kRsTile = kRsIPT * kBlock;
+struct RsSrc {
+    const uint32_t* keys;  // [count], or nullptr with kGen
+    const uint32_t* vals;
+    const float* depth[QG_MAX_VIEWS];
+    const int32_t* ntiles[QG_MAX_VIEWS];
+    int64_t n;
+};
 
-__global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* __restrict__ kin,
-                                                     const uint32_t* __restrict__ count_ptr, int pass,
-                                                     uint32_t* __restrict__ cnt, int64_t nb_cap) {
+template <bool kGen>
+__device__ __forceinline__ uint32_t rs_key(const RsSrc& src, uint64_t idx) {
+    if constexpr (kGen) {
+        const int v = (int)(idx / (uint64_t)src.n);
+        const int64_t i = (int64_t)idx - (int64_t)v * src.n;
+        return src.ntiles[v][i] > 0 ? __float_as_uint(src.depth[v][i]) : 0xFFFFFFFFu;
+    } else {
+        return src.keys[idx];
+    }
+}
+
+template <bool kGen>
+__device__ __forceinline__ uint32_t rs_val(const RsSrc& src, uint64_t idx) {
+    if constexpr (kGen)
+        return (uint32_t)idx;
+    else
+        return src.vals[idx];
+}
+
+template <int IPT, bool kGen>
+__global__ __launch_bounds__(kBlock) void k_rs_count(RsSrc src, const uint32_t* __restrict__ count_ptr,
+                                                     uint32_t count_fixed, int pass, uint32_t* __restrict__ cnt,
+                                                     int64_t nb_cap) {
+    constexpr int kTile = IPT * kBlock;
     __shared__ uint32_t s_h[kRadix];
-    const uint32_t count = *count_ptr;
-    const uint64_t blk0 = (uint64_t)blockIdx.x * kRsTile;
+    const uint32_t count = count_ptr ? *count_ptr : count_fixed;
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kTile;
     if (blk0 >= count) return;
     s_h[threadIdx.x] = 0;
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = __lane_id();
-    const uint64_t base = blk0 + (uint64_t)w * (kRsIPT * kWave);
+    const uint64_t base = blk0 + (uint64_t)w * (IPT * kWave);
     const int shift = kRadixBits * pass;
-    uint32_t key[kRsIPT];
+    uint32_t key[IPT];
 #pragma unroll
-    for (int r = 0; r < kRsIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
-        key[r] = idx < count ? kin[idx] : 0u;
+        key[r] = idx < count ? rs_key<kGen>(src, idx) : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < kRsIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
         if (idx < count) hist_add(s_h, (key[r] >> shift) & (kRadix - 1));
     }
@@ -362,14 +212,15 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* __restrict_
     cnt[(size_t)threadIdx.x * nb_cap + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// One workgroup per digit: exclusive scan of cnt[d][0 .. nb) in place, nb from the device count; tot[d] = total.
+// One workgroup per digit: exclusive scan of cnt[d][0 .. nb) in place, nb from the item count; tot[d] = total.
 constexpr int kRsScanThreads = 1024;
 
+template <int IPT>
 __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(uint32_t* __restrict__ cnt, int64_t nb_cap,
                                                             const uint32_t* __restrict__ count_ptr,
-                                                            uint32_t* __restrict__ tot) {
+                                                            uint32_t count_fixed, uint32_t* __restrict__ tot) {
     __shared__ uint32_t s_w[kRsScanThreads / kWave];
-    const int64_t nb = ceil_div((int64_t)*count_ptr, kRsTile);
+    const int64_t nb = ceil_div((int64_t)(count_ptr ? *count_ptr : count_fixed), IPT * kBlock);
     uint32_t* row = cnt + (size_t)blockIdx.x * nb_cap;
     const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
     uint32_t carry = 0;
@@ -392,28 +243,29 @@ __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(uint32_t* __restrict
     if (tid == 0) tot[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+template <int IPT, bool kGen>
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(RsSrc src, uint32_t* __restrict__ kout,
                                                        uint32_t* __restrict__ vout,
-                                                       const uint32_t* __restrict__ count_ptr, int pass,
-                                                       const uint32_t* __restrict__ cnt, int64_t nb_cap,
+                                                       const uint32_t* __restrict__ count_ptr, uint32_t count_fixed,
+                                                       int pass, const uint32_t* __restrict__ cnt, int64_t nb_cap,
                                                        const uint32_t* __restrict__ tot) {
+    constexpr int kTile = IPT * kBlock;
     __shared__ uint32_t s_cnt[kWaves][kRadix];
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_goff[kRadix];
-    __shared__ uint32_t s_key[kRsTile], s_val[kRsTile];
+    __shared__ uint32_t s_key[kTile], s_val[kTile];
     const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
-    const uint32_t count = *count_ptr;
-    const uint64_t blk0 = (uint64_t)blockIdx.x * kRsTile;
+    const uint32_t count = count_ptr ? *count_ptr : count_fixed;
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kTile;
     if (blk0 >= count) return;
-    const uint64_t base = blk0 + (uint64_t)w * (kRsIPT * kWave);
-    uint32_t key[kRsIPT], val[kRsIPT];
+    const uint64_t base = blk0 + (uint64_t)w * (IPT * kWave);
+    uint32_t key[IPT], val[IPT];
 #pragma unroll
-    for (int r = 0; r < kRsIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
         const bool valid = idx < count;
-        key[r] = valid ? kin[idx] : 0u;
-        val[r] = valid ? vin[idx] : 0u;
+        key[r] = valid ? rs_key<kGen>(src, idx) : 0u;
+        val[r] = valid ? rs_val<kGen>(src, idx) : 0u;
     }
     // output start of digit tid before this block: digit base (scan of the totals) + the earlier blocks' count
     const uint32_t before = cnt[(size_t)tid * nb_cap + blockIdx.x];
@@ -423,9 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
     __syncthreads();
-    uint32_t info[kRsIPT];
+    // per-wave digit counts; each item keeps its rank among the equal digits of its round, the round's count
+    // of that digit and the lowest lane holding it (8 | 8 | 16 bits)
+    uint32_t info[IPT];
 #pragma unroll
-    for (int r = 0; r < kRsIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
         const bool valid = idx < count;
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
@@ -433,9 +287,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
         const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt()), c = (uint32_t)__popcll(m);
         if (valid && rank == 0) atomicAdd(&s_cnt[w][d], c);
         info[r] = rank | (c << 8) | ((uint32_t)(__ffsll((unsigned long long)m) - 1) << 16);
-        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);  // one round at a time: the rounds' masks are not kept live together
     }
     __syncthreads();
+    // block-local start of digit tid (digits in order), and per-wave local starts within it
     uint32_t btot = 0;
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) btot += s_cnt[k][tid];
@@ -452,15 +307,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
         }
     }
     __syncthreads();
+    // stable ranks, items to their block-local places in digit order
 #pragma unroll
-    for (int r = 0; r < kRsIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const uint64_t idx = base + (uint64_t)r * kWave + lane;
         const bool valid = idx < count;
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         const uint32_t rank = info[r] & 0xffu;
         uint32_t start = 0;
         if (valid && rank == 0) start = atomicAdd(&s_cnt[w][d], (info[r] >> 8) & 0xffu);
-        start = __shfl(start, valid ? (int)(info[r] >> 16) : 0);
+        start = __shfl(start, valid ? (int)(info[r] >> 16) : 0);  // a valid lane's digit group holds itself
         if (valid) {
             const uint32_t pos = start + rank;
             s_key[pos] = key[r];
@@ -469,8 +325,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
         __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
+    // the block's items in digit order (ntot of them) to their output positions
 #pragma unroll
-    for (int r = 0; r < kRsIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const uint32_t i = (uint32_t)(r * kBlock + tid);
         if (i < ntot) {
             const uint32_t k = s_key[i];
@@ -481,11 +338,40 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
     }
 }
 
+// Items per thread of a pass over up to max_count items: 4 for up to 2^20 items (a wider grid), else 16.
+int rs_ipt(int64_t max_count) { return max_count <= (1 << 20) ? 4 : 16; }
+int64_t rs_blocks(int64_t max_count) { return std::max<int64_t>(1, ceil_div(max_count, rs_ipt(max_count) * kBlock)); }
+
+// One pass from src to (kout, vout); cnt holds [256][nb_cap] counts with nb_cap >= rs_blocks(max_count).
+template <int IPT, bool kGen>
+void rs_launch(const RsSrc& src, uint32_t* kout, uint32_t* vout, const uint32_t* count_ptr, uint32_t count_fixed,
+               int64_t max_count, int pass, uint32_t* cnt, int64_t nb_cap, uint32_t* tot, hipStream_t s) {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, ceil_div(max_count, IPT * kBlock));
+    k_rs_count<IPT, kGen><<<nb, kBlock, 0, s>>>(src, count_ptr, count_fixed, pass, cnt, nb_cap);
+    k_rs_scan<IPT><<<kRadix, kRsScanThreads, 0, s>>>(cnt, nb_cap, count_ptr, count_fixed, tot);
+    k_rs_scatter<IPT, kGen><<<nb, kBlock, 0, s>>>(src, kout, vout, count_ptr, count_fixed, pass, cnt, nb_cap, tot);
+}
+
+template <bool kGen>
+qg_status rs_pass(const RsSrc& src, uint32_t* kout, uint32_t* vout, const uint32_t* count_ptr, uint32_t count_fixed,
+                  int64_t max_count, int pass, uint32_t* cnt, int64_t nb_cap, uint32_t* tot, hipStream_t s,
+                  const char* tag) {
+    {
+        QG_TIMED(tag, s);
+        if (rs_ipt(max_count) == 4)
+            rs_launch<4, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
+        else
+            rs_launch<16, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
+    }
+    QG_LAUNCH_CHECK("radix pass");
+    return QG_OK;
+}
+
 // ------------------------------------------------------------------------------------------------
 // Binning kernels
 // ------------------------------------------------------------------------------------------------
-// Zeroes the tile ranges, both control blocks and the look-back arrays that the first kernel of each
-// sweep reads (one grid-stride pass over a list of word ranges).
+// Zeroes the tile ranges, the count scan's control block and look-back states, num_pairs and the sort count
+// (one grid-stride pass over a list of word ranges).
 struct ZeroList {
     uint32_t* p[8];
     int64_t words[8];
@@ -498,32 +384,6 @@ __global__ void k_bin_init(ZeroList z) {
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.words[k]; i += stride) z.p[k][i] = 0u;
 }
 
-// Depth keys of every (view, Gaussian) item (non-visible items sort last) and the depth digit histograms
-// (grid-stride over a capped grid, so few blocks flush histograms).
-constexpr int kHistBlocks = 256;
-
-__global__ __launch_bounds__(kBlock) void k_depth_keys(int64_t n, ViewTable vt, uint32_t* __restrict__ keys,
-                                                       uint32_t* __restrict__ vals, SortCtl* ctl) {
-    __shared__ uint32_t s_h[4][kRadix];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) s_h[p][threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t items = n * vt.V;
-    for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < items;
-         item += (int64_t)gridDim.x * blockDim.x) {
-        const int v = (int)(item / n);
-        const int64_t i = item - (int64_t)v * n;
-        const ProjDev& p = vt.proj[v];
-        const uint32_t key = p.ntiles[i] > 0 ? __float_as_uint(p.depth[i]) : 0xFFFFFFFFu;
-        keys[item] = key;
-        vals[item] = (uint32_t)item;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) hist_add(s_h[q], (key >> (8 * q)) & 0xFFu);
-    }
-    __syncthreads();
-    flush_hists(s_h, 4, ctl);
-}
-
 // Exclusive scan (64-bit) of the tile counts of the items in depth order, in one kernel with look-back;
 // the block holding the last item also writes the total, the tile sort's count (0 on overflow) and the
 // caller's num_pairs.
@@ -533,12 +393,12 @@ constexpr int kScanTile = kBlock * kScanIPT;
 __global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n, ViewTable vt,
                                                        const uint32_t* __restrict__ sorted, uint64_t* __restrict__ offs,
                                                        int64_t capacity, uint32_t* __restrict__ sort_count,
-                                                       int64_t* __restrict__ num_pairs, SortCtl* ctl,
+                                                       int64_t* __restrict__ num_pairs, ScanCtl* ctl,
                                                        uint64_t* lb) {
     __shared__ uint64_t s_w[kWaves];
     __shared__ uint32_t s_bid;
     __shared__ uint64_t s_excl;
-    if (threadIdx.x == 0) s_bid = atomicAdd(&ctl->ticket[kMaxPasses], 1u);
+    if (threadIdx.x == 0) s_bid = atomicAdd(&ctl->ticket, 1u);
     __syncthreads();
     const uint32_t bid = s_bid;
     const int64_t base = (int64_t)bid * kScanTile + (int64_t)threadIdx.x * kScanIPT;
@@ -573,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n,
         const uint64_t excl = s_excl;
         if ((int64_t)(bid + 1) * kScanTile >= items) {  // the last block
             const uint64_t t = excl + btot;
-            const bool failed = atomicAdd(&ctl->err, 0u) != 0;  // a depth pass or this scan gave up waiting
+            const bool failed = atomicAdd(&ctl->err, 0u) != 0;  // a wait of this scan gave up
             *num_pairs = failed ? -1 : (int64_t)t;
             *sort_count = (!failed && t <= (uint64_t)capacity) ? (uint32_t)t : 0u;
         }
@@ -591,23 +451,17 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n,
 // Emission, one thread per output pair (load-balanced whatever the rectangle sizes): a block owns 1024
 // consecutive output positions; the (view, Gaussian) items that cover them are consecutive in depth order
 // (every item with a non-empty rectangle owns at least one position, empty ones were sorted last), so the
-// block loads their offsets into LDS and each position finds its item by binary search there.  Blocks loop
-// over chunks of a capped grid; the tile digit histograms of the following passes are accumulated on the
-// way and flushed once per block.
+// block loads their offsets into LDS and each position finds its item by binary search there.
 constexpr int kEmitPer = 1024;
 
 __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTable vt,
                                               const uint32_t* __restrict__ sorted,
                                               const uint64_t* __restrict__ offs,
-                                              const uint32_t* __restrict__ sort_count, int tpasses,
-                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals,
-                                              SortCtl* ctl) {
+                                              const uint32_t* __restrict__ sort_count,
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
     __shared__ uint64_t s_off[kEmitPer];
-    __shared__ uint32_t s_h[kMaxPasses][kRadix];
     __shared__ int64_t s_k0;
     const uint64_t P = *sort_count;
-#pragma unroll
-    for (int q = 0; q < kMaxPasses; ++q) s_h[q][threadIdx.x] = 0;
     for (uint64_t chunk = blockIdx.x; chunk * kEmitPer < P; chunk += gridDim.x) {
         const uint64_t base = chunk * kEmitPer;
         __syncthreads();  // the previous chunk is done with s_off
@@ -654,19 +508,15 @@ __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTabl
             const uint32_t key = vt.cam[v].tile_off + ty * (uint32_t)vt.cam[v].grid_w + tx;
             tkeys[p] = key;
             tvals[p] = (uint32_t)i;
-            for (int q = 0; q < tpasses; ++q) hist_add(s_h[q], (key >> (8 * q)) & 0xFFu);
         }
     }
-    __syncthreads();
-    flush_hists(s_h, tpasses, ctl);
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ sort_count,
-                         uint32_t* __restrict__ ranges, SortCtl* ctl, int64_t* __restrict__ num_pairs) {
+                         uint32_t* __restrict__ ranges) {
     const uint32_t P = *sort_count;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    if (p == 0 && atomicAdd(&ctl->err, 0u) != 0) *num_pairs = -1;  // a tile pass gave up waiting
     const uint32_t t = tkeys[p];
     if (p == 0 || tkeys[p - 1] != t) ranges[2 * (size_t)t] = (uint32_t)p;
     if (p == (int64_t)P - 1 || tkeys[p + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)p + 1;
@@ -685,36 +535,16 @@ __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __r
     keys[p] = ((uint64_t)t << 32) | db;
 }
 
-int ipt_for(int64_t max_count) { return max_count <= (1 << 16) ? 4 : 16; }
-int64_t sweep_blocks(int64_t max_count) { return std::max<int64_t>(1, ceil_div(max_count, ipt_for(max_count) * kBlock)); }
-
-qg_status sweep_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const uint32_t* count_ptr,
-                     uint32_t count_fixed, int64_t max_count, int pass, SortCtl* ctl, uint64_t* lb_cur,
-                     uint64_t* lb_next, hipStream_t s, const char* tag) {
-    const unsigned nb = (unsigned)sweep_blocks(max_count);
-    {
-        QG_TIMED(tag, s);
-        if (ipt_for(max_count) == 4)
-            k_onesweep<4><<<nb, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, pass, ctl, lb_cur, lb_next);
-        else
-            k_onesweep<16><<<nb, kBlock, 0, s>>>(kin, vin, kout, vout, count_ptr, count_fixed, pass, ctl, lb_cur,
-                                                 lb_next);
-    }
-    QG_LAUNCH_CHECK("radix pass");
-    return QG_OK;
-}
-
 struct BinWs {
     uint32_t *dkA, *dkB, *dvA, *dvB;  // depth sort, V*n
     uint64_t* offs;                   // V*n
     uint32_t* sort_count;
     uint32_t *tkA, *tkB, *tvB;        // tile sort, capacity
-    SortCtl *ctl_depth, *ctl_tile;
-    uint64_t *lb_d0, *lb_d1;          // depth look-back, [blocks][256] each
-    uint32_t* rs_cnt;                 // tile passes: per-block digit counts [256][nb_rs], scanned in place
-    uint32_t* rs_tot;                 // tile passes: digit totals [256]
+    ScanCtl* ctl;                     // count scan
+    uint32_t* rs_cnt;                 // radix passes: per-block digit counts [256][nb_cnt], scanned in place
+    uint32_t* rs_tot;                 // radix passes: digit totals [256]
     uint64_t* lb_scan;                // count-scan look-back, [blocks]
-    int64_t nb_depth, nb_rs, nb_scan;
+    int64_t nb_cnt, nb_scan;
     size_t bytes;
 };
 
@@ -729,8 +559,7 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     const int64_t items = n * V;
     const int64_t it1 = std::max<int64_t>(items, 1);
     const int64_t cap1 = std::max<int64_t>(capacity, 1);
-    w.nb_depth = sweep_blocks(it1);
-    w.nb_rs = std::max<int64_t>(1, ceil_div(cap1, kRsTile));
+    w.nb_cnt = std::max(rs_blocks(it1), rs_blocks(cap1));
     w.nb_scan = std::max<int64_t>(1, ceil_div(it1, kScanTile));
     w.dkA = (uint32_t*)take(4 * it1);
     w.dkB = (uint32_t*)take(4 * it1);
@@ -741,11 +570,8 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     w.tkA = (uint32_t*)take(4 * cap1);
     w.tkB = (uint32_t*)take(4 * cap1);
     w.tvB = (uint32_t*)take(4 * cap1);
-    w.ctl_depth = (SortCtl*)take(sizeof(SortCtl));
-    w.ctl_tile = (SortCtl*)take(sizeof(SortCtl));
-    w.lb_d0 = (uint64_t*)take(8 * kRadix * w.nb_depth);
-    w.lb_d1 = (uint64_t*)take(8 * kRadix * w.nb_depth);
-    w.rs_cnt = (uint32_t*)take(4 * kRadix * w.nb_rs);
+    w.ctl = (ScanCtl*)take(sizeof(ScanCtl));
+    w.rs_cnt = (uint32_t*)take(4 * kRadix * w.nb_cnt);
     w.rs_tot = (uint32_t*)take(4 * kRadix);
     w.lb_scan = (uint64_t*)take(8 * w.nb_scan);
     w.bytes = off;
@@ -793,26 +619,20 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     int tbits = 1;
     while ((1ll << tbits) < T) ++tbits;
     const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
-    // 0. clear the ranges, the control blocks and the first look-back array of each sweep
+    // 0. clear the ranges, the count scan's control block and look-back states, num_pairs and the sort count
     {
         ZeroList z{};
         z.p[0] = tile_ranges;
         z.words[0] = 2 * T;
-        z.p[1] = (uint32_t*)w.ctl_depth;
-        z.words[1] = sizeof(SortCtl) / 4;
-        z.p[2] = (uint32_t*)w.ctl_tile;
-        z.words[2] = sizeof(SortCtl) / 4;
-        z.p[3] = (uint32_t*)w.lb_d0;
-        z.words[3] = items > 0 ? 2 * kRadix * w.nb_depth : 0;
-        z.p[4] = w.rs_tot;  // (nothing of the tile passes needs clearing)
-        z.words[4] = 0;
-        z.p[5] = (uint32_t*)w.lb_scan;
-        z.words[5] = 2 * w.nb_scan;
-        z.p[6] = (uint32_t*)num_pairs;  // stays 0 for an empty input
-        z.words[6] = 2;
-        z.p[7] = w.sort_count;
-        z.words[7] = 1;
-        z.n = 8;
+        z.p[1] = (uint32_t*)w.ctl;
+        z.words[1] = sizeof(ScanCtl) / 4;
+        z.p[2] = (uint32_t*)w.lb_scan;
+        z.words[2] = 2 * w.nb_scan;
+        z.p[3] = (uint32_t*)num_pairs;  // stays 0 for an empty input
+        z.words[3] = 2;
+        z.p[4] = w.sort_count;
+        z.words[4] = 1;
+        z.n = 5;
         int64_t most = 0;
         for (int k = 0; k < z.n; ++k) most = std::max(most, z.words[k]);
         QG_TIMED("bin_init", s);
@@ -820,29 +640,35 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     }
     QG_LAUNCH_CHECK("qg_bin init");
     if (items == 0) return QG_OK;
-    // 1. depth keys (+ histograms) and the 4-pass depth sort over (view, Gaussian) items
-    {
-        QG_TIMED("bin_depth_keys", s);
-        k_depth_keys<<<(unsigned)std::min<int64_t>(ceil_div(items, kBlock), kHistBlocks), kBlock, 0, s>>>(
-            n, vt, w.dkA, w.dvA, w.ctl_depth);
+    // 1. the 4-pass depth sort over (view, Gaussian) items; the first pass makes the keys
+    RsSrc src{};
+    src.n = n;
+    for (int v = 0; v < V; ++v) {
+        src.depth[v] = vt.proj[v].depth;
+        src.ntiles[v] = vt.proj[v].ntiles;
     }
-    QG_LAUNCH_CHECK("qg_bin depth keys");
     uint32_t *ka = w.dkA, *va = w.dvA, *kb = w.dkB, *vb = w.dvB;
-    uint64_t *la = w.lb_d0, *lbb = w.lb_d1;
     for (int pass = 0; pass < 4; ++pass) {
-        qg_status st = sweep_pass(ka, va, kb, vb, nullptr, (uint32_t)items, items, pass, w.ctl_depth, la,
-                                  pass < 3 ? lbb : nullptr, s, "sort_depth");
+        qg_status st;
+        if (pass == 0) {
+            st = rs_pass<true>(src, ka, va, nullptr, (uint32_t)items, items, pass, w.rs_cnt, w.nb_cnt, w.rs_tot, s,
+                               "sort_depth");
+        } else {
+            src.keys = ka;
+            src.vals = va;
+            st = rs_pass<false>(src, kb, vb, nullptr, (uint32_t)items, items, pass, w.rs_cnt, w.nb_cnt, w.rs_tot, s,
+                                "sort_depth");
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
         if (st != QG_OK) return st;
-        std::swap(ka, kb);
-        std::swap(va, vb);
-        std::swap(la, lbb);
     }
     const uint32_t* sorted_items = va;
     // 2. tile counts in depth order: one-kernel scan, total, overflow check
     {
         QG_TIMED("bin_count_scan", s);
         k_count_scan<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.offs, capacity, w.sort_count,
-                                                             num_pairs, w.ctl_depth, w.lb_scan);
+                                                             num_pairs, w.ctl, w.lb_scan);
     }
     QG_LAUNCH_CHECK("qg_bin count");
     if (capacity == 0) return QG_OK;
@@ -851,20 +677,18 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     {
         QG_TIMED("bin_emit", s);
         k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(items, n, vt, sorted_items, w.offs,
-                                                                      w.sort_count, 0, w.tkA, vbuf0, w.ctl_tile);
+                                                                      w.sort_count, w.tkA, vbuf0);
     }
     QG_LAUNCH_CHECK("qg_bin emit");
     // 3. stable sort by tile id: reduce, scan and scatter per 8-bit pass
     uint32_t *tk_in = w.tkA, *tk_out = w.tkB, *tv_in = vbuf0, *tv_out = vbuf1;
     for (int pass = 0; pass < tpasses; ++pass) {
-        {
-            QG_TIMED("sort_tile", s);
-            k_rs_count<<<(unsigned)w.nb_rs, kBlock, 0, s>>>(tk_in, w.sort_count, pass, w.rs_cnt, w.nb_rs);
-            k_rs_scan<<<kRadix, kRsScanThreads, 0, s>>>(w.rs_cnt, w.nb_rs, w.sort_count, w.rs_tot);
-            k_rs_scatter<<<(unsigned)w.nb_rs, kBlock, 0, s>>>(tk_in, tv_in, tk_out, tv_out, w.sort_count, pass,
-                                                              w.rs_cnt, w.nb_rs, w.rs_tot);
-        }
-        QG_LAUNCH_CHECK("radix pass (tile)");
+        RsSrc ts{};
+        ts.keys = tk_in;
+        ts.vals = tv_in;
+        qg_status st = rs_pass<false>(ts, tk_out, tv_out, w.sort_count, 0u, capacity, pass, w.rs_cnt, w.nb_cnt,
+                                      w.rs_tot, s, "sort_tile");
+        if (st != QG_OK) return st;
         std::swap(tk_in, tk_out);
         std::swap(tv_in, tv_out);
     }
@@ -872,8 +696,7 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     // 4. tile ranges (and optional 64-bit keys)
     {
         QG_TIMED("bin_ranges", s);
-        k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges, w.ctl_tile,
-                                                                   num_pairs);
+        k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges);
     }
     QG_LAUNCH_CHECK("qg_bin ranges");
     if (keys) {
