@@ -55,6 +55,37 @@ struct ViewPtrsCU {
 // run of tiles: neighbouring tiles share splats, so they should share an L2.
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t per_xcd) { return (b % 8) * per_xcd + b / 8; }
 
+// Tile order of the blend kernels' plain grid.  Workgroups are dispatched to the 8 XCDs round-robin (block b
+// runs on XCD b % 8), and each XCD has its own L2.  Tiles are grouped into super-tiles of S x S tiles (per
+// view, padded at the right and bottom edges); super-tile j goes to XCD j % 8, and its S*S tiles run as
+// consecutive workgroups of that XCD.  Neighbouring tiles, which share most of their Gaussians, thus share an
+// L2, while every XCD gets super-tiles from all over the image: the dense middle of a view is spread over
+// all eight XCDs instead of falling to the one or two that a contiguous band of tiles would give it.
+struct TileMap {
+    int32_t S;                         // super-tile side in tiles
+    int32_t V;
+    int64_t supers;                    // super-tiles over all views
+    int32_t sup_off[QG_MAX_VIEWS + 1];  // first super-tile of each view
+    int32_t sw[QG_MAX_VIEWS];          // super-tiles per row of each view
+};
+
+// Global tile of workgroup b, or -1 for a workgroup that falls on padding.
+__device__ __forceinline__ int64_t map_tile(const TileMap& m, const ViewTable& vt, int64_t b) {
+    const int S2 = m.S * m.S;
+    const int64_t k = b >> 3;
+    const int64_t j = (k / S2) * 8 + (b & 7);
+    if (j >= m.supers) return -1;
+    const int mm = (int)(k % S2);
+    int v = 0;
+    while (v + 1 < m.V && j >= m.sup_off[v + 1]) ++v;
+    const int64_t jl = j - m.sup_off[v];
+    const int tx = (int)(jl % m.sw[v]) * m.S + mm % m.S;
+    const int ty = (int)(jl / m.sw[v]) * m.S + mm / m.S;
+    const CamDev& c = vt.cam[v];
+    if (tx >= c.grid_w || ty >= c.grid_h) return -1;
+    return (int64_t)c.tile_off + (int64_t)ty * c.grid_w + tx;
+}
+
 __device__ __forceinline__ int view_of_tile(const ViewTable& vt, uint32_t t) {
     int v = 0;
     for (int k = 1; k < vt.V; ++k)
@@ -250,14 +281,14 @@ template <int TW, int TH, int BD>
 __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, float bg0, float bg1,
                                                    float bg2, ViewPtrsF image, ViewPtrsF tfinal, ViewPtrsU lastp,
-                                                   int64_t per_xcd, Sched sc) {
+                                                   TileMap tm, Sched sc) {
     __shared__ float4 s_a[BD];  // x, y, o, A'
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float s_c[BD];   // b
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     if (sc.order == nullptr) {
-        const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
-        if (tile < vt.total_tiles)
+        const int64_t tile = map_tile(tm, vt, blockIdx.x);
+        if (tile >= 0)
             fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c, s_pos);
         return;
     }
@@ -469,7 +500,7 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
                                                    const uint32_t* __restrict__ ranges, float bg0, float bg1,
                                                    float bg2, ViewPtrsCF tfinal, ViewPtrsCU lastp, ViewPtrsCF gimage,
                                                    float* __restrict__ grad2d, int64_t g2d_view_stride,
-                                                   PairPart pp, int64_t per_xcd, Sched sc) {
+                                                   PairPart pp, TileMap tm, Sched sc) {
     __shared__ float4 s_a[BD];  // x, y, o, A'
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float4 s_c[BD];  // b, A, B, C
@@ -477,8 +508,8 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     __shared__ float s_red[8][12];  // half-row totals of the 9 gradient components
     if (sc.order == nullptr) {
-        const int64_t tile = xcd_tile(blockIdx.x, per_xcd);
-        if (tile < vt.total_tiles)
+        const int64_t tile = map_tile(tm, vt, blockIdx.x);
+        if (tile >= 0)
             bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp,
                                  tile, s_a, s_b, s_c, s_gid, s_pos, s_red);
         return;
@@ -511,6 +542,25 @@ int64_t resident_blocks(const void* kernel) {
     return r;
 }
 
+// The plain grid's tile order (super-tiles of 4 x 4 tiles) and its size, a multiple of 8 * 16 workgroups.
+constexpr int kSuperTile = 4;
+
+TileMap make_tile_map(const ViewTable& vt, int64_t* grid) {
+    TileMap m{};
+    m.S = kSuperTile;
+    m.V = vt.V;
+    int64_t j = 0;
+    for (int v = 0; v < vt.V; ++v) {
+        m.sup_off[v] = (int32_t)j;
+        m.sw[v] = (int32_t)ceil_div(vt.cam[v].grid_w, kSuperTile);
+        j += (int64_t)m.sw[v] * ceil_div(vt.cam[v].grid_h, kSuperTile);
+    }
+    m.sup_off[vt.V] = (int32_t)j;
+    m.supers = j;
+    *grid = ceil_div(j, 8) * 8 * kSuperTile * kSuperTile;
+    return m;
+}
+
 inline Sched make_sched(const qg_tiling& t, int64_t total_tiles) {
     Sched sc = {nullptr, nullptr};
     if (t.schedule) {
@@ -525,9 +575,9 @@ template <int TW, int TH, int BD>
 qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp,
                        hipStream_t s) {
-    const int64_t per = ceil_div(vt.total_tiles, 8);
+    int64_t grid = 0;
+    const TileMap tm = make_tile_map(vt, &grid);
     const Sched sc = make_sched(tiling, vt.total_tiles);
-    int64_t grid = per * 8;
     if (sc.order) {
         const int64_t res = resident_blocks(reinterpret_cast<const void*>(k_render_fwd<TW, TH, BD>));
         QG_REQUIRE(res > 0, "occupancy query failed");
@@ -536,7 +586,7 @@ qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
     {
         QG_TIMED("render_fwd", s);
         k_render_fwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp,
-                                                                per, sc);
+                                                                tm, sc);
     }
     QG_LAUNCH_CHECK("qg_render_fwd");
     return QG_OK;
@@ -546,9 +596,9 @@ template <int TW, int TH, int BD>
 qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
                        float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
-    const int64_t per = ceil_div(vt.total_tiles, 8);
+    int64_t grid = 0;
+    const TileMap tm = make_tile_map(vt, &grid);
     const Sched sc = make_sched(tiling, vt.total_tiles);
-    int64_t grid = per * 8;
     if (sc.order) {
         const int64_t res = resident_blocks(reinterpret_cast<const void*>(k_render_bwd<TW, TH, BD>));
         QG_REQUIRE(res > 0, "occupancy query failed");
@@ -557,7 +607,7 @@ qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
     {
         QG_TIMED("blend_bwd", s);
         k_render_bwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
-                                                                grad2d, stride, pp, per, sc);
+                                                                grad2d, stride, pp, tm, sc);
     }
     QG_LAUNCH_CHECK("qg_render_bwd");
     return QG_OK;
