@@ -448,18 +448,20 @@ __global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n,
     }
 }
 
-// Emission, one thread per output pair (load-balanced whatever the rectangle sizes): a block owns 1024
-// consecutive output positions; the (view, Gaussian) items that cover them are consecutive in depth order
-// (every item with a non-empty rectangle owns at least one position, empty ones were sorted last), so the
-// block loads their offsets into LDS and each position finds its item by binary search there.
+// Emission, load-balanced whatever the rectangle sizes: a block owns 1024 consecutive output positions, four
+// consecutive ones per thread.  The (view, Gaussian) items that cover them are consecutive in depth order
+// (every item with a non-empty rectangle owns at least one position; empty ones were sorted last), so the
+// block loads their offsets into LDS; a thread finds the item of its first position by binary search there
+// and walks forward for the next three, and writes its four keys and values with one 16-byte store each.
 constexpr int kEmitPer = 1024;
+constexpr int kEmitPerThread = kEmitPer / 256;
 
 __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTable vt,
                                               const uint32_t* __restrict__ sorted,
                                               const uint64_t* __restrict__ offs,
                                               const uint32_t* __restrict__ sort_count,
                                               uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
-    __shared__ uint64_t s_off[kEmitPer];
+    __shared__ uint64_t s_off[kEmitPer + 1];
     __shared__ int64_t s_k0;
     const uint64_t P = *sort_count;
     for (uint64_t chunk = blockIdx.x; chunk * kEmitPer < P; chunk += gridDim.x) {
@@ -482,44 +484,105 @@ __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTabl
         }
         __syncthreads();
         const int64_t k0 = s_k0;
-        for (int t = threadIdx.x; t < kEmitPer; t += 256) {
+        for (int t = threadIdx.x; t <= kEmitPer; t += 256) {  // one more than the chunk's items: a sentinel
             const int64_t k = k0 + t;
             s_off[t] = k < items ? offs[k] : ~0ull;
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < kEmitPer; t += 256) {
-            const uint64_t p = base + t;
-            if (p >= P) break;
-            int lo = 0, hi = kEmitPer - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= p)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+        const uint64_t p0 = base + (uint64_t)threadIdx.x * kEmitPerThread;
+        if (p0 >= P) continue;
+        int lo = 0, hi = kEmitPer - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p0)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        uint32_t key[kEmitPerThread], val[kEmitPerThread];
+        int cur = -1;
+        uint32_t w = 1, x0 = 0, y0 = 0, toff = 0, gw = 0, gi = 0;
+        float inv_w = 1.f;
+#pragma unroll
+        for (int j = 0; j < kEmitPerThread; ++j) {
+            const uint64_t p = p0 + j;
+            key[j] = val[j] = 0u;
+            if (p >= P) continue;
+            while (s_off[lo + 1] <= p) ++lo;  // the owner of p (lo + 1 <= kEmitPer: the sentinel stops the walk)
+            if (lo != cur) {
+                cur = lo;
+                const uint32_t item = sorted[k0 + lo];
+                int v = 0;
+                while (v + 1 < vt.V && (int64_t)item >= (int64_t)(v + 1) * n) ++v;
+                gi = (uint32_t)((int64_t)item - (int64_t)v * n);
+                const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[gi];
+                w = (uint32_t)(r.z - r.x);
+                x0 = (uint32_t)r.x;
+                y0 = (uint32_t)r.y;
+                toff = vt.cam[v].tile_off;
+                gw = (uint32_t)vt.cam[v].grid_w;
+                inv_w = 1.f / (float)w;
             }
-            const uint32_t j = (uint32_t)(p - s_off[lo]);
-            const uint32_t item = sorted[k0 + lo];
-            const int v = (int)(item / n);
-            const int64_t i = item - (int64_t)v * n;
-            const int4 r = reinterpret_cast<const int4*>(vt.proj[v].rect)[i];
-            const uint32_t w = (uint32_t)(r.z - r.x);
-            const uint32_t ty = (uint32_t)r.y + j / w, tx = (uint32_t)r.x + j % w;
-            const uint32_t key = vt.cam[v].tile_off + ty * (uint32_t)vt.cam[v].grid_w + tx;
-            tkeys[p] = key;
-            tvals[p] = (uint32_t)i;
+            // (row, column) of the j-th tile of the rectangle: j < 2^22, so the float quotient is within one of
+            // the integer quotient, and one correction step makes it exact
+            const uint32_t jj = (uint32_t)(p - s_off[lo]);
+            uint32_t q = (uint32_t)((float)jj * inv_w);
+            int rr = (int)jj - (int)(q * w);
+            if (rr < 0) {
+                --q;
+                rr += (int)w;
+            } else if (rr >= (int)w) {
+                ++q;
+                rr -= (int)w;
+            }
+            key[j] = toff + (y0 + q) * gw + x0 + (uint32_t)rr;
+            val[j] = gi;
+        }
+        // (tkeys is workspace, 256-byte aligned; tvals may be the caller's array, which need not be)
+        if (p0 + kEmitPerThread <= P && (reinterpret_cast<uintptr_t>(tvals) & 15) == 0) {
+            *reinterpret_cast<uint4*>(tkeys + p0) = make_uint4(key[0], key[1], key[2], key[3]);
+            *reinterpret_cast<uint4*>(tvals + p0) = make_uint4(val[0], val[1], val[2], val[3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kEmitPerThread; ++j)
+                if (p0 + j < P) {
+                    tkeys[p0 + j] = key[j];
+                    tvals[p0 + j] = val[j];
+                }
         }
     }
 }
 
+// Tile ranges from the sorted keys, four positions per thread (one 16-byte load and the two neighbours).
+constexpr int kRangesPerThread = 4;
+
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ sort_count,
                          uint32_t* __restrict__ ranges) {
-    const uint32_t P = *sort_count;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const uint32_t t = tkeys[p];
-    if (p == 0 || tkeys[p - 1] != t) ranges[2 * (size_t)t] = (uint32_t)p;
-    if (p == (int64_t)P - 1 || tkeys[p + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)p + 1;
+    const uint64_t P = *sort_count;
+    const uint64_t p0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangesPerThread;
+    if (p0 >= P) return;
+    uint32_t k[kRangesPerThread + 1];
+    if (p0 + kRangesPerThread <= P) {
+        const uint4 q = *reinterpret_cast<const uint4*>(tkeys + p0);
+        k[0] = q.x;
+        k[1] = q.y;
+        k[2] = q.z;
+        k[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRangesPerThread; ++j) k[j] = p0 + j < P ? tkeys[p0 + j] : 0u;
+    }
+    k[kRangesPerThread] = p0 + kRangesPerThread < P ? tkeys[p0 + kRangesPerThread] : 0u;
+    uint32_t prev = p0 > 0 ? tkeys[p0 - 1] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRangesPerThread; ++j) {
+        const uint64_t p = p0 + j;
+        if (p >= P) break;
+        const uint32_t t = k[j];
+        if (p == 0 || prev != t) ranges[2 * (size_t)t] = (uint32_t)p;
+        if (p + 1 == P || k[j + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)p + 1;
+        prev = t;
+    }
 }
 
 __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ tvals,
@@ -696,7 +759,8 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     // 4. tile ranges (and optional 64-bit keys)
     {
         QG_TIMED("bin_ranges", s);
-        k_ranges<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, w.sort_count, tile_ranges);
+        k_ranges<<<(unsigned)std::max<int64_t>(1, ceil_div(capacity, 256 * kRangesPerThread)), 256, 0, s>>>(
+            tk_in, w.sort_count, tile_ranges);
     }
     QG_LAUNCH_CHECK("qg_bin ranges");
     if (keys) {
