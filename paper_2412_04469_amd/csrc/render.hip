@@ -323,6 +323,11 @@ __device__ __forceinline__ void row_sums(float (&v)[K]) {
     for (int k = 0; k < K; ++k) v[k] += dpp_term<0x114, 0xf>(v[k]);  // row_shr:4
 }
 
+// Pixel slots of the blend adjoint's second pass that run branch-free (bit k: slot k).  With slot 0 masked
+// instead of skipped, the per-entry sums start from registers that always hold slot 0's terms, so the compiler
+// needs no copies to zero them for the path that would skip it.
+constexpr int kBwdMaskedSlots = 0x1;
+
 template <int TW, int TH, int BD>
 __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
@@ -432,12 +437,14 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 onv[k] = on;
             }
             if (__ballot(hit) == 0) continue;
-            // pass 2: gradients and the suffix colour, only in the lanes whose pixel is on (an off pixel would add
-            // exact zeros); the branch is on the exec mask, so a pixel slot no lane reaches costs nothing
+            // pass 2: gradients and the suffix colour, only in the lanes whose pixel is on (an off pixel adds exact
+            // zeros).  Slots in kBwdMaskedSlots run in every lane with alpha taken as 0 where the pixel is off; the
+            // others branch on the exec mask, so a slot that no lane reaches costs nothing.
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                if (!onv[k]) continue;
-                const float al = alv[k], dy = dyv[k], Ti = T[k];
+                const bool masked = (kBwdMaskedSlots >> k) & 1;
+                if (!masked && !onv[k]) continue;
+                const float al = (masked && !onv[k]) ? 0.f : alv[k], dy = dyv[k], Ti = T[k];
                 const float w = al * Ti;
                 acc[6] = __builtin_fmaf(w, G0[k], acc[6]);
                 acc[7] = __builtin_fmaf(w, G1[k], acc[7]);
@@ -448,7 +455,7 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
                 // geometric part: zero where the 0.99 clamp is active.  With m = alpha dL/dalpha,
                 // dL/dq = -m/2 (q = A dx^2 + 2 B dx dy + C dy^2); the constant factors -1/2 and -1 of the
                 // conic terms are applied once per entry after the wave sum (kGeomScale).
-                const float dLda = rawv[k] <= kAlphaMax ? Ti * d : 0.f;
+                const float dLda = (rawv[k] <= kAlphaMax && (!masked || onv[k])) ? Ti * d : 0.f;
                 acc[5] = __builtin_fmaf(dLda, ekv[k], acc[5]);
                 const float m = al * dLda;
                 const float mdy = m * dy;
