@@ -471,6 +471,10 @@ __device__ __forceinline__ void bwd_tile(const ViewTable& vt, const uint32_t* __
             acc[3] = dx * M1;
             acc[4] = M2;
             row_sums<9>(acc);
+            // the sums are formed here, in all lanes, so that each step is one DPP add (left to itself the
+            // compiler moves the last step's adds into the branch below, as a DPP move plus an add)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(acc[k]));
             if ((lane & 7) == 7) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) s_red[lane >> 3][k] = acc[k];
