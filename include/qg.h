@@ -241,15 +241,14 @@ qg_status qg_project(int64_t n, int64_t ld, const float* attrs, int32_t sh_degre
  * per-tile depth order of Eq. 2.  Global tile id of view v = sum of the earlier views' tile counts +
  * ty * grid_w(v) + tx.  The sort is a stable LSD radix sort: the 32 depth bits are sorted once per
  * (view, Gaussian) before pairs are emitted, then the tile bits over the pairs; each 8-bit pass counts,
- * scans and scatters in three kernels, with no waits between workgroups.  The per-(view, Gaussian) tile
- * counts are scanned in one kernel by decoupled look-back between workgroups, whose waits are bounded.
+ * scans and scatters in three kernels, and the per-(view, Gaussian) tile counts are scanned by a reduce
+ * and an apply kernel: no workgroup ever waits for another.
  *   vals        [capacity] uint32 sorted Gaussian indices (within their view).
  *   keys        [capacity] uint64 sorted keys (optional, NULL to skip).
  *   tile_ranges [total_tiles][2] uint32 half-open spans into vals ([0,0) for an empty tile).
  *   num_pairs   [1] int64: the pair count P.  If P > capacity nothing is emitted, tile_ranges are all
- *               empty, and the caller must not render this step; re-run with capacity >= P.  -1 reports
- *               that a workgroup of the count scan gave up waiting for its predecessors (an internal
- *               failure; the results of the call are invalid).
+ *               empty, and the caller must not render this step; re-run with capacity >= P.  Never
+ *               negative (a reader may treat a negative value as a corrupt count).
  *   ws          qg_bin_workspace_size(n, V, capacity, total_tiles) bytes.
  * capacity <= 2^32 - 1.  total_tiles = sum over views of ceil(W/tile_w) * ceil(H/tile_h).
  */

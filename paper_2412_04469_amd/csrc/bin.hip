@@ -12,11 +12,9 @@
 // its items' digits, one workgroup per digit scans those counts over the blocks, and each block then
 // places its items (stable ranks by wave64 ballot matching on the digit bits, per-wave digit counters in
 // LDS), orders them by digit in LDS and writes them out in digit runs.  The first depth pass makes its keys
-// from the projection on the fly.  The per-(view, Gaussian) tile counts are scanned in one kernel by
-// decoupled look-back: block b publishes its count, adds up the counts (or the already inclusive prefixes)
-// of blocks b-1, b-2, ... and publishes its own inclusive prefix.  Blocks take their logical index from a
-// ticket counter when they start, so a block only ever waits for blocks that are already running, and
-// every wait is bounded (a give-up sets an error word, reported as num_pairs = -1, instead of hanging).
+// from the projection on the fly.  The per-(view, Gaussian) tile counts are scanned the same way, without
+// waits: each block sums its items' counts, then each block adds up the sums of the blocks before it and
+// scans its own items.
 #include <algorithm>
 #include <mutex>
 
@@ -30,62 +28,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-// Look-back state word: 2 flag bits over a 62-bit value.
-constexpr uint64_t kFlagAgg = 1ull << 62;  // value = this block's own count
-constexpr uint64_t kFlagInc = 2ull << 62;  // value = inclusive prefix over blocks 0..b
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-constexpr uint32_t kMaxSpin = 1u << 22;    // polls before a wait gives up (never reached when blocks progress)
-
-// Control block of the count scan in the workspace (zeroed by k_bin_init for every call).
-struct ScanCtl {
-    uint32_t ticket;  // logical block index of the count scan
-    uint32_t err;     // non-zero if a look-back wait gave up
-};
-
-__device__ __forceinline__ void store_state(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t load_state(const uint64_t* p) {
-    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
-
-// Exclusive prefix of block `bid` over blocks 0..bid-1, given the published states at lb[0 .. bid), by a
-// whole wave: lane l reads the state of predecessor j - l, so one round covers 64 predecessors.  The lanes up to the nearest inclusive prefix (or up to the first state not yet
-// published, which ends the round) are summed by a wave reduction.  Every lane returns the prefix.
-__device__ __forceinline__ uint64_t look_back_wave(const uint64_t* lb, uint32_t bid, uint32_t* err) {
-    const int lane = __lane_id();
-    uint64_t excl = 0;
-    int64_t j = (int64_t)bid - 1;
-    uint32_t spins = 0;
-    while (j >= 0) {
-        const int64_t p = j - lane;
-        const uint64_t st = p >= 0 ? load_state(lb + p) : kFlagInc;
-        const uint64_t f = st & ~kValMask;
-        const uint64_t unpub = __ballot(f == 0), inc = __ballot(f == kFlagInc);
-        // lanes before the first unpublished state and up to (including) the first inclusive one
-        const int first_unpub = unpub ? __ffsll((unsigned long long)unpub) - 1 : 64;
-        const int first_inc = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
-        const bool done = first_inc < first_unpub;
-        const int used = done ? first_inc + 1 : first_unpub;
-        uint64_t v = lane < used ? (st & kValMask) : 0;
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-        excl += v;
-        if (done) break;
-        j -= used;
-        if (used == 0) {
-            if (++spins > kMaxSpin) {
-                if (lane == 0) atomicOr(err, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        } else {
-            spins = 0;
-        }
-    }
-    return excl;
-}
 
 // Lanes of this wave holding the same digit (among active, valid lanes).
 __device__ __forceinline__ uint64_t match8(uint32_t d, bool valid) {
@@ -370,7 +313,7 @@ qg_status rs_pass(const RsSrc& src, uint32_t* kout, uint32_t* vout, const uint32
 // ------------------------------------------------------------------------------------------------
 // Binning kernels
 // ------------------------------------------------------------------------------------------------
-// Zeroes the tile ranges, the count scan's control block and look-back states, num_pairs and the sort count
+// Zeroes the tile ranges, num_pairs and the sort count
 // (one grid-stride pass over a list of word ranges).
 struct ZeroList {
     uint32_t* p[8];
@@ -384,62 +327,64 @@ __global__ void k_bin_init(ZeroList z) {
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.words[k]; i += stride) z.p[k][i] = 0u;
 }
 
-// Exclusive scan (64-bit) of the tile counts of the items in depth order, in one kernel with look-back;
-// the block holding the last item also writes the total, the tile sort's count (0 on overflow) and the
-// caller's num_pairs.
-constexpr int kScanIPT = 16;
+// Exclusive scan (64-bit) of the tile counts of the items in depth order, reduce then apply: k_count_reduce
+// sums each block's items; k_count_apply adds up the sums of the blocks before its own, scans its items into
+// offs, and its last block writes the total, the tile sort's count (0 on overflow) and the caller's
+// num_pairs.  A thread owns kScanIPT consecutive items.
+constexpr int kScanIPT = 4;
 constexpr int kScanTile = kBlock * kScanIPT;
 
-__global__ __launch_bounds__(kBlock) void k_count_scan(int64_t items, int64_t n, ViewTable vt,
-                                                       const uint32_t* __restrict__ sorted, uint64_t* __restrict__ offs,
-                                                       int64_t capacity, uint32_t* __restrict__ sort_count,
-                                                       int64_t* __restrict__ num_pairs, ScanCtl* ctl,
-                                                       uint64_t* lb) {
+__device__ __forceinline__ uint64_t item_tiles(const ViewTable& vt, int64_t n, uint32_t item) {
+    int v = 0;
+    while (v + 1 < vt.V && (int64_t)item >= (int64_t)(v + 1) * n) ++v;
+    return (uint64_t)vt.proj[v].ntiles[(int64_t)item - (int64_t)v * n];
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_reduce(int64_t items, int64_t n, ViewTable vt,
+                                                         const uint32_t* __restrict__ sorted,
+                                                         uint64_t* __restrict__ bsum) {
     __shared__ uint64_t s_w[kWaves];
-    __shared__ uint32_t s_bid;
-    __shared__ uint64_t s_excl;
-    if (threadIdx.x == 0) s_bid = atomicAdd(&ctl->ticket, 1u);
-    __syncthreads();
-    const uint32_t bid = s_bid;
-    const int64_t base = (int64_t)bid * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanIPT; ++r) {
+        const int64_t k = base + r;
+        if (k < items) acc += item_tiles(vt, n, sorted[k]);
+    }
+    uint64_t tot;
+    block_excl_scan<uint64_t>(acc, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_apply(int64_t items, int64_t n, ViewTable vt,
+                                                        const uint32_t* __restrict__ sorted,
+                                                        const uint64_t* __restrict__ bsum,
+                                                        uint64_t* __restrict__ offs, int64_t capacity,
+                                                        uint32_t* __restrict__ sort_count,
+                                                        int64_t* __restrict__ num_pairs) {
+    __shared__ uint64_t s_w[kWaves];
+    // start of this block: the sum of the blocks before it
+    uint64_t pre = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) pre += bsum[b];
+    uint64_t start;
+    block_excl_scan<uint64_t>(pre, s_w, &start);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
     uint64_t c[kScanIPT];
     uint64_t acc = 0;
 #pragma unroll
     for (int r = 0; r < kScanIPT; ++r) {
         const int64_t k = base + r;
-        uint64_t x = 0;
-        if (k < items) {
-            const uint32_t item = sorted[k];
-            const int v = (int)(item / n);
-            x = (uint64_t)vt.proj[v].ntiles[item - (int64_t)v * n];
-        }
-        c[r] = x;
-        acc += x;
+        c[r] = k < items ? item_tiles(vt, n, sorted[k]) : 0;
+        acc += c[r];
     }
     uint64_t btot;
     const uint64_t ex = block_excl_scan<uint64_t>(acc, s_w, &btot);
-    if (threadIdx.x < kWave) {  // wave 0 looks back
-        uint64_t excl = 0;
-        if (bid == 0) {
-            if (threadIdx.x == 0) store_state(lb, kFlagInc | btot);
-        } else {
-            if (threadIdx.x == 0) store_state(lb + bid, kFlagAgg | btot);
-            excl = look_back_wave(lb, bid, &ctl->err);
-            if (threadIdx.x == 0) store_state(lb + bid, kFlagInc | (excl + btot));
-        }
-        if (threadIdx.x == 0) s_excl = excl;
+    if (threadIdx.x == 0 && (int64_t)(blockIdx.x + 1) * kScanTile >= items) {  // the last block
+        const uint64_t t = start + btot;
+        *num_pairs = (int64_t)t;
+        *sort_count = t <= (uint64_t)capacity ? (uint32_t)t : 0u;
     }
-    if (threadIdx.x == 0) {
-        const uint64_t excl = s_excl;
-        if ((int64_t)(bid + 1) * kScanTile >= items) {  // the last block
-            const uint64_t t = excl + btot;
-            const bool failed = atomicAdd(&ctl->err, 0u) != 0;  // a wait of this scan gave up
-            *num_pairs = failed ? -1 : (int64_t)t;
-            *sort_count = (!failed && t <= (uint64_t)capacity) ? (uint32_t)t : 0u;
-        }
-    }
-    __syncthreads();
-    uint64_t run = s_excl + ex;
+    uint64_t run = start + ex;
 #pragma unroll
     for (int r = 0; r < kScanIPT; ++r) {
         const int64_t k = base + r;
@@ -603,10 +548,9 @@ struct BinWs {
     uint64_t* offs;                   // V*n
     uint32_t* sort_count;
     uint32_t *tkA, *tkB, *tvB;        // tile sort, capacity
-    ScanCtl* ctl;                     // count scan
     uint32_t* rs_cnt;                 // radix passes: per-block digit counts [256][nb_cnt], scanned in place
     uint32_t* rs_tot;                 // radix passes: digit totals [256]
-    uint64_t* lb_scan;                // count-scan look-back, [blocks]
+    uint64_t* bsum;                   // count scan: per-block sums, [blocks]
     int64_t nb_cnt, nb_scan;
     size_t bytes;
 };
@@ -633,10 +577,9 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     w.tkA = (uint32_t*)take(4 * cap1);
     w.tkB = (uint32_t*)take(4 * cap1);
     w.tvB = (uint32_t*)take(4 * cap1);
-    w.ctl = (ScanCtl*)take(sizeof(ScanCtl));
     w.rs_cnt = (uint32_t*)take(4 * kRadix * w.nb_cnt);
     w.rs_tot = (uint32_t*)take(4 * kRadix);
-    w.lb_scan = (uint64_t*)take(8 * w.nb_scan);
+    w.bsum = (uint64_t*)take(8 * w.nb_scan);
     w.bytes = off;
     return w;
 }
@@ -682,20 +625,16 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     int tbits = 1;
     while ((1ll << tbits) < T) ++tbits;
     const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
-    // 0. clear the ranges, the count scan's control block and look-back states, num_pairs and the sort count
+    // 0. clear the ranges, num_pairs and the sort count
     {
         ZeroList z{};
         z.p[0] = tile_ranges;
         z.words[0] = 2 * T;
-        z.p[1] = (uint32_t*)w.ctl;
-        z.words[1] = sizeof(ScanCtl) / 4;
-        z.p[2] = (uint32_t*)w.lb_scan;
-        z.words[2] = 2 * w.nb_scan;
-        z.p[3] = (uint32_t*)num_pairs;  // stays 0 for an empty input
-        z.words[3] = 2;
-        z.p[4] = w.sort_count;
-        z.words[4] = 1;
-        z.n = 5;
+        z.p[1] = (uint32_t*)num_pairs;  // stays 0 for an empty input
+        z.words[1] = 2;
+        z.p[2] = w.sort_count;
+        z.words[2] = 1;
+        z.n = 3;
         int64_t most = 0;
         for (int k = 0; k < z.n; ++k) most = std::max(most, z.words[k]);
         QG_TIMED("bin_init", s);
@@ -727,11 +666,12 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
         if (st != QG_OK) return st;
     }
     const uint32_t* sorted_items = va;
-    // 2. tile counts in depth order: one-kernel scan, total, overflow check
+    // 2. tile counts in depth order: scan, total, overflow check
     {
         QG_TIMED("bin_count_scan", s);
-        k_count_scan<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.offs, capacity, w.sort_count,
-                                                             num_pairs, w.ctl, w.lb_scan);
+        k_count_reduce<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum);
+        k_count_apply<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum, w.offs, capacity,
+                                                             w.sort_count, num_pairs);
     }
     QG_LAUNCH_CHECK("qg_bin count");
     if (capacity == 0) return QG_OK;

@@ -105,11 +105,11 @@ class Rasterizer:
                          self.t_last, stream)
 
     def pair_count(self) -> int:
-        """Pair count of the last qg_bin (host sync).  Raises QGError if the sort reported that a workgroup gave
-        up waiting for its predecessors (num_pairs < 0): the tile lists of that binning are invalid."""
+        """Pair count of the last qg_bin (host sync).  Raises QGError on a negative count, which qg_bin never
+        writes: the count buffer (and the tile lists with it) would then be corrupt."""
         p = int(self.num_pairs.item())
         if p < 0:
-            raise qg.QGError(qg.QG_ERR_HIP, f"qg_bin reported an internal sort failure (num_pairs = {p})")
+            raise qg.QGError(qg.QG_ERR_HIP, f"invalid pair count from qg_bin (num_pairs = {p})")
         return p
 
     def overflowed(self) -> bool:

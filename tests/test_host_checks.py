@@ -1,8 +1,9 @@
 """Host-side checks of the fit path, on the CPU with no kernel launched.
 
-A binning whose sort gave up waiting reports num_pairs = -1 (its tile lists are invalid).  Every place that
-reads the pair count -- the rasterizer's capacity check, both fitters, the streaming driver -- must turn that
-into a QGError instead of treating it as "no overflow".  The value is written into num_pairs from the host."""
+qg_bin never writes a negative pair count, so a negative one means a corrupt count buffer (and invalid tile
+lists).  Every place that reads the pair count -- the rasterizer's capacity check, both fitters, the streaming
+driver -- must turn it into a QGError instead of treating it as "no overflow".  The value is written into
+num_pairs from the host."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +22,7 @@ def _setup(n=50, views=2):
     return cams, prev, gts
 
 
-def test_rasterizer_pair_count_rejects_a_failed_sort():
+def test_rasterizer_pair_count_rejects_a_negative_count():
     cams, prev, _ = _setup()
     r = Rasterizer(50, cams, device="cpu", capacity=100)
     r.num_pairs[0] = 40
@@ -32,7 +33,7 @@ def test_rasterizer_pair_count_rejects_a_failed_sort():
     for call in (r.pair_count, r.overflowed, r.ensure_capacity):
         with pytest.raises(qg.QGError) as e:
             call()
-        assert e.value.status == qg.QG_ERR_HIP and "sort failure" in str(e.value)
+        assert e.value.status == qg.QG_ERR_HIP and "invalid pair count" in str(e.value)
 
 
 def test_fitters_and_stream_reject_a_failed_sort():
