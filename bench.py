@@ -61,6 +61,48 @@ def traffic_for(kernel):
     return t["bytes_per_launch"]
 
 
+def measured_peaks():
+    """The chip's ceilings as this build can reach them, measured on the box next to the datasheet figures:
+    HBM from a plain 1 GiB device-to-device copy (2 GiB moved; best of 10), FP32 vector from the library's FMA
+    probe (single FMAs, the instruction its kernels are built with, packed FP32 being disabled; best of 5)."""
+    import torch
+    from paper_2412_04469_amd import qg
+    n = (1 << 30) // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(11):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    hbm = 2.0 * n * 4 / (best * 1e-3) / 1e9
+    del src, dst
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks, iters = 16 * cus, 2048
+    out = torch.empty(blocks * 256, device="cuda")
+    qg.qg_probe_fma(blocks, iters, out)  # first launch
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        qg.qg_probe_fma(blocks, iters, out)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    flops = blocks * 256.0 * iters * 16 * 2
+    fma = flops / (best * 1e-3) / 1e12
+    torch.cuda.empty_cache()
+    return {"hbm_copy_gbs": round(hbm, 1), "hbm_datasheet_gbs": PEAK_HBM_GBS,
+            "fp32_fma_tflops": round(fma, 2), "fp32_datasheet_tflops": PEAK_FP32_TFLOPS,
+            "fp32_unpacked_datasheet_tflops": PEAK_FP32_TFLOPS / 2,
+            "protocol": "1 GiB device-to-device copy, best of 10; FMA probe (16 register-resident FMA chains per "
+                        "thread, 16 workgroups of 256 per CU, 2048 iterations), best of 5"}
+
+
 def copy_probe(mib):
     """A plain device-to-device copy of mib MiB (mib MiB read, mib MiB written), three times: the calibration
     kernel for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -936,6 +978,13 @@ def main():
     del fitter
     torch.cuda.empty_cache()
     log(f"headline: {ms_step:.4f} ms/step")
+    # the measured ceilings beside the datasheet ones, and the blend kernels against the measured FMA rate
+    peaks = measured_peaks()
+    result["measured_peaks"] = peaks
+    log(f"measured peaks: copy {peaks['hbm_copy_gbs']} GB/s, FMA {peaks['fp32_fma_tflops']} TFLOP/s")
+    for r in (result["roofline"], result["roofline_blend_fwd"]):
+        if r and r.get("unit") == "TFLOP/s" and peaks["fp32_fma_tflops"] > 0:
+            r["frac_of_measured_fma"] = round(r["achieved"] / peaks["fp32_fma_tflops"], 4)
     result["paper_context"] = PAPER_CONTEXT
     if not args.no_configs:
         result["configs"] = configs_section(args)

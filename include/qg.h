@@ -633,6 +633,14 @@ qg_status qg_adam_multi(int32_t nseg, const qg_adam_segment* segs, float b1, flo
 /* Zero `bytes` bytes at dst with a fill kernel (no memset node, so it is safe to capture). */
 qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream);
 
+/*
+ * Measurement helper for the FP32 vector roofline (not part of the method): `blocks` workgroups of 256 threads,
+ * each thread advancing 16 independent FP32 multiply-add chains `iters` times in registers (single FMAs, the
+ * instruction the library's kernels are built with), then writing one float to out[blocks * 256] (device).
+ * Work: blocks * 256 * iters * 16 * 2 flop.  QG_ERR_ARG if blocks < 1, iters < 1 or out is NULL.
+ */
+qg_status qg_probe_fma(int32_t blocks, int32_t iters, float* out, qg_stream stream);
+
 /* ---------------------------------------------------------------------------------------------- */
 /* Diagnostics: per-kernel timing with HIP events.                                                 */
 /* ---------------------------------------------------------------------------------------------- */

@@ -233,6 +233,38 @@ extern "C" int64_t qg_total_tiles(const qg_camera* cams, int32_t V, qg_tiling ti
     return t.total_tiles;
 }
 
+namespace {
+
+// FP32 FMA issue probe: kProbeChains independent multiply-add chains per thread, held in registers, each
+// advanced `iters` times; one float per thread is written so that the work is kept.
+constexpr int kProbeChains = 16;
+
+__global__ __launch_bounds__(256) void k_fma_probe(int32_t iters, float x, float y, float* __restrict__ out) {
+    float a[kProbeChains];
+#pragma unroll
+    for (int k = 0; k < kProbeChains; ++k) a[k] = (float)(threadIdx.x + k) * 1e-3f;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kProbeChains; ++k) a[k] = __builtin_fmaf(a[k], x, y);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kProbeChains; ++k) s += a[k];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+}  // namespace
+
+extern "C" qg_status qg_probe_fma(int32_t blocks, int32_t iters, float* out, qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(blocks >= 1 && iters >= 1, "blocks and iters must be >= 1");
+    QG_REQUIRE(out != nullptr, "out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    k_fma_probe<<<(unsigned)blocks, 256, 0, s>>>(iters, 0.999f, 1e-4f, out);
+    QG_LAUNCH_CHECK("qg_probe_fma");
+    return QG_OK;
+}
+
 extern "C" qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream) {
     clear_error();
     QG_REQUIRE(bytes >= 0, "bytes < 0");

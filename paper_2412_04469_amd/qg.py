@@ -70,6 +70,7 @@ def lib():
             "qg_get_deterministic": ([], i32),
             "qg_deterministic_workspace_size": ([i64, i32, i64], sz),
             "qg_zero": ([P, i64, P], i32),
+            "qg_probe_fma": ([i32, i32, P, P], i32),
             "qg_total_tiles": ([CAM, i32, qg_tiling], i64),
             "qg_decode_residuals": ([i64, i64, P, P, i32, P, P, i32, i32, P, P, P, f32, f32, f32, P, P, P, P], i32),
             "qg_decode_lreg_blocks": ([i64], i64),
@@ -223,6 +224,10 @@ def qg_version():
 
 def qg_zero(dst, nbytes, stream=None):
     _check(lib().qg_zero(_ptr(dst), int(nbytes), _stream(stream)))
+
+
+def qg_probe_fma(blocks, iters, out, stream=None):
+    _check(lib().qg_probe_fma(int(blocks), int(iters), _ptr(out), _stream(stream)))
 
 
 PROPOSAL_PARAMS = 6540
