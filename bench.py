@@ -283,17 +283,17 @@ def batched_section(args):
     torch.cuda.synchronize()
     log(f"batched: ground truth for {len(wl.cams)} views rendered")
 
-    def make(tile, batch, persistent):
-        f = BatchedFitter(prev, wl.cams, gts, FitConfig(tile=tuple(tile)), batch=batch, persistent=persistent)
+    def make(tile, batch, heaviest_first):
+        f = BatchedFitter(prev, wl.cams, gts, FitConfig(tile=tuple(tile)), batch=batch, heaviest_first=heaviest_first)
         f.size_capacity()
         return f
 
     if args.tune == "full":
         cands = candidates()
     elif args.tune == "quick":
-        cands = [dict(tile=t, batch=64, persistent=p) for t in ((16, 16), (8, 8), (32, 8)) for p in (False, True)]
+        cands = [dict(tile=t, batch=64, heaviest_first=h) for t in ((16, 16), (8, 8), (32, 8)) for h in (False, True)]
     else:
-        cands = [dict(tile=(16, 16), batch=64, persistent=True)]
+        cands = [dict(tile=(16, 16), batch=64, heaviest_first=True)]
     from paper_2412_04469_amd.autotune import cache_key
     best, table = autotune(make, cands, steps=5, warmup=1, log=log, cache_path=args.tune_cache or None,
                            key=cache_key(wl.cams, wl.scene.n))
@@ -331,9 +331,9 @@ def batched_section(args):
     return {"workload": wl.name, "n_gaussians": wl.scene.n, "views": len(wl.cams), "pixels": px,
             "ms_per_step": round(ms, 4), "mpix_per_s": round(px / (ms * 1e-3) / 1e6, 1), "pairs": pairs,
             "overflow": overflow, "schedule": {"tile": "%dx%d" % tuple(best["tile"]), "batch": best["batch"],
-                                               "persistent": best["persistent"]},
+                                               "heaviest_first": best["heaviest_first"]},
             "autotune_ms": {"%dx%d/b%d/%s" % (c["tile"][0], c["tile"][1], c["batch"],
-                                              "persistent" if c["persistent"] else "grid"): round(t, 4)
+                                              "heaviest-first" if c["heaviest_first"] else "xcd-groups"): round(t, 4)
                             for c, t in table},
             "per_view_launches_ms": round(per_view, 4),
             "form": "one captured graph per step; loss = mean of per-view mean L1"}
@@ -505,7 +505,7 @@ def frame_section(args):
 
     def run_batched(views, lr):
         bcfg = dataclasses.replace(cfg, group_views=views, batched_lr_scale=lr)
-        bat = BatchedFitter(prev, wl.cams, gts, bcfg, persistent=False, eval_cam=held)
+        bat = BatchedFitter(prev, wl.cams, gts, bcfg, eval_cam=held)
         bat.size_capacity()
         w0 = (bat.W1.clone(), bat.W2.clone())
         for _ in bat.groups:  # every view group's step captured; the decoder goes back to its initial weights

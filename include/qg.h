@@ -93,10 +93,11 @@ typedef struct {
  *                    Results do not depend on it.
  *   reserved         must be 0.
  *   schedule         optional device buffer written by qg_schedule_tiles for the current binning: the blend
- *                    kernels then run a grid that is resident on the chip at once and take tiles from it,
- *                    heaviest first.  NULL = one workgroup per tile.  Results do not depend on it, except
- *                    for the order of the float atomics of the blend adjoint.  Calls that use one schedule
- *                    buffer must not run concurrently.
+ *                    kernels' workgroup b then takes the b-th tile of its heaviest-first order (workgroups
+ *                    start in index order, so the longest tile lists start first).  NULL = tiles in groups
+ *                    of 4x4 dealt round-robin to the XCDs.  One workgroup per tile either way; results do not
+ *                    depend on it, except for the order of the float atomics of the blend adjoint.  The blend
+ *                    calls only read the buffer.
  * qg_project and qg_bin read only the tile shape.
  */
 typedef struct {
@@ -295,14 +296,14 @@ qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* cams, int32_t
 
 /*
  * Heaviest-first tile order for the blend kernels (a scheduling aid; no arithmetic of the method).
- * schedule [device] qg_schedule_words(total_tiles) words: 2 work counters, QG_SCHEDULE_BUCKETS bucket
- * offsets, then the order of all tiles by decreasing entry count (on a log scale, 8 steps per octave;
- * order within a step is arbitrary).  Build it after each qg_bin and pass it as qg_tiling.schedule to
- * qg_render_fwd / qg_render_bwd / qg_render_decode_bwd; every such call leaves the counters at zero.
- * Stream-ordered, no allocation, safe under graph capture.
+ * schedule [device] qg_schedule_words(total_tiles) words: QG_SCHEDULE_BUCKETS working words (bucket offsets),
+ * then the order of all tiles by decreasing entry count (on a log scale, 8 steps per octave; order within a
+ * step is arbitrary).  Build it after each qg_bin and pass it as qg_tiling.schedule to qg_render_fwd /
+ * qg_render_bwd / qg_render_decode_bwd.  Up to 2^18 tiles one workgroup builds it in LDS.  Stream-ordered,
+ * no allocation, safe under graph capture.
  */
 #define QG_SCHEDULE_BUCKETS 512
-#define QG_SCHEDULE_HEADER_WORDS (2 + QG_SCHEDULE_BUCKETS)
+#define QG_SCHEDULE_HEADER_WORDS QG_SCHEDULE_BUCKETS
 int64_t qg_schedule_words(int64_t total_tiles);
 qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile_ranges, uint32_t* schedule,
                             int64_t schedule_words, qg_stream stream);

@@ -1,8 +1,8 @@
 """Autotuning of the batched fit: the blend schedule of the step, and the step grouping of the frame.
 
 Blend schedule.  The tile shape (8x8, 16x16, 32x8), the LDS batch depth of the blend kernels (32, 64, 128, 256
-entries) and the work distribution (one workgroup per tile, or a resident grid taking tiles heaviest-first)
-change how the blend and its adjoint run, never what they compute: images, T_final and last are bit-identical
+entries) and the tile order (groups of tiles dealt round-robin to the XCDs, or heaviest first) change how the
+blend and its adjoint run, never what they compute: images, T_final and last are bit-identical
 across all of them, and the adjoint differs only in the order of its float atomics.  The autotuner therefore
 times the real captured step of each candidate on the real inputs and keeps the fastest.  Choices can be kept
 in a JSON cache file, keyed by device, resolution bucket, Gaussian-count bucket and view count.
@@ -23,13 +23,13 @@ import torch
 
 TILES = ((16, 16), (8, 8), (32, 8))
 BATCHES = (32, 64, 128, 256)
-PERSISTENT = (False, True)
+HEAVIEST_FIRST = (False, True)
 # (views per step, learning-rate factor) candidates of the step grouping
 GROUPINGS = ((2, 1.5), (4, 2.5), (5, 2.0), (10, 3.0))
 
 
-def candidates(tiles=TILES, batches=BATCHES, persistent=PERSISTENT):
-    return [dict(tile=t, batch=b, persistent=p) for t, b, p in itertools.product(tiles, batches, persistent)]
+def candidates(tiles=TILES, batches=BATCHES, heaviest_first=HEAVIEST_FIRST):
+    return [dict(tile=t, batch=b, heaviest_first=h) for t, b, h in itertools.product(tiles, batches, heaviest_first)]
 
 
 def time_steps(fitter, steps: int, warmup: int) -> float:
@@ -63,7 +63,7 @@ def _load(path):
 
 
 def autotune(make_fitter, cands=None, steps: int = 6, warmup: int = 2, log=None, cache_path=None, key=None):
-    """make_fitter(tile=..., batch=..., persistent=...) -> a sized BatchedFitter on the workload to tune.
+    """make_fitter(tile=..., batch=..., heaviest_first=...) -> a sized BatchedFitter on the workload to tune.
 
     Each candidate is built, stepped `warmup` times (the first step of each view group is eager and captures
     the group's graph) and timed over `steps` graph replays.  Returns (best candidate, [(candidate, ms)]).
@@ -72,7 +72,7 @@ def autotune(make_fitter, cands=None, steps: int = 6, warmup: int = 2, log=None,
     if cache_path and key:
         hit = _load(cache_path).get(key)
         if hit:
-            best = dict(tile=tuple(hit["tile"]), batch=int(hit["batch"]), persistent=bool(hit["persistent"]))
+            best = dict(tile=tuple(hit["tile"]), batch=int(hit["batch"]), heaviest_first=bool(hit["heaviest_first"]))
             if log:
                 log(f"autotune: cached choice {best} for {key}")
             return best, []
@@ -93,7 +93,7 @@ def autotune(make_fitter, cands=None, steps: int = 6, warmup: int = 2, log=None,
     best = min(table, key=lambda cm: cm[1])[0]
     if cache_path and key:
         data = _load(cache_path)
-        data[key] = dict(tile=list(best["tile"]), batch=best["batch"], persistent=best["persistent"],
+        data[key] = dict(tile=list(best["tile"]), batch=best["batch"], heaviest_first=best["heaviest_first"],
                          ms=round(min(ms for _, ms in table), 4))
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:

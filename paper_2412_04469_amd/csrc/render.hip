@@ -15,8 +15,6 @@
 //
 // The blend alpha is evaluated by one inline function used by both kernels, with explicit fused
 // multiply-adds, so the forward's skip/clamp/termination decisions are reproduced exactly.
-#include <map>
-#include <mutex>
 
 #include "qg_internal.h"
 
@@ -251,31 +249,13 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
     }
 }
 
-// Work distribution.  Without a schedule: one workgroup per tile, XCD-aware order.  With a schedule (the
-// order of qg_schedule_tiles, heaviest tiles first): a grid that fits on the chip at once, each workgroup
-// taking the next tile from a device counter until the list is exhausted; the last workgroup to finish
-// puts both counters back to zero, so the schedule is ready for the next kernel without a reset.
+// Work distribution: one workgroup per tile.  Without a schedule, in the super-tile order of map_tile.  With a
+// schedule (qg_schedule_tiles, heaviest tiles first), workgroup b takes tile order[b]: workgroups are dispatched
+// in index order, round-robin over the XCDs and their CUs, so the longest tile lists start first and spread over
+// the SIMDs, and the short ones fill in behind them.
 struct Sched {
     const uint32_t* order;  // [total_tiles] or nullptr
-    uint32_t* ctr;          // [2]: next item, finished workgroups
 };
-
-__device__ __forceinline__ uint32_t next_item(uint32_t* ctr) {
-    uint32_t item = 0;
-    if (threadIdx.x == 0) item = atomicAdd(ctr, 1u);
-    return __builtin_amdgcn_readfirstlane(item);
-}
-
-__device__ __forceinline__ void finish_sched(uint32_t* ctr) {
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(ctr + 1, 1u) == gridDim.x - 1) {
-            __threadfence();
-            atomicExch(ctr, 0u);
-            atomicExch(ctr + 1, 0u);
-        }
-    }
-}
 
 template <int TW, int TH, int BD>
 __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
@@ -286,19 +266,10 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float s_c[BD];   // b
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
-    if (sc.order == nullptr) {
-        const int64_t tile = map_tile(tm, vt, blockIdx.x);
-        if (tile >= 0)
-            fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c, s_pos);
-        return;
-    }
-    for (;;) {
-        const uint32_t item = next_item(sc.ctr);
-        if (item >= (uint32_t)vt.total_tiles) break;
-        fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, sc.order[item], s_a, s_b, s_c,
-                             s_pos);
-    }
-    finish_sched(sc.ctr);
+    const int64_t tile = sc.order ? (blockIdx.x < vt.total_tiles ? (int64_t)sc.order[blockIdx.x] : -1)
+                                  : map_tile(tm, vt, blockIdx.x);
+    if (tile >= 0)
+        fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c, s_pos);
 }
 
 // ---- wave64 sums of K values at once: DPP inclusive scans inside each 8-lane half row (row_shr 1, 2, 4,
@@ -518,39 +489,11 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
     __shared__ uint32_t s_gid[BD];
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     __shared__ float s_red[8][12];  // half-row totals of the 9 gradient components
-    if (sc.order == nullptr) {
-        const int64_t tile = map_tile(tm, vt, blockIdx.x);
-        if (tile >= 0)
-            bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp,
-                                 tile, s_a, s_b, s_c, s_gid, s_pos, s_red);
-        return;
-    }
-    for (;;) {
-        const uint32_t item = next_item(sc.ctr);
-        if (item >= (uint32_t)vt.total_tiles) break;
-        bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp,
-                             sc.order[item], s_a, s_b, s_c, s_gid, s_pos, s_red);
-    }
-    finish_sched(sc.ctr);
-}
-
-// Resident workgroups of a kernel on the whole current device (the persistent grid size), cached per
-// (kernel, device): every template instantiation is a different kernel with its own occupancy.
-int64_t resident_blocks(const void* kernel) {
-    static std::mutex mu;
-    static std::map<std::pair<const void*, int>, int64_t> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({kernel, dev});
-    if (it != cache.end()) return it->second;
-    int cus = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || cus <= 0 || per_cu <= 0)
-        return 0;
-    const int64_t r = (int64_t)cus * per_cu;
-    cache[{kernel, dev}] = r;
-    return r;
+    const int64_t tile = sc.order ? (blockIdx.x < vt.total_tiles ? (int64_t)sc.order[blockIdx.x] : -1)
+                                  : map_tile(tm, vt, blockIdx.x);
+    if (tile >= 0)
+        bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp, tile,
+                             s_a, s_b, s_c, s_gid, s_pos, s_red);
 }
 
 // The plain grid's tile order (super-tiles of 4 x 4 tiles) and its size, a multiple of 8 * 16 workgroups.
@@ -572,13 +515,9 @@ TileMap make_tile_map(const ViewTable& vt, int64_t* grid) {
     return m;
 }
 
-inline Sched make_sched(const qg_tiling& t, int64_t total_tiles) {
-    Sched sc = {nullptr, nullptr};
-    if (t.schedule) {
-        sc.ctr = t.schedule;
-        sc.order = t.schedule + QG_SCHEDULE_HEADER_WORDS;
-    }
-    (void)total_tiles;
+inline Sched make_sched(const qg_tiling& t) {
+    Sched sc = {nullptr};
+    if (t.schedule) sc.order = t.schedule + QG_SCHEDULE_HEADER_WORDS;
     return sc;
 }
 
@@ -588,12 +527,8 @@ qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
                        hipStream_t s) {
     int64_t grid = 0;
     const TileMap tm = make_tile_map(vt, &grid);
-    const Sched sc = make_sched(tiling, vt.total_tiles);
-    if (sc.order) {
-        const int64_t res = resident_blocks(reinterpret_cast<const void*>(k_render_fwd<TW, TH, BD>));
-        QG_REQUIRE(res > 0, "occupancy query failed");
-        grid = std::min<int64_t>(vt.total_tiles, res);
-    }
+    const Sched sc = make_sched(tiling);
+    if (sc.order) grid = vt.total_tiles;
     {
         QG_TIMED("render_fwd", s);
         k_render_fwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp,
@@ -609,12 +544,8 @@ qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
                        float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
     int64_t grid = 0;
     const TileMap tm = make_tile_map(vt, &grid);
-    const Sched sc = make_sched(tiling, vt.total_tiles);
-    if (sc.order) {
-        const int64_t res = resident_blocks(reinterpret_cast<const void*>(k_render_bwd<TW, TH, BD>));
-        QG_REQUIRE(res > 0, "occupancy query failed");
-        grid = std::min<int64_t>(vt.total_tiles, res);
-    }
+    const Sched sc = make_sched(tiling);
+    if (sc.order) grid = vt.total_tiles;
     {
         QG_TIMED("blend_bwd", s);
         k_render_bwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
@@ -776,7 +707,10 @@ qg_status launch_bwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* va
 // Tiles are bucketed by the length of their entry list on a log scale (float exponent and the top three
 // mantissa bits, 8 buckets per octave), buckets are laid out heaviest first, and tiles are scattered into
 // their bucket (order inside a bucket is arbitrary: every tile is blended by exactly one wave either way).
+// Up to kSchedOneBlock tiles one workgroup does it all in LDS; above, a histogram, a scan and a scatter kernel
+// go through the schedule's bucket words.
 constexpr int kSchedBuckets = QG_SCHEDULE_BUCKETS;
+constexpr int64_t kSchedOneBlock = 1 << 18;
 
 __device__ __forceinline__ uint32_t sched_bucket(uint32_t len) {
     if (len == 0) return kSchedBuckets - 1;
@@ -787,6 +721,35 @@ __device__ __forceinline__ uint32_t sched_bucket(uint32_t len) {
 __global__ void k_sched_clear(uint32_t* __restrict__ w) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < QG_SCHEDULE_HEADER_WORDS) w[i] = 0u;
+}
+
+// The whole order in one workgroup of 1024 threads: histogram, exclusive scan and scatter in LDS.
+__global__ __launch_bounds__(1024) void k_sched_one(int64_t total, const uint32_t* __restrict__ ranges,
+                                                    uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_h[kSchedBuckets];
+    __shared__ uint32_t s_w[1024 / 64];
+    for (int k = threadIdx.x; k < kSchedBuckets; k += blockDim.x) s_h[k] = 0;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x)
+        atomicAdd(&s_h[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    __syncthreads();
+    // exclusive scan of the kSchedBuckets counts: wave scans, then the wave totals in order
+    const int k = threadIdx.x, w = k / 64, lane = __lane_id();
+    uint32_t c = k < kSchedBuckets ? s_h[k] : 0u, x = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int j = 0; j < w; ++j) base += s_w[j];
+    if (k < kSchedBuckets) s_h[k] = base + x - c;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
+        const uint32_t pos = atomicAdd(&s_h[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+        order[pos] = (uint32_t)t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_sched_hist(int64_t total, const uint32_t* __restrict__ ranges,
@@ -1080,15 +1043,19 @@ extern "C" qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile
     QG_REQUIRE(schedule_words >= qg_schedule_words(total_tiles), "schedule buffer too small: %lld < %lld words",
                (long long)schedule_words, (long long)qg_schedule_words(total_tiles));
     hipStream_t s = (hipStream_t)stream;
-    uint32_t* hist = schedule + 2;
+    uint32_t* hist = schedule;
     uint32_t* order = schedule + QG_SCHEDULE_HEADER_WORDS;
     const unsigned grid = (unsigned)ceil_div(total_tiles, 256);
     {
         QG_TIMED("schedule", s);
-        k_sched_clear<<<(unsigned)ceil_div(QG_SCHEDULE_HEADER_WORDS, 256), 256, 0, s>>>(schedule);
-        k_sched_hist<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist);
-        k_sched_scan<<<1, kSchedBuckets, 0, s>>>(hist);
-        k_sched_scatter<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist, order);
+        if (total_tiles <= kSchedOneBlock) {
+            k_sched_one<<<1, 1024, 0, s>>>(total_tiles, tile_ranges, order);
+        } else {
+            k_sched_clear<<<(unsigned)ceil_div(QG_SCHEDULE_HEADER_WORDS, 256), 256, 0, s>>>(schedule);
+            k_sched_hist<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist);
+            k_sched_scan<<<1, kSchedBuckets, 0, s>>>(hist);
+            k_sched_scatter<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist, order);
+        }
     }
     QG_LAUNCH_CHECK("qg_schedule_tiles");
     return QG_OK;

@@ -39,6 +39,7 @@ class FitConfig:
     hidden: int = 32
     tile: tuple = (16, 16)
     batch: int = 0  # blend LDS batch depth (0 = 64)
+    heaviest_first: bool = True  # blend tiles in heaviest-first order (a scheduling choice; results unchanged)
     sh_degree: int = 3
     dilation: float = 0.3
     bg: tuple = (0.0, 0.0, 0.0)
@@ -242,7 +243,8 @@ class FrameFitter(ResidualState):
         self.dws = torch.empty(self.dws_bytes, dtype=torch.uint8, device=dev)
         self.fused = not self.linear
         self.rast = Rasterizer(n, [self.cams[0]], tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
-                               bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch)
+                               bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch,
+                               heaviest_first=cfg.heaviest_first)
         if cfg.densify:  # the densification statistic and the per-view viewspace gradient it is taken from
             self.d_accum = torch.zeros(max(n, 1), device=dev)
             self.d_count = torch.zeros(max(n, 1), device=dev)
@@ -467,17 +469,18 @@ class BatchedFitter(ResidualState):
     their tiles, and the loss is the mean over the group's views of the per-view mean L1 (weight 1/V each).
     The step has no host synchronisation and no host-dependent arguments (the Adam step count lives on the
     device), so each group's step is captured once into a graph and replayed.  Blend scheduling (tile shape,
-    LDS batch depth, persistent heaviest-first order) is chosen per fitter; results do not depend on it."""
+    LDS batch depth, heaviest-first tile order) is chosen per fitter; results do not depend on it."""
 
     def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
-                 capacity=None, seed=0, batch=0, persistent=True, graph=True, eval_cam=None):
+                 capacity=None, seed=0, batch=0, heaviest_first=None, graph=True, eval_cam=None):
         super().__init__(prev_attrs, cfg, W1, W2, seed, lr_scale=cfg.batched_lr_scale)
         assert not self.linear, "batched steps use the fused MLP-decoder calls"
         self.cams = list(cams)
         # the captured steps read the ground truth from these buffers: new frames are copied into them
         self.gts = [g.clone() for g in gts]
         self.groups = view_groups(len(self.cams), min(int(cfg.group_views), qg.MAX_VIEWS))
-        self.batch, self.persistent, self.use_graph = int(batch), bool(persistent), bool(graph)
+        hf = cfg.heaviest_first if heaviest_first is None else bool(heaviest_first)
+        self.batch, self.heaviest_first, self.use_graph = int(batch), hf, bool(graph)
         dev = self.device
         n = self.n
         self.rasts = []
@@ -485,7 +488,7 @@ class BatchedFitter(ResidualState):
         for g in self.groups:
             r = Rasterizer(n, [self.cams[v] for v in g], tile=cfg.tile, sh_degree=cfg.sh_degree,
                            dilation=cfg.dilation, bg=cfg.bg, device=dev, capacity=capacity, batch=batch,
-                           persistent=persistent)
+                           heaviest_first=hf)
             self.rasts.append(r)
             self.gimgs.append([torch.empty_like(im) for im in r.images])
             self.counts.append([im.numel() for im in r.images])

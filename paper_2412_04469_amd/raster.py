@@ -20,13 +20,13 @@ def _u32(shape, device):
 
 class Rasterizer:
     def __init__(self, n, cams, tile=(16, 16), sh_degree=3, dilation=0.3, bg=(0.0, 0.0, 0.0), device="cuda",
-                 capacity=None, want_keys=False, batch=0, persistent=False):
+                 capacity=None, want_keys=False, batch=0, heaviest_first=False):
         self.n = int(n)
         self.cams = list(cams)
         self.V = len(self.cams)
         self.tile_wh = tuple(tile)
         self.batch = int(batch)
-        self.persistent = bool(persistent)
+        self.heaviest_first = bool(heaviest_first)
         self.tile = qg.tiling(*tile)
         self.sh_degree = int(sh_degree)
         self.dilation = float(dilation)
@@ -47,7 +47,7 @@ class Rasterizer:
         self.total_tiles = qg.qg_total_tiles(self.cams, self.tile)
         self.ranges = _u32((self.total_tiles, 2), d)
         self.schedule = None
-        if self.persistent:
+        if self.heaviest_first:  # blend tiles in heaviest-first order (qg_schedule_tiles after each binning)
             self.schedule = torch.zeros(qg.qg_schedule_words(self.total_tiles), dtype=torch.int32, device=d)
         self.tile = qg.tiling(*tile, batch=self.batch, schedule=self.schedule)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=d)

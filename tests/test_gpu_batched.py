@@ -1,6 +1,6 @@
 """Multi-view batching, blend scheduling and graph replay (GPU, through the C ABI).
 
-* Blend scheduling (LDS batch depth 32/64/128, persistent heaviest-first order) changes no result: images,
+* Blend scheduling (LDS batch depth 32/64/128, heaviest-first tile order) changes no result: images,
   T_final and last are bit-identical, the adjoint equal up to the order of its float atomics.
 * A batched multi-view launch equals the per-view launches: images and T_final bit-identical, each tile's
   entry list identical, each pixel's last contributor at the same position in its tile's list; the
@@ -31,8 +31,8 @@ def uneven_cams():
             synth.make_camera((-2.5, 0.4, -3.0), 70, 45, f=64)]
 
 
-def _render(raster, sc, cams, tile=(16, 16), batch=0, persistent=False):
-    rast = raster.Rasterizer(sc.n, cams, tile=tile, batch=batch, persistent=persistent, bg=(0.1, 0.2, 0.3))
+def _render(raster, sc, cams, tile=(16, 16), batch=0, heaviest_first=False):
+    rast = raster.Rasterizer(sc.n, cams, tile=tile, batch=batch, heaviest_first=heaviest_first, bg=(0.1, 0.2, 0.3))
     attrs = to_dev(sc.planes())
     rast.forward(attrs)
     torch.cuda.synchronize()
@@ -51,14 +51,23 @@ def _grad_images(cams, seed):
     return [to_dev(rng.normal(size=(3, c.height, c.width)) / (3 * c.width * c.height)) for c in cams]
 
 
-def test_schedule_is_heaviest_first_permutation(qgm):
+@pytest.mark.parametrize("large", [False, True])
+def test_schedule_is_heaviest_first_permutation(qgm, large):
+    """Up to 2^18 tiles one workgroup builds the order; above (three 3840x2160 views in 8x8 tiles: 388,800) a
+    histogram, a scan and a scatter kernel do.  Either way the images equal the unscheduled render's bit for
+    bit."""
     qg, raster = qgm
     sc = small_scene(seed=30, n=5000)
-    cams = uneven_cams()
-    rast, _ = _render(raster, sc, cams, persistent=True)
+    cams = uneven_cams() if not large else [synth.make_camera((0.3 * v, 0.0, -4.0), 3840, 2160, f=3200)
+                                            for v in range(3)]
+    tile = (16, 16) if not large else (8, 8)
+    rast, _ = _render(raster, sc, cams, tile, heaviest_first=True)
+    assert (rast.total_tiles > 1 << 18) == large
+    ref, _ = _render(raster, sc, cams, tile)
+    for v in range(len(cams)):
+        assert torch.equal(rast.images[v], ref.images[v])
     s = rast.schedule.cpu().numpy().view(np.uint32)
-    hdr = 2 + 512
-    assert s[0] == 0 and s[1] == 0  # the blend left the work counters at zero
+    hdr = 512  # QG_SCHEDULE_HEADER_WORDS: the bucket words, then the order
     order = s[hdr:hdr + rast.total_tiles].astype(np.int64)
     assert np.array_equal(np.sort(order), np.arange(rast.total_tiles))
     rg = rast.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
@@ -79,18 +88,18 @@ def test_blend_scheduling_does_not_change_results(qgm, tile):
     ref, attrs = _render(raster, sc, cams, tile)
     gis = _grad_images(cams, 7)
     g_ref = _grad(ref, attrs, gis)
-    for batch, persistent in [(32, False), (128, False), (64, True), (128, True), (32, True)]:
-        r, _ = _render(raster, sc, cams, tile, batch, persistent)
-        for rep in range(2):  # the persistent counters must be back at zero for the second launch
+    for batch, heaviest_first in [(32, False), (128, False), (64, True), (128, True), (32, True)]:
+        r, _ = _render(raster, sc, cams, tile, batch, heaviest_first)
+        for rep in range(2):  # a second launch on the same buffers gives the same result
             if rep:
                 r.render()
                 torch.cuda.synchronize()
             for v in range(len(cams)):
-                assert torch.equal(r.images[v], ref.images[v]), (batch, persistent, v)
+                assert torch.equal(r.images[v], ref.images[v]), (batch, heaviest_first, v)
                 assert torch.equal(r.tfinal[v], ref.tfinal[v])
                 assert torch.equal(r.last[v], ref.last[v])
         g = _grad(r, attrs, gis)
-        assert rel_l2(g, g_ref) <= 1e-5, (batch, persistent, rel_l2(g, g_ref))
+        assert rel_l2(g, g_ref) <= 1e-5, (batch, heaviest_first, rel_l2(g, g_ref))
 
 
 def _tile_of_pixels(cam, tw, th, off):
@@ -100,13 +109,13 @@ def _tile_of_pixels(cam, tw, th, off):
     return off + ty[:, None] * gw + tx[None, :]
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batched_views_equal_single_views(qgm, persistent):
+@pytest.mark.parametrize("heaviest_first", [False, True])
+def test_batched_views_equal_single_views(qgm, heaviest_first):
     qg, raster = qgm
     sc = small_scene(seed=32, n=6000)
     cams = uneven_cams()
     tw, th = 16, 16
-    bat, attrs = _render(raster, sc, cams, (tw, th), 64, persistent)
+    bat, attrs = _render(raster, sc, cams, (tw, th), 64, heaviest_first)
     gis = _grad_images(cams, 8)
     g_bat = _grad(bat, attrs, gis)
     g_sum = np.zeros_like(g_bat)
@@ -168,7 +177,7 @@ def test_graph_replay_matches_eager_step(qgm):
     qg, raster = qgm
     from paper_2412_04469_amd.fit import BatchedFitter
     prev, cams, gts = _fit_inputs()
-    f = BatchedFitter(prev, cams, gts, persistent=True, graph=True)
+    f = BatchedFitter(prev, cams, gts, heaviest_first=True, graph=True)
     f.size_capacity()
     f.step()  # eager first step, then capture
     torch.cuda.synchronize()
@@ -198,7 +207,7 @@ def test_batched_fit_reduces_loss(qgm):
     qg, raster = qgm
     from paper_2412_04469_amd.fit import BatchedFitter
     prev, cams, gts = _fit_inputs(seed=35)
-    f = BatchedFitter(prev, cams, gts, persistent=True, graph=True)
+    f = BatchedFitter(prev, cams, gts, heaviest_first=True, graph=True)
     f.size_capacity()
     f.step()
     first = np.mean(f.losses())

@@ -179,7 +179,7 @@ def test_batched_workload_fullsize_sampled_parity():
     lp = rng.normal(0, 0.01, (3, n)).astype(np.float32)
     a = rng.normal(0, 1.0, n).astype(np.float32)
     gts = [torch.zeros(3, c.height, c.width, device="cuda") for c in wl.cams]
-    f = BatchedFitter(to_dev(prev), wl.cams, gts, cfg, persistent=False, graph=False)
+    f = BatchedFitter(to_dev(prev), wl.cams, gts, cfg, heaviest_first=False, graph=False)
     assert len(f.groups) == 1 and len(f.groups[0]) == 12
     f.lat.copy_(to_dev(lat))
     f.lp.copy_(to_dev(lp))

@@ -76,13 +76,13 @@ def test_autotune_cache_returns_the_stored_choice(tmp_path):
     assert key.endswith("|V3") and "n2^19" in key
     path = str(tmp_path / "tune.json")
     with open(path, "w") as f:
-        json.dump({key: {"tile": [32, 8], "batch": 256, "persistent": False, "ms": 6.1}}, f)
+        json.dump({key: {"tile": [32, 8], "batch": 256, "heaviest_first": False, "ms": 6.1}}, f)
 
     def never(**_):
         raise AssertionError("a cached choice must not be timed")
 
     best, table = AT.autotune(never, cache_path=path, key=key)
-    assert best == {"tile": (32, 8), "batch": 256, "persistent": False} and table == []
+    assert best == {"tile": (32, 8), "batch": 256, "heaviest_first": False} and table == []
     assert len(AT.candidates()) == 24
 
 
