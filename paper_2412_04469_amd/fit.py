@@ -621,7 +621,8 @@ class AttributeFitter:
         self.cams = list(cams)
         self.gts = [g.clone() for g in gts]
         self.rast = Rasterizer(self.n, self.cams, tile=cfg.tile, sh_degree=cfg.sh_degree, dilation=cfg.dilation,
-                               bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch)
+                               bg=cfg.bg, device=dev, capacity=capacity, batch=cfg.batch,
+                               heaviest_first=cfg.heaviest_first)
         self.grad = torch.zeros_like(self.attrs)
         self.m = torch.zeros_like(self.attrs)
         self.v = torch.zeros_like(self.attrs)
