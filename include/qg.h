@@ -92,12 +92,11 @@ typedef struct {
  *   batch            tile-list entries staged per LDS batch in the blend kernels: 32, 64, 128 or 256 (0 = 64).
  *                    Results do not depend on it.
  *   reserved         must be 0.
- *   schedule         optional device buffer written by qg_schedule_tiles for the current binning: the blend
- *                    kernels' workgroup b then takes the b-th tile of its heaviest-first order (workgroups
- *                    start in index order, so the longest tile lists start first).  NULL = tiles in groups
- *                    of 4x4 dealt round-robin to the XCDs.  One workgroup per tile either way; results do not
- *                    depend on it, except for the order of the float atomics of the blend adjoint.  The blend
- *                    calls only read the buffer.
+ *   schedule         optional device buffer written by qg_schedule_tiles for the current binning.  NULL =
+ *                    tiles in groups of 4x4 dealt round-robin to the 8 XCDs; with a schedule each XCD keeps
+ *                    the same tiles and takes them heaviest first.  One workgroup per tile either way; results
+ *                    do not depend on it, except for the order of the float atomics of the blend adjoint.  The
+ *                    blend calls only read the buffer.
  * qg_project and qg_bin read only the tile shape.
  */
 typedef struct {
@@ -295,18 +294,21 @@ qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* cams, int32_t
                         float* const* T_final, uint32_t* const* last, qg_stream stream);
 
 /*
- * Heaviest-first tile order for the blend kernels (a scheduling aid; no arithmetic of the method).
- * schedule [device] qg_schedule_words(total_tiles) words: QG_SCHEDULE_BUCKETS working words (bucket offsets),
- * then the order of all tiles by decreasing entry count (on a log scale, 8 steps per octave; order within a
- * step is arbitrary).  Build it after each qg_bin and pass it as qg_tiling.schedule to qg_render_fwd /
- * qg_render_bwd / qg_render_decode_bwd.  Up to 2^18 tiles one workgroup builds it in LDS.  Stream-ordered,
- * no allocation, safe under graph capture.
+ * Heaviest-first tile order for the blend kernels (a scheduling aid; no arithmetic of the method).  Each tile
+ * keeps the XCD that the 4x4 super-tile order gives it (neighbouring tiles share an L2); within each XCD the
+ * tiles are ordered by decreasing entry count (on a log scale, 8 steps per octave; order within a step is
+ * arbitrary), so that on every XCD the longest tile lists start first.
+ * cams [host] V, tiling: the cameras and tiling of the binning (tile shape only is read).
+ * schedule [device] qg_schedule_words(total_tiles) words: the 8 XCD segments' starts and lengths, 8 * 512
+ * working words, then the order.  Build it after each qg_bin and pass it as qg_tiling.schedule to
+ * qg_render_fwd / qg_render_bwd / qg_render_decode_bwd.  Up to 2^18 tiles one workgroup builds it in LDS.
+ * Stream-ordered, no allocation, safe under graph capture.  QG_ERR_ARG for bad cameras, NULL pointers or a
+ * short buffer.
  */
-#define QG_SCHEDULE_BUCKETS 512
-#define QG_SCHEDULE_HEADER_WORDS QG_SCHEDULE_BUCKETS
+#define QG_SCHEDULE_HEADER_WORDS (16 + 8 * 512)
 int64_t qg_schedule_words(int64_t total_tiles);
-qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile_ranges, uint32_t* schedule,
-                            int64_t schedule_words, qg_stream stream);
+qg_status qg_schedule_tiles(const qg_camera* cams, int32_t V, qg_tiling tiling, const uint32_t* tile_ranges,
+                            uint32_t* schedule, int64_t schedule_words, qg_stream stream);
 
 /*
  * Adjoint of qg_render_fwd followed by the adjoint of qg_project (Eq. 1-2), for the loss gradient

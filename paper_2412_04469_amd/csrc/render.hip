@@ -67,6 +67,11 @@ struct TileMap {
     int32_t sw[QG_MAX_VIEWS];          // super-tiles per row of each view
 };
 
+// XCD of a tile under that order: its super-tile's index mod 8.
+__device__ __forceinline__ uint32_t xcd_of_tile(const TileMap& m, const ViewTable& vt, int v, int tx, int ty) {
+    return (uint32_t)((m.sup_off[v] + (int64_t)(ty / m.S) * m.sw[v] + tx / m.S) & 7);
+}
+
 // Global tile of workgroup b, or -1 for a workgroup that falls on padding.
 __device__ __forceinline__ int64_t map_tile(const TileMap& m, const ViewTable& vt, int64_t b) {
     const int S2 = m.S * m.S;
@@ -250,12 +255,20 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
 }
 
 // Work distribution: one workgroup per tile.  Without a schedule, in the super-tile order of map_tile.  With a
-// schedule (qg_schedule_tiles, heaviest tiles first), workgroup b takes tile order[b]: workgroups are dispatched
-// in index order, round-robin over the XCDs and their CUs, so the longest tile lists start first and spread over
-// the SIMDs, and the short ones fill in behind them.
+// schedule (qg_schedule_tiles), each XCD keeps the same tiles, taken heaviest first: workgroup b runs on XCD
+// x = b mod 8 and takes the (b div 8)-th tile of x's segment of the order.  Workgroups start in index order,
+// so on every XCD the longest tile lists start first and spread over its SIMDs, and the short ones fill in
+// behind them, while neighbouring tiles still share the XCD's L2.
 struct Sched {
-    const uint32_t* order;  // [total_tiles] or nullptr
+    const uint32_t* seg;    // [16]: start and length of each XCD's segment of the order, or nullptr
+    const uint32_t* order;  // [total_tiles]
 };
+
+__device__ __forceinline__ int64_t sched_tile(const Sched& sc, const TileMap& tm, const ViewTable& vt) {
+    if (!sc.seg) return map_tile(tm, vt, blockIdx.x);
+    const uint32_t x = blockIdx.x & 7, k = blockIdx.x >> 3;
+    return k < sc.seg[8 + x] ? (int64_t)sc.order[sc.seg[x] + k] : -1;
+}
 
 template <int TW, int TH, int BD>
 __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
@@ -266,8 +279,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t*
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float s_c[BD];   // b
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
-    const int64_t tile = sc.order ? (blockIdx.x < vt.total_tiles ? (int64_t)sc.order[blockIdx.x] : -1)
-                                  : map_tile(tm, vt, blockIdx.x);
+    const int64_t tile = sched_tile(sc, tm, vt);
     if (tile >= 0)
         fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c, s_pos);
 }
@@ -489,8 +501,7 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
     __shared__ uint32_t s_gid[BD];
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     __shared__ float s_red[8][12];  // half-row totals of the 9 gradient components
-    const int64_t tile = sc.order ? (blockIdx.x < vt.total_tiles ? (int64_t)sc.order[blockIdx.x] : -1)
-                                  : map_tile(tm, vt, blockIdx.x);
+    const int64_t tile = sched_tile(sc, tm, vt);
     if (tile >= 0)
         bwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, tfinal, lastp, gimage, grad2d, g2d_view_stride, pp, tile,
                              s_a, s_b, s_c, s_gid, s_pos, s_red);
@@ -499,25 +510,38 @@ __global__ __launch_bounds__(64, 5) void k_render_bwd(ViewTable vt, const uint32
 // The plain grid's tile order (super-tiles of 4 x 4 tiles) and its size, a multiple of 8 * 16 workgroups.
 constexpr int kSuperTile = 4;
 
-TileMap make_tile_map(const ViewTable& vt, int64_t* grid) {
+TileMap make_tile_map(const ViewTable& vt, int64_t* grid, int64_t* xcd_max = nullptr) {
     TileMap m{};
     m.S = kSuperTile;
     m.V = vt.V;
     int64_t j = 0;
+    int64_t per_xcd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int v = 0; v < vt.V; ++v) {
         m.sup_off[v] = (int32_t)j;
-        m.sw[v] = (int32_t)ceil_div(vt.cam[v].grid_w, kSuperTile);
-        j += (int64_t)m.sw[v] * ceil_div(vt.cam[v].grid_h, kSuperTile);
+        const int gw = vt.cam[v].grid_w, gh = vt.cam[v].grid_h;
+        m.sw[v] = (int32_t)ceil_div(gw, kSuperTile);
+        const int64_t sh = ceil_div(gh, kSuperTile);
+        if (xcd_max) {  // tiles of each XCD: whole super-tiles, plus the clipped ones of the last row and column
+            for (int64_t sy = 0; sy < sh; ++sy)
+                for (int64_t sx = 0; sx < m.sw[v]; ++sx)
+                    per_xcd[(j + sy * m.sw[v] + sx) & 7] += std::min<int64_t>(kSuperTile, gw - sx * kSuperTile) *
+                                                             std::min<int64_t>(kSuperTile, gh - sy * kSuperTile);
+        }
+        j += (int64_t)m.sw[v] * sh;
     }
     m.sup_off[vt.V] = (int32_t)j;
     m.supers = j;
     *grid = ceil_div(j, 8) * 8 * kSuperTile * kSuperTile;
+    if (xcd_max) *xcd_max = *std::max_element(per_xcd, per_xcd + 8);
     return m;
 }
 
 inline Sched make_sched(const qg_tiling& t) {
-    Sched sc = {nullptr};
-    if (t.schedule) sc.order = t.schedule + QG_SCHEDULE_HEADER_WORDS;
+    Sched sc = {nullptr, nullptr};
+    if (t.schedule) {
+        sc.seg = t.schedule;
+        sc.order = t.schedule + QG_SCHEDULE_HEADER_WORDS;
+    }
     return sc;
 }
 
@@ -525,10 +549,10 @@ template <int TW, int TH, int BD>
 qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp,
                        hipStream_t s) {
-    int64_t grid = 0;
-    const TileMap tm = make_tile_map(vt, &grid);
+    int64_t grid = 0, xcd_max = 0;
+    const TileMap tm = make_tile_map(vt, &grid, tiling.schedule ? &xcd_max : nullptr);
     const Sched sc = make_sched(tiling);
-    if (sc.order) grid = vt.total_tiles;
+    if (sc.seg) grid = 8 * xcd_max;
     {
         QG_TIMED("render_fwd", s);
         k_render_fwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp,
@@ -542,10 +566,10 @@ template <int TW, int TH, int BD>
 qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsCF& tf, const ViewPtrsCU& lp, const ViewPtrsCF& gi,
                        float* grad2d, int64_t stride, PairPart pp, hipStream_t s) {
-    int64_t grid = 0;
-    const TileMap tm = make_tile_map(vt, &grid);
+    int64_t grid = 0, xcd_max = 0;
+    const TileMap tm = make_tile_map(vt, &grid, tiling.schedule ? &xcd_max : nullptr);
     const Sched sc = make_sched(tiling);
-    if (sc.order) grid = vt.total_tiles;
+    if (sc.seg) grid = 8 * xcd_max;
     {
         QG_TIMED("blend_bwd", s);
         k_render_bwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], tf, lp, gi,
@@ -703,14 +727,17 @@ qg_status launch_bwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* va
     return QG_OK;
 }
 
-// ---- heaviest-first tile order --------------------------------------------------------------------
-// Tiles are bucketed by the length of their entry list on a log scale (float exponent and the top three
-// mantissa bits, 8 buckets per octave), buckets are laid out heaviest first, and tiles are scattered into
-// their bucket (order inside a bucket is arbitrary: every tile is blended by exactly one wave either way).
-// Up to kSchedOneBlock tiles one workgroup does it all in LDS; above, a histogram, a scan and a scatter kernel
-// go through the schedule's bucket words.
-constexpr int kSchedBuckets = QG_SCHEDULE_BUCKETS;
+// ---- heaviest-first tile order, per XCD ----------------------------------------------------------------
+// Every tile keeps the XCD that the super-tile order gives it.  Within each XCD the tiles are ordered by the
+// length of their entry list, heaviest first, on a log scale (float exponent and the top three mantissa bits, 8
+// buckets per octave; order inside a bucket is arbitrary: every tile is blended by exactly one wave either way).
+// The sort key is (XCD, bucket).  Schedule layout: 8 segment starts, 8 segment lengths, kSchedKeys key words,
+// then the order.  Up to kSchedOneBlock tiles one workgroup builds it in LDS; above, a histogram, a scan and a
+// scatter kernel go through the key words.
+constexpr int kSchedBuckets = 512;
+constexpr int kSchedKeys = 8 * kSchedBuckets;
 constexpr int64_t kSchedOneBlock = 1 << 18;
+static_assert(QG_SCHEDULE_HEADER_WORDS == 16 + kSchedKeys, "schedule header: 8 starts, 8 lengths, the key words");
 
 __device__ __forceinline__ uint32_t sched_bucket(uint32_t len) {
     if (len == 0) return kSchedBuckets - 1;
@@ -718,74 +745,89 @@ __device__ __forceinline__ uint32_t sched_bucket(uint32_t len) {
     return (uint32_t)(kSchedBuckets - 2) - min(key, (uint32_t)(kSchedBuckets - 2));
 }
 
-__global__ void k_sched_clear(uint32_t* __restrict__ w) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < QG_SCHEDULE_HEADER_WORDS) w[i] = 0u;
+__device__ __forceinline__ uint32_t sched_key(const TileMap& m, const ViewTable& vt, const uint32_t* __restrict__ ranges,
+                                              int64_t t) {
+    const int v = view_of_tile(vt, (uint32_t)t);
+    const CamDev& c = vt.cam[v];
+    const int local = (int)((uint32_t)t - c.tile_off);
+    return xcd_of_tile(m, vt, v, local % c.grid_w, local / c.grid_w) * kSchedBuckets +
+           sched_bucket(ranges[2 * t + 1] - ranges[2 * t]);
 }
 
-// The whole order in one workgroup of 1024 threads: histogram, exclusive scan and scatter in LDS.
-__global__ __launch_bounds__(1024) void k_sched_one(int64_t total, const uint32_t* __restrict__ ranges,
-                                                    uint32_t* __restrict__ order) {
-    __shared__ uint32_t s_h[kSchedBuckets];
-    __shared__ uint32_t s_w[1024 / 64];
-    for (int k = threadIdx.x; k < kSchedBuckets; k += blockDim.x) s_h[k] = 0;
-    __syncthreads();
-    for (int64_t t = threadIdx.x; t < total; t += blockDim.x)
-        atomicAdd(&s_h[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
-    __syncthreads();
-    // exclusive scan of the kSchedBuckets counts: wave scans, then the wave totals in order
+// In-place exclusive scan of kSchedKeys counts by a workgroup of 1024 threads (four consecutive keys each), and
+// the 8 XCD segments' starts and lengths into seg[0..15].  `total` is the sum of the counts.
+__device__ __forceinline__ void sched_scan_keys(uint32_t* h, uint32_t* s_w, uint32_t* seg, uint32_t total) {
     const int k = threadIdx.x, w = k / 64, lane = __lane_id();
-    uint32_t c = k < kSchedBuckets ? s_h[k] : 0u, x = c;
+    uint32_t c[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = h[4 * k + i];
+    const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+    uint32_t x = sum;
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(x, o);
         if (lane >= o) x += y;
     }
     if (lane == 63) s_w[w] = x;
     __syncthreads();
-    uint32_t base = 0;
-    for (int j = 0; j < w; ++j) base += s_w[j];
-    if (k < kSchedBuckets) s_h[k] = base + x - c;
-    __syncthreads();
-    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
-        const uint32_t pos = atomicAdd(&s_h[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
-        order[pos] = (uint32_t)t;
+    uint32_t run = x - sum;
+    for (int j = 0; j < w; ++j) run += s_w[j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[4 * k + i] = run;
+        run += c[i];
     }
+    __syncthreads();
+    if (k < 8) {
+        const uint32_t st = h[k * kSchedBuckets];
+        seg[k] = st;
+        seg[8 + k] = (k < 7 ? h[(k + 1) * kSchedBuckets] : total) - st;
+    }
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_sched_hist(int64_t total, const uint32_t* __restrict__ ranges,
-                                                    uint32_t* __restrict__ hist) {
-    __shared__ uint32_t s_h[kSchedBuckets];
-    for (int k = threadIdx.x; k < kSchedBuckets; k += blockDim.x) s_h[k] = 0;
+// The whole schedule in one workgroup of 1024 threads: key histogram, scan and scatter in LDS.
+__global__ __launch_bounds__(1024) void k_sched_one(int64_t total, ViewTable vt, TileMap tm,
+                                                    const uint32_t* __restrict__ ranges, uint32_t* __restrict__ sched) {
+    __shared__ uint32_t s_h[kSchedKeys];
+    __shared__ uint32_t s_w[1024 / 64];
+    for (int k = threadIdx.x; k < kSchedKeys; k += blockDim.x) s_h[k] = 0;
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < total) atomicAdd(&s_h[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) atomicAdd(&s_h[sched_key(tm, vt, ranges, t)], 1u);
     __syncthreads();
-    for (int k = threadIdx.x; k < kSchedBuckets; k += blockDim.x)
+    sched_scan_keys(s_h, s_w, sched, (uint32_t)total);
+    uint32_t* order = sched + QG_SCHEDULE_HEADER_WORDS;
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x)
+        order[atomicAdd(&s_h[sched_key(tm, vt, ranges, t)], 1u)] = (uint32_t)t;
+}
+
+__global__ void k_sched_clear(uint32_t* __restrict__ w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < QG_SCHEDULE_HEADER_WORDS) w[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sched_hist(int64_t total, ViewTable vt, TileMap tm,
+                                                    const uint32_t* __restrict__ ranges, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[kSchedKeys];
+    for (int k = threadIdx.x; k < kSchedKeys; k += blockDim.x) s_h[k] = 0;
+    __syncthreads();
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&s_h[sched_key(tm, vt, ranges, t)], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kSchedKeys; k += blockDim.x)
         if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
 }
 
-// Exclusive scan of the bucket counts in place (one workgroup of kSchedBuckets threads).
-__global__ __launch_bounds__(kSchedBuckets) void k_sched_scan(uint32_t* __restrict__ hist) {
-    __shared__ uint32_t s[kSchedBuckets];
-    const int k = threadIdx.x;
-    const uint32_t c = hist[k];
-    s[k] = c;
-    __syncthreads();
-    for (int off = 1; off < kSchedBuckets; off <<= 1) {
-        const uint32_t add = k >= off ? s[k - off] : 0u;
-        __syncthreads();
-        s[k] += add;
-        __syncthreads();
-    }
-    hist[k] = s[k] - c;
+__global__ __launch_bounds__(1024) void k_sched_scan(int64_t total, uint32_t* __restrict__ sched) {
+    __shared__ uint32_t s_w[1024 / 64];
+    sched_scan_keys(sched + 16, s_w, sched, (uint32_t)total);
 }
 
-__global__ void k_sched_scatter(int64_t total, const uint32_t* __restrict__ ranges, uint32_t* __restrict__ offs,
-                                uint32_t* __restrict__ order) {
+__global__ void k_sched_scatter(int64_t total, ViewTable vt, TileMap tm, const uint32_t* __restrict__ ranges,
+                                uint32_t* __restrict__ sched) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const uint32_t pos = atomicAdd(&offs[sched_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
-    order[pos] = (uint32_t)t;
+    const uint32_t pos = atomicAdd(&sched[16 + sched_key(tm, vt, ranges, t)], 1u);
+    sched[QG_SCHEDULE_HEADER_WORDS + pos] = (uint32_t)t;
 }
 
 // ---- adaptive masked training (Sec. 3.3, "Adaptive Masked Training") -------------------------------
@@ -1034,27 +1076,30 @@ extern "C" int64_t qg_schedule_words(int64_t total_tiles) {
     return QG_SCHEDULE_HEADER_WORDS + total_tiles;
 }
 
-extern "C" qg_status qg_schedule_tiles(int64_t total_tiles, const uint32_t* tile_ranges, uint32_t* schedule,
-                                       int64_t schedule_words, qg_stream stream) {
+extern "C" qg_status qg_schedule_tiles(const qg_camera* cams, int32_t V, qg_tiling tiling, const uint32_t* tile_ranges,
+                                       uint32_t* schedule, int64_t schedule_words, qg_stream stream) {
     clear_error();
-    QG_REQUIRE(total_tiles >= 1 && total_tiles < (1ll << 32), "total_tiles=%lld outside [1, 2^32)",
-               (long long)total_tiles);
+    ViewTable vt;
+    if (!make_view_table(cams, nullptr, V, tiling, false, &vt)) return QG_ERR_ARG;
+    const int64_t total_tiles = vt.total_tiles;
+    QG_REQUIRE(total_tiles >= 1, "no tiles");
     QG_REQUIRE(tile_ranges && schedule, "a pointer is NULL");
     QG_REQUIRE(schedule_words >= qg_schedule_words(total_tiles), "schedule buffer too small: %lld < %lld words",
                (long long)schedule_words, (long long)qg_schedule_words(total_tiles));
+    int64_t grid_unused = 0;
+    const TileMap tm = make_tile_map(vt, &grid_unused);
     hipStream_t s = (hipStream_t)stream;
-    uint32_t* hist = schedule;
-    uint32_t* order = schedule + QG_SCHEDULE_HEADER_WORDS;
-    const unsigned grid = (unsigned)ceil_div(total_tiles, 256);
     {
         QG_TIMED("schedule", s);
         if (total_tiles <= kSchedOneBlock) {
-            k_sched_one<<<1, 1024, 0, s>>>(total_tiles, tile_ranges, order);
+            k_sched_one<<<1, 1024, 0, s>>>(total_tiles, vt, tm, tile_ranges, schedule);
         } else {
+            const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total_tiles, 256), 1024);
             k_sched_clear<<<(unsigned)ceil_div(QG_SCHEDULE_HEADER_WORDS, 256), 256, 0, s>>>(schedule);
-            k_sched_hist<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist);
-            k_sched_scan<<<1, kSchedBuckets, 0, s>>>(hist);
-            k_sched_scatter<<<grid, 256, 0, s>>>(total_tiles, tile_ranges, hist, order);
+            k_sched_hist<<<grid, 256, 0, s>>>(total_tiles, vt, tm, tile_ranges, schedule + 16);
+            k_sched_scan<<<1, 1024, 0, s>>>(total_tiles, schedule);
+            k_sched_scatter<<<(unsigned)ceil_div(total_tiles, 256), 256, 0, s>>>(total_tiles, vt, tm, tile_ranges,
+                                                                                 schedule);
         }
     }
     QG_LAUNCH_CHECK("qg_schedule_tiles");

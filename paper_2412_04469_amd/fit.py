@@ -292,9 +292,10 @@ class FrameFitter(ResidualState):
             qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                  self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
                                  r.t_proj, self.attrs, self.gate, None, stream, gate_noise=self.noise)
-            r.bin(stream)
-            if masked:
+            r.bin(stream, schedule=not masked)
+            if masked:  # the blend order is taken over the masked tile lists
                 qg.qg_mask_tile_ranges(r.total_tiles, r.ranges, self.masks[v][1], stream)
+                r.schedule_tiles(stream)
             r.render(stream)
         else:
             assert not masked, "masked steps use the fused path"

@@ -120,7 +120,7 @@ def lib():
             "qg_proposal_fwd": ([i64, i64, P, P, P, P, i64, P], i32),
             "qg_proposal_bwd_workspace_size": ([], sz),
             "qg_proposal_bwd": ([i64, P, i64, i64, P, P, P, P, P, P, P, sz, P], i32),
-            "qg_schedule_tiles": ([i64, P, P, i64, P], i32),
+            "qg_schedule_tiles": ([CAM, i32, qg_tiling, P, P, i64, P], i32),
             "qg_gate_noise": ([i64, ctypes.c_uint64, i32, P, P, P], i32),
             "qg_linear_decoder_params": ([ctypes.POINTER(i32)], i64),
             "qg_decode_linear_blocks": ([i64], i64),
@@ -256,8 +256,10 @@ def qg_schedule_words(total_tiles):
     return int(lib().qg_schedule_words(int(total_tiles)))
 
 
-def qg_schedule_tiles(total_tiles, tile_ranges, schedule, stream=None):
-    _check(lib().qg_schedule_tiles(int(total_tiles), _ptr(tile_ranges), _ptr(schedule), int(schedule.numel()),
+def qg_schedule_tiles(cams, tile, tile_ranges, schedule, stream=None):
+    """cams: a camera_array (or a list of cameras); tile: the binning's qg_tiling."""
+    ca = camera_array(cams)
+    _check(lib().qg_schedule_tiles(ca, len(ca), tile, _ptr(tile_ranges), _ptr(schedule), int(schedule.numel()),
                                    _stream(stream)))
 
 

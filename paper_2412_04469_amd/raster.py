@@ -94,11 +94,17 @@ class Rasterizer:
         qg.qg_project(self.n, attrs.stride(0), attrs, self.sh_degree, self.qcams, self.tile, self.dilation,
                       self.t_proj, stream)
 
-    def bin(self, stream=None):
+    def bin(self, stream=None, schedule=True):
+        """qg_bin, then (heaviest_first, unless schedule=False) the blend order of the new tile lists."""
         qg.qg_bin(self.n, self.t_proj, self.qcams, self.tile, self.capacity, self.vals, self.keys, self.ranges,
                   self.num_pairs, self.bin_ws, self.bin_ws_bytes, stream)
+        if schedule:
+            self.schedule_tiles(stream)
+
+    def schedule_tiles(self, stream=None):
+        """Heaviest-first blend order of the current tile lists (no-op without heaviest_first)."""
         if self.schedule is not None:
-            qg.qg_schedule_tiles(self.total_tiles, self.ranges, self.schedule, stream)
+            qg.qg_schedule_tiles(self.qcams, self.tile, self.ranges, self.schedule, stream)
 
     def render(self, stream=None):
         qg.qg_render_fwd(self.t_proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.t_img, self.t_tf,

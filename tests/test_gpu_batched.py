@@ -51,11 +51,26 @@ def _grad_images(cams, seed):
     return [to_dev(rng.normal(size=(3, c.height, c.width)) / (3 * c.width * c.height)) for c in cams]
 
 
+def _xcd_of_tiles(cams, tile):
+    """Per global tile, its XCD under the 4x4 super-tile order: the super-tile's index (views in turn, rows of
+    super-tiles in turn) mod 8."""
+    out, j = [], 0
+    for c in cams:
+        gw, gh = -(-c.width // tile[0]), -(-c.height // tile[1])
+        sw, sh = -(-gw // 4), -(-gh // 4)
+        ty, tx = np.divmod(np.arange(gw * gh), gw)
+        out.append((j + (ty // 4) * sw + tx // 4) % 8)
+        j += sw * sh
+    return np.concatenate(out)
+
+
 @pytest.mark.parametrize("large", [False, True])
-def test_schedule_is_heaviest_first_permutation(qgm, large):
-    """Up to 2^18 tiles one workgroup builds the order; above (three 3840x2160 views in 8x8 tiles: 388,800) a
-    histogram, a scan and a scatter kernel do.  Either way the images equal the unscheduled render's bit for
-    bit."""
+def test_schedule_is_heaviest_first_per_xcd(qgm, large):
+    """The schedule holds 8 XCD segments: each holds exactly the tiles that the super-tile order puts on that
+    XCD, heaviest first (up to the 1/8-octave bucket width, empty tiles last), and together they are a
+    permutation of all tiles.  Up to 2^18 tiles one workgroup builds it; above (three 3840x2160 views in 8x8
+    tiles: 388,800) a histogram, a scan and a scatter kernel do.  Either way the images equal the unscheduled
+    render's bit for bit."""
     qg, raster = qgm
     sc = small_scene(seed=30, n=5000)
     cams = uneven_cams() if not large else [synth.make_camera((0.3 * v, 0.0, -4.0), 3840, 2160, f=3200)
@@ -63,21 +78,28 @@ def test_schedule_is_heaviest_first_permutation(qgm, large):
     tile = (16, 16) if not large else (8, 8)
     rast, _ = _render(raster, sc, cams, tile, heaviest_first=True)
     assert (rast.total_tiles > 1 << 18) == large
+    s = rast.schedule.cpu().numpy().view(np.uint32).astype(np.int64)
+    hdr = 16 + 8 * 512  # QG_SCHEDULE_HEADER_WORDS
+    start, length = s[0:8], s[8:16]
+    assert start[0] == 0 and np.array_equal(start[1:], np.cumsum(length)[:-1]) and length.sum() == rast.total_tiles
+    order = s[hdr:hdr + rast.total_tiles]
+    assert np.array_equal(np.sort(order), np.arange(rast.total_tiles))
+    xcd = _xcd_of_tiles(cams, tile)
+    rg = rast.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    lens = rg[:, 1] - rg[:, 0]
+    for x in range(8):
+        seg = order[start[x]:start[x] + length[x]]
+        assert np.all(xcd[seg] == x)
+        ln = lens[seg]
+        if len(ln) == 0:
+            continue
+        assert ln[0] == ln.max() or ln[0] * 9 > ln.max() * 8  # within one bucket (1/8 octave) of the heaviest
+        assert np.all(ln[1:] * 8 <= ln[:-1] * 9 + 8)  # non-increasing up to the bucket width
+        if (ln == 0).any():
+            assert np.all(ln[int(np.argmax(ln == 0)):] == 0)  # empty tiles last
     ref, _ = _render(raster, sc, cams, tile)
     for v in range(len(cams)):
         assert torch.equal(rast.images[v], ref.images[v])
-    s = rast.schedule.cpu().numpy().view(np.uint32)
-    hdr = 512  # QG_SCHEDULE_HEADER_WORDS: the bucket words, then the order
-    order = s[hdr:hdr + rast.total_tiles].astype(np.int64)
-    assert np.array_equal(np.sort(order), np.arange(rast.total_tiles))
-    rg = rast.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
-    ln = (rg[:, 1] - rg[:, 0])[order]
-    assert ln[0] == ln.max() or ln[0] * 9 > ln.max() * 8  # within one bucket (1/8 octave) of the heaviest
-    # non-increasing up to the bucket width; empty tiles last
-    assert np.all(ln[1:] * 8 <= ln[:-1] * 9 + 8)
-    if (ln == 0).any():
-        first_empty = int(np.argmax(ln == 0))
-        assert np.all(ln[first_empty:] == 0)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
