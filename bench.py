@@ -156,6 +156,8 @@ def parse():
     p.add_argument("--no-densify", action="store_true", help="skip the per-frame densification measurement")
     p.add_argument("--no-paper-decoder", action="store_true", help="skip the paper-mode decoder measurement")
     p.add_argument("--config-steps", type=int, default=20, help="timed steps of the small and dense workloads")
+    p.add_argument("--graph", action="store_true",
+                   help="time the headline steps replayed from per-view graphs (the eager time is reported beside)")
     p.add_argument("--oracle-small-reps", type=int, default=10)
     p.add_argument("--oracle-small-only", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -877,21 +879,24 @@ def main():
     prev = torch.as_tensor(wl.scene.planes()).to(dev)
     target = torch.as_tensor(wl.target_scene.planes()).to(dev)
     gts = render_views(target, wl.cams, cfg)
-    fitter = FrameFitter(prev, wl.cams, gts, cfg)
+    fitter = FrameFitter(prev, wl.cams, gts, cfg, graph=args.graph)
     P_max = fitter.size_capacity()
     V = len(wl.cams)
     stream = torch.cuda.current_stream()
 
-    # warm-up, with every kernel bracketed by events to find the per-kernel breakdown (from the second warm-up
-    # step on: the first one also pays each kernel's first launch)
+    # warm-up, eager, with every kernel bracketed by events to find the per-kernel breakdown (from the second
+    # warm-up step on: the first one also pays each kernel's first launch); then every view's step is captured
     timed_warm = max(args.warmup - 1, 1)
     for i in range(args.warmup):
         if i == args.warmup - timed_warm:
             torch.cuda.synchronize()
             qg.qg_timing_enable(True)
-        fitter.step(i % V)
+        fitter.step(i % V, eager=True)
     torch.cuda.synchronize()
     rep = qg.qg_timing_report()
+    if fitter.use_graph:
+        for v in range(V):
+            fitter.capture(v)
     qg.qg_timing_enable(False)
     per_step = {k: ms / timed_warm for k, (c, ms) in rep.items()}
     counts = {k: c / timed_warm for k, (c, ms) in rep.items()}
@@ -908,22 +913,30 @@ def main():
     torch.cuda.synchronize()
     assert not fitter.rast.overflowed()
 
-    # timed region: only the dominant kernel is bracketed by library events
-    qg.qg_timing_enable(True, dominant)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    # timed region: eager steps, only the dominant kernel bracketed by library events (with --graph, the steps
+    # replayed from their graphs, then the same steps eagerly for the dominant kernel's launches)
+    def timed_steps(first, eager):
+        qg.qg_timing_enable(True, dominant)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for i in range(args.steps):
+            fitter.step((first + i) % V, eager=eager)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        dom = qg.qg_timing_report().get(dominant, (0, 0.0))
+        qg.qg_timing_enable(False)
+        return start.elapsed_time(stop) / args.steps, dom
+
     first = args.warmup
-    torch.cuda.synchronize()
-    start.record(stream)
-    for i in range(args.steps):
-        fitter.step((first + i) % V)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_total = start.elapsed_time(stop)
-    dom = qg.qg_timing_report().get(dominant, (0, 0.0))
-    qg.qg_timing_enable(False)
+    ms_step, dom = timed_steps(first, not fitter.use_graph)
     overflow = fitter.rast.overflowed()
-    ms_step = ms_total / args.steps
+    ms_eager = None
+    if fitter.use_graph:
+        # the same steps again, eagerly: the dominant kernel's launches bracketed by events (a replayed graph
+        # holds no library events), and the eager step time beside the replayed one
+        ms_eager, dom = timed_steps(first, True)
     dom_avg_ms = dom[1] / max(dom[0], 1)
     views = [(first + i) % V for i in range(args.steps)]
     mean_evals = float(np.mean([evals[v] for v in views]))
@@ -940,6 +953,8 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for(dominant), "kernel": dominant,
                 "units_per_launch": args.n, "work_per_unit": f"{BYTES_PER_GAUSS.get(dominant)} B per Gaussian"}
     roof["avg_launch_ms"] = round(dom_avg_ms, 4)
+    if fitter.use_graph:
+        roof["timing"] = "event-bracketed launches of the same steps run eagerly after the timed region"
     # the blend forward against the same FP32 peak (its launch time from the event-bracketed warm-up steps)
     fwd_ms = per_step.get("render_fwd", 0.0) / max(counts.get("render_fwd", 1.0), 1e-9)
     blend_fwd = None
@@ -972,12 +987,15 @@ def main():
         "roofline": roof,
         "roofline_blend_fwd": blend_fwd,
         "step_ms_distribution": dist,
+        "step_form": ("one captured graph per view, replayed (the eager step time beside it)" if fitter.use_graph
+                      else "eager launches"),
+        "eager_ms_per_step": None if ms_eager is None else round(ms_eager, 4),
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "launches_per_step": {k: counts[k] for k in sorted(counts)},
     }
     del fitter
     torch.cuda.empty_cache()
-    log(f"headline: {ms_step:.4f} ms/step")
+    log(f"headline: {ms_step:.4f} ms/step" + ("" if ms_eager is None else f" (eager {ms_eager:.4f})"))
     # the measured ceilings beside the datasheet ones, and the blend kernels against the measured FMA rate
     peaks = measured_peaks()
     result["measured_peaks"] = peaks

@@ -327,12 +327,18 @@ __global__ void k_bin_init(ZeroList z) {
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.words[k]; i += stride) z.p[k][i] = 0u;
 }
 
-// Exclusive scan (64-bit) of the tile counts of the items in depth order, reduce then apply: k_count_reduce
-// sums each block's items; k_count_apply adds up the sums of the blocks before its own, scans its items into
-// offs, and its last block writes the total, the tile sort's count (0 on overflow) and the caller's
-// num_pairs.  A thread owns kScanIPT consecutive items.
+// Exclusive scan (64-bit) of the tile counts of the items in order (depth order, or item order when `sorted` is
+// null), reduce then apply: k_count_reduce sums each block's items (pairs and items with a non-empty
+// rectangle) and clears the tile ranges; k_count_apply adds up the sums of the blocks before its own, scans its
+// items, and writes the items with a non-empty rectangle in order, compacted, with their first pair positions
+// (comp_item, comp_offs).  Its last block writes the total, the tile sort's count (0 on overflow), the number of
+// compacted items and the caller's num_pairs.  A thread owns kScanIPT consecutive items.
 constexpr int kScanIPT = 4;
 constexpr int kScanTile = kBlock * kScanIPT;
+
+__device__ __forceinline__ uint32_t item_at(const uint32_t* sorted, int64_t k) {
+    return sorted ? sorted[k] : (uint32_t)k;
+}
 
 __device__ __forceinline__ uint64_t item_tiles(const ViewTable& vt, int64_t n, uint32_t item) {
     int v = 0;
@@ -342,73 +348,109 @@ __device__ __forceinline__ uint64_t item_tiles(const ViewTable& vt, int64_t n, u
 
 __global__ __launch_bounds__(kBlock) void k_count_reduce(int64_t items, int64_t n, ViewTable vt,
                                                          const uint32_t* __restrict__ sorted,
-                                                         uint64_t* __restrict__ bsum) {
+                                                         uint64_t* __restrict__ bsum, uint32_t* __restrict__ vsum,
+                                                         uint32_t* __restrict__ ranges, int64_t range_words) {
     __shared__ uint64_t s_w[kWaves];
+    __shared__ uint32_t s_v[kWaves];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < range_words; i += (int64_t)gridDim.x * kBlock)
+        ranges[i] = 0u;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
     uint64_t acc = 0;
+    uint32_t vis = 0;
 #pragma unroll
     for (int r = 0; r < kScanIPT; ++r) {
         const int64_t k = base + r;
-        if (k < items) acc += item_tiles(vt, n, sorted[k]);
+        if (k < items) {
+            const uint64_t c = item_tiles(vt, n, item_at(sorted, k));
+            acc += c;
+            vis += c > 0;
+        }
     }
     uint64_t tot;
     block_excl_scan<uint64_t>(acc, s_w, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    uint32_t vtot;
+    block_excl_scan<uint32_t>(vis, s_v, &vtot);
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = tot;
+        vsum[blockIdx.x] = vtot;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_count_apply(int64_t items, int64_t n, ViewTable vt,
                                                         const uint32_t* __restrict__ sorted,
                                                         const uint64_t* __restrict__ bsum,
-                                                        uint64_t* __restrict__ offs, int64_t capacity,
+                                                        const uint32_t* __restrict__ vsum,
+                                                        uint32_t* __restrict__ comp_item,
+                                                        uint64_t* __restrict__ comp_offs, int64_t capacity,
                                                         uint32_t* __restrict__ sort_count,
+                                                        uint32_t* __restrict__ n_comp,
                                                         int64_t* __restrict__ num_pairs) {
     __shared__ uint64_t s_w[kWaves];
-    // start of this block: the sum of the blocks before it
+    __shared__ uint32_t s_v[kWaves];
+    // start of this block: the sums of the blocks before it
     uint64_t pre = 0;
-    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) pre += bsum[b];
+    uint32_t vpre = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) {
+        pre += bsum[b];
+        vpre += vsum[b];
+    }
     uint64_t start;
     block_excl_scan<uint64_t>(pre, s_w, &start);
+    uint32_t vstart;
+    block_excl_scan<uint32_t>(vpre, s_v, &vstart);
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
     uint64_t c[kScanIPT];
+    uint32_t it[kScanIPT];
     uint64_t acc = 0;
+    uint32_t vis = 0;
 #pragma unroll
     for (int r = 0; r < kScanIPT; ++r) {
         const int64_t k = base + r;
-        c[r] = k < items ? item_tiles(vt, n, sorted[k]) : 0;
+        it[r] = k < items ? item_at(sorted, k) : 0u;
+        c[r] = k < items ? item_tiles(vt, n, it[r]) : 0;
         acc += c[r];
+        vis += c[r] > 0;
     }
     uint64_t btot;
     const uint64_t ex = block_excl_scan<uint64_t>(acc, s_w, &btot);
+    uint32_t vbtot;
+    const uint32_t vex = block_excl_scan<uint32_t>(vis, s_v, &vbtot);
     if (threadIdx.x == 0 && (int64_t)(blockIdx.x + 1) * kScanTile >= items) {  // the last block
         const uint64_t t = start + btot;
         *num_pairs = (int64_t)t;
         *sort_count = t <= (uint64_t)capacity ? (uint32_t)t : 0u;
+        *n_comp = vstart + vbtot;
     }
     uint64_t run = start + ex;
+    uint32_t slot = vstart + vex;
 #pragma unroll
     for (int r = 0; r < kScanIPT; ++r) {
-        const int64_t k = base + r;
-        if (k < items) offs[k] = run;
+        if (c[r] > 0) {
+            comp_item[slot] = it[r];
+            comp_offs[slot] = run;
+            ++slot;
+        }
         run += c[r];
     }
 }
 
 // Emission, load-balanced whatever the rectangle sizes: a block owns 1024 consecutive output positions, four
-// consecutive ones per thread.  The (view, Gaussian) items that cover them are consecutive in depth order
-// (every item with a non-empty rectangle owns at least one position; empty ones were sorted last), so the
-// block loads their offsets into LDS; a thread finds the item of its first position by binary search there
-// and walks forward for the next three, and writes its four keys and values with one 16-byte store each.
+// consecutive ones per thread.  The compacted items that cover them are consecutive (each owns at least one
+// position), so at most 1024 of them do, and the block loads their offsets into LDS; a thread finds the item
+// of its first position by binary search there and walks forward for the next three, and writes its four keys
+// and values with one 16-byte store each.
 constexpr int kEmitPer = 1024;
 constexpr int kEmitPerThread = kEmitPer / 256;
 
-__global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTable vt,
-                                              const uint32_t* __restrict__ sorted,
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ n_comp, int64_t n, ViewTable vt,
+                                              const uint32_t* __restrict__ comp_item,
                                               const uint64_t* __restrict__ offs,
                                               const uint32_t* __restrict__ sort_count,
                                               uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
     __shared__ uint64_t s_off[kEmitPer + 1];
     __shared__ int64_t s_k0;
     const uint64_t P = *sort_count;
+    const int64_t items = *n_comp;  // >= 1 whenever P > 0
     for (uint64_t chunk = blockIdx.x; chunk * kEmitPer < P; chunk += gridDim.x) {
         const uint64_t base = chunk * kEmitPer;
         __syncthreads();  // the previous chunk is done with s_off
@@ -456,7 +498,7 @@ __global__ __launch_bounds__(256) void k_emit(int64_t items, int64_t n, ViewTabl
             while (s_off[lo + 1] <= p) ++lo;  // the owner of p (lo + 1 <= kEmitPer: the sentinel stops the walk)
             if (lo != cur) {
                 cur = lo;
-                const uint32_t item = sorted[k0 + lo];
+                const uint32_t item = comp_item[k0 + lo];
                 int v = 0;
                 while (v + 1 < vt.V && (int64_t)item >= (int64_t)(v + 1) * n) ++v;
                 gi = (uint32_t)((int64_t)item - (int64_t)v * n);
@@ -530,6 +572,197 @@ __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __r
     }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Per-tile depth order.  When every tile's list is short, the pairs are emitted in (view, Gaussian) order
+// instead of depth order, the stable tile sort then leaves each tile's list in Gaussian order, and one
+// wavefront per tile sorts that list by (depth key, position in the list), the depth key being the one the
+// depth passes use (the bits of the depth; a tile's Gaussians all belong to its view).  The positions make
+// every key distinct and keep equal depths in Gaussian order, so the result equals the depth-first order.
+// Lists of up to kSegCap entries are sorted in registers by a bitonic network over the next power of two
+// (64 E keys, E consecutive keys per lane: exchanges between keys less than E apart stay in the lane, the
+// others pair lane l with lane l ^ (distance / E)), the Gaussians kept in LDS by position.  Longer lists
+// take stable 8-bit LSD radix passes through global memory (the tile sort's spare value array): the wave
+// counts digits by ballot matching, scans the 256 counts, then places each item at its digit's cursor plus
+// its rank among the equal digits of its round, rounds in order; a digit every key shares is skipped.
+// ------------------------------------------------------------------------------------------------
+constexpr int kSegCap = 1024;
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, m), hi = __shfl_xor((uint32_t)(x >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of the wave's 64 E keys; lane l holds keys l E .. l E + E - 1 in x.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
+    constexpr int N = kWave * E;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= E) {
+                // partner key in lane ^ (j / E), same register; the lower lane of the pair keeps the minimum
+                // in an ascending run (bit k of the key index clear), the maximum in a descending one
+                const int m = j / E;
+                const bool asc = ((lane * E) & k) == 0;
+                const bool keep_min = ((lane & m) == 0) == asc;
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const uint64_t o = shfl_xor64(x[r], m);
+                    x[r] = keep_min ? (x[r] < o ? x[r] : o) : (x[r] < o ? o : x[r]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    if (r & j) continue;
+                    const bool asc = k < E ? (r & k) == 0 : ((lane * E) & k) == 0;
+                    const uint64_t a = x[r], b = x[r ^ j];
+                    const bool sw = asc ? (b < a) : (a < b);
+                    x[r] = sw ? b : a;
+                    x[r ^ j] = sw ? a : b;
+                }
+            }
+        }
+    }
+}
+
+// Sorts the tile list src[0 .. L) (L <= 64 E) in registers; s_val holds the list's Gaussians by position.
+template <int E>
+__device__ __forceinline__ void seg_sort_regs(uint32_t* __restrict__ src, uint32_t L, const float* __restrict__ depth,
+                                              uint32_t* s_val) {
+    const int lane = __lane_id();
+    uint64_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t e = (uint32_t)(lane * E + r);
+        x[r] = ~0ull;  // padding: after every key of the list
+        if (e < L) {
+            const uint32_t g = src[e];
+            s_val[e] = g;
+            x[r] = ((uint64_t)__float_as_uint(depth[g]) << 32) | e;
+        }
+    }
+    wave_bitonic<E>(x);
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t e = (uint32_t)(lane * E + r);
+        if (e < L) src[e] = s_val[(uint32_t)x[r]];
+    }
+}
+
+// One stable pass on digit (key >> shift) & 255 over L items: key(i) and val(i) read item i of the source,
+// put(pos, val) writes the destination.  hist: 256 words of LDS.
+template <class Key, class Val, class Put>
+__device__ __forceinline__ void seg_pass(uint32_t L, int shift, uint32_t* hist, const Key& key, const Val& val,
+                                         const Put& put) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hist[4 * lane + j] = 0u;
+    wave_lds_sync();
+    for (uint32_t r0 = 0; r0 < L; r0 += kWave) {
+        const uint32_t i = r0 + lane;
+        const bool valid = i < L;
+        const uint32_t d = valid ? (key(i) >> shift) & (kRadix - 1) : 0u;
+        const uint64_t m = match8(d, valid);
+        if (valid && __popcll(m & lanemask_lt()) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(m));
+    }
+    wave_lds_sync();
+    // exclusive scan of the 256 counts: four consecutive digits per lane
+    uint32_t h[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        h[j] = hist[4 * lane + j];
+        sum += h[j];
+    }
+    uint32_t run = wave_incl_scan(sum) - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        hist[4 * lane + j] = run;
+        run += h[j];
+    }
+    wave_lds_sync();
+    for (uint32_t r0 = 0; r0 < L; r0 += kWave) {
+        const uint32_t i = r0 + lane;
+        const bool valid = i < L;
+        const uint32_t d = valid ? (key(i) >> shift) & (kRadix - 1) : 0u;
+        const uint64_t m = match8(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
+        uint32_t base = 0;
+        if (valid && rank == 0) base = atomicAdd(&hist[d], (uint32_t)__popcll(m));
+        base = __shfl(base, valid ? (int)(__ffsll((unsigned long long)m) - 1) : 0);
+        if (valid) put(base + rank, val(i));
+    }
+    wave_lds_sync();
+}
+
+__global__ __launch_bounds__(kWave) void k_seg_sort(ViewTable vt, const uint32_t* __restrict__ ranges,
+                                                    uint32_t* __restrict__ vals, uint32_t* __restrict__ spare,
+                                                    int64_t T) {
+    __shared__ uint32_t s_val[kSegCap];
+    __shared__ uint32_t s_h[kRadix];
+    const int64_t t = blockIdx.x;
+    if (t >= T) return;
+    const uint32_t start = ranges[2 * t], L = ranges[2 * t + 1] - start;
+    if (L <= 1) return;
+    int v = 0;
+    for (int k = 1; k < vt.V; ++k)
+        if ((uint32_t)t >= vt.cam[k].tile_off) v = k;
+    const float* __restrict__ depth = vt.proj[v].depth;
+    uint32_t* const src = vals + start;
+    if (L <= 64) {
+        seg_sort_regs<1>(src, L, depth, s_val);
+    } else if (L <= 128) {
+        seg_sort_regs<2>(src, L, depth, s_val);
+    } else if (L <= 256) {
+        seg_sort_regs<4>(src, L, depth, s_val);
+    } else if (L <= 512) {
+        seg_sort_regs<8>(src, L, depth, s_val);
+    } else if (L <= (uint32_t)kSegCap) {
+        seg_sort_regs<16>(src, L, depth, s_val);
+    } else {
+        const int lane = __lane_id();
+        uint32_t kor = 0u, kand = ~0u;  // the digits every key shares
+        for (uint32_t i = lane; i < L; i += kWave) {
+            const uint32_t k = __float_as_uint(depth[src[i]]);
+            kor |= k;
+            kand &= k;
+        }
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            kor |= __shfl_xor(kor, o);
+            kand &= __shfl_xor(kand, o);
+        }
+        const uint32_t diff = kor ^ kand;
+        uint32_t* a = src;
+        uint32_t* b = spare + start;
+        for (int p = 0; p < 4; ++p) {
+            const int shift = kRadixBits * p;
+            if (((diff >> shift) & (kRadix - 1)) == 0) continue;
+            const uint32_t* as = a;
+            uint32_t* bd = b;
+            seg_pass(L, shift, s_h, [&](uint32_t i) { return __float_as_uint(depth[as[i]]); },
+                     [&](uint32_t i) { return as[i]; }, [&](uint32_t pos, uint32_t g) { bd[pos] = g; });
+            // this pass's global writes complete, and no stale line of them in the vector cache, before the next
+            // pass reads them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            uint32_t* tmp = a;
+            a = b;
+            b = tmp;
+        }
+        if (a != src)
+            for (uint32_t i = lane; i < L; i += kWave) src[i] = a[i];
+    }
+}
+
 __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ tvals,
                          const uint32_t* __restrict__ sort_count, ViewTable vt, uint64_t* __restrict__ keys) {
     const uint32_t P = *sort_count;
@@ -544,13 +777,15 @@ __global__ void k_keys64(const uint32_t* __restrict__ tkeys, const uint32_t* __r
 }
 
 struct BinWs {
-    uint32_t *dkA, *dkB, *dvA, *dvB;  // depth sort, V*n
-    uint64_t* offs;                   // V*n
+    uint32_t *dkA, *dkB, *dvA, *dvB;  // depth sort, V*n (dkB then holds the compacted items)
+    uint64_t* offs;                   // V*n: first pair position of each compacted item
     uint32_t* sort_count;
+    uint32_t* n_comp;                 // number of compacted items
     uint32_t *tkA, *tkB, *tvB;        // tile sort, capacity
     uint32_t* rs_cnt;                 // radix passes: per-block digit counts [256][nb_cnt], scanned in place
     uint32_t* rs_tot;                 // radix passes: digit totals [256]
-    uint64_t* bsum;                   // count scan: per-block sums, [blocks]
+    uint64_t* bsum;                   // count scan: per-block pair sums, [blocks]
+    uint32_t* vsum;                   // count scan: per-block counts of items with pairs, [blocks]
     int64_t nb_cnt, nb_scan;
     size_t bytes;
 };
@@ -574,12 +809,14 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     w.dvB = (uint32_t*)take(4 * it1);
     w.offs = (uint64_t*)take(8 * it1);
     w.sort_count = (uint32_t*)take(4);
+    w.n_comp = (uint32_t*)take(4);
     w.tkA = (uint32_t*)take(4 * cap1);
     w.tkB = (uint32_t*)take(4 * cap1);
     w.tvB = (uint32_t*)take(4 * cap1);
     w.rs_cnt = (uint32_t*)take(4 * kRadix * w.nb_cnt);
     w.rs_tot = (uint32_t*)take(4 * kRadix);
     w.bsum = (uint64_t*)take(8 * w.nb_scan);
+    w.vsum = (uint32_t*)take(4 * w.nb_scan);
     w.bytes = off;
     return w;
 }
@@ -617,6 +854,10 @@ qg_status bin_check(int64_t n, const qg_projected* proj, const qg_camera* cams, 
     return QG_OK;
 }
 
+// Per-tile depth order (k_seg_sort) when the average tile list the capacity allows is at most this long;
+// above, the depth passes over the (view, Gaussian) items.  Both give the same lists.
+constexpr int64_t kSegAvgMax = 512;
+
 qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, uint32_t* vals, uint64_t* keys,
                   uint32_t* tile_ranges, int64_t* num_pairs, void* ws, hipStream_t s) {
     BinWs w = bin_ws_layout((char*)ws, n, V, capacity);
@@ -625,53 +866,60 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     int tbits = 1;
     while ((1ll << tbits) < T) ++tbits;
     const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
-    // 0. clear the ranges, num_pairs and the sort count
-    {
+    if (items == 0) {  // clear the ranges, num_pairs and the sort count; nothing else to do
         ZeroList z{};
         z.p[0] = tile_ranges;
         z.words[0] = 2 * T;
-        z.p[1] = (uint32_t*)num_pairs;  // stays 0 for an empty input
+        z.p[1] = (uint32_t*)num_pairs;
         z.words[1] = 2;
         z.p[2] = w.sort_count;
         z.words[2] = 1;
         z.n = 3;
-        int64_t most = 0;
-        for (int k = 0; k < z.n; ++k) most = std::max(most, z.words[k]);
-        QG_TIMED("bin_init", s);
-        k_bin_init<<<(unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(most, 256), 1), 4096), 256, 0, s>>>(z);
-    }
-    QG_LAUNCH_CHECK("qg_bin init");
-    if (items == 0) return QG_OK;
-    // 1. the 4-pass depth sort over (view, Gaussian) items; the first pass makes the keys
-    RsSrc src{};
-    src.n = n;
-    for (int v = 0; v < V; ++v) {
-        src.depth[v] = vt.proj[v].depth;
-        src.ntiles[v] = vt.proj[v].ntiles;
-    }
-    uint32_t *ka = w.dkA, *va = w.dvA, *kb = w.dkB, *vb = w.dvB;
-    for (int pass = 0; pass < 4; ++pass) {
-        qg_status st;
-        if (pass == 0) {
-            st = rs_pass<true>(src, ka, va, nullptr, (uint32_t)items, items, pass, w.rs_cnt, w.nb_cnt, w.rs_tot, s,
-                               "sort_depth");
-        } else {
-            src.keys = ka;
-            src.vals = va;
-            st = rs_pass<false>(src, kb, vb, nullptr, (uint32_t)items, items, pass, w.rs_cnt, w.nb_cnt, w.rs_tot, s,
-                                "sort_depth");
-            std::swap(ka, kb);
-            std::swap(va, vb);
+        {
+            QG_TIMED("bin_init", s);
+            k_bin_init<<<(unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(2 * T, 256), 1), 4096), 256, 0, s>>>(z);
         }
-        if (st != QG_OK) return st;
+        QG_LAUNCH_CHECK("qg_bin init");
+        return QG_OK;
     }
-    const uint32_t* sorted_items = va;
-    // 2. tile counts in depth order: scan, total, overflow check
+    // 1. depth order: the 4-pass depth sort over (view, Gaussian) items (the first pass makes the keys), or,
+    //    with short tile lists, none here (k_seg_sort orders each tile's list at the end)
+    const bool per_tile = capacity <= kSegAvgMax * T;
+    const uint32_t* sorted_items = nullptr;
+    if (!per_tile) {
+        RsSrc src{};
+        src.n = n;
+        for (int v = 0; v < V; ++v) {
+            src.depth[v] = vt.proj[v].depth;
+            src.ntiles[v] = vt.proj[v].ntiles;
+        }
+        uint32_t *ka = w.dkA, *va = w.dvA, *kb = w.dkB, *vb = w.dvB;
+        for (int pass = 0; pass < 4; ++pass) {
+            qg_status st;
+            if (pass == 0) {
+                st = rs_pass<true>(src, ka, va, nullptr, (uint32_t)items, items, pass, w.rs_cnt, w.nb_cnt, w.rs_tot,
+                                   s, "sort_depth");
+            } else {
+                src.keys = ka;
+                src.vals = va;
+                st = rs_pass<false>(src, kb, vb, nullptr, (uint32_t)items, items, pass, w.rs_cnt, w.nb_cnt,
+                                    w.rs_tot, s, "sort_depth");
+                std::swap(ka, kb);
+                std::swap(va, vb);
+            }
+            if (st != QG_OK) return st;
+        }
+        sorted_items = va;  // w.dvB after 4 passes; the keys, in w.dkB, are dead: w.dkB takes the compacted items
+    }
+    // 2. tile counts in order: scan, compaction of the items with pairs, total, overflow check; the ranges are
+    //    cleared on the way
+    uint32_t* comp_item = w.dkB;
     {
         QG_TIMED("bin_count_scan", s);
-        k_count_reduce<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum);
-        k_count_apply<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum, w.offs, capacity,
-                                                             w.sort_count, num_pairs);
+        k_count_reduce<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum, w.vsum,
+                                                              tile_ranges, 2 * T);
+        k_count_apply<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum, w.vsum, comp_item,
+                                                             w.offs, capacity, w.sort_count, w.n_comp, num_pairs);
     }
     QG_LAUNCH_CHECK("qg_bin count");
     if (capacity == 0) return QG_OK;
@@ -679,7 +927,7 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
     {
         QG_TIMED("bin_emit", s);
-        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(items, n, vt, sorted_items, w.offs,
+        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(w.n_comp, n, vt, comp_item, w.offs,
                                                                       w.sort_count, w.tkA, vbuf0);
     }
     QG_LAUNCH_CHECK("qg_bin emit");
@@ -695,14 +943,21 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
         std::swap(tk_in, tk_out);
         std::swap(tv_in, tv_out);
     }
-    // tk_in / tv_in hold the sorted pairs; tv_in == vals by construction
-    // 4. tile ranges (and optional 64-bit keys)
+    // tk_in / tv_in hold the sorted pairs; tv_in == vals by construction, w.tvB is spare
+    // 4. tile ranges, then (per-tile order) each tile's list by depth
     {
         QG_TIMED("bin_ranges", s);
         k_ranges<<<(unsigned)std::max<int64_t>(1, ceil_div(capacity, 256 * kRangesPerThread)), 256, 0, s>>>(
             tk_in, w.sort_count, tile_ranges);
     }
     QG_LAUNCH_CHECK("qg_bin ranges");
+    if (per_tile) {
+        {
+            QG_TIMED("bin_seg_sort", s);
+            k_seg_sort<<<(unsigned)T, kWave, 0, s>>>(vt, tile_ranges, vals, w.tvB, T);
+        }
+        QG_LAUNCH_CHECK("qg_bin tile depth order");
+    }
     if (keys) {
         k_keys64<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, tv_in, w.sort_count, vt, keys);
         QG_LAUNCH_CHECK("qg_bin keys");

@@ -201,11 +201,13 @@ class ResidualState:
                                self.lp, self.a, c.gamma0, c.gamma1, c.tau, self.attrs, self.gate, self.lreg_part,
                                stream, gate_noise=gate_noise)
 
-    def adam(self, stream=None, step_state=None):
-        """One Adam step over every parameter segment (clearing the gradients it read)."""
+    def adam(self, stream=None, step_state=None, t=None):
+        """One Adam step over every parameter segment (clearing the gradients it read); t: the host step count
+        of the update (default self.t), unused with step_state."""
         b1, b2 = self.cfg.betas
+        t = self.t if t is None else t
         for segs in self.adam_segs_list:
-            qg.qg_adam_multi(segs, b1, b2, self.cfg.eps, self.t, True, stream, step_state=step_state)
+            qg.qg_adam_multi(segs, b1, b2, self.cfg.eps, t, True, stream, step_state=step_state)
 
     def _eval_psnr(self, rast, cam, gt, loss_part, loss_out, stream=None):
         """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync)."""
@@ -224,15 +226,23 @@ class ResidualState:
 
 
 class FrameFitter(ResidualState):
-    """Single-view steps (the plain form): each optimiser iteration renders one training view."""
+    """Single-view steps (the plain form): each optimiser iteration renders one training view.
+
+    graph=True (MLP decoder, no densification): the unmasked L1 step of view v runs eagerly the first time and
+    is then captured into a graph of its own, which later steps on v replay on the current stream (one graph
+    per view: the camera is a launch argument).  Every step then takes the Adam step count and the stochastic
+    gate's step from the device counter, and the ground truth is copied into buffers the fitter owns, so that
+    a replay reads the current frame's.  Masked and D-SSIM steps still run eagerly."""
 
     def __init__(self, prev_attrs: torch.Tensor, cams, gts, cfg: FitConfig = FitConfig(), W1=None, W2=None,
-                 capacity=None, seed=0):
+                 capacity=None, seed=0, graph=False):
         super().__init__(prev_attrs, cfg, W1, W2, seed)
         self.cams = list(cams)
         # one set of image buffers serves every view
         assert all((c.width, c.height) == (self.cams[0].width, self.cams[0].height) for c in self.cams)
-        self.gts = gts
+        self.use_graph = bool(graph) and not cfg.densify and not self.linear
+        self.graphs = {}
+        self.gts = [g.clone() for g in gts] if self.use_graph else gts
         dev = self.device
         n, L, H = self.n, cfg.latent_dim, cfg.hidden
         self.grad_attrs = torch.zeros_like(self.prev)
@@ -264,9 +274,18 @@ class FrameFitter(ResidualState):
             self.dssim_out = torch.zeros(1, dtype=torch.float64, device=dev)
 
     def _alloc_fws(self):
-        """The fused adjoint's workspace (plus the deterministic-mode partials, sized by the pair capacity)."""
+        """The fused adjoint's workspace (plus the deterministic-mode partials, sized by the pair capacity);
+        captured graphs hold the addresses of the buffers that were re-allocated, so they are dropped."""
         self.fws_bytes = qg.qg_render_decode_bwd_workspace_size(self.n, 1) + self.rast.det_ws_bytes()
         self.fws = torch.empty(self.fws_bytes, dtype=torch.uint8, device=self.device)
+        self.graphs = {}
+
+    def reset_frame(self, prev_attrs=None, gts=None, a_init=None, lat_init=None, lp_init=None):
+        if gts is not None and self.use_graph:
+            for dst, src in zip(self.gts, gts):
+                dst.copy_(src)
+            gts = None
+        super().reset_frame(prev_attrs, gts, a_init, lat_init, lp_init)
 
     # -- the step ------------------------------------------------------------------------------
     def forward_view(self, v, stream=None):
@@ -280,13 +299,39 @@ class FrameFitter(ResidualState):
         """Per-view (dilated pixel mask [H][W] u8, tile flags u8) from GateInitializer.masks, for masked steps."""
         self.masks = masks
 
-    def step(self, v, stream=None, masked=False):
+    def step(self, v, stream=None, masked=False, eager=False):
         """One optimiser iteration on training view v (enqueue only).  masked: render and backpropagate only the
-        tiles flagged in view v's mask, with the L1 over its masked pixels (Sec. 3.3)."""
+        tiles flagged in view v's mask, with the L1 over its masked pixels (Sec. 3.3).  With graph=True an
+        unmasked L1 step replays view v's graph (captured after its first, eager, step) unless eager is set."""
+        c = self.cfg
+        if self.use_graph and not masked and c.lambda_dssim == 0.0:
+            g = None if eager else self.graphs.get(v)
+            if g is not None:
+                g.replay()
+            else:
+                self._enqueue(v, stream, False)
+                if not eager:
+                    self.capture(v)
+            self.t += 1
+            return
+        self._enqueue(v, stream, masked)
+        self.t += 1
+
+    def capture(self, v):
+        """Capture view v's step into its graph (recorded, not run).  The library's kernels must have been
+        launched once before (any eager step does that)."""
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._enqueue(v, None, False)
+        self.graphs[v] = g
+
+    def _enqueue(self, v, stream, masked):
         c = self.cfg
         r = self.rast
+        dev_step = self.step_state if self.use_graph else None  # the step count on the device (graph mode)
         if self.noise is not None:
-            qg.qg_gate_noise(self.n, c.gate_seed, self.t, self.noise, stream=stream)
+            qg.qg_gate_noise(self.n, c.gate_seed, self.t, self.noise, step_state=dev_step, stream=stream)
         if self.fused:
             r.qcams = self.qcams[v]
             qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
@@ -344,8 +389,7 @@ class FrameFitter(ResidualState):
             cam = self.cams[v]
             qg.qg_densify_accumulate(self.n, self.d_gxy, r.proj[0]["ntiles"], cam.width / 2.0, cam.height / 2.0,
                                      self.d_accum, self.d_count, stream)
-        self.t += 1
-        self.adam(stream)
+        self.adam(stream, step_state=dev_step, t=self.t + 1)  # step() counts this update after enqueueing it
 
     def loss_value(self, stream=None):
         """L1 of the last step (host sync)."""
@@ -365,8 +409,7 @@ class FrameFitter(ResidualState):
             self.rast.project(self.attrs)
             self.rast.bin()
             worst = max(worst, self.rast.pair_count())
-        if worst * 1.05 > self.rast.capacity:
-            self.rast._alloc_capacity(int(worst * margin))
+        self.rast.fit_capacity(worst, margin)
         return worst
 
 
@@ -584,8 +627,7 @@ class BatchedFitter(ResidualState):
             r.bin()
             p = r.pair_count()
             worst.append(p)
-            if p * 1.05 > r.capacity:
-                r._alloc_capacity(int(p * margin))
+            r.fit_capacity(p, margin)
         self.invalidate()
         return worst
 
@@ -648,8 +690,7 @@ class AttributeFitter:
         r.project(self.attrs)
         r.bin()
         p = r.pair_count()
-        if p * 1.05 > r.capacity:
-            r._alloc_capacity(int(p * margin))
+        r.fit_capacity(p, margin)
         self.graph = None
         return p
 

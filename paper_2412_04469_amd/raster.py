@@ -122,6 +122,15 @@ class Rasterizer:
         """True if the last qg_bin found more pairs than the capacity (host sync; raises as pair_count)."""
         return self.pair_count() > self.capacity
 
+    def fit_capacity(self, pairs: int, margin=1.3) -> bool:
+        """Size the pair capacity for a measured pair count: pairs * margin (at least 1024) when the current one
+        leaves less than 5% headroom or is more than twice that.  Returns True if the buffers were re-allocated."""
+        want = max(1024, int(pairs * margin))
+        if pairs * 1.05 > self.capacity or self.capacity > 2 * want:
+            self._alloc_capacity(want)
+            return True
+        return False
+
     def ensure_capacity(self, margin=1.25) -> bool:
         """Host-synchronising check of the last bin; grows the buffers and returns True if it overflowed."""
         p = self.pair_count()

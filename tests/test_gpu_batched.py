@@ -238,3 +238,44 @@ def test_batched_fit_reduces_loss(qgm):
     assert not f.overflowed()
     last = np.mean(f.losses())
     assert last < first, (first, last)
+
+
+def test_frame_fitter_graph_replay_matches_eager_step(qgm):
+    """The per-view graphs of FrameFitter(graph=True): a replayed step of view v equals the same step run
+    eagerly from the same state (image bit for bit, parameter updates up to float atomic order), for each view
+    and again after other views' replays; the device step counter advances once per step."""
+    qg, raster = qgm
+    from paper_2412_04469_amd.fit import FitConfig, FrameFitter, render_views
+    n = 3000
+    base = small_scene(seed=36, n=n)
+    rng = synth.rng_for(37)
+    moved = base.copy()
+    moved.means[: n // 10] += rng.normal(0, 0.05, size=(n // 10, 3)).astype(np.float32)
+    cams = [synth.make_camera((0.0, 0.0, -4.0), 160, 120, f=160),
+            synth.make_camera((1.5, -0.3, -3.6), 160, 120, f=150),
+            synth.make_camera((-1.8, 0.4, -3.2), 160, 120, f=140)]
+    gts = render_views(to_dev(moved.planes()), cams, FitConfig())
+    f = FrameFitter(to_dev(base.planes()), cams, gts, FitConfig(), graph=True)
+    f.size_capacity()
+    for v in range(len(cams)):  # first step of each view: eager, then captured
+        f.step(v)
+    torch.cuda.synchronize()
+    assert sorted(f.graphs) == [0, 1, 2]
+    keys = ["lat", "lp", "a", "W1", "W2"]
+    for rnd, v in enumerate([0, 1, 2, 1]):
+        s0 = _state(f)
+        f.step(v, eager=True)
+        torch.cuda.synchronize()
+        eager_img = f.rast.images[0].clone()
+        eager = _state(f)
+        _restore(f, s0)
+        f.step(v)  # graph replay
+        torch.cuda.synchronize()
+        assert not f.rast.overflowed()
+        assert torch.equal(f.rast.images[0], eager_img), rnd
+        rep = _state(f)
+        assert torch.equal(rep[3], eager[3])
+        for k, p0, pe, pr in zip(keys, s0[0], eager[0], rep[0]):
+            de, dr = (pe - p0).cpu().numpy(), (pr - p0).cpu().numpy()
+            assert rel_l2(dr, de) <= 1e-3, (rnd, k, rel_l2(dr, de))
+    assert int(f.step_state[0].item()) == len(cams) + 4

@@ -143,6 +143,41 @@ def test_bin_bit_exact(qgm, tile, sizes, n):
         assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
 
 
+def test_bin_long_tile_lists(qgm):
+    """Short average lists (the per-tile depth order) with a few tiles far longer than the lists kept in LDS:
+    3,000 rectangles share the four centre tiles of a 512x512 view, whose lists then go through global memory.
+    The lists equal the oracle's, and those of the depth-pass path (a capacity far above the average)."""
+    qg, raster = qgm
+    rng = synth.rng_for(29)
+    n, tile = 20000, (16, 16)
+    cams = [synth.make_camera((0, 0, -4), 512, 512)]
+    gw = gh = 32
+    rect = _random_rects(rng, n, gw, gh, max_w=4)
+    hot = rng.permutation(n)[:3000]
+    rect[hot] = np.array([15, 15, 17, 17], np.int32)
+    depth = rng.uniform(0.3, 30.0, n).astype(np.float32)
+    depth[rng.integers(0, n, n // 10)] = depth[0]
+    rast = raster.Rasterizer(n, cams, tile=tile, want_keys=True, capacity=64)
+    _fill_proj_for_bin(qg, rast.proj[0], rect, depth)
+    k, vv = OB.make_pairs_fast(rect, depth, gw, 0)
+    ks, vs = OB.sort_pairs(k, vv)
+    ranges = OB.tile_ranges(ks, gw * gh)
+    assert np.diff(ranges, axis=1).max() > 2048
+    rast.bin()
+    assert rast.ensure_capacity()
+    assert rast.capacity <= 512 * rast.total_tiles  # the per-tile path
+    for cap in (None, 600 * rast.total_tiles):  # then the depth passes
+        if cap:
+            rast._alloc_capacity(cap)
+        rast.bin()
+        torch.cuda.synchronize()
+        P = int(rast.num_pairs.item())
+        assert P == len(ks)
+        assert np.array_equal(rast.vals[:P].cpu().numpy().astype(np.uint32), vs), cap
+        assert np.array_equal(rast.keys[:P].cpu().numpy().view(np.uint64), ks)
+        assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
+
+
 def test_bin_empty(qgm):
     qg, raster = qgm
     cams = [synth.make_camera((0, 0, -4), 64, 48)]
