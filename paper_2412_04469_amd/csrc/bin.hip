@@ -609,22 +609,25 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             if (j >= E) {
                 // partner key in lane ^ (j / E), same register; the lower lane of the pair keeps the minimum
-                // in an ascending run (bit k of the key index clear), the maximum in a descending one
+                // in an ascending run (bit k of the key index clear), the maximum in a descending one: a lane
+                // takes its partner's key when (key < partner's) differs from "keep the minimum" (keys are
+                // distinct except the equal padding keys, where either choice is the same)
                 const int m = j / E;
-                const bool asc = ((lane * E) & k) == 0;
-                const bool keep_min = ((lane & m) == 0) == asc;
+                const bool keep_max = ((lane & m) == 0) != (((lane * E) & k) == 0);
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
                     const uint64_t o = shfl_xor64(x[r], m);
-                    x[r] = keep_min ? (x[r] < o ? x[r] : o) : (x[r] < o ? o : x[r]);
+                    const bool take = (x[r] < o) == keep_max;
+                    x[r] = take ? o : x[r];
                 }
             } else {
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
                     if (r & j) continue;
-                    const bool asc = k < E ? (r & k) == 0 : ((lane * E) & k) == 0;
+                    // swap when the pair is out of order for its run's direction
+                    const bool desc = k < E ? (r & k) != 0 : ((lane * E) & k) != 0;
                     const uint64_t a = x[r], b = x[r ^ j];
-                    const bool sw = asc ? (b < a) : (a < b);
+                    const bool sw = (b < a) != desc;
                     x[r] = sw ? b : a;
                     x[r ^ j] = sw ? a : b;
                 }
