@@ -239,10 +239,13 @@ qg_status qg_project(int64_t n, int64_t ld, const float* attrs, int32_t sh_degre
  * Every (view, Gaussian) pair whose rectangle covers a tile yields one entry.  Entries are ordered by
  * the 64-bit key (global tile id << 32) | float32 bits of depth, ties by Gaussian index -- the
  * per-tile depth order of Eq. 2.  Global tile id of view v = sum of the earlier views' tile counts +
- * ty * grid_w(v) + tx.  The sort is a stable LSD radix sort: the 32 depth bits are sorted once per
- * (view, Gaussian) before pairs are emitted, then the tile bits over the pairs; each 8-bit pass counts,
- * scans and scatters in three kernels, and the per-(view, Gaussian) tile counts are scanned by a reduce
- * and an apply kernel: no workgroup ever waits for another.
+ * ty * grid_w(v) + tx.  The per-(view, Gaussian) tile counts are scanned by a reduce and an apply kernel, the
+ * pairs are emitted, and they are sorted by their tile bits with stable 8-bit LSD radix passes (count, scan
+ * and scatter kernels).  The depth order comes from one of two routes with the same result: when capacity
+ * <= 512 * total_tiles (short tile lists) the pairs are emitted in (view, Gaussian) order and one wavefront
+ * per tile then sorts its list by (depth bits, position in the list); otherwise the 32 depth bits are sorted
+ * once per (view, Gaussian) by four radix passes before the pairs are emitted in that order.  No workgroup
+ * ever waits for another.
  *   vals        [capacity] uint32 sorted Gaussian indices (within their view).
  *   keys        [capacity] uint64 sorted keys (optional, NULL to skip).
  *   tile_ranges [total_tiles][2] uint32 half-open spans into vals ([0,0) for an empty tile).

@@ -1,20 +1,23 @@
-// Tile binning by (tile, depth) keys with a device LSD radix sort.
+// Tile binning by (tile, depth) keys with device LSD radix sorts.
 //
 // The blend of Eq. 2 visits, per pixel, the Gaussians in depth order; tiling restricts each pixel to the
 // Gaussians whose tile rectangle covers its tile.  The order wanted is that of the 64-bit key
-// (global tile << 32 | depth bits), ties by Gaussian index.  An LSD radix sort on that key first sorts
-// by the 32 depth bits, then by the tile bits.  All pairs of one (view, Gaussian) share the depth
-// digits, so the depth passes are run once per (view, Gaussian) before pairs are emitted (4 passes
-// over V*n items instead of 4 passes over P pairs), and only the tile bits are sorted over the pairs
-// (2 passes for up to 65,536 tiles).
+// (global tile << 32 | depth bits), ties by Gaussian index.  All pairs of one (view, Gaussian) share the
+// depth bits, so the pairs are only ever sorted by their tile bits (2 passes for up to 65,536 tiles), and the
+// depth order comes from one of two routes:
+//   * short tile lists (the capacity allows at most 512 pairs per tile on average): the pairs are emitted in
+//     (view, Gaussian) order, the stable tile sort keeps that order within each tile, and one wavefront per
+//     tile sorts its list by (depth bits, position) -- by depth, ties by Gaussian index;
+//   * otherwise the depth bits are sorted once per (view, Gaussian) by 4 radix passes over V*n items (instead
+//     of 4 passes over P pairs), and the pairs are emitted in that order.
 //
 // Every 8-bit pass is reduce-then-scan, three kernels with no waits between workgroups: each block counts
 // its items' digits, one workgroup per digit scans those counts over the blocks, and each block then
 // places its items (stable ranks by wave64 ballot matching on the digit bits, per-wave digit counters in
 // LDS), orders them by digit in LDS and writes them out in digit runs.  The first depth pass makes its keys
 // from the projection on the fly.  The per-(view, Gaussian) tile counts are scanned the same way, without
-// waits: each block sums its items' counts, then each block adds up the sums of the blocks before it and
-// scans its own items.
+// waits: each block sums its items' counts, then each block adds up the sums of the blocks before it, scans
+// its own items and writes the items that have pairs, compacted, for the emission kernel.
 #include <algorithm>
 #include <mutex>
 
