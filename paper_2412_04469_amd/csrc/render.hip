@@ -201,34 +201,42 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
             cnt += (int)__popcll(m);
         }
         __syncthreads();
-        for (int jj = 0; jj < cnt; ++jj) {
-            const float4 a = s_a[jj];
-            const float4 bb = s_b[jj];
-            const float cb = s_c[jj];
-            const uint32_t pos1 = s_pos[jj] + 1;
-            const float dx = fx - a.x;
+        // two entries per iteration: the wave checks whether any of its pixels still composites once per pair
+        // (a stopped pixel takes no entry, so the check only saves work)
+        for (int j0 = 0; j0 < cnt; j0 += 2) {
             bool any2 = false;
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                // skip if alpha < 1/255; stop before T' < 1e-4.  The branches are on the exec mask: lanes
-                // that skip the entry do no work, and a pixel slot where no lane takes it costs nothing more.
-                const float dy = fy[k] - a.y;
-                const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
-                const float al = fminf(kAlphaMax, raw);
-                if (T[k] > 0.f && al >= kAlphaMin) {
-                    const float w = al * T[k];
-                    const float tn = T[k] - w;  // T (1 - alpha)
-                    if (tn < kTMin) {
-                        T[k] = -T[k];  // stopped: this entry and all later ones are not taken
-                    } else {
-                        C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
-                        C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
-                        C2[k] = __builtin_fmaf(cb, w, C2[k]);
-                        T[k] = tn;
-                        last[k] = pos1;
+            for (int u = 0; u < 2; ++u) {
+                const int jj = j0 + u;
+                if (u > 0 && jj >= cnt) break;
+                const float4 a = s_a[jj];
+                const float4 bb = s_b[jj];
+                const float cb = s_c[jj];
+                const uint32_t pos1 = s_pos[jj] + 1;
+                const float dx = fx - a.x;
+                any2 = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    // skip if alpha < 1/255; stop before T' < 1e-4.  The branches are on the exec mask: lanes
+                    // that skip the entry do no work, and a pixel slot where no lane takes it costs nothing more.
+                    const float dy = fy[k] - a.y;
+                    const float raw = a.z * blend_e(a.w, bb.x, bb.y, dx, dy);
+                    const float al = fminf(kAlphaMax, raw);
+                    if (T[k] > 0.f && al >= kAlphaMin) {
+                        const float w = al * T[k];
+                        const float tn = T[k] - w;  // T (1 - alpha)
+                        if (tn < kTMin) {
+                            T[k] = -T[k];  // stopped: this entry and all later ones are not taken
+                        } else {
+                            C0[k] = __builtin_fmaf(bb.z, w, C0[k]);
+                            C1[k] = __builtin_fmaf(bb.w, w, C1[k]);
+                            C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                            T[k] = tn;
+                            last[k] = pos1;
+                        }
                     }
+                    any2 |= T[k] > 0.f;
                 }
-                any2 |= T[k] > 0.f;
             }
             if (__ballot(any2) == 0) break;
         }
