@@ -596,9 +596,46 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
-    const uint32_t lo = __shfl_xor((uint32_t)x, m), hi = __shfl_xor((uint32_t)(x >> 32), m);
+// The value of lane l ^ M (M = 1, 2, 4, 8, 16 or 32).  Inside a 16-lane row the exchange runs on the vector
+// unit by DPP (quad permutations for 1 and 2; row rotations by 8, and by 4 and 12 with a select, since lane
+// l - n is rotation n's source); across rows by a lane shuffle through the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v) {
+    if constexpr (M == 1) {
+        return dpp_u32<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    } else if constexpr (M == 2) {
+        return dpp_u32<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    } else if constexpr (M == 8) {
+        return dpp_u32<0x128>(v);  // row_ror:8
+    } else if constexpr (M == 4) {
+        const uint32_t a = dpp_u32<0x124>(v), b = dpp_u32<0x12C>(v);  // row_ror:4 (lane l - 4), row_ror:12 (l + 4)
+        return (__lane_id() & 4) ? a : b;
+    } else {
+        return (uint32_t)__shfl_xor((int)v, M);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t x) {
+    const uint32_t lo = xor_lane_u32<M>((uint32_t)x), hi = xor_lane_u32<M>((uint32_t)(x >> 32));
     return ((uint64_t)hi << 32) | lo;
+}
+
+// m is a constant once the bitonic network is unrolled, and the switch folds away.
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+    switch (m) {
+        case 1: return xor_lane_u64<1>(x);
+        case 2: return xor_lane_u64<2>(x);
+        case 4: return xor_lane_u64<4>(x);
+        case 8: return xor_lane_u64<8>(x);
+        case 16: return xor_lane_u64<16>(x);
+        default: return xor_lane_u64<32>(x);
+    }
 }
 
 // Ascending bitonic sort of the wave's 64 E keys; lane l holds keys l E .. l E + E - 1 in x.
