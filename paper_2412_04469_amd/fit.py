@@ -242,6 +242,7 @@ class FrameFitter(ResidualState):
         assert all((c.width, c.height) == (self.cams[0].width, self.cams[0].height) for c in self.cams)
         self.use_graph = bool(graph) and not cfg.densify and not self.linear
         self.graphs = {}
+        self.overflows = 0  # training steps found overflowed at a PSNR check (see psnr)
         self.gts = [g.clone() for g in gts] if self.use_graph else gts
         dev = self.device
         n, L, H = self.n, cfg.latent_dim, cfg.hidden
@@ -397,10 +398,14 @@ class FrameFitter(ResidualState):
         return float(self.loss_out[0].item())
 
     def psnr(self, cam, gt, stream=None):
-        """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync)."""
+        """PSNR of the decoded frame rendered at ``cam`` against ``gt`` (host sync).  First checks the last
+        training step's binning: if it overflowed, the pair capacity grows for the steps that follow and
+        ``overflows`` counts it (that step rendered no entries)."""
+        if self.rast.ensure_capacity():
+            self.overflows += 1
         return self._eval_psnr(self.rast, cam, gt, self.loss_part, self.loss_out, stream)
 
-    def size_capacity(self, margin=1.3):
+    def size_capacity(self, margin=1.5):
         """Bin every view once (host syncs) and size the pair capacity for all of them."""
         worst = 0
         self.decode()
@@ -618,7 +623,7 @@ class BatchedFitter(ResidualState):
         """True if the last binning of some group exceeded its pair capacity (host sync)."""
         return any([r.overflowed() for r in self.rasts])
 
-    def size_capacity(self, margin=1.3):
+    def size_capacity(self, margin=1.5):
         """Bin every group once (host syncs) and size each group's pair capacity; drops captured graphs."""
         self.decode()
         worst = []
@@ -684,7 +689,7 @@ class AttributeFitter:
         self.use_graph = bool(graph)
         self.graph = None
 
-    def size_capacity(self, margin=1.3):
+    def size_capacity(self, margin=1.5):
         """Bin once (host sync) and size the pair capacity; drops a captured graph."""
         r = self.rast
         r.project(self.attrs)

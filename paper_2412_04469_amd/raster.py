@@ -122,7 +122,7 @@ class Rasterizer:
         """True if the last qg_bin found more pairs than the capacity (host sync; raises as pair_count)."""
         return self.pair_count() > self.capacity
 
-    def fit_capacity(self, pairs: int, margin=1.3) -> bool:
+    def fit_capacity(self, pairs: int, margin=1.5) -> bool:
         """Size the pair capacity for a measured pair count: pairs * margin (at least 1024) when the current one
         leaves less than 5% headroom or is more than twice that.  Returns True if the buffers were re-allocated."""
         want = max(1024, int(pairs * margin))
