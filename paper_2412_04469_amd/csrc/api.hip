@@ -274,7 +274,7 @@ extern "C" qg_status qg_zero(void* dst, int64_t bytes, qg_stream stream) {
     uintptr_t a = (uintptr_t)dst;
     if (a % 16 == 0 && bytes % 16 == 0) {
         const int64_t n16 = bytes / 16;
-        const int64_t blocks = std::min<int64_t>(ceil_div(n16, 256), 2048);
+        const int64_t blocks = std::min<int64_t>(ceil_div(n16, 256), 16384);
         {
             QG_TIMED("zero", s);
             k_zero16<<<(unsigned)blocks, 256, 0, s>>>((uint4*)dst, n16);

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(1024) void k_reduce_parts(const float* __restrict__
     const int col = threadIdx.x % 16, rg = threadIdx.x / 16;
     const int o = blockIdx.x * 16 + col;
     float acc = 0.f;
-#pragma unroll 4
+#pragma unroll 16
     for (int64_t b = rg; b < nblocks; b += 64) acc += part[(size_t)b * kWidth + o];
     s[rg][col] = acc;
     __syncthreads();

@@ -793,18 +793,39 @@ __device__ __forceinline__ void sched_scan_keys(uint32_t* h, uint32_t* s_w, uint
     __syncthreads();
 }
 
-// The whole schedule in one workgroup of 1024 threads: key histogram, scan and scatter in LDS.
+// The whole schedule in one workgroup of 1024 threads: key histogram, scan and scatter in LDS.  Up to
+// kSchedKeep keys per thread (8192 tiles) are kept in registers between the histogram and the scatter;
+// beyond, the scatter computes them again.
+constexpr int kSchedKeep = 8;
+
 __global__ __launch_bounds__(1024) void k_sched_one(int64_t total, ViewTable vt, TileMap tm,
                                                     const uint32_t* __restrict__ ranges, uint32_t* __restrict__ sched) {
     __shared__ uint32_t s_h[kSchedKeys];
     __shared__ uint32_t s_w[1024 / 64];
     for (int k = threadIdx.x; k < kSchedKeys; k += blockDim.x) s_h[k] = 0;
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) atomicAdd(&s_h[sched_key(tm, vt, ranges, t)], 1u);
+    uint32_t key[kSchedKeep];
+#pragma unroll
+    for (int r = 0; r < kSchedKeep; ++r) {
+        const int64_t t = threadIdx.x + (int64_t)r * blockDim.x;
+        key[r] = t < total ? sched_key(tm, vt, ranges, t) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSchedKeep; ++r) {
+        const int64_t t = threadIdx.x + (int64_t)r * blockDim.x;
+        if (t < total) atomicAdd(&s_h[key[r]], 1u);
+    }
+    for (int64_t t = threadIdx.x + (int64_t)kSchedKeep * blockDim.x; t < total; t += blockDim.x)
+        atomicAdd(&s_h[sched_key(tm, vt, ranges, t)], 1u);
     __syncthreads();
     sched_scan_keys(s_h, s_w, sched, (uint32_t)total);
     uint32_t* order = sched + QG_SCHEDULE_HEADER_WORDS;
-    for (int64_t t = threadIdx.x; t < total; t += blockDim.x)
+#pragma unroll
+    for (int r = 0; r < kSchedKeep; ++r) {
+        const int64_t t = threadIdx.x + (int64_t)r * blockDim.x;
+        if (t < total) order[atomicAdd(&s_h[key[r]], 1u)] = (uint32_t)t;
+    }
+    for (int64_t t = threadIdx.x + (int64_t)kSchedKeep * blockDim.x; t < total; t += blockDim.x)
         order[atomicAdd(&s_h[sched_key(tm, vt, ranges, t)], 1u)] = (uint32_t)t;
 }
 

@@ -124,9 +124,10 @@ class Rasterizer:
 
     def fit_capacity(self, pairs: int, margin=1.5) -> bool:
         """Size the pair capacity for a measured pair count: pairs * margin (at least 1024) when the current one
-        leaves less than 5% headroom or is more than twice that.  Returns True if the buffers were re-allocated."""
+        leaves less than 5% headroom or is more than 1.25 times that.  Returns True if the buffers were
+        re-allocated."""
         want = max(1024, int(pairs * margin))
-        if pairs * 1.05 > self.capacity or self.capacity > 2 * want:
+        if pairs * 1.05 > self.capacity or self.capacity > 1.25 * want:
             self._alloc_capacity(want)
             return True
         return False
