@@ -38,8 +38,9 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Two waves per block, one chunk of 64 Gaussians per wave (straight-line code): 29 KB of LDS per block lets
-// three waves share a SIMD.
+// Two waves per block, one chunk of 64 Gaussians per wave (straight-line code).  The decoder's output reaches
+// the lanes one group of 16 Gaussians at a time through a 16-row LDS buffer (7 KB per block), so LDS no longer
+// bounds the occupancy; the registers allow three waves per SIMD.
 __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, const float* __restrict__ prev,
                                                         const float* __restrict__ lat, const float* __restrict__ W1,
                                                         const float* __restrict__ W2, const float* __restrict__ lp,
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, c
                                                         float dilation,
                                                         int tile_w, int tile_h, float* __restrict__ attrs_out,
                                                         float* __restrict__ gate_out, float* __restrict__ lreg_part) {
-    __shared__ float s_res[2][kChunk][kM + 1];
+    __shared__ float s_res[2][16][kM + 1];
     __shared__ float s_red[2];
     const int lane = __lane_id(), w = threadIdx.x / 64, c = lane % 16;
     const int64_t nchunks = ceil_div(n, kChunk);
@@ -73,22 +74,26 @@ __global__ __launch_bounds__(128) void k_decode_project(int64_t n, int64_t ld, c
         {
             FwdOps ops;
             load_fwd_ops(W1, W2, ops);
+            // one group of 16 Gaussians at a time through a 16-row buffer; the group's own lanes add its rows
 #pragma unroll
             for (int sg = 0; sg < 4; ++sg) {
                 const int64_t gs = base + 16 * sg + c;
                 const bool vs = gs < n;
                 auto latf = [&](int k) { return vs ? rintf(lat[pidx(k, ld32, (uint32_t)gs)]) : 0.f; };
-                auto outf = [&](int m, float v) { s_res[w][16 * sg + c][m] = v; };
+                auto outf = [&](int m, float v) { s_res[w][c][m] = v; };
                 decode_group_fwd(ops, latf, outf);
+                wave_sync_lds();
+                if (lane / 16 == sg) {
+#pragma unroll
+                    for (int k = 3; k < QG_N_PLANES; ++k) at[k] = at[k] + s_res[w][c][k - 3];
+                }
+                wave_sync_lds();
             }
         }
-        wave_sync_lds();
         if (gv) {
             const float gg = gate_of(an, g0, g1, tau, nullptr, nullptr);
 #pragma unroll
             for (int k = 0; k < 3; ++k) at[k] = __builtin_fmaf(gg, lpv[k], at[k]);
-#pragma unroll
-            for (int k = 3; k < QG_N_PLANES; ++k) at[k] = at[k] + s_res[w][lane][k - 3];
             if (attrs_out) {
 #pragma unroll
                 for (int k = 0; k < QG_N_PLANES; ++k) attrs_out[pidx(k, ld32, g32)] = at[k];
