@@ -297,6 +297,21 @@ qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* cams, int32_t
                         float* const* T_final, uint32_t* const* last, qg_stream stream);
 
 /*
+ * qg_render_fwd followed, in the same kernel, by the L1 term of Eq. 3 against gt: for each view v, as
+ * qg_l1_loss(3 W_v H_v, image[v], gt[v], scale[v], grad_image[v], ...) would write it, grad_image[v] =
+ * scale[v] * sign(image - gt) / (3 W_v H_v) (bit-identical values).  partials [2 * total_tiles] doubles: per
+ * tile, sum |image - gt| and sum (clamp(image, 0, 1) - gt)^2 over its pixels' three channels (the sums of
+ * qg_l1_loss, grouped by tile, so their rounding differs in the last bits); a view's tiles are the consecutive
+ * global tile ids of that view, and qg_loss_reduce_parts(view tiles, 3 W_v H_v, partials + 2 * first tile,
+ * out) gives that view's L1 and MSE.  gt, grad_image: [host] arrays of V device pointers, planar [3][H][W]
+ * float; scale: [host] V floats.  Errors: QG_ERR_ARG for a NULL pointer or a non-finite scale.
+ */
+qg_status qg_render_fwd_l1(const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                           const uint32_t* vals, const uint32_t* tile_ranges, const float* bg, float* const* image,
+                           float* const* T_final, uint32_t* const* last, const float* const* gt,
+                           const float* scale, float* const* grad_image, double* partials, qg_stream stream);
+
+/*
  * Heaviest-first tile order for the blend kernels (a scheduling aid; no arithmetic of the method).  Each tile
  * keeps the XCD that the 4x4 super-tile order gives it (neighbouring tiles share an L2); within each XCD the
  * tiles are ordered by decreasing entry count (on a log scale, 8 steps per octave; order within a step is
@@ -609,6 +624,10 @@ qg_status qg_ssim_loss(int32_t C, int32_t H, int32_t W, const float* image, cons
 qg_status qg_l1_loss(int64_t count, const float* image, const float* gt, float scale, float* grad_image,
                      double* partials, qg_stream stream);
 qg_status qg_loss_reduce(int64_t count, const double* partials, double* out, qg_stream stream);
+/* As qg_loss_reduce over nparts pairs of partial sums (e.g. the per-tile partials of qg_render_fwd_l1),
+ * divided by count. */
+qg_status qg_loss_reduce_parts(int64_t nparts, int64_t count, const double* partials, double* out,
+                               qg_stream stream);
 
 /*
  * One bias-corrected Adam step on `count` parameters (beta = (b1, b2), eps) at 1-based step `t`:

@@ -1,6 +1,7 @@
 // L1 loss with its image gradient and the clamped-image MSE used for PSNR; Adam.
 #include <cmath>
 
+#include "l1_term.h"
 #include "qg_internal.h"
 
 namespace qg {
@@ -9,14 +10,6 @@ namespace {
 constexpr int kLBlock = 256;
 constexpr int kLIPT = 16;
 constexpr int64_t kLTile = (int64_t)kLBlock * kLIPT;
-
-__device__ __forceinline__ float l1_term(float x, float y, float gscale, float& sa, float& sb) {
-    const float d = x - y;
-    sa += fabsf(d);
-    const float c = fminf(1.f, fmaxf(0.f, x)) - y;
-    sb = __builtin_fmaf(c, c, sb);
-    return d > 0.f ? gscale : (d < 0.f ? -gscale : 0.f);
-}
 
 // The block's two sums (in double) to part[2b], part[2b + 1], in a fixed order.
 __device__ __forceinline__ void l1_block_partials(float sa, float sb, double* s_a, double* s_b, double* part) {
@@ -319,6 +312,18 @@ extern "C" qg_status qg_loss_reduce(int64_t count, const double* partials, doubl
         k_loss_reduce<<<1, 64, 0, (hipStream_t)stream>>>(qg_loss_blocks(count), count, partials, out);
     }
     QG_LAUNCH_CHECK("qg_loss_reduce");
+    return QG_OK;
+}
+
+extern "C" qg_status qg_loss_reduce_parts(int64_t nparts, int64_t count, const double* partials, double* out,
+                                          qg_stream stream) {
+    clear_error();
+    QG_REQUIRE(nparts >= 0 && count >= 0 && (nparts == 0 || partials) && out, "bad arguments");
+    {
+        QG_TIMED("loss_reduce", (hipStream_t)stream);
+        k_loss_reduce<<<1, 64, 0, (hipStream_t)stream>>>(nparts, count, partials, out);
+    }
+    QG_LAUNCH_CHECK("qg_loss_reduce_parts");
     return QG_OK;
 }
 

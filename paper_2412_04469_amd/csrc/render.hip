@@ -16,6 +16,7 @@
 // The blend alpha is evaluated by one inline function used by both kernels, with explicit fused
 // multiply-adds, so the forward's skip/clamp/termination decisions are reproduced exactly.
 
+#include "l1_term.h"
 #include "qg_internal.h"
 
 namespace qg {
@@ -47,6 +48,15 @@ struct ViewPtrsU {
 };
 struct ViewPtrsCU {
     const uint32_t* p[QG_MAX_VIEWS];
+};
+
+// The L1 term of Eq. 3 in the blend forward's epilogue (qg_render_fwd_l1): per view the ground truth, the
+// gradient image and the gradient scale (scale / element count); per tile two partial sums.
+struct FwdL1 {
+    const float* gt[QG_MAX_VIEWS];
+    float* grad[QG_MAX_VIEWS];
+    float gscale[QG_MAX_VIEWS];
+    double* part;  // [2 * total_tiles]
 };
 
 // Map workgroup -> tile so that each of the 8 XCDs (which take workgroups round-robin) gets a contiguous
@@ -137,12 +147,14 @@ struct TileGeom {
     static constexpr int ROWS_PER_K = 64 / TW;  // rows advanced per pixel slot
 };
 
-// Blend of one tile (one wave); BD entries are staged per LDS batch.
-template <int TW, int TH, int BD>
+// Blend of one tile (one wave); BD entries are staged per LDS batch.  kL1: the epilogue also writes the L1
+// gradient of each output value and the tile's two partial sums (l1).
+template <int TW, int TH, int BD, bool kL1>
 __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, float bg0, float bg1, float bg2,
                                          const ViewPtrsF& image, const ViewPtrsF& tfinal, const ViewPtrsU& lastp,
-                                         int64_t tile, float4* s_a, float4* s_b, float* s_c, uint32_t* s_pos) {
+                                         const FwdL1& l1, int64_t tile, float4* s_a, float4* s_b, float* s_c,
+                                         uint32_t* s_pos) {
     constexpr int PPL = TileGeom<TW, TH>::PPL;
     constexpr int RPK = TileGeom<TW, TH>::ROWS_PER_K;
     const int v = view_of_tile(vt, (uint32_t)tile);
@@ -246,6 +258,7 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
     float* img = image.p[v];
     float* tf = tfinal.p[v];
     uint32_t* lp = lastp.p[v];
+    float sa = 0.f, sb = 0.f;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int py = py0 + k * RPK;
@@ -253,11 +266,32 @@ __device__ __forceinline__ void fwd_tile(const ViewTable& vt, const uint32_t* __
             const size_t o = (size_t)py * W + px;
             const size_t plane = (size_t)W * H;
             const float tk = fabsf(T[k]);
-            img[o] = C0[k] + tk * bg0;
-            img[plane + o] = C1[k] + tk * bg1;
-            img[2 * plane + o] = C2[k] + tk * bg2;
+            const float c0 = C0[k] + tk * bg0, c1 = C1[k] + tk * bg1, c2 = C2[k] + tk * bg2;
+            img[o] = c0;
+            img[plane + o] = c1;
+            img[2 * plane + o] = c2;
             tf[o] = tk;
             lp[o] = last[k];
+            if constexpr (kL1) {
+                const float* __restrict__ g = l1.gt[v];
+                float* __restrict__ gr = l1.grad[v];
+                const float gs = l1.gscale[v];
+                gr[o] = l1_term(c0, g[o], gs, sa, sb);
+                gr[plane + o] = l1_term(c1, g[plane + o], gs, sa, sb);
+                gr[2 * plane + o] = l1_term(c2, g[2 * plane + o], gs, sa, sb);
+            }
+        }
+    }
+    if constexpr (kL1) {  // the tile's sums: lane values in double, added over the wave in a fixed order
+        double da = sa, db = sb;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            da += __shfl_xor(da, o);
+            db += __shfl_xor(db, o);
+        }
+        if (lane == 0) {
+            l1.part[2 * tile] = da;
+            l1.part[2 * tile + 1] = db;
         }
     }
 }
@@ -278,18 +312,19 @@ __device__ __forceinline__ int64_t sched_tile(const Sched& sc, const TileMap& tm
     return k < sc.seg[8 + x] ? (int64_t)sc.order[sc.seg[x] + k] : -1;
 }
 
-template <int TW, int TH, int BD>
+template <int TW, int TH, int BD, bool kL1>
 __global__ __launch_bounds__(64) void k_render_fwd(ViewTable vt, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, float bg0, float bg1,
                                                    float bg2, ViewPtrsF image, ViewPtrsF tfinal, ViewPtrsU lastp,
-                                                   TileMap tm, Sched sc) {
+                                                   FwdL1 l1, TileMap tm, Sched sc) {
     __shared__ float4 s_a[BD];  // x, y, o, A'
     __shared__ float4 s_b[BD];  // 2B', C', r, g
     __shared__ float s_c[BD];   // b
     __shared__ uint32_t s_pos[BD];  // position of the entry in vals
     const int64_t tile = sched_tile(sc, tm, vt);
     if (tile >= 0)
-        fwd_tile<TW, TH, BD>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, tile, s_a, s_b, s_c, s_pos);
+        fwd_tile<TW, TH, BD, kL1>(vt, vals, ranges, bg0, bg1, bg2, image, tfinal, lastp, l1, tile, s_a, s_b, s_c,
+                                  s_pos);
 }
 
 // ---- wave64 sums of K values at once: DPP inclusive scans inside each 8-lane half row (row_shr 1, 2, 4,
@@ -556,15 +591,19 @@ inline Sched make_sched(const qg_tiling& t) {
 template <int TW, int TH, int BD>
 qg_status launch_fwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp,
-                       hipStream_t s) {
+                       const FwdL1* l1, hipStream_t s) {
     int64_t grid = 0, xcd_max = 0;
     const TileMap tm = make_tile_map(vt, &grid, tiling.schedule ? &xcd_max : nullptr);
     const Sched sc = make_sched(tiling);
     if (sc.seg) grid = 8 * xcd_max;
-    {
+    if (l1) {
+        QG_TIMED("render_fwd_l1", s);
+        k_render_fwd<TW, TH, BD, true><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf,
+                                                                      lp, *l1, tm, sc);
+    } else {
         QG_TIMED("render_fwd", s);
-        k_render_fwd<TW, TH, BD><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf, lp,
-                                                                tm, sc);
+        k_render_fwd<TW, TH, BD, false><<<(unsigned)grid, 64, 0, s>>>(vt, vals, ranges, bg[0], bg[1], bg[2], img, tf,
+                                                                       lp, FwdL1{}, tm, sc);
     }
     QG_LAUNCH_CHECK("qg_render_fwd");
     return QG_OK;
@@ -590,11 +629,11 @@ qg_status launch_bwd_t(const ViewTable& vt, const qg_tiling& tiling, const uint3
 template <int TW, int TH>
 qg_status launch_fwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
                        const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp,
-                       hipStream_t s) {
-    if (t.batch == 32) return launch_fwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, img, tf, lp, s);
-    if (t.batch == 128) return launch_fwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, img, tf, lp, s);
-    if (t.batch == 256) return launch_fwd_t<TW, TH, 256>(vt, t, vals, ranges, bg, img, tf, lp, s);
-    return launch_fwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, img, tf, lp, s);
+                       const FwdL1* l1, hipStream_t s) {
+    if (t.batch == 32) return launch_fwd_t<TW, TH, 32>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
+    if (t.batch == 128) return launch_fwd_t<TW, TH, 128>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
+    if (t.batch == 256) return launch_fwd_t<TW, TH, 256>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
+    return launch_fwd_t<TW, TH, 64>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
 }
 
 template <int TW, int TH>
@@ -608,10 +647,11 @@ qg_status launch_bwd_b(const ViewTable& vt, const qg_tiling& t, const uint32_t* 
 }
 
 qg_status launch_fwd(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
-                     const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp, hipStream_t s) {
-    if (t.tile_w == 16) return launch_fwd_b<16, 16>(vt, t, vals, ranges, bg, img, tf, lp, s);
-    if (t.tile_w == 8) return launch_fwd_b<8, 8>(vt, t, vals, ranges, bg, img, tf, lp, s);
-    return launch_fwd_b<32, 8>(vt, t, vals, ranges, bg, img, tf, lp, s);
+                     const float* bg, const ViewPtrsF& img, const ViewPtrsF& tf, const ViewPtrsU& lp, const FwdL1* l1,
+                     hipStream_t s) {
+    if (t.tile_w == 16) return launch_fwd_b<16, 16>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
+    if (t.tile_w == 8) return launch_fwd_b<8, 8>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
+    return launch_fwd_b<32, 8>(vt, t, vals, ranges, bg, img, tf, lp, l1, s);
 }
 
 qg_status launch_bwd_tiles(const ViewTable& vt, const qg_tiling& t, const uint32_t* vals, const uint32_t* ranges,
@@ -1051,7 +1091,35 @@ extern "C" qg_status qg_render_fwd(const qg_projected* proj, const qg_camera* ca
         tf.p[v] = T_final[v];
         lp.p[v] = last[v];
     }
-    return launch_fwd(vt, tiling, vals, tile_ranges, bg, img, tf, lp, (hipStream_t)stream);
+    return launch_fwd(vt, tiling, vals, tile_ranges, bg, img, tf, lp, nullptr, (hipStream_t)stream);
+}
+
+extern "C" qg_status qg_render_fwd_l1(const qg_projected* proj, const qg_camera* cams, int32_t V, qg_tiling tiling,
+                                      const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
+                                      float* const* image, float* const* T_final, uint32_t* const* last,
+                                      const float* const* gt, const float* scale, float* const* grad_image,
+                                      double* partials, qg_stream stream) {
+    clear_error();
+    ViewTable vt;
+    if (!make_view_table(cams, proj, V, tiling, true, &vt)) return QG_ERR_ARG;
+    QG_REQUIRE(tile_ranges && bg && image && T_final && last && gt && scale && grad_image && partials,
+               "a required pointer is NULL");
+    ViewPtrsF img = {}, tf = {};
+    ViewPtrsU lp = {};
+    FwdL1 l1 = {};
+    for (int v = 0; v < V; ++v) {
+        QG_REQUIRE(image[v] && T_final[v] && last[v] && gt[v] && grad_image[v], "view %d: a pointer is NULL", v);
+        QG_REQUIRE(std::isfinite(scale[v]), "view %d: scale is not finite", v);
+        img.p[v] = image[v];
+        tf.p[v] = T_final[v];
+        lp.p[v] = last[v];
+        l1.gt[v] = gt[v];
+        l1.grad[v] = grad_image[v];
+        const int64_t count = 3ll * cams[v].width * cams[v].height;
+        l1.gscale[v] = scale[v] / (float)count;  // as qg_l1_loss over the view's 3 H W values
+    }
+    l1.part = partials;
+    return launch_fwd(vt, tiling, vals, tile_ranges, bg, img, tf, lp, &l1, (hipStream_t)stream);
 }
 
 extern "C" size_t qg_render_bwd_workspace_size(int64_t n, int32_t V) {

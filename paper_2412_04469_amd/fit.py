@@ -1,7 +1,7 @@
 """Per-frame residual fitting (Sec. 3.2-3.4, Eq. 4-11) driven entirely through the C ABI.
 
 One optimiser iteration on one training view (one epoch covers all views, Sec. 4.1) enqueues:
-    qg_decode_project -> qg_bin -> qg_render_fwd -> qg_l1_loss -> qg_render_decode_bwd -> qg_adam_multi
+    qg_decode_project -> qg_bin -> qg_render_fwd_l1 (blend and L1 term) -> qg_render_decode_bwd -> qg_adam_multi
 (or the unfused qg_decode_residuals -> qg_project -> ... -> qg_render_bwd -> qg_decode_residuals_bwd)
 on the current stream with no host synchronisation.  The fitted quantities per frame are the
 latents, the shared decoder weights, the pre-gate position residuals l_p and the gate logits a
@@ -266,7 +266,12 @@ class FrameFitter(ResidualState):
         img = self.rast.images[0]
         self.count = img.numel()
         self.grad_img = torch.empty_like(img)
-        self.loss_part = torch.empty(2 * qg.qg_loss_blocks(self.count), dtype=torch.float64, device=dev)
+        # the loss partials: per block of qg_l1_loss, or per tile when the blend forward writes the L1 term
+        self.loss_part = torch.empty(2 * max(qg.qg_loss_blocks(self.count), self.rast.total_tiles),
+                                     dtype=torch.float64, device=dev)
+        self.loss_tiles = 0  # tiles of per-tile partials from the last step (0: qg_l1_loss's blocks)
+        self.t_gimg = qg._ptr_array([self.grad_img])
+        self.t_one = qg.float_array([1.0])
         self.loss_out = torch.zeros(2, dtype=torch.float64, device=dev)
         if cfg.lambda_dssim > 0.0:
             C, H, W = img.shape
@@ -333,6 +338,7 @@ class FrameFitter(ResidualState):
         dev_step = self.step_state if self.use_graph else None  # the step count on the device (graph mode)
         if self.noise is not None:
             qg.qg_gate_noise(self.n, c.gate_seed, self.t, self.noise, step_state=dev_step, stream=stream)
+        fused_l1 = self.fused and not masked and c.lambda_dssim == 0.0  # blend and L1 term in one kernel
         if self.fused:
             r.qcams = self.qcams[v]
             qg.qg_decode_project(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
@@ -342,11 +348,15 @@ class FrameFitter(ResidualState):
             if masked:  # the blend order is taken over the masked tile lists
                 qg.qg_mask_tile_ranges(r.total_tiles, r.ranges, self.masks[v][1], stream)
                 r.schedule_tiles(stream)
-            r.render(stream)
+            if fused_l1:
+                r.render_l1(qg._ptr_array([self.gts[v]]), self.t_one, self.t_gimg, self.loss_part, stream)
+            else:
+                r.render(stream)
         else:
             assert not masked, "masked steps use the fused path"
             self.decode(stream, gate_noise=self.noise)
             self.forward_view(v, stream)
+        self.loss_tiles = r.total_tiles if fused_l1 else 0
         if masked:
             assert c.lambda_dssim == 0.0, "masked steps fit the L1 term"
             pix = self.masks[v][0]
@@ -359,7 +369,7 @@ class FrameFitter(ResidualState):
             C, H, W = r.images[0].shape
             qg.qg_ssim_loss(C, H, W, r.images[0], self.gts[v], c.lambda_dssim, self.grad_img, self.dssim_out,
                             self.ssim_ws, self.ssim_ws_bytes, stream)
-        else:
+        elif not fused_l1:
             qg.qg_l1_loss(self.count, r.images[0], self.gts[v], 1.0, self.grad_img, self.loss_part, stream)
         # parameter gradients are zero here: they start zeroed and qg_adam_multi clears them after use
         gxy = None
@@ -394,7 +404,10 @@ class FrameFitter(ResidualState):
 
     def loss_value(self, stream=None):
         """L1 of the last step (host sync)."""
-        qg.qg_loss_reduce(self.count, self.loss_part, self.loss_out, stream)
+        if self.loss_tiles:  # per-tile partials of the blend's L1 epilogue
+            qg.qg_loss_reduce_parts(self.loss_tiles, self.count, self.loss_part, self.loss_out, stream)
+        else:
+            qg.qg_loss_reduce(self.count, self.loss_part, self.loss_out, stream)
         return float(self.loss_out[0].item())
 
     def psnr(self, cam, gt, stream=None):
@@ -403,6 +416,7 @@ class FrameFitter(ResidualState):
         ``overflows`` counts it (that step rendered no entries)."""
         if self.rast.ensure_capacity():
             self.overflows += 1
+        self.loss_tiles = 0  # the partials now hold the evaluation view's blocks
         return self._eval_psnr(self.rast, cam, gt, self.loss_part, self.loss_out, stream)
 
     def size_capacity(self, margin=1.5):
@@ -533,7 +547,7 @@ class BatchedFitter(ResidualState):
         dev = self.device
         n = self.n
         self.rasts = []
-        self.gimgs, self.loss_parts, self.counts = [], [], []
+        self.gimgs, self.loss_parts, self.counts, self.view_tiles = [], [], [], []
         for g in self.groups:
             r = Rasterizer(n, [self.cams[v] for v in g], tile=cfg.tile, sh_degree=cfg.sh_degree,
                            dilation=cfg.dilation, bg=cfg.bg, device=dev, capacity=capacity, batch=batch,
@@ -541,9 +555,12 @@ class BatchedFitter(ResidualState):
             self.rasts.append(r)
             self.gimgs.append([torch.empty_like(im) for im in r.images])
             self.counts.append([im.numel() for im in r.images])
-            self.loss_parts.append([torch.empty(2 * qg.qg_loss_blocks(im.numel()), dtype=torch.float64, device=dev)
-                                    for im in r.images])
+            # the blend's L1 epilogue writes two partial sums per tile; a view's are its tiles' (consecutive ids)
+            self.loss_parts.append(torch.empty(2 * r.total_tiles, dtype=torch.float64, device=dev))
+            self.view_tiles.append([qg.qg_total_tiles([self.cams[v]], r.tile) for v in g])
         self.t_gimg = [qg._ptr_array(gl) for gl in self.gimgs]
+        self.t_gt = [qg._ptr_array([self.gts[v] for v in g]) for g in self.groups]
+        self.t_scale = [qg.float_array([1.0 / len(g)] * len(g)) for g in self.groups]
         self._alloc_fws()
         for r in self.rasts:
             r.capacity_listeners.append(self._alloc_fws)
@@ -581,11 +598,8 @@ class BatchedFitter(ResidualState):
                              self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.sh_degree, r.qcams, r.tile, c.dilation,
                              r.t_proj, self.attrs, self.gate, None, stream, gate_noise=self.noise)
         r.bin(stream)
-        r.render(stream)
-        w = 1.0 / len(views)
-        for k, v in enumerate(views):
-            qg.qg_l1_loss(self.counts[gi][k], r.images[k], self.gts[v], w, self.gimgs[gi][k], self.loss_parts[gi][k],
-                          stream)
+        # blend and the L1 term of each view (weight 1/V) in one kernel
+        r.render_l1(self.t_gt[gi], self.t_scale[gi], self.t_gimg[gi], self.loss_parts[gi], stream)
         qg.qg_render_decode_bwd(self.n, self.ld, self.prev, self.lat, c.latent_dim, self.W1, self.W2, c.hidden, 56,
                                 self.lp, self.a, c.gamma0, c.gamma1, c.tau, c.lambda_reg, c.sh_degree, r.qcams,
                                 r.tile, c.dilation, r.t_proj, r.vals, r.ranges, r.bg, r.t_tf, r.t_last,
@@ -640,9 +654,11 @@ class BatchedFitter(ResidualState):
         """Per-view mean L1 of the last step of group gi (host sync)."""
         gi = (self.next_group - 1) % len(self.groups) if gi is None else gi
         out = []
-        for k, cnt in enumerate(self.counts[gi]):
-            qg.qg_loss_reduce(cnt, self.loss_parts[gi][k], self.eval_out)
+        first = 0
+        for cnt, nt in zip(self.counts[gi], self.view_tiles[gi]):
+            qg.qg_loss_reduce_parts(nt, cnt, self.loss_parts[gi][2 * first:], self.eval_out)
             out.append(float(self.eval_out[0].item()))
+            first += nt
         return out
 
     def psnr(self, cam, gt, stream=None):
@@ -652,8 +668,8 @@ class BatchedFitter(ResidualState):
 class AttributeFitter:
     """Direct fit of the attribute planes (no residual decoder): the plain differentiable-rasterizer step that the
     small, batched and dense-overlap workloads time.  One optimiser iteration covers all cameras of the fitter in
-    one multi-view launch of each call: qg_project -> qg_bin -> qg_render_fwd -> per-view qg_l1_loss (weight 1/V)
-    -> qg_render_bwd -> qg_adam_multi over five parameter groups (means, quaternions, log-scales, opacity logits,
+    one multi-view launch of each call: qg_project -> qg_bin -> qg_render_fwd_l1 (blend and the per-view L1 term,
+    weight 1/V) -> qg_render_bwd -> qg_adam_multi over five parameter groups (means, quaternions, log-scales, opacity logits,
     SH) with the 3D-GS learning rates.  The step has no host synchronisation, so it is captured once as a graph
     and replayed; the pair capacity is sized beforehand (size_capacity)."""
 
@@ -684,8 +700,12 @@ class AttributeFitter:
         self.adam_segs = qg.adam_segments(*[[sg[k] for sg in segs] for k in range(5)])
         self.gimgs = [torch.empty_like(im) for im in self.rast.images]
         self.counts = [im.numel() for im in self.rast.images]
-        self.loss_parts = [torch.empty(2 * qg.qg_loss_blocks(c), dtype=torch.float64, device=dev)
-                           for c in self.counts]
+        # two partial sums per tile from the blend's L1 epilogue; a view's are its tiles' (consecutive ids)
+        self.loss_part = torch.empty(2 * self.rast.total_tiles, dtype=torch.float64, device=dev)
+        self.view_tiles = [qg.qg_total_tiles([c], self.rast.tile) for c in self.cams]
+        self.t_gt = qg._ptr_array(self.gts)
+        self.t_gimg = qg._ptr_array(self.gimgs)
+        self.t_scale = qg.float_array([1.0 / len(self.cams)] * len(self.cams))
         self.use_graph = bool(graph)
         self.graph = None
 
@@ -703,10 +723,7 @@ class AttributeFitter:
         r = self.rast
         r.project(self.attrs, stream)
         r.bin(stream)
-        r.render(stream)
-        w = 1.0 / len(self.cams)
-        for k in range(len(self.cams)):
-            qg.qg_l1_loss(self.counts[k], r.images[k], self.gts[k], w, self.gimgs[k], self.loss_parts[k], stream)
+        r.render_l1(self.t_gt, self.t_scale, self.t_gimg, self.loss_part, stream)
         r.backward(self.attrs, self.gimgs, self.grad, stream=stream)
         b1, b2 = self.cfg.betas
         qg.qg_adam_multi(self.adam_segs, b1, b2, self.cfg.eps, 0, True, stream, step_state=self.step_state)
@@ -730,9 +747,11 @@ class AttributeFitter:
         """Mean over views of the per-view mean L1 of the last step (host sync)."""
         out = torch.zeros(2, dtype=torch.float64, device=self.device)
         tot = 0.0
-        for c, part in zip(self.counts, self.loss_parts):
-            qg.qg_loss_reduce(c, part, out)
+        first = 0
+        for c, nt in zip(self.counts, self.view_tiles):
+            qg.qg_loss_reduce_parts(nt, c, self.loss_part[2 * first:], out)
             tot += float(out[0].item())
+            first += nt
         return tot / len(self.counts)
 
 

@@ -85,6 +85,7 @@ def lib():
             "qg_bin_noalloc": ([i64, PRJ, CAM, i32, qg_tiling, i64, P, P, P, P, P], i32),
             "qg_bin_noalloc_max_bytes": ([], sz),
             "qg_render_fwd": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P, P, P], i32),
+            "qg_render_fwd_l1": ([PRJ, CAM, i32, qg_tiling, P, P, P, P, P, P, P, P, P, P, P], i32),
             "qg_render_bwd_workspace_size": ([i64, i32], sz),
             "qg_render_bwd": ([i64, i64, P, i32, CAM, i32, qg_tiling, f32, PRJ, P, P, P, P, P, P, P, P, P, P, sz, P],
                               i32),
@@ -102,6 +103,7 @@ def lib():
             "qg_dilate_mask": ([CAM, i32, qg_tiling, i32, P, P, P, P, P], i32),
             "qg_mask_tile_ranges": ([i64, P, P, P], i32),
             "qg_loss_reduce": ([i64, P, P, P], i32),
+            "qg_loss_reduce_parts": ([i64, i64, P, P, P], i32),
             "qg_adam": ([i64, P, P, P, P, f32, f32, f32, f32, i32, P], i32),
             "qg_timing_enable": ([i32, ctypes.c_char_p], i32),
             "qg_adam_multi": ([i32, ctypes.POINTER(qg_adam_segment), f32, f32, f32, i32, P, i32, P], i32),
@@ -354,6 +356,23 @@ def qg_render_fwd(proj, cams, tile, vals, tile_ranges, bg, image, T_final, last,
                                _ptr_array(T_final), _ptr_array(last), _stream(stream)))
 
 
+def float_array(xs):
+    """A [host] array of floats (e.g. the per-view scales of qg_render_fwd_l1)."""
+    if isinstance(xs, ctypes.Array):
+        return xs
+    return (ctypes.c_float * len(xs))(*[float(x) for x in xs])
+
+
+def qg_render_fwd_l1(proj, cams, tile, vals, tile_ranges, bg, image, T_final, last, gt, scale, grad_image, partials,
+                     stream=None):
+    ca = camera_array(cams)
+    pa = projected_array(proj)
+    bga = (ctypes.c_float * 3)(*[float(b) for b in bg])
+    _check(lib().qg_render_fwd_l1(pa, ca, len(cams), tile, _ptr(vals), _ptr(tile_ranges), bga, _ptr_array(image),
+                                  _ptr_array(T_final), _ptr_array(last), _ptr_array(gt), float_array(scale),
+                                  _ptr_array(grad_image), _ptr(partials), _stream(stream)))
+
+
 def qg_render_bwd_workspace_size(n, V):
     return int(lib().qg_render_bwd_workspace_size(int(n), int(V)))
 
@@ -442,6 +461,10 @@ def qg_mask_tile_ranges(total_tiles, tile_ranges, tile_flags, stream=None):
 
 def qg_loss_reduce(count, partials, out, stream=None):
     _check(lib().qg_loss_reduce(int(count), _ptr(partials), _ptr(out), _stream(stream)))
+
+
+def qg_loss_reduce_parts(nparts, count, partials, out, stream=None):
+    _check(lib().qg_loss_reduce_parts(int(nparts), int(count), _ptr(partials), _ptr(out), _stream(stream)))
 
 
 def qg_adam(count, param, grad, m, v, lr, b1, b2, eps, t, stream=None):

@@ -110,6 +110,12 @@ class Rasterizer:
         qg.qg_render_fwd(self.t_proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.t_img, self.t_tf,
                          self.t_last, stream)
 
+    def render_l1(self, gts, scales, grad_images, partials, stream=None):
+        """render, with the L1 term of each view against gts[v] (gradient scale scales[v]) in the same kernel:
+        grad_images[v] as qg_l1_loss writes it, partials [2 * total_tiles] float64 per tile."""
+        qg.qg_render_fwd_l1(self.t_proj, self.qcams, self.tile, self.vals, self.ranges, self.bg, self.t_img,
+                            self.t_tf, self.t_last, gts, scales, grad_images, partials, stream)
+
     def pair_count(self) -> int:
         """Pair count of the last qg_bin (host sync).  Raises QGError on a negative count, which qg_bin never
         writes: the count buffer (and the tile lists with it) would then be corrupt."""

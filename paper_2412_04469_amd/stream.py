@@ -156,6 +156,7 @@ def _train_loss(fitter, views):
         qg.qg_l1_loss(fitter.count, fitter.rast.images[0], fitter.gts[v], 1.0, None, fitter.loss_part)
         qg.qg_loss_reduce(fitter.count, fitter.loss_part, fitter.loss_out)
         tot += float(fitter.loss_out[0].item())
+    fitter.loss_tiles = 0  # its partials now hold these blocks, not a step's per-tile sums
     return tot / len(views)
 
 

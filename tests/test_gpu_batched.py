@@ -279,3 +279,48 @@ def test_frame_fitter_graph_replay_matches_eager_step(qgm):
             de, dr = (pe - p0).cpu().numpy(), (pr - p0).cpu().numpy()
             assert rel_l2(dr, de) <= 1e-3, (rnd, k, rel_l2(dr, de))
     assert int(f.step_state[0].item()) == len(cams) + 4
+
+
+@pytest.mark.parametrize("heaviest_first", [False, True])
+def test_render_fwd_l1_equals_render_then_l1(qgm, heaviest_first):
+    """qg_render_fwd_l1 over three uneven views equals qg_render_fwd followed by one qg_l1_loss per view: image,
+    T_final and last bit for bit, the L1 gradient bit for bit (per-view scale), and each view's L1 and MSE from
+    its tiles' partials (qg_loss_reduce_parts) equal to qg_loss_reduce's within rounding."""
+    qg, raster = qgm
+    sc = small_scene(seed=38, n=5000)
+    cams = uneven_cams()
+    ref, attrs = _render(raster, sc, cams, (16, 16), 64, heaviest_first)
+    rng = np.random.default_rng(39)
+    gts = [to_dev(rng.uniform(0.0, 1.0, size=(3, c.height, c.width))) for c in cams]
+    scales = [1.0, 0.5, 2.0]
+    ref_grads, ref_loss = [], []
+    for v, c in enumerate(cams):
+        cnt = 3 * c.width * c.height
+        g = torch.empty_like(gts[v])
+        part = torch.empty(2 * qg.qg_loss_blocks(cnt), dtype=torch.float64, device="cuda")
+        out = torch.zeros(2, dtype=torch.float64, device="cuda")
+        qg.qg_l1_loss(cnt, ref.images[v], gts[v], scales[v], g, part)
+        qg.qg_loss_reduce(cnt, part, out)
+        ref_grads.append(g)
+        ref_loss.append(out.cpu().numpy())
+    fused = raster.Rasterizer(sc.n, cams, tile=(16, 16), batch=64, heaviest_first=heaviest_first,
+                              bg=(0.1, 0.2, 0.3))
+    fused.forward(attrs)  # binning (and a plain render, overwritten next)
+    grads = [torch.full_like(g, 7.0) for g in gts]
+    part = torch.full((2 * fused.total_tiles,), -1.0, dtype=torch.float64, device="cuda")
+    fused.render_l1(gts, scales, grads, part)
+    torch.cuda.synchronize()
+    first = 0
+    for v, c in enumerate(cams):
+        assert torch.equal(fused.images[v], ref.images[v])
+        assert torch.equal(fused.tfinal[v], ref.tfinal[v])
+        assert torch.equal(fused.last[v], ref.last[v])
+        assert torch.equal(grads[v], ref_grads[v]), v
+        nt = qg.qg_total_tiles([c], fused.tile)
+        out = torch.zeros(2, dtype=torch.float64, device="cuda")
+        qg.qg_loss_reduce_parts(nt, 3 * c.width * c.height, part[2 * first:], out)
+        got = out.cpu().numpy()
+        assert np.allclose(got, ref_loss[v], rtol=1e-6, atol=0), (v, got, ref_loss[v])
+        first += nt
+    assert first == fused.total_tiles
+    assert (part.cpu().numpy() >= 0).all()  # every tile wrote its partials
