@@ -31,6 +31,9 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+// Threads per radix block above 2^22 items: 8192 items per block, so each block's digit runs (and the
+// contiguous writes they make) are twice as long as with 256 threads.
+constexpr int kRsBigBlock = 512;
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
 // Lanes of this wave holding the same digit (among active, valid lanes).
@@ -129,16 +132,16 @@ __device__ __forceinline__ uint32_t rs_val(const RsSrc& src, uint64_t idx) {
         return src.vals[idx];
 }
 
-template <int IPT, bool kGen>
-__global__ __launch_bounds__(kBlock) void k_rs_count(RsSrc src, const uint32_t* __restrict__ count_ptr,
-                                                     uint32_t count_fixed, int pass, uint32_t* __restrict__ cnt,
-                                                     int64_t nb_cap) {
-    constexpr int kTile = IPT * kBlock;
+template <int IPT, int BLK, bool kGen>
+__global__ __launch_bounds__(BLK) void k_rs_count(RsSrc src, const uint32_t* __restrict__ count_ptr,
+                                                  uint32_t count_fixed, int pass, uint32_t* __restrict__ cnt,
+                                                  int64_t nb_cap) {
+    constexpr int kTile = IPT * BLK;
     __shared__ uint32_t s_h[kRadix];
     const uint32_t count = count_ptr ? *count_ptr : count_fixed;
     const uint64_t blk0 = (uint64_t)blockIdx.x * kTile;
     if (blk0 >= count) return;
-    s_h[threadIdx.x] = 0;
+    if (threadIdx.x < kRadix) s_h[threadIdx.x] = 0;
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint64_t base = blk0 + (uint64_t)w * (IPT * kWave);
@@ -155,18 +158,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(RsSrc src, const uint32_t* 
         if (idx < count) hist_add(s_h, (key[r] >> shift) & (kRadix - 1));
     }
     __syncthreads();
-    cnt[(size_t)threadIdx.x * nb_cap + blockIdx.x] = s_h[threadIdx.x];
+    if (threadIdx.x < kRadix) cnt[(size_t)threadIdx.x * nb_cap + blockIdx.x] = s_h[threadIdx.x];
 }
 
 // One workgroup per digit: exclusive scan of cnt[d][0 .. nb) in place, nb from the item count; tot[d] = total.
 constexpr int kRsScanThreads = 1024;
 
-template <int IPT>
+template <int IPT, int BLK>
 __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(uint32_t* __restrict__ cnt, int64_t nb_cap,
                                                             const uint32_t* __restrict__ count_ptr,
                                                             uint32_t count_fixed, uint32_t* __restrict__ tot) {
     __shared__ uint32_t s_w[kRsScanThreads / kWave];
-    const int64_t nb = ceil_div((int64_t)(count_ptr ? *count_ptr : count_fixed), IPT * kBlock);
+    const int64_t nb = ceil_div((int64_t)(count_ptr ? *count_ptr : count_fixed), IPT * BLK);
     uint32_t* row = cnt + (size_t)blockIdx.x * nb_cap;
     const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
     uint32_t carry = 0;
@@ -189,15 +192,16 @@ __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(uint32_t* __restrict
     if (tid == 0) tot[blockIdx.x] = carry;
 }
 
-template <int IPT, bool kGen>
-__global__ __launch_bounds__(kBlock) void k_rs_scatter(RsSrc src, uint32_t* __restrict__ kout,
+template <int IPT, int BLK, bool kGen>
+__global__ __launch_bounds__(BLK) void k_rs_scatter(RsSrc src, uint32_t* __restrict__ kout,
                                                        uint32_t* __restrict__ vout,
                                                        const uint32_t* __restrict__ count_ptr, uint32_t count_fixed,
                                                        int pass, const uint32_t* __restrict__ cnt, int64_t nb_cap,
                                                        const uint32_t* __restrict__ tot) {
-    constexpr int kTile = IPT * kBlock;
-    __shared__ uint32_t s_cnt[kWaves][kRadix];
-    __shared__ uint32_t s_w[kWaves];
+    constexpr int kTile = IPT * BLK;
+    constexpr int kW = BLK / kWave;
+    __shared__ uint32_t s_cnt[kW][kRadix];
+    __shared__ uint32_t s_w[kW];
     __shared__ uint32_t s_goff[kRadix];
     __shared__ uint32_t s_key[kTile], s_val[kTile];
     const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
@@ -214,12 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(RsSrc src, uint32_t* __re
         val[r] = valid ? rs_val<kGen>(src, idx) : 0u;
     }
     // output start of digit tid before this block: digit base (scan of the totals) + the earlier blocks' count
-    const uint32_t before = cnt[(size_t)tid * nb_cap + blockIdx.x];
+    const bool dig = tid < kRadix;  // this thread also stands for digit tid
+    const uint32_t before = dig ? cnt[(size_t)tid * nb_cap + blockIdx.x] : 0u;
     uint32_t dtot;
-    const uint32_t dbase = block_excl_scan<uint32_t>(tot[tid], s_w, &dtot);
+    const uint32_t dbase = block_excl_scan<uint32_t>(dig ? tot[tid] : 0u, s_w, &dtot);
     const int shift = kRadixBits * pass;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
+    for (int i = tid; i < kW * kRadix; i += BLK) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
     // per-wave digit counts; each item keeps its rank among the equal digits of its round, the round's count
     // of that digit and the lowest lane holding it (8 | 8 | 16 bits)
@@ -238,15 +242,17 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(RsSrc src, uint32_t* __re
     __syncthreads();
     // block-local start of digit tid (digits in order), and per-wave local starts within it
     uint32_t btot = 0;
+    if (dig) {
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) btot += s_cnt[k][tid];
+        for (int k = 0; k < kW; ++k) btot += s_cnt[k][tid];
+    }
     uint32_t ntot;
     const uint32_t lbase = block_excl_scan<uint32_t>(btot, s_w, &ntot);
-    s_goff[tid] = dbase + before - lbase;
-    {
+    if (dig) {
+        s_goff[tid] = dbase + before - lbase;
         uint32_t run = lbase;
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
+        for (int k = 0; k < kW; ++k) {
             const uint32_t c = s_cnt[k][tid];
             s_cnt[k][tid] = run;
             run += c;
@@ -274,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(RsSrc src, uint32_t* __re
     // the block's items in digit order (ntot of them) to their output positions
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const uint32_t i = (uint32_t)(r * kBlock + tid);
+        const uint32_t i = (uint32_t)(r * BLK + tid);
         if (i < ntot) {
             const uint32_t k = s_key[i];
             const uint32_t pos = i + s_goff[(k >> shift) & (kRadix - 1)];
@@ -284,18 +290,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(RsSrc src, uint32_t* __re
     }
 }
 
-// Items per thread of a pass over up to max_count items: 4 for up to 2^20 items (a wider grid), else 16.
+// Items per thread of a pass over up to max_count items: 4 for up to 2^20 items (a wider grid), else 16; and
+// threads per block: kRsBigBlock above 2^22 items (longer digit runs per block, so longer contiguous writes).
 int rs_ipt(int64_t max_count) { return max_count <= (1 << 20) ? 4 : 16; }
-int64_t rs_blocks(int64_t max_count) { return std::max<int64_t>(1, ceil_div(max_count, rs_ipt(max_count) * kBlock)); }
+int rs_threads(int64_t max_count) { return max_count <= (1 << 22) ? kBlock : kRsBigBlock; }
+int64_t rs_blocks(int64_t max_count) {
+    return std::max<int64_t>(1, ceil_div(max_count, (int64_t)rs_ipt(max_count) * rs_threads(max_count)));
+}
 
 // One pass from src to (kout, vout); cnt holds [256][nb_cap] counts with nb_cap >= rs_blocks(max_count).
-template <int IPT, bool kGen>
+template <int IPT, int BLK, bool kGen>
 void rs_launch(const RsSrc& src, uint32_t* kout, uint32_t* vout, const uint32_t* count_ptr, uint32_t count_fixed,
                int64_t max_count, int pass, uint32_t* cnt, int64_t nb_cap, uint32_t* tot, hipStream_t s) {
-    const unsigned nb = (unsigned)std::max<int64_t>(1, ceil_div(max_count, IPT * kBlock));
-    k_rs_count<IPT, kGen><<<nb, kBlock, 0, s>>>(src, count_ptr, count_fixed, pass, cnt, nb_cap);
-    k_rs_scan<IPT><<<kRadix, kRsScanThreads, 0, s>>>(cnt, nb_cap, count_ptr, count_fixed, tot);
-    k_rs_scatter<IPT, kGen><<<nb, kBlock, 0, s>>>(src, kout, vout, count_ptr, count_fixed, pass, cnt, nb_cap, tot);
+    const unsigned nb = (unsigned)std::max<int64_t>(1, ceil_div(max_count, IPT * BLK));
+    k_rs_count<IPT, BLK, kGen><<<nb, BLK, 0, s>>>(src, count_ptr, count_fixed, pass, cnt, nb_cap);
+    k_rs_scan<IPT, BLK><<<kRadix, kRsScanThreads, 0, s>>>(cnt, nb_cap, count_ptr, count_fixed, tot);
+    k_rs_scatter<IPT, BLK, kGen><<<nb, BLK, 0, s>>>(src, kout, vout, count_ptr, count_fixed, pass, cnt, nb_cap, tot);
 }
 
 template <bool kGen>
@@ -305,9 +315,11 @@ qg_status rs_pass(const RsSrc& src, uint32_t* kout, uint32_t* vout, const uint32
     {
         QG_TIMED(tag, s);
         if (rs_ipt(max_count) == 4)
-            rs_launch<4, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
+            rs_launch<4, kBlock, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
+        else if (rs_threads(max_count) == kBlock)
+            rs_launch<16, kBlock, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
         else
-            rs_launch<16, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
+            rs_launch<16, kRsBigBlock, kGen>(src, kout, vout, count_ptr, count_fixed, max_count, pass, cnt, nb_cap, tot, s);
     }
     QG_LAUNCH_CHECK("radix pass");
     return QG_OK;
