@@ -457,19 +457,27 @@ __global__ __launch_bounds__(kBlock) void k_count_apply(int64_t items, int64_t n
 constexpr int kEmitPer = 1024;
 constexpr int kEmitPerThread = kEmitPer / 256;
 
+// A block takes per_block consecutive chunks: the first item of each later chunk is read off the previous
+// chunk's LDS window when the window reaches it, so only the first chunk pays the search over offs.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ n_comp, int64_t n, ViewTable vt,
                                               const uint32_t* __restrict__ comp_item,
                                               const uint64_t* __restrict__ offs,
                                               const uint32_t* __restrict__ sort_count,
-                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals,
+                                              int64_t per_block) {
     __shared__ uint64_t s_off[kEmitPer + 1];
-    __shared__ int64_t s_k0;
+    __shared__ int64_t s_k0, s_next;
     const uint64_t P = *sort_count;
     const int64_t items = *n_comp;  // >= 1 whenever P > 0
-    for (uint64_t chunk = blockIdx.x; chunk * kEmitPer < P; chunk += gridDim.x) {
-        const uint64_t base = chunk * kEmitPer;
-        __syncthreads();  // the previous chunk is done with s_off
-        if (threadIdx.x < kWave) {
+    if (threadIdx.x == 0) s_next = -1;
+    const int64_t c_end = ((int64_t)blockIdx.x + 1) * per_block;
+    for (int64_t chunk = (int64_t)blockIdx.x * per_block; chunk < c_end && (uint64_t)chunk * kEmitPer < P; ++chunk) {
+        const uint64_t base = (uint64_t)chunk * kEmitPer;
+        __syncthreads();  // the previous chunk is done with s_off, and s_next is set
+        const int64_t carried = s_next;
+        if (carried >= 0) {
+            if (threadIdx.x == 0) s_k0 = carried;
+        } else if (threadIdx.x < kWave) {
             // last k with offs[k] <= base (offs is non-decreasing, offs[0] = 0): 64 probes per round, so the
             // range shrinks 64-fold per dependent load
             const int lane = (int)threadIdx.x;
@@ -486,14 +494,43 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ n_com
         }
         __syncthreads();
         const int64_t k0 = s_k0;
-        for (int t = threadIdx.x; t <= kEmitPer; t += 256) {  // one more than the chunk's items: a sentinel
-            const int64_t k = k0 + t;
-            s_off[t] = k < items ? offs[k] : ~0ull;
+        // the window: the offsets of items k0, k0 + 1, ..., 256 at a time, until one starts past the chunk (the
+        // chunk's 1024 positions belong to at most 1024 items, so at most kEmitPer + 1 entries; past the last
+        // item a sentinel)
+        const uint64_t nb = base + kEmitPer;  // the next chunk's first position
+        int wn = 0;
+        for (;;) {
+            const int t = wn + (int)threadIdx.x;
+            if (t <= kEmitPer) {
+                const int64_t k = k0 + t;
+                s_off[t] = k < items ? offs[k] : ~0ull;
+            }
+            __syncthreads();
+            wn = std::min(wn + 256, kEmitPer + 1);
+            if (wn > kEmitPer || s_off[wn - 1] >= nb) break;
         }
-        __syncthreads();
+        if (threadIdx.x == 0) {
+            // the next chunk's first item, from this window when it holds it (items with pairs have increasing
+            // offsets), else found by the search
+            int64_t nx = -1;
+            if (s_off[wn - 1] == nb) {
+                nx = k0 + wn - 1;
+            } else if (s_off[wn - 1] > nb) {
+                int lo = 0, hi = wn - 2;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= nb)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                nx = k0 + lo;
+            }
+            s_next = nx;
+        }
         const uint64_t p0 = base + (uint64_t)threadIdx.x * kEmitPerThread;
         if (p0 >= P) continue;
-        int lo = 0, hi = kEmitPer - 1;
+        int lo = 0, hi = wn - 2;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= p0)
@@ -510,7 +547,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ n_com
             const uint64_t p = p0 + j;
             key[j] = val[j] = 0u;
             if (p >= P) continue;
-            while (s_off[lo + 1] <= p) ++lo;  // the owner of p (lo + 1 <= kEmitPer: the sentinel stops the walk)
+            while (s_off[lo + 1] <= p) ++lo;  // the owner of p (s_off[wn - 1] lies past the chunk: the walk stops)
             if (lo != cur) {
                 cur = lo;
                 const uint32_t item = comp_item[k0 + lo];
@@ -982,8 +1019,11 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     uint32_t* vbuf1 = (tpasses % 2 == 1) ? vals : w.tvB;
     {
         QG_TIMED("bin_emit", s);
-        k_emit<<<(unsigned)ceil_div(capacity, kEmitPer), 256, 0, s>>>(w.n_comp, n, vt, comp_item, w.offs,
-                                                                      w.sort_count, w.tkA, vbuf0);
+        // consecutive chunks per block once the grid would exceed 8192 blocks
+        const int64_t chunks = std::max<int64_t>(1, ceil_div(capacity, kEmitPer));
+        const int64_t per_block = std::max<int64_t>(1, chunks / 8192);
+        k_emit<<<(unsigned)ceil_div(chunks, per_block), 256, 0, s>>>(w.n_comp, n, vt, comp_item, w.offs,
+                                                                    w.sort_count, w.tkA, vbuf0, per_block);
     }
     QG_LAUNCH_CHECK("qg_bin emit");
     // 3. stable sort by tile id: reduce, scan and scatter per 8-bit pass
