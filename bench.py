@@ -501,6 +501,7 @@ def frame_section(args):
     log(f"frame: storage {storage['mb_per_frame']:.4f} MB")
     fps = render_fps(plain, plain.rast, list(wl.cams) + [held])
     log(f"frame: render {fps['fps_median']} FPS")
+    overflows_p = plain.overflows
     del plain
     torch.cuda.empty_cache()
     runs = {}
@@ -537,7 +538,7 @@ def frame_section(args):
     log(f"frame: batched {chosen} {'reaches target at %.3f s' % rb['sec_per_frame'] if rb['sec_per_frame'] else 'does not reach the target'}")
     return {"workload": wl.name, "target_psnr_db": tgt, "iterations_plain": args.frame_iters,
             "storage_plain": storage, "render": fps,
-            "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p, "overflows": plain.overflows},
+            "plain": {"sec_per_frame": round(hit_p, 4), "trajectory": traj_p, "overflows": overflows_p},
             "batched": rb,
             "grouping_table": [{"views_per_step": v, "lr_scale": l, "sec_per_frame": None if t is None else round(t, 4)}
                                for v, l, t in table],
