@@ -44,7 +44,7 @@ BYTES_PER_GAUSS = {"project": 236.0 + 73.0, "decode_fwd": 524.0, "decode_bwd": 3
 # device copy run in the same process (--copy-probe-mib).  The figure is reported only while the kernel's source
 # file still has the hash it had when the counters were taken.
 TRAFFIC = {
-    "blend_bwd": {"bytes_per_launch": 135804183, "source": "paper_2412_04469_amd/csrc/render.hip", "sha": "bec717dd77fba380",
+    "blend_bwd": {"bytes_per_launch": 135826388, "source": "paper_2412_04469_amd/csrc/render.hip", "sha": "c0ad5526d6cd193e",
                   "profile": "profiles/blend_bwd_traffic_gauss300k_1352x1014.md"},
 }
 
