@@ -399,6 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_count_apply(int64_t items, int64_t n
                                                         uint64_t* __restrict__ comp_offs, int64_t capacity,
                                                         uint32_t* __restrict__ sort_count,
                                                         uint32_t* __restrict__ n_comp,
+                                                        uint32_t* __restrict__ long_count,
                                                         int64_t* __restrict__ num_pairs) {
     __shared__ uint64_t s_w[kWaves];
     __shared__ uint32_t s_v[kWaves];
@@ -435,6 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_count_apply(int64_t items, int64_t n
         *num_pairs = (int64_t)t;
         *sort_count = t <= (uint64_t)capacity ? (uint32_t)t : 0u;
         *n_comp = vstart + vbtot;
+        *long_count = 0u;
     }
     uint64_t run = start + ex;
     uint32_t slot = vstart + vex;
@@ -626,18 +628,22 @@ __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __r
 
 // ------------------------------------------------------------------------------------------------
 // Per-tile depth order.  When every tile's list is short, the pairs are emitted in (view, Gaussian) order
-// instead of depth order, the stable tile sort then leaves each tile's list in Gaussian order, and one
-// wavefront per tile sorts that list by (depth key, position in the list), the depth key being the one the
-// depth passes use (the bits of the depth; a tile's Gaussians all belong to its view).  The positions make
-// every key distinct and keep equal depths in Gaussian order, so the result equals the depth-first order.
-// Lists of up to kSegCap entries are sorted in registers by a bitonic network over the next power of two
-// (64 E keys, E consecutive keys per lane: exchanges between keys less than E apart stay in the lane, the
-// others pair lane l with lane l ^ (distance / E)), the Gaussians kept in LDS by position.  Longer lists
-// take stable 8-bit LSD radix passes through global memory (the tile sort's spare value array): the wave
-// counts digits by ballot matching, scans the 256 counts, then places each item at its digit's cursor plus
-// its rank among the equal digits of its round, rounds in order; a digit every key shares is skipped.
+// instead of depth order, and the stable tile sort then leaves each tile's list in Gaussian order.  Each list
+// is then sorted by the key (depth bits << 32 | Gaussian), the depth bits being the ones the depth passes
+// sort by (a tile's Gaussians all belong to its view).  A Gaussian appears at most once in a list, so the
+// keys are distinct, and equal depths stay in Gaussian order, the order the depth passes leave them in: the
+// result equals the depth-first order, and the sorted keys' low words are the list itself.
+// Lists of up to kSegCap entries: one wavefront per tile, a bitonic network over the next power of two in
+// registers (64 E keys, E consecutive keys per lane; exchanges between keys less than E apart stay in the
+// lane, the others pair lane l with lane l ^ (distance / E)).  Longer lists are put on a work list that
+// k_seg_sort_long takes: a 512-thread block per list, merge-sorting lists of up to kLongCap entries in LDS;
+// longer ones are sorted run by run (kLongCap keys each) in LDS, and the runs merged by a bitonic network
+// through global memory.
 // ------------------------------------------------------------------------------------------------
 constexpr int kSegCap = 1024;
+constexpr int kLongThreads = 512;
+constexpr int kChunk = 1024;     // keys per wavefront in the register half-cleaners: 16 per lane
+constexpr int kLongCap = 8192;   // keys k_seg_sort_long keeps in LDS (64 KiB)
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -645,9 +651,10 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The value of lane l ^ M (M = 1, 2, 4, 8, 16 or 32).  Inside a 16-lane row the exchange runs on the vector
-// unit by DPP (quad permutations for 1 and 2; row rotations by 8, and by 4 and 12 with a select, since lane
-// l - n is rotation n's source); across rows by a lane shuffle through the LDS crossbar.
+// The value of lane l ^ M (M a constant).  Inside a 16-lane row the exchange runs on the vector unit by DPP (quad
+// permutations for 1, 2 and 3; row rotations by 8, and by 4 and 12 with a select, since lane l - n is rotation
+// n's source; the half-row and row mirrors for 7 and 15); across rows by a lane shuffle through the LDS
+// crossbar.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
@@ -659,6 +666,12 @@ __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v) {
         return dpp_u32<0xB1>(v);  // quad_perm [1, 0, 3, 2]
     } else if constexpr (M == 2) {
         return dpp_u32<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    } else if constexpr (M == 3) {
+        return dpp_u32<0x1B>(v);  // quad_perm [3, 2, 1, 0]
+    } else if constexpr (M == 7) {
+        return dpp_u32<0x141>(v);  // row_half_mirror
+    } else if constexpr (M == 15) {
+        return dpp_u32<0x140>(v);  // row_mirror
     } else if constexpr (M == 8) {
         return dpp_u32<0x128>(v);  // row_ror:8
     } else if constexpr (M == 4) {
@@ -675,183 +688,360 @@ __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// m is a constant once the bitonic network is unrolled, and the switch folds away.
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
-    switch (m) {
-        case 1: return xor_lane_u64<1>(x);
-        case 2: return xor_lane_u64<2>(x);
-        case 4: return xor_lane_u64<4>(x);
-        case 8: return xor_lane_u64<8>(x);
-        case 16: return xor_lane_u64<16>(x);
-        default: return xor_lane_u64<32>(x);
-    }
+__device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return b < a ? b : a; }
+__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return b < a ? a : b; }
+
+// Sort key of Gaussian g in a tile list: depth bits above, the Gaussian below.
+__device__ __forceinline__ uint64_t seg_key(const float* __restrict__ depth, uint32_t g) {
+    return ((uint64_t)__float_as_uint(depth[g]) << 32) | g;
 }
 
-// Ascending bitonic sort of the wave's 64 E keys; lane l holds keys l E .. l E + E - 1 in x.
-template <int E>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
-    constexpr int N = kWave * E;
+// Ascending bitonic sort of the wave's 64 E keys; lane l holds keys l E .. l E + E - 1 in x.  The network's
+// levels K and distances J are template arguments, so that every exchange compiles to straight-line code.
+template <int E, int K, int J>
+__device__ __forceinline__ void wave_bitonic_stage(uint64_t (&x)[E]) {
     const int lane = __lane_id();
+    if constexpr (J >= E) {
+        // partner key in lane ^ (J / E), same register; the lower lane of the pair keeps the minimum in an
+        // ascending run (bit K of the key index clear), the maximum in a descending one: a lane takes its
+        // partner's key when (key < partner's) differs from "keep the minimum" (keys are distinct except the
+        // equal padding keys, where either choice is the same)
+        constexpr int M = J / E;
+        const bool keep_max = ((lane & M) == 0) != (((lane * E) & K) == 0);
 #pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
+        for (int r = 0; r < E; ++r) {
+            const uint64_t o = xor_lane_u64<M>(x[r]);
+            const bool take = (x[r] < o) == keep_max;
+            x[r] = take ? o : x[r];
+        }
+    } else {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= E) {
-                // partner key in lane ^ (j / E), same register; the lower lane of the pair keeps the minimum
-                // in an ascending run (bit k of the key index clear), the maximum in a descending one: a lane
-                // takes its partner's key when (key < partner's) differs from "keep the minimum" (keys are
-                // distinct except the equal padding keys, where either choice is the same)
-                const int m = j / E;
-                const bool keep_max = ((lane & m) == 0) != (((lane * E) & k) == 0);
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    const uint64_t o = shfl_xor64(x[r], m);
-                    const bool take = (x[r] < o) == keep_max;
-                    x[r] = take ? o : x[r];
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    if (r & j) continue;
-                    // swap when the pair is out of order for its run's direction
-                    const bool desc = k < E ? (r & k) != 0 : ((lane * E) & k) != 0;
-                    const uint64_t a = x[r], b = x[r ^ j];
-                    const bool sw = (b < a) != desc;
-                    x[r] = sw ? b : a;
-                    x[r ^ j] = sw ? a : b;
-                }
-            }
+        for (int r = 0; r < E; ++r) {
+            if (r & J) continue;
+            // swap when the pair is out of order for its run's direction
+            const bool desc = K < E ? (r & K) != 0 : ((lane * E) & K) != 0;
+            const uint64_t a = x[r], b = x[r ^ J];
+            const bool sw = (b < a) != desc;
+            x[r] = sw ? b : a;
+            x[r ^ J] = sw ? a : b;
         }
     }
 }
 
-// Sorts the tile list src[0 .. L) (L <= 64 E) in registers; s_val holds the list's Gaussians by position.
+template <int E, int K, int J>
+__device__ __forceinline__ void wave_bitonic_merge(uint64_t (&x)[E]) {
+    if constexpr (J > 0) {
+        wave_bitonic_stage<E, K, J>(x);
+        wave_bitonic_merge<E, K, J / 2>(x);
+    }
+}
+
+template <int E, int K = 2>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E]) {
+    if constexpr (K <= kWave * E) {
+        wave_bitonic_merge<E, K, K / 2>(x);
+        wave_bitonic<E, 2 * K>(x);
+    }
+}
+
+// Sorts the tile list src[0 .. L) (L <= 64 E) in registers.
 template <int E>
-__device__ __forceinline__ void seg_sort_regs(uint32_t* __restrict__ src, uint32_t L, const float* __restrict__ depth,
-                                              uint32_t* s_val) {
+__device__ __forceinline__ void seg_sort_regs(uint32_t* __restrict__ src, uint32_t L, const float* __restrict__ depth) {
     const int lane = __lane_id();
     uint64_t x[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t e = (uint32_t)(lane * E + r);
-        x[r] = ~0ull;  // padding: after every key of the list
-        if (e < L) {
-            const uint32_t g = src[e];
-            s_val[e] = g;
-            x[r] = ((uint64_t)__float_as_uint(depth[g]) << 32) | e;
-        }
+        x[r] = e < L ? seg_key(depth, src[e]) : ~0ull;  // padding: after every key of the list
     }
     wave_bitonic<E>(x);
-    wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t e = (uint32_t)(lane * E + r);
-        if (e < L) src[e] = s_val[(uint32_t)x[r]];
+        if (e < L) src[e] = (uint32_t)x[r];
     }
 }
 
-// One stable pass on digit (key >> shift) & 255 over L items: key(i) and val(i) read item i of the source,
-// put(pos, val) writes the destination.  hist: 256 words of LDS.
-template <class Key, class Val, class Put>
-__device__ __forceinline__ void seg_pass(uint32_t L, int shift, uint32_t* hist, const Key& key, const Val& val,
-                                         const Put& put) {
-    const int lane = __lane_id();
+// ---- k_seg_sort_long.  Lists over kLongCap entries: sorted runs of kLongCap keys are merged by the bitonic
+// network in the form whose every exchange keeps the smaller key at the lower index (each merge level k
+// opens by comparing key i with its mirror image in the level's block, i ^ (k - 1), and continues with
+// half-cleaners i, i + j).  Keys past the list's end count as +infinity: an exchange with one of them never
+// moves it, so the network runs on any length without padding the list in memory.  Half-cleaners at
+// distances below kLongCap run in LDS, those below kChunk = 1024 in registers, a wavefront's 1024 keys
+// strided: lane l, register r holds chunk key l + 64 r (distances below 64 pair lanes, 64 and above
+// registers; the chunk's LDS loads and stores are consecutive across lanes).
+
+// Half-cleaner at distance J over the chunk x, every pair ascending.
+template <int J>
+__device__ __forceinline__ void chunk_half(uint64_t (&x)[16]) {
+    if constexpr (J >= 64) {
+        constexpr int M = J >> 6;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) hist[4 * lane + j] = 0u;
-    wave_lds_sync();
-    for (uint32_t r0 = 0; r0 < L; r0 += kWave) {
-        const uint32_t i = r0 + lane;
-        const bool valid = i < L;
-        const uint32_t d = valid ? (key(i) >> shift) & (kRadix - 1) : 0u;
-        const uint64_t m = match8(d, valid);
-        if (valid && __popcll(m & lanemask_lt()) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(m));
-    }
-    wave_lds_sync();
-    // exclusive scan of the 256 counts: four consecutive digits per lane
-    uint32_t h[4], sum = 0;
+        for (int r = 0; r < 16; ++r) {
+            if (r & M) continue;
+            const uint64_t a = x[r], b = x[r | M];
+            x[r] = min64(a, b);
+            x[r | M] = max64(a, b);
+        }
+    } else {
+        const bool lower = (__lane_id() & J) == 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        h[j] = hist[4 * lane + j];
-        sum += h[j];
+        for (int r = 0; r < 16; ++r) {
+            const uint64_t o = xor_lane_u64<J>(x[r]);
+            x[r] = lower ? min64(x[r], o) : max64(x[r], o);
+        }
     }
-    uint32_t run = wave_incl_scan(sum) - sum;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        hist[4 * lane + j] = run;
-        run += h[j];
-    }
-    wave_lds_sync();
-    for (uint32_t r0 = 0; r0 < L; r0 += kWave) {
-        const uint32_t i = r0 + lane;
-        const bool valid = i < L;
-        const uint32_t d = valid ? (key(i) >> shift) & (kRadix - 1) : 0u;
-        const uint64_t m = match8(d, valid);
-        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
-        uint32_t base = 0;
-        if (valid && rank == 0) base = atomicAdd(&hist[d], (uint32_t)__popcll(m));
-        base = __shfl(base, valid ? (int)(__ffsll((unsigned long long)m) - 1) : 0);
-        if (valid) put(base + rank, val(i));
-    }
-    wave_lds_sync();
 }
 
+template <int J>
+__device__ __forceinline__ void chunk_halves(uint64_t (&x)[16]) {
+    if constexpr (J > 0) {
+        chunk_half<J>(x);
+        chunk_halves<J / 2>(x);
+    }
+}
+
+__device__ __forceinline__ void chunk_merge(uint64_t (&x)[16]) { chunk_halves<kChunk / 2>(x); }
+
+// One exchange over keys i < p < n of s[]: the smaller stays at i.
+__device__ __forceinline__ void lds_exchange(uint64_t* s, uint32_t i, uint32_t p) {
+    const uint64_t a = s[i], b = s[p];
+    if (b < a) {
+        s[i] = b;
+        s[p] = a;
+    }
+}
+
+// The merge sort keeps key i at s[i + i / 16]: one unused slot per 16 keys, so that lanes reading keys a few
+// apart (a thread's outputs are 4 to 16 keys from its neighbour's) fall in different LDS banks.
+constexpr int kLongSlots = kLongCap + kLongCap / 16;
+__device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
+
+// Merge sort of keys 0 .. n - 1 (key(i) gives key i; n <= kLongThreads * IPT) into s (padded): runs of 64 keys
+// sorted by one wavefront each in registers, then pairs of runs merged level by level.  Thread t produces
+// outputs t IPT .. t IPT + IPT - 1 of its pair of runs (the pair's length, twice the run, is a multiple of
+// IPT): a binary search along the merge path finds how many of the first ones come from each run, IPT
+// merge steps collect them in registers, and after a barrier they overwrite s in place.
+template <int IPT, class Key>
+__device__ __forceinline__ void lds_sort_run(uint64_t* s, uint32_t n, const Key& key) {
+    static_assert(IPT <= 2 * kWave, "a thread's outputs must lie in one pair of runs");
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    // the keys, a thread's loads issued 16 at a time before the stores
+    constexpr int G = IPT < 16 ? IPT : 16;
+#pragma unroll
+    for (int r0 = 0; r0 < IPT; r0 += G) {
+        uint64_t x[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const uint32_t e = tid + (uint32_t)(r0 + r) * kLongThreads;
+            x[r] = e < n ? key(e) : ~0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const uint32_t e = tid + (uint32_t)(r0 + r) * kLongThreads;
+            if (e < n) s[lds_pad(e)] = x[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = wave; c * kWave < n; c += kLongThreads / kWave) {
+        const uint32_t e = c * kWave + lane;
+        uint64_t x[1] = {e < n ? s[lds_pad(e)] : ~0ull};
+        wave_bitonic<1>(x);
+        if (e < n) s[lds_pad(e)] = x[0];
+    }
+    __syncthreads();
+    const uint32_t o0 = tid * IPT;
+    for (uint32_t run = kWave; run < n; run <<= 1) {
+        uint64_t out[IPT];
+        if (o0 < n) {
+            const uint32_t b = o0 / (2 * run) * (2 * run);
+            const uint32_t a1 = min(b + run, n), na = a1 - b, nb = min(b + 2 * run, n) - a1;
+            const uint32_t d = o0 - b;
+            // i = number of keys of the first run among the pair's first d outputs (keys are distinct)
+            uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s[lds_pad(b + mid)] < s[lds_pad(a1 + d - mid - 1)])
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            uint32_t i = lo, j = d - lo;
+            uint64_t ka = i < na ? s[lds_pad(b + i)] : ~0ull, kb = j < nb ? s[lds_pad(a1 + j)] : ~0ull;
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) {
+                const bool ta = ka < kb;
+                out[r] = ta ? ka : kb;
+                i += ta;
+                j += !ta;
+                if (r + 1 < IPT) {
+                    const bool ok = ta ? i < na : j < nb;
+                    const uint64_t nk = ok ? s[lds_pad(ta ? b + i : a1 + j)] : ~0ull;
+                    ka = ta ? nk : ka;
+                    kb = ta ? kb : nk;
+                }
+            }
+        }
+        __syncthreads();
+        if (o0 < n) {
+#pragma unroll
+            for (int r = 0; r < IPT; ++r)
+                if (o0 + r < n) s[lds_pad(o0 + r)] = out[r];
+        }
+        __syncthreads();
+    }
+}
+
+// Global-memory form for lists over kLongCap keys: key i of the list is hi[i] << 32 | lo[i] (lo = the list,
+// hi = a spare array at the same positions).  All the block's global writes are complete, and no stale
+// line of them in the vector cache, before any thread reads them.
+__device__ __forceinline__ void block_global_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void global_exchange(uint32_t* hi, uint32_t* lo, uint64_t i, uint64_t p) {
+    const uint64_t a = ((uint64_t)hi[i] << 32) | lo[i], b = ((uint64_t)hi[p] << 32) | lo[p];
+    if (b < a) {
+        hi[i] = (uint32_t)(b >> 32);
+        lo[i] = (uint32_t)b;
+        hi[p] = (uint32_t)(a >> 32);
+        lo[p] = (uint32_t)a;
+    }
+}
+
+__device__ void seg_sort_global(uint64_t* s, uint32_t* lo, uint32_t* hi, uint64_t L, const float* __restrict__ depth) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t runs = (L + kLongCap - 1) / kLongCap;
+    // runs of kLongCap keys sorted in LDS, then stored as hi / lo
+    for (uint64_t c = 0; c < runs; ++c) {
+        const uint64_t b = c * kLongCap;
+        const uint32_t n = (uint32_t)(L - b < (uint64_t)kLongCap ? L - b : (uint64_t)kLongCap);
+        lds_sort_run<kLongCap / kLongThreads>(s, n, [&](uint32_t e) { return seg_key(depth, lo[b + e]); });
+        for (uint32_t e = tid; e < n; e += kLongThreads) {
+            const uint64_t k = s[lds_pad(e)];
+            hi[b + e] = (uint32_t)(k >> 32);
+            lo[b + e] = (uint32_t)k;
+        }
+        block_global_sync();
+    }
+    uint64_t npow = kLongCap;
+    while (npow < L) npow <<= 1;
+    for (uint64_t k = 2 * (uint64_t)kLongCap; k <= npow; k <<= 1) {
+        for (uint64_t q = tid; q < npow / 2; q += kLongThreads) {
+            const uint64_t h = k >> 1, i = (q / h) * k + q % h, p = i ^ (k - 1);
+            if (p < L) global_exchange(hi, lo, i, p);
+        }
+        block_global_sync();
+        for (uint64_t j = k >> 2; j >= (uint64_t)kLongCap; j >>= 1) {
+            for (uint64_t q = tid; q < npow / 2; q += kLongThreads) {
+                const uint64_t i = (q / j) * 2 * j + q % j, p = i + j;
+                if (p < L) global_exchange(hi, lo, i, p);
+            }
+            block_global_sync();
+        }
+        // half-cleaners below kLongCap: run by run in LDS
+        for (uint64_t c = 0; c < runs; ++c) {
+            const uint64_t b = c * kLongCap;
+            const uint32_t n = (uint32_t)(L - b < (uint64_t)kLongCap ? L - b : (uint64_t)kLongCap);
+            const uint32_t nr = (n + kChunk - 1) / kChunk * kChunk;
+            for (uint32_t e = tid; e < nr; e += kLongThreads)
+                s[e] = e < n ? ((uint64_t)hi[b + e] << 32) | lo[b + e] : ~0ull;
+            __syncthreads();
+            for (uint32_t j = kLongCap / 2; j >= (uint32_t)kChunk; j >>= 1) {
+                for (uint32_t q = tid; q < kLongCap / 2; q += kLongThreads) {
+                    const uint32_t i = (q / j) * 2 * j + q % j, p = i + j;
+                    if (p < nr) lds_exchange(s, i, p);
+                }
+                __syncthreads();
+            }
+            const uint32_t wave = tid / kWave, lane = tid % kWave;
+            for (uint32_t cc = wave; cc < nr / kChunk; cc += kLongThreads / kWave) {
+                uint64_t x[16];
+                uint64_t* sc = s + cc * kChunk + lane;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) x[r] = sc[64 * r];
+                chunk_merge(x);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) sc[64 * r] = x[r];
+            }
+            __syncthreads();
+            for (uint32_t e = tid; e < n; e += kLongThreads) {
+                hi[b + e] = (uint32_t)(s[e] >> 32);
+                lo[b + e] = (uint32_t)s[e];
+            }
+            block_global_sync();
+        }
+    }
+}
+
+// One wavefront per tile: lists of up to kSegCap entries sorted here, longer ones appended to long_list
+// (long_count entries, at most max_long) for k_seg_sort_long.
 __global__ __launch_bounds__(kWave) void k_seg_sort(ViewTable vt, const uint32_t* __restrict__ ranges,
-                                                    uint32_t* __restrict__ vals, uint32_t* __restrict__ spare,
-                                                    int64_t T) {
-    __shared__ uint32_t s_val[kSegCap];
-    __shared__ uint32_t s_h[kRadix];
+                                                    uint32_t* __restrict__ vals, uint32_t* __restrict__ long_count,
+                                                    uint32_t* __restrict__ long_list, uint32_t max_long, int64_t T) {
     const int64_t t = blockIdx.x;
     if (t >= T) return;
     const uint32_t start = ranges[2 * t], L = ranges[2 * t + 1] - start;
     if (L <= 1) return;
+    if (L > (uint32_t)kSegCap) {
+        if (__lane_id() == 0) {
+            const uint32_t q = atomicAdd(long_count, 1u);
+            if (q < max_long) long_list[q] = (uint32_t)t;
+        }
+        return;
+    }
     int v = 0;
     for (int k = 1; k < vt.V; ++k)
         if ((uint32_t)t >= vt.cam[k].tile_off) v = k;
     const float* __restrict__ depth = vt.proj[v].depth;
     uint32_t* const src = vals + start;
     if (L <= 64) {
-        seg_sort_regs<1>(src, L, depth, s_val);
+        seg_sort_regs<1>(src, L, depth);
     } else if (L <= 128) {
-        seg_sort_regs<2>(src, L, depth, s_val);
+        seg_sort_regs<2>(src, L, depth);
     } else if (L <= 256) {
-        seg_sort_regs<4>(src, L, depth, s_val);
+        seg_sort_regs<4>(src, L, depth);
     } else if (L <= 512) {
-        seg_sort_regs<8>(src, L, depth, s_val);
-    } else if (L <= (uint32_t)kSegCap) {
-        seg_sort_regs<16>(src, L, depth, s_val);
+        seg_sort_regs<8>(src, L, depth);
     } else {
-        const int lane = __lane_id();
-        uint32_t kor = 0u, kand = ~0u;  // the digits every key shares
-        for (uint32_t i = lane; i < L; i += kWave) {
-            const uint32_t k = __float_as_uint(depth[src[i]]);
-            kor |= k;
-            kand &= k;
+        seg_sort_regs<16>(src, L, depth);
+    }
+}
+
+// One block per listed tile (the grid strides over the list; with an empty list every block returns at once).
+// spare: a free array of the capacity, the high words of the keys of lists over kLongCap entries.
+__global__ __launch_bounds__(kLongThreads) void k_seg_sort_long(ViewTable vt, const uint32_t* __restrict__ ranges,
+                                                                uint32_t* __restrict__ vals,
+                                                                uint32_t* __restrict__ spare,
+                                                                const uint32_t* __restrict__ long_count,
+                                                                const uint32_t* __restrict__ long_list,
+                                                                uint32_t max_long) {
+    __shared__ uint64_t s[kLongSlots];
+    const uint32_t nl = min(*long_count, max_long);
+    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
+        const uint32_t t = long_list[q];
+        const uint32_t start = ranges[2 * t], L = ranges[2 * t + 1] - start;
+        int v = 0;
+        for (int k = 1; k < vt.V; ++k)
+            if (t >= vt.cam[k].tile_off) v = k;
+        const float* __restrict__ depth = vt.proj[v].depth;
+        uint32_t* const src = vals + start;
+        if (L <= (uint32_t)kLongCap) {
+            const auto key = [&](uint32_t e) { return seg_key(depth, src[e]); };
+            static_assert(kLongCap == 16 * kLongThreads, "outputs per thread: 4, 8 or 16");
+            if (L <= 4u * kLongThreads)
+                lds_sort_run<4>(s, L, key);
+            else if (L <= 8u * kLongThreads)
+                lds_sort_run<8>(s, L, key);
+            else
+                lds_sort_run<16>(s, L, key);
+            for (uint32_t e = threadIdx.x; e < L; e += kLongThreads) src[e] = (uint32_t)s[lds_pad(e)];
+        } else {
+            seg_sort_global(s, src, spare + start, L, depth);
         }
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            kor |= __shfl_xor(kor, o);
-            kand &= __shfl_xor(kand, o);
-        }
-        const uint32_t diff = kor ^ kand;
-        uint32_t* a = src;
-        uint32_t* b = spare + start;
-        for (int p = 0; p < 4; ++p) {
-            const int shift = kRadixBits * p;
-            if (((diff >> shift) & (kRadix - 1)) == 0) continue;
-            const uint32_t* as = a;
-            uint32_t* bd = b;
-            seg_pass(L, shift, s_h, [&](uint32_t i) { return __float_as_uint(depth[as[i]]); },
-                     [&](uint32_t i) { return as[i]; }, [&](uint32_t pos, uint32_t g) { bd[pos] = g; });
-            // this pass's global writes complete, and no stale line of them in the vector cache, before the next
-            // pass reads them
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            uint32_t* tmp = a;
-            a = b;
-            b = tmp;
-        }
-        if (a != src)
-            for (uint32_t i = lane; i < L; i += kWave) src[i] = a[i];
+        __syncthreads();  // s is reused by the next tile
     }
 }
 
@@ -873,6 +1063,9 @@ struct BinWs {
     uint64_t* offs;                   // V*n: first pair position of each compacted item
     uint32_t* sort_count;
     uint32_t* n_comp;                 // number of compacted items
+    uint32_t* long_count;             // per-tile order: number of tile lists over kSegCap entries
+    uint32_t* long_list;              // per-tile order: those tiles, [max_long]
+    uint32_t max_long;
     uint32_t *tkA, *tkB, *tvB;        // tile sort, capacity
     uint32_t* rs_cnt;                 // radix passes: per-block digit counts [256][nb_cnt], scanned in place
     uint32_t* rs_tot;                 // radix passes: digit totals [256]
@@ -902,6 +1095,10 @@ BinWs bin_ws_layout(char* base, int64_t n, int32_t V, int64_t capacity) {
     w.offs = (uint64_t*)take(8 * it1);
     w.sort_count = (uint32_t*)take(4);
     w.n_comp = (uint32_t*)take(4);
+    w.long_count = (uint32_t*)take(4);
+    // lists over kSegCap entries: at most capacity / (kSegCap + 1) of them fit in the capacity
+    w.max_long = (uint32_t)(cap1 / (kSegCap + 1));
+    w.long_list = (uint32_t*)take(4 * std::max<int64_t>(w.max_long, 1));
     w.tkA = (uint32_t*)take(4 * cap1);
     w.tkB = (uint32_t*)take(4 * cap1);
     w.tvB = (uint32_t*)take(4 * cap1);
@@ -1011,7 +1208,8 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
         k_count_reduce<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum, w.vsum,
                                                               tile_ranges, 2 * T);
         k_count_apply<<<(unsigned)w.nb_scan, kBlock, 0, s>>>(items, n, vt, sorted_items, w.bsum, w.vsum, comp_item,
-                                                             w.offs, capacity, w.sort_count, w.n_comp, num_pairs);
+                                                             w.offs, capacity, w.sort_count, w.n_comp,
+                                                             w.long_count, num_pairs);
     }
     QG_LAUNCH_CHECK("qg_bin count");
     if (capacity == 0) return QG_OK;
@@ -1049,9 +1247,17 @@ qg_status bin_run(int64_t n, const ViewTable& vt, int32_t V, int64_t capacity, u
     if (per_tile) {
         {
             QG_TIMED("bin_seg_sort", s);
-            k_seg_sort<<<(unsigned)T, kWave, 0, s>>>(vt, tile_ranges, vals, w.tvB, T);
+            k_seg_sort<<<(unsigned)T, kWave, 0, s>>>(vt, tile_ranges, vals, w.long_count, w.long_list,
+                                                     w.max_long, T);
         }
         QG_LAUNCH_CHECK("qg_bin tile depth order");
+        if (w.max_long > 0) {
+            QG_TIMED("bin_seg_sort_long", s);
+            k_seg_sort_long<<<std::min(w.max_long, 256u), kLongThreads, 0, s>>>(vt, tile_ranges, vals, w.tvB,
+                                                                                w.long_count, w.long_list,
+                                                                                w.max_long);
+        }
+        QG_LAUNCH_CHECK("qg_bin long tile lists");
     }
     if (keys) {
         k_keys64<<<(unsigned)ceil_div(capacity, 256), 256, 0, s>>>(tk_in, tv_in, w.sort_count, vt, keys);

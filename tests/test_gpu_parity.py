@@ -143,18 +143,26 @@ def test_bin_bit_exact(qgm, tile, sizes, n):
         assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
 
 
-def test_bin_long_tile_lists(qgm):
-    """Short average lists (the per-tile depth order) with a few tiles far longer than the lists kept in LDS:
-    3,000 rectangles share the four centre tiles of a 512x512 view, whose lists then go through global memory.
+@pytest.mark.parametrize("layout", ["hot_lds", "hot_global", "many_long"])
+def test_bin_long_tile_lists(qgm, layout):
+    """Short average lists (the per-tile depth order) with tiles far longer than one wavefront sorts:
+    hot_lds: 3,000 rectangles share the four centre tiles of a 512x512 view (lists sorted in LDS);
+    hot_global: 20,000 do (lists longer than LDS holds, merged through global memory);
+    many_long: 1,100 rectangles cover the top 10 tile rows (320 long lists, more than the blocks that sort them).
     The lists equal the oracle's, and those of the depth-pass path (a capacity far above the average)."""
     qg, raster = qgm
     rng = synth.rng_for(29)
-    n, tile = 20000, (16, 16)
+    tile = (16, 16)
     cams = [synth.make_camera((0, 0, -4), 512, 512)]
     gw = gh = 32
-    rect = _random_rects(rng, n, gw, gh, max_w=4)
-    hot = rng.permutation(n)[:3000]
-    rect[hot] = np.array([15, 15, 17, 17], np.int32)
+    if layout == "many_long":
+        n = 8000
+        rect = _random_rects(rng, n, gw, gh, max_w=2)
+        rect[rng.permutation(n)[:1100]] = np.array([0, 0, gw, 10], np.int32)
+    else:
+        n, hot_n = (20000, 3000) if layout == "hot_lds" else (30000, 20000)
+        rect = _random_rects(rng, n, gw, gh, max_w=4)
+        rect[rng.permutation(n)[:hot_n]] = np.array([15, 15, 17, 17], np.int32)
     depth = rng.uniform(0.3, 30.0, n).astype(np.float32)
     depth[rng.integers(0, n, n // 10)] = depth[0]
     rast = raster.Rasterizer(n, cams, tile=tile, want_keys=True, capacity=64)
@@ -162,7 +170,13 @@ def test_bin_long_tile_lists(qgm):
     k, vv = OB.make_pairs_fast(rect, depth, gw, 0)
     ks, vs = OB.sort_pairs(k, vv)
     ranges = OB.tile_ranges(ks, gw * gh)
-    assert np.diff(ranges, axis=1).max() > 2048
+    lens = np.diff(ranges, axis=1)[:, 0]
+    if layout == "hot_lds":
+        assert 2048 < lens.max() <= 8192
+    elif layout == "hot_global":
+        assert lens.max() > 16384  # three runs of the LDS capacity (8,192)
+    else:
+        assert (lens > 1024).sum() > 256
     rast.bin()
     assert rast.ensure_capacity()
     assert rast.capacity <= 512 * rast.total_tiles  # the per-tile path
