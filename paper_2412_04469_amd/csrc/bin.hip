@@ -901,14 +901,33 @@ __device__ __forceinline__ void block_global_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-__device__ __forceinline__ void global_exchange(uint32_t* hi, uint32_t* lo, uint64_t i, uint64_t p) {
-    const uint64_t a = ((uint64_t)hi[i] << 32) | lo[i], b = ((uint64_t)hi[p] << 32) | lo[p];
-    if (b < a) {
-        hi[i] = (uint32_t)(b >> 32);
-        lo[i] = (uint32_t)b;
-        hi[p] = (uint32_t)(a >> 32);
-        lo[p] = (uint32_t)a;
+// One exchange stage over the list in global memory: pair(q, i, p) gives exchange q (of `half`); exchanges
+// with p >= L are skipped.  A thread loads kGlobalBatch pairs before it compares and stores any of them.
+constexpr int kGlobalBatch = 8;
+template <class Pair>
+__device__ __forceinline__ void global_stage(uint32_t* hi, uint32_t* lo, uint64_t L, uint64_t half, const Pair& pair) {
+    for (uint64_t q0 = threadIdx.x; q0 < half; q0 += (uint64_t)kGlobalBatch * kLongThreads) {
+        uint64_t i[kGlobalBatch], p[kGlobalBatch], a[kGlobalBatch], b[kGlobalBatch];
+        bool ok[kGlobalBatch];
+#pragma unroll
+        for (int r = 0; r < kGlobalBatch; ++r) {
+            const uint64_t q = q0 + (uint64_t)r * kLongThreads;
+            pair(q, i[r], p[r]);
+            ok[r] = q < half && p[r] < L;
+            a[r] = ok[r] ? ((uint64_t)hi[i[r]] << 32) | lo[i[r]] : 0ull;
+            b[r] = ok[r] ? ((uint64_t)hi[p[r]] << 32) | lo[p[r]] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < kGlobalBatch; ++r) {
+            if (ok[r] && b[r] < a[r]) {
+                hi[i[r]] = (uint32_t)(b[r] >> 32);
+                lo[i[r]] = (uint32_t)b[r];
+                hi[p[r]] = (uint32_t)(a[r] >> 32);
+                lo[p[r]] = (uint32_t)a[r];
+            }
+        }
     }
+    block_global_sync();
 }
 
 __device__ void seg_sort_global(uint64_t* s, uint32_t* lo, uint32_t* hi, uint64_t L, const float* __restrict__ depth) {
@@ -929,25 +948,34 @@ __device__ void seg_sort_global(uint64_t* s, uint32_t* lo, uint32_t* hi, uint64_
     uint64_t npow = kLongCap;
     while (npow < L) npow <<= 1;
     for (uint64_t k = 2 * (uint64_t)kLongCap; k <= npow; k <<= 1) {
-        for (uint64_t q = tid; q < npow / 2; q += kLongThreads) {
-            const uint64_t h = k >> 1, i = (q / h) * k + q % h, p = i ^ (k - 1);
-            if (p < L) global_exchange(hi, lo, i, p);
-        }
-        block_global_sync();
-        for (uint64_t j = k >> 2; j >= (uint64_t)kLongCap; j >>= 1) {
-            for (uint64_t q = tid; q < npow / 2; q += kLongThreads) {
-                const uint64_t i = (q / j) * 2 * j + q % j, p = i + j;
-                if (p < L) global_exchange(hi, lo, i, p);
-            }
-            block_global_sync();
-        }
+        const uint64_t h = k >> 1;
+        global_stage(hi, lo, L, npow / 2, [&](uint64_t q, uint64_t& i, uint64_t& p) {
+            i = (q / h) * k + q % h;
+            p = i ^ (k - 1);
+        });
+        for (uint64_t j = k >> 2; j >= (uint64_t)kLongCap; j >>= 1)
+            global_stage(hi, lo, L, npow / 2, [&](uint64_t q, uint64_t& i, uint64_t& p) {
+                i = (q / j) * 2 * j + q % j;
+                p = i + j;
+            });
         // half-cleaners below kLongCap: run by run in LDS
         for (uint64_t c = 0; c < runs; ++c) {
             const uint64_t b = c * kLongCap;
             const uint32_t n = (uint32_t)(L - b < (uint64_t)kLongCap ? L - b : (uint64_t)kLongCap);
             const uint32_t nr = (n + kChunk - 1) / kChunk * kChunk;
-            for (uint32_t e = tid; e < nr; e += kLongThreads)
-                s[e] = e < n ? ((uint64_t)hi[b + e] << 32) | lo[b + e] : ~0ull;
+            for (uint32_t e0 = tid; e0 < nr; e0 += kGlobalBatch * kLongThreads) {
+                uint64_t x[kGlobalBatch];
+#pragma unroll
+                for (int r = 0; r < kGlobalBatch; ++r) {
+                    const uint32_t e = e0 + r * kLongThreads;
+                    x[r] = e < n ? ((uint64_t)hi[b + e] << 32) | lo[b + e] : ~0ull;
+                }
+#pragma unroll
+                for (int r = 0; r < kGlobalBatch; ++r) {
+                    const uint32_t e = e0 + r * kLongThreads;
+                    if (e < nr) s[e] = x[r];
+                }
+            }
             __syncthreads();
             for (uint32_t j = kLongCap / 2; j >= (uint32_t)kChunk; j >>= 1) {
                 for (uint32_t q = tid; q < kLongCap / 2; q += kLongThreads) {
