@@ -242,8 +242,9 @@ qg_status qg_project(int64_t n, int64_t ld, const float* attrs, int32_t sh_degre
  * ty * grid_w(v) + tx.  The per-(view, Gaussian) tile counts are scanned by a reduce and an apply kernel, the
  * pairs are emitted, and they are sorted by their tile bits with stable 8-bit LSD radix passes (count, scan
  * and scatter kernels).  The depth order comes from one of two routes with the same result: when capacity
- * <= 512 * total_tiles (short tile lists) the pairs are emitted in (view, Gaussian) order and one wavefront
- * per tile then sorts its list by (depth bits, position in the list); otherwise the 32 depth bits are sorted
+ * <= 512 * total_tiles (short tile lists) the pairs are emitted in (view, Gaussian) order and each tile's list
+ * is then sorted by (depth bits, Gaussian index): one wavefront per tile for lists of up to 1024 entries, a
+ * 512-thread workgroup per longer list (merge sort in LDS); otherwise the 32 depth bits are sorted
  * once per (view, Gaussian) by four radix passes before the pairs are emitted in that order.  No workgroup
  * ever waits for another.
  *   vals        [capacity] uint32 sorted Gaussian indices (within their view).
