@@ -153,6 +153,7 @@ def parse():
     p.add_argument("--batched-lr-scale", type=float, default=1.0,
                    help="learning-rate factor of the batched steps in the sec/frame sections")
     p.add_argument("--no-configs", action="store_true", help="skip the small and dense-overlap workload steps")
+    p.add_argument("--no-hot-tiles", action="store_true", help="skip the binning timings with one hot tile")
     p.add_argument("--no-densify", action="store_true", help="skip the per-frame densification measurement")
     p.add_argument("--no-paper-decoder", action="store_true", help="skip the paper-mode decoder measurement")
     p.add_argument("--config-steps", type=int, default=20, help="timed steps of the small and dense workloads")
@@ -390,6 +391,50 @@ def attribute_step_section(wl, steps, warmup, tile=(16, 16)):
     del f
     torch.cuda.empty_cache()
     return out
+
+
+def hot_tile_section(hot_sizes=(0, 2000, 8000, 30000), reps=10):
+    """qg_bin alone on one 1024x1024 view (f = 1024, distance 4) of 60 k Gaussians drawn as in the small workload,
+    plus a cluster of `hot` Gaussians (means N(0, 0.005), log-scales N(-6, 0.3)) that falls in a few tiles: the
+    per-tile depth order (capacity 1.5 x the pairs) against the depth passes (capacity 600 pairs per tile), ms
+    per call from events around `reps` calls, and the longest tile list."""
+    import torch
+    from paper_2412_04469_amd import raster, synth
+    cam = synth.make_camera((0.0, 0.0, -4.0), 1024, 1024, f=1024)
+    rows = []
+    for hot in hot_sizes:
+        rng = synth.rng_for(31)
+        planes = synth.draw_scene(rng, 60_000).planes()
+        if hot:
+            cluster = synth.draw_scene(rng, hot, mean_std=0.005, log_scale_mu=-6.0, log_scale_std=0.3)
+            planes = np.concatenate([planes, cluster.planes()], axis=1)
+        attrs = torch.as_tensor(np.ascontiguousarray(planes)).cuda()
+        rast = raster.Rasterizer(attrs.shape[1], [cam], capacity=1024)
+        rast.project(attrs)
+        rast.bin(schedule=False)
+        rast.fit_capacity(rast.pair_count())
+        row = {"hot": hot, "pairs": None, "longest_list": None}
+        stream = torch.cuda.current_stream()
+        for route, cap in (("per_tile", rast.capacity), ("depth_passes", 600 * rast.total_tiles)):
+            rast._alloc_capacity(cap)
+            for _ in range(3):
+                rast.bin(schedule=False)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                rast.bin(schedule=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            row[route + "_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+            row[route + "_capacity_per_tile"] = round(cap / rast.total_tiles, 1)
+        row["pairs"] = rast.pair_count()
+        r = rast.ranges.cpu().numpy().astype(np.int64)
+        row["longest_list"] = int((r[:, 1] - r[:, 0]).max())
+        rows.append(row)
+        log(f"hot tiles: cluster {hot}: longest list {row['longest_list']}, per-tile {row['per_tile_ms']:.3f} ms, "
+            f"depth passes {row['depth_passes_ms']:.3f} ms")
+    return {"workload": "gauss60k_1024x1024_1view_plus_cluster", "rows": rows,
+            "form": "qg_bin alone (no schedule), events around %d calls" % reps}
 
 
 def configs_section(args):
@@ -1009,6 +1054,8 @@ def main():
     result["paper_context"] = PAPER_CONTEXT
     if not args.no_configs:
         result["configs"] = configs_section(args)
+    if not args.no_hot_tiles:
+        result["binning_hot_tiles"] = hot_tile_section()
     if not args.no_batched:
         result["batched"] = batched_section(args)
     if not args.no_frame:
