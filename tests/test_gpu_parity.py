@@ -143,40 +143,52 @@ def test_bin_bit_exact(qgm, tile, sizes, n):
         assert np.array_equal(rast.ranges.cpu().numpy().astype(np.uint32), ranges)
 
 
-@pytest.mark.parametrize("layout", ["hot_lds", "hot_global", "many_long"])
+@pytest.mark.parametrize("layout", ["hot_lds", "hot_global", "many_long", "two_views"])
 def test_bin_long_tile_lists(qgm, layout):
     """Short average lists (the per-tile depth order) with tiles far longer than one wavefront sorts:
     hot_lds: 3,000 rectangles share the four centre tiles of a 512x512 view (lists sorted in LDS);
     hot_global: 20,000 do (lists longer than LDS holds, merged through global memory);
-    many_long: 1,100 rectangles cover the top 10 tile rows (320 long lists, more than the blocks that sort them).
+    many_long: 1,100 rectangles cover the top 10 tile rows (320 long lists, more than the blocks that sort them);
+    two_views: a hot spot in each of two views of different sizes (each long list takes its own view's depths).
     The lists equal the oracle's, and those of the depth-pass path (a capacity far above the average)."""
     qg, raster = qgm
     rng = synth.rng_for(29)
     tile = (16, 16)
-    cams = [synth.make_camera((0, 0, -4), 512, 512)]
-    gw = gh = 32
-    if layout == "many_long":
-        n = 8000
-        rect = _random_rects(rng, n, gw, gh, max_w=2)
-        rect[rng.permutation(n)[:1100]] = np.array([0, 0, gw, 10], np.int32)
-    else:
-        n, hot_n = (20000, 3000) if layout == "hot_lds" else (30000, 20000)
-        rect = _random_rects(rng, n, gw, gh, max_w=4)
-        rect[rng.permutation(n)[:hot_n]] = np.array([15, 15, 17, 17], np.int32)
-    depth = rng.uniform(0.3, 30.0, n).astype(np.float32)
-    depth[rng.integers(0, n, n // 10)] = depth[0]
+    sizes = [(512, 512), (384, 256)] if layout == "two_views" else [(512, 512)]
+    cams = [synth.make_camera((0, 0, -4), w, h) for (w, h) in sizes]
+    n = {"hot_lds": 20000, "hot_global": 30000, "many_long": 8000, "two_views": 12000}[layout]
     rast = raster.Rasterizer(n, cams, tile=tile, want_keys=True, capacity=64)
-    _fill_proj_for_bin(qg, rast.proj[0], rect, depth)
-    k, vv = OB.make_pairs_fast(rect, depth, gw, 0)
-    ks, vs = OB.sort_pairs(k, vv)
-    ranges = OB.tile_ranges(ks, gw * gh)
+    keys_all, vals_all = [], []
+    off = 0
+    for v, c in enumerate(cams):
+        gw, gh = -(-c.width // tile[0]), -(-c.height // tile[1])
+        if layout == "many_long":
+            rect = _random_rects(rng, n, gw, gh, max_w=2)
+            rect[rng.permutation(n)[:1100]] = np.array([0, 0, gw, 10], np.int32)
+        else:
+            hot_n = {"hot_lds": 3000, "hot_global": 20000, "two_views": 3000 - 500 * v}[layout]
+            rect = _random_rects(rng, n, gw, gh, max_w=4)
+            cx, cy = gw // 2 - 1, gh // 2 - 1
+            rect[rng.permutation(n)[:hot_n]] = np.array([cx, cy, cx + 2, cy + 2], np.int32)
+        depth = rng.uniform(0.3, 30.0, n).astype(np.float32)
+        depth[rng.integers(0, n, n // 10)] = depth[0]
+        _fill_proj_for_bin(qg, rast.proj[v], rect, depth)
+        k, vv = OB.make_pairs_fast(rect, depth, gw, off)
+        keys_all.append(k)
+        vals_all.append(vv)
+        off += gw * gh
+    ks, vs = OB.sort_pairs(np.concatenate(keys_all), np.concatenate(vals_all))
+    ranges = OB.tile_ranges(ks, off)
     lens = np.diff(ranges, axis=1)[:, 0]
-    if layout == "hot_lds":
+    if layout in ("hot_lds", "two_views"):
         assert 2048 < lens.max() <= 8192
     elif layout == "hot_global":
         assert lens.max() > 16384  # three runs of the LDS capacity (8,192)
     else:
         assert (lens > 1024).sum() > 256
+    if layout == "two_views":  # a long list in each view
+        t0 = -(-sizes[0][0] // tile[0]) * -(-sizes[0][1] // tile[1])
+        assert lens[:t0].max() > 1024 and lens[t0:].max() > 1024
     rast.bin()
     assert rast.ensure_capacity()
     assert rast.capacity <= 512 * rast.total_tiles  # the per-tile path
