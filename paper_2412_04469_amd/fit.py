@@ -421,14 +421,15 @@ class FrameFitter(ResidualState):
 
     def size_capacity(self, margin=1.5):
         """Bin every view once (host syncs) and size the pair capacity for all of them."""
-        worst = 0
+        worst = longest = 0
         self.decode()
         for v in range(len(self.cams)):
             self.rast.qcams = self.qcams[v]
             self.rast.project(self.attrs)
             self.rast.bin()
             worst = max(worst, self.rast.pair_count())
-        self.rast.fit_capacity(worst, margin)
+            longest = max(longest, self.rast.longest_list())
+        self.rast.fit_capacity(worst, margin, longest)
         return worst
 
 
@@ -646,7 +647,7 @@ class BatchedFitter(ResidualState):
             r.bin()
             p = r.pair_count()
             worst.append(p)
-            r.fit_capacity(p, margin)
+            r.fit_capacity(p, margin, r.longest_list())
         self.invalidate()
         return worst
 
@@ -715,7 +716,7 @@ class AttributeFitter:
         r.project(self.attrs)
         r.bin()
         p = r.pair_count()
-        r.fit_capacity(p, margin)
+        r.fit_capacity(p, margin, r.longest_list())
         self.graph = None
         return p
 

@@ -9,9 +9,18 @@ from __future__ import annotations
 
 import math
 
+import numpy as np
 import torch
 
 from . import qg
+
+
+# qg_bin orders each tile list by depth itself (the per-tile route) when capacity <= PER_TILE_AVG * total_tiles;
+# above, it sorts the depths of all (view, Gaussian) items first (the depth passes).
+PER_TILE_AVG = 512
+# The longest list the per-tile route sorts within one workgroup's LDS.  Longer lists are merged through global
+# memory by one workgroup each, which takes longer than the depth passes.
+PER_TILE_LIST_MAX = 8192
 
 
 def _u32(shape, device):
@@ -128,12 +137,24 @@ class Rasterizer:
         """True if the last qg_bin found more pairs than the capacity (host sync; raises as pair_count)."""
         return self.pair_count() > self.capacity
 
-    def fit_capacity(self, pairs: int, margin=1.5) -> bool:
+    def longest_list(self) -> int:
+        """Entries in the longest tile list of the last qg_bin (host copy of the ranges; 0 after an overflow)."""
+        r = self.ranges.cpu().numpy().astype(np.int64)
+        return int((r[:, 1] - r[:, 0]).max()) if r.size else 0
+
+    def fit_capacity(self, pairs: int, margin=1.5, longest: int = 0) -> bool:
         """Size the pair capacity for a measured pair count: pairs * margin (at least 1024) when the current one
-        leaves less than 5% headroom or is more than 1.25 times that.  Returns True if the buffers were
+        leaves less than 5% headroom or is more than 1.25 times that.  If a tile list is longer than
+        PER_TILE_LIST_MAX (``longest``, as longest_list gives it), the capacity is kept above
+        PER_TILE_AVG * total_tiles, where qg_bin takes the depth passes.  Returns True if the buffers were
         re-allocated."""
         want = max(1024, int(pairs * margin))
-        if pairs * 1.05 > self.capacity or self.capacity > 1.25 * want:
+        depth_route = PER_TILE_AVG * self.total_tiles + 1
+        long_lists = longest > PER_TILE_LIST_MAX
+        if long_lists:
+            want = max(want, depth_route)
+        if (pairs * 1.05 > self.capacity or self.capacity > 1.25 * want
+                or (long_lists and self.capacity < depth_route)):
             self._alloc_capacity(want)
             return True
         return False

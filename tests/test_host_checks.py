@@ -36,6 +36,26 @@ def test_rasterizer_pair_count_rejects_a_negative_count():
         assert e.value.status == qg.QG_ERR_HIP and "invalid pair count" in str(e.value)
 
 
+def test_capacity_sizing_keeps_very_long_tile_lists_on_the_depth_passes():
+    """fit_capacity sizes for the pair count (the per-tile route when that is at most 512 pairs per tile on
+    average), unless a tile list is longer than the per-tile route sorts in LDS: then the capacity stays above
+    512 per tile, where qg_bin takes the depth passes.  Ranges are written from the host."""
+    from paper_2412_04469_amd import raster as R
+    cams, _, _ = _setup(n=50, views=2)
+    r = Rasterizer(50, cams, device="cpu", capacity=100)
+    T = r.total_tiles
+    r.ranges.zero_()
+    r.ranges[0, 1] = 300
+    assert r.longest_list() == 300
+    assert r.fit_capacity(2000, 1.5, r.longest_list()) and r.capacity == 3000
+    assert r.capacity <= R.PER_TILE_AVG * T
+    r.ranges[1, 0], r.ranges[1, 1] = 300, 300 + R.PER_TILE_LIST_MAX + 1
+    assert r.longest_list() == R.PER_TILE_LIST_MAX + 1
+    assert r.fit_capacity(2000, 1.5, r.longest_list()) and r.capacity == R.PER_TILE_AVG * T + 1
+    assert not r.fit_capacity(2000, 1.5, r.longest_list())  # already sized
+    assert r.fit_capacity(2000, 1.5, 0) and r.capacity == 3000  # back on the per-tile route
+
+
 def test_fitters_and_stream_reject_a_failed_sort():
     cams, prev, gts = _setup()
     bf = BatchedFitter(prev, cams, gts, FitConfig(), graph=False)
