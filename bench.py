@@ -62,7 +62,7 @@ def traffic_for(kernel):
 
 
 def measured_peaks():
-    """The chip's ceilings as this build can reach them, measured on the box next to the datasheet figures:
+    """The chip's ceilings as this library's code reaches them, measured on the running GPU beside the datasheet figures:
     HBM from a plain 1 GiB device-to-device copy (2 GiB moved; best of 10), FP32 vector from the library's FMA
     probe (single FMAs, the instruction its kernels are built with, packed FP32 being disabled; best of 5)."""
     import torch
