@@ -817,8 +817,8 @@ __device__ __forceinline__ void lds_exchange(uint64_t* s, uint32_t i, uint32_t p
 constexpr int kLongSlots = kLongCap + kLongCap / 16;
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
 
-// Merge sort of keys 0 .. n - 1 (key(i) gives key i; n <= kLongThreads * IPT) into s (padded): runs of 64 keys
-// sorted by one wavefront each in registers, then pairs of runs merged level by level.  Thread t produces
+// Merge sort of keys 0 .. n - 1 (key(i) gives key i; n <= kLongThreads * IPT) into s (padded): runs of 256 keys
+// sorted by one wavefront each in registers (four per lane), then pairs of runs merged level by level.  Thread t produces
 // outputs t IPT .. t IPT + IPT - 1 of its pair of runs (the pair's length, twice the run, is a multiple of
 // IPT): a binary search along the merge path finds how many of the first ones come from each run, IPT
 // merge steps collect them in registers, and after a barrier they overwrite s in place.
@@ -843,15 +843,25 @@ __device__ __forceinline__ void lds_sort_run(uint64_t* s, uint32_t n, const Key&
         }
     }
     __syncthreads();
-    for (uint32_t c = wave; c * kWave < n; c += kLongThreads / kWave) {
-        const uint32_t e = c * kWave + lane;
-        uint64_t x[1] = {e < n ? s[lds_pad(e)] : ~0ull};
-        wave_bitonic<1>(x);
-        if (e < n) s[lds_pad(e)] = x[0];
+    constexpr int kRunE = 4;
+    constexpr uint32_t kRun = kWave * kRunE;
+    for (uint32_t c = wave; c * kRun < n; c += kLongThreads / kWave) {
+        uint64_t x[kRunE];
+#pragma unroll
+        for (int r = 0; r < kRunE; ++r) {
+            const uint32_t e = c * kRun + lane * kRunE + r;
+            x[r] = e < n ? s[lds_pad(e)] : ~0ull;
+        }
+        wave_bitonic<kRunE>(x);
+#pragma unroll
+        for (int r = 0; r < kRunE; ++r) {
+            const uint32_t e = c * kRun + lane * kRunE + r;
+            if (e < n) s[lds_pad(e)] = x[r];
+        }
     }
     __syncthreads();
     const uint32_t o0 = tid * IPT;
-    for (uint32_t run = kWave; run < n; run <<= 1) {
+    for (uint32_t run = kRun; run < n; run <<= 1) {
         uint64_t out[IPT];
         if (o0 < n) {
             const uint32_t b = o0 / (2 * run) * (2 * run);
